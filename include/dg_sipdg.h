@@ -1,0 +1,207 @@
+/*
+ * dg_sipdg.h -- C-ABI of the MI355X SIP-DG Helmholtz / Poisson library.
+ *
+ * The library solves the implicit sub-problems of the IMEX Runge-Kutta / SDC
+ * projection schemes of arXiv 2112.04167 (Alg. 3 and Alg. 4):
+ *
+ *   Helmholtz (diffusion substep, one per velocity component):
+ *       v - dt a_ii div(nu grad v) = g   ->   lambda u - div(nu grad u) = f,
+ *       lambda = 1/(dt a_ii), f = lambda g, homogeneous Dirichlet data;
+ *   Poisson (projection substep):
+ *       lap(psi) = div(v')  with Neumann data  ->  lambda = 0, nu = 1.
+ *
+ * Discretisation (Sec. 3.3): hexahedral elements, tensor-product Lagrange
+ * polynomials of degree P on GLL points, DG-SEM with the symmetric interior
+ * penalty method.  All integrals use the (P+1)-point GLL rule, so the mass
+ * matrix M is diagonal.  The discrete operator is A = lambda M + K_nu:
+ *
+ *   a(u,v) = sum_K int_K (nu grad u.grad v + lambda u v)
+ *          + sum_F int_F (-{nu d_n u}[v] - {nu d_n v}[u] + sigma [u][v]),
+ *   sigma  = max(nu_L, nu_R) (P+1)^2 / min(h_L, h_R)  at every face node,
+ *
+ * h being the element extent normal to the face; a Dirichlet face uses the
+ * interior trace, the outward normal and sigma = nu (P+1)^2 / h; a Neumann
+ * face adds nothing; periodic axes wrap around.
+ *
+ * Stopping rule (Sec. 4: relative RMS residual at the collocation points):
+ *   || M^-1 (b - A x) ||_2 <= tol || M^-1 b ||_2   with b = M f.
+ *
+ * Meshes are Cartesian products of 1D vertex arrays (uniform or graded).
+ *
+ * ---------------------------------------------------------------- layout --
+ * Every nodal array (x, y, rhs, nu_field) is element-major: node (a,b,c) of
+ * element (ex,ey,ez) is at
+ *     ((ez*ny + ey)*nx + ex)*(P+1)^3 + (c*(P+1) + b)*(P+1) + a,
+ * its coordinates are x = xv[ex] + (xv[ex+1]-xv[ex]) (1 + xi_a)/2 (likewise
+ * y, z), xi the GLL nodes on [-1,1].
+ *
+ * ------------------------------------------------------------- ownership --
+ * The caller owns every device array passed in (rhs, x, y, nu_field); the
+ * library never frees them.  The library owns the mesh handle, its geometry
+ * and its solver workspace (allocated at the first solve, grown on demand,
+ * freed by dg_mesh_destroy).  All work is enqueued on the mesh's HIP stream
+ * (or the stream passed to helmholtz_apply); the *_solve calls return after
+ * the result is known (they synchronise that stream).
+ *
+ * ---------------------------------------------------------------- errors --
+ * Every call returns a status: 0 = DG_OK, > 0 a warning, < 0 an error, and
+ * never throws across the ABI.  dg_last_error() returns a thread-local text
+ * for the last error.  On an error the contents of output arrays are
+ * unspecified; on DG_NOT_CONVERGED x holds the last iterate and info is set.
+ * A mesh handle must not be used by two threads at once.
+ */
+#ifndef DG_SIPDG_H
+#define DG_SIPDG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    DG_OK = 0,
+    DG_NOT_CONVERGED = 1,
+    DG_ERR_ARG = -1,
+    DG_ERR_OOM = -2,
+    DG_ERR_DEVICE = -3,
+    DG_ERR_NOT_SPD = -4,     /* p^T A p <= 0 met in CG */
+    DG_ERR_NONFINITE = -5,   /* NaN / Inf in the data or in a CG scalar */
+    DG_ERR_BUDGET = -6       /* request larger than the server's HBM budget */
+};
+
+enum { DG_BC_PERIODIC = 0, DG_BC_DIRICHLET = 1, DG_BC_NEUMANN = 2 };  /* per axis */
+enum { DG_FP64 = 0, DG_FP32 = 1, DG_MIXED = 1 };  /* apply: FP32 data; solve: FP32 inner + FP64 IR */
+
+typedef struct dg_mesh dg_mesh;  /* opaque */
+
+typedef struct {
+    double tol;         /* relative collocation residual (default 1e-10) */
+    int maxit;          /* CG iteration cap (FP64) / outer IR cap (mixed) */
+    int precision;      /* DG_FP64 or DG_MIXED */
+    double inner_tol;   /* mixed: relative tolerance of each FP32 inner solve */
+    int inner_maxit;    /* mixed: iteration cap of each inner solve */
+    int rhs_is_weak;    /* 0: rhs is the nodal f (b = M f); 1: rhs is b itself */
+    int fixed_iters;    /* > 0: run exactly this many CG iterations, no stopping test */
+} dg_solve_opts;
+
+typedef struct {
+    int iters;            /* CG iterations (mixed: sum of inner iterations) */
+    int outer_iters;      /* IR steps (0 in FP64 mode) */
+    int status;
+    double rel_res;       /* recurrence residual at exit (FP64: CG recurrence) */
+    double true_rel_res;  /* || M^-1 (b - A x) || / || M^-1 b || recomputed from x */
+    double seconds;       /* host wall time of the call */
+} dg_solve_info;
+
+/* Default options: tol 1e-10, maxit 100000, FP64, inner_tol 1e-4,
+   inner_maxit 20000, nodal rhs, no fixed iteration count. */
+void dg_default_opts(dg_solve_opts *opts);
+
+/* Create a Cartesian mesh of nx*ny*nz hexahedra of degree P (1 <= P <= 8,
+   the HIP kernels cover 3 <= P <= 8) from host vertex arrays xv[nx+1],
+   yv[ny+1], zv[nz+1] (strictly increasing), with per-axis boundary
+   conditions bc[3] (DG_BC_*).  The element extents and GLL tables are
+   copied to the device.  hip_stream: the HIP stream the mesh's work goes to
+   (NULL = default stream).  Returns DG_ERR_ARG on bad sizes or vertices. */
+int dg_mesh_create(int nx, int ny, int nz, int P, const double *xv, const double *yv,
+                   const double *zv, const int bc[3], void *hip_stream, dg_mesh **out);
+int dg_mesh_destroy(dg_mesh *m);
+int64_t dg_mesh_ndof(const dg_mesh *m);                      /* E (P+1)^3 */
+/* Bytes of device workspace a solve allocates (for admission control). */
+size_t dg_solve_footprint(const dg_mesh *m, int precision, int nrhs);
+
+/* y = (lambda M + K_nu) x  -- the matrix-free, sum-factorised SIP-DG apply
+   (the Helmholtz operator of Alg. 3's diffusion solve; lambda = 0 gives the
+   Laplacian of the projection solve, with the mesh's own BCs).
+   x, y: device arrays of dg_mesh_ndof values, double (DG_FP64) or float
+   (DG_FP32), x != y.  nu_field: device nodal viscosity of the same type, or
+   NULL for the constant nu_const (> 0).  stream: HIP stream (NULL = the
+   mesh's stream).  Asynchronous: returns once the kernel is enqueued. */
+int helmholtz_apply(dg_mesh *m, double lambda, const void *nu_field, double nu_const,
+                    const void *x, void *y, int precision, void *stream);
+
+/* d = diag(lambda M + K_nu), same argument conventions as helmholtz_apply
+   (the Jacobi preconditioner). */
+int helmholtz_diag(dg_mesh *m, double lambda, const void *nu_field, double nu_const, void *d,
+                   int precision, void *stream);
+
+/* Solve (lambda M + K_nu) x = b by Jacobi-preconditioned CG (FP64), or by
+   FP64 iterative refinement around FP32 Jacobi-PCG inner solves (DG_MIXED;
+   FP64 residuals, updates and dot products).  lambda >= 0; nu_field: device
+   double nodal viscosity or NULL for nu_const.  rhs: device double, the
+   nodal f (b = M f) unless opts->rhs_is_weak.  x: device double, output (the
+   initial guess is zero).  If lambda = 0 and the mesh has no Dirichlet axis
+   the problem is singular: b is projected to mean zero and x is returned
+   with M-weighted mean zero.  opts may be NULL (defaults), info may be NULL. */
+int helmholtz_solve(dg_mesh *m, double lambda, const double *nu_field, double nu_const,
+                    const double *rhs, double *x, const dg_solve_opts *opts, dg_solve_info *info);
+
+/* The pressure Poisson problem of the projection substep (Alg. 3): lambda = 0,
+   nu = 1, and every Dirichlet axis of the mesh becomes a natural Neumann
+   axis (the pressure carries Neumann data).  The system is then singular
+   (constants): rhs is projected, x is returned with M-weighted mean zero. */
+int poisson_solve(dg_mesh *m, const double *rhs, double *x, const dg_solve_opts *opts,
+                  dg_solve_info *info);
+
+/* nsys systems on one mesh, solved together in one persistent launch per
+   refinement step (FP32 inner CG with per-system scalars and retirement,
+   FP64 refinement): the 3 velocity Helmholtz problems and the pressure
+   Poisson problem of one implicit stage.  lambdas[i], nu_fields[i] (device
+   double nodal or NULL for nu = 1), is_poisson[i] (1: lambda ignored, Poisson
+   as in poisson_solve), rhs[i], x[i] (device double).  infos[nsys] may be
+   NULL.  nsys <= 8. */
+int helmholtz_solve_batched(dg_mesh *m, int nsys, const double *lambdas,
+                            const double *const *nu_fields, const int *is_poisson,
+                            const double *const *rhs, double *const *x,
+                            const dg_solve_opts *opts, dg_solve_info *infos);
+
+/* ------------------------------------------------------------- serving --
+ * A request server: solves arrive at any time, are admitted when their
+ * device footprint fits the HBM budget and a slot is free, and run
+ * concurrently (continuous batching: every scheduler tick advances every
+ * admitted solve by a chunk of CG iterations, each on its own stream, and
+ * admits new work as slots and memory free up).  All solve state stays on
+ * the device; the host only sees each solve's scalars. */
+typedef struct {
+    int n;             /* n^3 elements on the unit cube, all axes periodic */
+    int P;             /* degree, 3..8 */
+    int is_poisson;    /* 1: lambda = 0 (singular, projected) */
+    double lambda;     /* Helmholtz lambda (nu = 1) */
+    const double *rhs; /* host nodal f, n^3 (P+1)^3 values; copied at submit */
+    double tol;        /* relative collocation residual */
+    int precision;     /* DG_FP64 or DG_MIXED */
+} dg_request;
+
+int dg_server_create(size_t hbm_budget_bytes, int max_slots, void **srv);
+/* Non-blocking.  Copies the request and its rhs; returns an id.
+   DG_ERR_BUDGET if the request can never fit the budget. */
+int dg_server_submit(void *srv, const dg_request *req, int64_t *req_id);
+/* DG_OK and info when done; DG_NOT_CONVERGED (> 0) ... see below; returns 2
+   (DG_PENDING) while queued or running. */
+int dg_server_poll(void *srv, int64_t req_id, dg_solve_info *info);
+/* Copy a finished request's solution (n^3 (P+1)^3 doubles) to host memory
+   and release it. */
+int dg_server_fetch(void *srv, int64_t req_id, double *x_host);
+/* Block until every submitted request has finished. */
+int dg_server_drain(void *srv);
+/* Latency / throughput statistics of finished requests (seconds). */
+typedef struct {
+    int64_t completed;
+    double p50, p99, mean, max;
+    double makespan;          /* first submit -> last completion */
+    double peak_bytes;        /* largest admitted footprint sum */
+    int peak_active;          /* largest number of concurrently admitted solves */
+} dg_server_stats;
+int dg_server_get_stats(void *srv, dg_server_stats *st);
+int dg_server_destroy(void *srv);
+
+enum { DG_PENDING = 2 };
+
+const char *dg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

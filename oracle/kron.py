@@ -121,10 +121,13 @@ class FDM:
             # the zero mode of each periodic/Neumann axis is its smallest eigenvalue
             self.den[0, 0, 0] = np.inf
 
-    def _apply_tensor(self, U, Sx, Sy, Sz):
-        U = np.einsum("kz,zyx->kyx", Sz, U, optimize=True)
-        U = np.einsum("jy,kyx->kjx", Sy, U, optimize=True)
-        return np.einsum("ix,kjx->kji", Sx, U, optimize=True)
+    @staticmethod
+    def _apply_tensor(U, Ax, Ay, Az):
+        """out[k,j,i] = sum_{z,y,x} Az[k,z] Ay[j,y] Ax[i,x] U[z,y,x]."""
+        U = U @ Ax.T
+        U = np.matmul(Ay, U)
+        Z = U.shape[0]
+        return (Az @ U.reshape(Z, -1)).reshape(Az.shape[0], U.shape[1], U.shape[2])
 
     def solve(self, b):
         """x* for the load vector b (ABI layout)."""

@@ -1,0 +1,12 @@
+"""MI355X-native SIP-DG Helmholtz / Poisson solver (implicit-stage solve of
+the IMEX Runge-Kutta / SDC projection schemes of arXiv 2112.04167).
+
+The compute path is the HIP library built from csrc/ (see include/dg_sipdg.h);
+this package only marshals arguments to it.
+"""
+from .binding import (DG_BC_DIRICHLET, DG_BC_NEUMANN, DG_BC_PERIODIC, DG_ERR_ARG,  # noqa: F401
+                      DG_ERR_BUDGET, DG_ERR_DEVICE, DG_ERR_NONFINITE, DG_ERR_NOT_SPD, DG_ERR_OOM,
+                      DG_FP32, DG_FP64, DG_MIXED, DG_NOT_CONVERGED, DG_OK, DG_PENDING, DGError,
+                      Mesh, Server, default_opts, dg_mesh_create, exported_symbols,
+                      helmholtz_apply, helmholtz_diag, helmholtz_solve, helmholtz_solve_batched,
+                      last_error, lib, mesh_from_spec, poisson_solve)

@@ -1,0 +1,313 @@
+"""ctypes binding of the SIP-DG C-ABI (include/dg_sipdg.h).
+
+Argument marshalling only: every step of the apply and the solves runs in the
+HIP library.  PyTorch supplies device memory and streams.  If the library has
+not been built the import fails loudly; there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libdgsipdg.so")
+
+DG_OK, DG_NOT_CONVERGED, DG_PENDING = 0, 1, 2
+DG_ERR_ARG, DG_ERR_OOM, DG_ERR_DEVICE, DG_ERR_NOT_SPD, DG_ERR_NONFINITE, DG_ERR_BUDGET = \
+    -1, -2, -3, -4, -5, -6
+DG_BC_PERIODIC, DG_BC_DIRICHLET, DG_BC_NEUMANN = 0, 1, 2
+DG_FP64, DG_FP32, DG_MIXED = 0, 1, 1
+
+STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", 2: "PENDING", -1: "ERR_ARG", -2: "ERR_OOM",
+                -3: "ERR_DEVICE", -4: "ERR_NOT_SPD", -5: "ERR_NONFINITE", -6: "ERR_BUDGET"}
+
+
+class DGError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s (%d): %s" % (STATUS_NAMES.get(status, "?"), status, msg))
+        self.status = status
+
+
+class dg_solve_opts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int), ("precision", ctypes.c_int),
+                ("inner_tol", ctypes.c_double), ("inner_maxit", ctypes.c_int),
+                ("rhs_is_weak", ctypes.c_int), ("fixed_iters", ctypes.c_int)]
+
+
+class dg_solve_info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("outer_iters", ctypes.c_int), ("status", ctypes.c_int),
+                ("rel_res", ctypes.c_double), ("true_rel_res", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class dg_request(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("P", ctypes.c_int), ("is_poisson", ctypes.c_int),
+                ("lam", ctypes.c_double), ("rhs", ctypes.POINTER(ctypes.c_double)),
+                ("tol", ctypes.c_double), ("precision", ctypes.c_int)]
+
+
+class dg_server_stats(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_int64), ("p50", ctypes.c_double), ("p99", ctypes.c_double),
+                ("mean", ctypes.c_double), ("max", ctypes.c_double), ("makespan", ctypes.c_double),
+                ("peak_bytes", ctypes.c_double), ("peak_active", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+_VP = ctypes.c_void_p
+_SIGS = {
+    "dg_last_error": ([], ctypes.c_char_p),
+    "dg_default_opts": ([ctypes.POINTER(dg_solve_opts)], None),
+    "dg_mesh_create": ([ctypes.c_int] * 4 + [ctypes.POINTER(ctypes.c_double)] * 3 +
+                       [ctypes.POINTER(ctypes.c_int), _VP, ctypes.POINTER(_VP)], ctypes.c_int),
+    "dg_mesh_destroy": ([_VP], ctypes.c_int),
+    "dg_mesh_ndof": ([_VP], ctypes.c_int64),
+    "dg_solve_footprint": ([_VP, ctypes.c_int, ctypes.c_int], ctypes.c_size_t),
+    "helmholtz_apply": ([_VP, ctypes.c_double, _VP, ctypes.c_double, _VP, _VP, ctypes.c_int, _VP],
+                        ctypes.c_int),
+    "helmholtz_diag": ([_VP, ctypes.c_double, _VP, ctypes.c_double, _VP, ctypes.c_int, _VP],
+                       ctypes.c_int),
+    "helmholtz_solve": ([_VP, ctypes.c_double, _VP, ctypes.c_double, _VP, _VP,
+                         ctypes.POINTER(dg_solve_opts), ctypes.POINTER(dg_solve_info)], ctypes.c_int),
+    "poisson_solve": ([_VP, _VP, _VP, ctypes.POINTER(dg_solve_opts), ctypes.POINTER(dg_solve_info)],
+                      ctypes.c_int),
+    "helmholtz_solve_batched": ([_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(_VP), ctypes.POINTER(ctypes.c_int),
+                                 ctypes.POINTER(_VP), ctypes.POINTER(_VP),
+                                 ctypes.POINTER(dg_solve_opts), ctypes.POINTER(dg_solve_info)],
+                                ctypes.c_int),
+    "dg_server_create": ([ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(_VP)], ctypes.c_int),
+    "dg_server_submit": ([_VP, ctypes.POINTER(dg_request), ctypes.POINTER(ctypes.c_int64)],
+                         ctypes.c_int),
+    "dg_server_poll": ([_VP, ctypes.c_int64, ctypes.POINTER(dg_solve_info)], ctypes.c_int),
+    "dg_server_fetch": ([_VP, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "dg_server_drain": ([_VP], ctypes.c_int),
+    "dg_server_get_stats": ([_VP, ctypes.POINTER(dg_server_stats)], ctypes.c_int),
+    "dg_server_destroy": ([_VP], ctypes.c_int),
+}
+
+
+def lib():
+    """The loaded C-ABI library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("HIP library %s not built: run python -c 'import __graft_entry__ as g; "
+                              "g.build()'" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            f = getattr(L, name, None)
+            if f is None:
+                continue
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return [n for n in _SIGS if hasattr(lib(), n)]
+
+
+def last_error():
+    return lib().dg_last_error().decode()
+
+
+def _check(rc, allow_warning=False):
+    if rc < 0 or (rc > 0 and not allow_warning):
+        raise DGError(rc, last_error())
+    return rc
+
+
+def _dptr(t, dtype=None, n=None):
+    """Device pointer of a contiguous CUDA tensor (None -> NULL)."""
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError("expected dtype %s, got %s" % (dtype, t.dtype))
+    if n is not None and t.numel() != n:
+        raise ValueError("expected %d values, got %d" % (n, t.numel()))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def default_opts(**kw):
+    o = dg_solve_opts()
+    lib().dg_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+class Mesh:
+    """Owner of a dg_mesh handle."""
+
+    def __init__(self, handle, nx, ny, nz, P, bc):
+        self.handle = handle
+        self.nx, self.ny, self.nz, self.P, self.bc = nx, ny, nz, P, tuple(bc)
+        self.ndof = int(lib().dg_mesh_ndof(handle))
+
+    def destroy(self):
+        if self.handle:
+            lib().dg_mesh_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def footprint(self, precision=DG_FP64, nrhs=1):
+        return int(lib().dg_solve_footprint(self.handle, precision, nrhs))
+
+
+def dg_mesh_create(nx, ny, nz, P, xv, yv, zv, bc, stream=None):
+    arrs = [np.ascontiguousarray(v, dtype=np.float64) for v in (xv, yv, zv)]
+    for a, n in zip(arrs, (nx, ny, nz)):
+        if a.shape != (n + 1,):
+            raise ValueError("vertex array must have n+1 entries")
+    bca = (ctypes.c_int * 3)(*bc)
+    h = ctypes.c_void_p()
+    p = [a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for a in arrs]
+    _check(lib().dg_mesh_create(nx, ny, nz, P, p[0], p[1], p[2], bca, _stream_ptr(stream),
+                                ctypes.byref(h)))
+    return Mesh(h, nx, ny, nz, P, bc)
+
+
+def mesh_from_spec(spec, stream=None):
+    return dg_mesh_create(spec["nx"], spec["ny"], spec["nz"], spec["P"], spec["xv"], spec["yv"],
+                          spec["zv"], spec["bc"], stream)
+
+
+def _dtype(precision):
+    import torch
+    return torch.float64 if precision == DG_FP64 else torch.float32
+
+
+def helmholtz_apply(mesh, lam, nu_field, nu_const, x, y, precision=DG_FP64, stream=None):
+    dt = _dtype(precision)
+    _check(lib().helmholtz_apply(mesh.handle, float(lam), _dptr(nu_field, dt, mesh.ndof),
+                                 float(nu_const), _dptr(x, dt, mesh.ndof), _dptr(y, dt, mesh.ndof),
+                                 precision, _stream_ptr(stream)))
+
+
+def helmholtz_diag(mesh, lam, nu_field, nu_const, d, precision=DG_FP64, stream=None):
+    dt = _dtype(precision)
+    _check(lib().helmholtz_diag(mesh.handle, float(lam), _dptr(nu_field, dt, mesh.ndof),
+                                float(nu_const), _dptr(d, dt, mesh.ndof), precision,
+                                _stream_ptr(stream)))
+
+
+def helmholtz_solve(mesh, lam, nu_field, nu_const, rhs, x, opts=None, raise_on_error=True):
+    import torch
+    info = dg_solve_info()
+    rc = lib().helmholtz_solve(mesh.handle, float(lam), _dptr(nu_field, torch.float64, mesh.ndof),
+                               float(nu_const), _dptr(rhs, torch.float64, mesh.ndof),
+                               _dptr(x, torch.float64, mesh.ndof),
+                               ctypes.byref(opts) if opts is not None else None, ctypes.byref(info))
+    if raise_on_error:
+        _check(rc, allow_warning=True)
+    d = info.as_dict()
+    d["rc"] = rc
+    return d
+
+
+def poisson_solve(mesh, rhs, x, opts=None, raise_on_error=True):
+    import torch
+    info = dg_solve_info()
+    rc = lib().poisson_solve(mesh.handle, _dptr(rhs, torch.float64, mesh.ndof),
+                             _dptr(x, torch.float64, mesh.ndof),
+                             ctypes.byref(opts) if opts is not None else None, ctypes.byref(info))
+    if raise_on_error:
+        _check(rc, allow_warning=True)
+    d = info.as_dict()
+    d["rc"] = rc
+    return d
+
+
+def helmholtz_solve_batched(mesh, lambdas, nu_fields, is_poisson, rhs, xs, opts=None,
+                            raise_on_error=True):
+    import torch
+    n = len(rhs)
+    lam = (ctypes.c_double * n)(*[float(v) for v in lambdas])
+    nus = (ctypes.c_void_p * n)(*[_dptr(v, torch.float64, mesh.ndof) if v is not None else None
+                                  for v in nu_fields])
+    pois = (ctypes.c_int * n)(*[int(v) for v in is_poisson])
+    rr = (ctypes.c_void_p * n)(*[_dptr(v, torch.float64, mesh.ndof) for v in rhs])
+    xx = (ctypes.c_void_p * n)(*[_dptr(v, torch.float64, mesh.ndof) for v in xs])
+    infos = (dg_solve_info * n)()
+    rc = lib().helmholtz_solve_batched(mesh.handle, n, lam, nus, pois, rr, xx,
+                                       ctypes.byref(opts) if opts is not None else None, infos)
+    if raise_on_error:
+        _check(rc, allow_warning=True)
+    return rc, [i.as_dict() for i in infos]
+
+
+class Server:
+    """Continuous-batching request server (dg_server_*)."""
+
+    def __init__(self, hbm_budget_bytes, max_slots):
+        h = ctypes.c_void_p()
+        _check(lib().dg_server_create(int(hbm_budget_bytes), int(max_slots), ctypes.byref(h)))
+        self.handle = h
+        self._keep = {}
+
+    def submit(self, n, P, lam, rhs_host, is_poisson=False, tol=1e-10, precision=DG_FP64):
+        rhs = np.ascontiguousarray(rhs_host, dtype=np.float64)
+        req = dg_request(n=n, P=P, is_poisson=int(is_poisson), lam=float(lam),
+                         rhs=rhs.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), tol=tol,
+                         precision=precision)
+        rid = ctypes.c_int64()
+        _check(lib().dg_server_submit(self.handle, ctypes.byref(req), ctypes.byref(rid)))
+        return rid.value
+
+    def poll(self, rid):
+        info = dg_solve_info()
+        rc = lib().dg_server_poll(self.handle, rid, ctypes.byref(info))
+        if rc < 0:
+            raise DGError(rc, last_error())
+        return rc, info.as_dict()
+
+    def fetch(self, rid, ndof):
+        out = np.empty(ndof)
+        _check(lib().dg_server_fetch(self.handle, rid,
+                                     out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    def drain(self):
+        _check(lib().dg_server_drain(self.handle))
+
+    def stats(self):
+        st = dg_server_stats()
+        _check(lib().dg_server_get_stats(self.handle, ctypes.byref(st)))
+        return st.as_dict()
+
+    def destroy(self):
+        if self.handle:
+            lib().dg_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

@@ -1,0 +1,486 @@
+// CG vector kernels of the SIP-DG solve (gfx950).
+//
+// Jacobi-preconditioned CG on A = lambda M + K_nu (arXiv 2112.04167: Krylov
+// solves of the implicit pressure and diffusion problems, Sec. 3.3; stopping
+// on the relative RMS residual at the collocation points, Sec. 4, i.e. on
+// ||M^-1 r|| / ||M^-1 b||).  One CG step is three kernels:
+//
+//   apply   q = A p, with p.q and sum(q) reduced    -> alpha = rho / p.q
+//   update  x += alpha p, r -= alpha q, reductions  -> rho', beta, residual
+//   pupdate (singular: r -= mean r)  p = r/d + beta p
+//
+// All scalars live in device memory (CgScalars); the last work-group of each
+// reduction computes them, so no host round trip is needed per iteration.
+// A solve that has finished (converged, iteration cap, breakdown) sets
+// `done` and every later CG kernel returns at once, which lets the host
+// enqueue iterations in chunks and read the state back rarely.
+//
+// Threads use the element/line mapping of the apply kernel: thread (el, l)
+// owns line l = a + (P+1) b of element el and walks c = 0..P, so the GLL
+// mass J w_a w_b w_c is formed in registers.  Dot products are FP64 for FP32
+// vectors too.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <type_traits>
+
+#include "dg_internal.h"
+#include "kernels.h"
+#include "device_common.h"
+#include "gll_constexpr.h"
+
+namespace dg {
+
+namespace {
+
+// per-thread line context
+template <int P, typename T>
+struct LineCtx {
+    bool active;
+    size_t base;  // index of node (a,b,0)
+    T Jw;         // J w_a w_b
+};
+
+template <int P, typename T>
+__device__ __forceinline__ LineCtx<P, T> line_ctx(const CgVecArgs<T> &A)
+{
+    using S = Shape<P>;
+    LineCtx<P, T> c;
+    const int tid = threadIdx.x;
+    const int el_loc = tid / S::NL;
+    const int l = tid - el_loc * S::NL;
+    const int el = blockIdx.x * S::EB + el_loc;
+    c.active = (tid < S::NT) && (el < A.nel);
+    c.base = (size_t)el * S::N3 + l;
+    c.Jw = 0;
+    if (c.active) {
+        const int nx = A.n[0], ny = A.n[1];
+        const int ex = el % nx, r = el / nx, ey = r % ny, ez = r / ny;
+        c.Jw = A.hx[ex] * A.hy[ey] * A.hz[ez] * (T)0.125 * (T)kGll<P>.w[l % S::n] *
+               (T)kGll<P>.w[l / S::n];
+    }
+    return c;
+}
+
+// set-up, stage 1: b = M f (or b = f if weak), sum b and sum b^2
+template <int P, typename T, bool SING>
+__global__ void __launch_bounds__(Shape<P>::NTP) k_setup1(CgVecArgs<T> A)
+{
+    using S = Shape<P>;
+    __shared__ double sh[16 * 2];
+    const LineCtx<P, T> c = line_ctx<P, T>(A);
+    double red[2] = {0.0, 0.0};
+    if (c.active) {
+#pragma unroll
+        for (int k = 0; k < S::n; ++k) {
+            const size_t gi = c.base + (size_t)k * S::NL;
+            const T m = c.Jw * (T)kGll<P>.w[k];
+            const T b = A.weak ? A.src[gi] : m * A.src[gi];
+            A.bvec[gi] = b;
+            red[0] += (double)b;
+            red[1] += (double)b * (double)b;
+        }
+    }
+    double tot[2];
+    if (publish_and_reduce<2>(red, A.partial, A.counter, gridDim.x, tot, sh) && threadIdx.x == 0) {
+        CgScalars *sc = A.sc;
+        sc->mean_b = SING ? tot[0] / (double)sc->ndof : 0.0;
+        if (!isfinite(tot[1])) {
+            sc->status = DG_ERR_NONFINITE;
+            sc->done = 1;
+        }
+    }
+}
+
+// set-up, stage 2: project b (singular), r = b, x = 0, z = r/d, p = z and the
+// initial norms.  d == nullptr: outer refinement loop (no z, p).
+template <int P, typename T, bool SING>
+__global__ void __launch_bounds__(Shape<P>::NTP) k_setup2(CgVecArgs<T> A)
+{
+    using S = Shape<P>;
+    __shared__ double sh[16 * 4];
+    const LineCtx<P, T> c = line_ctx<P, T>(A);
+    const double mb = A.sc->mean_b;
+    double red[4] = {0.0, 0.0, 0.0, 0.0};
+    if (c.active) {
+#pragma unroll
+        for (int k = 0; k < S::n; ++k) {
+            const size_t gi = c.base + (size_t)k * S::NL;
+            const T m = c.Jw * (T)kGll<P>.w[k];
+            T b = A.bvec[gi];
+            if (SING) {
+                b = (T)((double)b - mb);
+                A.bvec[gi] = b;
+            }
+            A.r[gi] = b;
+            A.x[gi] = (T)0;
+            const double rm = (double)b / (double)m;
+            red[1] += rm * rm;
+            red[3] += 1.0 / ((double)m * (double)m);
+            if (A.d) {
+                const T d = A.d[gi];
+                const T z = b / d;
+                A.p[gi] = z;
+                red[0] += (double)b * (double)z;
+                red[2] += 1.0 / (double)d;
+            }
+        }
+    }
+    double tot[4];
+    if (publish_and_reduce<4>(red, A.partial, A.counter, gridDim.x, tot, sh) && threadIdx.x == 0) {
+        CgScalars *sc = A.sc;
+        sc->rho = tot[0];
+        sc->bnorm2 = tot[1];
+        sc->res2 = tot[1];
+        sc->true_res2 = tot[1];
+        sc->sum_invd = tot[2];
+        sc->sum_invM2 = tot[3];
+        sc->tol2 = sc->tol2 * tot[1];  // host stored tol^2
+        sc->iter = 0;
+        sc->mean_r = 0.0;
+        if (!isfinite(tot[1]) || !isfinite(tot[0])) {
+            sc->status = DG_ERR_NONFINITE;
+            sc->done = 1;
+        } else if (tot[1] == 0.0 || (sc->fixed_iters <= 0 && tot[1] <= sc->tol2)) {
+            sc->done = 1;
+        }
+    }
+}
+
+// x += alpha p, r -= alpha q; reductions for rho' and the residual
+template <int P, typename T, bool SING>
+__global__ void __launch_bounds__(Shape<P>::NTP) k_update(CgVecArgs<T> A)
+{
+    using S = Shape<P>;
+    constexpr int NC = SING ? 5 : 2;
+    __shared__ double sh[16 * NC];
+    if (A.sc->done) return;
+    const T alpha = (T)A.sc->alpha;
+    const LineCtx<P, T> c = line_ctx<P, T>(A);
+    double red[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) red[k] = 0.0;
+    if (c.active) {
+#pragma unroll
+        for (int k = 0; k < S::n; ++k) {
+            const size_t gi = c.base + (size_t)k * S::NL;
+            const T m = c.Jw * (T)kGll<P>.w[k];
+            const T p = A.p[gi];
+            A.x[gi] = fma(alpha, p, A.x[gi]);
+            const T r = fma(-alpha, A.q[gi], A.r[gi]);
+            A.r[gi] = r;
+            const double rd = (double)r / (double)A.d[gi];
+            const double rm = (double)r / (double)m;
+            if (SING) {
+                red[0] += (double)r;
+                red[1] += (double)r * rd;
+                red[2] += rd;
+                red[3] += rm * rm;
+                red[4] += rm / (double)m;
+            } else {
+                red[0] += (double)r * rd;
+                red[1] += rm * rm;
+            }
+        }
+    }
+    double tot[NC];
+    if (publish_and_reduce<NC>(red, A.partial, A.counter, gridDim.x, tot, sh) && threadIdx.x == 0) {
+        CgScalars *sc = A.sc;
+        double rz, res2;
+        if (SING) {
+            const double mr = tot[0] / (double)sc->ndof;
+            rz = tot[1] - 2.0 * mr * tot[2] + mr * mr * sc->sum_invd;
+            res2 = tot[3] - 2.0 * mr * tot[4] + mr * mr * sc->sum_invM2;
+            sc->mean_r = mr;
+        } else {
+            rz = tot[0];
+            res2 = tot[1];
+            sc->mean_r = 0.0;
+        }
+        if (res2 < 0.0) res2 = 0.0;
+        sc->beta = rz / sc->rho;
+        sc->rho = rz;
+        sc->res2 = res2;
+        sc->iter += 1;
+        if (!isfinite(rz) || !isfinite(res2)) {
+            sc->status = DG_ERR_NONFINITE;
+            sc->done = 1;
+        } else if (sc->fixed_iters > 0) {
+            if (sc->iter >= sc->fixed_iters) sc->done = 1;
+        } else if (res2 <= sc->tol2) {
+            sc->done = 1;
+        } else if (sc->iter >= sc->maxit) {
+            sc->status = DG_NOT_CONVERGED;
+            sc->done = 1;
+        }
+    }
+}
+
+// (singular: r -= mean r)  p = r/d + beta p
+template <int P, typename T, bool SING>
+__global__ void __launch_bounds__(Shape<P>::NTP) k_pupdate(CgVecArgs<T> A)
+{
+    using S = Shape<P>;
+    if (A.sc->done) return;
+    const T beta = (T)A.sc->beta;
+    const double mr = A.sc->mean_r;
+    const LineCtx<P, T> c = line_ctx<P, T>(A);
+    if (!c.active) return;
+#pragma unroll
+    for (int k = 0; k < S::n; ++k) {
+        const size_t gi = c.base + (size_t)k * S::NL;
+        T r = A.r[gi];
+        if (SING) {
+            r = (T)((double)r - mr);
+            A.r[gi] = r;
+        }
+        A.p[gi] = fma(beta, A.p[gi], r / A.d[gi]);
+    }
+}
+
+// singular: shift = sum(M x) / sum(M)
+template <int P, typename T>
+__global__ void __launch_bounds__(Shape<P>::NTP) k_mean_x(CgVecArgs<T> A)
+{
+    using S = Shape<P>;
+    __shared__ double sh[16 * 2];
+    const LineCtx<P, T> c = line_ctx<P, T>(A);
+    double red[2] = {0.0, 0.0};
+    if (c.active) {
+#pragma unroll
+        for (int k = 0; k < S::n; ++k) {
+            const size_t gi = c.base + (size_t)k * S::NL;
+            const double m = (double)(c.Jw * (T)kGll<P>.w[k]);
+            red[0] += m * (double)A.x[gi];
+            red[1] += m;
+        }
+    }
+    double tot[2];
+    if (publish_and_reduce<2>(red, A.partial, A.counter, gridDim.x, tot, sh) && threadIdx.x == 0)
+        A.sc->shift = tot[0] / tot[1];
+}
+
+template <int P, typename T>
+__global__ void __launch_bounds__(Shape<P>::NTP) k_shift_x(CgVecArgs<T> A)
+{
+    using S = Shape<P>;
+    const LineCtx<P, T> c = line_ctx<P, T>(A);
+    if (!c.active) return;
+    const double s = A.sc->shift;
+#pragma unroll
+    for (int k = 0; k < S::n; ++k) {
+        const size_t gi = c.base + (size_t)k * S::NL;
+        A.x[gi] = (T)((double)A.x[gi] - s);
+    }
+}
+
+// mixed precision: scale = RMS of the projected FP64 residual
+template <int P>
+__global__ void __launch_bounds__(Shape<P>::NTP) k_ir_scale(CgVecArgs<float> A)
+{
+    using S = Shape<P>;
+    __shared__ double sh[16];
+    const LineCtx<P, float> c = line_ctx<P, float>(A);
+    const double mr = A.sc->mean_r;
+    double red[1] = {0.0};
+    if (c.active) {
+#pragma unroll
+        for (int k = 0; k < S::n; ++k) {
+            const double v = A.src64[c.base + (size_t)k * S::NL] - mr;
+            red[0] += v * v;
+        }
+    }
+    double tot[1];
+    if (publish_and_reduce<1>(red, A.partial, A.counter, gridDim.x, tot, sh) && threadIdx.x == 0) {
+        const double rms = sqrt(tot[0] / (double)A.sc->ndof);
+        A.sc->scale = rms > 0.0 ? rms : 1.0;
+    }
+}
+
+// r32 = (r64 - mean_r) / scale
+template <int P>
+__global__ void __launch_bounds__(Shape<P>::NTP) k_ir_to_inner(CgVecArgs<float> A)
+{
+    using S = Shape<P>;
+    const LineCtx<P, float> c = line_ctx<P, float>(A);
+    if (!c.active) return;
+    const double mr = A.sc->mean_r, inv = 1.0 / A.sc->scale;
+#pragma unroll
+    for (int k = 0; k < S::n; ++k) {
+        const size_t gi = c.base + (size_t)k * S::NL;
+        A.r[gi] = (float)((A.src64[gi] - mr) * inv);
+    }
+}
+
+// x64 += scale * x32
+template <int P>
+__global__ void __launch_bounds__(Shape<P>::NTP) k_ir_accumulate(CgVecArgs<float> A)
+{
+    using S = Shape<P>;
+    const LineCtx<P, float> c = line_ctx<P, float>(A);
+    if (!c.active) return;
+    const double s = A.sc->scale;
+#pragma unroll
+    for (int k = 0; k < S::n; ++k) {
+        const size_t gi = c.base + (size_t)k * S::NL;
+        A.dst64[gi] = fma(s, (double)A.x[gi], A.dst64[gi]);
+    }
+}
+
+__global__ void k_f64_to_f32(const double *__restrict__ a, float *__restrict__ b, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        b[i] = (float)a[i];
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ launchers --
+
+template <typename F>
+static int with_P(int P, F &&f)
+{
+    switch (P) {
+        case 3: f(std::integral_constant<int, 3>{}); break;
+        case 4: f(std::integral_constant<int, 4>{}); break;
+        case 5: f(std::integral_constant<int, 5>{}); break;
+        case 6: f(std::integral_constant<int, 6>{}); break;
+        case 7: f(std::integral_constant<int, 7>{}); break;
+        case 8: f(std::integral_constant<int, 8>{}); break;
+        default: set_error("polynomial degree outside 3..8"); return DG_ERR_ARG;
+    }
+    DG_HIP_CHECK(hipGetLastError());
+    return DG_OK;
+}
+
+template <typename F>
+static void with_bool(bool b, F &&f)
+{
+    if (b) f(std::true_type{});
+    else f(std::false_type{});
+}
+
+static void fill_h(const MeshDev &m, CgVecArgs<double> &a)
+{
+    a.hx = m.h64;
+    a.hy = m.h64 + m.n[0];
+    a.hz = m.h64 + m.n[0] + m.n[1];
+}
+static void fill_h(const MeshDev &m, CgVecArgs<float> &a)
+{
+    a.hx = m.h32;
+    a.hy = m.h32 + m.n[0];
+    a.hz = m.h32 + m.n[0] + m.n[1];
+}
+
+template <typename T>
+static void prep(const MeshDev &m, CgVecArgs<T> &a)
+{
+    fill_h(m, a);
+    for (int d = 0; d < 3; ++d) a.n[d] = m.n[d];
+    a.nel = (int)m.nel;
+    a.ngroups = apply_groups(m.P, m.nel);
+}
+
+#define DG_GRID(PC) dim3(apply_groups(decltype(PC)::value, m.nel)), dim3(Shape<decltype(PC)::value>::NTP)
+
+template <typename T>
+int cg_setup(const MeshDev &m, CgVecArgs<T> a, hipStream_t s)
+{
+    prep(m, a);
+    return with_P(m.P, [&](auto PC) {
+        constexpr int P = decltype(PC)::value;
+        with_bool(a.singular, [&](auto SC) {
+            constexpr bool SG = decltype(SC)::value;
+            hipLaunchKernelGGL((k_setup1<P, T, SG>), DG_GRID(PC), 0, s, a);
+            hipLaunchKernelGGL((k_setup2<P, T, SG>), DG_GRID(PC), 0, s, a);
+        });
+    });
+}
+
+template <typename T>
+int cg_update(const MeshDev &m, CgVecArgs<T> a, hipStream_t s)
+{
+    prep(m, a);
+    return with_P(m.P, [&](auto PC) {
+        constexpr int P = decltype(PC)::value;
+        with_bool(a.singular, [&](auto SC) {
+            constexpr bool SG = decltype(SC)::value;
+            hipLaunchKernelGGL((k_update<P, T, SG>), DG_GRID(PC), 0, s, a);
+        });
+    });
+}
+
+template <typename T>
+int cg_pupdate(const MeshDev &m, CgVecArgs<T> a, hipStream_t s)
+{
+    prep(m, a);
+    return with_P(m.P, [&](auto PC) {
+        constexpr int P = decltype(PC)::value;
+        with_bool(a.singular, [&](auto SC) {
+            constexpr bool SG = decltype(SC)::value;
+            hipLaunchKernelGGL((k_pupdate<P, T, SG>), DG_GRID(PC), 0, s, a);
+        });
+    });
+}
+
+template <typename T>
+int cg_finish(const MeshDev &m, CgVecArgs<T> a, hipStream_t s)
+{
+    prep(m, a);
+    if (!a.singular) return DG_OK;
+    return with_P(m.P, [&](auto PC) {
+        constexpr int P = decltype(PC)::value;
+        hipLaunchKernelGGL((k_mean_x<P, T>), DG_GRID(PC), 0, s, a);
+        hipLaunchKernelGGL((k_shift_x<P, T>), DG_GRID(PC), 0, s, a);
+    });
+}
+
+int ir_scale(const MeshDev &m, CgVecArgs<float> a, hipStream_t s)
+{
+    prep(m, a);
+    return with_P(m.P, [&](auto PC) {
+        constexpr int P = decltype(PC)::value;
+        hipLaunchKernelGGL((k_ir_scale<P>), DG_GRID(PC), 0, s, a);
+    });
+}
+
+int ir_to_inner(const MeshDev &m, CgVecArgs<float> a, hipStream_t s)
+{
+    prep(m, a);
+    return with_P(m.P, [&](auto PC) {
+        constexpr int P = decltype(PC)::value;
+        hipLaunchKernelGGL((k_ir_to_inner<P>), DG_GRID(PC), 0, s, a);
+    });
+}
+
+int ir_accumulate(const MeshDev &m, CgVecArgs<float> a, hipStream_t s)
+{
+    prep(m, a);
+    return with_P(m.P, [&](auto PC) {
+        constexpr int P = decltype(PC)::value;
+        hipLaunchKernelGGL((k_ir_accumulate<P>), DG_GRID(PC), 0, s, a);
+    });
+}
+
+int convert_f64_to_f32(const double *a, float *b, size_t n, hipStream_t s)
+{
+    const size_t blocks = std::min<size_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_f64_to_f32, dim3((unsigned)std::max<size_t>(blocks, 1)), dim3(256), 0, s,
+                       a, b, n);
+    DG_HIP_CHECK(hipGetLastError());
+    return DG_OK;
+}
+
+template int cg_setup<double>(const MeshDev &, CgVecArgs<double>, hipStream_t);
+template int cg_setup<float>(const MeshDev &, CgVecArgs<float>, hipStream_t);
+template int cg_update<double>(const MeshDev &, CgVecArgs<double>, hipStream_t);
+template int cg_update<float>(const MeshDev &, CgVecArgs<float>, hipStream_t);
+template int cg_pupdate<double>(const MeshDev &, CgVecArgs<double>, hipStream_t);
+template int cg_pupdate<float>(const MeshDev &, CgVecArgs<float>, hipStream_t);
+template int cg_finish<double>(const MeshDev &, CgVecArgs<double>, hipStream_t);
+template int cg_finish<float>(const MeshDev &, CgVecArgs<float>, hipStream_t);
+
+}  // namespace dg

@@ -1,0 +1,69 @@
+// Internal declarations of the SIP-DG library (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "dg_sipdg.h"
+
+namespace dg {
+
+constexpr int kMaxN = 9;  // P <= 8
+constexpr int kMinPKernel = 3;
+constexpr int kMaxPKernel = 8;
+
+// thread-local error text behind dg_last_error()
+void set_error(const std::string &msg);
+
+#define DG_HIP_CHECK(expr)                                                        \
+    do {                                                                          \
+        hipError_t _e = (expr);                                                   \
+        if (_e != hipSuccess) {                                                   \
+            ::dg::set_error(std::string(#expr) + ": " + hipGetErrorString(_e));   \
+            return DG_ERR_DEVICE;                                                 \
+        }                                                                         \
+    } while (0)
+
+// 1D GLL tables of degree P (host, FP64), computed from their definitions.
+struct GllTables {
+    int P = 0;
+    std::vector<double> xi, w, D;  // D row-major (i, j) = l_j'(xi_i)
+    std::vector<double> K1;        // D^T diag(w) D (1D stiffness on [-1,1] without the 2/h factor)
+};
+GllTables make_gll(int P);
+
+// Geometry / BC description the kernels read (device pointers).
+template <typename T>
+struct Geo {
+    const T *h[3];   // element extents per axis (device)
+    int n[3];        // elements per axis
+    int bc[3];       // DG_BC_* per axis (after any Poisson BC mapping)
+};
+
+struct MeshDev {
+    int n[3];
+    int P;
+    int bc[3];
+    int64_t nel, ndof;
+    std::vector<double> v[3];  // host vertices
+    double *h64 = nullptr;     // device: hx | hy | hz
+    float *h32 = nullptr;
+};
+
+// --- kernel launchers (kernels_apply.hip) ---------------------------------
+// y = A x; T = double or float; nu == nullptr -> constant nu_c.
+// If partial != nullptr each work-group writes (x.y partial, sum(y) partial)
+// into partial[2*blk] and the last group reduces them into red_out[0..1]
+// (FP64, fixed order), using counter (zeroed, reset after use).
+template <typename T>
+int launch_apply(const MeshDev &m, const int bc[3], double lambda, const T *nu, double nu_c,
+                 const T *x, T *y, hipStream_t s);
+template <typename T>
+int launch_diag(const MeshDev &m, const int bc[3], double lambda, const T *nu, double nu_c, T *d,
+                hipStream_t s);
+int apply_groups(int P, int64_t nel);  // number of work-groups of the apply grid
+
+}  // namespace dg

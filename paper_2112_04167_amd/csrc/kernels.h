@@ -1,0 +1,105 @@
+// Device-side CG state and kernel launchers (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "dg_internal.h"
+
+namespace dg {
+
+// Scalars of one CG solve, resident in device memory.  Written only by the
+// last work-group of a reduction (one thread), read by every later kernel.
+struct CgScalars {
+    double rho;        // r.z of the current iterate
+    double alpha, beta;
+    double pq, sumq;   // p.Ap and sum(Ap) of the current step
+    double bnorm2;     // ||M^-1 b||^2
+    double res2;       // ||M^-1 r||^2 (recurrence; singular: of the projected r)
+    double tol2;       // tol^2 * bnorm2
+    double mean_r;     // singular: mean of r removed in the p-update
+    double mean_b;     // singular: mean of the load removed at set-up
+    double sum_invd;   // singular: sum 1/d
+    double sum_invM2;  // singular: sum 1/M^2
+    double shift;      // singular: M-weighted mean of x removed at the end
+    double true_res2;  // ||M^-1 (b - A x)||^2 of the last residual evaluation
+    double scale;      // mixed: scaling of the inner right-hand side
+    int iter, maxit, fixed_iters, done, status, singular;
+    long long ndof;
+    int pad[2];
+};
+
+// Device helpers called by the last work-group of a reduction.
+__device__ inline void cg_after_apply(CgScalars *sc, double pq, double sumq)
+{
+    sc->pq = pq;
+    sc->sumq = sumq;
+    if (!isfinite(pq)) {
+        sc->status = DG_ERR_NONFINITE;
+        sc->done = 1;
+    } else if (pq <= 0.0) {
+        sc->status = DG_ERR_NOT_SPD;
+        sc->done = 1;
+    } else {
+        sc->alpha = sc->rho / pq;
+    }
+}
+
+__device__ inline void resid_finish(CgScalars *sc, const double (&t)[4])
+{
+    // t = {sum (r/M)^2, sum r, sum r/M^2, sum 1/M^2}
+    double res2 = t[0];
+    if (sc->singular) {
+        const double m = t[1] / (double)sc->ndof;
+        res2 = t[0] - 2.0 * m * t[2] + m * m * t[3];
+        sc->mean_r = m;
+    } else {
+        sc->mean_r = 0.0;
+    }
+    sc->true_res2 = res2 > 0.0 ? res2 : 0.0;
+}
+
+template <typename T>
+int launch_apply_cg(const MeshDev &m, const int bc[3], double lambda, const T *nu, double nu_c,
+                    const T *p, T *q, double *partial, unsigned *counter, CgScalars *sc,
+                    hipStream_t s);
+template <typename T>
+int launch_resid(const MeshDev &m, const int bc[3], double lambda, const T *nu, double nu_c,
+                 const T *x, const T *b, T *r, double *partial, unsigned *counter, CgScalars *sc,
+                 hipStream_t s);
+int apply_threads(int P);
+
+// CG vector kernels (element/line mapped, FP64 reductions)
+template <typename T>
+struct CgVecArgs {
+    T *x, *r, *p;
+    const T *q, *d;
+    const T *src;       // set-up: rhs (nodal f or weak b); convert: FP64 source
+    T *bvec;            // set-up: the load vector b
+    const double *src64;
+    double *dst64;
+    const T *hx, *hy, *hz;
+    int n[3];
+    int nel, ngroups;
+    int weak;
+    bool singular;      // host-side: selects the singular (projected) kernels
+    double *partial;
+    unsigned *counter;
+    CgScalars *sc;
+};
+
+const GllTables &gll_cached(int P);
+
+template <typename T>
+int cg_setup(const MeshDev &m, CgVecArgs<T> a, hipStream_t s);   // b, r, z, p, x = 0, norms
+template <typename T>
+int cg_update(const MeshDev &m, CgVecArgs<T> a, hipStream_t s);  // x, r and the new rho
+template <typename T>
+int cg_pupdate(const MeshDev &m, CgVecArgs<T> a, hipStream_t s); // p = z + beta p
+template <typename T>
+int cg_finish(const MeshDev &m, CgVecArgs<T> a, hipStream_t s);  // singular: x -= M-mean
+// mixed precision: r32 = (r64 - mean_r) / scale (scale = max |.|), and x64 += scale * d32
+int convert_f64_to_f32(const double *a, float *b, size_t n, hipStream_t s);
+int ir_scale(const MeshDev &m, CgVecArgs<float> a, hipStream_t s);      // sc->scale = RMS(src64 - mean_r)
+int ir_to_inner(const MeshDev &m, CgVecArgs<float> a, hipStream_t s);   // r = (src64 - mean_r)/scale
+int ir_accumulate(const MeshDev &m, CgVecArgs<float> a, hipStream_t s); // dst64 += scale * x
+
+}  // namespace dg

@@ -1,0 +1,545 @@
+// C-ABI entry points: meshes, the matrix-free apply, and the Jacobi-PCG /
+// mixed-precision refinement drivers (host side).
+//
+// The drivers enqueue whole CG iterations (apply, update, p-update) in
+// chunks; the device keeps every scalar and flags completion itself, so the
+// host reads the solver state back once per chunk only.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+
+#include "dg_internal.h"
+#include "kernels.h"
+
+namespace dg {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+const GllTables &gll_cached(int P)
+{
+    static std::mutex mu;
+    static std::map<int, std::unique_ptr<GllTables>> cache;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(P);
+    if (it == cache.end()) it = cache.emplace(P, std::make_unique<GllTables>(make_gll(P))).first;
+    return *it->second;
+}
+
+}  // namespace dg
+
+using namespace dg;
+
+// Workspace of one mesh: FP64 CG vectors, FP32 inner vectors, reduction
+// scratch and the device scalar blocks.
+struct Workspace {
+    size_t bytes = 0;
+    void *base = nullptr;
+    int64_t ndof = 0;
+    int precision = -1;
+    double *r64 = nullptr, *p64 = nullptr, *q64 = nullptr, *d64 = nullptr, *b64 = nullptr;
+    float *x32 = nullptr, *r32 = nullptr, *p32 = nullptr, *q32 = nullptr, *d32 = nullptr,
+          *b32 = nullptr, *nu32 = nullptr;
+    double *partial = nullptr;
+    unsigned *counter = nullptr;
+    CgScalars *sc = nullptr;      // [0] outer / FP64, [1] inner FP32
+    CgScalars *host_sc = nullptr; // pinned
+};
+
+struct dg_mesh {
+    MeshDev dev;
+    hipStream_t stream = nullptr;
+    Workspace ws;
+};
+
+namespace {
+
+size_t partial_doubles(const MeshDev &m) { return (size_t)apply_groups(m.P, m.nel) * 6 + 64; }
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+size_t footprint(const MeshDev &m, int precision)
+{
+    const size_t N = (size_t)m.ndof;
+    size_t b = 0;
+    b += 5 * align256(N * sizeof(double));  // r, p, q, d, b (FP64)
+    if (precision == DG_MIXED) b += 7 * align256(N * sizeof(float));
+    b += align256(partial_doubles(m) * sizeof(double));
+    b += align256(256) + align256(2 * sizeof(CgScalars));
+    return b;
+}
+
+int ensure_workspace(dg_mesh *m, int precision)
+{
+    Workspace &w = m->ws;
+    const size_t need = footprint(m->dev, precision);
+    if (w.base && w.bytes >= need && w.ndof == m->dev.ndof &&
+        (precision != DG_MIXED || w.precision == DG_MIXED))
+        return DG_OK;
+    if (w.base) {
+        DG_HIP_CHECK(hipStreamSynchronize(m->stream));
+        DG_HIP_CHECK(hipFree(w.base));
+        w.base = nullptr;
+    }
+    if (!w.host_sc) DG_HIP_CHECK(hipHostMalloc((void **)&w.host_sc, 2 * sizeof(CgScalars), 0));
+    hipError_t e = hipMalloc(&w.base, need);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("workspace allocation of " + std::to_string(need) + " bytes failed");
+        w.base = nullptr;
+        return DG_ERR_OOM;
+    }
+    w.bytes = need;
+    w.ndof = m->dev.ndof;
+    w.precision = precision;
+    char *p = (char *)w.base;
+    const size_t N = (size_t)m->dev.ndof;
+    auto take = [&](size_t bytes) {
+        char *r = p;
+        p += align256(bytes);
+        return (void *)r;
+    };
+    w.r64 = (double *)take(N * 8);
+    w.p64 = (double *)take(N * 8);
+    w.q64 = (double *)take(N * 8);
+    w.d64 = (double *)take(N * 8);
+    w.b64 = (double *)take(N * 8);
+    if (precision == DG_MIXED) {
+        w.x32 = (float *)take(N * 4);
+        w.r32 = (float *)take(N * 4);
+        w.p32 = (float *)take(N * 4);
+        w.q32 = (float *)take(N * 4);
+        w.d32 = (float *)take(N * 4);
+        w.b32 = (float *)take(N * 4);
+        w.nu32 = (float *)take(N * 4);
+    } else {
+        w.x32 = w.r32 = w.p32 = w.q32 = w.d32 = w.b32 = w.nu32 = nullptr;
+    }
+    w.partial = (double *)take(partial_doubles(m->dev) * 8);
+    w.counter = (unsigned *)take(256);
+    w.sc = (CgScalars *)take(2 * sizeof(CgScalars));
+    DG_HIP_CHECK(hipMemsetAsync(w.counter, 0, 256, m->stream));
+    return DG_OK;
+}
+
+CgScalars init_scalars(const MeshDev &m, double tol, int maxit, int fixed_iters, bool singular)
+{
+    CgScalars s;
+    std::memset(&s, 0, sizeof(s));
+    s.tol2 = tol * tol;
+    s.maxit = maxit;
+    s.fixed_iters = fixed_iters;
+    s.singular = singular ? 1 : 0;
+    s.ndof = m.ndof;
+    s.status = DG_OK;
+    return s;
+}
+
+bool has_dirichlet(const int bc[3])
+{
+    return bc[0] == DG_BC_DIRICHLET || bc[1] == DG_BC_DIRICHLET || bc[2] == DG_BC_DIRICHLET;
+}
+
+template <typename T>
+CgVecArgs<T> vec_args(const Workspace &w, bool singular, CgScalars *sc)
+{
+    CgVecArgs<T> a{};
+    a.partial = w.partial;
+    a.counter = w.counter;
+    a.sc = sc;
+    a.singular = singular;
+    return a;
+}
+
+double now()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Run CG iterations until the device flags completion.  T: vector type.
+template <typename T>
+int cg_iterate(dg_mesh *m, const int bc[3], double lambda, const T *nu, double nu_c,
+               CgVecArgs<T> a, CgScalars *dev_sc, CgScalars *host_sc, int cap_hint)
+{
+    const MeshDev &md = m->dev;
+    hipStream_t s = m->stream;
+    int chunk = 4;
+    int launched = 0;
+    for (;;) {
+        for (int k = 0; k < chunk; ++k) {
+            int rc = launch_apply_cg<T>(md, bc, lambda, nu, nu_c, a.p, const_cast<T *>(a.q),
+                                        a.partial, a.counter, dev_sc, s);
+            if (rc) return rc;
+            if ((rc = cg_update<T>(md, a, s))) return rc;
+            if ((rc = cg_pupdate<T>(md, a, s))) return rc;
+        }
+        launched += chunk;
+        DG_HIP_CHECK(hipMemcpyAsync(host_sc, dev_sc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
+        DG_HIP_CHECK(hipStreamSynchronize(s));
+        if (host_sc->done) break;
+        if (launched > cap_hint + 64) {
+            set_error("CG did not flag completion");
+            return DG_ERR_DEVICE;
+        }
+        chunk = std::min(chunk * 2, 64);
+    }
+    return DG_OK;
+}
+
+int check_mesh(dg_mesh *m)
+{
+    if (!m) {
+        set_error("null mesh");
+        return DG_ERR_ARG;
+    }
+    return DG_OK;
+}
+
+// FP64 Jacobi-PCG
+int solve_fp64(dg_mesh *m, const int bc[3], double lambda, const double *nu, double nu_c,
+               const double *rhs, double *x, const dg_solve_opts &o, dg_solve_info &info)
+{
+    int rc = ensure_workspace(m, DG_FP64);
+    if (rc) return rc;
+    Workspace &w = m->ws;
+    const MeshDev &md = m->dev;
+    hipStream_t s = m->stream;
+    const bool singular = (lambda == 0.0) && !has_dirichlet(bc);
+    CgScalars init = init_scalars(md, o.tol, o.maxit, o.fixed_iters, singular);
+    *w.host_sc = init;
+    DG_HIP_CHECK(hipMemcpyAsync(w.sc, w.host_sc, sizeof(CgScalars), hipMemcpyHostToDevice, s));
+    if ((rc = launch_diag<double>(md, bc, lambda, nu, nu_c, w.d64, s))) return rc;
+    CgVecArgs<double> a = vec_args<double>(w, singular, w.sc);
+    a.x = x;
+    a.r = w.r64;
+    a.p = w.p64;
+    a.q = w.q64;
+    a.d = w.d64;
+    a.src = rhs;
+    a.bvec = w.b64;
+    a.weak = o.rhs_is_weak;
+    if ((rc = cg_setup<double>(md, a, s))) return rc;
+    const int cap = o.fixed_iters > 0 ? o.fixed_iters : o.maxit;
+    if ((rc = cg_iterate<double>(m, bc, lambda, nu, nu_c, a, w.sc, w.host_sc, cap))) return rc;
+    if ((rc = cg_finish<double>(md, a, s))) return rc;
+    // true residual from x
+    if ((rc = launch_resid<double>(md, bc, lambda, nu, nu_c, x, w.b64, w.q64, w.partial, w.counter,
+                                   w.sc, s)))
+        return rc;
+    DG_HIP_CHECK(hipMemcpyAsync(w.host_sc, w.sc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
+    DG_HIP_CHECK(hipStreamSynchronize(s));
+    const CgScalars &h = *w.host_sc;
+    info.iters = h.iter;
+    info.outer_iters = 0;
+    info.status = h.status;
+    info.rel_res = h.bnorm2 > 0 ? std::sqrt(h.res2 / h.bnorm2) : 0.0;
+    info.true_rel_res = h.bnorm2 > 0 ? std::sqrt(h.true_res2 / h.bnorm2) : 0.0;
+    return h.status;
+}
+
+// FP64 iterative refinement around FP32 Jacobi-PCG
+int solve_mixed(dg_mesh *m, const int bc[3], double lambda, const double *nu, double nu_c,
+                const double *rhs, double *x, const dg_solve_opts &o, dg_solve_info &info)
+{
+    int rc = ensure_workspace(m, DG_MIXED);
+    if (rc) return rc;
+    Workspace &w = m->ws;
+    const MeshDev &md = m->dev;
+    hipStream_t s = m->stream;
+    const bool singular = (lambda == 0.0) && !has_dirichlet(bc);
+    const size_t N = (size_t)md.ndof;
+    CgScalars *osc = w.sc, *isc = w.sc + 1;
+    CgScalars *hosc = w.host_sc, *hisc = w.host_sc + 1;
+
+    // FP32 operator data
+    const float *nu32 = nullptr;
+    if (nu) {
+        if ((rc = convert_f64_to_f32(nu, w.nu32, N, s))) return rc;
+        nu32 = w.nu32;
+    }
+    if ((rc = launch_diag<float>(md, bc, lambda, nu32, nu_c, w.d32, s))) return rc;
+
+    // outer set-up: b (projected), r = b, x = 0, ||M^-1 b||
+    *hosc = init_scalars(md, o.tol, o.maxit, 0, singular);
+    DG_HIP_CHECK(hipMemcpyAsync(osc, hosc, sizeof(CgScalars), hipMemcpyHostToDevice, s));
+    CgVecArgs<double> oa = vec_args<double>(w, singular, osc);
+    oa.x = x;
+    oa.r = w.r64;
+    oa.p = nullptr;
+    oa.q = nullptr;
+    oa.d = nullptr;
+    oa.src = rhs;
+    oa.bvec = w.b64;
+    oa.weak = o.rhs_is_weak;
+    if ((rc = cg_setup<double>(md, oa, s))) return rc;
+    DG_HIP_CHECK(hipMemcpyAsync(hosc, osc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
+    DG_HIP_CHECK(hipStreamSynchronize(s));
+    const double bnorm2 = hosc->bnorm2;
+    const double tol2 = o.tol * o.tol * bnorm2;
+    int status = hosc->status;
+    double res2 = bnorm2;
+    int outer = 0, inner_total = 0;
+    while (status == DG_OK && bnorm2 > 0.0 && res2 > tol2) {
+        if (outer >= o.maxit) {
+            status = DG_NOT_CONVERGED;
+            break;
+        }
+        // inner right-hand side r32 = (r64 - mean_r) / scale (mean_r set by the residual)
+        CgVecArgs<float> ia = vec_args<float>(w, singular, osc);
+        ia.src64 = w.r64;
+        ia.r = w.b32;
+        if ((rc = ir_scale(md, ia, s))) return rc;
+        if ((rc = ir_to_inner(md, ia, s))) return rc;
+        // inner FP32 PCG on A32 d = r32 (weak right-hand side)
+        *hisc = init_scalars(md, o.inner_tol, o.inner_maxit, 0, singular);
+        DG_HIP_CHECK(hipMemcpyAsync(isc, hisc, sizeof(CgScalars), hipMemcpyHostToDevice, s));
+        CgVecArgs<float> ca = vec_args<float>(w, singular, isc);
+        ca.x = w.x32;
+        ca.r = w.r32;
+        ca.p = w.p32;
+        ca.q = w.q32;
+        ca.d = w.d32;
+        ca.src = w.b32;
+        ca.bvec = w.b32;  // in place (already weak)
+        ca.weak = 1;
+        if ((rc = cg_setup<float>(md, ca, s))) return rc;
+        if ((rc = cg_iterate<float>(m, bc, lambda, nu32, nu_c, ca, isc, hisc, o.inner_maxit)))
+            return rc;
+        inner_total += hisc->iter;
+        if (hisc->status < 0 && hisc->status != DG_ERR_NOT_SPD) {
+            status = hisc->status;
+            break;
+        }
+        // x64 += scale * x32 ; r64 = b - A64 x64 (projected), ||M^-1 r||
+        CgVecArgs<float> acc = vec_args<float>(w, singular, osc);
+        acc.x = w.x32;
+        acc.dst64 = x;
+        if ((rc = ir_accumulate(md, acc, s))) return rc;
+        if ((rc = launch_resid<double>(md, bc, lambda, nu, nu_c, x, w.b64, w.r64, w.partial,
+                                       w.counter, osc, s)))
+            return rc;
+        DG_HIP_CHECK(hipMemcpyAsync(hosc, osc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
+        DG_HIP_CHECK(hipStreamSynchronize(s));
+        res2 = hosc->true_res2;
+        ++outer;
+        if (!std::isfinite(res2)) status = DG_ERR_NONFINITE;
+    }
+    if (singular) {
+        if ((rc = cg_finish<double>(md, oa, s))) return rc;
+        if ((rc = launch_resid<double>(md, bc, lambda, nu, nu_c, x, w.b64, w.r64, w.partial,
+                                       w.counter, osc, s)))
+            return rc;
+        DG_HIP_CHECK(hipMemcpyAsync(hosc, osc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
+        DG_HIP_CHECK(hipStreamSynchronize(s));
+        res2 = hosc->true_res2;
+    }
+    info.iters = inner_total;
+    info.outer_iters = outer;
+    info.status = status;
+    info.rel_res = bnorm2 > 0 ? std::sqrt(res2 / bnorm2) : 0.0;
+    info.true_rel_res = info.rel_res;
+    return status;
+}
+
+int solve_common(dg_mesh *m, const int bc[3], double lambda, const double *nu, double nu_c,
+                 const double *rhs, double *x, const dg_solve_opts *opts, dg_solve_info *info)
+{
+    const double t0 = now();
+    if (int rc = check_mesh(m)) return rc;
+    dg_solve_opts o;
+    dg_default_opts(&o);
+    if (opts) o = *opts;
+    if (!rhs || !x || (const void *)rhs == (const void *)x) {
+        set_error("rhs and x must be distinct device arrays");
+        return DG_ERR_ARG;
+    }
+    if (!(lambda >= 0.0) || !std::isfinite(lambda) || (!nu && !(nu_c > 0.0))) {
+        set_error("lambda must be >= 0 and nu > 0");
+        return DG_ERR_ARG;
+    }
+    if (!(o.tol > 0.0) || o.maxit < 0 || (o.precision != DG_FP64 && o.precision != DG_MIXED)) {
+        set_error("bad solver options");
+        return DG_ERR_ARG;
+    }
+    dg_solve_info inf{};
+    int rc;
+    if (o.precision == DG_MIXED) {
+        if (!(o.inner_tol > 0.0 && o.inner_tol < 1.0) || o.inner_maxit <= 0) {
+            set_error("bad inner solver options");
+            return DG_ERR_ARG;
+        }
+        rc = solve_mixed(m, bc, lambda, nu, nu_c, rhs, x, o, inf);
+    } else {
+        rc = solve_fp64(m, bc, lambda, nu, nu_c, rhs, x, o, inf);
+    }
+    inf.seconds = now() - t0;
+    if (rc < 0 && g_last_error.empty()) set_error("solver error " + std::to_string(rc));
+    if (rc == DG_ERR_NOT_SPD) set_error("CG breakdown: p^T A p <= 0");
+    if (rc == DG_ERR_NONFINITE) set_error("non-finite value in the data or the iteration");
+    if (info) *info = inf;
+    return rc;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- C-ABI --
+
+extern "C" {
+
+const char *dg_last_error(void) { return g_last_error.c_str(); }
+
+void dg_default_opts(dg_solve_opts *o)
+{
+    if (!o) return;
+    o->tol = 1e-10;
+    o->maxit = 100000;
+    o->precision = DG_FP64;
+    o->inner_tol = 1e-4;
+    o->inner_maxit = 20000;
+    o->rhs_is_weak = 0;
+    o->fixed_iters = 0;
+}
+
+int dg_mesh_create(int nx, int ny, int nz, int P, const double *xv, const double *yv,
+                   const double *zv, const int bc[3], void *hip_stream, dg_mesh **out)
+{
+    g_last_error.clear();
+    if (!out || !xv || !yv || !zv || !bc) {
+        set_error("null argument");
+        return DG_ERR_ARG;
+    }
+    *out = nullptr;
+    if (nx < 1 || ny < 1 || nz < 1 || P < kMinPKernel || P > kMaxPKernel) {
+        set_error("need n >= 1 per axis and 3 <= P <= 8");
+        return DG_ERR_ARG;
+    }
+    const int64_t nel = (int64_t)nx * ny * nz;
+    const int64_t ndof = nel * (P + 1) * (P + 1) * (P + 1);
+    if (ndof >= (int64_t)1 << 31) {
+        set_error("mesh too large (>= 2^31 nodes)");
+        return DG_ERR_ARG;
+    }
+    const int nn[3] = {nx, ny, nz};
+    const double *vv[3] = {xv, yv, zv};
+    for (int d = 0; d < 3; ++d) {
+        if (bc[d] != DG_BC_PERIODIC && bc[d] != DG_BC_DIRICHLET && bc[d] != DG_BC_NEUMANN) {
+            set_error("bad boundary condition code");
+            return DG_ERR_ARG;
+        }
+        for (int k = 0; k < nn[d]; ++k)
+            if (!(vv[d][k + 1] > vv[d][k]) || !std::isfinite(vv[d][k + 1] - vv[d][k])) {
+                set_error("vertices must be finite and strictly increasing");
+                return DG_ERR_ARG;
+            }
+    }
+    auto m = std::make_unique<dg_mesh>();
+    MeshDev &d = m->dev;
+    d.P = P;
+    d.nel = nel;
+    d.ndof = ndof;
+    for (int k = 0; k < 3; ++k) {
+        d.n[k] = nn[k];
+        d.bc[k] = bc[k];
+        d.v[k].assign(vv[k], vv[k] + nn[k] + 1);
+    }
+    m->stream = (hipStream_t)hip_stream;
+    std::vector<double> h;
+    for (int k = 0; k < 3; ++k)
+        for (int e = 0; e < nn[k]; ++e) h.push_back(d.v[k][e + 1] - d.v[k][e]);
+    std::vector<float> hf(h.begin(), h.end());
+    DG_HIP_CHECK(hipMalloc((void **)&d.h64, h.size() * sizeof(double)));
+    DG_HIP_CHECK(hipMalloc((void **)&d.h32, hf.size() * sizeof(float)));
+    DG_HIP_CHECK(hipMemcpy(d.h64, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+    DG_HIP_CHECK(hipMemcpy(d.h32, hf.data(), hf.size() * sizeof(float), hipMemcpyHostToDevice));
+    (void)gll_cached(P);
+    *out = m.release();
+    return DG_OK;
+}
+
+int dg_mesh_destroy(dg_mesh *m)
+{
+    if (!m) return DG_OK;
+    (void)hipStreamSynchronize(m->stream);
+    if (m->ws.base) (void)hipFree(m->ws.base);
+    if (m->ws.host_sc) (void)hipHostFree(m->ws.host_sc);
+    if (m->dev.h64) (void)hipFree(m->dev.h64);
+    if (m->dev.h32) (void)hipFree(m->dev.h32);
+    delete m;
+    return DG_OK;
+}
+
+int64_t dg_mesh_ndof(const dg_mesh *m) { return m ? m->dev.ndof : -1; }
+
+size_t dg_solve_footprint(const dg_mesh *m, int precision, int nrhs)
+{
+    if (!m) return 0;
+    return footprint(m->dev, precision) * (size_t)std::max(1, nrhs);
+}
+
+int helmholtz_apply(dg_mesh *m, double lambda, const void *nu_field, double nu_const,
+                    const void *x, void *y, int precision, void *stream)
+{
+    if (int rc = check_mesh(m)) return rc;
+    if (!x || !y || x == y) {
+        set_error("x and y must be distinct device arrays");
+        return DG_ERR_ARG;
+    }
+    if (!nu_field && !(nu_const > 0.0)) {
+        set_error("nu_const must be > 0 without a nu field");
+        return DG_ERR_ARG;
+    }
+    hipStream_t s = stream ? (hipStream_t)stream : m->stream;
+    if (precision == DG_FP64)
+        return launch_apply<double>(m->dev, m->dev.bc, lambda, (const double *)nu_field, nu_const,
+                                    (const double *)x, (double *)y, s);
+    if (precision == DG_FP32)
+        return launch_apply<float>(m->dev, m->dev.bc, lambda, (const float *)nu_field, nu_const,
+                                   (const float *)x, (float *)y, s);
+    set_error("precision must be DG_FP64 or DG_FP32");
+    return DG_ERR_ARG;
+}
+
+int helmholtz_diag(dg_mesh *m, double lambda, const void *nu_field, double nu_const, void *dout,
+                   int precision, void *stream)
+{
+    if (int rc = check_mesh(m)) return rc;
+    if (!dout || (!nu_field && !(nu_const > 0.0))) {
+        set_error("bad arguments");
+        return DG_ERR_ARG;
+    }
+    hipStream_t s = stream ? (hipStream_t)stream : m->stream;
+    if (precision == DG_FP64)
+        return launch_diag<double>(m->dev, m->dev.bc, lambda, (const double *)nu_field, nu_const,
+                                   (double *)dout, s);
+    if (precision == DG_FP32)
+        return launch_diag<float>(m->dev, m->dev.bc, lambda, (const float *)nu_field, nu_const,
+                                  (float *)dout, s);
+    set_error("precision must be DG_FP64 or DG_FP32");
+    return DG_ERR_ARG;
+}
+
+int helmholtz_solve(dg_mesh *m, double lambda, const double *nu_field, double nu_const,
+                    const double *rhs, double *x, const dg_solve_opts *opts, dg_solve_info *info)
+{
+    if (int rc = check_mesh(m)) return rc;
+    return solve_common(m, m->dev.bc, lambda, nu_field, nu_const, rhs, x, opts, info);
+}
+
+int poisson_solve(dg_mesh *m, const double *rhs, double *x, const dg_solve_opts *opts,
+                  dg_solve_info *info)
+{
+    if (int rc = check_mesh(m)) return rc;
+    int bc[3];
+    for (int d = 0; d < 3; ++d)
+        bc[d] = m->dev.bc[d] == DG_BC_DIRICHLET ? DG_BC_NEUMANN : m->dev.bc[d];
+    return solve_common(m, bc, 0.0, nullptr, 1.0, rhs, x, opts, info);
+}
+
+}  // extern "C"

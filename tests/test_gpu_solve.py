@@ -1,0 +1,229 @@
+"""GPU parity of the Jacobi-PCG Helmholtz / Poisson solves (FP64) and of the
+mixed-precision refinement against the oracle.
+
+Checks (rule: ||M^-1 r|| <= tol ||M^-1 b||, tol = 1e-10, Sec. 4 of the paper):
+  * against the exact discrete solution x* (fast diagonalisation or dense
+    Cholesky): ||x - x*|| <= 1e-10 ||x*|| where the conditioning allows it;
+  * against the oracle's own PCG: same iteration count (+-1) and, in the
+    iteration-locked mode (fixed_iters), ||x - x_oracle|| <= 1e-11 ||x_oracle||;
+  * the true residual recomputed from x;
+  * status codes of the failure modes."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import dense, kron, naive, pcg
+from tests.gpu_util import say, to_dev, torch_dev
+from tests.helpers import make_spec, ndof, manufactured_u, channel_nu
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_solve(spec, lam, nu, f, poisson=False, **opts):
+    import paper_2112_04167_amd as dg
+    torch, dev = torch_dev()
+    mesh = dg.mesh_from_spec(spec)
+    fd = to_dev(f)
+    xd = torch.zeros_like(fd)
+    o = dg.default_opts(**opts)
+    if poisson:
+        info = dg.poisson_solve(mesh, fd, xd, o, raise_on_error=False)
+    else:
+        nud = None if np.isscalar(nu) else to_dev(nu)
+        info = dg.helmholtz_solve(mesh, lam, nud, nu if np.isscalar(nu) else 0.0, fd, xd, o,
+                                  raise_on_error=False)
+    x = xd.cpu().numpy()
+    mesh.destroy()
+    return x, info
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def test_small_periodic_manufactured():
+    spec = synth.mesh_spec("small_periodic")
+    lam = 1.0
+    u = manufactured_u(spec)
+    f = (lam + 12 * np.pi ** 2) * u
+    x, info = gpu_solve(spec, lam, 1.0, f)
+    say("small periodic manufactured", info)
+    assert info["status"] == 0
+    xs = kron.FDM(spec, lam).solve(dense.mass_diag(spec) * f)
+    assert rel(x, xs) <= 1e-10
+    assert info["true_rel_res"] <= 1e-10
+    # discretisation error vs the PDE solution: the M-norm error of x must be
+    # that of x* (4.09e-5 for n=4, P=4, lambda=nu=1; order P+1 in the oracle pins)
+    M = dense.mass_diag(spec)
+    em = np.sqrt(np.dot(M, (x - u) ** 2))
+    es = np.sqrt(np.dot(M, (xs - u) ** 2))
+    assert es < 5e-5 and abs(em - es) <= 1e-6 * es
+
+
+def test_small_periodic_random_matches_oracle_pcg():
+    spec = synth.mesh_spec("small_periodic")
+    f = synth.uniform_field(ndof(spec), 0)
+    x, info = gpu_solve(spec, 1.0, 1.0, f)
+    op = naive.Operator(spec, 1.0, 1.0)
+    M = dense.mass_diag(spec)
+    xo, io = pcg.pcg(op.apply, M * f, op.diag(), M, tol=1e-10)
+    say("small periodic random", info, "oracle iters", io["iters"])
+    assert abs(info["iters"] - io["iters"]) <= 1
+    xs = kron.FDM(spec, 1.0).solve(M * f)
+    assert rel(x, xs) <= 1e-10
+    assert rel(x, xo) <= 1e-10
+    # the recomputed residual of the GPU result, by the oracle
+    assert pcg.true_rel_res(op.apply, x, M * f, M) <= 1.2e-10
+
+
+@pytest.mark.parametrize("k", [1, 7, 40])
+def test_iteration_locked(k):
+    spec = make_spec((3, 2, 2), 5, (0, 1, 2), True)
+    f = synth.uniform_field(ndof(spec), 9)
+    lam = 30.0
+    x, info = gpu_solve(spec, lam, 1.0, f, fixed_iters=k)
+    assert info["iters"] == k
+    op = naive.Operator(spec, lam, 1.0)
+    M = dense.mass_diag(spec)
+    xo, io = pcg.pcg(op.apply, M * f, op.diag(), M, fixed_iters=k)
+    assert rel(x, xo) <= 1e-11
+
+
+def test_nodal_nu_against_cholesky():
+    spec = make_spec((2, 2, 2), 4, (0, 0, 1), False)
+    nu = channel_nu(spec, 1.0)
+    lam = 50.0
+    f = synth.uniform_field(ndof(spec), 17)
+    x, info = gpu_solve(spec, lam, nu, f)
+    A = dense.assemble(spec, lam, nu)
+    M = dense.mass_diag(spec)
+    xs = dense.solve(spec, A, M * f, lam)
+    assert info["status"] == 0
+    assert rel(x, xs) <= 1e-10
+
+
+def test_nodal_nu_iteration_locked():
+    spec = make_spec((3, 3, 2), 5, (0, 0, 1), False)
+    nu = channel_nu(spec)
+    lam = synth.batched_lambda()
+    f = synth.uniform_field(ndof(spec), 41)
+    x, info = gpu_solve(spec, lam, nu, f, fixed_iters=6)
+    op = naive.Operator(spec, lam, nu)
+    M = dense.mass_diag(spec)
+    xo, _ = pcg.pcg(op.apply, M * f, op.diag(), M, fixed_iters=6)
+    assert rel(x, xo) <= 1e-11
+
+
+def test_singular_poisson_small():
+    spec = make_spec((3, 3, 2), 3, (0, 1, 0), True)   # Dirichlet y becomes Neumann
+    f = synth.uniform_field(ndof(spec), 3)
+    x, info = gpu_solve(spec, 0.0, 1.0, f, poisson=True, tol=1e-11)
+    say("poisson small", info)
+    assert info["status"] == 0
+    pspec = dict(spec)
+    pspec["bc"] = (0, 2, 0)
+    M = dense.mass_diag(pspec)
+    xs = kron.FDM(pspec, 0.0).solve(M * f)
+    assert rel(x, xs) <= 1e-8
+    assert abs(np.dot(M, x)) <= 1e-12 * np.linalg.norm(x)
+    op = naive.Operator(pspec, 0.0, 1.0)
+    xo, io = pcg.pcg(op.apply, M * f, op.diag(), M, tol=1e-11, singular=True)
+    assert abs(info["iters"] - io["iters"]) <= 2
+    assert rel(x, xo) <= 1e-9
+
+
+def test_singular_poisson_iteration_locked():
+    spec = make_spec((2, 3, 2), 4, (0, 2, 0), False)
+    f = synth.uniform_field(ndof(spec), 8)
+    x, info = gpu_solve(spec, 0.0, 1.0, f, poisson=True, fixed_iters=25)
+    op = naive.Operator(spec, 0.0, 1.0)
+    M = dense.mass_diag(spec)
+    xo, _ = pcg.pcg(op.apply, M * f, op.diag(), M, fixed_iters=25, singular=True)
+    assert rel(x, xo) <= 1e-11
+
+
+def test_dirichlet_stretched_large_lambda():
+    n = 6
+    spec = synth.scaled_mesh_spec("stretched_large", n)
+    lam = synth.large_helmholtz_lambda()
+    f = synth.uniform_field(ndof(spec), 21120)
+    x, info = gpu_solve(spec, lam, 1.0, f)
+    say("stretched dirichlet", info)
+    xs = kron.FDM(spec, lam).solve(dense.mass_diag(spec) * f)
+    assert info["status"] == 0
+    assert rel(x, xs) <= 1e-10
+
+
+def test_maxit_returns_last_iterate():
+    spec = make_spec((2, 2, 2), 4, (0, 0, 0), False)
+    f = synth.uniform_field(ndof(spec), 1)
+    x, info = gpu_solve(spec, 1.0, 1.0, f, maxit=3, tol=1e-12)
+    assert info["rc"] == 1 and info["status"] == 1 and info["iters"] == 3
+    op = naive.Operator(spec, 1.0, 1.0)
+    M = dense.mass_diag(spec)
+    xo, io = pcg.pcg(op.apply, M * f, op.diag(), M, tol=1e-12, maxit=3)
+    assert io["status"] == pcg.NOT_CONVERGED
+    assert rel(x, xo) <= 1e-12
+
+
+def test_nonfinite_rhs():
+    spec = make_spec((2, 2, 2), 4, (0, 0, 0), False)
+    f = synth.uniform_field(ndof(spec), 1)
+    f[17] = np.nan
+    _, info = gpu_solve(spec, 1.0, 1.0, f)
+    assert info["rc"] == -5
+
+
+def test_bad_arguments():
+    spec = make_spec((2, 2, 2), 4, (0, 0, 0), False)
+    f = synth.uniform_field(ndof(spec), 1)
+    _, info = gpu_solve(spec, -1.0, 1.0, f)
+    assert info["rc"] == -1
+
+
+def test_solve_bitwise_deterministic():
+    spec = synth.mesh_spec("small_periodic")
+    f = synth.uniform_field(ndof(spec), 4)
+    x1, _ = gpu_solve(spec, 1.0, 1.0, f)
+    x2, _ = gpu_solve(spec, 1.0, 1.0, f)
+    assert np.array_equal(x1, x2)
+
+
+@pytest.mark.parametrize("lam", [1e2, 1e4, 1e6])
+def test_mixed_precision_small(lam):
+    spec = synth.mesh_spec("mixed_small")
+    u = manufactured_u(spec)
+    f = (lam + 12 * np.pi ** 2) * u + synth.uniform_field(ndof(spec), synth.SEEDS["mixed"])
+    x, info = gpu_solve(spec, lam, 1.0, f, precision=1)
+    M = dense.mass_diag(spec)
+    xs = kron.FDM(spec, lam).solve(M * f)
+    e = rel(x, xs)
+    say("mixed lam=%g" % lam, info, "err vs x*", e)
+    assert info["status"] == 0 and info["outer_iters"] >= 1
+    assert info["true_rel_res"] <= 1e-10
+    assert e <= 1e-10
+
+
+def test_mixed_precision_poisson():
+    spec = make_spec((3, 3, 3), 5, (0, 1, 0), False)
+    f = synth.uniform_field(ndof(spec), 44)
+    x, info = gpu_solve(spec, 0.0, 1.0, f, poisson=True, precision=1)
+    pspec = dict(spec)
+    pspec["bc"] = (0, 2, 0)
+    M = dense.mass_diag(pspec)
+    xs = kron.FDM(pspec, 0.0).solve(M * f)
+    say("mixed poisson", info, rel(x, xs))
+    assert info["status"] == 0
+    assert rel(x, xs) <= 1e-8
+
+
+def test_stretched_large_helmholtz_full_size():
+    spec = synth.mesh_spec("stretched_large")
+    lam = synth.large_helmholtz_lambda()
+    f = synth.uniform_field(ndof(spec), synth.SEEDS["large_helmholtz"])
+    x, info = gpu_solve(spec, lam, 1.0, f)
+    say("large helmholtz", info)
+    assert info["status"] == 0
+    assert 30 <= info["iters"] <= 45
+    xs = kron.FDM(spec, lam).solve(dense.mass_diag(spec) * f)
+    assert rel(x, xs) <= 1e-10
