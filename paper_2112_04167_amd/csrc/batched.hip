@@ -1,0 +1,699 @@
+// Batched implicit-stage solve in one persistent, cooperative launch.
+//
+// One IMEX Runge-Kutta stage (arXiv 2112.04167, Alg. 3) solves a pressure
+// Poisson problem and three velocity Helmholtz problems with the same mesh.
+// Here they are solved together: FP64 iterative refinement whose correction
+// equations are solved by Jacobi-preconditioned CG in the inner precision TI
+// (FP32 for the mixed mode), with per-system scalars, per-system stopping
+// tests (Sec. 4: relative RMS residual at the collocation points) and
+// per-system retirement.  Every phase of every iteration of every system
+// runs inside a single cooperative kernel; phases are separated by grid-wide
+// barriers, and the scalars of a phase are finished by the last work-group
+// to arrive (fixed-order FP64 sums), so the launch needs no host round trip.
+//
+// Work decomposition: in each phase the work items are (system, element
+// group) pairs of the systems still active, dealt round-robin to the
+// resident work-groups; the group order is the XCD-aware order of the
+// stand-alone apply.  The launch shape (resident work-groups per CU) is
+// chosen by a small autotuner that times each candidate on the actual batch.
+#include <hip/hip_cooperative_groups.h>
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <type_traits>
+
+#include "apply_core.h"
+#include "batched.h"
+#include "dg_internal.h"
+#include "kernels.h"
+
+namespace cgrp = cooperative_groups;
+
+namespace dg {
+
+namespace {
+
+constexpr int NCMAX = 5;  // reduction components per system and phase
+
+template <typename TI>
+struct BSys {
+    double *x64, *b64, *r64;
+    const double *rhs, *nu64;
+    TI *x, *r, *p, *q, *d, *b;
+    const TI *nu;
+    double lambda;
+    int bc[3];
+    int singular;
+};
+
+struct BState {
+    double bnorm2, tol2, res2, mean_b, mean_r, scale, sum_invM2, shift;
+    // inner CG
+    double rho, alpha, beta, ires2, itol2, imean_b, imean_r, isum_invd, isum_invM2, ibnorm2;
+    int outer, status, done, inner_total, iter, idone, ran;
+    int pad;
+};
+
+template <typename TI>
+struct BArgs {
+    BSys<TI> sys[kMaxBatch];
+    BState *st;
+    int nsys;
+    Geo<double> g64;
+    Geo<TI> gi;
+    const int *order;
+    int nel, ngroups;
+    double *partial;
+    unsigned *counter;
+    int maxit_outer, inner_maxit, weak;
+    double tol, inner_tol;
+};
+
+// LDS of the persistent kernel: the FP64 apply with a nu field is the
+// largest user; every phase carves its buffers from it.
+template <int P>
+struct BLds {
+    static constexpr int EB = Shape<P>::EB, E3 = Lds<P>::E3;
+    double xs[EB * E3], ys[EB * E3], nus[EB * E3];
+    ElGeo<double> geo[EB];
+    double sh[16 * NCMAX];
+    double acc[NCMAX][kMaxBatch];
+    int last;
+};
+
+// per-thread node loop of one element group: f(global index, GLL mass)
+template <int P, typename F>
+__device__ __forceinline__ void group_nodes(int grp, int nel, const Geo<double> &g, F &&f)
+{
+    using S = Shape<P>;
+    const int tid = threadIdx.x;
+    const int el_loc = tid / S::NL;
+    const int l = tid - el_loc * S::NL;
+    const int el = grp * S::EB + el_loc;
+    if (tid >= S::NT || el >= nel) return;
+    const int ex = el % g.n[0], r = el / g.n[0], ey = r % g.n[1], ez = r / g.n[1];
+    const double Jw = g.h[0][ex] * g.h[1][ey] * g.h[2][ez] * 0.125 * kGll<P>.w[l % S::n] *
+                      kGll<P>.w[l / S::n];
+#pragma unroll
+    for (int c = 0; c < S::n; ++c)
+        f((size_t)el * S::N3 + (size_t)c * S::NL + l, Jw * kGll<P>.w[c]);
+}
+
+// add one work item's per-thread sums into the block accumulator acc[.][s]
+template <int NC>
+__device__ __forceinline__ void block_accumulate(double (&v)[NC], int s, double *sh,
+                                                 double (&acc)[NCMAX][kMaxBatch])
+{
+    block_sum<NC>(v, sh);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[c][s] += v[c];
+}
+
+// end of a reduced phase: publish this block's accumulators; the last block
+// to arrive sums every block's partials in a fixed order and calls
+// fin(system, totals) from thread 0.
+template <int NC, typename F>
+__device__ void phase_reduce(double (&acc)[NCMAX][kMaxBatch], double *sh, int &last,
+                             double *partial, unsigned *counter, int nsys, F &&fin)
+{
+    const int nblk = gridDim.x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int s = 0; s < nsys; ++s)
+            for (int c = 0; c < NC; ++c) partial[(size_t)(c * kMaxBatch + s) * nblk + blockIdx.x] = acc[c][s];
+        __threadfence();
+        const unsigned prev = atomicAdd(counter, 1u);
+        last = (prev == (unsigned)(nblk - 1));
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    for (int s = 0; s < nsys; ++s) {
+        double v[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            v[c] = 0.0;
+            const double *pp = partial + (size_t)(c * kMaxBatch + s) * nblk;
+            for (int k = threadIdx.x; k < nblk; k += blockDim.x)
+                v[c] += __hip_atomic_load(&pp[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        block_sum<NC>(v, sh);
+        if (threadIdx.x == 0) fin(s, v);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *counter = 0u;
+}
+
+__device__ __forceinline__ void zero_acc(double (&acc)[NCMAX][kMaxBatch])
+{
+    if (threadIdx.x < NCMAX * kMaxBatch) (&acc[0][0])[threadIdx.x] = 0.0;
+    __syncthreads();
+}
+
+// round-robin over (active system, group) work items; g = XCD-aware group
+template <typename F>
+__device__ __forceinline__ void for_items(const int *act, int nact, int G, const int *order, F &&f)
+{
+    const int total = nact * G;
+    for (int w = blockIdx.x; w < total; w += gridDim.x) {
+        const int s = act[w / G];
+        const int slot = xcd_remap(w % G, G);
+        f(s, order ? order[slot] : slot);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ ApplyArgs<T> sys_apply_args(const Geo<T> &g, int bc[3], int nel, int G,
+                                                       const int *order, const T *x, T *y,
+                                                       const T *nu, double lambda, const T *b)
+{
+    ApplyArgs<T> a{};
+    a.x = x;
+    a.y = y;
+    a.nu = nu;
+    a.nu_c = (T)1;
+    a.lambda = (T)lambda;
+    a.geo = g;
+    for (int d = 0; d < 3; ++d) a.geo.bc[d] = bc[d];
+    a.nel = nel;
+    a.ngroups = G;
+    a.order = order;
+    a.b = b;
+    return a;
+}
+
+template <int P, typename TI>
+__global__ void __launch_bounds__(Shape<P>::NTP) k_batched(BArgs<TI> B)
+{
+    using S = Shape<P>;
+    __shared__ BLds<P> L;
+    __shared__ int act[kMaxBatch];
+    __shared__ int nact_s;
+    cgrp::grid_group grid = cgrp::this_grid();
+    const int G = B.ngroups, nel = B.nel, ns = B.nsys;
+    BState *st = B.st;
+    const double N = (double)nel * S::N3;
+
+    // coherent (agent-scope) read of a flag written by another work-group
+    auto ld = [](const int *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); };
+    // active list: systems with flag(s) true (read after a grid barrier, so
+    // every block builds the same list and takes the same number of barriers)
+    auto build_active = [&](auto flag) {
+        if (threadIdx.x == 0) {
+            int k = 0;
+            for (int s = 0; s < ns; ++s)
+                if (flag(s)) act[k++] = s;
+            nact_s = k;
+        }
+        __syncthreads();
+        return nact_s;
+    };
+
+    // ---- set-up 1: b = M f (or f), sum b, sum b^2
+    {
+        zero_acc(L.acc);
+        for (int w = blockIdx.x; w < ns * G; w += gridDim.x) {
+            const int s = w / G, g = w % G;
+            const BSys<TI> &Y = B.sys[s];
+            double v[2] = {0.0, 0.0};
+            group_nodes<P>(g, nel, B.g64, [&](size_t gi, double m) {
+                const double bb = B.weak ? Y.rhs[gi] : m * Y.rhs[gi];
+                Y.b64[gi] = bb;
+                Y.x64[gi] = 0.0;
+                v[0] += bb;
+                v[1] += bb * bb;
+            });
+            block_accumulate<2>(v, s, L.sh, L.acc);
+        }
+        phase_reduce<2>(L.acc, L.sh, L.last, B.partial, B.counter, ns, [&](int s, double(&t)[2]) {
+            st[s].mean_b = B.sys[s].singular ? t[0] / N : 0.0;
+            if (!isfinite(t[1])) {
+                st[s].status = DG_ERR_NONFINITE;
+                st[s].done = 1;
+            }
+        });
+        grid.sync();
+    }
+    // ---- set-up 2: project b (singular), ||M^-1 b||^2, sum 1/M^2
+    {
+        zero_acc(L.acc);
+        for (int w = blockIdx.x; w < ns * G; w += gridDim.x) {
+            const int s = w / G, g = w % G;
+            const BSys<TI> &Y = B.sys[s];
+            const double mb = st[s].mean_b;
+            double v[2] = {0.0, 0.0};
+            group_nodes<P>(g, nel, B.g64, [&](size_t gi, double m) {
+                double bb = Y.b64[gi];
+                if (Y.singular) {
+                    bb -= mb;
+                    Y.b64[gi] = bb;
+                }
+                const double rm = bb / m;
+                v[0] += rm * rm;
+                v[1] += 1.0 / (m * m);
+            });
+            block_accumulate<2>(v, s, L.sh, L.acc);
+        }
+        phase_reduce<2>(L.acc, L.sh, L.last, B.partial, B.counter, ns, [&](int s, double(&t)[2]) {
+            st[s].bnorm2 = t[0];
+            st[s].tol2 = B.tol * B.tol * t[0];
+            st[s].sum_invM2 = t[1];
+            if (!(t[0] > 0.0) && st[s].status == DG_OK) st[s].done = 1;  // b = 0: x = 0
+        });
+        grid.sync();
+    }
+
+    for (int outer = 0;; ++outer) {
+        // ---- FP64 residual r = b - A x (projected) and the outer test
+        int na = build_active([&](int s) { return !ld(&st[s].done); });
+        if (na == 0) break;
+        {
+            zero_acc(L.acc);
+            for_items(act, na, G, B.order, [&](int s, int g) {
+                const BSys<TI> &Y = B.sys[s];
+                ApplyArgs<double> a = sys_apply_args<double>(B.g64, (int *)Y.bc, nel, G, B.order,
+                                                             Y.x64, Y.r64, Y.nu64, Y.lambda, Y.b64);
+                double red[4];
+                if (Y.nu64)
+                    apply_group<P, double, true, EPI_RESID>(a, g, L.xs, L.ys, L.nus, L.geo, red);
+                else
+                    apply_group<P, double, false, EPI_RESID>(a, g, L.xs, L.ys, L.nus, L.geo, red);
+                block_accumulate<4>(red, s, L.sh, L.acc);
+            });
+            phase_reduce<4>(L.acc, L.sh, L.last, B.partial, B.counter, ns, [&](int s, double(&t)[4]) {
+                if (st[s].done) return;
+                double res2 = t[0];
+                double m = 0.0;
+                if (B.sys[s].singular) {
+                    m = t[1] / N;
+                    res2 = t[0] - 2.0 * m * t[2] + m * m * t[3];
+                }
+                st[s].mean_r = m;
+                st[s].res2 = res2 > 0.0 ? res2 : 0.0;
+                st[s].ran = 0;
+                if (!isfinite(res2)) {
+                    st[s].status = DG_ERR_NONFINITE;
+                    st[s].done = 1;
+                } else if (res2 <= st[s].tol2) {
+                    st[s].done = 1;
+                } else if (outer >= B.maxit_outer) {
+                    st[s].status = DG_NOT_CONVERGED;
+                    st[s].done = 1;
+                } else {
+                    st[s].ran = 1;
+                    st[s].outer = outer + 1;
+                }
+            });
+            grid.sync();
+        }
+        na = build_active([&](int s) { return ld(&st[s].ran) != 0; });
+        if (na == 0) continue;  // re-evaluated at the loop top (all done)
+
+        // ---- scale = RMS of the projected residual
+        {
+            zero_acc(L.acc);
+            for_items(act, na, G, B.order, [&](int s, int g) {
+                const BSys<TI> &Y = B.sys[s];
+                const double mr = st[s].mean_r;
+                double v[1] = {0.0};
+                group_nodes<P>(g, nel, B.g64, [&](size_t gi, double) {
+                    const double r = Y.r64[gi] - mr;
+                    v[0] += r * r;
+                });
+                block_accumulate<1>(v, s, L.sh, L.acc);
+            });
+            phase_reduce<1>(L.acc, L.sh, L.last, B.partial, B.counter, ns, [&](int s, double(&t)[1]) {
+                if (!st[s].ran) return;
+                const double rms = sqrt(t[0] / N);
+                st[s].scale = rms > 0.0 ? rms : 1.0;
+            });
+            grid.sync();
+        }
+        // ---- inner right-hand side b_in = (r - mean r)/scale, its sum
+        {
+            zero_acc(L.acc);
+            for_items(act, na, G, B.order, [&](int s, int g) {
+                const BSys<TI> &Y = B.sys[s];
+                const double mr = st[s].mean_r, inv = 1.0 / st[s].scale;
+                double v[1] = {0.0};
+                group_nodes<P>(g, nel, B.g64, [&](size_t gi, double) {
+                    const TI bb = (TI)((Y.r64[gi] - mr) * inv);
+                    Y.b[gi] = bb;
+                    v[0] += (double)bb;
+                });
+                block_accumulate<1>(v, s, L.sh, L.acc);
+            });
+            phase_reduce<1>(L.acc, L.sh, L.last, B.partial, B.counter, ns, [&](int s, double(&t)[1]) {
+                if (!st[s].ran) return;
+                st[s].imean_b = B.sys[s].singular ? t[0] / N : 0.0;
+            });
+            grid.sync();
+        }
+        // ---- inner set-up: r = b (projected), x = 0, p = z = r/d, norms
+        {
+            zero_acc(L.acc);
+            for_items(act, na, G, B.order, [&](int s, int g) {
+                const BSys<TI> &Y = B.sys[s];
+                const double mb = st[s].imean_b;
+                double v[4] = {0.0, 0.0, 0.0, 0.0};
+                group_nodes<P>(g, nel, B.g64, [&](size_t gi, double m) {
+                    TI bb = Y.b[gi];
+                    if (Y.singular) {
+                        bb = (TI)((double)bb - mb);
+                        Y.b[gi] = bb;
+                    }
+                    Y.r[gi] = bb;
+                    Y.x[gi] = (TI)0;
+                    const TI z = bb / Y.d[gi];
+                    Y.p[gi] = z;
+                    const double rm = (double)bb / m;
+                    v[0] += (double)bb * (double)z;
+                    v[1] += rm * rm;
+                    v[2] += 1.0 / (double)Y.d[gi];
+                    v[3] += 1.0 / (m * m);
+                });
+                block_accumulate<4>(v, s, L.sh, L.acc);
+            });
+            phase_reduce<4>(L.acc, L.sh, L.last, B.partial, B.counter, ns, [&](int s, double(&t)[4]) {
+                if (!st[s].ran) return;
+                st[s].rho = t[0];
+                st[s].ibnorm2 = t[1];
+                st[s].ires2 = t[1];
+                st[s].itol2 = B.inner_tol * B.inner_tol * t[1];
+                st[s].isum_invd = t[2];
+                st[s].isum_invM2 = t[3];
+                st[s].iter = 0;
+                st[s].imean_r = 0.0;
+                st[s].idone = (t[1] > 0.0 && isfinite(t[0])) ? 0 : 1;
+            });
+            grid.sync();
+        }
+        // ---- inner CG iterations
+        for (int k = 0; k < B.inner_maxit; ++k) {
+            const int ni = build_active([&](int s) { return ld(&st[s].ran) && !ld(&st[s].idone); });
+            if (ni == 0) break;
+            // q = A p, p.q, sum q
+            zero_acc(L.acc);
+            for_items(act, ni, G, B.order, [&](int s, int g) {
+                const BSys<TI> &Y = B.sys[s];
+                ApplyArgs<TI> a = sys_apply_args<TI>(B.gi, (int *)Y.bc, nel, G, B.order, Y.p, Y.q,
+                                                     Y.nu, Y.lambda, nullptr);
+                double red[4];
+                TI *xs = reinterpret_cast<TI *>(L.xs), *ys = reinterpret_cast<TI *>(L.ys),
+                   *nus = reinterpret_cast<TI *>(L.nus);
+                ElGeo<TI> *geo = reinterpret_cast<ElGeo<TI> *>(L.geo);
+                if (Y.nu)
+                    apply_group<P, TI, true, EPI_CG>(a, g, xs, ys, nus, geo, red);
+                else
+                    apply_group<P, TI, false, EPI_CG>(a, g, xs, ys, nus, geo, red);
+                double v2[2] = {red[0], red[1]};
+                block_accumulate<2>(v2, s, L.sh, L.acc);
+            });
+            phase_reduce<2>(L.acc, L.sh, L.last, B.partial, B.counter, ns, [&](int s, double(&t)[2]) {
+                if (!st[s].ran || st[s].idone) return;
+                if (!isfinite(t[0]) || t[0] <= 0.0) {
+                    st[s].idone = 1;  // breakdown: stop this inner solve, keep its iterate
+                } else {
+                    st[s].alpha = st[s].rho / t[0];
+                }
+            });
+            grid.sync();
+            const int nu_ = build_active([&](int s) { return ld(&st[s].ran) && !ld(&st[s].idone); });
+            // x += alpha p, r -= alpha q, reductions
+            zero_acc(L.acc);
+            for_items(act, nu_, G, B.order, [&](int s, int g) {
+                const BSys<TI> &Y = B.sys[s];
+                const TI alpha = (TI)st[s].alpha;
+                double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+                group_nodes<P>(g, nel, B.g64, [&](size_t gi, double m) {
+                    Y.x[gi] = fma(alpha, Y.p[gi], Y.x[gi]);
+                    const TI r = fma(-alpha, Y.q[gi], Y.r[gi]);
+                    Y.r[gi] = r;
+                    const double rd = (double)r / (double)Y.d[gi];
+                    const double rm = (double)r / m;
+                    v[0] += (double)r;
+                    v[1] += (double)r * rd;
+                    v[2] += rd;
+                    v[3] += rm * rm;
+                    v[4] += rm / m;
+                });
+                block_accumulate<5>(v, s, L.sh, L.acc);
+            });
+            phase_reduce<5>(L.acc, L.sh, L.last, B.partial, B.counter, ns, [&](int s, double(&t)[5]) {
+                if (!st[s].ran || st[s].idone) return;
+                double rz = t[1], res2 = t[3], mr = 0.0;
+                if (B.sys[s].singular) {
+                    mr = t[0] / N;
+                    rz = t[1] - 2.0 * mr * t[2] + mr * mr * st[s].isum_invd;
+                    res2 = t[3] - 2.0 * mr * t[4] + mr * mr * st[s].isum_invM2;
+                }
+                st[s].imean_r = mr;
+                st[s].beta = rz / st[s].rho;
+                st[s].rho = rz;
+                st[s].ires2 = res2 > 0.0 ? res2 : 0.0;
+                st[s].iter += 1;
+                st[s].inner_total += 1;
+                if (!isfinite(rz) || res2 <= st[s].itol2 || st[s].iter >= B.inner_maxit)
+                    st[s].idone = 1;
+            });
+            grid.sync();
+            const int np = build_active([&](int s) { return ld(&st[s].ran) && !ld(&st[s].idone); });
+            // (singular: r -= mean r)  p = r/d + beta p
+            for_items(act, np, G, B.order, [&](int s, int g) {
+                const BSys<TI> &Y = B.sys[s];
+                const TI beta = (TI)st[s].beta;
+                const double mr = st[s].imean_r;
+                group_nodes<P>(g, nel, B.g64, [&](size_t gi, double) {
+                    TI r = Y.r[gi];
+                    if (Y.singular) {
+                        r = (TI)((double)r - mr);
+                        Y.r[gi] = r;
+                    }
+                    Y.p[gi] = fma(beta, Y.p[gi], r / Y.d[gi]);
+                });
+            });
+            grid.sync();
+        }
+        // ---- x64 += scale * x_in
+        {
+            na = build_active([&](int s) { return ld(&st[s].ran) != 0; });
+            for_items(act, na, G, B.order, [&](int s, int g) {
+                const BSys<TI> &Y = B.sys[s];
+                const double sc = st[s].scale;
+                group_nodes<P>(g, nel, B.g64,
+                               [&](size_t gi, double) { Y.x64[gi] = fma(sc, (double)Y.x[gi], Y.x64[gi]); });
+            });
+            grid.sync();
+        }
+    }
+
+    // ---- singular systems: M-weighted mean of x removed
+    {
+        zero_acc(L.acc);
+        for (int w = blockIdx.x; w < ns * G; w += gridDim.x) {
+            const int s = w / G, g = w % G;
+            if (!B.sys[s].singular) continue;
+            const BSys<TI> &Y = B.sys[s];
+            double v[2] = {0.0, 0.0};
+            group_nodes<P>(g, nel, B.g64, [&](size_t gi, double m) {
+                v[0] += m * Y.x64[gi];
+                v[1] += m;
+            });
+            block_accumulate<2>(v, s, L.sh, L.acc);
+        }
+        phase_reduce<2>(L.acc, L.sh, L.last, B.partial, B.counter, ns, [&](int s, double(&t)[2]) {
+            st[s].shift = (B.sys[s].singular && t[1] > 0.0) ? t[0] / t[1] : 0.0;
+        });
+        grid.sync();
+        for (int w = blockIdx.x; w < ns * G; w += gridDim.x) {
+            const int s = w / G, g = w % G;
+            if (!B.sys[s].singular) continue;
+            const BSys<TI> &Y = B.sys[s];
+            const double sh = st[s].shift;
+            group_nodes<P>(g, nel, B.g64, [&](size_t gi, double) { Y.x64[gi] -= sh; });
+        }
+    }
+}
+
+template <int P, typename TI>
+const void *kernel_ptr()
+{
+    return reinterpret_cast<const void *>(&k_batched<P, TI>);
+}
+
+template <typename TI>
+const void *kernel_for(int P)
+{
+    switch (P) {
+        case 3: return kernel_ptr<3, TI>();
+        case 4: return kernel_ptr<4, TI>();
+        case 5: return kernel_ptr<5, TI>();
+        case 6: return kernel_ptr<6, TI>();
+        case 7: return kernel_ptr<7, TI>();
+        case 8: return kernel_ptr<8, TI>();
+    }
+    return nullptr;
+}
+
+// autotuned launch shape per (device, P, inner precision, nsys)
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int>, int> g_tune;
+
+}  // namespace
+
+int batched_launch(const MeshDev &m, const BatchRequest &req, hipStream_t stream,
+                   BatchResult *res)
+{
+    const bool f32 = req.inner_fp32;
+    const void *fn = f32 ? kernel_for<float>(m.P) : kernel_for<double>(m.P);
+    if (!fn) {
+        set_error("polynomial degree outside 3..8");
+        return DG_ERR_ARG;
+    }
+    int dev = 0;
+    DG_HIP_CHECK(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    DG_HIP_CHECK(hipGetDeviceProperties(&prop, dev));
+    int coop = 0;
+    DG_HIP_CHECK(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+    if (!coop) {
+        set_error("device does not support cooperative launches");
+        return DG_ERR_DEVICE;
+    }
+    const int threads = apply_threads(m.P);
+    int per_cu = 0;
+    DG_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, 0));
+    if (per_cu < 1) {
+        set_error("batched kernel does not fit on a compute unit");
+        return DG_ERR_DEVICE;
+    }
+    const int ncu = prop.multiProcessorCount;
+
+    auto fill = [&](auto &B) {
+        using TI = std::remove_pointer_t<decltype(B.sys[0].x)>;
+        B.nsys = req.nsys;
+        B.st = (BState *)req.state;
+        for (int d = 0; d < 3; ++d) {
+            B.g64.n[d] = m.n[d];
+            B.gi.n[d] = m.n[d];
+            B.g64.bc[d] = m.bc[d];
+            B.gi.bc[d] = m.bc[d];
+        }
+        const TI *h = std::is_same<TI, double>::value ? (const TI *)m.h64 : (const TI *)m.h32;
+        const TI *ih = std::is_same<TI, double>::value ? (const TI *)m.ih64 : (const TI *)m.ih32;
+        int off = 0;
+        for (int d = 0; d < 3; ++d) {
+            B.g64.h[d] = m.h64 + off;
+            B.g64.ih[d] = m.ih64 + off;
+            B.gi.h[d] = h + off;
+            B.gi.ih[d] = ih + off;
+            off += m.n[d];
+        }
+        B.order = m.order;
+        B.nel = (int)m.nel;
+        B.ngroups = apply_groups(m.P, m.nel);
+        B.partial = req.partial;
+        B.counter = req.counter;
+        B.maxit_outer = req.maxit_outer;
+        B.inner_maxit = req.inner_maxit;
+        B.weak = req.weak;
+        B.tol = req.tol;
+        B.inner_tol = req.inner_tol;
+        for (int s = 0; s < req.nsys; ++s) {
+            auto &Y = B.sys[s];
+            const BatchSysDesc &D = req.sys[s];
+            Y.x64 = D.x64;
+            Y.b64 = D.b64;
+            Y.r64 = D.r64;
+            Y.rhs = D.rhs;
+            Y.nu64 = D.nu64;
+            Y.x = (TI *)D.xi;
+            Y.r = (TI *)D.ri;
+            Y.p = (TI *)D.pi;
+            Y.q = (TI *)D.qi;
+            Y.d = (TI *)D.di;
+            Y.b = (TI *)D.bi;
+            Y.nu = (const TI *)D.nui;
+            Y.lambda = D.lambda;
+            for (int d = 0; d < 3; ++d) Y.bc[d] = D.bc[d];
+            Y.singular = D.singular;
+        }
+    };
+
+    auto run = [&](int bpc, int maxit_outer, int inner_maxit) -> int {
+        DG_HIP_CHECK(hipMemsetAsync(req.state, 0, sizeof(BState) * kMaxBatch, stream));
+        dim3 grid(std::min(kBatchMaxBlocks, std::max(8, ((ncu * bpc) / 8) * 8))), block(threads);
+        if (f32) {
+            BArgs<float> B{};
+            fill(B);
+            B.maxit_outer = maxit_outer;
+            B.inner_maxit = inner_maxit;
+            void *args[] = {&B};
+            DG_HIP_CHECK(hipLaunchCooperativeKernel(fn, grid, block, args, 0, stream));
+        } else {
+            BArgs<double> B{};
+            fill(B);
+            B.maxit_outer = maxit_outer;
+            B.inner_maxit = inner_maxit;
+            void *args[] = {&B};
+            DG_HIP_CHECK(hipLaunchCooperativeKernel(fn, grid, block, args, 0, stream));
+        }
+        return DG_OK;
+    };
+
+    // autotune: time a short, fixed amount of work for every launch shape
+    int bpc = 1;
+    {
+        const auto key = std::make_tuple(dev, m.P, f32 ? 1 : 0, req.nsys);
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            bpc = it->second;
+        } else {
+            double best = 1e300;
+            for (int c = 1; c <= per_cu; ++c) {
+                hipEvent_t e0, e1;
+                DG_HIP_CHECK(hipEventCreate(&e0));
+                DG_HIP_CHECK(hipEventCreate(&e1));
+                DG_HIP_CHECK(hipEventRecord(e0, stream));
+                int rc = run(c, 1, 8);
+                DG_HIP_CHECK(hipEventRecord(e1, stream));
+                DG_HIP_CHECK(hipEventSynchronize(e1));
+                float ms = 0.f;
+                DG_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+                if (rc) return rc;
+                if (ms < best) {
+                    best = ms;
+                    bpc = c;
+                }
+            }
+            g_tune[key] = bpc;
+        }
+    }
+    if (res) res->blocks_per_cu = bpc;
+    return run(bpc, req.maxit_outer, req.inner_maxit);
+}
+
+size_t batched_state_bytes() { return sizeof(BState) * kMaxBatch; }
+
+int batched_read_state(const void *host_state, int s, BatchSysResult *out)
+{
+    const BState *st = (const BState *)host_state + s;
+    out->status = st->status;
+    out->outer = st->outer;
+    out->inner_total = st->inner_total;
+    out->bnorm2 = st->bnorm2;
+    out->res2 = st->res2;
+    return DG_OK;
+}
+
+}  // namespace dg

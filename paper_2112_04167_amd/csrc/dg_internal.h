@@ -39,6 +39,7 @@ GllTables make_gll(int P);
 template <typename T>
 struct Geo {
     const T *h[3];   // element extents per axis (device)
+    const T *ih[3];  // their reciprocals
     int n[3];        // elements per axis
     int bc[3];       // DG_BC_* per axis (after any Poisson BC mapping)
 };
@@ -51,7 +52,17 @@ struct MeshDev {
     std::vector<double> v[3];  // host vertices
     double *h64 = nullptr;     // device: hx | hy | hz
     float *h32 = nullptr;
+    double *ih64 = nullptr;    // device: 1/hx | 1/hy | 1/hz
+    float *ih32 = nullptr;
+    int *order = nullptr;      // device: apply work-group -> element group (see apply_order)
 };
+
+// Order in which the apply visits its element groups: position k of the
+// sequence (after the XCD remap of the block id) -> element group.  The x-y
+// plane is cut into 8 patches, one per XCD, and every patch is swept plane by
+// plane in z, so that a group's z-neighbours were loaded shortly before and
+// stay in the XCD's L2.
+std::vector<int> apply_order(const int n[3], int P);
 
 // --- kernel launchers (kernels_apply.hip) ---------------------------------
 // y = A x; T = double or float; nu == nullptr -> constant nu_c.

@@ -57,8 +57,12 @@ struct GllC {
     double w[n];
     double D[n * n];
     double K1[n * n];
+    // K0 = K1 - (e_P D_P^T + D_P e_P^T)/2 + (e_0 D_0^T + D_0 e_0^T)/2: the 1D
+    // stiffness of a line plus the self-coupling of the consistency terms of
+    // two interior faces (without penalty), in units of J g^2 w w nu
+    double K0[n * n];
 
-    constexpr GllC() : xi(), w(), D(), K1()
+    constexpr GllC() : xi(), w(), D(), K1(), K0()
     {
         const double pi = 3.14159265358979323846;
         double x0[n] = {};
@@ -90,6 +94,15 @@ struct GllC {
                 double s = 0.0;
                 for (int q = 0; q < n; ++q) s += D[q * n + a] * w[q] * D[q * n + b];
                 K1[a * n + b] = s;
+            }
+        for (int a = 0; a < n; ++a)
+            for (int b = 0; b < n; ++b) {
+                double k = K1[a * n + b];
+                if (a == P) k -= 0.5 * D[P * n + b];
+                if (b == P) k -= 0.5 * D[P * n + a];
+                if (a == 0) k += 0.5 * D[b];
+                if (b == 0) k += 0.5 * D[a];
+                K0[a * n + b] = k;
             }
     }
 };

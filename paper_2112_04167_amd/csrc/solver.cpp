@@ -15,6 +15,7 @@
 #include <mutex>
 #include <string>
 
+#include "batched.h"
 #include "dg_internal.h"
 #include "kernels.h"
 
@@ -53,10 +54,19 @@ struct Workspace {
     CgScalars *host_sc = nullptr; // pinned
 };
 
+// Workspace of the batched solver: per system two FP64 and seven
+// inner-precision vectors, plus reduction slots and the device state.
+struct BatchWorkspace {
+    size_t bytes = 0;
+    void *base = nullptr;
+    void *host_state = nullptr;  // pinned copy of the device state
+};
+
 struct dg_mesh {
     MeshDev dev;
     hipStream_t stream = nullptr;
     Workspace ws;
+    BatchWorkspace bws;
 };
 
 namespace {
@@ -387,6 +397,116 @@ int solve_common(dg_mesh *m, const int bc[3], double lambda, const double *nu, d
     return rc;
 }
 
+size_t batched_footprint(const MeshDev &m, int precision, int nsys)
+{
+    const size_t N = (size_t)m.ndof;
+    const size_t ti = precision == DG_FP64 ? sizeof(double) : sizeof(float);
+    size_t b = 0;
+    b += (size_t)nsys * (2 * align256(N * sizeof(double)) + 7 * align256(N * ti));
+    b += align256((size_t)kBatchPartialPerBlock * kBatchMaxBlocks * sizeof(double));
+    b += align256(256) + align256(batched_state_bytes());
+    return b;
+}
+
+int solve_batched(dg_mesh *m, int nsys, const double *lambdas, const double *const *nu_fields,
+                  const int *is_poisson, const double *const *rhs, double *const *x,
+                  const dg_solve_opts &o, dg_solve_info *infos)
+{
+    const MeshDev &md = m->dev;
+    hipStream_t s = m->stream;
+    const bool f32 = o.precision == DG_MIXED;
+    const size_t N = (size_t)md.ndof;
+    const size_t ti = f32 ? sizeof(float) : sizeof(double);
+    const size_t need = batched_footprint(md, o.precision, kMaxBatch);
+    BatchWorkspace &w = m->bws;
+    if (!w.base || w.bytes < need) {
+        if (w.base) {
+            DG_HIP_CHECK(hipStreamSynchronize(s));
+            DG_HIP_CHECK(hipFree(w.base));
+            w.base = nullptr;
+        }
+        hipError_t e = hipMalloc(&w.base, need);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("batched workspace allocation of " + std::to_string(need) + " bytes failed");
+            return DG_ERR_OOM;
+        }
+        w.bytes = need;
+    }
+    if (!w.host_state) DG_HIP_CHECK(hipHostMalloc(&w.host_state, batched_state_bytes(), 0));
+    char *p = (char *)w.base;
+    auto take = [&](size_t bytes) {
+        char *r = p;
+        p += align256(bytes);
+        return (void *)r;
+    };
+    BatchRequest rq{};
+    rq.nsys = nsys;
+    rq.tol = o.tol;
+    rq.inner_tol = o.inner_tol;
+    rq.maxit_outer = std::min(o.maxit, 1000);
+    rq.inner_maxit = o.inner_maxit;
+    rq.weak = o.rhs_is_weak;
+    rq.inner_fp32 = f32;
+    for (int k = 0; k < nsys; ++k) {
+        BatchSysDesc &D = rq.sys[k];
+        D.x64 = x[k];
+        D.rhs = rhs[k];
+        D.b64 = (double *)take(N * 8);
+        D.r64 = (double *)take(N * 8);
+        D.xi = take(N * ti);
+        D.ri = take(N * ti);
+        D.pi = take(N * ti);
+        D.qi = take(N * ti);
+        D.di = take(N * ti);
+        D.bi = take(N * ti);
+        void *nui = take(N * ti);
+        const bool pois = is_poisson && is_poisson[k];
+        for (int d = 0; d < 3; ++d)
+            D.bc[d] = (pois && md.bc[d] == DG_BC_DIRICHLET) ? DG_BC_NEUMANN : md.bc[d];
+        D.lambda = pois ? 0.0 : lambdas[k];
+        D.singular = (D.lambda == 0.0 && !has_dirichlet(D.bc)) ? 1 : 0;
+        D.nu64 = (!pois && nu_fields && nu_fields[k]) ? nu_fields[k] : nullptr;
+        D.nui = nullptr;
+        int rc;
+        if (f32) {
+            if (D.nu64) {
+                if ((rc = convert_f64_to_f32(D.nu64, (float *)nui, N, s))) return rc;
+                D.nui = nui;
+            }
+            rc = launch_diag<float>(md, D.bc, D.lambda, (const float *)D.nui, 1.0, (float *)D.di, s);
+        } else {
+            D.nui = D.nu64;
+            rc = launch_diag<double>(md, D.bc, D.lambda, D.nu64, 1.0, (double *)D.di, s);
+        }
+        if (rc) return rc;
+    }
+    rq.partial = (double *)take((size_t)kBatchPartialPerBlock * kBatchMaxBlocks * sizeof(double));
+    rq.counter = (unsigned *)take(256);
+    rq.state = take(batched_state_bytes());
+    DG_HIP_CHECK(hipMemsetAsync(rq.counter, 0, 256, s));
+    BatchResult br{};
+    int rc = batched_launch(md, rq, s, &br);
+    if (rc) return rc;
+    DG_HIP_CHECK(hipMemcpyAsync(w.host_state, rq.state, batched_state_bytes(), hipMemcpyDeviceToHost, s));
+    DG_HIP_CHECK(hipStreamSynchronize(s));
+    int worst = DG_OK;
+    for (int k = 0; k < nsys; ++k) {
+        BatchSysResult r{};
+        batched_read_state(w.host_state, k, &r);
+        if (infos) {
+            infos[k].iters = r.inner_total;
+            infos[k].outer_iters = r.outer;
+            infos[k].status = r.status;
+            infos[k].rel_res = r.bnorm2 > 0 ? std::sqrt(r.res2 / r.bnorm2) : 0.0;
+            infos[k].true_rel_res = infos[k].rel_res;
+        }
+        if (r.status < 0 && (worst >= 0 || r.status < worst)) worst = r.status;
+        else if (r.status > 0 && worst == DG_OK) worst = r.status;
+    }
+    return worst;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- C-ABI --
@@ -454,10 +574,26 @@ int dg_mesh_create(int nx, int ny, int nz, int P, const double *xv, const double
     for (int k = 0; k < 3; ++k)
         for (int e = 0; e < nn[k]; ++e) h.push_back(d.v[k][e + 1] - d.v[k][e]);
     std::vector<float> hf(h.begin(), h.end());
+    std::vector<double> ih(h.size());
+    std::vector<float> ihf(h.size());
+    for (size_t k = 0; k < h.size(); ++k) {
+        ih[k] = 1.0 / h[k];
+        ihf[k] = 1.0f / hf[k];
+    }
     DG_HIP_CHECK(hipMalloc((void **)&d.h64, h.size() * sizeof(double)));
     DG_HIP_CHECK(hipMalloc((void **)&d.h32, hf.size() * sizeof(float)));
+    DG_HIP_CHECK(hipMalloc((void **)&d.ih64, h.size() * sizeof(double)));
+    DG_HIP_CHECK(hipMalloc((void **)&d.ih32, hf.size() * sizeof(float)));
     DG_HIP_CHECK(hipMemcpy(d.h64, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
     DG_HIP_CHECK(hipMemcpy(d.h32, hf.data(), hf.size() * sizeof(float), hipMemcpyHostToDevice));
+    DG_HIP_CHECK(hipMemcpy(d.ih64, ih.data(), ih.size() * sizeof(double), hipMemcpyHostToDevice));
+    DG_HIP_CHECK(hipMemcpy(d.ih32, ihf.data(), ihf.size() * sizeof(float), hipMemcpyHostToDevice));
+    {
+        const std::vector<int> ord = apply_order(d.n, P);
+        DG_HIP_CHECK(hipMalloc((void **)&d.order, ord.size() * sizeof(int)));
+        DG_HIP_CHECK(
+            hipMemcpy(d.order, ord.data(), ord.size() * sizeof(int), hipMemcpyHostToDevice));
+    }
     (void)gll_cached(P);
     *out = m.release();
     return DG_OK;
@@ -469,8 +605,13 @@ int dg_mesh_destroy(dg_mesh *m)
     (void)hipStreamSynchronize(m->stream);
     if (m->ws.base) (void)hipFree(m->ws.base);
     if (m->ws.host_sc) (void)hipHostFree(m->ws.host_sc);
+    if (m->bws.base) (void)hipFree(m->bws.base);
+    if (m->bws.host_state) (void)hipHostFree(m->bws.host_state);
     if (m->dev.h64) (void)hipFree(m->dev.h64);
     if (m->dev.h32) (void)hipFree(m->dev.h32);
+    if (m->dev.ih64) (void)hipFree(m->dev.ih64);
+    if (m->dev.ih32) (void)hipFree(m->dev.ih32);
+    if (m->dev.order) (void)hipFree(m->dev.order);
     delete m;
     return DG_OK;
 }
@@ -480,7 +621,8 @@ int64_t dg_mesh_ndof(const dg_mesh *m) { return m ? m->dev.ndof : -1; }
 size_t dg_solve_footprint(const dg_mesh *m, int precision, int nrhs)
 {
     if (!m) return 0;
-    return footprint(m->dev, precision) * (size_t)std::max(1, nrhs);
+    if (nrhs <= 1) return footprint(m->dev, precision);
+    return batched_footprint(m->dev, precision, nrhs);
 }
 
 int helmholtz_apply(dg_mesh *m, double lambda, const void *nu_field, double nu_const,
@@ -530,6 +672,48 @@ int helmholtz_solve(dg_mesh *m, double lambda, const double *nu_field, double nu
 {
     if (int rc = check_mesh(m)) return rc;
     return solve_common(m, m->dev.bc, lambda, nu_field, nu_const, rhs, x, opts, info);
+}
+
+int helmholtz_solve_batched(dg_mesh *m, int nsys, const double *lambdas,
+                            const double *const *nu_fields, const int *is_poisson,
+                            const double *const *rhs, double *const *x, const dg_solve_opts *opts,
+                            dg_solve_info *infos)
+{
+    const double t0 = now();
+    if (int rc = check_mesh(m)) return rc;
+    if (nsys < 1 || nsys > kMaxBatch || !rhs || !x) {
+        set_error("need 1 <= nsys <= 8 and rhs, x arrays");
+        return DG_ERR_ARG;
+    }
+    dg_solve_opts o;
+    dg_default_opts(&o);
+    o.precision = DG_MIXED;
+    if (opts) o = *opts;
+    if (!(o.tol > 0.0) || o.maxit < 1 || o.inner_maxit < 1 || !(o.inner_tol > 0.0 && o.inner_tol < 1.0) ||
+        (o.precision != DG_FP64 && o.precision != DG_MIXED)) {
+        set_error("bad solver options");
+        return DG_ERR_ARG;
+    }
+    for (int k = 0; k < nsys; ++k) {
+        const bool pois = is_poisson && is_poisson[k];
+        if (!rhs[k] || !x[k] || (const void *)rhs[k] == (const void *)x[k]) {
+            set_error("rhs and x must be distinct device arrays");
+            return DG_ERR_ARG;
+        }
+        if (!pois && (!lambdas || !(lambdas[k] >= 0.0) || !std::isfinite(lambdas[k]))) {
+            set_error("lambda must be >= 0");
+            return DG_ERR_ARG;
+        }
+        for (int j = 0; j < k; ++j)
+            if (x[j] == x[k]) {
+                set_error("every system needs its own x");
+                return DG_ERR_ARG;
+            }
+    }
+    int rc = solve_batched(m, nsys, lambdas, nu_fields, is_poisson, rhs, x, o, infos);
+    if (infos)
+        for (int k = 0; k < nsys; ++k) infos[k].seconds = now() - t0;
+    return rc;
 }
 
 int poisson_solve(dg_mesh *m, const double *rhs, double *x, const dg_solve_opts *opts,

@@ -18,7 +18,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = [os.path.join(HERE, "csrc", f)
-                  for f in ("kernels.hip", "device_common.h", "gll_constexpr.h")]
+                  for f in ("kernels.hip", "apply_core.h", "device_common.h", "gll_constexpr.h")]
 
 
 def kernel_sha():

@@ -1,0 +1,140 @@
+"""GPU parity of the persistent batched stage solve (3 velocity Helmholtz
+systems with a nodal viscosity + 1 pressure Poisson system, FP32 inner CG,
+FP64 refinement) against the oracle, and against the same systems solved
+one at a time.
+
+Bars: every system's collocation residual recomputed by the oracle
+<= 1e-10 (x 1.2 for the recomputation's own rounding); velocity results vs
+the exact discrete solution (dense Cholesky) <= 1e-10 relative; pressure
+(singular, kappa ~ 1e5..1e6) vs fast diagonalisation <= 1e-8 relative."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import dense, kron, naive, pcg
+from tests.gpu_util import say, to_dev, torch_dev
+from tests.helpers import make_spec, ndof, channel_nu
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def run_batched(spec, lams, nus, pois, fs, precision=1, **kw):
+    import paper_2112_04167_amd as dg
+    torch, dev = torch_dev()
+    mesh = dg.mesh_from_spec(spec)
+    rhs = [to_dev(f) for f in fs]
+    xs = [torch.zeros_like(r) for r in rhs]
+    nud = [None if v is None else to_dev(v) for v in nus]
+    o = dg.default_opts(precision=precision, **kw)
+    rc, infos = dg.helmholtz_solve_batched(mesh, lams, nud, pois, rhs, xs, o, raise_on_error=False)
+    out = [x.cpu().numpy() for x in xs]
+    mesh.destroy()
+    return rc, infos, out
+
+
+def stage_problem(spec):
+    N = ndof(spec)
+    nu = channel_nu(spec)
+    lam = synth.batched_lambda()
+    fs = [synth.uniform_field(N, s) for s in synth.SEEDS["batched_velocity"]]
+    fs.append(synth.uniform_field(N, synth.SEEDS["batched_pressure"]))
+    return [lam, lam, lam, 0.0], [nu, nu, nu, None], [0, 0, 0, 1], fs, nu, lam
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_batched_small_against_exact(precision):
+    spec = make_spec((2, 3, 2), 5, (0, 0, 1), False)
+    lams, nus, pois, fs, nu, lam = stage_problem(spec)
+    rc, infos, xs = run_batched(spec, lams, nus, pois, fs, precision=precision)
+    say("batched small", rc, infos)
+    assert rc == 0
+    M = dense.mass_diag(spec)
+    A = dense.assemble(spec, lam, nu)
+    opv = naive.Operator(spec, lam, nu)
+    for k in range(3):
+        xs_ = dense.solve(spec, A, M * fs[k], lam)
+        assert infos[k]["status"] == 0
+        assert rel(xs[k], xs_) <= 1e-10
+        assert pcg.true_rel_res(opv.apply, xs[k], M * fs[k], M) <= 1.2e-10
+    pspec = dict(spec)
+    pspec["bc"] = (0, 0, 2)
+    Mp = dense.mass_diag(pspec)
+    xp = kron.FDM(pspec, 0.0).solve(Mp * fs[3])
+    assert infos[3]["status"] == 0
+    assert rel(xs[3], xp) <= 1e-8
+    assert abs(np.dot(Mp, xs[3])) <= 1e-12 * np.linalg.norm(xs[3])
+    opp = naive.Operator(pspec, 0.0, 1.0)
+    assert pcg.true_rel_res(opp.apply, xs[3], Mp * fs[3], Mp, singular=True) <= 1.2e-10
+
+
+def test_batched_equals_solo():
+    import paper_2112_04167_amd as dg
+    torch, dev = torch_dev()
+    spec = make_spec((3, 3, 3), 5, (0, 0, 1), False)
+    lams, nus, pois, fs, nu, lam = stage_problem(spec)
+    rc, infos, xb = run_batched(spec, lams, nus, pois, fs)
+    assert rc == 0
+    mesh = dg.mesh_from_spec(spec)
+    o = dg.default_opts(precision=1)
+    for k in range(4):
+        fd = to_dev(fs[k])
+        xd = torch.zeros_like(fd)
+        if pois[k]:
+            info = dg.poisson_solve(mesh, fd, xd, o)
+            tol = 1e-8
+        else:
+            info = dg.helmholtz_solve(mesh, lams[k], to_dev(nus[k]), 0.0, fd, xd, o)
+            tol = 2e-10
+        assert info["status"] == 0
+        assert rel(xb[k], xd.cpu().numpy()) <= tol, k
+    mesh.destroy()
+
+
+def test_batched_retirement_and_iteration_counts():
+    # the Poisson system needs far more inner iterations than the velocity
+    # systems; each system reports its own counts
+    spec = make_spec((3, 3, 3), 5, (0, 0, 1), False)
+    lams, nus, pois, fs, nu, lam = stage_problem(spec)
+    rc, infos, xs = run_batched(spec, lams, nus, pois, fs)
+    assert rc == 0
+    vel = [infos[k]["iters"] for k in range(3)]
+    assert infos[3]["iters"] > 3 * max(vel)
+    for i in infos:
+        assert i["true_rel_res"] <= 1e-10 and i["outer_iters"] >= 1
+
+
+def test_batched_single_system_and_errors():
+    import paper_2112_04167_amd as dg
+    spec = make_spec((2, 2, 2), 4, (0, 0, 0), False)
+    f = synth.uniform_field(ndof(spec), 3)
+    rc, infos, xs = run_batched(spec, [5.0], [None], [0], [f])
+    assert rc == 0
+    M = dense.mass_diag(spec)
+    assert rel(xs[0], kron.FDM(spec, 5.0).solve(M * f)) <= 1e-10
+    bad = f.copy()
+    bad[3] = np.inf
+    rc, infos, _ = run_batched(spec, [5.0, 5.0], [None, None], [0, 0], [f, bad])
+    assert rc == dg.DG_ERR_NONFINITE
+    assert infos[0]["status"] == 0 and infos[1]["status"] == dg.DG_ERR_NONFINITE
+
+
+def test_batched_channel_full_size():
+    spec = synth.mesh_spec("batched_channel")   # 24^3, P=5, 3.0M nodes per field
+    lams, nus, pois, fs, nu, lam = stage_problem(spec)
+    rc, infos, xs = run_batched(spec, lams, nus, pois, fs)
+    say("batched channel", rc, infos)
+    assert rc == 0
+    M = dense.mass_diag(spec)
+    opv = naive.Operator(spec, lam, nu)
+    for k in range(3):
+        assert pcg.true_rel_res(opv.apply, xs[k], M * fs[k], M) <= 1.2e-10
+    pspec = dict(spec)
+    pspec["bc"] = (0, 0, 2)
+    opp = naive.Operator(pspec, 0.0, 1.0)
+    assert pcg.true_rel_res(opp.apply, xs[3], M * fs[3], M, singular=True) <= 1.2e-10
+    xp = kron.FDM(pspec, 0.0).solve(M * fs[3])
+    assert rel(xs[3], xp) <= 1e-8
