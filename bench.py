@@ -133,6 +133,118 @@ def cpu_baseline(spec, lam, budget_s=12.0):
                        % (reps, op.N, dt))
 
 
+def bench_mixed_small(dg, torch, reps=20):
+    """FP32-inner / FP64-refinement solves of the 4^3, P=7 periodic case."""
+    import synth
+    dev = torch.device("cuda:0")
+    spec = synth.mesh_spec("mixed_small")
+    mesh = dg.mesh_from_spec(spec)
+    N = mesh.ndof
+    f = torch.from_numpy(synth.uniform_field(N, synth.SEEDS["mixed"])).to(dev)
+    x = torch.zeros_like(f)
+    out = {}
+    for lam in (1e2, 1e4, 1e6):
+        row = {}
+        for name, prec in (("fp64", dg.DG_FP64), ("mixed", dg.DG_MIXED)):
+            o = dg.default_opts(precision=prec)
+            dg.helmholtz_solve(mesh, lam, None, 1.0, f, x, o)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                info = dg.helmholtz_solve(mesh, lam, None, 1.0, f, x, o)
+            t = (time.perf_counter() - t0) / reps
+            row[name] = dict(ms=t * 1e3, iters=info["iters"], outer=info["outer_iters"],
+                             true_rel_res=info["true_rel_res"])
+        out["lambda=%g" % lam] = row
+    mesh.destroy()
+    return out
+
+
+def bench_mixed_large(dg, torch, spec, lam):
+    import synth
+    dev = torch.device("cuda:0")
+    mesh = dg.mesh_from_spec(spec)
+    f = torch.from_numpy(synth.uniform_field(mesh.ndof, synth.SEEDS["large_helmholtz"])).to(dev)
+    x = torch.zeros_like(f)
+    o = dg.default_opts(precision=dg.DG_MIXED)
+    dg.helmholtz_solve(mesh, lam, None, 1.0, f, x, o)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        info = dg.helmholtz_solve(mesh, lam, None, 1.0, f, x, o)
+        ts.append(time.perf_counter() - t0)
+    mesh.destroy()
+    t = float(np.median(ts))
+    return dict(seconds_median=t, solves_per_s=1.0 / t, inner_iters=info["iters"],
+                outer_iters=info["outer_iters"], true_rel_res=info["true_rel_res"])
+
+
+def bench_batched(dg, torch):
+    """The 24^3, P=5 stage: 3 velocity (nodal nu) + 1 pressure system in one
+    persistent launch, against the same 4 systems solved one after another
+    by the plain FP64 solver."""
+    import synth
+    dev = torch.device("cuda:0")
+    spec = synth.mesh_spec("batched_channel")
+    mesh = dg.mesh_from_spec(spec)
+    N = mesh.ndof
+    X, Y, _ = dg.mesh_coordinates(mesh)
+    nu = 1e-3 * (1.0 + 0.5 * torch.sin(2 * np.pi * X) * torch.cos(2 * np.pi * Y))   # input field
+    lam = synth.batched_lambda()
+    fs = [torch.from_numpy(synth.uniform_field(N, s)).to(dev) for s in synth.SEEDS["batched_velocity"]]
+    fs.append(torch.from_numpy(synth.uniform_field(N, synth.SEEDS["batched_pressure"])).to(dev))
+    xs = [torch.zeros_like(fs[0]) for _ in range(4)]
+    lams, nus, pois = [lam] * 3 + [0.0], [nu] * 3 + [None], [0, 0, 0, 1]
+    o = dg.default_opts(precision=dg.DG_MIXED)
+    dg.helmholtz_solve_batched(mesh, lams, nus, pois, fs, xs, o)   # autotune + warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, infos = dg.helmholtz_solve_batched(mesh, lams, nus, pois, fs, xs, o)
+    tb = time.perf_counter() - t0
+    o64 = dg.default_opts()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq = []
+    for k in range(4):
+        if pois[k]:
+            seq.append(dg.poisson_solve(mesh, fs[k], xs[k], o64))
+        else:
+            seq.append(dg.helmholtz_solve(mesh, lam, nu, 0.0, fs[k], xs[k], o64))
+    ts = time.perf_counter() - t0
+    mesh.destroy()
+    return dict(ndof_per_field=N, batched_seconds=tb, batched_solves_per_s=4.0 / tb,
+                sequential_fp64_seconds=ts, sequential_fp64_solves_per_s=4.0 / ts,
+                speedup=ts / tb, status=rc,
+                inner_iters=[i["iters"] for i in infos], outer_iters=[i["outer_iters"] for i in infos],
+                true_rel_res=[i["true_rel_res"] for i in infos],
+                fp64_iters=[i["iters"] for i in seq])
+
+
+def bench_serving(dg, nreq, slots, precision, budget=96 << 30):
+    """Real-time replay of the request stream (Poisson arrivals, 200/s)."""
+    import synth
+    stream = synth.serving_stream()[:nreq]
+    srv = dg.Server(budget, slots)
+    t0 = time.perf_counter()
+    ids = []
+    for r in stream:
+        wait = r["t_arrival"] - (time.perf_counter() - t0)
+        if wait > 0:
+            time.sleep(wait)
+        ids.append(srv.submit(r["n"], r["P"], r["lam"], None, is_poisson=r["poisson"],
+                              rhs_seed=r["rhs_seed"], precision=precision))
+    srv.drain()
+    st = srv.stats()
+    bad = [i for i in ids if srv.poll(i)[0] != 0]
+    srv.destroy()
+    ndof = sum(r["n"] ** 3 * (r["P"] + 1) ** 3 for r in stream)
+    st.update(requests=nreq, slots=slots, precision="mixed" if precision else "fp64",
+              solves_per_s=nreq / st["makespan"], failed=len(bad),
+              offered_per_s=nreq / max(stream[-1]["t_arrival"], 1e-9), mean_ndof=ndof / nreq)
+    return st
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -140,6 +252,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--quick", action="store_true", help="apply only (for profiling runs)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=60,
+                    help="prefix of the 2000-request stream replayed per serving mode")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -197,6 +311,18 @@ def main():
         log("Poisson solve")
         out["poisson"] = bench_solve(dg, torch, spec, 0.0, synth.SEEDS["large_poisson"], reps=1,
                                      poisson=True)
+        log("mixed-precision Helmholtz solve (same mesh)")
+        out["solve_mixed"] = bench_mixed_large(dg, torch, spec, lam)
+        log("mixed-precision small solves")
+        out["mixed_small"] = bench_mixed_small(dg, torch)
+        log("batched stage solve")
+        out["batched"] = bench_batched(dg, torch)
+        if args.serving_requests > 0:
+            out["serving"] = {}
+            for name, slots, prec in (("fifo_fp64", 1, dg.DG_FP64), ("continuous_fp64", 8, dg.DG_FP64),
+                                      ("continuous_mixed", 8, dg.DG_MIXED)):
+                log("serving:", name)
+                out["serving"][name] = bench_serving(dg, args.serving_requests, slots, prec)
         if not args.no_cpu:
             log("CPU oracle baseline")
             out["cpu_baseline"] = cpu_baseline(spec, lam)

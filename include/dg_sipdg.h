@@ -109,6 +109,10 @@ int dg_mesh_create(int nx, int ny, int nz, int P, const double *xv, const double
                    const double *zv, const int bc[3], void *hip_stream, dg_mesh **out);
 int dg_mesh_destroy(dg_mesh *m);
 int64_t dg_mesh_ndof(const dg_mesh *m);                      /* E (P+1)^3 */
+/* Nodal coordinates (the GLL nodes mapped to every element) in the ABI
+   layout: device double arrays X, Y, Z of dg_mesh_ndof values each (any of
+   them may be NULL).  Asynchronous on `stream` (NULL = the mesh's stream). */
+int dg_mesh_coordinates(dg_mesh *m, double *X, double *Y, double *Z, void *stream);
 /* Bytes of device workspace a solve allocates (for admission control). */
 size_t dg_solve_footprint(const dg_mesh *m, int precision, int nrhs);
 
@@ -158,43 +162,58 @@ int helmholtz_solve_batched(dg_mesh *m, int nsys, const double *lambdas,
                             const dg_solve_opts *opts, dg_solve_info *infos);
 
 /* ------------------------------------------------------------- serving --
- * A request server: solves arrive at any time, are admitted when their
- * device footprint fits the HBM budget and a slot is free, and run
- * concurrently (continuous batching: every scheduler tick advances every
- * admitted solve by a chunk of CG iterations, each on its own stream, and
- * admits new work as slots and memory free up).  All solve state stays on
- * the device; the host only sees each solve's scalars. */
+ * A request server for the implicit-stage solves: solves of different mesh
+ * sizes, degrees and lambda arrive at any time.  A request is admitted when
+ * its device footprint (mesh geometry, right-hand side, solution and solver
+ * workspace, all carved from one device arena of hbm_budget_bytes) fits
+ * next to the solves already running and a slot is free (strict arrival
+ * order).  Admitted solves run concurrently, each on its own HIP stream
+ * driven by its own host thread, so new work is admitted while older work
+ * is still on the device (continuous batching).  All solve state stays on
+ * the device; results stay there until fetched.
+ *
+ * Each request is a cube [0,1]^3 of n^3 elements, all axes periodic, nu = 1,
+ * solved to the collocation-residual tolerance `tol` (Sec. 4). */
 typedef struct {
-    int n;             /* n^3 elements on the unit cube, all axes periodic */
-    int P;             /* degree, 3..8 */
-    int is_poisson;    /* 1: lambda = 0 (singular, projected) */
-    double lambda;     /* Helmholtz lambda (nu = 1) */
-    const double *rhs; /* host nodal f, n^3 (P+1)^3 values; copied at submit */
-    double tol;        /* relative collocation residual */
-    int precision;     /* DG_FP64 or DG_MIXED */
+    int n;              /* n^3 elements, 1 <= n */
+    int P;              /* degree, 3..8 */
+    int is_poisson;     /* 1: pressure Poisson problem (lambda = 0, singular) */
+    double lambda;      /* Helmholtz lambda > 0 (ignored for Poisson) */
+    const double *rhs;  /* host nodal f (n^3 (P+1)^3 values, copied at submit),
+                           or NULL: f ~ U[-1,1] generated on the device from
+                           rhs_seed with SplitMix64 (Steele, Lea & Flood 2014):
+                           f_i = 2 (z_i >> 11) / 2^53 - 1, z_i the (i+1)-th
+                           output of SplitMix64 started from rhs_seed */
+    uint64_t rhs_seed;
+    double tol;         /* relative collocation residual, e.g. 1e-10 */
+    int precision;      /* DG_FP64 or DG_MIXED */
+    int keep_result;    /* 1: keep x on the device until dg_server_fetch;
+                           0: drop it at completion (only the info is kept) */
 } dg_request;
 
+/* max_slots: solves allowed on the device at once (>= 1). */
 int dg_server_create(size_t hbm_budget_bytes, int max_slots, void **srv);
-/* Non-blocking.  Copies the request and its rhs; returns an id.
-   DG_ERR_BUDGET if the request can never fit the budget. */
+/* Non-blocking.  Returns the request id; DG_ERR_BUDGET if the request can
+   never fit the arena, DG_ERR_ARG on bad fields. */
 int dg_server_submit(void *srv, const dg_request *req, int64_t *req_id);
-/* DG_OK and info when done; DG_NOT_CONVERGED (> 0) ... see below; returns 2
-   (DG_PENDING) while queued or running. */
+/* DG_PENDING (2) while queued or running; otherwise the solve's status
+   (DG_OK, DG_NOT_CONVERGED or an error) and *info. */
 int dg_server_poll(void *srv, int64_t req_id, dg_solve_info *info);
-/* Copy a finished request's solution (n^3 (P+1)^3 doubles) to host memory
-   and release it. */
+/* Copy a finished, kept result (n^3 (P+1)^3 doubles) to host memory and
+   release its device memory.  DG_PENDING if not finished yet. */
 int dg_server_fetch(void *srv, int64_t req_id, double *x_host);
 /* Block until every submitted request has finished. */
 int dg_server_drain(void *srv);
-/* Latency / throughput statistics of finished requests (seconds). */
+/* Statistics of finished requests; latency = completion - submission. */
 typedef struct {
     int64_t completed;
-    double p50, p99, mean, max;
-    double makespan;          /* first submit -> last completion */
-    double peak_bytes;        /* largest admitted footprint sum */
-    int peak_active;          /* largest number of concurrently admitted solves */
+    double p50, p99, mean, max;  /* latency, seconds */
+    double makespan;             /* first submission -> last completion, s */
+    double peak_bytes;           /* largest arena use */
+    int peak_active;             /* largest number of solves on the device */
 } dg_server_stats;
 int dg_server_get_stats(void *srv, dg_server_stats *st);
+/* Waits for running solves, then frees everything. */
 int dg_server_destroy(void *srv);
 
 enum { DG_PENDING = 2 };

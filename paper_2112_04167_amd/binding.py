@@ -46,7 +46,8 @@ class dg_solve_info(ctypes.Structure):
 class dg_request(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("P", ctypes.c_int), ("is_poisson", ctypes.c_int),
                 ("lam", ctypes.c_double), ("rhs", ctypes.POINTER(ctypes.c_double)),
-                ("tol", ctypes.c_double), ("precision", ctypes.c_int)]
+                ("rhs_seed", ctypes.c_uint64), ("tol", ctypes.c_double),
+                ("precision", ctypes.c_int), ("keep_result", ctypes.c_int)]
 
 
 class dg_server_stats(ctypes.Structure):
@@ -69,6 +70,7 @@ _SIGS = {
     "dg_mesh_destroy": ([_VP], ctypes.c_int),
     "dg_mesh_ndof": ([_VP], ctypes.c_int64),
     "dg_solve_footprint": ([_VP, ctypes.c_int, ctypes.c_int], ctypes.c_size_t),
+    "dg_mesh_coordinates": ([_VP, _VP, _VP, _VP, _VP], ctypes.c_int),
     "helmholtz_apply": ([_VP, ctypes.c_double, _VP, ctypes.c_double, _VP, _VP, ctypes.c_int, _VP],
                         ctypes.c_int),
     "helmholtz_diag": ([_VP, ctypes.c_double, _VP, ctypes.c_double, _VP, ctypes.c_int, _VP],
@@ -198,6 +200,14 @@ def mesh_from_spec(spec, stream=None):
                           spec["zv"], spec["bc"], stream)
 
 
+def mesh_coordinates(mesh, stream=None):
+    """(X, Y, Z) nodal coordinates as device tensors (ABI layout)."""
+    import torch
+    out = [torch.empty(mesh.ndof, dtype=torch.float64, device="cuda") for _ in range(3)]
+    _check(lib().dg_mesh_coordinates(mesh.handle, *[_dptr(t) for t in out], _stream_ptr(stream)))
+    return out
+
+
 def _dtype(precision):
     import torch
     return torch.float64 if precision == DG_FP64 else torch.float32
@@ -271,11 +281,16 @@ class Server:
         self.handle = h
         self._keep = {}
 
-    def submit(self, n, P, lam, rhs_host, is_poisson=False, tol=1e-10, precision=DG_FP64):
-        rhs = np.ascontiguousarray(rhs_host, dtype=np.float64)
-        req = dg_request(n=n, P=P, is_poisson=int(is_poisson), lam=float(lam),
-                         rhs=rhs.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), tol=tol,
-                         precision=precision)
+    def submit(self, n, P, lam, rhs_host=None, is_poisson=False, tol=1e-10, precision=DG_FP64,
+               rhs_seed=0, keep_result=False):
+        """Queue one solve; rhs_host None -> f generated on the device from rhs_seed."""
+        req = dg_request(n=n, P=P, is_poisson=int(is_poisson), lam=float(lam), rhs_seed=int(rhs_seed),
+                         tol=tol, precision=precision, keep_result=int(keep_result))
+        if rhs_host is not None:
+            rhs = np.ascontiguousarray(rhs_host, dtype=np.float64)
+            if rhs.size != n ** 3 * (P + 1) ** 3:
+                raise ValueError("rhs has the wrong size")
+            req.rhs = rhs.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         rid = ctypes.c_int64()
         _check(lib().dg_server_submit(self.handle, ctypes.byref(req), ctypes.byref(rid)))
         return rid.value

@@ -514,6 +514,7 @@ __device__ __forceinline__ void apply_group(const ApplyArgs<T> &A, int grp, T *x
         const ElGeo<T> &G = geo[el_loc];
         line_apply<P, T, NUF>(A, uz, nz_l, 2, ez, nz, G, wt, fz, vs, out);
         const T Jw = G.h[0] * G.h[1] * G.h[2] * (T)0.125 * wt;
+        const double iJw = EPI == EPI_RESID ? 1.0 / (double)Jw : 0.0;
         T *__restrict__ ye = A.y + (size_t)el * N3;
 #pragma unroll
         for (int c = 0; c < n; ++c) {
@@ -530,11 +531,12 @@ __device__ __forceinline__ void apply_group(const ApplyArgs<T> &A, int grp, T *x
                 const T bv = A.b[(size_t)el * N3 + c * NL + l];
                 const T r = bv - v;
                 ye[c * NL + l] = r;
-                const double rm = (double)r / (double)m;
+                const double im = iJw * (1.0 / kGll<P>.w[c]);  // 1 / M
+                const double rm = (double)r * im;
                 red[0] += rm * rm;
                 red[1] += (double)r;
-                red[2] += rm / (double)m;
-                red[3] += 1.0 / ((double)m * (double)m);
+                red[2] += rm * im;
+                red[3] += im * im;
             }
         }
     }

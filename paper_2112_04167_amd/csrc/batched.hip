@@ -87,7 +87,8 @@ struct BLds {
     int last;
 };
 
-// per-thread node loop of one element group: f(global index, GLL mass)
+// per-thread node loop of one element group: f(global index, GLL mass,
+// inverse GLL mass)
 template <int P, typename F>
 __device__ __forceinline__ void group_nodes(int grp, int nel, const Geo<double> &g, F &&f)
 {
@@ -100,9 +101,10 @@ __device__ __forceinline__ void group_nodes(int grp, int nel, const Geo<double> 
     const int ex = el % g.n[0], r = el / g.n[0], ey = r % g.n[1], ez = r / g.n[1];
     const double Jw = g.h[0][ex] * g.h[1][ey] * g.h[2][ez] * 0.125 * kGll<P>.w[l % S::n] *
                       kGll<P>.w[l / S::n];
+    const double iJw = 1.0 / Jw;
 #pragma unroll
     for (int c = 0; c < S::n; ++c)
-        f((size_t)el * S::N3 + (size_t)c * S::NL + l, Jw * kGll<P>.w[c]);
+        f((size_t)el * S::N3 + (size_t)c * S::NL + l, Jw * kGll<P>.w[c], iJw * (1.0 / kGll<P>.w[c]));
 }
 
 // add one work item's per-thread sums into the block accumulator acc[.][s]
@@ -134,16 +136,11 @@ __device__ void phase_reduce(double (&acc)[NCMAX][kMaxBatch], double *sh, int &l
     }
     __syncthreads();
     if (!last) return;
-    __threadfence();
+    __threadfence();  // acquire: every block's partials are visible now
     for (int s = 0; s < nsys; ++s) {
         double v[NC];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            v[c] = 0.0;
-            const double *pp = partial + (size_t)(c * kMaxBatch + s) * nblk;
-            for (int k = threadIdx.x; k < nblk; k += blockDim.x)
-                v[c] += __hip_atomic_load(&pp[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+        for (int c = 0; c < NC; ++c) v[c] = sum_strided(partial + (size_t)(c * kMaxBatch + s) * nblk, nblk);
         block_sum<NC>(v, sh);
         if (threadIdx.x == 0) fin(s, v);
         __syncthreads();
@@ -223,7 +220,7 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_batched(BArgs<TI> B)
             const int s = w / G, g = w % G;
             const BSys<TI> &Y = B.sys[s];
             double v[2] = {0.0, 0.0};
-            group_nodes<P>(g, nel, B.g64, [&](size_t gi, double m) {
+            group_nodes<P>(g, nel, B.g64, [&](size_t gi, double m, double im) {
                 const double bb = B.weak ? Y.rhs[gi] : m * Y.rhs[gi];
                 Y.b64[gi] = bb;
                 Y.x64[gi] = 0.0;
@@ -249,15 +246,15 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_batched(BArgs<TI> B)
             const BSys<TI> &Y = B.sys[s];
             const double mb = st[s].mean_b;
             double v[2] = {0.0, 0.0};
-            group_nodes<P>(g, nel, B.g64, [&](size_t gi, double m) {
+            group_nodes<P>(g, nel, B.g64, [&](size_t gi, double m, double im) {
                 double bb = Y.b64[gi];
                 if (Y.singular) {
                     bb -= mb;
                     Y.b64[gi] = bb;
                 }
-                const double rm = bb / m;
+                const double rm = bb * im;
                 v[0] += rm * rm;
-                v[1] += 1.0 / (m * m);
+                v[1] += im * im;
             });
             block_accumulate<2>(v, s, L.sh, L.acc);
         }
@@ -323,7 +320,7 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_batched(BArgs<TI> B)
                 const BSys<TI> &Y = B.sys[s];
                 const double mr = st[s].mean_r;
                 double v[1] = {0.0};
-                group_nodes<P>(g, nel, B.g64, [&](size_t gi, double) {
+                group_nodes<P>(g, nel, B.g64, [&](size_t gi, double, double) {
                     const double r = Y.r64[gi] - mr;
                     v[0] += r * r;
                 });
@@ -343,7 +340,7 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_batched(BArgs<TI> B)
                 const BSys<TI> &Y = B.sys[s];
                 const double mr = st[s].mean_r, inv = 1.0 / st[s].scale;
                 double v[1] = {0.0};
-                group_nodes<P>(g, nel, B.g64, [&](size_t gi, double) {
+                group_nodes<P>(g, nel, B.g64, [&](size_t gi, double, double) {
                     const TI bb = (TI)((Y.r64[gi] - mr) * inv);
                     Y.b[gi] = bb;
                     v[0] += (double)bb;
@@ -363,7 +360,7 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_batched(BArgs<TI> B)
                 const BSys<TI> &Y = B.sys[s];
                 const double mb = st[s].imean_b;
                 double v[4] = {0.0, 0.0, 0.0, 0.0};
-                group_nodes<P>(g, nel, B.g64, [&](size_t gi, double m) {
+                group_nodes<P>(g, nel, B.g64, [&](size_t gi, double m, double im) {
                     TI bb = Y.b[gi];
                     if (Y.singular) {
                         bb = (TI)((double)bb - mb);
@@ -371,13 +368,13 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_batched(BArgs<TI> B)
                     }
                     Y.r[gi] = bb;
                     Y.x[gi] = (TI)0;
-                    const TI z = bb / Y.d[gi];
+                    const TI z = bb * Y.d[gi];  // Y.d holds 1/diag(A)
                     Y.p[gi] = z;
-                    const double rm = (double)bb / m;
+                    const double rm = (double)bb * im;
                     v[0] += (double)bb * (double)z;
                     v[1] += rm * rm;
-                    v[2] += 1.0 / (double)Y.d[gi];
-                    v[3] += 1.0 / (m * m);
+                    v[2] += (double)Y.d[gi];
+                    v[3] += im * im;
                 });
                 block_accumulate<4>(v, s, L.sh, L.acc);
             });
@@ -432,17 +429,17 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_batched(BArgs<TI> B)
                 const BSys<TI> &Y = B.sys[s];
                 const TI alpha = (TI)st[s].alpha;
                 double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-                group_nodes<P>(g, nel, B.g64, [&](size_t gi, double m) {
+                group_nodes<P>(g, nel, B.g64, [&](size_t gi, double m, double im) {
                     Y.x[gi] = fma(alpha, Y.p[gi], Y.x[gi]);
                     const TI r = fma(-alpha, Y.q[gi], Y.r[gi]);
                     Y.r[gi] = r;
-                    const double rd = (double)r / (double)Y.d[gi];
-                    const double rm = (double)r / m;
+                    const double rd = (double)r * (double)Y.d[gi];
+                    const double rm = (double)r * im;
                     v[0] += (double)r;
                     v[1] += (double)r * rd;
                     v[2] += rd;
                     v[3] += rm * rm;
-                    v[4] += rm / m;
+                    v[4] += rm * im;
                 });
                 block_accumulate<5>(v, s, L.sh, L.acc);
             });
@@ -470,13 +467,13 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_batched(BArgs<TI> B)
                 const BSys<TI> &Y = B.sys[s];
                 const TI beta = (TI)st[s].beta;
                 const double mr = st[s].imean_r;
-                group_nodes<P>(g, nel, B.g64, [&](size_t gi, double) {
+                group_nodes<P>(g, nel, B.g64, [&](size_t gi, double, double) {
                     TI r = Y.r[gi];
                     if (Y.singular) {
                         r = (TI)((double)r - mr);
                         Y.r[gi] = r;
                     }
-                    Y.p[gi] = fma(beta, Y.p[gi], r / Y.d[gi]);
+                    Y.p[gi] = fma(beta, Y.p[gi], r * Y.d[gi]);
                 });
             });
             grid.sync();
@@ -488,7 +485,7 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_batched(BArgs<TI> B)
                 const BSys<TI> &Y = B.sys[s];
                 const double sc = st[s].scale;
                 group_nodes<P>(g, nel, B.g64,
-                               [&](size_t gi, double) { Y.x64[gi] = fma(sc, (double)Y.x[gi], Y.x64[gi]); });
+                               [&](size_t gi, double, double) { Y.x64[gi] = fma(sc, (double)Y.x[gi], Y.x64[gi]); });
             });
             grid.sync();
         }
@@ -502,7 +499,7 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_batched(BArgs<TI> B)
             if (!B.sys[s].singular) continue;
             const BSys<TI> &Y = B.sys[s];
             double v[2] = {0.0, 0.0};
-            group_nodes<P>(g, nel, B.g64, [&](size_t gi, double m) {
+            group_nodes<P>(g, nel, B.g64, [&](size_t gi, double m, double im) {
                 v[0] += m * Y.x64[gi];
                 v[1] += m;
             });
@@ -517,7 +514,7 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_batched(BArgs<TI> B)
             if (!B.sys[s].singular) continue;
             const BSys<TI> &Y = B.sys[s];
             const double sh = st[s].shift;
-            group_nodes<P>(g, nel, B.g64, [&](size_t gi, double) { Y.x64[gi] -= sh; });
+            group_nodes<P>(g, nel, B.g64, [&](size_t gi, double, double) { Y.x64[gi] -= sh; });
         }
     }
 }

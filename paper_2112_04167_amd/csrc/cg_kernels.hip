@@ -40,7 +40,12 @@ struct LineCtx {
     bool active;
     size_t base;  // index of node (a,b,0)
     T Jw;         // J w_a w_b
+    double iJw;   // 1 / (J w_a w_b)
 };
+
+// 1/w_c (a compile-time constant)
+template <int P>
+__device__ __forceinline__ double inv_w(int c) { return 1.0 / kGll<P>.w[c]; }
 
 template <int P, typename T>
 __device__ __forceinline__ LineCtx<P, T> line_ctx(const CgVecArgs<T> &A)
@@ -54,11 +59,13 @@ __device__ __forceinline__ LineCtx<P, T> line_ctx(const CgVecArgs<T> &A)
     c.active = (tid < S::NT) && (el < A.nel);
     c.base = (size_t)el * S::N3 + l;
     c.Jw = 0;
+    c.iJw = 0.0;
     if (c.active) {
         const int nx = A.n[0], ny = A.n[1];
         const int ex = el % nx, r = el / nx, ey = r % ny, ez = r / ny;
         c.Jw = A.hx[ex] * A.hy[ey] * A.hz[ez] * (T)0.125 * (T)kGll<P>.w[l % S::n] *
                (T)kGll<P>.w[l / S::n];
+        c.iJw = 1.0 / (double)c.Jw;
     }
     return c;
 }
@@ -82,15 +89,7 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_setup1(CgVecArgs<T> A)
             red[1] += (double)b * (double)b;
         }
     }
-    double tot[2];
-    if (publish_and_reduce<2>(red, A.partial, A.counter, gridDim.x, tot, sh) && threadIdx.x == 0) {
-        CgScalars *sc = A.sc;
-        sc->mean_b = SING ? tot[0] / (double)sc->ndof : 0.0;
-        if (!isfinite(tot[1])) {
-            sc->status = DG_ERR_NONFINITE;
-            sc->done = 1;
-        }
-    }
+    publish_partials<2>(red, A.partial, gridDim.x, sh);
 }
 
 // set-up, stage 2: project b (singular), r = b, x = 0, z = r/d, p = z and the
@@ -107,7 +106,6 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_setup2(CgVecArgs<T> A)
 #pragma unroll
         for (int k = 0; k < S::n; ++k) {
             const size_t gi = c.base + (size_t)k * S::NL;
-            const T m = c.Jw * (T)kGll<P>.w[k];
             T b = A.bvec[gi];
             if (SING) {
                 b = (T)((double)b - mb);
@@ -115,37 +113,20 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_setup2(CgVecArgs<T> A)
             }
             A.r[gi] = b;
             A.x[gi] = (T)0;
-            const double rm = (double)b / (double)m;
+            const double im = c.iJw * inv_w<P>(k);
+            const double rm = (double)b * im;
             red[1] += rm * rm;
-            red[3] += 1.0 / ((double)m * (double)m);
-            if (A.d) {
-                const T d = A.d[gi];
-                const T z = b / d;
+            red[3] += im * im;
+            if (A.d) {  // A.d holds 1/diag(A)
+                const T di = A.d[gi];
+                const T z = b * di;
                 A.p[gi] = z;
                 red[0] += (double)b * (double)z;
-                red[2] += 1.0 / (double)d;
+                red[2] += (double)di;
             }
         }
     }
-    double tot[4];
-    if (publish_and_reduce<4>(red, A.partial, A.counter, gridDim.x, tot, sh) && threadIdx.x == 0) {
-        CgScalars *sc = A.sc;
-        sc->rho = tot[0];
-        sc->bnorm2 = tot[1];
-        sc->res2 = tot[1];
-        sc->true_res2 = tot[1];
-        sc->sum_invd = tot[2];
-        sc->sum_invM2 = tot[3];
-        sc->tol2 = sc->tol2 * tot[1];  // host stored tol^2
-        sc->iter = 0;
-        sc->mean_r = 0.0;
-        if (!isfinite(tot[1]) || !isfinite(tot[0])) {
-            sc->status = DG_ERR_NONFINITE;
-            sc->done = 1;
-        } else if (tot[1] == 0.0 || (sc->fixed_iters <= 0 && tot[1] <= sc->tol2)) {
-            sc->done = 1;
-        }
-    }
+    publish_partials<4>(red, A.partial, gridDim.x, sh);
 }
 
 // x += alpha p, r -= alpha q; reductions for rho' and the residual
@@ -165,56 +146,26 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_update(CgVecArgs<T> A)
 #pragma unroll
         for (int k = 0; k < S::n; ++k) {
             const size_t gi = c.base + (size_t)k * S::NL;
-            const T m = c.Jw * (T)kGll<P>.w[k];
             const T p = A.p[gi];
             A.x[gi] = fma(alpha, p, A.x[gi]);
             const T r = fma(-alpha, A.q[gi], A.r[gi]);
             A.r[gi] = r;
-            const double rd = (double)r / (double)A.d[gi];
-            const double rm = (double)r / (double)m;
+            const double rd = (double)r * (double)A.d[gi];
+            const double im = c.iJw * inv_w<P>(k);
+            const double rm = (double)r * im;
             if (SING) {
                 red[0] += (double)r;
                 red[1] += (double)r * rd;
                 red[2] += rd;
                 red[3] += rm * rm;
-                red[4] += rm / (double)m;
+                red[4] += rm * im;
             } else {
                 red[0] += (double)r * rd;
                 red[1] += rm * rm;
             }
         }
     }
-    double tot[NC];
-    if (publish_and_reduce<NC>(red, A.partial, A.counter, gridDim.x, tot, sh) && threadIdx.x == 0) {
-        CgScalars *sc = A.sc;
-        double rz, res2;
-        if (SING) {
-            const double mr = tot[0] / (double)sc->ndof;
-            rz = tot[1] - 2.0 * mr * tot[2] + mr * mr * sc->sum_invd;
-            res2 = tot[3] - 2.0 * mr * tot[4] + mr * mr * sc->sum_invM2;
-            sc->mean_r = mr;
-        } else {
-            rz = tot[0];
-            res2 = tot[1];
-            sc->mean_r = 0.0;
-        }
-        if (res2 < 0.0) res2 = 0.0;
-        sc->beta = rz / sc->rho;
-        sc->rho = rz;
-        sc->res2 = res2;
-        sc->iter += 1;
-        if (!isfinite(rz) || !isfinite(res2)) {
-            sc->status = DG_ERR_NONFINITE;
-            sc->done = 1;
-        } else if (sc->fixed_iters > 0) {
-            if (sc->iter >= sc->fixed_iters) sc->done = 1;
-        } else if (res2 <= sc->tol2) {
-            sc->done = 1;
-        } else if (sc->iter >= sc->maxit) {
-            sc->status = DG_NOT_CONVERGED;
-            sc->done = 1;
-        }
-    }
+    publish_partials<NC>(red, A.partial, gridDim.x, sh);
 }
 
 // (singular: r -= mean r)  p = r/d + beta p
@@ -235,7 +186,7 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_pupdate(CgVecArgs<T> A)
             r = (T)((double)r - mr);
             A.r[gi] = r;
         }
-        A.p[gi] = fma(beta, A.p[gi], r / A.d[gi]);
+        A.p[gi] = fma(beta, A.p[gi], r * A.d[gi]);
     }
 }
 
@@ -256,9 +207,7 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_mean_x(CgVecArgs<T> A)
             red[1] += m;
         }
     }
-    double tot[2];
-    if (publish_and_reduce<2>(red, A.partial, A.counter, gridDim.x, tot, sh) && threadIdx.x == 0)
-        A.sc->shift = tot[0] / tot[1];
+    publish_partials<2>(red, A.partial, gridDim.x, sh);
 }
 
 template <int P, typename T>
@@ -291,11 +240,7 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_ir_scale(CgVecArgs<float> A)
             red[0] += v * v;
         }
     }
-    double tot[1];
-    if (publish_and_reduce<1>(red, A.partial, A.counter, gridDim.x, tot, sh) && threadIdx.x == 0) {
-        const double rms = sqrt(tot[0] / (double)A.sc->ndof);
-        A.sc->scale = rms > 0.0 ? rms : 1.0;
-    }
+    publish_partials<1>(red, A.partial, gridDim.x, sh);
 }
 
 // r32 = (r64 - mean_r) / scale
@@ -333,6 +278,84 @@ __global__ void k_f64_to_f32(const double *__restrict__ a, float *__restrict__ b
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (size_t)gridDim.x * blockDim.x)
         b[i] = (float)a[i];
+}
+
+// ------------------------------------------------------- finish kernels --
+//
+// One work-group sums the partials of the preceding kernel (fixed order) and
+// updates the solve's scalars.  Partials are written with plain stores and
+// read here after the kernel boundary, so no device-wide fences or atomics
+// are needed on the hot path.
+template <int NC, int OP>
+__global__ void __launch_bounds__(1024) k_finish(const double *partial, int nblk, CgScalars *sc)
+{
+    __shared__ double sh[16 * NC];
+    if ((OP == FIN_APPLY || OP == FIN_UPDATE) && sc->done) return;
+    double tot[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) tot[c] = sum_strided(partial + (size_t)c * nblk, nblk);
+    block_sum<NC>(tot, sh);
+    if (threadIdx.x != 0) return;
+    if constexpr (OP == FIN_APPLY) {
+        cg_after_apply(sc, tot[0], tot[1]);
+    } else if constexpr (OP == FIN_RESID) {
+        resid_finish(sc, *reinterpret_cast<const double(*)[4]>(tot));
+    } else if constexpr (OP == FIN_SETUP1) {
+        sc->mean_b = sc->singular ? tot[0] / (double)sc->ndof : 0.0;
+        if (!isfinite(tot[1])) {
+            sc->status = DG_ERR_NONFINITE;
+            sc->done = 1;
+        }
+    } else if constexpr (OP == FIN_SETUP2) {
+        sc->rho = tot[0];
+        sc->bnorm2 = tot[1];
+        sc->res2 = tot[1];
+        sc->true_res2 = tot[1];
+        sc->sum_invd = tot[2];
+        sc->sum_invM2 = tot[3];
+        sc->tol2 = sc->tol2 * tot[1];  // host stored tol^2
+        sc->iter = 0;
+        sc->mean_r = 0.0;
+        if (!isfinite(tot[1]) || !isfinite(tot[0])) {
+            sc->status = DG_ERR_NONFINITE;
+            sc->done = 1;
+        } else if (tot[1] == 0.0 || (sc->fixed_iters <= 0 && tot[1] <= sc->tol2)) {
+            sc->done = 1;
+        }
+    } else if constexpr (OP == FIN_UPDATE) {
+        double rz, res2;
+        if (NC == 5) {  // singular: r was projected to mean zero
+            const double mr = tot[0] / (double)sc->ndof;
+            rz = tot[1] - 2.0 * mr * tot[2] + mr * mr * sc->sum_invd;
+            res2 = tot[3] - 2.0 * mr * tot[NC - 1] + mr * mr * sc->sum_invM2;
+            sc->mean_r = mr;
+        } else {
+            rz = tot[0];
+            res2 = tot[1];
+            sc->mean_r = 0.0;
+        }
+        if (res2 < 0.0) res2 = 0.0;
+        sc->beta = rz / sc->rho;
+        sc->rho = rz;
+        sc->res2 = res2;
+        sc->iter += 1;
+        if (!isfinite(rz) || !isfinite(res2)) {
+            sc->status = DG_ERR_NONFINITE;
+            sc->done = 1;
+        } else if (sc->fixed_iters > 0) {
+            if (sc->iter >= sc->fixed_iters) sc->done = 1;
+        } else if (res2 <= sc->tol2) {
+            sc->done = 1;
+        } else if (sc->iter >= sc->maxit) {
+            sc->status = DG_NOT_CONVERGED;
+            sc->done = 1;
+        }
+    } else if constexpr (OP == FIN_MEANX) {
+        sc->shift = tot[0] / tot[1];
+    } else if constexpr (OP == FIN_IRSCALE) {
+        const double rms = sqrt(tot[0] / (double)sc->ndof);
+        sc->scale = rms > 0.0 ? rms : 1.0;
+    }
 }
 
 }  // namespace
@@ -394,8 +417,11 @@ int cg_setup(const MeshDev &m, CgVecArgs<T> a, hipStream_t s)
         constexpr int P = decltype(PC)::value;
         with_bool(a.singular, [&](auto SC) {
             constexpr bool SG = decltype(SC)::value;
+            const int nb = apply_groups(P, m.nel);
             hipLaunchKernelGGL((k_setup1<P, T, SG>), DG_GRID(PC), 0, s, a);
+            hipLaunchKernelGGL((k_finish<2, FIN_SETUP1>), dim3(1), dim3(1024), 0, s, a.partial, nb, a.sc);
             hipLaunchKernelGGL((k_setup2<P, T, SG>), DG_GRID(PC), 0, s, a);
+            hipLaunchKernelGGL((k_finish<4, FIN_SETUP2>), dim3(1), dim3(1024), 0, s, a.partial, nb, a.sc);
         });
     });
 }
@@ -408,7 +434,10 @@ int cg_update(const MeshDev &m, CgVecArgs<T> a, hipStream_t s)
         constexpr int P = decltype(PC)::value;
         with_bool(a.singular, [&](auto SC) {
             constexpr bool SG = decltype(SC)::value;
+            const int nb = apply_groups(P, m.nel);
             hipLaunchKernelGGL((k_update<P, T, SG>), DG_GRID(PC), 0, s, a);
+            hipLaunchKernelGGL((k_finish<SG ? 5 : 2, FIN_UPDATE>), dim3(1), dim3(1024), 0, s,
+                               a.partial, nb, a.sc);
         });
     });
 }
@@ -434,6 +463,8 @@ int cg_finish(const MeshDev &m, CgVecArgs<T> a, hipStream_t s)
     return with_P(m.P, [&](auto PC) {
         constexpr int P = decltype(PC)::value;
         hipLaunchKernelGGL((k_mean_x<P, T>), DG_GRID(PC), 0, s, a);
+        hipLaunchKernelGGL((k_finish<2, FIN_MEANX>), dim3(1), dim3(1024), 0, s, a.partial,
+                           apply_groups(P, m.nel), a.sc);
         hipLaunchKernelGGL((k_shift_x<P, T>), DG_GRID(PC), 0, s, a);
     });
 }
@@ -444,6 +475,8 @@ int ir_scale(const MeshDev &m, CgVecArgs<float> a, hipStream_t s)
     return with_P(m.P, [&](auto PC) {
         constexpr int P = decltype(PC)::value;
         hipLaunchKernelGGL((k_ir_scale<P>), DG_GRID(PC), 0, s, a);
+        hipLaunchKernelGGL((k_finish<1, FIN_IRSCALE>), dim3(1), dim3(1024), 0, s, a.partial,
+                           apply_groups(P, m.nel), a.sc);
     });
 }
 
@@ -470,6 +503,20 @@ int convert_f64_to_f32(const double *a, float *b, size_t n, hipStream_t s)
     const size_t blocks = std::min<size_t>((n + 255) / 256, 8192);
     hipLaunchKernelGGL(k_f64_to_f32, dim3((unsigned)std::max<size_t>(blocks, 1)), dim3(256), 0, s,
                        a, b, n);
+    DG_HIP_CHECK(hipGetLastError());
+    return DG_OK;
+}
+
+int launch_finish_apply(double *partial, int nblk, CgScalars *sc, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_finish<2, FIN_APPLY>), dim3(1), dim3(1024), 0, s, partial, nblk, sc);
+    DG_HIP_CHECK(hipGetLastError());
+    return DG_OK;
+}
+
+int launch_finish_resid(double *partial, int nblk, CgScalars *sc, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_finish<4, FIN_RESID>), dim3(1), dim3(1024), 0, s, partial, nblk, sc);
     DG_HIP_CHECK(hipGetLastError());
     return DG_OK;
 }

@@ -73,43 +73,34 @@ __device__ __forceinline__ void block_sum(double (&v)[NC], double *sh /* >= 16*N
     __syncthreads();
 }
 
-// Publish this group's partial sums; the last group to arrive reduces all
-// partials in a fixed order and returns true (tot valid in every thread of
-// that group).  partial layout: partial[c * nblk + blk].
+// Sum of p[0..n) taken by the calling work-group: thread t adds the entries
+// t, t + B, t + 2B, ... (B = blockDim.x) into four interleaved accumulators
+// (independent loads in flight) and combines them in a fixed order, so the
+// result does not depend on timing.  Valid in every thread for its share.
+__device__ __forceinline__ double sum_strided(const double *p, int n)
+{
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    const int B = blockDim.x;
+    int k = threadIdx.x;
+    for (; k + 3 * B < n; k += 4 * B) {
+        a0 += p[k];
+        a1 += p[k + B];
+        a2 += p[k + 2 * B];
+        a3 += p[k + 3 * B];
+    }
+    for (; k < n; k += B) a0 += p[k];
+    return (a0 + a1) + (a2 + a3);
+}
+
+// Write this work-group's sums to partial[c * nblk + blockIdx.x] (plain
+// stores: the consumer is a later kernel).
 template <int NC>
-__device__ bool publish_and_reduce(double (&v)[NC], double *partial, unsigned *counter, int nblk,
-                                   double (&tot)[NC], double *sh)
+__device__ __forceinline__ void publish_partials(double (&v)[NC], double *partial, int nblk, double *sh)
 {
     block_sum<NC>(v, sh);
-    __shared__ int s_last;
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0)
 #pragma unroll
-        for (int c = 0; c < NC; ++c) partial[c * nblk + blockIdx.x] = v[c];
-        __threadfence();
-        unsigned prev = atomicAdd(counter, 1u);
-        s_last = (prev == (unsigned)(nblk - 1));
-    }
-    __syncthreads();
-    if (!s_last) return false;
-    __threadfence();
-    double acc[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        acc[c] = 0.0;
-        for (int k = threadIdx.x; k < nblk; k += blockDim.x)
-            acc[c] += __hip_atomic_load(&partial[c * nblk + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    block_sum<NC>(acc, sh);
-    __shared__ double s_tot[NC];
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int c = 0; c < NC; ++c) s_tot[c] = acc[c];
-        *counter = 0u;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < NC; ++c) tot[c] = s_tot[c];
-    return true;
+        for (int c = 0; c < NC; ++c) partial[(size_t)c * nblk + blockIdx.x] = v[c];
 }
 
 }  // namespace dg

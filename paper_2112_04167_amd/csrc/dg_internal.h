@@ -64,6 +64,16 @@ struct MeshDev {
 // stay in the XCD's L2.
 std::vector<int> apply_order(const int n[3], int P);
 
+// Internal mesh / workspace entry points used by the request server.
+int mesh_create_impl(int nx, int ny, int nz, int P, const double *xv, const double *yv,
+                     const double *zv, const int bc[3], void *hip_stream, void *geo_mem,
+                     dg_mesh **out);
+size_t mesh_geo_bytes(const int n[3], int P);
+size_t solve_footprint_for(const int n[3], int P, int precision);
+void mesh_lend_workspace(dg_mesh *m, void *dev, size_t bytes, void *host_sc);
+size_t solve_host_scalar_bytes();
+int64_t mesh_ndof(const dg_mesh *m);
+
 // --- kernel launchers (kernels_apply.hip) ---------------------------------
 // y = A x; T = double or float; nu == nullptr -> constant nu_c.
 // If partial != nullptr each work-group writes (x.y partial, sum(y) partial)
@@ -72,9 +82,10 @@ std::vector<int> apply_order(const int n[3], int P);
 template <typename T>
 int launch_apply(const MeshDev &m, const int bc[3], double lambda, const T *nu, double nu_c,
                  const T *x, T *y, hipStream_t s);
+// d = diag(A), or 1/diag(A) when inverse (the Jacobi preconditioner)
 template <typename T>
 int launch_diag(const MeshDev &m, const int bc[3], double lambda, const T *nu, double nu_c, T *d,
-                hipStream_t s);
+                hipStream_t s, bool inverse = false);
 int apply_groups(int P, int64_t nel);  // number of work-groups of the apply grid
 
 }  // namespace dg

@@ -57,6 +57,11 @@ __device__ inline void resid_finish(CgScalars *sc, const double (&t)[4])
     sc->true_res2 = res2 > 0.0 ? res2 : 0.0;
 }
 
+// reductions finished by a one-work-group kernel after the producer
+enum { FIN_APPLY = 0, FIN_RESID, FIN_SETUP1, FIN_SETUP2, FIN_UPDATE, FIN_MEANX, FIN_IRSCALE };
+int launch_finish_apply(double *partial, int nblk, CgScalars *sc, hipStream_t s);
+int launch_finish_resid(double *partial, int nblk, CgScalars *sc, hipStream_t s);
+
 template <typename T>
 int launch_apply_cg(const MeshDev &m, const int bc[3], double lambda, const T *nu, double nu_c,
                     const T *p, T *q, double *partial, unsigned *counter, CgScalars *sc,

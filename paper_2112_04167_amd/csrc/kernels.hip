@@ -63,21 +63,16 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_apply(ApplyArgs<T> A)
     double red[4];
     apply_group<P, T, NUF, EPI>(A, grp, xs, ys, nus, geo, red);
     if constexpr (EPI == EPI_CG) {
-        double tot[2], red2[2] = {red[0], red[1]};
-        if (publish_and_reduce<2>(red2, A.partial, A.counter, gridDim.x, tot, red_sh)) {
-            if (threadIdx.x == 0) cg_after_apply(A.sc, tot[0], tot[1]);
-        }
+        double red2[2] = {red[0], red[1]};
+        publish_partials<2>(red2, A.partial, gridDim.x, red_sh);
     } else if constexpr (EPI == EPI_RESID) {
-        double tot[4];
-        if (publish_and_reduce<4>(red, A.partial, A.counter, gridDim.x, tot, red_sh)) {
-            if (threadIdx.x == 0) resid_finish(A.sc, tot);
-        }
+        publish_partials<4>(red, A.partial, gridDim.x, red_sh);
     }
 }
 
 // ---------------------------------------------------------- diag kernel --
 
-template <int P, typename T, bool NUF>
+template <int P, typename T, bool NUF, bool INV>
 __global__ void __launch_bounds__(Shape<P>::NTP) k_diag(ApplyArgs<T> A)
 {
     using S = Shape<P>;
@@ -137,7 +132,7 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_diag(ApplyArgs<T> A)
                 s += om * (sig + (T)2 * sgn * nuo * g * Dff);
             }
         }
-        A.y[gi] = s;
+        A.y[gi] = INV ? (T)1 / s : s;
     }
 }
 
@@ -270,7 +265,8 @@ int launch_apply_cg(const MeshDev &m, const int bc[3], double lambda, const T *n
     a.partial = partial;
     a.counter = counter;
     a.sc = sc;
-    return dispatch_apply<T, EPI_CG>(m.P, a, nu != nullptr, s);
+    if (int rc = dispatch_apply<T, EPI_CG>(m.P, a, nu != nullptr, s)) return rc;
+    return launch_finish_apply(partial, a.ngroups, sc, s);
 }
 
 template <typename T>
@@ -283,31 +279,37 @@ int launch_resid(const MeshDev &m, const int bc[3], double lambda, const T *nu, 
     a.partial = partial;
     a.counter = counter;
     a.sc = sc;
-    return dispatch_apply<T, EPI_RESID>(m.P, a, nu != nullptr, s);
+    if (int rc = dispatch_apply<T, EPI_RESID>(m.P, a, nu != nullptr, s)) return rc;
+    return launch_finish_resid(partial, a.ngroups, sc, s);
 }
 
 template <int P, typename T>
-static void launch_diag_P(const ApplyArgs<T> &a, bool nuf, hipStream_t s)
+static void launch_diag_P(const ApplyArgs<T> &a, bool nuf, bool inv, hipStream_t s)
 {
     dim3 grid(a.ngroups), block(Shape<P>::NTP);
-    if (nuf)
-        hipLaunchKernelGGL((k_diag<P, T, true>), grid, block, 0, s, a);
+    if (nuf && inv)
+        hipLaunchKernelGGL((k_diag<P, T, true, true>), grid, block, 0, s, a);
+    else if (nuf)
+        hipLaunchKernelGGL((k_diag<P, T, true, false>), grid, block, 0, s, a);
+    else if (inv)
+        hipLaunchKernelGGL((k_diag<P, T, false, true>), grid, block, 0, s, a);
     else
-        hipLaunchKernelGGL((k_diag<P, T, false>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_diag<P, T, false, false>), grid, block, 0, s, a);
 }
 
 template <typename T>
 int launch_diag(const MeshDev &m, const int bc[3], double lambda, const T *nu, double nu_c, T *d,
-                hipStream_t s)
+                hipStream_t s, bool inverse)
 {
     ApplyArgs<T> a = make_args<T>(m, bc, lambda, nu, nu_c, nullptr, d);
+    const bool nf = nu != nullptr;
     switch (m.P) {
-        case 3: launch_diag_P<3, T>(a, nu != nullptr, s); break;
-        case 4: launch_diag_P<4, T>(a, nu != nullptr, s); break;
-        case 5: launch_diag_P<5, T>(a, nu != nullptr, s); break;
-        case 6: launch_diag_P<6, T>(a, nu != nullptr, s); break;
-        case 7: launch_diag_P<7, T>(a, nu != nullptr, s); break;
-        case 8: launch_diag_P<8, T>(a, nu != nullptr, s); break;
+        case 3: launch_diag_P<3, T>(a, nf, inverse, s); break;
+        case 4: launch_diag_P<4, T>(a, nf, inverse, s); break;
+        case 5: launch_diag_P<5, T>(a, nf, inverse, s); break;
+        case 6: launch_diag_P<6, T>(a, nf, inverse, s); break;
+        case 7: launch_diag_P<7, T>(a, nf, inverse, s); break;
+        case 8: launch_diag_P<8, T>(a, nf, inverse, s); break;
         default: set_error("polynomial degree outside 3..8"); return DG_ERR_ARG;
     }
     DG_HIP_CHECK(hipGetLastError());
@@ -324,7 +326,7 @@ int launch_diag(const MeshDev &m, const int bc[3], double lambda, const T *nu, d
                                  const T *, const T *, T *, double *, unsigned *, CgScalars *,   \
                                  hipStream_t);                                                   \
     template int launch_diag<T>(const MeshDev &, const int[3], double, const T *, double, T *,  \
-                                hipStream_t);
+                                hipStream_t, bool);
 DG_INST(double)
 DG_INST(float)
 

@@ -52,6 +52,8 @@ struct Workspace {
     unsigned *counter = nullptr;
     CgScalars *sc = nullptr;      // [0] outer / FP64, [1] inner FP32
     CgScalars *host_sc = nullptr; // pinned
+    bool external = false;        // memory lent by the caller (never freed here)
+    bool host_external = false;
 };
 
 // Workspace of the batched solver: per system two FP64 and seven
@@ -67,6 +69,8 @@ struct dg_mesh {
     hipStream_t stream = nullptr;
     Workspace ws;
     BatchWorkspace bws;
+    void *geo_block = nullptr;  // device: extents, reciprocals, visiting order
+    bool geo_external = false;
 };
 
 namespace {
@@ -93,20 +97,27 @@ int ensure_workspace(dg_mesh *m, int precision)
     if (w.base && w.bytes >= need && w.ndof == m->dev.ndof &&
         (precision != DG_MIXED || w.precision == DG_MIXED))
         return DG_OK;
-    if (w.base) {
-        DG_HIP_CHECK(hipStreamSynchronize(m->stream));
-        DG_HIP_CHECK(hipFree(w.base));
-        w.base = nullptr;
+    if (w.external) {
+        if (w.bytes < need) {
+            set_error("lent workspace too small for this solve");
+            return DG_ERR_ARG;
+        }
+    } else {
+        if (w.base) {
+            DG_HIP_CHECK(hipStreamSynchronize(m->stream));
+            DG_HIP_CHECK(hipFree(w.base));
+            w.base = nullptr;
+        }
+        hipError_t e = hipMalloc(&w.base, need);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("workspace allocation of " + std::to_string(need) + " bytes failed");
+            w.base = nullptr;
+            return DG_ERR_OOM;
+        }
     }
     if (!w.host_sc) DG_HIP_CHECK(hipHostMalloc((void **)&w.host_sc, 2 * sizeof(CgScalars), 0));
-    hipError_t e = hipMalloc(&w.base, need);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        set_error("workspace allocation of " + std::to_string(need) + " bytes failed");
-        w.base = nullptr;
-        return DG_ERR_OOM;
-    }
-    w.bytes = need;
+    if (!w.external) w.bytes = need;
     w.ndof = m->dev.ndof;
     w.precision = precision;
     char *p = (char *)w.base;
@@ -225,7 +236,7 @@ int solve_fp64(dg_mesh *m, const int bc[3], double lambda, const double *nu, dou
     CgScalars init = init_scalars(md, o.tol, o.maxit, o.fixed_iters, singular);
     *w.host_sc = init;
     DG_HIP_CHECK(hipMemcpyAsync(w.sc, w.host_sc, sizeof(CgScalars), hipMemcpyHostToDevice, s));
-    if ((rc = launch_diag<double>(md, bc, lambda, nu, nu_c, w.d64, s))) return rc;
+    if ((rc = launch_diag<double>(md, bc, lambda, nu, nu_c, w.d64, s, true))) return rc;
     CgVecArgs<double> a = vec_args<double>(w, singular, w.sc);
     a.x = x;
     a.r = w.r64;
@@ -274,7 +285,7 @@ int solve_mixed(dg_mesh *m, const int bc[3], double lambda, const double *nu, do
         if ((rc = convert_f64_to_f32(nu, w.nu32, N, s))) return rc;
         nu32 = w.nu32;
     }
-    if ((rc = launch_diag<float>(md, bc, lambda, nu32, nu_c, w.d32, s))) return rc;
+    if ((rc = launch_diag<float>(md, bc, lambda, nu32, nu_c, w.d32, s, true))) return rc;
 
     // outer set-up: b (projected), r = b, x = 0, ||M^-1 b||
     *hosc = init_scalars(md, o.tol, o.maxit, 0, singular);
@@ -397,6 +408,58 @@ int solve_common(dg_mesh *m, const int bc[3], double lambda, const double *nu, d
     return rc;
 }
 
+// Device block of the mesh geometry: hx|hy|hz, 1/h (FP64), the same in FP32,
+// and the visiting order of the apply's element groups.
+size_t geo_bytes(const int n[3], int P, int64_t nel)
+{
+    const size_t S = (size_t)n[0] + n[1] + n[2];
+    return align256(S * 8) * 2 + align256(S * 4) * 2 + align256((size_t)apply_groups(P, nel) * 4);
+}
+
+int upload_geometry(dg_mesh *m, void *ext)
+{
+    MeshDev &d = m->dev;
+    const size_t S = (size_t)d.n[0] + d.n[1] + d.n[2];
+    const size_t bytes = geo_bytes(d.n, d.P, d.nel);
+    std::vector<char> host(bytes, 0);
+    char *hp = host.data();
+    size_t off = 0;
+    auto put = [&](const void *src, size_t nb) {
+        std::memcpy(hp + off, src, nb);
+        const size_t at = off;
+        off += align256(nb);
+        return at;
+    };
+    std::vector<double> h, ih;
+    std::vector<float> hf, ihf;
+    for (int k = 0; k < 3; ++k)
+        for (int e = 0; e < d.n[k]; ++e) h.push_back(d.v[k][e + 1] - d.v[k][e]);
+    for (double v : h) {
+        ih.push_back(1.0 / v);
+        hf.push_back((float)v);
+        ihf.push_back(1.0f / (float)v);
+    }
+    const std::vector<int> ord = apply_order(d.n, d.P);
+    const size_t o_h64 = put(h.data(), S * 8), o_ih64 = put(ih.data(), S * 8);
+    const size_t o_h32 = put(hf.data(), S * 4), o_ih32 = put(ihf.data(), S * 4);
+    const size_t o_ord = put(ord.data(), ord.size() * 4);
+    if (ext) {
+        m->geo_block = ext;
+        m->geo_external = true;
+    } else {
+        DG_HIP_CHECK(hipMalloc(&m->geo_block, bytes));
+    }
+    char *base = (char *)m->geo_block;
+    d.h64 = (double *)(base + o_h64);
+    d.ih64 = (double *)(base + o_ih64);
+    d.h32 = (float *)(base + o_h32);
+    d.ih32 = (float *)(base + o_ih32);
+    d.order = (int *)(base + o_ord);
+    DG_HIP_CHECK(hipMemcpyAsync(m->geo_block, host.data(), bytes, hipMemcpyHostToDevice, m->stream));
+    DG_HIP_CHECK(hipStreamSynchronize(m->stream));
+    return DG_OK;
+}
+
 size_t batched_footprint(const MeshDev &m, int precision, int nsys)
 {
     const size_t N = (size_t)m.ndof;
@@ -474,10 +537,10 @@ int solve_batched(dg_mesh *m, int nsys, const double *lambdas, const double *con
                 if ((rc = convert_f64_to_f32(D.nu64, (float *)nui, N, s))) return rc;
                 D.nui = nui;
             }
-            rc = launch_diag<float>(md, D.bc, D.lambda, (const float *)D.nui, 1.0, (float *)D.di, s);
+            rc = launch_diag<float>(md, D.bc, D.lambda, (const float *)D.nui, 1.0, (float *)D.di, s, true);
         } else {
             D.nui = D.nu64;
-            rc = launch_diag<double>(md, D.bc, D.lambda, D.nu64, 1.0, (double *)D.di, s);
+            rc = launch_diag<double>(md, D.bc, D.lambda, D.nu64, 1.0, (double *)D.di, s, true);
         }
         if (rc) return rc;
     }
@@ -509,26 +572,11 @@ int solve_batched(dg_mesh *m, int nsys, const double *lambdas, const double *con
 
 }  // namespace
 
-// ---------------------------------------------------------------- C-ABI --
+namespace dg {
 
-extern "C" {
-
-const char *dg_last_error(void) { return g_last_error.c_str(); }
-
-void dg_default_opts(dg_solve_opts *o)
-{
-    if (!o) return;
-    o->tol = 1e-10;
-    o->maxit = 100000;
-    o->precision = DG_FP64;
-    o->inner_tol = 1e-4;
-    o->inner_maxit = 20000;
-    o->rhs_is_weak = 0;
-    o->fixed_iters = 0;
-}
-
-int dg_mesh_create(int nx, int ny, int nz, int P, const double *xv, const double *yv,
-                   const double *zv, const int bc[3], void *hip_stream, dg_mesh **out)
+int mesh_create_impl(int nx, int ny, int nz, int P, const double *xv, const double *yv,
+                     const double *zv, const int bc[3], void *hip_stream, void *geo_mem,
+                     dg_mesh **out)
 {
     g_last_error.clear();
     if (!out || !xv || !yv || !zv || !bc) {
@@ -570,53 +618,124 @@ int dg_mesh_create(int nx, int ny, int nz, int P, const double *xv, const double
         d.v[k].assign(vv[k], vv[k] + nn[k] + 1);
     }
     m->stream = (hipStream_t)hip_stream;
-    std::vector<double> h;
-    for (int k = 0; k < 3; ++k)
-        for (int e = 0; e < nn[k]; ++e) h.push_back(d.v[k][e + 1] - d.v[k][e]);
-    std::vector<float> hf(h.begin(), h.end());
-    std::vector<double> ih(h.size());
-    std::vector<float> ihf(h.size());
-    for (size_t k = 0; k < h.size(); ++k) {
-        ih[k] = 1.0 / h[k];
-        ihf[k] = 1.0f / hf[k];
-    }
-    DG_HIP_CHECK(hipMalloc((void **)&d.h64, h.size() * sizeof(double)));
-    DG_HIP_CHECK(hipMalloc((void **)&d.h32, hf.size() * sizeof(float)));
-    DG_HIP_CHECK(hipMalloc((void **)&d.ih64, h.size() * sizeof(double)));
-    DG_HIP_CHECK(hipMalloc((void **)&d.ih32, hf.size() * sizeof(float)));
-    DG_HIP_CHECK(hipMemcpy(d.h64, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
-    DG_HIP_CHECK(hipMemcpy(d.h32, hf.data(), hf.size() * sizeof(float), hipMemcpyHostToDevice));
-    DG_HIP_CHECK(hipMemcpy(d.ih64, ih.data(), ih.size() * sizeof(double), hipMemcpyHostToDevice));
-    DG_HIP_CHECK(hipMemcpy(d.ih32, ihf.data(), ihf.size() * sizeof(float), hipMemcpyHostToDevice));
-    {
-        const std::vector<int> ord = apply_order(d.n, P);
-        DG_HIP_CHECK(hipMalloc((void **)&d.order, ord.size() * sizeof(int)));
-        DG_HIP_CHECK(
-            hipMemcpy(d.order, ord.data(), ord.size() * sizeof(int), hipMemcpyHostToDevice));
-    }
+    if (int rc = upload_geometry(m.get(), geo_mem)) return rc;
     (void)gll_cached(P);
     *out = m.release();
     return DG_OK;
+}
+
+size_t mesh_geo_bytes(const int n[3], int P)
+{
+    return geo_bytes(n, P, (int64_t)n[0] * n[1] * n[2]);
+}
+
+size_t solve_footprint_for(const int n[3], int P, int precision)
+{
+    MeshDev d;
+    d.P = P;
+    for (int k = 0; k < 3; ++k) d.n[k] = n[k];
+    d.nel = (int64_t)n[0] * n[1] * n[2];
+    d.ndof = d.nel * (P + 1) * (P + 1) * (P + 1);
+    return footprint(d, precision);
+}
+
+void mesh_lend_workspace(dg_mesh *m, void *dev, size_t bytes, void *host_sc)
+{
+    m->ws.base = dev;
+    m->ws.bytes = bytes;
+    m->ws.external = true;
+    m->ws.ndof = -1;
+    m->ws.host_sc = (CgScalars *)host_sc;
+    m->ws.host_external = true;
+}
+
+size_t solve_host_scalar_bytes() { return 2 * sizeof(CgScalars); }
+
+int64_t mesh_ndof(const dg_mesh *m) { return m->dev.ndof; }
+
+}  // namespace dg
+
+// X[node] = 1D coordinate table of axis d at (element index, node index)
+__global__ void k_expand_coords(const double *tab, int nx, int ny, int nz, int n, double *X,
+                                double *Y, double *Z)
+{
+    const size_t n3 = (size_t)n * n * n;
+    const size_t N = (size_t)nx * ny * nz * n3;
+    const double *tx = tab, *ty = tab + (size_t)nx * n, *tz = ty + (size_t)ny * n;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const size_t el = i / n3, loc = i - el * n3;
+        const int a = (int)(loc % n), b = (int)((loc / n) % n), c = (int)(loc / ((size_t)n * n));
+        const int ex = (int)(el % nx), ey = (int)((el / nx) % ny), ez = (int)(el / ((size_t)nx * ny));
+        if (X) X[i] = tx[(size_t)ex * n + a];
+        if (Y) Y[i] = ty[(size_t)ey * n + b];
+        if (Z) Z[i] = tz[(size_t)ez * n + c];
+    }
+}
+
+// ---------------------------------------------------------------- C-ABI --
+
+extern "C" {
+
+const char *dg_last_error(void) { return g_last_error.c_str(); }
+
+void dg_default_opts(dg_solve_opts *o)
+{
+    if (!o) return;
+    o->tol = 1e-10;
+    o->maxit = 100000;
+    o->precision = DG_FP64;
+    o->inner_tol = 1e-4;
+    o->inner_maxit = 20000;
+    o->rhs_is_weak = 0;
+    o->fixed_iters = 0;
+}
+
+int dg_mesh_create(int nx, int ny, int nz, int P, const double *xv, const double *yv,
+                   const double *zv, const int bc[3], void *hip_stream, dg_mesh **out)
+{
+    return dg::mesh_create_impl(nx, ny, nz, P, xv, yv, zv, bc, hip_stream, nullptr, out);
 }
 
 int dg_mesh_destroy(dg_mesh *m)
 {
     if (!m) return DG_OK;
     (void)hipStreamSynchronize(m->stream);
-    if (m->ws.base) (void)hipFree(m->ws.base);
-    if (m->ws.host_sc) (void)hipHostFree(m->ws.host_sc);
+    if (m->ws.base && !m->ws.external) (void)hipFree(m->ws.base);
+    if (m->ws.host_sc && !m->ws.host_external) (void)hipHostFree(m->ws.host_sc);
     if (m->bws.base) (void)hipFree(m->bws.base);
     if (m->bws.host_state) (void)hipHostFree(m->bws.host_state);
-    if (m->dev.h64) (void)hipFree(m->dev.h64);
-    if (m->dev.h32) (void)hipFree(m->dev.h32);
-    if (m->dev.ih64) (void)hipFree(m->dev.ih64);
-    if (m->dev.ih32) (void)hipFree(m->dev.ih32);
-    if (m->dev.order) (void)hipFree(m->dev.order);
+    if (m->geo_block && !m->geo_external) (void)hipFree(m->geo_block);
     delete m;
     return DG_OK;
 }
 
 int64_t dg_mesh_ndof(const dg_mesh *m) { return m ? m->dev.ndof : -1; }
+
+int dg_mesh_coordinates(dg_mesh *m, double *X, double *Y, double *Z, void *stream)
+{
+    if (int rc = check_mesh(m)) return rc;
+    const MeshDev &d = m->dev;
+    const int n = d.P + 1;
+    const GllTables &t = gll_cached(d.P);
+    std::vector<double> tab;
+    for (int k = 0; k < 3; ++k)
+        for (int e = 0; e < d.n[k]; ++e) {
+            const double x0 = d.v[k][e], h = d.v[k][e + 1] - d.v[k][e];
+            for (int a = 0; a < n; ++a) tab.push_back(x0 + h * 0.5 * (1.0 + t.xi[a]));
+        }
+    hipStream_t s = stream ? (hipStream_t)stream : m->stream;
+    double *dt = nullptr;
+    DG_HIP_CHECK(hipMalloc((void **)&dt, tab.size() * sizeof(double)));
+    DG_HIP_CHECK(hipMemcpyAsync(dt, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    const size_t blocks = std::min<size_t>(((size_t)d.ndof + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_expand_coords, dim3((unsigned)blocks), dim3(256), 0, s, dt, d.n[0], d.n[1],
+                       d.n[2], n, X, Y, Z);
+    DG_HIP_CHECK(hipGetLastError());
+    DG_HIP_CHECK(hipStreamSynchronize(s));
+    DG_HIP_CHECK(hipFree(dt));
+    return DG_OK;
+}
 
 size_t dg_solve_footprint(const dg_mesh *m, int precision, int nrhs)
 {

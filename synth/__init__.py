@@ -54,6 +54,20 @@ def uniform_field(ndof, seed, lo=-1.0, hi=1.0, dtype=np.float64):
     return rng.uniform(lo, hi, size=ndof).astype(dtype)
 
 
+def splitmix64_uniform(n, seed):
+    """f_i = 2 (z_i >> 11) / 2^53 - 1 with z_i the (i+1)-th output of
+    SplitMix64 (Steele, Lea & Flood 2014) started from `seed` -- the
+    counter-based generator the request server uses on the device."""
+    gamma = np.uint64(0x9E3779B97F4A7C15)
+    i = np.arange(1, n + 1, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + i * gamma
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    return 2.0 * ((z >> np.uint64(11)).astype(np.float64) / 9007199254740992.0) - 1.0
+
+
 def ndof(n, P):
     return n[0] * n[1] * n[2] * (P + 1) ** 3
 

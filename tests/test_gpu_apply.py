@@ -130,3 +130,16 @@ def test_apply_batched_channel_nodal_nu_full_size():
     y = gpu_apply(spec, lam, nu, x)
     yr = naive.Operator(spec, lam, nu).apply(x)
     assert np.abs(y - yr).max() <= 1e-12 * np.abs(yr).max()
+
+
+def test_mesh_coordinates():
+    import paper_2112_04167_amd as dg
+    from tests.helpers import node_coords
+    torch, dev = torch_dev()
+    spec = make_spec((3, 2, 4), 5, (0, 1, 2), True)
+    mesh = dg.mesh_from_spec(spec)
+    X, Y, Z = [t.cpu().numpy() for t in dg.mesh_coordinates(mesh)]
+    Xr, Yr, Zr = node_coords(spec)
+    for a, b in ((X, Xr), (Y, Yr), (Z, Zr)):
+        assert np.abs(a - b).max() <= 1e-15
+    mesh.destroy()
