@@ -38,7 +38,7 @@ struct BatchSysResult {
     double bnorm2, res2;
 };
 
-// partial-sum slots the kernel needs per resident work-group
+// partial-sum slots per resident work-group and parity buffer (two buffers)
 constexpr int kBatchPartialPerBlock = 5 * kMaxBatch;
 constexpr int kBatchMaxBlocks = 4096;  // resident work-groups at most
 

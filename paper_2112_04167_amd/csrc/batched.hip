@@ -84,7 +84,6 @@ struct BLds {
     ElGeo<double> geo[EB];
     double sh[16 * NCMAX];
     double acc[NCMAX][kMaxBatch];
-    int last;
 };
 
 // per-thread node loop of one element group: f(global index, GLL mass,
@@ -118,25 +117,26 @@ __device__ __forceinline__ void block_accumulate(double (&v)[NC], int s, double 
         for (int c = 0; c < NC; ++c) acc[c][s] += v[c];
 }
 
-// end of a reduced phase: publish this block's accumulators; the last block
-// to arrive sums every block's partials in a fixed order and calls
-// fin(system, totals) from thread 0.
+// End of a reduced phase: publish this block's accumulators with plain
+// stores (into the buffer of the current phase parity), wait at the grid
+// barrier, then let every block sum all blocks' partials in the same fixed
+// order and apply fin(system, totals) to its own copy of the scalars
+// (thread 0).  Every block thus holds bitwise identical scalars and takes the
+// same decisions, without device-wide atomics or a second barrier.  The two
+// parity buffers alternate, so a block that races ahead into the next
+// reduced phase never overwrites partials another block is still reading.
 template <int NC, typename F>
-__device__ void phase_reduce(double (&acc)[NCMAX][kMaxBatch], double *sh, int &last,
-                             double *partial, unsigned *counter, int nsys, F &&fin)
+__device__ void phase_reduce(cgrp::grid_group &grid, double (&acc)[NCMAX][kMaxBatch], double *sh,
+                             double *partial_base, int &parity, int nsys, F &&fin)
 {
     const int nblk = gridDim.x;
+    double *partial = partial_base + (size_t)parity * kBatchPartialPerBlock * nblk;
+    parity ^= 1;
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0)
         for (int s = 0; s < nsys; ++s)
             for (int c = 0; c < NC; ++c) partial[(size_t)(c * kMaxBatch + s) * nblk + blockIdx.x] = acc[c][s];
-        __threadfence();
-        const unsigned prev = atomicAdd(counter, 1u);
-        last = (prev == (unsigned)(nblk - 1));
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();  // acquire: every block's partials are visible now
+    grid.sync();
     for (int s = 0; s < nsys; ++s) {
         double v[NC];
 #pragma unroll
@@ -145,7 +145,6 @@ __device__ void phase_reduce(double (&acc)[NCMAX][kMaxBatch], double *sh, int &l
         if (threadIdx.x == 0) fin(s, v);
         __syncthreads();
     }
-    if (threadIdx.x == 0) *counter = 0u;
 }
 
 __device__ __forceinline__ void zero_acc(double (&acc)[NCMAX][kMaxBatch])
@@ -160,7 +159,8 @@ __device__ __forceinline__ void for_items(const int *act, int nact, int G, const
 {
     const int total = nact * G;
     for (int w = blockIdx.x; w < total; w += gridDim.x) {
-        const int s = act[w / G];
+        // uniform in the work-group: keeps per-system pointers in scalar registers
+        const int s = __builtin_amdgcn_readfirstlane(act[w / G]);
         const int slot = xcd_remap(w % G, G);
         f(s, order ? order[slot] : slot);
     }
@@ -193,15 +193,18 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_batched(BArgs<TI> B)
     __shared__ BLds<P> L;
     __shared__ int act[kMaxBatch];
     __shared__ int nact_s;
+    __shared__ BState st[kMaxBatch];  // this block's copy of the per-system scalars
     cgrp::grid_group grid = cgrp::this_grid();
     const int G = B.ngroups, nel = B.nel, ns = B.nsys;
-    BState *st = B.st;
     const double N = (double)nel * S::N3;
+    int parity = 0;
+    for (int k = threadIdx.x; k < (int)(kMaxBatch * sizeof(BState) / sizeof(int)); k += blockDim.x)
+        reinterpret_cast<int *>(st)[k] = 0;
+    __syncthreads();
 
-    // coherent (agent-scope) read of a flag written by another work-group
-    auto ld = [](const int *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); };
-    // active list: systems with flag(s) true (read after a grid barrier, so
-    // every block builds the same list and takes the same number of barriers)
+    // active list: systems with flag(s) true (the flags are this block's
+    // copy, identical in every block, so every block takes the same branches
+    // and the same number of grid barriers)
     auto build_active = [&](auto flag) {
         if (threadIdx.x == 0) {
             int k = 0;
@@ -217,7 +220,7 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_batched(BArgs<TI> B)
     {
         zero_acc(L.acc);
         for (int w = blockIdx.x; w < ns * G; w += gridDim.x) {
-            const int s = w / G, g = w % G;
+            const int s = __builtin_amdgcn_readfirstlane(w / G), g = w % G;
             const BSys<TI> &Y = B.sys[s];
             double v[2] = {0.0, 0.0};
             group_nodes<P>(g, nel, B.g64, [&](size_t gi, double m, double im) {
@@ -229,20 +232,19 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_batched(BArgs<TI> B)
             });
             block_accumulate<2>(v, s, L.sh, L.acc);
         }
-        phase_reduce<2>(L.acc, L.sh, L.last, B.partial, B.counter, ns, [&](int s, double(&t)[2]) {
+        phase_reduce<2>(grid, L.acc, L.sh, B.partial, parity, ns, [&](int s, double(&t)[2]) {
             st[s].mean_b = B.sys[s].singular ? t[0] / N : 0.0;
             if (!isfinite(t[1])) {
                 st[s].status = DG_ERR_NONFINITE;
                 st[s].done = 1;
             }
         });
-        grid.sync();
     }
     // ---- set-up 2: project b (singular), ||M^-1 b||^2, sum 1/M^2
     {
         zero_acc(L.acc);
         for (int w = blockIdx.x; w < ns * G; w += gridDim.x) {
-            const int s = w / G, g = w % G;
+            const int s = __builtin_amdgcn_readfirstlane(w / G), g = w % G;
             const BSys<TI> &Y = B.sys[s];
             const double mb = st[s].mean_b;
             double v[2] = {0.0, 0.0};
@@ -258,18 +260,17 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_batched(BArgs<TI> B)
             });
             block_accumulate<2>(v, s, L.sh, L.acc);
         }
-        phase_reduce<2>(L.acc, L.sh, L.last, B.partial, B.counter, ns, [&](int s, double(&t)[2]) {
+        phase_reduce<2>(grid, L.acc, L.sh, B.partial, parity, ns, [&](int s, double(&t)[2]) {
             st[s].bnorm2 = t[0];
             st[s].tol2 = B.tol * B.tol * t[0];
             st[s].sum_invM2 = t[1];
             if (!(t[0] > 0.0) && st[s].status == DG_OK) st[s].done = 1;  // b = 0: x = 0
         });
-        grid.sync();
     }
 
     for (int outer = 0;; ++outer) {
         // ---- FP64 residual r = b - A x (projected) and the outer test
-        int na = build_active([&](int s) { return !ld(&st[s].done); });
+        int na = build_active([&](int s) { return !st[s].done; });
         if (na == 0) break;
         {
             zero_acc(L.acc);
@@ -284,7 +285,7 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_batched(BArgs<TI> B)
                     apply_group<P, double, false, EPI_RESID>(a, g, L.xs, L.ys, L.nus, L.geo, red);
                 block_accumulate<4>(red, s, L.sh, L.acc);
             });
-            phase_reduce<4>(L.acc, L.sh, L.last, B.partial, B.counter, ns, [&](int s, double(&t)[4]) {
+            phase_reduce<4>(grid, L.acc, L.sh, B.partial, parity, ns, [&](int s, double(&t)[4]) {
                 if (st[s].done) return;
                 double res2 = t[0];
                 double m = 0.0;
@@ -308,9 +309,8 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_batched(BArgs<TI> B)
                     st[s].outer = outer + 1;
                 }
             });
-            grid.sync();
         }
-        na = build_active([&](int s) { return ld(&st[s].ran) != 0; });
+        na = build_active([&](int s) { return st[s].ran != 0; });
         if (na == 0) continue;  // re-evaluated at the loop top (all done)
 
         // ---- scale = RMS of the projected residual
@@ -326,12 +326,11 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_batched(BArgs<TI> B)
                 });
                 block_accumulate<1>(v, s, L.sh, L.acc);
             });
-            phase_reduce<1>(L.acc, L.sh, L.last, B.partial, B.counter, ns, [&](int s, double(&t)[1]) {
+            phase_reduce<1>(grid, L.acc, L.sh, B.partial, parity, ns, [&](int s, double(&t)[1]) {
                 if (!st[s].ran) return;
                 const double rms = sqrt(t[0] / N);
                 st[s].scale = rms > 0.0 ? rms : 1.0;
             });
-            grid.sync();
         }
         // ---- inner right-hand side b_in = (r - mean r)/scale, its sum
         {
@@ -347,11 +346,10 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_batched(BArgs<TI> B)
                 });
                 block_accumulate<1>(v, s, L.sh, L.acc);
             });
-            phase_reduce<1>(L.acc, L.sh, L.last, B.partial, B.counter, ns, [&](int s, double(&t)[1]) {
+            phase_reduce<1>(grid, L.acc, L.sh, B.partial, parity, ns, [&](int s, double(&t)[1]) {
                 if (!st[s].ran) return;
                 st[s].imean_b = B.sys[s].singular ? t[0] / N : 0.0;
             });
-            grid.sync();
         }
         // ---- inner set-up: r = b (projected), x = 0, p = z = r/d, norms
         {
@@ -378,7 +376,7 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_batched(BArgs<TI> B)
                 });
                 block_accumulate<4>(v, s, L.sh, L.acc);
             });
-            phase_reduce<4>(L.acc, L.sh, L.last, B.partial, B.counter, ns, [&](int s, double(&t)[4]) {
+            phase_reduce<4>(grid, L.acc, L.sh, B.partial, parity, ns, [&](int s, double(&t)[4]) {
                 if (!st[s].ran) return;
                 st[s].rho = t[0];
                 st[s].ibnorm2 = t[1];
@@ -390,11 +388,10 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_batched(BArgs<TI> B)
                 st[s].imean_r = 0.0;
                 st[s].idone = (t[1] > 0.0 && isfinite(t[0])) ? 0 : 1;
             });
-            grid.sync();
         }
         // ---- inner CG iterations
         for (int k = 0; k < B.inner_maxit; ++k) {
-            const int ni = build_active([&](int s) { return ld(&st[s].ran) && !ld(&st[s].idone); });
+            const int ni = build_active([&](int s) { return st[s].ran && !st[s].idone; });
             if (ni == 0) break;
             // q = A p, p.q, sum q
             zero_acc(L.acc);
@@ -413,7 +410,7 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_batched(BArgs<TI> B)
                 double v2[2] = {red[0], red[1]};
                 block_accumulate<2>(v2, s, L.sh, L.acc);
             });
-            phase_reduce<2>(L.acc, L.sh, L.last, B.partial, B.counter, ns, [&](int s, double(&t)[2]) {
+            phase_reduce<2>(grid, L.acc, L.sh, B.partial, parity, ns, [&](int s, double(&t)[2]) {
                 if (!st[s].ran || st[s].idone) return;
                 if (!isfinite(t[0]) || t[0] <= 0.0) {
                     st[s].idone = 1;  // breakdown: stop this inner solve, keep its iterate
@@ -421,8 +418,7 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_batched(BArgs<TI> B)
                     st[s].alpha = st[s].rho / t[0];
                 }
             });
-            grid.sync();
-            const int nu_ = build_active([&](int s) { return ld(&st[s].ran) && !ld(&st[s].idone); });
+            const int nu_ = build_active([&](int s) { return st[s].ran && !st[s].idone; });
             // x += alpha p, r -= alpha q, reductions
             zero_acc(L.acc);
             for_items(act, nu_, G, B.order, [&](int s, int g) {
@@ -443,7 +439,7 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_batched(BArgs<TI> B)
                 });
                 block_accumulate<5>(v, s, L.sh, L.acc);
             });
-            phase_reduce<5>(L.acc, L.sh, L.last, B.partial, B.counter, ns, [&](int s, double(&t)[5]) {
+            phase_reduce<5>(grid, L.acc, L.sh, B.partial, parity, ns, [&](int s, double(&t)[5]) {
                 if (!st[s].ran || st[s].idone) return;
                 double rz = t[1], res2 = t[3], mr = 0.0;
                 if (B.sys[s].singular) {
@@ -460,8 +456,7 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_batched(BArgs<TI> B)
                 if (!isfinite(rz) || res2 <= st[s].itol2 || st[s].iter >= B.inner_maxit)
                     st[s].idone = 1;
             });
-            grid.sync();
-            const int np = build_active([&](int s) { return ld(&st[s].ran) && !ld(&st[s].idone); });
+            const int np = build_active([&](int s) { return st[s].ran && !st[s].idone; });
             // (singular: r -= mean r)  p = r/d + beta p
             for_items(act, np, G, B.order, [&](int s, int g) {
                 const BSys<TI> &Y = B.sys[s];
@@ -480,7 +475,7 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_batched(BArgs<TI> B)
         }
         // ---- x64 += scale * x_in
         {
-            na = build_active([&](int s) { return ld(&st[s].ran) != 0; });
+            na = build_active([&](int s) { return st[s].ran != 0; });
             for_items(act, na, G, B.order, [&](int s, int g) {
                 const BSys<TI> &Y = B.sys[s];
                 const double sc = st[s].scale;
@@ -495,7 +490,7 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_batched(BArgs<TI> B)
     {
         zero_acc(L.acc);
         for (int w = blockIdx.x; w < ns * G; w += gridDim.x) {
-            const int s = w / G, g = w % G;
+            const int s = __builtin_amdgcn_readfirstlane(w / G), g = w % G;
             if (!B.sys[s].singular) continue;
             const BSys<TI> &Y = B.sys[s];
             double v[2] = {0.0, 0.0};
@@ -505,18 +500,20 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_batched(BArgs<TI> B)
             });
             block_accumulate<2>(v, s, L.sh, L.acc);
         }
-        phase_reduce<2>(L.acc, L.sh, L.last, B.partial, B.counter, ns, [&](int s, double(&t)[2]) {
+        phase_reduce<2>(grid, L.acc, L.sh, B.partial, parity, ns, [&](int s, double(&t)[2]) {
             st[s].shift = (B.sys[s].singular && t[1] > 0.0) ? t[0] / t[1] : 0.0;
         });
-        grid.sync();
         for (int w = blockIdx.x; w < ns * G; w += gridDim.x) {
-            const int s = w / G, g = w % G;
+            const int s = __builtin_amdgcn_readfirstlane(w / G), g = w % G;
             if (!B.sys[s].singular) continue;
             const BSys<TI> &Y = B.sys[s];
             const double sh = st[s].shift;
             group_nodes<P>(g, nel, B.g64, [&](size_t gi, double, double) { Y.x64[gi] -= sh; });
         }
     }
+    if (blockIdx.x == 0)
+        for (int k = threadIdx.x; k < (int)(kMaxBatch * sizeof(BState) / sizeof(int)); k += blockDim.x)
+            reinterpret_cast<int *>(B.st)[k] = reinterpret_cast<const int *>(st)[k];
 }
 
 template <int P, typename TI>

@@ -466,7 +466,7 @@ size_t batched_footprint(const MeshDev &m, int precision, int nsys)
     const size_t ti = precision == DG_FP64 ? sizeof(double) : sizeof(float);
     size_t b = 0;
     b += (size_t)nsys * (2 * align256(N * sizeof(double)) + 7 * align256(N * ti));
-    b += align256((size_t)kBatchPartialPerBlock * kBatchMaxBlocks * sizeof(double));
+    b += align256((size_t)2 * kBatchPartialPerBlock * kBatchMaxBlocks * sizeof(double));
     b += align256(256) + align256(batched_state_bytes());
     return b;
 }
@@ -544,7 +544,7 @@ int solve_batched(dg_mesh *m, int nsys, const double *lambdas, const double *con
         }
         if (rc) return rc;
     }
-    rq.partial = (double *)take((size_t)kBatchPartialPerBlock * kBatchMaxBlocks * sizeof(double));
+    rq.partial = (double *)take((size_t)2 * kBatchPartialPerBlock * kBatchMaxBlocks * sizeof(double));
     rq.counter = (unsigned *)take(256);
     rq.state = take(batched_state_bytes());
     DG_HIP_CHECK(hipMemsetAsync(rq.counter, 0, 256, s));
