@@ -7,11 +7,14 @@
 namespace dg {
 
 constexpr int kMaxBatch = 8;
+constexpr int kBatchMaxBlocks = 4096;           // resident work-groups at most
+constexpr int kBatchNC = 6;                     // reduction components per system and phase
+constexpr int kBatchSlots = kBatchNC * kMaxBatch;
 
 struct BatchSysDesc {
-    double *x64, *b64, *r64;
-    const double *rhs, *nu64;
-    void *xi, *ri, *pi, *qi, *di, *bi;  // inner-precision vectors
+    double *x64, *b64, *r64;            // solution (caller), load, FP64 residual
+    const double *rhs, *nu64;           // right-hand side, FP64 nu field or null
+    void *xi, *ri, *pi, *qi, *di;       // inner-precision CG vectors (di = 1/diag)
     const void *nui;                    // inner-precision nu field or null
     double lambda;
     int bc[3];
@@ -21,29 +24,31 @@ struct BatchSysDesc {
 struct BatchRequest {
     int nsys;
     BatchSysDesc sys[kMaxBatch];
-    void *state;  // device, batched_state_bytes()
-    double *partial;
-    unsigned *counter;
-    double tol, inner_tol;
-    int maxit_outer, inner_maxit, weak;
+    void *results;    // device, batched_result_bytes()
+    void *sync;       // device, batched_sync_bytes(); its counters are cleared per launch
+    double *partial;  // device, batched_partial_doubles()
+    double tol;       // FP64 stopping tolerance (relative, collocation RMS residual)
+    double delta;     // replacement threshold on the recurrence residual (0: only at convergence)
+    double mass_mean; // domain volume / ndof: typical GLL mass, sets the inner scaling
+    int maxit;        // cap on inner iterations (per system)
+    int max_replace;  // cap on FP64 residual replacements (per system)
+    int weak;
     bool inner_fp32;
 };
 
-struct BatchResult {
-    int blocks_per_cu;
-};
-
 struct BatchSysResult {
-    int status, outer, inner_total;
-    double bnorm2, res2;
+    int status, iters, replaced;
+    double bnorm2, res64;
 };
 
-// partial-sum slots per resident work-group and parity buffer (two buffers)
-constexpr int kBatchPartialPerBlock = 5 * kMaxBatch;
-constexpr int kBatchMaxBlocks = 4096;  // resident work-groups at most
-
-int batched_launch(const MeshDev &m, const BatchRequest &req, hipStream_t stream, BatchResult *res);
-size_t batched_state_bytes();
-int batched_read_state(const void *host_state, int s, BatchSysResult *out);
+size_t batched_sync_bytes();
+size_t batched_result_bytes();
+size_t batched_partial_doubles();
+// launches the solve (autotuning the launch shape on first use of a shape key)
+int batched_launch(const MeshDev &m, const BatchRequest &req, hipStream_t stream, int *blocks_per_cu);
+// after the stream has completed: per-system results and the barrier's error flag
+int batched_read_results(const void *host_results, int s, BatchSysResult *out);
+int batched_check_sync(const void *host_sync_err);
+size_t batched_sync_err_offset();
 
 }  // namespace dg

@@ -1,32 +1,52 @@
 // Batched implicit-stage solve in one persistent, cooperative launch.
 //
 // One IMEX Runge-Kutta stage (arXiv 2112.04167, Alg. 3) solves a pressure
-// Poisson problem and three velocity Helmholtz problems with the same mesh.
-// Here they are solved together: FP64 iterative refinement whose correction
-// equations are solved by Jacobi-preconditioned CG in the inner precision TI
-// (FP32 for the mixed mode), with per-system scalars, per-system stopping
-// tests (Sec. 4: relative RMS residual at the collocation points) and
-// per-system retirement.  Every phase of every iteration of every system
-// runs inside a single cooperative kernel; phases are separated by grid-wide
-// barriers, and the scalars of a phase are finished by the last work-group
-// to arrive (fixed-order FP64 sums), so the launch needs no host round trip.
+// Poisson problem and three velocity Helmholtz problems on the same mesh.
+// Here they are solved together, each with its own scalars, stopping test
+// (Sec. 4: relative RMS residual at the collocation points) and retirement,
+// in one kernel that never returns to the host.
+//
+// Method per system (inner precision TI: FP32 in the mixed mode, FP64
+// otherwise): Jacobi-preconditioned CG on A_TI, with residual replacement
+// (van der Vorst & Ye 2000; the "reliable updates" of mixed-precision CG).
+// The inner vectors hold a correction x_TI and the residual scaled by a
+// power of two s.  When the recurrence residual has dropped by the factor
+// delta since the last replacement, or claims convergence, the correction
+// is flushed into the FP64 solution, the residual is recomputed in FP64
+// (r = b - A_64 x_64, the stopping test is taken on it), and the recurrence
+// continues from that residual with the same search direction rescaled, so
+// the Krylov space is kept instead of restarting as plain iterative
+// refinement would.
+//
+// Grid barrier.  A cooperative-groups grid barrier on this chip costs tens
+// of microseconds, growing with the work-group count: every work-group
+// writes back its XCD's L2 and arrives on one device-scope counter.  Here
+// the work-groups of an XCD (identified from the hardware XCC_ID register at
+// start-up) first meet on a counter in their shared L2; the last arrival
+// writes the XCD's L2 back once and arrives on the global counter; the last
+// XCD releases a global flag, and every work-group acquires (invalidates
+// its L1 and the XCD's non-coherent L2 lines) once it sees the flag.
+// Reductions ride on the barrier: each work-group publishes its
+// partial sums before arriving and, once released, adds all work-groups'
+// partials in a fixed order, so every work-group holds bitwise identical
+// scalars and takes the same branches.  Every wait has a spin
+// limit that raises an error flag instead of hanging.
 //
 // Work decomposition: in each phase the work items are (system, element
-// group) pairs of the systems still active, dealt round-robin to the
-// resident work-groups; the group order is the XCD-aware order of the
-// stand-alone apply.  The launch shape (resident work-groups per CU) is
-// chosen by a small autotuner that times each candidate on the actual batch.
+// group) pairs of the systems taking part, dealt round-robin to the resident
+// work-groups in the XCD-aware group order of the stand-alone apply.  The
+// number of resident work-groups per CU is chosen by a small autotuner that
+// times each candidate on the actual batch.
 #include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <chrono>
 #include <cmath>
+#include <cstddef>
+#include <cstring>
 #include <map>
 #include <mutex>
-#include <string>
 #include <tuple>
-#include <type_traits>
 
 #include "apply_core.h"
 #include "batched.h"
@@ -39,55 +59,212 @@ namespace dg {
 
 namespace {
 
-constexpr int NCMAX = 5;  // reduction components per system and phase
+constexpr int kXcdIds = 16;                // XCC_ID values tracked
+constexpr unsigned kSpinLimit = 1u << 22;  // polls before a wait gives up
+
+// ------------------------------------------------------------ grid barrier
+
+struct SyncBlock {
+    unsigned reg[kXcdIds * 64];    // work-groups per XCD (registration)
+    unsigned cnt[kXcdIds * 64];    // XCD-local arrivals
+    unsigned gcnt[64];             // XCDs arrived
+    unsigned gflag[64];            // generation released by the last XCD
+    unsigned err[64];              // a wait hit its spin limit
+};
+
+struct SyncArea {
+    SyncBlock sb;
+};
+
+struct BarCtx {
+    int xcc, nx;     // this work-group's XCD and the number of work-groups on it
+    unsigned nxa;    // XCDs holding work-groups
+    unsigned gen;    // barrier generation
+    int parity;      // partial-sum buffer in use
+};
+
+__device__ __forceinline__ unsigned hw_xcc_id()
+{
+    unsigned v;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
+    return v & (kXcdIds - 1);
+}
+
+// acquire at device scope: drop this CU's L1 and the XCD's non-coherent L2
+// lines (a work-group-scope invalidate leaves the L1 in place)
+__device__ __forceinline__ void acquire_agent() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+
+__device__ __forceinline__ unsigned ld_agent(const unsigned *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ bool spin_ne(const unsigned *flag, unsigned gen, unsigned *err)
+{
+    for (unsigned k = 0;; ++k) {
+        if (ld_agent(flag) != gen) return true;
+        if ((k & 255u) == 255u && ld_agent(err)) return false;
+        if (k > kSpinLimit) {
+            __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+// Once per launch: count the work-groups on each XCD.
+__device__ void grid_register(SyncArea *sa, BarCtx &bc, cgrp::grid_group &grid)
+{
+    if (threadIdx.x == 0) {
+        const unsigned x = hw_xcc_id();
+        bc.xcc = (int)x;
+        __hip_atomic_fetch_add(&sa->sb.reg[x * 64], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    grid.sync();
+    if (threadIdx.x == 0) {
+        bc.nx = (int)ld_agent(&sa->sb.reg[bc.xcc * 64]);
+        unsigned n = 0;
+        for (int y = 0; y < kXcdIds; ++y) n += ld_agent(&sa->sb.reg[y * 64]) ? 1u : 0u;
+        bc.nxa = n;
+        bc.gen = 0;
+        bc.parity = 0;
+    }
+    __syncthreads();
+}
+
+// Grid barrier with an optional sum of ncomp values per work-group.
+// mine[0..ncomp): this work-group's values (LDS, final before the call);
+// tot[0..ncomp): the grid totals on return (LDS).  part: [2][slots][nblk].
+// After the barrier every work-group adds all work-groups' values itself, in
+// work-group order, so all copies of the totals are bitwise identical.
+__device__ void grid_reduce(SyncArea *sa, double *part, BarCtx &bc, const double *mine, double *tot,
+                            int ncomp, double *sh)
+{
+    const int tid = threadIdx.x, nblk = gridDim.x;
+    const int par = bc.parity;
+    double *pp = part + (size_t)par * kBatchSlots * nblk;
+    if (tid < ncomp) pp[(size_t)tid * nblk + blockIdx.x] = mine[tid];
+    // every thread's stores have reached L2 before the work-group arrives
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    SyncBlock *sb = &sa->sb;
+    if (tid == 0) {
+        const int x = bc.xcc;
+        const unsigned gen = bc.gen;
+        const unsigned prev =
+            __hip_atomic_fetch_add(&sb->cnt[x * 64], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (prev == (unsigned)bc.nx - 1) {
+            // the whole XCD has arrived: publish its data device-wide once,
+            // then arrive globally
+            __hip_atomic_store(&sb->cnt[x * 64], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            const unsigned p2 = __hip_atomic_fetch_add(&sb->gcnt[0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            if (p2 == bc.nxa - 1) {
+                __hip_atomic_store(&sb->gcnt[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&sb->gflag[0], gen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        spin_ne(&sb->gflag[0], gen, sb->err);
+        acquire_agent();
+        bc.gen = gen + 1;
+        bc.parity = par ^ 1;
+    }
+    __syncthreads();
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int k0 = 0; k0 < ncomp; k0 += 16) {
+        double v[16];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) v[c] = 0.0;
+        for (int b = tid; b < nblk; b += blockDim.x)
+#pragma unroll
+            for (int c = 0; c < 16; ++c)
+                if (k0 + c < ncomp) v[c] += pp[(size_t)(k0 + c) * nblk + b];
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+            if (k0 + c < ncomp)
+                for (int off = 32; off > 0; off >>= 1) v[c] += __shfl_down(v[c], off, 64);
+        if ((tid & 63) == 0)
+#pragma unroll
+            for (int c = 0; c < 16; ++c) sh[c * 16 + (tid >> 6)] = v[c];
+        __syncthreads();
+        if (tid < 16 && k0 + tid < ncomp) {
+            double s = 0.0;
+            for (int w = 0; w < nw; ++w) s += sh[tid * 16 + w];
+            tot[k0 + tid] = s;
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------- the solver
 
 template <typename TI>
 struct BSys {
     double *x64, *b64, *r64;
     const double *rhs, *nu64;
-    TI *x, *r, *p, *q, *d, *b;
+    TI *x, *r, *p, *q;
+    const TI *d;  // 1 / diag(A_TI)
     const TI *nu;
     double lambda;
     int bc[3];
     int singular;
 };
 
-struct BState {
-    double bnorm2, tol2, res2, mean_b, mean_r, scale, sum_invM2, shift;
-    // inner CG
-    double rho, alpha, beta, ires2, itol2, imean_b, imean_r, isum_invd, isum_invM2, ibnorm2;
-    int outer, status, done, inner_total, iter, idone, ran;
-    int pad;
+struct BResult {
+    double bnorm2, res64;
+    int status, iters, replaced, pad;
 };
 
 template <typename TI>
 struct BArgs {
     BSys<TI> sys[kMaxBatch];
-    BState *st;
-    int nsys;
+    BResult *res;
+    SyncArea *sa;
+    double *partial;
     Geo<double> g64;
     Geo<TI> gi;
     const int *order;
-    int nel, ngroups;
-    double *partial;
-    unsigned *counter;
-    int maxit_outer, inner_maxit, weak;
-    double tol, inner_tol;
+    int nel, ngroups, nsys, weak, maxit, max_replace;
+    double tol, delta, mass_mean;
 };
 
-// LDS of the persistent kernel: the FP64 apply with a nu field is the
-// largest user; every phase carves its buffers from it.
+// per-system scalars; every work-group holds an identical copy
+struct SysSt {
+    double bnorm2, tol2, res64;
+    double mean_b;              // singular: mean removed from the load
+    double s, s_new;            // inner scaling (power of two): true = s * stored
+    double rho, alpha, pfac;    // CG scalars (pfac: coefficient of p in the p-update)
+    double res2, ref2;          // recurrence ||M^-1 r||^2 (scaled), at the last replacement
+    double mean_r, mean64;      // singular: means removed from r (inner / FP64)
+    double sum_invd, sum_invM2; // singular: sum 1/diag, sum 1/M^2
+    double shift;
+    int status, done, iters, replaced, repl;
+};
+
 template <int P>
 struct BLds {
     static constexpr int EB = Shape<P>::EB, E3 = Lds<P>::E3;
     double xs[EB * E3], ys[EB * E3], nus[EB * E3];
     ElGeo<double> geo[EB];
-    double sh[16 * NCMAX];
-    double acc[NCMAX][kMaxBatch];
+    double sh[16 * 16];
+    double acc[kBatchSlots];
+    double tot[kBatchSlots];
 };
 
-// per-thread node loop of one element group: f(global index, GLL mass,
-// inverse GLL mass)
+// waves per SIMD asked of the compiler: the FP32 instantiation is capped so
+// that its (frequent) FP32 phases keep the occupancy of the stand-alone FP32
+// kernels; the rare FP64 residual may spill there.
+template <int P, typename TI>
+struct BatchOcc {
+    static constexpr int W = sizeof(TI) == 4 ? (P <= 6 ? 4 : 3) : 1;
+};
+
+__device__ __forceinline__ double pow2_near(double v)
+{
+    if (!(v > 0.0) || !isfinite(v)) return 1.0;
+    return exp2(rint(log2(v)));
+}
+
+// per-thread node loop of one element group: f(global index, GLL mass, 1/mass)
 template <int P, typename F>
 __device__ __forceinline__ void group_nodes(int grp, int nel, const Geo<double> &g, F &&f)
 {
@@ -106,68 +283,8 @@ __device__ __forceinline__ void group_nodes(int grp, int nel, const Geo<double> 
         f((size_t)el * S::N3 + (size_t)c * S::NL + l, Jw * kGll<P>.w[c], iJw * (1.0 / kGll<P>.w[c]));
 }
 
-// add one work item's per-thread sums into the block accumulator acc[.][s]
-template <int NC>
-__device__ __forceinline__ void block_accumulate(double (&v)[NC], int s, double *sh,
-                                                 double (&acc)[NCMAX][kMaxBatch])
-{
-    block_sum<NC>(v, sh);
-    if (threadIdx.x == 0)
-#pragma unroll
-        for (int c = 0; c < NC; ++c) acc[c][s] += v[c];
-}
-
-// End of a reduced phase: publish this block's accumulators with plain
-// stores (into the buffer of the current phase parity), wait at the grid
-// barrier, then let every block sum all blocks' partials in the same fixed
-// order and apply fin(system, totals) to its own copy of the scalars
-// (thread 0).  Every block thus holds bitwise identical scalars and takes the
-// same decisions, without device-wide atomics or a second barrier.  The two
-// parity buffers alternate, so a block that races ahead into the next
-// reduced phase never overwrites partials another block is still reading.
-template <int NC, typename F>
-__device__ void phase_reduce(cgrp::grid_group &grid, double (&acc)[NCMAX][kMaxBatch], double *sh,
-                             double *partial_base, int &parity, int nsys, F &&fin)
-{
-    const int nblk = gridDim.x;
-    double *partial = partial_base + (size_t)parity * kBatchPartialPerBlock * nblk;
-    parity ^= 1;
-    __syncthreads();
-    if (threadIdx.x == 0)
-        for (int s = 0; s < nsys; ++s)
-            for (int c = 0; c < NC; ++c) partial[(size_t)(c * kMaxBatch + s) * nblk + blockIdx.x] = acc[c][s];
-    grid.sync();
-    for (int s = 0; s < nsys; ++s) {
-        double v[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) v[c] = sum_strided(partial + (size_t)(c * kMaxBatch + s) * nblk, nblk);
-        block_sum<NC>(v, sh);
-        if (threadIdx.x == 0) fin(s, v);
-        __syncthreads();
-    }
-}
-
-__device__ __forceinline__ void zero_acc(double (&acc)[NCMAX][kMaxBatch])
-{
-    if (threadIdx.x < NCMAX * kMaxBatch) (&acc[0][0])[threadIdx.x] = 0.0;
-    __syncthreads();
-}
-
-// round-robin over (active system, group) work items; g = XCD-aware group
-template <typename F>
-__device__ __forceinline__ void for_items(const int *act, int nact, int G, const int *order, F &&f)
-{
-    const int total = nact * G;
-    for (int w = blockIdx.x; w < total; w += gridDim.x) {
-        // uniform in the work-group: keeps per-system pointers in scalar registers
-        const int s = __builtin_amdgcn_readfirstlane(act[w / G]);
-        const int slot = xcd_remap(w % G, G);
-        f(s, order ? order[slot] : slot);
-    }
-}
-
 template <typename T>
-__device__ __forceinline__ ApplyArgs<T> sys_apply_args(const Geo<T> &g, int bc[3], int nel, int G,
+__device__ __forceinline__ ApplyArgs<T> sys_apply_args(const Geo<T> &g, const int *bc, int nel, int G,
                                                        const int *order, const T *x, T *y,
                                                        const T *nu, double lambda, const T *b)
 {
@@ -187,363 +304,459 @@ __device__ __forceinline__ ApplyArgs<T> sys_apply_args(const Geo<T> &g, int bc[3
 }
 
 template <int P, typename TI>
-__global__ void __launch_bounds__(Shape<P>::NTP) k_batched(BArgs<TI> B)
+__global__ void __launch_bounds__(Shape<P>::NTP, (BatchOcc<P, TI>::W)) k_batched(BArgs<TI> B)
 {
     using S = Shape<P>;
     __shared__ BLds<P> L;
-    __shared__ int act[kMaxBatch];
-    __shared__ int nact_s;
-    __shared__ BState st[kMaxBatch];  // this block's copy of the per-system scalars
+    __shared__ SysSt st[kMaxBatch];
+    __shared__ BarCtx bc;
+    __shared__ int list[kMaxBatch];
+    __shared__ int nlist;
     cgrp::grid_group grid = cgrp::this_grid();
+    const int tid = threadIdx.x;
     const int G = B.ngroups, nel = B.nel, ns = B.nsys;
     const double N = (double)nel * S::N3;
-    int parity = 0;
-    for (int k = threadIdx.x; k < (int)(kMaxBatch * sizeof(BState) / sizeof(int)); k += blockDim.x)
-        reinterpret_cast<int *>(st)[k] = 0;
-    __syncthreads();
 
-    // active list: systems with flag(s) true (the flags are this block's
-    // copy, identical in every block, so every block takes the same branches
-    // and the same number of grid barriers)
-    auto build_active = [&](auto flag) {
-        if (threadIdx.x == 0) {
+    for (int k = tid; k < (int)(kMaxBatch * sizeof(SysSt) / sizeof(int)); k += blockDim.x)
+        reinterpret_cast<int *>(st)[k] = 0;
+    grid_register(B.sa, bc, grid);
+
+    // systems for which pred(s) holds, in index order (identical in every
+    // work-group); returns their number
+    auto make_list = [&](auto pred) -> int {
+        if (tid == 0) {
             int k = 0;
             for (int s = 0; s < ns; ++s)
-                if (flag(s)) act[k++] = s;
-            nact_s = k;
+                if (pred(st[s])) list[k++] = s;
+            nlist = k;
         }
         __syncthreads();
-        return nact_s;
+        return nlist;
     };
-
-    // ---- set-up 1: b = M f (or f), sum b, sum b^2
-    {
-        zero_acc(L.acc);
-        for (int w = blockIdx.x; w < ns * G; w += gridDim.x) {
-            const int s = __builtin_amdgcn_readfirstlane(w / G), g = w % G;
-            const BSys<TI> &Y = B.sys[s];
-            double v[2] = {0.0, 0.0};
-            group_nodes<P>(g, nel, B.g64, [&](size_t gi, double m, double im) {
-                const double bb = B.weak ? Y.rhs[gi] : m * Y.rhs[gi];
-                Y.b64[gi] = bb;
-                Y.x64[gi] = 0.0;
-                v[0] += bb;
-                v[1] += bb * bb;
-            });
-            block_accumulate<2>(v, s, L.sh, L.acc);
+    auto clear_acc = [&]() {
+        if (tid < kBatchSlots) L.acc[tid] = 0.0;
+        __syncthreads();
+    };
+    // work items (slot in the list, system, element group)
+    auto items = [&](int n, auto &&f) {
+        for (int w = blockIdx.x; w < n * G; w += gridDim.x) {
+            const int slot = w / G;
+            const int s = __builtin_amdgcn_readfirstlane(list[slot]);
+            const int g = xcd_remap(w % G, G);
+            f(slot, s, B.order ? B.order[g] : g);
         }
-        phase_reduce<2>(grid, L.acc, L.sh, B.partial, parity, ns, [&](int s, double(&t)[2]) {
-            st[s].mean_b = B.sys[s].singular ? t[0] / N : 0.0;
-            if (!isfinite(t[1])) {
-                st[s].status = DG_ERR_NONFINITE;
-                st[s].done = 1;
+    };
+    auto add_acc = [&](auto &v, int slot) {
+        constexpr int K = sizeof(v) / sizeof(double);
+        block_sum<K>(v, L.sh);
+        if (tid == 0)
+#pragma unroll
+            for (int c = 0; c < K; ++c) L.acc[slot * K + c] += v[c];
+    };
+    // sum the accumulators of n systems (k components each, the k of the
+    // phase's add_acc) over the grid,
+    // then fin(system, totals) on thread 0 in list order
+    auto reduce = [&](int n, int k, auto &&fin) {
+        grid_reduce(B.sa, B.partial, bc, L.acc, L.tot, n * k, L.sh);
+        if (tid == 0)
+            for (int slot = 0; slot < n; ++slot) fin(st[list[slot]], list[slot], &L.tot[slot * k]);
+        __syncthreads();
+    };
+    auto barrier = [&]() { grid_reduce(B.sa, B.partial, bc, L.acc, L.tot, 0, L.sh); };
+
+    TI *xs = reinterpret_cast<TI *>(L.xs), *ys = reinterpret_cast<TI *>(L.ys),
+       *nus = reinterpret_cast<TI *>(L.nus);
+    ElGeo<TI> *geo = reinterpret_cast<ElGeo<TI> *>(L.geo);
+
+    // ---- set-up 1: b = M f (or f), x = 0; sum b, sum b^2
+    int n = make_list([](const SysSt &) { return true; });
+    clear_acc();
+    items(n, [&](int slot, int s, int g) {
+        const BSys<TI> &Y = B.sys[s];
+        double v[2] = {0.0, 0.0};
+        group_nodes<P>(g, nel, B.g64, [&](size_t gi, double m, double) {
+            const double bb = B.weak ? Y.rhs[gi] : m * Y.rhs[gi];
+            Y.b64[gi] = bb;
+            Y.x64[gi] = 0.0;
+            v[0] += bb;
+            v[1] += bb * bb;
+        });
+        add_acc(v, slot);
+    });
+    reduce(n, 2, [&](SysSt &y, int s, const double *t) {
+        y.status = DG_OK;
+        y.mean_b = B.sys[s].singular ? t[0] / N : 0.0;
+        const double ms = t[1] / N - y.mean_b * y.mean_b;
+        y.s = pow2_near(sqrt(ms > 0.0 ? ms : t[1] / N));
+        if (!isfinite(t[1])) {
+            y.status = DG_ERR_NONFINITE;
+            y.done = 1;
+        }
+    });
+
+    // ---- set-up 2: project b (singular); inner r = b / s, x = 0, p = z = r/diag
+    n = make_list([](const SysSt &y) { return !y.done; });
+    clear_acc();
+    items(n, [&](int slot, int s, int g) {
+        const BSys<TI> &Y = B.sys[s];
+        const double mb = st[s].mean_b, is = 1.0 / st[s].s;
+        double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        group_nodes<P>(g, nel, B.g64, [&](size_t gi, double, double im) {
+            double bb = Y.b64[gi];
+            if (Y.singular) {
+                bb -= mb;
+                Y.b64[gi] = bb;
+            }
+            const TI r = (TI)(bb * is);
+            const TI z = r * Y.d[gi];
+            Y.r[gi] = r;
+            Y.x[gi] = (TI)0;
+            Y.p[gi] = z;
+            const double rm = bb * im, rs = (double)r * im;
+            v[0] += rm * rm;
+            v[1] += im * im;
+            v[2] += (double)Y.d[gi];
+            v[3] += (double)r * (double)z;
+            v[4] += rs * rs;
+        });
+        add_acc(v, slot);
+    });
+    reduce(n, 5, [&](SysSt &y, int, const double *t) {
+        y.bnorm2 = t[0];
+        y.res64 = t[0];
+        y.tol2 = B.tol * B.tol * t[0];
+        y.sum_invM2 = t[1];
+        y.sum_invd = t[2];
+        y.rho = t[3];
+        y.res2 = y.ref2 = t[4];
+        if (!isfinite(t[0]) || !isfinite(t[3])) {
+            y.status = DG_ERR_NONFINITE;
+            y.done = 1;
+        } else if (!(t[0] > 0.0)) {
+            y.done = 1;  // b = 0: x = 0
+        }
+    });
+
+    for (;;) {
+        if (ld_agent(B.sa->sb.err)) break;  // a barrier wait gave up (uniform after any barrier)
+        n = make_list([](const SysSt &y) { return !y.done; });
+        if (n == 0) break;
+
+        // ---- q = A p; p.q, sum q
+        clear_acc();
+        items(n, [&](int slot, int s, int g) {
+            const BSys<TI> &Y = B.sys[s];
+            ApplyArgs<TI> a = sys_apply_args<TI>(B.gi, Y.bc, nel, G, B.order, Y.p, Y.q, Y.nu, Y.lambda, nullptr);
+            double red[4];
+            if (Y.nu)
+                apply_group<P, TI, true, EPI_CG>(a, g, xs, ys, nus, geo, red);
+            else
+                apply_group<P, TI, false, EPI_CG>(a, g, xs, ys, nus, geo, red);
+            double v[2] = {red[0], red[1]};
+            add_acc(v, slot);
+        });
+        reduce(n, 2, [&](SysSt &y, int, const double *t) {
+            if (!isfinite(t[0])) {
+                y.status = DG_ERR_NONFINITE;
+                y.done = 1;
+            } else if (!(t[0] > 0.0)) {
+                y.status = DG_ERR_NOT_SPD;
+                y.done = 1;
+            } else {
+                y.alpha = y.rho / t[0];
             }
         });
-    }
-    // ---- set-up 2: project b (singular), ||M^-1 b||^2, sum 1/M^2
-    {
-        zero_acc(L.acc);
-        for (int w = blockIdx.x; w < ns * G; w += gridDim.x) {
-            const int s = __builtin_amdgcn_readfirstlane(w / G), g = w % G;
-            const BSys<TI> &Y = B.sys[s];
-            const double mb = st[s].mean_b;
-            double v[2] = {0.0, 0.0};
-            group_nodes<P>(g, nel, B.g64, [&](size_t gi, double m, double im) {
-                double bb = Y.b64[gi];
-                if (Y.singular) {
-                    bb -= mb;
-                    Y.b64[gi] = bb;
-                }
-                const double rm = bb * im;
-                v[0] += rm * rm;
-                v[1] += im * im;
-            });
-            block_accumulate<2>(v, s, L.sh, L.acc);
-        }
-        phase_reduce<2>(grid, L.acc, L.sh, B.partial, parity, ns, [&](int s, double(&t)[2]) {
-            st[s].bnorm2 = t[0];
-            st[s].tol2 = B.tol * B.tol * t[0];
-            st[s].sum_invM2 = t[1];
-            if (!(t[0] > 0.0) && st[s].status == DG_OK) st[s].done = 1;  // b = 0: x = 0
-        });
-    }
 
-    for (int outer = 0;; ++outer) {
-        // ---- FP64 residual r = b - A x (projected) and the outer test
-        int na = build_active([&](int s) { return !st[s].done; });
-        if (na == 0) break;
-        {
-            zero_acc(L.acc);
-            for_items(act, na, G, B.order, [&](int s, int g) {
+        // ---- x += alpha p, r -= alpha q; sums for rho' and ||M^-1 r||
+        n = make_list([](const SysSt &y) { return !y.done; });
+        clear_acc();
+        items(n, [&](int slot, int s, int g) {
+            const BSys<TI> &Y = B.sys[s];
+            const TI alpha = (TI)st[s].alpha;
+            double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+            group_nodes<P>(g, nel, B.g64, [&](size_t gi, double, double im) {
+                Y.x[gi] = fma(alpha, Y.p[gi], Y.x[gi]);
+                const TI r = fma(-alpha, Y.q[gi], Y.r[gi]);
+                Y.r[gi] = r;
+                const double rd = (double)r * (double)Y.d[gi];
+                const double rm = (double)r * im;
+                v[0] += (double)r;
+                v[1] += (double)r * rd;
+                v[2] += rd;
+                v[3] += rm * rm;
+                v[4] += rm * im;
+            });
+            add_acc(v, slot);
+        });
+        reduce(n, 5, [&](SysSt &y, int s, const double *t) {
+            double rz = t[1], res2 = t[3], mr = 0.0;
+            if (B.sys[s].singular) {
+                mr = t[0] / N;
+                rz = t[1] - 2.0 * mr * t[2] + mr * mr * y.sum_invd;
+                res2 = t[3] - 2.0 * mr * t[4] + mr * mr * y.sum_invM2;
+            }
+            if (res2 < 0.0) res2 = 0.0;
+            y.iters += 1;
+            y.mean_r = mr;
+            if (!isfinite(rz) || !isfinite(res2)) {
+                y.status = DG_ERR_NONFINITE;
+                y.done = 1;
+                return;
+            }
+            y.res2 = res2;
+            if (res2 * y.s * y.s <= y.tol2 || res2 <= B.delta * B.delta * y.ref2 || y.iters >= B.maxit) {
+                y.repl = 1;  // flush, FP64 residual, replace (the p-update follows it)
+            } else {
+                y.pfac = rz / y.rho;
+                y.rho = rz;
+            }
+        });
+
+        n = make_list([](const SysSt &y) { return !y.done && y.repl; });
+        if (n > 0) {
+            // ---- flush: x_64 += s x_TI, x_TI = 0
+            items(n, [&](int, int s, int g) {
                 const BSys<TI> &Y = B.sys[s];
-                ApplyArgs<double> a = sys_apply_args<double>(B.g64, (int *)Y.bc, nel, G, B.order,
-                                                             Y.x64, Y.r64, Y.nu64, Y.lambda, Y.b64);
+                const double sc = st[s].s;
+                group_nodes<P>(g, nel, B.g64, [&](size_t gi, double, double) {
+                    Y.x64[gi] = fma(sc, (double)Y.x[gi], Y.x64[gi]);
+                    Y.x[gi] = (TI)0;
+                });
+            });
+            barrier();
+            // ---- FP64 residual r_64 = b - A_64 x_64 and the stopping test
+            clear_acc();
+            items(n, [&](int slot, int s, int g) {
+                const BSys<TI> &Y = B.sys[s];
+                ApplyArgs<double> a = sys_apply_args<double>(B.g64, Y.bc, nel, G, B.order, Y.x64, Y.r64,
+                                                             Y.nu64, Y.lambda, Y.b64);
                 double red[4];
                 if (Y.nu64)
                     apply_group<P, double, true, EPI_RESID>(a, g, L.xs, L.ys, L.nus, L.geo, red);
                 else
                     apply_group<P, double, false, EPI_RESID>(a, g, L.xs, L.ys, L.nus, L.geo, red);
-                block_accumulate<4>(red, s, L.sh, L.acc);
+                add_acc(red, slot);
             });
-            phase_reduce<4>(grid, L.acc, L.sh, B.partial, parity, ns, [&](int s, double(&t)[4]) {
-                if (st[s].done) return;
-                double res2 = t[0];
-                double m = 0.0;
+            reduce(n, 4, [&](SysSt &y, int s, const double *t) {
+                double res = t[0], m = 0.0;
                 if (B.sys[s].singular) {
                     m = t[1] / N;
-                    res2 = t[0] - 2.0 * m * t[2] + m * m * t[3];
+                    res = t[0] - 2.0 * m * t[2] + m * m * t[3];
                 }
-                st[s].mean_r = m;
-                st[s].res2 = res2 > 0.0 ? res2 : 0.0;
-                st[s].ran = 0;
-                if (!isfinite(res2)) {
-                    st[s].status = DG_ERR_NONFINITE;
-                    st[s].done = 1;
-                } else if (res2 <= st[s].tol2) {
-                    st[s].done = 1;
-                } else if (outer >= B.maxit_outer) {
-                    st[s].status = DG_NOT_CONVERGED;
-                    st[s].done = 1;
+                if (res < 0.0) res = 0.0;
+                y.res64 = res;
+                y.mean64 = m;
+                y.replaced += 1;
+                if (!isfinite(res)) {
+                    y.status = DG_ERR_NONFINITE;
+                    y.done = 1;
+                } else if (res <= y.tol2) {
+                    y.done = 1;
+                } else if (y.iters >= B.maxit || y.replaced >= B.max_replace) {
+                    y.status = DG_NOT_CONVERGED;
+                    y.done = 1;
                 } else {
-                    st[s].ran = 1;
-                    st[s].outer = outer + 1;
+                    y.s_new = pow2_near(sqrt(res / N) * B.mass_mean);
                 }
+                if (y.done) y.repl = 0;
             });
-        }
-        na = build_active([&](int s) { return st[s].ran != 0; });
-        if (na == 0) continue;  // re-evaluated at the loop top (all done)
-
-        // ---- scale = RMS of the projected residual
-        {
-            zero_acc(L.acc);
-            for_items(act, na, G, B.order, [&](int s, int g) {
-                const BSys<TI> &Y = B.sys[s];
-                const double mr = st[s].mean_r;
-                double v[1] = {0.0};
-                group_nodes<P>(g, nel, B.g64, [&](size_t gi, double, double) {
-                    const double r = Y.r64[gi] - mr;
-                    v[0] += r * r;
-                });
-                block_accumulate<1>(v, s, L.sh, L.acc);
-            });
-            phase_reduce<1>(grid, L.acc, L.sh, B.partial, parity, ns, [&](int s, double(&t)[1]) {
-                if (!st[s].ran) return;
-                const double rms = sqrt(t[0] / N);
-                st[s].scale = rms > 0.0 ? rms : 1.0;
-            });
-        }
-        // ---- inner right-hand side b_in = (r - mean r)/scale, its sum
-        {
-            zero_acc(L.acc);
-            for_items(act, na, G, B.order, [&](int s, int g) {
-                const BSys<TI> &Y = B.sys[s];
-                const double mr = st[s].mean_r, inv = 1.0 / st[s].scale;
-                double v[1] = {0.0};
-                group_nodes<P>(g, nel, B.g64, [&](size_t gi, double, double) {
-                    const TI bb = (TI)((Y.r64[gi] - mr) * inv);
-                    Y.b[gi] = bb;
-                    v[0] += (double)bb;
-                });
-                block_accumulate<1>(v, s, L.sh, L.acc);
-            });
-            phase_reduce<1>(grid, L.acc, L.sh, B.partial, parity, ns, [&](int s, double(&t)[1]) {
-                if (!st[s].ran) return;
-                st[s].imean_b = B.sys[s].singular ? t[0] / N : 0.0;
-            });
-        }
-        // ---- inner set-up: r = b (projected), x = 0, p = z = r/d, norms
-        {
-            zero_acc(L.acc);
-            for_items(act, na, G, B.order, [&](int s, int g) {
-                const BSys<TI> &Y = B.sys[s];
-                const double mb = st[s].imean_b;
-                double v[4] = {0.0, 0.0, 0.0, 0.0};
-                group_nodes<P>(g, nel, B.g64, [&](size_t gi, double m, double im) {
-                    TI bb = Y.b[gi];
-                    if (Y.singular) {
-                        bb = (TI)((double)bb - mb);
-                        Y.b[gi] = bb;
-                    }
-                    Y.r[gi] = bb;
-                    Y.x[gi] = (TI)0;
-                    const TI z = bb * Y.d[gi];  // Y.d holds 1/diag(A)
-                    Y.p[gi] = z;
-                    const double rm = (double)bb * im;
-                    v[0] += (double)bb * (double)z;
-                    v[1] += rm * rm;
-                    v[2] += (double)Y.d[gi];
-                    v[3] += im * im;
-                });
-                block_accumulate<4>(v, s, L.sh, L.acc);
-            });
-            phase_reduce<4>(grid, L.acc, L.sh, B.partial, parity, ns, [&](int s, double(&t)[4]) {
-                if (!st[s].ran) return;
-                st[s].rho = t[0];
-                st[s].ibnorm2 = t[1];
-                st[s].ires2 = t[1];
-                st[s].itol2 = B.inner_tol * B.inner_tol * t[1];
-                st[s].isum_invd = t[2];
-                st[s].isum_invM2 = t[3];
-                st[s].iter = 0;
-                st[s].imean_r = 0.0;
-                st[s].idone = (t[1] > 0.0 && isfinite(t[0])) ? 0 : 1;
-            });
-        }
-        // ---- inner CG iterations
-        for (int k = 0; k < B.inner_maxit; ++k) {
-            const int ni = build_active([&](int s) { return st[s].ran && !st[s].idone; });
-            if (ni == 0) break;
-            // q = A p, p.q, sum q
-            zero_acc(L.acc);
-            for_items(act, ni, G, B.order, [&](int s, int g) {
-                const BSys<TI> &Y = B.sys[s];
-                ApplyArgs<TI> a = sys_apply_args<TI>(B.gi, (int *)Y.bc, nel, G, B.order, Y.p, Y.q,
-                                                     Y.nu, Y.lambda, nullptr);
-                double red[4];
-                TI *xs = reinterpret_cast<TI *>(L.xs), *ys = reinterpret_cast<TI *>(L.ys),
-                   *nus = reinterpret_cast<TI *>(L.nus);
-                ElGeo<TI> *geo = reinterpret_cast<ElGeo<TI> *>(L.geo);
-                if (Y.nu)
-                    apply_group<P, TI, true, EPI_CG>(a, g, xs, ys, nus, geo, red);
-                else
-                    apply_group<P, TI, false, EPI_CG>(a, g, xs, ys, nus, geo, red);
-                double v2[2] = {red[0], red[1]};
-                block_accumulate<2>(v2, s, L.sh, L.acc);
-            });
-            phase_reduce<2>(grid, L.acc, L.sh, B.partial, parity, ns, [&](int s, double(&t)[2]) {
-                if (!st[s].ran || st[s].idone) return;
-                if (!isfinite(t[0]) || t[0] <= 0.0) {
-                    st[s].idone = 1;  // breakdown: stop this inner solve, keep its iterate
-                } else {
-                    st[s].alpha = st[s].rho / t[0];
-                }
-            });
-            const int nu_ = build_active([&](int s) { return st[s].ran && !st[s].idone; });
-            // x += alpha p, r -= alpha q, reductions
-            zero_acc(L.acc);
-            for_items(act, nu_, G, B.order, [&](int s, int g) {
-                const BSys<TI> &Y = B.sys[s];
-                const TI alpha = (TI)st[s].alpha;
-                double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-                group_nodes<P>(g, nel, B.g64, [&](size_t gi, double m, double im) {
-                    Y.x[gi] = fma(alpha, Y.p[gi], Y.x[gi]);
-                    const TI r = fma(-alpha, Y.q[gi], Y.r[gi]);
-                    Y.r[gi] = r;
-                    const double rd = (double)r * (double)Y.d[gi];
-                    const double rm = (double)r * im;
-                    v[0] += (double)r;
-                    v[1] += (double)r * rd;
-                    v[2] += rd;
-                    v[3] += rm * rm;
-                    v[4] += rm * im;
-                });
-                block_accumulate<5>(v, s, L.sh, L.acc);
-            });
-            phase_reduce<5>(grid, L.acc, L.sh, B.partial, parity, ns, [&](int s, double(&t)[5]) {
-                if (!st[s].ran || st[s].idone) return;
-                double rz = t[1], res2 = t[3], mr = 0.0;
-                if (B.sys[s].singular) {
-                    mr = t[0] / N;
-                    rz = t[1] - 2.0 * mr * t[2] + mr * mr * st[s].isum_invd;
-                    res2 = t[3] - 2.0 * mr * t[4] + mr * mr * st[s].isum_invM2;
-                }
-                st[s].imean_r = mr;
-                st[s].beta = rz / st[s].rho;
-                st[s].rho = rz;
-                st[s].ires2 = res2 > 0.0 ? res2 : 0.0;
-                st[s].iter += 1;
-                st[s].inner_total += 1;
-                if (!isfinite(rz) || res2 <= st[s].itol2 || st[s].iter >= B.inner_maxit)
-                    st[s].idone = 1;
-            });
-            const int np = build_active([&](int s) { return st[s].ran && !st[s].idone; });
-            // (singular: r -= mean r)  p = r/d + beta p
-            for_items(act, np, G, B.order, [&](int s, int g) {
-                const BSys<TI> &Y = B.sys[s];
-                const TI beta = (TI)st[s].beta;
-                const double mr = st[s].imean_r;
-                group_nodes<P>(g, nel, B.g64, [&](size_t gi, double, double) {
-                    TI r = Y.r[gi];
-                    if (Y.singular) {
-                        r = (TI)((double)r - mr);
+            n = make_list([](const SysSt &y) { return !y.done && y.repl; });
+            if (n > 0) {
+                // ---- replace: r_TI = (r_64 - mean) / s_new, z = r/diag
+                clear_acc();
+                items(n, [&](int slot, int s, int g) {
+                    const BSys<TI> &Y = B.sys[s];
+                    const double m = st[s].mean64, is = 1.0 / st[s].s_new;
+                    double v[4] = {0.0, 0.0, 0.0, 0.0};
+                    group_nodes<P>(g, nel, B.g64, [&](size_t gi, double, double im) {
+                        const TI r = (TI)((Y.r64[gi] - m) * is);
                         Y.r[gi] = r;
-                    }
-                    Y.p[gi] = fma(beta, Y.p[gi], r * Y.d[gi]);
+                        const double z = (double)r * (double)Y.d[gi];
+                        const double rm = (double)r * im;
+                        v[0] += (double)r * z;
+                        v[1] += rm * rm;
+                        v[2] += (double)r;
+                        v[3] += z;
+                    });
+                    add_acc(v, slot);
                 });
-            });
-            grid.sync();
+                reduce(n, 4, [&](SysSt &y, int s, const double *t) {
+                    double rz = t[0], mr = 0.0;
+                    if (B.sys[s].singular) {
+                        mr = t[2] / N;
+                        rz = t[0] - 2.0 * mr * t[3] + mr * mr * y.sum_invd;
+                    }
+                    y.mean_r = mr;
+                    y.pfac = (rz / y.rho) * (y.s_new / y.s);
+                    y.rho = rz;
+                    y.s = y.s_new;
+                    y.res2 = y.ref2 = t[1];
+                    y.repl = 0;
+                    if (!isfinite(rz)) {
+                        y.status = DG_ERR_NONFINITE;
+                        y.done = 1;
+                    }
+                });
+            }
         }
-        // ---- x64 += scale * x_in
-        {
-            na = build_active([&](int s) { return st[s].ran != 0; });
-            for_items(act, na, G, B.order, [&](int s, int g) {
-                const BSys<TI> &Y = B.sys[s];
-                const double sc = st[s].scale;
-                group_nodes<P>(g, nel, B.g64,
-                               [&](size_t gi, double, double) { Y.x64[gi] = fma(sc, (double)Y.x[gi], Y.x64[gi]); });
+
+        // ---- (singular: r -= mean r)  p = r/diag + pfac p
+        n = make_list([](const SysSt &y) { return !y.done; });
+        items(n, [&](int, int s, int g) {
+            const BSys<TI> &Y = B.sys[s];
+            const TI pf = (TI)st[s].pfac;
+            const double mr = st[s].mean_r;
+            const bool sing = Y.singular;
+            group_nodes<P>(g, nel, B.g64, [&](size_t gi, double, double) {
+                TI r = Y.r[gi];
+                if (sing) {
+                    r = (TI)((double)r - mr);
+                    Y.r[gi] = r;
+                }
+                Y.p[gi] = fma(pf, Y.p[gi], r * Y.d[gi]);
             });
-            grid.sync();
-        }
+        });
+        barrier();
     }
 
-    // ---- singular systems: M-weighted mean of x removed
+    // ---- singular systems: remove the M-weighted mean of x
+    n = make_list([&](const SysSt &y) { return y.status >= 0 && y.bnorm2 > 0.0; });
     {
-        zero_acc(L.acc);
-        for (int w = blockIdx.x; w < ns * G; w += gridDim.x) {
-            const int s = __builtin_amdgcn_readfirstlane(w / G), g = w % G;
-            if (!B.sys[s].singular) continue;
+        // keep only singular systems (list order preserved)
+        if (tid == 0) {
+            int k = 0;
+            for (int i = 0; i < nlist; ++i)
+                if (B.sys[list[i]].singular) list[k++] = list[i];
+            nlist = k;
+        }
+        __syncthreads();
+        n = nlist;
+    }
+    if (n > 0 && !ld_agent(B.sa->sb.err)) {
+        clear_acc();
+        items(n, [&](int slot, int s, int g) {
             const BSys<TI> &Y = B.sys[s];
             double v[2] = {0.0, 0.0};
-            group_nodes<P>(g, nel, B.g64, [&](size_t gi, double m, double im) {
+            group_nodes<P>(g, nel, B.g64, [&](size_t gi, double m, double) {
                 v[0] += m * Y.x64[gi];
                 v[1] += m;
             });
-            block_accumulate<2>(v, s, L.sh, L.acc);
-        }
-        phase_reduce<2>(grid, L.acc, L.sh, B.partial, parity, ns, [&](int s, double(&t)[2]) {
-            st[s].shift = (B.sys[s].singular && t[1] > 0.0) ? t[0] / t[1] : 0.0;
+            add_acc(v, slot);
         });
-        for (int w = blockIdx.x; w < ns * G; w += gridDim.x) {
-            const int s = __builtin_amdgcn_readfirstlane(w / G), g = w % G;
-            if (!B.sys[s].singular) continue;
+        reduce(n, 2, [&](SysSt &y, int, const double *t) { y.shift = t[1] > 0.0 ? t[0] / t[1] : 0.0; });
+        items(n, [&](int, int s, int g) {
             const BSys<TI> &Y = B.sys[s];
             const double sh = st[s].shift;
             group_nodes<P>(g, nel, B.g64, [&](size_t gi, double, double) { Y.x64[gi] -= sh; });
-        }
+        });
     }
-    if (blockIdx.x == 0)
-        for (int k = threadIdx.x; k < (int)(kMaxBatch * sizeof(BState) / sizeof(int)); k += blockDim.x)
-            reinterpret_cast<int *>(B.st)[k] = reinterpret_cast<const int *>(st)[k];
-}
-
-template <int P, typename TI>
-const void *kernel_ptr()
-{
-    return reinterpret_cast<const void *>(&k_batched<P, TI>);
+    if (blockIdx.x == 0 && tid == 0)
+        for (int s = 0; s < ns; ++s) {
+            BResult r;
+            r.bnorm2 = st[s].bnorm2;
+            r.res64 = st[s].res64;
+            r.status = st[s].status;
+            r.iters = st[s].iters;
+            r.replaced = st[s].replaced;
+            r.pad = 0;
+            B.res[s] = r;
+        }
 }
 
 template <typename TI>
 const void *kernel_for(int P)
 {
     switch (P) {
-        case 3: return kernel_ptr<3, TI>();
-        case 4: return kernel_ptr<4, TI>();
-        case 5: return kernel_ptr<5, TI>();
-        case 6: return kernel_ptr<6, TI>();
-        case 7: return kernel_ptr<7, TI>();
-        case 8: return kernel_ptr<8, TI>();
+        case 3: return reinterpret_cast<const void *>(&k_batched<3, TI>);
+        case 4: return reinterpret_cast<const void *>(&k_batched<4, TI>);
+        case 5: return reinterpret_cast<const void *>(&k_batched<5, TI>);
+        case 6: return reinterpret_cast<const void *>(&k_batched<6, TI>);
+        case 7: return reinterpret_cast<const void *>(&k_batched<7, TI>);
+        case 8: return reinterpret_cast<const void *>(&k_batched<8, TI>);
     }
     return nullptr;
 }
 
-// autotuned launch shape per (device, P, inner precision, nsys)
+template <typename TI>
+void fill_args(BArgs<TI> &B, const MeshDev &m, const BatchRequest &req)
+{
+    B.nsys = req.nsys;
+    B.res = (BResult *)req.results;
+    B.sa = (SyncArea *)req.sync;
+    B.partial = req.partial;
+    const TI *h = sizeof(TI) == 8 ? (const TI *)m.h64 : (const TI *)m.h32;
+    const TI *ih = sizeof(TI) == 8 ? (const TI *)m.ih64 : (const TI *)m.ih32;
+    int off = 0;
+    for (int d = 0; d < 3; ++d) {
+        B.g64.n[d] = B.gi.n[d] = m.n[d];
+        B.g64.bc[d] = B.gi.bc[d] = m.bc[d];
+        B.g64.h[d] = m.h64 + off;
+        B.g64.ih[d] = m.ih64 + off;
+        B.gi.h[d] = h + off;
+        B.gi.ih[d] = ih + off;
+        off += m.n[d];
+    }
+    B.order = m.order;
+    B.nel = (int)m.nel;
+    B.ngroups = apply_groups(m.P, m.nel);
+    B.weak = req.weak;
+    B.maxit = req.maxit;
+    B.max_replace = req.max_replace;
+    B.tol = req.tol;
+    B.delta = req.delta;
+    B.mass_mean = req.mass_mean;
+    for (int s = 0; s < req.nsys; ++s) {
+        const BatchSysDesc &D = req.sys[s];
+        BSys<TI> &Y = B.sys[s];
+        Y.x64 = D.x64;
+        Y.b64 = D.b64;
+        Y.r64 = D.r64;
+        Y.rhs = D.rhs;
+        Y.nu64 = D.nu64;
+        Y.x = (TI *)D.xi;
+        Y.r = (TI *)D.ri;
+        Y.p = (TI *)D.pi;
+        Y.q = (TI *)D.qi;
+        Y.d = (const TI *)D.di;
+        Y.nu = (const TI *)D.nui;
+        Y.lambda = D.lambda;
+        for (int d = 0; d < 3; ++d) Y.bc[d] = D.bc[d];
+        Y.singular = D.singular;
+    }
+}
+
+// autotuned launch shape per (device, P, inner precision, nsys, mesh size)
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int, int>, int> g_tune;
+std::map<std::tuple<int, int, int, int, long long>, int> g_tune;
 
 }  // namespace
 
-int batched_launch(const MeshDev &m, const BatchRequest &req, hipStream_t stream,
-                   BatchResult *res)
+size_t batched_sync_bytes() { return sizeof(SyncArea); }
+size_t batched_result_bytes() { return sizeof(BResult) * kMaxBatch; }
+size_t batched_partial_doubles() { return (size_t)2 * kBatchSlots * kBatchMaxBlocks; }
+size_t batched_sync_err_offset() { return offsetof(SyncArea, sb) + offsetof(SyncBlock, err); }
+
+int batched_check_sync(const void *host_sync_err)
+{
+    if (*(const unsigned *)host_sync_err) {
+        set_error("batched solve: a grid barrier wait exceeded its spin limit");
+        return DG_ERR_DEVICE;
+    }
+    return DG_OK;
+}
+
+int batched_read_results(const void *host_results, int s, BatchSysResult *out)
+{
+    const BResult *r = (const BResult *)host_results + s;
+    out->status = r->status;
+    out->iters = r->iters;
+    out->replaced = r->replaced;
+    out->bnorm2 = r->bnorm2;
+    out->res64 = r->res64;
+    return DG_OK;
+}
+
+int batched_launch(const MeshDev &m, const BatchRequest &req, hipStream_t stream, int *blocks_per_cu)
 {
     const bool f32 = req.inner_fp32;
     const void *fn = f32 ? kernel_for<float>(m.P) : kernel_for<double>(m.P);
@@ -553,10 +766,9 @@ int batched_launch(const MeshDev &m, const BatchRequest &req, hipStream_t stream
     }
     int dev = 0;
     DG_HIP_CHECK(hipGetDevice(&dev));
-    hipDeviceProp_t prop;
-    DG_HIP_CHECK(hipGetDeviceProperties(&prop, dev));
-    int coop = 0;
+    int coop = 0, ncu = 0;
     DG_HIP_CHECK(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+    DG_HIP_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     if (!coop) {
         set_error("device does not support cooperative launches");
         return DG_ERR_DEVICE;
@@ -568,74 +780,21 @@ int batched_launch(const MeshDev &m, const BatchRequest &req, hipStream_t stream
         set_error("batched kernel does not fit on a compute unit");
         return DG_ERR_DEVICE;
     }
-    const int ncu = prop.multiProcessorCount;
+    per_cu = std::min(per_cu, kBatchMaxBlocks / ncu);
 
-    auto fill = [&](auto &B) {
-        using TI = std::remove_pointer_t<decltype(B.sys[0].x)>;
-        B.nsys = req.nsys;
-        B.st = (BState *)req.state;
-        for (int d = 0; d < 3; ++d) {
-            B.g64.n[d] = m.n[d];
-            B.gi.n[d] = m.n[d];
-            B.g64.bc[d] = m.bc[d];
-            B.gi.bc[d] = m.bc[d];
-        }
-        const TI *h = std::is_same<TI, double>::value ? (const TI *)m.h64 : (const TI *)m.h32;
-        const TI *ih = std::is_same<TI, double>::value ? (const TI *)m.ih64 : (const TI *)m.ih32;
-        int off = 0;
-        for (int d = 0; d < 3; ++d) {
-            B.g64.h[d] = m.h64 + off;
-            B.g64.ih[d] = m.ih64 + off;
-            B.gi.h[d] = h + off;
-            B.gi.ih[d] = ih + off;
-            off += m.n[d];
-        }
-        B.order = m.order;
-        B.nel = (int)m.nel;
-        B.ngroups = apply_groups(m.P, m.nel);
-        B.partial = req.partial;
-        B.counter = req.counter;
-        B.maxit_outer = req.maxit_outer;
-        B.inner_maxit = req.inner_maxit;
-        B.weak = req.weak;
-        B.tol = req.tol;
-        B.inner_tol = req.inner_tol;
-        for (int s = 0; s < req.nsys; ++s) {
-            auto &Y = B.sys[s];
-            const BatchSysDesc &D = req.sys[s];
-            Y.x64 = D.x64;
-            Y.b64 = D.b64;
-            Y.r64 = D.r64;
-            Y.rhs = D.rhs;
-            Y.nu64 = D.nu64;
-            Y.x = (TI *)D.xi;
-            Y.r = (TI *)D.ri;
-            Y.p = (TI *)D.pi;
-            Y.q = (TI *)D.qi;
-            Y.d = (TI *)D.di;
-            Y.b = (TI *)D.bi;
-            Y.nu = (const TI *)D.nui;
-            Y.lambda = D.lambda;
-            for (int d = 0; d < 3; ++d) Y.bc[d] = D.bc[d];
-            Y.singular = D.singular;
-        }
-    };
-
-    auto run = [&](int bpc, int maxit_outer, int inner_maxit) -> int {
-        DG_HIP_CHECK(hipMemsetAsync(req.state, 0, sizeof(BState) * kMaxBatch, stream));
-        dim3 grid(std::min(kBatchMaxBlocks, std::max(8, ((ncu * bpc) / 8) * 8))), block(threads);
+    auto run = [&](int bpc, int maxit) -> int {
+        DG_HIP_CHECK(hipMemsetAsync(req.sync, 0, sizeof(SyncBlock), stream));
+        const dim3 grid(ncu * bpc), block(threads);
         if (f32) {
             BArgs<float> B{};
-            fill(B);
-            B.maxit_outer = maxit_outer;
-            B.inner_maxit = inner_maxit;
+            fill_args(B, m, req);
+            B.maxit = maxit;
             void *args[] = {&B};
             DG_HIP_CHECK(hipLaunchCooperativeKernel(fn, grid, block, args, 0, stream));
         } else {
             BArgs<double> B{};
-            fill(B);
-            B.maxit_outer = maxit_outer;
-            B.inner_maxit = inner_maxit;
+            fill_args(B, m, req);
+            B.maxit = maxit;
             void *args[] = {&B};
             DG_HIP_CHECK(hipLaunchCooperativeKernel(fn, grid, block, args, 0, stream));
         }
@@ -644,50 +803,37 @@ int batched_launch(const MeshDev &m, const BatchRequest &req, hipStream_t stream
 
     // autotune: time a short, fixed amount of work for every launch shape
     int bpc = 1;
+    const auto key = std::make_tuple(dev, m.P, f32 ? 1 : 0, req.nsys, (long long)m.nel);
     {
-        const auto key = std::make_tuple(dev, m.P, f32 ? 1 : 0, req.nsys);
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune.find(key);
         if (it != g_tune.end()) {
-            bpc = it->second;
+            bpc = std::min(it->second, per_cu);
         } else {
             double best = 1e300;
+            hipEvent_t e0, e1;
+            DG_HIP_CHECK(hipEventCreate(&e0));
+            DG_HIP_CHECK(hipEventCreate(&e1));
             for (int c = 1; c <= per_cu; ++c) {
-                hipEvent_t e0, e1;
-                DG_HIP_CHECK(hipEventCreate(&e0));
-                DG_HIP_CHECK(hipEventCreate(&e1));
                 DG_HIP_CHECK(hipEventRecord(e0, stream));
-                int rc = run(c, 1, 8);
+                int rc = run(c, 8);
                 DG_HIP_CHECK(hipEventRecord(e1, stream));
                 DG_HIP_CHECK(hipEventSynchronize(e1));
                 float ms = 0.f;
                 DG_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
-                (void)hipEventDestroy(e0);
-                (void)hipEventDestroy(e1);
                 if (rc) return rc;
                 if (ms < best) {
                     best = ms;
                     bpc = c;
                 }
             }
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
             g_tune[key] = bpc;
         }
     }
-    if (res) res->blocks_per_cu = bpc;
-    return run(bpc, req.maxit_outer, req.inner_maxit);
-}
-
-size_t batched_state_bytes() { return sizeof(BState) * kMaxBatch; }
-
-int batched_read_state(const void *host_state, int s, BatchSysResult *out)
-{
-    const BState *st = (const BState *)host_state + s;
-    out->status = st->status;
-    out->outer = st->outer;
-    out->inner_total = st->inner_total;
-    out->bnorm2 = st->bnorm2;
-    out->res2 = st->res2;
-    return DG_OK;
+    if (blocks_per_cu) *blocks_per_cu = bpc;
+    return run(bpc, req.maxit);
 }
 
 }  // namespace dg

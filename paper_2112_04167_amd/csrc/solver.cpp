@@ -465,9 +465,9 @@ size_t batched_footprint(const MeshDev &m, int precision, int nsys)
     const size_t N = (size_t)m.ndof;
     const size_t ti = precision == DG_FP64 ? sizeof(double) : sizeof(float);
     size_t b = 0;
-    b += (size_t)nsys * (2 * align256(N * sizeof(double)) + 7 * align256(N * ti));
-    b += align256((size_t)2 * kBatchPartialPerBlock * kBatchMaxBlocks * sizeof(double));
-    b += align256(256) + align256(batched_state_bytes());
+    b += (size_t)nsys * (2 * align256(N * sizeof(double)) + 6 * align256(N * ti));
+    b += align256(batched_partial_doubles() * sizeof(double));
+    b += align256(batched_sync_bytes()) + align256(batched_result_bytes());
     return b;
 }
 
@@ -496,7 +496,8 @@ int solve_batched(dg_mesh *m, int nsys, const double *lambdas, const double *con
         }
         w.bytes = need;
     }
-    if (!w.host_state) DG_HIP_CHECK(hipHostMalloc(&w.host_state, batched_state_bytes(), 0));
+    const size_t host_bytes = batched_result_bytes() + 256;
+    if (!w.host_state) DG_HIP_CHECK(hipHostMalloc(&w.host_state, host_bytes, 0));
     char *p = (char *)w.base;
     auto take = [&](size_t bytes) {
         char *r = p;
@@ -506,11 +507,18 @@ int solve_batched(dg_mesh *m, int nsys, const double *lambdas, const double *con
     BatchRequest rq{};
     rq.nsys = nsys;
     rq.tol = o.tol;
-    rq.inner_tol = o.inner_tol;
-    rq.maxit_outer = std::min(o.maxit, 1000);
-    rq.inner_maxit = o.inner_maxit;
+    // mixed: replace the FP32 recurrence residual once it has dropped by
+    // inner_tol; FP64: only when it claims convergence
+    rq.delta = f32 ? o.inner_tol : 0.0;
+    rq.maxit = o.inner_maxit;
+    rq.max_replace = std::max(1, std::min(o.maxit, 1000));
     rq.weak = o.rhs_is_weak;
     rq.inner_fp32 = f32;
+    {
+        double vol = 1.0;
+        for (int d = 0; d < 3; ++d) vol *= md.v[d][md.n[d]] - md.v[d][0];
+        rq.mass_mean = vol / (double)md.ndof;
+    }
     for (int k = 0; k < nsys; ++k) {
         BatchSysDesc &D = rq.sys[k];
         D.x64 = x[k];
@@ -522,7 +530,6 @@ int solve_batched(dg_mesh *m, int nsys, const double *lambdas, const double *con
         D.pi = take(N * ti);
         D.qi = take(N * ti);
         D.di = take(N * ti);
-        D.bi = take(N * ti);
         void *nui = take(N * ti);
         const bool pois = is_poisson && is_poisson[k];
         for (int d = 0; d < 3; ++d)
@@ -544,24 +551,27 @@ int solve_batched(dg_mesh *m, int nsys, const double *lambdas, const double *con
         }
         if (rc) return rc;
     }
-    rq.partial = (double *)take((size_t)2 * kBatchPartialPerBlock * kBatchMaxBlocks * sizeof(double));
-    rq.counter = (unsigned *)take(256);
-    rq.state = take(batched_state_bytes());
-    DG_HIP_CHECK(hipMemsetAsync(rq.counter, 0, 256, s));
-    BatchResult br{};
-    int rc = batched_launch(md, rq, s, &br);
+    rq.partial = (double *)take(batched_partial_doubles() * sizeof(double));
+    rq.sync = take(batched_sync_bytes());
+    rq.results = take(batched_result_bytes());
+    int bpc = 0;
+    int rc = batched_launch(md, rq, s, &bpc);
     if (rc) return rc;
-    DG_HIP_CHECK(hipMemcpyAsync(w.host_state, rq.state, batched_state_bytes(), hipMemcpyDeviceToHost, s));
+    char *hs = (char *)w.host_state;
+    DG_HIP_CHECK(hipMemcpyAsync(hs, rq.results, batched_result_bytes(), hipMemcpyDeviceToHost, s));
+    DG_HIP_CHECK(hipMemcpyAsync(hs + batched_result_bytes(), (char *)rq.sync + batched_sync_err_offset(),
+                                sizeof(unsigned), hipMemcpyDeviceToHost, s));
     DG_HIP_CHECK(hipStreamSynchronize(s));
+    if ((rc = batched_check_sync(hs + batched_result_bytes()))) return rc;
     int worst = DG_OK;
     for (int k = 0; k < nsys; ++k) {
         BatchSysResult r{};
-        batched_read_state(w.host_state, k, &r);
+        batched_read_results(hs, k, &r);
         if (infos) {
-            infos[k].iters = r.inner_total;
-            infos[k].outer_iters = r.outer;
+            infos[k].iters = r.iters;
+            infos[k].outer_iters = r.replaced;
             infos[k].status = r.status;
-            infos[k].rel_res = r.bnorm2 > 0 ? std::sqrt(r.res2 / r.bnorm2) : 0.0;
+            infos[k].rel_res = r.bnorm2 > 0 ? std::sqrt(r.res64 / r.bnorm2) : 0.0;
             infos[k].true_rel_res = infos[k].rel_res;
         }
         if (r.status < 0 && (worst >= 0 || r.status < worst)) worst = r.status;

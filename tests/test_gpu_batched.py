@@ -31,6 +31,8 @@ def run_batched(spec, lams, nus, pois, fs, precision=1, **kw):
     nud = [None if v is None else to_dev(v) for v in nus]
     o = dg.default_opts(precision=precision, **kw)
     rc, infos = dg.helmholtz_solve_batched(mesh, lams, nud, pois, rhs, xs, o, raise_on_error=False)
+    if rc < 0:
+        say("batched solve returned", rc, dg.last_error())
     out = [x.cpu().numpy() for x in xs]
     mesh.destroy()
     return rc, infos, out
