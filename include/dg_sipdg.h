@@ -78,24 +78,26 @@ typedef struct dg_mesh dg_mesh;  /* opaque */
 
 typedef struct {
     double tol;         /* relative collocation residual (default 1e-10) */
-    int maxit;          /* CG iteration cap (FP64) / outer IR cap (mixed) */
+    int maxit;          /* CG iteration cap (FP64) / cap on FP64 residual replacements (mixed) */
     int precision;      /* DG_FP64 or DG_MIXED */
-    double inner_tol;   /* mixed: relative tolerance of each FP32 inner solve */
-    int inner_maxit;    /* mixed: iteration cap of each inner solve */
+    double inner_tol;   /* mixed: the FP32 CG recurrence residual is replaced by the FP64
+                           residual b - A x once it has dropped by this factor since the
+                           last replacement (or claims convergence) */
+    int inner_maxit;    /* mixed (and batched): cap on FP32 CG iterations in total */
     int rhs_is_weak;    /* 0: rhs is the nodal f (b = M f); 1: rhs is b itself */
     int fixed_iters;    /* > 0: run exactly this many CG iterations, no stopping test */
 } dg_solve_opts;
 
 typedef struct {
-    int iters;            /* CG iterations (mixed: sum of inner iterations) */
-    int outer_iters;      /* IR steps (0 in FP64 mode) */
+    int iters;            /* CG iterations (mixed: FP32 iterations) */
+    int outer_iters;      /* mixed: FP64 residual evaluations (replacements); 0 in FP64 mode */
     int status;
     double rel_res;       /* recurrence residual at exit (FP64: CG recurrence) */
     double true_rel_res;  /* || M^-1 (b - A x) || / || M^-1 b || recomputed from x */
     double seconds;       /* host wall time of the call */
 } dg_solve_info;
 
-/* Default options: tol 1e-10, maxit 100000, FP64, inner_tol 1e-4,
+/* Default options: tol 1e-10, maxit 100000, FP64, inner_tol 1e-2,
    inner_maxit 20000, nodal rhs, no fixed iteration count. */
 void dg_default_opts(dg_solve_opts *opts);
 
@@ -149,13 +151,18 @@ int helmholtz_solve(dg_mesh *m, double lambda, const double *nu_field, double nu
 int poisson_solve(dg_mesh *m, const double *rhs, double *x, const dg_solve_opts *opts,
                   dg_solve_info *info);
 
-/* nsys systems on one mesh, solved together in one persistent launch per
-   refinement step (FP32 inner CG with per-system scalars and retirement,
-   FP64 refinement): the 3 velocity Helmholtz problems and the pressure
-   Poisson problem of one implicit stage.  lambdas[i], nu_fields[i] (device
-   double nodal or NULL for nu = 1), is_poisson[i] (1: lambda ignored, Poisson
-   as in poisson_solve), rhs[i], x[i] (device double).  infos[nsys] may be
-   NULL.  nsys <= 8. */
+/* nsys systems on one mesh, solved together in one persistent, cooperative
+   launch: the 3 velocity Helmholtz problems and the pressure Poisson problem
+   of one implicit stage (Alg. 3).  Each system runs Jacobi-PCG with its own
+   scalars, stopping test and retirement; with DG_MIXED the recurrence is
+   FP32 with FP64 residual replacement (as in helmholtz_solve), with DG_FP64
+   it is FP64 throughout.  lambdas[i], nu_fields[i] (device double nodal or
+   NULL for nu = 1), is_poisson[i] (1: lambda ignored, Poisson as in
+   poisson_solve), rhs[i], x[i] (device double, output).  infos[nsys] may be
+   NULL.  nsys <= 8.  The launch shape (resident work-groups per CU) is
+   autotuned per (device, P, precision, nsys, mesh size) on first use.
+   Returns the worst status over the systems; DG_ERR_DEVICE if the device
+   cannot run cooperative launches or a grid-barrier wait timed out. */
 int helmholtz_solve_batched(dg_mesh *m, int nsys, const double *lambdas,
                             const double *const *nu_fields, const int *is_poisson,
                             const double *const *rhs, double *const *x,

@@ -243,19 +243,80 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_ir_scale(CgVecArgs<float> A)
     publish_partials<1>(red, A.partial, gridDim.x, sh);
 }
 
-// r32 = (r64 - mean_r) / scale
+// r32 = (r64 - mean_r) / scale_new (the first inner right-hand side)
 template <int P>
 __global__ void __launch_bounds__(Shape<P>::NTP) k_ir_to_inner(CgVecArgs<float> A)
 {
     using S = Shape<P>;
     const LineCtx<P, float> c = line_ctx<P, float>(A);
+    const double mr = A.sc->mean_r, sn = A.sc->scale_new, inv = 1.0 / sn;
+    if (blockIdx.x == 0 && threadIdx.x == 0) A.sc->scale = sn;  // no work-group reads scale here
     if (!c.active) return;
-    const double mr = A.sc->mean_r, inv = 1.0 / A.sc->scale;
 #pragma unroll
     for (int k = 0; k < S::n; ++k) {
         const size_t gi = c.base + (size_t)k * S::NL;
         A.r[gi] = (float)((A.src64[gi] - mr) * inv);
     }
+}
+
+// residual replacement: r32 = (r64 - mean_r) / scale_new, x32 = 0; sums for
+// rho' = r.z (z = r/diag), ||M^-1 r||^2, sum r, sum z
+template <int P>
+__global__ void __launch_bounds__(Shape<P>::NTP) k_ir_replace(CgVecArgs<float> A)
+{
+    using S = Shape<P>;
+    __shared__ double sh[16 * 4];
+    const LineCtx<P, float> c = line_ctx<P, float>(A);
+    const double mr = A.sc->mean_r, inv = 1.0 / A.sc->scale_new;
+    double red[4] = {0.0, 0.0, 0.0, 0.0};
+    if (c.active) {
+#pragma unroll
+        for (int k = 0; k < S::n; ++k) {
+            const size_t gi = c.base + (size_t)k * S::NL;
+            const float r = (float)((A.src64[gi] - mr) * inv);
+            A.r[gi] = r;
+            A.x[gi] = 0.0f;
+            const double z = (double)r * (double)A.d[gi];
+            const double rm = (double)r * (c.iJw * inv_w<P>(k));
+            red[0] += (double)r * z;
+            red[1] += rm * rm;
+            red[2] += (double)r;
+            red[3] += z;
+        }
+    }
+    publish_partials<4>(red, A.partial, gridDim.x, sh);
+}
+
+__global__ void __launch_bounds__(1024) k_finish_replace(const double *partial, int nblk, CgScalars *in,
+                                                        CgScalars *out, double delta2, int restart)
+{
+    __shared__ double sh[16 * 4];
+    double t[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) t[c] = sum_strided(partial + (size_t)c * nblk, nblk);
+    block_sum<4>(t, sh);
+    if (threadIdx.x != 0) return;
+    double rz = t[0], mr = 0.0;
+    if (in->singular) {
+        mr = t[2] / (double)in->ndof;
+        rz = t[0] - 2.0 * mr * t[3] + mr * mr * in->sum_invd;
+    }
+    // the recurrence residual being replaced belongs to the step that set
+    // done; its predecessor's r.z is rho_prev
+    const double sn = out->scale_new;
+    in->beta = restart ? 0.0 : (rz / in->rho_prev) * (sn / out->scale);
+    in->rho = rz;
+    in->mean_r = mr;
+    in->res2 = t[1];
+    const double floor2 = out->tol2 / (sn * sn);
+    in->tol2 = delta2 * t[1] > floor2 ? delta2 * t[1] : floor2;
+    in->status = DG_OK;
+    in->done = 0;
+    if (!isfinite(rz) || !isfinite(t[1])) {
+        in->status = DG_ERR_NONFINITE;
+        in->done = 1;
+    }
+    out->scale = sn;
 }
 
 // x64 += scale * x32
@@ -336,6 +397,7 @@ __global__ void __launch_bounds__(1024) k_finish(const double *partial, int nblk
         }
         if (res2 < 0.0) res2 = 0.0;
         sc->beta = rz / sc->rho;
+        sc->rho_prev = sc->rho;
         sc->rho = rz;
         sc->res2 = res2;
         sc->iter += 1;
@@ -353,8 +415,9 @@ __global__ void __launch_bounds__(1024) k_finish(const double *partial, int nblk
     } else if constexpr (OP == FIN_MEANX) {
         sc->shift = tot[0] / tot[1];
     } else if constexpr (OP == FIN_IRSCALE) {
+        // a power of two, so that changing the scaling is exact
         const double rms = sqrt(tot[0] / (double)sc->ndof);
-        sc->scale = rms > 0.0 ? rms : 1.0;
+        sc->scale_new = (rms > 0.0 && isfinite(rms)) ? exp2(rint(log2(rms))) : 1.0;
     }
 }
 
@@ -486,6 +549,18 @@ int ir_to_inner(const MeshDev &m, CgVecArgs<float> a, hipStream_t s)
     return with_P(m.P, [&](auto PC) {
         constexpr int P = decltype(PC)::value;
         hipLaunchKernelGGL((k_ir_to_inner<P>), DG_GRID(PC), 0, s, a);
+    });
+}
+
+int ir_replace(const MeshDev &m, CgVecArgs<float> a, CgScalars *inner, double delta2, bool restart,
+               hipStream_t s)
+{
+    prep(m, a);
+    return with_P(m.P, [&](auto PC) {
+        constexpr int P = decltype(PC)::value;
+        hipLaunchKernelGGL((k_ir_replace<P>), DG_GRID(PC), 0, s, a);
+        hipLaunchKernelGGL(k_finish_replace, dim3(1), dim3(1024), 0, s, a.partial, apply_groups(P, m.nel),
+                           inner, a.sc, delta2, restart ? 1 : 0);
     });
 }
 

@@ -10,6 +10,7 @@ namespace dg {
 // last work-group of a reduction (one thread), read by every later kernel.
 struct CgScalars {
     double rho;        // r.z of the current iterate
+    double rho_prev;   // r.z of the previous iterate (for a residual replacement)
     double alpha, beta;
     double pq, sumq;   // p.Ap and sum(Ap) of the current step
     double bnorm2;     // ||M^-1 b||^2
@@ -21,7 +22,8 @@ struct CgScalars {
     double sum_invM2;  // singular: sum 1/M^2
     double shift;      // singular: M-weighted mean of x removed at the end
     double true_res2;  // ||M^-1 (b - A x)||^2 of the last residual evaluation
-    double scale;      // mixed: scaling of the inner right-hand side
+    double scale;      // mixed: power-of-two scaling of the inner vectors (true = scale * stored)
+    double scale_new;  // mixed: scaling chosen for the next residual replacement
     int iter, maxit, fixed_iters, done, status, singular;
     long long ndof;
     int pad[2];
@@ -101,10 +103,16 @@ template <typename T>
 int cg_pupdate(const MeshDev &m, CgVecArgs<T> a, hipStream_t s); // p = z + beta p
 template <typename T>
 int cg_finish(const MeshDev &m, CgVecArgs<T> a, hipStream_t s);  // singular: x -= M-mean
-// mixed precision: r32 = (r64 - mean_r) / scale (scale = max |.|), and x64 += scale * d32
+// mixed precision (a.sc: the refinement scalars)
 int convert_f64_to_f32(const double *a, float *b, size_t n, hipStream_t s);
-int ir_scale(const MeshDev &m, CgVecArgs<float> a, hipStream_t s);      // sc->scale = RMS(src64 - mean_r)
-int ir_to_inner(const MeshDev &m, CgVecArgs<float> a, hipStream_t s);   // r = (src64 - mean_r)/scale
+int ir_scale(const MeshDev &m, CgVecArgs<float> a, hipStream_t s);      // sc->scale_new = 2^round(log2 RMS(src64 - mean_r))
+int ir_to_inner(const MeshDev &m, CgVecArgs<float> a, hipStream_t s);   // r = (src64 - mean_r)/scale_new; scale = scale_new
 int ir_accumulate(const MeshDev &m, CgVecArgs<float> a, hipStream_t s); // dst64 += scale * x
+// residual replacement of the inner CG: r = (src64 - mean_r)/scale_new, x = 0,
+// then (on inner) rho, beta = rho'/rho * scale_new/scale (0 if restart), the
+// replacement threshold tol2 = max(delta2 ||M^-1 r||^2, outer tol2/scale_new^2),
+// done = 0; finally scale = scale_new.  Follow with cg_pupdate.
+int ir_replace(const MeshDev &m, CgVecArgs<float> a, CgScalars *inner, double delta2, bool restart,
+               hipStream_t s);
 
 }  // namespace dg
