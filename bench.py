@@ -14,11 +14,17 @@ Also reported on the same JSON line (each measured after the timed steps):
                 (collocation-residual rule), solves/s and DOF-iterations/s
   poisson       the pressure Poisson solve of the same mesh (lambda = 0)
   mixed         FP32-inner / FP64-refinement solves of the 4^3, P=7 case
+  solve_mixed   the same Helmholtz solve, FP32 CG with FP64 residual
+                replacement, to the same 1e-10 residual
+  poisson_mixed the Poisson solve in the mixed mode
+  mixed_small   FP64 vs mixed on the 4^3, P=7 case, lambda in {1e2,1e4,1e6}
   batched       the 24^3, P=5 stage (3 velocity + 1 pressure) in one
-                persistent launch per refinement step vs 4 sequential FP64
+                persistent launch vs the same 4 systems solved one after the
+                other by the plain FP64 solver
   serving       the request stream (Poisson arrivals), p50/p99 latency
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
+                       [--legs solve,poisson,...] [--no-cpu]
 """
 import argparse
 import json
@@ -160,19 +166,28 @@ def bench_mixed_small(dg, torch, reps=20):
     return out
 
 
-def bench_mixed_large(dg, torch, spec, lam):
+def bench_mixed_large(dg, torch, spec, lam, poisson=False):
+    """The mixed-precision solve of the large mesh (same right-hand side and
+    1e-10 residual rule as the FP64 leg of the same problem)."""
     import synth
     dev = torch.device("cuda:0")
     mesh = dg.mesh_from_spec(spec)
-    f = torch.from_numpy(synth.uniform_field(mesh.ndof, synth.SEEDS["large_helmholtz"])).to(dev)
+    seed = synth.SEEDS["large_poisson" if poisson else "large_helmholtz"]
+    f = torch.from_numpy(synth.uniform_field(mesh.ndof, seed)).to(dev)
     x = torch.zeros_like(f)
     o = dg.default_opts(precision=dg.DG_MIXED)
-    dg.helmholtz_solve(mesh, lam, None, 1.0, f, x, o)
+
+    def solve():
+        if poisson:
+            return dg.poisson_solve(mesh, f, x, o)
+        return dg.helmholtz_solve(mesh, lam, None, 1.0, f, x, o)
+
+    solve()
     torch.cuda.synchronize()
     ts = []
-    for _ in range(5):
+    for _ in range(1 if poisson else 5):
         t0 = time.perf_counter()
-        info = dg.helmholtz_solve(mesh, lam, None, 1.0, f, x, o)
+        info = solve()
         ts.append(time.perf_counter() - t0)
     mesh.destroy()
     t = float(np.median(ts))
@@ -251,6 +266,9 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--quick", action="store_true", help="apply only (for profiling runs)")
+    ap.add_argument("--legs", default="all",
+                    help="comma-separated legs after the apply: solve, poisson, solve_mixed, "
+                         "poisson_mixed, mixed_small, batched, serving (default all)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=60,
                     help="prefix of the 2000-request stream replayed per serving mode")
@@ -305,19 +323,29 @@ def main():
                      "kernel_avg_us": avg * 1e6, "kernel_min_us": float(durs.min()) * 1e6,
                      "algorithmic_bytes_per_launch": APPLY_BYTES_PER_DOF_FP64 * N},
     }
+    legs = set(("solve", "poisson", "solve_mixed", "poisson_mixed", "mixed_small", "batched", "serving")
+               if args.legs == "all" else args.legs.split(","))
     if not args.quick:
-        log("FP64 Helmholtz solve")
-        out["solve"] = bench_solve(dg, torch, spec, lam, synth.SEEDS["large_helmholtz"], reps=5)
-        log("Poisson solve")
-        out["poisson"] = bench_solve(dg, torch, spec, 0.0, synth.SEEDS["large_poisson"], reps=1,
-                                     poisson=True)
-        log("mixed-precision Helmholtz solve (same mesh)")
-        out["solve_mixed"] = bench_mixed_large(dg, torch, spec, lam)
-        log("mixed-precision small solves")
-        out["mixed_small"] = bench_mixed_small(dg, torch)
-        log("batched stage solve")
-        out["batched"] = bench_batched(dg, torch)
-        if args.serving_requests > 0:
+        if "solve" in legs:
+            log("FP64 Helmholtz solve")
+            out["solve"] = bench_solve(dg, torch, spec, lam, synth.SEEDS["large_helmholtz"], reps=5)
+        if "poisson" in legs:
+            log("Poisson solve")
+            out["poisson"] = bench_solve(dg, torch, spec, 0.0, synth.SEEDS["large_poisson"], reps=1,
+                                         poisson=True)
+        if "solve_mixed" in legs:
+            log("mixed-precision Helmholtz solve (same mesh)")
+            out["solve_mixed"] = bench_mixed_large(dg, torch, spec, lam)
+        if "poisson_mixed" in legs:
+            log("mixed-precision Poisson solve (same mesh)")
+            out["poisson_mixed"] = bench_mixed_large(dg, torch, spec, 0.0, poisson=True)
+        if "mixed_small" in legs:
+            log("mixed-precision small solves")
+            out["mixed_small"] = bench_mixed_small(dg, torch)
+        if "batched" in legs:
+            log("batched stage solve")
+            out["batched"] = bench_batched(dg, torch)
+        if args.serving_requests > 0 and "serving" in legs:
             out["serving"] = {}
             for name, slots, prec in (("fifo_fp64", 1, dg.DG_FP64), ("continuous_fp64", 8, dg.DG_FP64),
                                       ("continuous_mixed", 8, dg.DG_MIXED)):

@@ -51,18 +51,34 @@ def counter(db, name, pattern, grid=None):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--trace", required=True)
-    ap.add_argument("--fetch", required=True)
-    ap.add_argument("--write", required=True)
+    ap.add_argument("--fetch", help="FETCH_SIZE pass (omit for a trace-only summary)")
+    ap.add_argument("--write", help="WRITE_SIZE pass (omit for a trace-only summary)")
     ap.add_argument("--kernel", required=True)
     ap.add_argument("--calib", default="__amd_rocclr_copyBuffer")
     ap.add_argument("--calib-grid", type=int, default=131072)
     ap.add_argument("--calib-bytes", type=float, default=float(1 << 30))
-    ap.add_argument("--algo-bytes", type=float, required=True)
+    ap.add_argument("--algo-bytes", type=float, default=0.0)
     ap.add_argument("--cmd", action="append", default=[])
     ap.add_argument("--title", default="rocprofv3 summary")
     a = ap.parse_args()
 
     allk, sel = trace_stats(a.trace, a.kernel)
+    if not (a.fetch and a.write):
+        print("# %s" % a.title)
+        print()
+        print("Commands (from the repository root):")
+        print()
+        for c in a.cmd:
+            print("    " + c)
+        print()
+        print("## Kernel trace (rocprofv3 --kernel-trace --stats)")
+        print()
+        print("| kernel | calls | total us | average us | % |")
+        print("|---|---|---|---|---|")
+        for name, calls, tot, avg, pct in allk[:16]:
+            short = name if len(name) < 90 else name[:87] + "..."
+            print("| `%s` | %d | %.1f | %.2f | %.1f |" % (short, calls, tot, avg, pct))
+        return
     fk = counter(a.fetch, "FETCH_SIZE", a.kernel) * 1024.0
     wk = counter(a.write, "WRITE_SIZE", a.kernel) * 1024.0
     fc = counter(a.fetch, "FETCH_SIZE", a.calib, a.calib_grid) * 1024.0
