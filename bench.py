@@ -20,7 +20,7 @@ Also reported on the same JSON line (each measured after the timed steps):
   mixed_small   FP64 vs mixed on the 4^3, P=7 case, lambda in {1e2,1e4,1e6}
   batched       the 24^3, P=5 stage (3 velocity + 1 pressure) in one
                 persistent launch vs the same 4 systems solved one after the
-                other by the plain FP64 solver
+                other by the plain FP64 solver (and by the mixed solver)
   serving       the request stream (Poisson arrivals), p50/p99 latency
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
@@ -218,22 +218,30 @@ def bench_batched(dg, torch):
     rc, infos = dg.helmholtz_solve_batched(mesh, lams, nus, pois, fs, xs, o)
     tb = time.perf_counter() - t0
     o64 = dg.default_opts()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    seq = []
-    for k in range(4):
-        if pois[k]:
-            seq.append(dg.poisson_solve(mesh, fs[k], xs[k], o64))
-        else:
-            seq.append(dg.helmholtz_solve(mesh, lam, nu, 0.0, fs[k], xs[k], o64))
-    ts = time.perf_counter() - t0
+
+    def sequential(o):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        seq = []
+        for k in range(4):
+            if pois[k]:
+                seq.append(dg.poisson_solve(mesh, fs[k], xs[k], o))
+            else:
+                seq.append(dg.helmholtz_solve(mesh, lam, nu, 0.0, fs[k], xs[k], o))
+        return time.perf_counter() - t0, seq
+
+    ts, seq = sequential(o64)
+    tm, seqm = sequential(o)
     mesh.destroy()
     return dict(ndof_per_field=N, batched_seconds=tb, batched_solves_per_s=4.0 / tb,
                 sequential_fp64_seconds=ts, sequential_fp64_solves_per_s=4.0 / ts,
+                sequential_mixed_seconds=tm, sequential_mixed_solves_per_s=4.0 / tm,
                 speedup=ts / tb, status=rc,
                 inner_iters=[i["iters"] for i in infos], outer_iters=[i["outer_iters"] for i in infos],
                 true_rel_res=[i["true_rel_res"] for i in infos],
-                fp64_iters=[i["iters"] for i in seq])
+                fp64_iters=[i["iters"] for i in seq],
+                sequential_mixed_iters=[i["iters"] for i in seqm],
+                sequential_mixed_true_rel_res=[i["true_rel_res"] for i in seqm])
 
 
 def bench_serving(dg, nreq, slots, precision, budget=96 << 30):

@@ -410,13 +410,18 @@ struct Lds {
 // part; the caller provides the LDS buffers xs, ys [EB*E3], nus [EB*E3 if
 // NUF] and geo [EB]).  red receives this thread's share of the epilogue
 // sums (EPI_CG: x.y, sum y; EPI_RESID: sum (r/M)^2, sum r, sum r/M^2,
-// sum 1/M^2).
-template <int P, typename T, bool NUF, int EPI>
+// sum 1/M^2).  EBX: elements per group (default: the kernels' group size;
+// a smaller EBX lets a caller run the apply in less LDS, the group index
+// then counting groups of EBX elements).  LAZY: load each direction's
+// neighbour lines just before its sweep instead of all up front (fewer
+// registers, less latency overlap).
+template <int P, typename T, bool NUF, int EPI, int EBX = Shape<P>::EB, bool LAZY = false>
 __device__ __forceinline__ void apply_group(const ApplyArgs<T> &A, int grp, T *xs, T *ys, T *nus,
                                             ElGeo<T> *geo, double (&red)[4])
 {
     using S = Shape<P>;
-    constexpr int n = S::n, NL = S::NL, N3 = S::N3, EB = S::EB, NT = S::NT;
+    constexpr int n = S::n, NL = S::NL, N3 = S::N3, EB = EBX, NT = EBX * NL;
+    static_assert(EBX >= 1 && EBX <= S::EB, "group size");
     constexpr int SB = Lds<P>::SB, SC = Lds<P>::SC, E3 = Lds<P>::E3;
     red[0] = red[1] = red[2] = red[3] = 0.0;
     const int tid = threadIdx.x;
@@ -447,9 +452,11 @@ __device__ __forceinline__ void apply_group(const ApplyArgs<T> &A, int grp, T *x
     if (active) {
 #pragma unroll
         for (int c = 0; c < n; ++c) uz[c] = xe[c * NL + l];
-        load_nb<P, T, NUF>(A, el, ex, nx, A.geo.bc[0], 1, j * NL + i * n, 1, fx);
-        load_nb<P, T, NUF>(A, el, ey, ny, A.geo.bc[1], nx, j * NL + i, n, fy);
-        load_nb<P, T, NUF>(A, el, ez, nz, A.geo.bc[2], nx * ny, l, NL, fz);
+        if constexpr (!LAZY) {
+            load_nb<P, T, NUF>(A, el, ex, nx, A.geo.bc[0], 1, j * NL + i * n, 1, fx);
+            load_nb<P, T, NUF>(A, el, ey, ny, A.geo.bc[1], nx, j * NL + i, n, fy);
+            load_nb<P, T, NUF>(A, el, ez, nz, A.geo.bc[2], nx * ny, l, NL, fz);
+        }
         // the element's geometry (every thread loads it, one writes it)
         const int ke[3] = {ex, ey, ez};
         ElGeo<T> g;
@@ -479,6 +486,7 @@ __device__ __forceinline__ void apply_group(const ApplyArgs<T> &A, int grp, T *x
 
     // phase B: x-lines (b=i, c=j)
     if (active) {
+        if constexpr (LAZY) load_nb<P, T, NUF>(A, el, ex, nx, A.geo.bc[0], 1, j * NL + i * n, 1, fx);
         T u[n], nl[n], out[n];
 #pragma unroll
         for (int a = 0; a < n; ++a) {
@@ -494,6 +502,7 @@ __device__ __forceinline__ void apply_group(const ApplyArgs<T> &A, int grp, T *x
 
     // phase C: y-lines (a=i, c=j)
     if (active) {
+        if constexpr (LAZY) load_nb<P, T, NUF>(A, el, ey, ny, A.geo.bc[1], nx, j * NL + i, n, fy);
         T u[n], nl[n], out[n];
 #pragma unroll
         for (int b = 0; b < n; ++b) {
@@ -509,6 +518,7 @@ __device__ __forceinline__ void apply_group(const ApplyArgs<T> &A, int grp, T *x
 
     // phase D: z-lines (a=i, b=j), mass term, epilogue
     if (active) {
+        if constexpr (LAZY) load_nb<P, T, NUF>(A, el, ez, nz, A.geo.bc[2], nx * ny, l, NL, fz);
         T out[n];
         T vs;
         const ElGeo<T> &G = geo[el_loc];

@@ -8,13 +8,13 @@ namespace dg {
 
 constexpr int kMaxBatch = 8;
 constexpr int kBatchMaxBlocks = 4096;           // resident work-groups at most
-constexpr int kBatchNC = 6;                     // reduction components per system and phase
+constexpr int kBatchNC = 8;                     // reduction components per system and phase
 constexpr int kBatchSlots = kBatchNC * kMaxBatch;
 
 struct BatchSysDesc {
     double *x64, *b64, *r64;            // solution (caller), load, FP64 residual
     const double *rhs, *nu64;           // right-hand side, FP64 nu field or null
-    void *xi, *ri, *pi, *qi, *di;       // inner-precision CG vectors (di = 1/diag)
+    void *xi, *ri, *pi, *qi, *ui, *si, *di;  // inner-precision CG vectors (di = 1/diag)
     const void *nui;                    // inner-precision nu field or null
     double lambda;
     int bc[3];

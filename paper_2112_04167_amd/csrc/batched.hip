@@ -81,6 +81,7 @@ struct BarCtx {
     unsigned nxa;    // XCDs holding work-groups
     unsigned gen;    // barrier generation
     int parity;      // partial-sum buffer in use
+    int err;         // a wait of this work-group gave up (spin limit or error flag)
 };
 
 __device__ __forceinline__ unsigned hw_xcc_id()
@@ -128,6 +129,7 @@ __device__ void grid_register(SyncArea *sa, BarCtx &bc, cgrp::grid_group &grid)
         bc.nxa = n;
         bc.gen = 0;
         bc.parity = 0;
+        bc.err = 0;
     }
     __syncthreads();
 }
@@ -163,7 +165,7 @@ __device__ void grid_reduce(SyncArea *sa, double *part, BarCtx &bc, const double
                 __hip_atomic_store(&sb->gflag[0], gen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
-        spin_ne(&sb->gflag[0], gen, sb->err);
+        if (!spin_ne(&sb->gflag[0], gen, sb->err)) bc.err = 1;
         acquire_agent();
         bc.gen = gen + 1;
         bc.parity = par ^ 1;
@@ -201,7 +203,7 @@ template <typename TI>
 struct BSys {
     double *x64, *b64, *r64;
     const double *rhs, *nu64;
-    TI *x, *r, *p, *q;
+    TI *x, *r, *p, *q, *u, *s;  // q holds w = A u
     const TI *d;  // 1 / diag(A_TI)
     const TI *nu;
     double lambda;
@@ -231,32 +233,46 @@ struct BArgs {
 struct SysSt {
     double bnorm2, tol2, res64;
     double mean_b;              // singular: mean removed from the load
-    double s, s_new;            // inner scaling (power of two): true = s * stored
-    double rho, alpha, pfac;    // CG scalars (pfac: coefficient of p in the p-update)
+    double s, s_new, s_old;     // inner scaling (power of two): true = s * stored
+    double gamma, alpha, coef;  // r.u of the step that made p, its alpha, and the
+                                // coefficient of the old p and s in the next update
+    double gamma_fresh;         // r.u right after a replacement
+    double us, ps;              // right after a replacement: u.s, p.s (old p, s)
+    double mw, sum_u;           // singular: mean of w = A u removed from s; sum u
     double res2, ref2;          // recurrence ||M^-1 r||^2 (scaled), at the last replacement
-    double mean_r, mean64;      // singular: means removed from r (inner / FP64)
+    double mean64;              // singular: mean removed from the FP64 residual
     double sum_invd, sum_invM2; // singular: sum 1/diag, sum 1/M^2
     double shift;
     int status, done, iters, replaced, repl;
+    int fresh;                  // 2: just set up, 1: just replaced, 0: in the recurrence
 };
 
-template <int P>
+// Group sizes: the inner-precision phases use the kernels' groups of EB
+// elements; the FP64 residual of an FP32 solve uses groups of EBH elements so
+// that its LDS fits in the FP32 buffers (it runs rarely).
+template <int P, typename TI>
+struct BShape {
+    static constexpr int EB = Shape<P>::EB;
+    static constexpr int EBH = sizeof(TI) == 8 ? EB : (EB + 1) / 2;
+    static constexpr int E3 = Lds<P>::E3;
+    static constexpr size_t VB = (size_t)EB * E3 * sizeof(TI) > (size_t)EBH * E3 * 8
+                                     ? (size_t)EB * E3 * sizeof(TI)
+                                     : (size_t)EBH * E3 * 8;
+    static constexpr size_t GB = EB * sizeof(ElGeo<TI>) > EBH * sizeof(ElGeo<double>)
+                                     ? EB * sizeof(ElGeo<TI>)
+                                     : EBH * sizeof(ElGeo<double>);
+};
+
+template <int P, typename TI>
 struct BLds {
-    static constexpr int EB = Shape<P>::EB, E3 = Lds<P>::E3;
-    double xs[EB * E3], ys[EB * E3], nus[EB * E3];
-    ElGeo<double> geo[EB];
+    using BS = BShape<P, TI>;
+    alignas(16) unsigned char xs[BS::VB], ys[BS::VB], nus[BS::VB];
+    alignas(16) unsigned char geo[BS::GB];
     double sh[16 * 16];
     double acc[kBatchSlots];
     double tot[kBatchSlots];
 };
 
-// waves per SIMD asked of the compiler: the FP32 instantiation is capped so
-// that its (frequent) FP32 phases keep the occupancy of the stand-alone FP32
-// kernels; the rare FP64 residual may spill there.
-template <int P, typename TI>
-struct BatchOcc {
-    static constexpr int W = sizeof(TI) == 4 ? (P <= 6 ? 4 : 3) : 1;
-};
 
 __device__ __forceinline__ double pow2_near(double v)
 {
@@ -283,6 +299,24 @@ __device__ __forceinline__ void group_nodes(int grp, int nel, const Geo<double> 
         f((size_t)el * S::N3 + (size_t)c * S::NL + l, Jw * kGll<P>.w[c], iJw * (1.0 / kGll<P>.w[c]));
 }
 
+// the same per line: f(index of node (a,b,0) of the thread's line, 1/(J w_a w_b));
+// the caller walks c = 0..P (stride (P+1)^2), loading all values of the line
+// before storing any, so that the loads are in flight together
+template <int P, typename F>
+__device__ __forceinline__ void group_lines(int grp, int nel, const Geo<double> &g, F &&f)
+{
+    using S = Shape<P>;
+    const int tid = threadIdx.x;
+    const int el_loc = tid / S::NL;
+    const int l = tid - el_loc * S::NL;
+    const int el = grp * S::EB + el_loc;
+    if (tid >= S::NT || el >= nel) return;
+    const int ex = el % g.n[0], r = el / g.n[0], ey = r % g.n[1], ez = r / g.n[1];
+    const double Jw = g.h[0][ex] * g.h[1][ey] * g.h[2][ez] * 0.125 * kGll<P>.w[l % S::n] *
+                      kGll<P>.w[l / S::n];
+    f((size_t)el * S::N3 + l, 1.0 / Jw);
+}
+
 template <typename T>
 __device__ __forceinline__ ApplyArgs<T> sys_apply_args(const Geo<T> &g, const int *bc, int nel, int G,
                                                        const int *order, const T *x, T *y,
@@ -304,14 +338,16 @@ __device__ __forceinline__ ApplyArgs<T> sys_apply_args(const Geo<T> &g, const in
 }
 
 template <int P, typename TI>
-__global__ void __launch_bounds__(Shape<P>::NTP, (BatchOcc<P, TI>::W)) k_batched(BArgs<TI> B)
+__device__ __forceinline__ void batched_body(BArgs<TI> &B)
 {
     using S = Shape<P>;
-    __shared__ BLds<P> L;
+    using BS = BShape<P, TI>;
+    __shared__ BLds<P, TI> L;
     __shared__ SysSt st[kMaxBatch];
     __shared__ BarCtx bc;
     __shared__ int list[kMaxBatch];
     __shared__ int nlist;
+    __shared__ int sh_flag;
     cgrp::grid_group grid = cgrp::this_grid();
     const int tid = threadIdx.x;
     const int G = B.ngroups, nel = B.nel, ns = B.nsys;
@@ -394,13 +430,13 @@ __global__ void __launch_bounds__(Shape<P>::NTP, (BatchOcc<P, TI>::W)) k_batched
         }
     });
 
-    // ---- set-up 2: project b (singular); inner r = b / s, x = 0, p = z = r/diag
+    // ---- set-up 2: project b (singular); inner r = b / s, u = r/diag, x = p = s = 0
     n = make_list([](const SysSt &y) { return !y.done; });
     clear_acc();
     items(n, [&](int slot, int s, int g) {
         const BSys<TI> &Y = B.sys[s];
         const double mb = st[s].mean_b, is = 1.0 / st[s].s;
-        double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         group_nodes<P>(g, nel, B.g64, [&](size_t gi, double, double im) {
             double bb = Y.b64[gi];
             if (Y.singular) {
@@ -408,27 +444,32 @@ __global__ void __launch_bounds__(Shape<P>::NTP, (BatchOcc<P, TI>::W)) k_batched
                 Y.b64[gi] = bb;
             }
             const TI r = (TI)(bb * is);
-            const TI z = r * Y.d[gi];
+            const TI u = r * Y.d[gi];
             Y.r[gi] = r;
+            Y.u[gi] = u;
             Y.x[gi] = (TI)0;
-            Y.p[gi] = z;
+            Y.p[gi] = (TI)0;
+            Y.s[gi] = (TI)0;
             const double rm = bb * im, rs = (double)r * im;
             v[0] += rm * rm;
             v[1] += im * im;
             v[2] += (double)Y.d[gi];
-            v[3] += (double)r * (double)z;
+            v[3] += (double)r * (double)u;
             v[4] += rs * rs;
+            v[5] += (double)u;
         });
         add_acc(v, slot);
     });
-    reduce(n, 5, [&](SysSt &y, int, const double *t) {
+    reduce(n, 6, [&](SysSt &y, int, const double *t) {
         y.bnorm2 = t[0];
         y.res64 = t[0];
         y.tol2 = B.tol * B.tol * t[0];
         y.sum_invM2 = t[1];
         y.sum_invd = t[2];
-        y.rho = t[3];
+        y.gamma = t[3];
         y.res2 = y.ref2 = t[4];
+        y.sum_u = t[5];
+        y.fresh = 2;  // no previous direction
         if (!isfinite(t[0]) || !isfinite(t[3])) {
             y.status = DG_ERR_NONFINITE;
             y.done = 1;
@@ -437,79 +478,144 @@ __global__ void __launch_bounds__(Shape<P>::NTP, (BatchOcc<P, TI>::W)) k_batched
         }
     });
 
+    // Jacobi-PCG with one reduction per iteration (the Chronopoulos-Gear
+    // arrangement): one element-wise phase (new direction p = u + beta p,
+    // s = A p by the same recurrence, x, r, and u = r/diag), then w = A u.
+    // The dot products of both phases are reduced together: gamma = r.u,
+    // ||M^-1 r||^2, and the pieces of (p', A p') = (p', s') for the next
+    // direction p' = u + beta' p, s' = w + beta' s, taken from the actual
+    // vectors (u.w, u.s, p.s; p.w = u.s by symmetry) rather than from the
+    // orthogonality relations of the textbook recurrence, which decay in
+    // FP32.  An iteration costs one grid-wide reduction and one plain barrier.
     for (;;) {
-        if (ld_agent(B.sa->sb.err)) break;  // a barrier wait gave up (uniform after any barrier)
+        // bc.err: a barrier wait of this work-group gave up; the others find
+        // the device flag in their own waits
         n = make_list([](const SysSt &y) { return !y.done; });
-        if (n == 0) break;
-
-        // ---- q = A p; p.q, sum q
+        if (n == 0 || bc.err) break;
         clear_acc();
+
+        // ---- p = u + beta p, s = (w - mean w) + beta s, x += alpha p,
+        //      r -= alpha s, u = r/diag; gamma, ||M^-1 r||^2, sum u
+        //      (systems just set up or replaced start at w = A u)
+        bool any_e = false;
+        if (tid == 0) {
+            int k = 0;
+            for (int i = 0; i < n; ++i) k += st[list[i]].fresh ? 0 : 1;
+            sh_flag = k;
+        }
+        __syncthreads();
+        any_e = sh_flag > 0;
+        if (any_e) {
+            items(n, [&](int slot, int s, int g) {
+                if (st[s].fresh) return;
+                const BSys<TI> &Y = B.sys[s];
+                const TI alpha = (TI)st[s].alpha, beta = (TI)st[s].coef, mw = (TI)st[s].mw;
+                double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                group_lines<P>(g, nel, B.g64, [&](size_t base, double iJw) {
+                    constexpr int n = S::n, NL = S::NL;
+                    TI uv[n], pv[n], wv[n], sv[n], xv[n], rv[n], dv[n];
+#pragma unroll
+                    for (int c = 0; c < n; ++c) {
+                        const size_t gi = base + (size_t)c * NL;
+                        uv[c] = Y.u[gi];
+                        pv[c] = Y.p[gi];
+                        wv[c] = Y.q[gi];
+                        sv[c] = Y.s[gi];
+                        xv[c] = Y.x[gi];
+                        rv[c] = Y.r[gi];
+                        dv[c] = Y.d[gi];
+                    }
+#pragma unroll
+                    for (int c = 0; c < n; ++c) {
+                        const size_t gi = base + (size_t)c * NL;
+                        const TI p = fma(beta, pv[c], uv[c]);
+                        const TI sd = fma(beta, sv[c], wv[c] - mw);
+                        const TI r = fma(-alpha, sd, rv[c]);
+                        const TI u = r * dv[c];
+                        Y.p[gi] = p;
+                        Y.s[gi] = sd;
+                        Y.x[gi] = fma(alpha, p, xv[c]);
+                        Y.r[gi] = r;
+                        Y.u[gi] = u;
+                        const double rm = (double)r * (iJw * (1.0 / kGll<P>.w[c]));
+                        v[0] += (double)r * (double)u;
+                        v[1] += rm * rm;
+                        v[2] += (double)u;
+                        v[3] += (double)u * (double)sd;
+                        v[4] += (double)p * (double)sd;
+                    }
+                });
+                add_acc(v, slot);
+            });
+            barrier();
+        }
+
+        // ---- w = A u; w.u, sum w
         items(n, [&](int slot, int s, int g) {
             const BSys<TI> &Y = B.sys[s];
-            ApplyArgs<TI> a = sys_apply_args<TI>(B.gi, Y.bc, nel, G, B.order, Y.p, Y.q, Y.nu, Y.lambda, nullptr);
+            ApplyArgs<TI> a = sys_apply_args<TI>(B.gi, Y.bc, nel, G, B.order, Y.u, Y.q, Y.nu, Y.lambda, nullptr);
             double red[4];
             if (Y.nu)
                 apply_group<P, TI, true, EPI_CG>(a, g, xs, ys, nus, geo, red);
             else
                 apply_group<P, TI, false, EPI_CG>(a, g, xs, ys, nus, geo, red);
-            double v[2] = {red[0], red[1]};
+            double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, red[0], red[1]};
             add_acc(v, slot);
         });
-        reduce(n, 2, [&](SysSt &y, int, const double *t) {
-            if (!isfinite(t[0])) {
-                y.status = DG_ERR_NONFINITE;
-                y.done = 1;
-            } else if (!(t[0] > 0.0)) {
-                y.status = DG_ERR_NOT_SPD;
-                y.done = 1;
+        reduce(n, 7, [&](SysSt &y, int s, const double *t) {
+            // t: [0] r.u [1] ||M^-1 r||^2 [2] sum u [3] u.s [4] p.s (this
+            //    step's element-wise phase; after a set-up or a replacement
+            //    they come from that phase) [5] u.w [6] sum w
+            double g1, r2, su, us, ps;
+            if (y.fresh) {
+                g1 = y.fresh == 1 ? y.gamma_fresh : y.gamma;
+                r2 = y.res2;
+                su = y.sum_u;
+                us = y.us;
+                ps = y.ps;
             } else {
-                y.alpha = y.rho / t[0];
+                g1 = t[0];
+                r2 = t[1] < 0.0 ? 0.0 : t[1];
+                su = t[2];
+                us = t[3];
+                ps = t[4];
+                y.iters += 1;
             }
-        });
-
-        // ---- x += alpha p, r -= alpha q; sums for rho' and ||M^-1 r||
-        n = make_list([](const SysSt &y) { return !y.done; });
-        clear_acc();
-        items(n, [&](int slot, int s, int g) {
-            const BSys<TI> &Y = B.sys[s];
-            const TI alpha = (TI)st[s].alpha;
-            double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-            group_nodes<P>(g, nel, B.g64, [&](size_t gi, double, double im) {
-                Y.x[gi] = fma(alpha, Y.p[gi], Y.x[gi]);
-                const TI r = fma(-alpha, Y.q[gi], Y.r[gi]);
-                Y.r[gi] = r;
-                const double rd = (double)r * (double)Y.d[gi];
-                const double rm = (double)r * im;
-                v[0] += (double)r;
-                v[1] += (double)r * rd;
-                v[2] += rd;
-                v[3] += rm * rm;
-                v[4] += rm * im;
-            });
-            add_acc(v, slot);
-        });
-        reduce(n, 5, [&](SysSt &y, int s, const double *t) {
-            double rz = t[1], res2 = t[3], mr = 0.0;
-            if (B.sys[s].singular) {
-                mr = t[0] / N;
-                rz = t[1] - 2.0 * mr * t[2] + mr * mr * y.sum_invd;
-                res2 = t[3] - 2.0 * mr * t[4] + mr * mr * y.sum_invM2;
-            }
-            if (res2 < 0.0) res2 = 0.0;
-            y.iters += 1;
-            y.mean_r = mr;
-            if (!isfinite(rz) || !isfinite(res2)) {
+            const double mw = B.sys[s].singular ? t[6] / N : 0.0;
+            // with w - mean w; p.(A u) = u.(A p) = u.s (s: the recurrence for A p)
+            const double uw = t[5] - mw * su, pw = us;
+            if (!isfinite(g1) || !isfinite(r2) || !isfinite(uw)) {
                 y.status = DG_ERR_NONFINITE;
                 y.done = 1;
                 return;
             }
-            y.res2 = res2;
-            if (res2 * y.s * y.s <= y.tol2 || res2 <= B.delta * B.delta * y.ref2 || y.iters >= B.maxit) {
-                y.repl = 1;  // flush, FP64 residual, replace (the p-update follows it)
-            } else {
-                y.pfac = rz / y.rho;
-                y.rho = rz;
+            if (!y.fresh) {
+                y.res2 = r2;
+                if (r2 * y.s * y.s <= y.tol2 || r2 <= B.delta * B.delta * y.ref2 || y.iters >= B.maxit) {
+                    y.repl = 1;  // keep gamma of the step that made p
+                    return;
+                }
             }
+            // coefficient of the old p and s (still in the scaling of the
+            // previous replacement) in p' = u + c p, s' = (w - mean w) + c s
+            double coef = 0.0;
+            if (y.fresh == 1)
+                coef = (g1 / y.gamma) * (y.s / y.s_old);
+            else if (!y.fresh)
+                coef = g1 / y.gamma;
+            // (p', A p') = (p', s') from this step's vectors
+            const double den = uw + coef * (us + pw) + coef * coef * ps;
+            if (!(den > 0.0)) {
+                y.status = DG_ERR_NOT_SPD;
+                y.done = 1;
+                return;
+            }
+            y.alpha = g1 / den;
+            y.coef = coef;
+            y.gamma = g1;
+            y.mw = mw;
+            y.sum_u = su;
+            y.fresh = 0;
         });
 
         n = make_list([](const SysSt &y) { return !y.done && y.repl; });
@@ -518,25 +624,47 @@ __global__ void __launch_bounds__(Shape<P>::NTP, (BatchOcc<P, TI>::W)) k_batched
             items(n, [&](int, int s, int g) {
                 const BSys<TI> &Y = B.sys[s];
                 const double sc = st[s].s;
-                group_nodes<P>(g, nel, B.g64, [&](size_t gi, double, double) {
-                    Y.x64[gi] = fma(sc, (double)Y.x[gi], Y.x64[gi]);
-                    Y.x[gi] = (TI)0;
+                group_lines<P>(g, nel, B.g64, [&](size_t base, double) {
+                    constexpr int n = S::n, NL = S::NL;
+                    double xd[n];
+                    TI xv[n];
+#pragma unroll
+                    for (int c = 0; c < n; ++c) {
+                        xd[c] = Y.x64[base + (size_t)c * NL];
+                        xv[c] = Y.x[base + (size_t)c * NL];
+                    }
+#pragma unroll
+                    for (int c = 0; c < n; ++c) {
+                        Y.x64[base + (size_t)c * NL] = fma(sc, (double)xv[c], xd[c]);
+                        Y.x[base + (size_t)c * NL] = (TI)0;
+                    }
                 });
             });
             barrier();
             // ---- FP64 residual r_64 = b - A_64 x_64 and the stopping test
             clear_acc();
-            items(n, [&](int slot, int s, int g) {
-                const BSys<TI> &Y = B.sys[s];
-                ApplyArgs<double> a = sys_apply_args<double>(B.g64, Y.bc, nel, G, B.order, Y.x64, Y.r64,
-                                                             Y.nu64, Y.lambda, Y.b64);
-                double red[4];
-                if (Y.nu64)
-                    apply_group<P, double, true, EPI_RESID>(a, g, L.xs, L.ys, L.nus, L.geo, red);
-                else
-                    apply_group<P, double, false, EPI_RESID>(a, g, L.xs, L.ys, L.nus, L.geo, red);
-                add_acc(red, slot);
-            });
+            {
+                constexpr int EBH = BS::EBH;
+                const int GH = (nel + EBH - 1) / EBH;
+                double *xd = reinterpret_cast<double *>(L.xs), *yd = reinterpret_cast<double *>(L.ys),
+                       *nd = reinterpret_cast<double *>(L.nus);
+                ElGeo<double> *gd = reinterpret_cast<ElGeo<double> *>(L.geo);
+                for (int w = blockIdx.x; w < n * GH; w += gridDim.x) {
+                    const int slot = w / GH;
+                    const int s = __builtin_amdgcn_readfirstlane(list[slot]);
+                    int g = xcd_remap(w % GH, GH);
+                    if (EBH == S::EB && B.order) g = B.order[g];
+                    const BSys<TI> &Y = B.sys[s];
+                    ApplyArgs<double> a = sys_apply_args<double>(B.g64, Y.bc, nel, GH, nullptr, Y.x64,
+                                                                 Y.r64, Y.nu64, Y.lambda, Y.b64);
+                    double red[4];
+                    if (Y.nu64)
+                        apply_group<P, double, true, EPI_RESID, EBH, true>(a, g, xd, yd, nd, gd, red);
+                    else
+                        apply_group<P, double, false, EPI_RESID, EBH, true>(a, g, xd, yd, nd, gd, red);
+                    add_acc(red, slot);
+                }
+            }
             reduce(n, 4, [&](SysSt &y, int s, const double *t) {
                 double res = t[0], m = 0.0;
                 if (B.sys[s].singular) {
@@ -562,61 +690,52 @@ __global__ void __launch_bounds__(Shape<P>::NTP, (BatchOcc<P, TI>::W)) k_batched
             });
             n = make_list([](const SysSt &y) { return !y.done && y.repl; });
             if (n > 0) {
-                // ---- replace: r_TI = (r_64 - mean) / s_new, z = r/diag
+                // ---- replace: r_TI = (r_64 - mean) / s_new, u = r/diag
                 clear_acc();
                 items(n, [&](int slot, int s, int g) {
                     const BSys<TI> &Y = B.sys[s];
                     const double m = st[s].mean64, is = 1.0 / st[s].s_new;
-                    double v[4] = {0.0, 0.0, 0.0, 0.0};
-                    group_nodes<P>(g, nel, B.g64, [&](size_t gi, double, double im) {
-                        const TI r = (TI)((Y.r64[gi] - m) * is);
-                        Y.r[gi] = r;
-                        const double z = (double)r * (double)Y.d[gi];
-                        const double rm = (double)r * im;
-                        v[0] += (double)r * z;
-                        v[1] += rm * rm;
-                        v[2] += (double)r;
-                        v[3] += z;
+                    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+                    group_lines<P>(g, nel, B.g64, [&](size_t base, double iJw) {
+                        constexpr int n = S::n, NL = S::NL;
+                        double rr[n];
+                        TI dv[n], pv[n], sv[n];
+#pragma unroll
+                        for (int c = 0; c < n; ++c) {
+                            rr[c] = Y.r64[base + (size_t)c * NL];
+                            dv[c] = Y.d[base + (size_t)c * NL];
+                            pv[c] = Y.p[base + (size_t)c * NL];
+                            sv[c] = Y.s[base + (size_t)c * NL];
+                        }
+#pragma unroll
+                        for (int c = 0; c < n; ++c) {
+                            const TI r = (TI)((rr[c] - m) * is);
+                            const TI u = r * dv[c];
+                            Y.r[base + (size_t)c * NL] = r;
+                            Y.u[base + (size_t)c * NL] = u;
+                            const double rm = (double)r * (iJw * (1.0 / kGll<P>.w[c]));
+                            v[0] += (double)r * (double)u;
+                            v[1] += rm * rm;
+                            v[2] += (double)u;
+                            v[3] += (double)u * (double)sv[c];
+                            v[4] += (double)pv[c] * (double)sv[c];
+                        }
                     });
                     add_acc(v, slot);
                 });
-                reduce(n, 4, [&](SysSt &y, int s, const double *t) {
-                    double rz = t[0], mr = 0.0;
-                    if (B.sys[s].singular) {
-                        mr = t[2] / N;
-                        rz = t[0] - 2.0 * mr * t[3] + mr * mr * y.sum_invd;
-                    }
-                    y.mean_r = mr;
-                    y.pfac = (rz / y.rho) * (y.s_new / y.s);
-                    y.rho = rz;
-                    y.s = y.s_new;
+                reduce(n, 5, [&](SysSt &y, int, const double *t) {
+                    y.gamma_fresh = t[0];
                     y.res2 = y.ref2 = t[1];
+                    y.sum_u = t[2];
+                    y.us = t[3];
+                    y.ps = t[4];
+                    y.s_old = y.s;
+                    y.s = y.s_new;
                     y.repl = 0;
-                    if (!isfinite(rz)) {
-                        y.status = DG_ERR_NONFINITE;
-                        y.done = 1;
-                    }
+                    y.fresh = 1;
                 });
             }
         }
-
-        // ---- (singular: r -= mean r)  p = r/diag + pfac p
-        n = make_list([](const SysSt &y) { return !y.done; });
-        items(n, [&](int, int s, int g) {
-            const BSys<TI> &Y = B.sys[s];
-            const TI pf = (TI)st[s].pfac;
-            const double mr = st[s].mean_r;
-            const bool sing = Y.singular;
-            group_nodes<P>(g, nel, B.g64, [&](size_t gi, double, double) {
-                TI r = Y.r[gi];
-                if (sing) {
-                    r = (TI)((double)r - mr);
-                    Y.r[gi] = r;
-                }
-                Y.p[gi] = fma(pf, Y.p[gi], r * Y.d[gi]);
-            });
-        });
-        barrier();
     }
 
     // ---- singular systems: remove the M-weighted mean of x
@@ -632,7 +751,7 @@ __global__ void __launch_bounds__(Shape<P>::NTP, (BatchOcc<P, TI>::W)) k_batched
         __syncthreads();
         n = nlist;
     }
-    if (n > 0 && !ld_agent(B.sa->sb.err)) {
+    if (n > 0 && !bc.err) {
         clear_acc();
         items(n, [&](int slot, int s, int g) {
             const BSys<TI> &Y = B.sys[s];
@@ -663,16 +782,40 @@ __global__ void __launch_bounds__(Shape<P>::NTP, (BatchOcc<P, TI>::W)) k_batched
         }
 }
 
+// The FP32 instantiation asks for the occupancy of the stand-alone FP32
+// apply (4 waves/SIMD), so that its frequent FP32 phases keep it; its rare
+// FP64 residual phase loads neighbour lines lazily to fit that budget.
+template <int P>
+__global__ void __launch_bounds__(Shape<P>::NTP, 4) k_batched_f32(BArgs<float> B)
+{
+    batched_body<P, float>(B);
+}
+
+template <int P>
+__global__ void __launch_bounds__(Shape<P>::NTP) k_batched_f64(BArgs<double> B)
+{
+    batched_body<P, double>(B);
+}
+
+template <int P, typename TI>
+const void *kernel_ptr()
+{
+    if constexpr (sizeof(TI) == 4)
+        return reinterpret_cast<const void *>(&k_batched_f32<P>);
+    else
+        return reinterpret_cast<const void *>(&k_batched_f64<P>);
+}
+
 template <typename TI>
 const void *kernel_for(int P)
 {
     switch (P) {
-        case 3: return reinterpret_cast<const void *>(&k_batched<3, TI>);
-        case 4: return reinterpret_cast<const void *>(&k_batched<4, TI>);
-        case 5: return reinterpret_cast<const void *>(&k_batched<5, TI>);
-        case 6: return reinterpret_cast<const void *>(&k_batched<6, TI>);
-        case 7: return reinterpret_cast<const void *>(&k_batched<7, TI>);
-        case 8: return reinterpret_cast<const void *>(&k_batched<8, TI>);
+        case 3: return kernel_ptr<3, TI>();
+        case 4: return kernel_ptr<4, TI>();
+        case 5: return kernel_ptr<5, TI>();
+        case 6: return kernel_ptr<6, TI>();
+        case 7: return kernel_ptr<7, TI>();
+        case 8: return kernel_ptr<8, TI>();
     }
     return nullptr;
 }
@@ -717,6 +860,8 @@ void fill_args(BArgs<TI> &B, const MeshDev &m, const BatchRequest &req)
         Y.r = (TI *)D.ri;
         Y.p = (TI *)D.pi;
         Y.q = (TI *)D.qi;
+        Y.u = (TI *)D.ui;
+        Y.s = (TI *)D.si;
         Y.d = (const TI *)D.di;
         Y.nu = (const TI *)D.nui;
         Y.lambda = D.lambda;

@@ -480,7 +480,7 @@ size_t batched_footprint(const MeshDev &m, int precision, int nsys)
     const size_t N = (size_t)m.ndof;
     const size_t ti = precision == DG_FP64 ? sizeof(double) : sizeof(float);
     size_t b = 0;
-    b += (size_t)nsys * (2 * align256(N * sizeof(double)) + 6 * align256(N * ti));
+    b += (size_t)nsys * (2 * align256(N * sizeof(double)) + 8 * align256(N * ti));
     b += align256(batched_partial_doubles() * sizeof(double));
     b += align256(batched_sync_bytes()) + align256(batched_result_bytes());
     return b;
@@ -544,6 +544,8 @@ int solve_batched(dg_mesh *m, int nsys, const double *lambdas, const double *con
         D.ri = take(N * ti);
         D.pi = take(N * ti);
         D.qi = take(N * ti);
+        D.ui = take(N * ti);
+        D.si = take(N * ti);
         D.di = take(N * ti);
         void *nui = take(N * ti);
         const bool pois = is_poisson && is_poisson[k];
