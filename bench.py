@@ -257,13 +257,30 @@ def bench_serving(dg, nreq, slots, precision, budget=96 << 30):
             time.sleep(wait)
         ids.append(srv.submit(r["n"], r["P"], r["lam"], None, is_poisson=r["poisson"],
                               rhs_seed=r["rhs_seed"], precision=precision))
+    # wait for the backlog, reporting progress
+    last = time.perf_counter()
+    while srv.stats()["completed"] < len(ids) and time.perf_counter() - t0 < 3600.0:
+        time.sleep(0.2)
+        if time.perf_counter() - last > 30.0:
+            last = time.perf_counter()
+            log("  serving: %d / %d done after %.0f s" % (srv.stats()["completed"], len(ids),
+                                                          last - t0))
     srv.drain()
     st = srv.stats()
-    bad = [i for i in ids if srv.poll(i)[0] != 0]
+    bad = []
+    for r, i in zip(stream, ids):
+        try:
+            rc, info = srv.poll(i)
+        except dg.DGError as e:
+            rc, info = e.status, dict(iters=-1, outer_iters=-1, true_rel_res=-1.0)
+        if rc != 0:
+            bad.append(dict(id=r["id"], status=rc, n=r["n"], P=r["P"], poisson=r["poisson"],
+                            lam=r["lam"], iters=info["iters"], outer=info["outer_iters"],
+                            rel_res=info["true_rel_res"]))
     srv.destroy()
     ndof = sum(r["n"] ** 3 * (r["P"] + 1) ** 3 for r in stream)
     st.update(requests=nreq, slots=slots, precision="mixed" if precision else "fp64",
-              solves_per_s=nreq / st["makespan"], failed=len(bad),
+              solves_per_s=nreq / st["makespan"], failed=len(bad), failures=bad[:20],
               offered_per_s=nreq / max(stream[-1]["t_arrival"], 1e-9), mean_ndof=ndof / nreq)
     return st
 
@@ -280,6 +297,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=60,
                     help="prefix of the 2000-request stream replayed per serving mode")
+    ap.add_argument("--serving-modes", default="fifo_fp64,continuous_fp64,continuous_mixed",
+                    help="serving modes to replay")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -357,6 +376,8 @@ def main():
             out["serving"] = {}
             for name, slots, prec in (("fifo_fp64", 1, dg.DG_FP64), ("continuous_fp64", 8, dg.DG_FP64),
                                       ("continuous_mixed", 8, dg.DG_MIXED)):
+                if name not in args.serving_modes.split(","):
+                    continue
                 log("serving:", name)
                 out["serving"][name] = bench_serving(dg, args.serving_requests, slots, prec)
         if not args.no_cpu:
