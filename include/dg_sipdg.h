@@ -89,7 +89,8 @@ typedef struct {
 } dg_solve_opts;
 
 typedef struct {
-    int iters;            /* CG iterations (mixed: FP32 iterations) */
+    int iters;            /* CG iterations (mixed: FP32 iterations, plus FP64 iterations if the
+                             solve continued in FP64 because the FP32 cycles stalled) */
     int outer_iters;      /* mixed: FP64 residual evaluations (replacements); 0 in FP64 mode */
     int status;
     double rel_res;       /* recurrence residual at exit (FP64: CG recurrence) */

@@ -287,8 +287,69 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_ir_replace(CgVecArgs<float> A
     publish_partials<4>(red, A.partial, gridDim.x, sh);
 }
 
+// FP64 CG restarted from a given residual (the continuation of a mixed solve
+// whose FP32 recurrence stalls): r = r - mean_r (singular), p = r/diag; sums
+// for rho = r.p, ||M^-1 r||^2, sum 1/diag, sum 1/M^2.  x keeps its value.
+template <int P, bool SING>
+__global__ void __launch_bounds__(Shape<P>::NTP) k_restart64(CgVecArgs<double> A)
+{
+    using S = Shape<P>;
+    __shared__ double sh[16 * 4];
+    const LineCtx<P, double> c = line_ctx<P, double>(A);
+    const double mr = A.sc->mean_r;
+    double red[4] = {0.0, 0.0, 0.0, 0.0};
+    if (c.active) {
+        double rv[S::n], dv[S::n];
+#pragma unroll
+        for (int k = 0; k < S::n; ++k) {
+            rv[k] = A.r[c.base + (size_t)k * S::NL];
+            dv[k] = A.d[c.base + (size_t)k * S::NL];
+        }
+#pragma unroll
+        for (int k = 0; k < S::n; ++k) {
+            const size_t gi = c.base + (size_t)k * S::NL;
+            const double r = SING ? rv[k] - mr : rv[k];
+            if (SING) A.r[gi] = r;
+            const double z = r * dv[k];
+            A.p[gi] = z;
+            const double im = c.iJw * inv_w<P>(k);
+            const double rm = r * im;
+            red[0] += r * z;
+            red[1] += rm * rm;
+            red[2] += dv[k];
+            red[3] += im * im;
+        }
+    }
+    publish_partials<4>(red, A.partial, gridDim.x, sh);
+}
+
+__global__ void __launch_bounds__(1024) k_finish_restart64(const double *partial, int nblk, CgScalars *sc)
+{
+    __shared__ double sh[16 * 4];
+    double t[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) t[c] = sum_strided(partial + (size_t)c * nblk, nblk);
+    block_sum<4>(t, sh);
+    if (threadIdx.x != 0) return;
+    sc->rho = t[0];
+    sc->res2 = t[1];
+    sc->sum_invd = t[2];
+    sc->sum_invM2 = t[3];
+    sc->mean_r = 0.0;
+    sc->iter = 0;
+    sc->status = DG_OK;
+    sc->done = 0;
+    if (!isfinite(t[0]) || !isfinite(t[1])) {
+        sc->status = DG_ERR_NONFINITE;
+        sc->done = 1;
+    } else if (t[1] <= sc->tol2) {
+        sc->done = 1;
+    }
+}
+
 __global__ void __launch_bounds__(1024) k_finish_replace(const double *partial, int nblk, CgScalars *in,
-                                                        CgScalars *out, double delta2, int restart)
+                                                        CgScalars *out, double delta2, int restart,
+                                                        int maxit)
 {
     __shared__ double sh[16 * 4];
     double t[4];
@@ -312,6 +373,7 @@ __global__ void __launch_bounds__(1024) k_finish_replace(const double *partial, 
     in->tol2 = delta2 * t[1] > floor2 ? delta2 * t[1] : floor2;
     in->status = DG_OK;
     in->done = 0;
+    in->maxit = maxit;
     if (!isfinite(rz) || !isfinite(t[1])) {
         in->status = DG_ERR_NONFINITE;
         in->done = 1;
@@ -553,14 +615,28 @@ int ir_to_inner(const MeshDev &m, CgVecArgs<float> a, hipStream_t s)
 }
 
 int ir_replace(const MeshDev &m, CgVecArgs<float> a, CgScalars *inner, double delta2, bool restart,
-               hipStream_t s)
+               int maxit, hipStream_t s)
 {
     prep(m, a);
     return with_P(m.P, [&](auto PC) {
         constexpr int P = decltype(PC)::value;
         hipLaunchKernelGGL((k_ir_replace<P>), DG_GRID(PC), 0, s, a);
         hipLaunchKernelGGL(k_finish_replace, dim3(1), dim3(1024), 0, s, a.partial, apply_groups(P, m.nel),
-                           inner, a.sc, delta2, restart ? 1 : 0);
+                           inner, a.sc, delta2, restart ? 1 : 0, maxit);
+    });
+}
+
+int cg_restart64(const MeshDev &m, CgVecArgs<double> a, hipStream_t s)
+{
+    prep(m, a);
+    return with_P(m.P, [&](auto PC) {
+        constexpr int P = decltype(PC)::value;
+        with_bool(a.singular, [&](auto SC) {
+            constexpr bool SG = decltype(SC)::value;
+            hipLaunchKernelGGL((k_restart64<P, SG>), DG_GRID(PC), 0, s, a);
+        });
+        hipLaunchKernelGGL(k_finish_restart64, dim3(1), dim3(1024), 0, s, a.partial,
+                           apply_groups(P, m.nel), a.sc);
     });
 }
 

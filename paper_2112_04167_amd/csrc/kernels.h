@@ -111,8 +111,12 @@ int ir_accumulate(const MeshDev &m, CgVecArgs<float> a, hipStream_t s); // dst64
 // residual replacement of the inner CG: r = (src64 - mean_r)/scale_new, x = 0,
 // then (on inner) rho, beta = rho'/rho * scale_new/scale (0 if restart), the
 // replacement threshold tol2 = max(delta2 ||M^-1 r||^2, outer tol2/scale_new^2),
-// done = 0; finally scale = scale_new.  Follow with cg_pupdate.
+// the inner iteration cap maxit (counted from the first inner set-up), done =
+// 0; finally scale = scale_new.  Follow with cg_pupdate.
 int ir_replace(const MeshDev &m, CgVecArgs<float> a, CgScalars *inner, double delta2, bool restart,
-               hipStream_t s);
+               int maxit, hipStream_t s);
+// FP64 CG restarted from the residual in a.r (mean a.sc->mean_r removed if
+// singular): p = r/diag, rho, residual norm; a.sc->tol2 is kept.
+int cg_restart64(const MeshDev &m, CgVecArgs<double> a, hipStream_t s);
 
 }  // namespace dg

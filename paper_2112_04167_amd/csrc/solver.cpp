@@ -270,6 +270,10 @@ int solve_fp64(dg_mesh *m, const int bc[3], double lambda, const double *nu, dou
 // convergence); then the FP32 correction is added to the FP64 solution, the
 // FP64 residual is recomputed and tested, and the recurrence continues from
 // it with the same search direction (rescaled) instead of restarting.
+// When the FP32 recurrence is limited by its precision (kappa * eps_32 not
+// small) -- a cycle falls far short of its target, or needs more than three
+// times the iterations of the first cycle -- or the FP32 iteration cap is
+// reached, the solve continues as FP64 PCG from the current solution.
 int solve_mixed(dg_mesh *m, const int bc[3], double lambda, const double *nu, double nu_c,
                 const double *rhs, double *x, const dg_solve_opts &o, dg_solve_info &info)
 {
@@ -331,9 +335,13 @@ int solve_mixed(dg_mesh *m, const int bc[3], double lambda, const double *nu, do
     int status = hosc->status;
     double res2 = bnorm2;
     int outer = 0;
-    int inner_iters = 0;
+    int inner_iters = 0, fp64_iters = 0;
+    bool fp64_continue = false;
+    double cycle_start = bnorm2;  // ||M^-1 r||^2 at the start of the FP32 cycle
+    int first_cycle = -1;         // FP32 iterations of the first cycle
     ia.r = w.r32;
     while (status == DG_OK && bnorm2 > 0.0 && res2 > tol2) {
+        const int iters_before = inner_iters;
         if ((rc = cg_iterate<float>(m, bc, lambda, nu32, nu_c, ca, isc, hisc, o.inner_maxit))) return rc;
         inner_iters = hisc->iter;
         const int istat = hisc->status;
@@ -341,6 +349,7 @@ int solve_mixed(dg_mesh *m, const int bc[3], double lambda, const double *nu, do
             status = istat;
             break;
         }
+        if (first_cycle < 0) first_cycle = inner_iters - iters_before;
         // x64 += scale * x32 ; r64 = b - A64 x64 (projected), ||M^-1 r||
         CgVecArgs<float> acc = vec_args<float>(w, singular, osc);
         acc.x = w.x32;
@@ -358,14 +367,44 @@ int solve_mixed(dg_mesh *m, const int bc[3], double lambda, const double *nu, do
             break;
         }
         if (res2 <= tol2) break;
-        if (outer >= o.maxit || inner_iters >= o.inner_maxit) {
+        const double target = std::max(o.inner_tol * o.inner_tol * cycle_start, tol2);
+        if (res2 > 25.0 * target || istat == DG_NOT_CONVERGED || inner_iters >= o.inner_maxit) {
+            fp64_continue = true;
+            break;
+        }
+        if (outer >= o.maxit) {
             status = DG_NOT_CONVERGED;
             break;
         }
+        cycle_start = res2;
         // replace the recurrence residual; a breakdown restarts the direction
         if ((rc = ir_scale(md, ia, s))) return rc;
-        if ((rc = ir_replace(md, ia, isc, o.inner_tol * o.inner_tol, istat == DG_ERR_NOT_SPD, s))) return rc;
+        const int cap = std::min<long long>(o.inner_maxit, (long long)inner_iters + std::max(3 * first_cycle, 50));
+        if ((rc = ir_replace(md, ia, isc, o.inner_tol * o.inner_tol, istat == DG_ERR_NOT_SPD, cap, s)))
+            return rc;
         if ((rc = cg_pupdate<float>(md, ca, s))) return rc;
+    }
+    if (fp64_continue && status == DG_OK) {
+        // FP64 PCG from x, starting at the residual r64 just computed
+        if ((rc = launch_diag<double>(md, bc, lambda, nu, nu_c, w.d64, s, true))) return rc;
+        CgVecArgs<double> fa = vec_args<double>(w, singular, osc);
+        fa.x = x;
+        fa.r = w.r64;
+        fa.p = w.p64;
+        fa.q = w.q64;
+        fa.d = w.d64;
+        if ((rc = cg_restart64(md, fa, s))) return rc;
+        if ((rc = cg_iterate<double>(m, bc, lambda, nu, nu_c, fa, osc, hosc, o.maxit))) return rc;
+        fp64_iters = hosc->iter;
+        status = hosc->status;
+        if (!singular && status >= 0) {
+            if ((rc = launch_resid<double>(md, bc, lambda, nu, nu_c, x, w.b64, w.r64, w.partial,
+                                           w.counter, osc, s)))
+                return rc;
+            DG_HIP_CHECK(hipMemcpyAsync(hosc, osc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
+            DG_HIP_CHECK(hipStreamSynchronize(s));
+            res2 = hosc->true_res2;
+        }
     }
     if (singular && status >= 0) {
         if ((rc = cg_finish<double>(md, oa, s))) return rc;
@@ -376,7 +415,7 @@ int solve_mixed(dg_mesh *m, const int bc[3], double lambda, const double *nu, do
         DG_HIP_CHECK(hipStreamSynchronize(s));
         res2 = hosc->true_res2;
     }
-    info.iters = inner_iters;
+    info.iters = inner_iters + fp64_iters;
     info.outer_iters = outer;
     info.status = status;
     info.rel_res = bnorm2 > 0 ? std::sqrt(res2 / bnorm2) : 0.0;

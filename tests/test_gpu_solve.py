@@ -211,6 +211,26 @@ def test_mixed_precision_small(lam):
     assert e <= 1e-9
 
 
+def test_mixed_precision_fp64_continuation():
+    # an FP32 iteration budget too small to converge forces the continuation
+    # in FP64 from the current solution; the result is held to the same rule
+    spec = make_spec((3, 3, 3), 5, (0, 0, 0), False)
+    lam = 1.0
+    f = synth.uniform_field(ndof(spec), 77)
+    x, info = gpu_solve(spec, lam, 1.0, f, precision=1, inner_maxit=10)
+    say("mixed -> fp64", info)
+    assert info["status"] == 0 and info["iters"] > 10 and info["outer_iters"] >= 1
+    M = dense.mass_diag(spec)
+    op = naive.Operator(spec, lam, 1.0)
+    assert pcg.true_rel_res(op.apply, x, M * f, M) <= 1.2e-10
+    assert rel(x, kron.FDM(spec, lam).solve(M * f)) <= 1e-9
+    # the singular (Poisson) path of the continuation
+    xp, infop = gpu_solve(spec, 0.0, 1.0, f, poisson=True, precision=1, inner_maxit=10)
+    assert infop["status"] == 0
+    assert pcg.true_rel_res(naive.Operator(spec, 0.0, 1.0).apply, xp, M * f, M, singular=True) <= 1.2e-10
+    assert abs(np.dot(M, xp)) <= 1e-12 * np.linalg.norm(xp)
+
+
 def test_mixed_precision_poisson():
     spec = make_spec((3, 3, 3), 5, (0, 1, 0), False)
     f = synth.uniform_field(ndof(spec), 44)
