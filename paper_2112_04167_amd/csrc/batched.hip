@@ -555,10 +555,11 @@ __device__ __forceinline__ void batched_body(BArgs<TI> &B)
             const BSys<TI> &Y = B.sys[s];
             ApplyArgs<TI> a = sys_apply_args<TI>(B.gi, Y.bc, nel, G, B.order, Y.u, Y.q, Y.nu, Y.lambda, nullptr);
             double red[4];
+            constexpr bool LZ = apply_lazy<P, TI>();
             if (Y.nu)
-                apply_group<P, TI, true, EPI_CG>(a, g, xs, ys, nus, geo, red);
+                apply_group<P, TI, true, EPI_CG, S::EB, LZ>(a, g, xs, ys, nus, geo, red);
             else
-                apply_group<P, TI, false, EPI_CG>(a, g, xs, ys, nus, geo, red);
+                apply_group<P, TI, false, EPI_CG, S::EB, LZ>(a, g, xs, ys, nus, geo, red);
             double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, red[0], red[1]};
             add_acc(v, slot);
         });

@@ -61,7 +61,7 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_apply(ApplyArgs<T> A)
     const int slot = xcd_remap(blockIdx.x, A.ngroups);
     const int grp = A.order ? A.order[slot] : slot;
     double red[4];
-    apply_group<P, T, NUF, EPI>(A, grp, xs, ys, nus, geo, red);
+    apply_group<P, T, NUF, EPI, Shape<P>::EB, apply_lazy<P, T>()>(A, grp, xs, ys, nus, geo, red);
     if constexpr (EPI == EPI_CG) {
         double red2[2] = {red[0], red[1]};
         publish_partials<2>(red2, A.partial, gridDim.x, red_sh);
