@@ -319,11 +319,10 @@ struct ApplyArgs {
     int nel;
     int ngroups;
     const int *order;  // visiting order of the element groups (may be null)
-    // EPI_CG: partial dot x.y and sum(y); last group computes alpha.
+    // EPI_CG: partial dot x.y and sum(y) (finished by a separate kernel).
     // EPI_RESID: y = b - A x, partial sums of (y/M)^2 and y, (y/M) and 1/M^2 sums
     const T *b;
     double *partial;
-    unsigned *counter;
     CgScalars *sc;
 };
 

@@ -9,8 +9,10 @@
 //   update  x += alpha p, r -= alpha q, reductions  -> rho', beta, residual
 //   pupdate (singular: r -= mean r)  p = r/d + beta p
 //
-// All scalars live in device memory (CgScalars); the last work-group of each
-// reduction computes them, so no host round trip is needed per iteration.
+// All scalars live in device memory (CgScalars).  Each reducing kernel writes
+// per-work-group partial sums; a one-work-group kernel launched after it sums
+// them in a fixed order and updates the scalars, so no host round trip is
+// needed per iteration.
 // A solve that has finished (converged, iteration cap, breakdown) sets
 // `done` and every later CG kernel returns at once, which lets the host
 // enqueue iterations in chunks and read the state back rarely.

@@ -74,11 +74,8 @@ void mesh_lend_workspace(dg_mesh *m, void *dev, size_t bytes, void *host_sc);
 size_t solve_host_scalar_bytes();
 int64_t mesh_ndof(const dg_mesh *m);
 
-// --- kernel launchers (kernels_apply.hip) ---------------------------------
+// --- kernel launchers (kernels.hip) ----------------------------------------
 // y = A x; T = double or float; nu == nullptr -> constant nu_c.
-// If partial != nullptr each work-group writes (x.y partial, sum(y) partial)
-// into partial[2*blk] and the last group reduces them into red_out[0..1]
-// (FP64, fixed order), using counter (zeroed, reset after use).
 template <typename T>
 int launch_apply(const MeshDev &m, const int bc[3], double lambda, const T *nu, double nu_c,
                  const T *x, T *y, hipStream_t s);

@@ -7,7 +7,8 @@
 namespace dg {
 
 // Scalars of one CG solve, resident in device memory.  Written only by the
-// last work-group of a reduction (one thread), read by every later kernel.
+// one-work-group kernel that finishes a reduction (one thread), read by every
+// later kernel.
 struct CgScalars {
     double rho;        // r.z of the current iterate
     double rho_prev;   // r.z of the previous iterate (for a residual replacement)
@@ -29,7 +30,7 @@ struct CgScalars {
     int pad[2];
 };
 
-// Device helpers called by the last work-group of a reduction.
+// Device helpers called by the kernels that finish a reduction.
 __device__ inline void cg_after_apply(CgScalars *sc, double pq, double sumq)
 {
     sc->pq = pq;
@@ -66,11 +67,11 @@ int launch_finish_resid(double *partial, int nblk, CgScalars *sc, hipStream_t s)
 
 template <typename T>
 int launch_apply_cg(const MeshDev &m, const int bc[3], double lambda, const T *nu, double nu_c,
-                    const T *p, T *q, double *partial, unsigned *counter, CgScalars *sc,
+                    const T *p, T *q, double *partial, CgScalars *sc,
                     hipStream_t s);
 template <typename T>
 int launch_resid(const MeshDev &m, const int bc[3], double lambda, const T *nu, double nu_c,
-                 const T *x, const T *b, T *r, double *partial, unsigned *counter, CgScalars *sc,
+                 const T *x, const T *b, T *r, double *partial, CgScalars *sc,
                  hipStream_t s);
 int apply_threads(int P);
 
@@ -89,7 +90,6 @@ struct CgVecArgs {
     int weak;
     bool singular;      // host-side: selects the singular (projected) kernels
     double *partial;
-    unsigned *counter;
     CgScalars *sc;
 };
 

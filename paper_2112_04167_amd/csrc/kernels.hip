@@ -27,8 +27,8 @@
 //
 // CG kernels use the same element/line mapping so that the GLL mass and the
 // Jacobi diagonal are available per node without index divisions; dot
-// products are FP64 and reduced deterministically (per-group partials, the
-// last group to finish sums them in a fixed order).
+// products are FP64 and reduced deterministically (per-group partials,
+// summed in a fixed order by a one-work-group kernel launched after them).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -258,12 +258,11 @@ int launch_apply(const MeshDev &m, const int bc[3], double lambda, const T *nu, 
 
 template <typename T>
 int launch_apply_cg(const MeshDev &m, const int bc[3], double lambda, const T *nu, double nu_c,
-                    const T *p, T *q, double *partial, unsigned *counter, CgScalars *sc,
+                    const T *p, T *q, double *partial, CgScalars *sc,
                     hipStream_t s)
 {
     ApplyArgs<T> a = make_args<T>(m, bc, lambda, nu, nu_c, p, q);
     a.partial = partial;
-    a.counter = counter;
     a.sc = sc;
     if (int rc = dispatch_apply<T, EPI_CG>(m.P, a, nu != nullptr, s)) return rc;
     return launch_finish_apply(partial, a.ngroups, sc, s);
@@ -271,13 +270,12 @@ int launch_apply_cg(const MeshDev &m, const int bc[3], double lambda, const T *n
 
 template <typename T>
 int launch_resid(const MeshDev &m, const int bc[3], double lambda, const T *nu, double nu_c,
-                 const T *x, const T *b, T *r, double *partial, unsigned *counter, CgScalars *sc,
+                 const T *x, const T *b, T *r, double *partial, CgScalars *sc,
                  hipStream_t s)
 {
     ApplyArgs<T> a = make_args<T>(m, bc, lambda, nu, nu_c, x, r);
     a.b = b;
     a.partial = partial;
-    a.counter = counter;
     a.sc = sc;
     if (int rc = dispatch_apply<T, EPI_RESID>(m.P, a, nu != nullptr, s)) return rc;
     return launch_finish_resid(partial, a.ngroups, sc, s);
@@ -320,10 +318,10 @@ int launch_diag(const MeshDev &m, const int bc[3], double lambda, const T *nu, d
     template int launch_apply<T>(const MeshDev &, const int[3], double, const T *, double,      \
                                  const T *, T *, hipStream_t);                                   \
     template int launch_apply_cg<T>(const MeshDev &, const int[3], double, const T *, double,   \
-                                    const T *, T *, double *, unsigned *, CgScalars *,           \
+                                    const T *, T *, double *, CgScalars *,                       \
                                     hipStream_t);                                                \
     template int launch_resid<T>(const MeshDev &, const int[3], double, const T *, double,      \
-                                 const T *, const T *, T *, double *, unsigned *, CgScalars *,   \
+                                 const T *, const T *, T *, double *, CgScalars *,               \
                                  hipStream_t);                                                   \
     template int launch_diag<T>(const MeshDev &, const int[3], double, const T *, double, T *,  \
                                 hipStream_t, bool);

@@ -49,7 +49,6 @@ struct Workspace {
     float *x32 = nullptr, *r32 = nullptr, *p32 = nullptr, *q32 = nullptr, *d32 = nullptr,
           *b32 = nullptr, *nu32 = nullptr;
     double *partial = nullptr;
-    unsigned *counter = nullptr;
     CgScalars *sc = nullptr;      // [0] outer / FP64, [1] inner FP32
     CgScalars *host_sc = nullptr; // pinned
     bool external = false;        // memory lent by the caller (never freed here)
@@ -86,7 +85,7 @@ size_t footprint(const MeshDev &m, int precision)
     b += 5 * align256(N * sizeof(double));  // r, p, q, d, b (FP64)
     if (precision == DG_MIXED) b += 7 * align256(N * sizeof(float));
     b += align256(partial_doubles(m) * sizeof(double));
-    b += align256(256) + align256(2 * sizeof(CgScalars));
+    b += align256(2 * sizeof(CgScalars));
     return b;
 }
 
@@ -144,9 +143,7 @@ int ensure_workspace(dg_mesh *m, int precision)
         w.x32 = w.r32 = w.p32 = w.q32 = w.d32 = w.b32 = w.nu32 = nullptr;
     }
     w.partial = (double *)take(partial_doubles(m->dev) * 8);
-    w.counter = (unsigned *)take(256);
     w.sc = (CgScalars *)take(2 * sizeof(CgScalars));
-    DG_HIP_CHECK(hipMemsetAsync(w.counter, 0, 256, m->stream));
     return DG_OK;
 }
 
@@ -173,7 +170,6 @@ CgVecArgs<T> vec_args(const Workspace &w, bool singular, CgScalars *sc)
 {
     CgVecArgs<T> a{};
     a.partial = w.partial;
-    a.counter = w.counter;
     a.sc = sc;
     a.singular = singular;
     return a;
@@ -196,7 +192,7 @@ int cg_iterate(dg_mesh *m, const int bc[3], double lambda, const T *nu, double n
     for (;;) {
         for (int k = 0; k < chunk; ++k) {
             int rc = launch_apply_cg<T>(md, bc, lambda, nu, nu_c, a.p, const_cast<T *>(a.q),
-                                        a.partial, a.counter, dev_sc, s);
+                                        a.partial, dev_sc, s);
             if (rc) return rc;
             if ((rc = cg_update<T>(md, a, s))) return rc;
             if ((rc = cg_pupdate<T>(md, a, s))) return rc;
@@ -251,7 +247,7 @@ int solve_fp64(dg_mesh *m, const int bc[3], double lambda, const double *nu, dou
     if ((rc = cg_iterate<double>(m, bc, lambda, nu, nu_c, a, w.sc, w.host_sc, cap))) return rc;
     if ((rc = cg_finish<double>(md, a, s))) return rc;
     // true residual from x
-    if ((rc = launch_resid<double>(md, bc, lambda, nu, nu_c, x, w.b64, w.q64, w.partial, w.counter,
+    if ((rc = launch_resid<double>(md, bc, lambda, nu, nu_c, x, w.b64, w.q64, w.partial,
                                    w.sc, s)))
         return rc;
     DG_HIP_CHECK(hipMemcpyAsync(w.host_sc, w.sc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
@@ -356,7 +352,7 @@ int solve_mixed(dg_mesh *m, const int bc[3], double lambda, const double *nu, do
         acc.dst64 = x;
         if ((rc = ir_accumulate(md, acc, s))) return rc;
         if ((rc = launch_resid<double>(md, bc, lambda, nu, nu_c, x, w.b64, w.r64, w.partial,
-                                       w.counter, osc, s)))
+                                       osc, s)))
             return rc;
         DG_HIP_CHECK(hipMemcpyAsync(hosc, osc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
         DG_HIP_CHECK(hipStreamSynchronize(s));
@@ -399,7 +395,7 @@ int solve_mixed(dg_mesh *m, const int bc[3], double lambda, const double *nu, do
         status = hosc->status;
         if (!singular && status >= 0) {
             if ((rc = launch_resid<double>(md, bc, lambda, nu, nu_c, x, w.b64, w.r64, w.partial,
-                                           w.counter, osc, s)))
+                                           osc, s)))
                 return rc;
             DG_HIP_CHECK(hipMemcpyAsync(hosc, osc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
             DG_HIP_CHECK(hipStreamSynchronize(s));
@@ -409,7 +405,7 @@ int solve_mixed(dg_mesh *m, const int bc[3], double lambda, const double *nu, do
     if (singular && status >= 0) {
         if ((rc = cg_finish<double>(md, oa, s))) return rc;
         if ((rc = launch_resid<double>(md, bc, lambda, nu, nu_c, x, w.b64, w.r64, w.partial,
-                                       w.counter, osc, s)))
+                                       osc, s)))
             return rc;
         DG_HIP_CHECK(hipMemcpyAsync(hosc, osc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
         DG_HIP_CHECK(hipStreamSynchronize(s));
