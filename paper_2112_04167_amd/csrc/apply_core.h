@@ -374,6 +374,99 @@ __device__ __forceinline__ void load_nb(const ApplyArgs<T> &A, int el, int k, in
     f.nuR = nuR;
 }
 
+// x-neighbour lines of a work-group of consecutive elements.  A face whose
+// neighbour is the adjacent element of the same group (same row) is read from
+// LDS in phase B (in_lo / in_hi).  Of the other ends, at most one is read here
+// (the low one if it lies outside the group, else the high one) with an
+// unconditional load (a thread with no such end reads one address in every
+// lane), so it is in flight with the other neighbour lines; a second outside
+// end (a group starting at the last element of a row, or nx = 1) is flagged
+// in far_hi and read in phase B.  Inside a group only its two end elements
+// need a line from global memory, which saves most of this access's L1
+// traffic (its lanes touch one cache line each).
+template <int P, typename T, bool NUF>
+__device__ __forceinline__ void load_nb_x(const ApplyArgs<T> &A, int el, int ex, int nx, int el_loc,
+                                          int EB, int off, bool &in_lo, bool &in_hi, bool &far_hi,
+                                          LineNb<T> &f)
+{
+    constexpr int n = P + 1, N3 = n * n * n;
+    int kL, kR;
+    const int klo = face_kind(ex, nx, A.geo.bc[0], false, kL);
+    const int khi = face_kind(ex, nx, A.geo.bc[0], true, kR);
+    in_lo = klo == 1 && ex > 0 && el_loc > 0;
+    in_hi = khi == 1 && ex < nx - 1 && el_loc + 1 < EB;
+    const bool g_lo = klo == 1 && !in_lo, g_hi = khi == 1 && !in_hi;
+    far_hi = g_lo && g_hi;
+    size_t b = 0;
+    int st = 0;
+    if (g_lo) {
+        b = (size_t)(el + (kL - ex)) * N3 + off;
+        st = 1;
+    } else if (g_hi) {
+        b = (size_t)(el + (kR - ex)) * N3 + off;
+        st = 1;
+    }
+    T v[n];
+#pragma unroll
+    for (int q = 0; q < n; ++q) v[q] = A.x[b + q * st];
+    T nuN = A.nu_c;
+    if constexpr (NUF) nuN = A.nu[b + (g_lo ? P : 0)];
+    const EoTab<P, T> &tb = c_eo<P, T>;
+    T sP = 0, s0 = 0;
+#pragma unroll
+    for (int q = 0; q < n; ++q) {
+        sP = fma(tb.DP[q], v[q], sP);
+        s0 = fma(tb.D0[q], v[q], s0);
+    }
+    f.uL = g_lo ? v[P] : (T)0;
+    f.sL = g_lo ? sP : (T)0;
+    f.uR = (g_hi && !g_lo) ? v[0] : (T)0;
+    f.sR = (g_hi && !g_lo) ? s0 : (T)0;
+    f.nuL = g_lo ? nuN : A.nu_c;
+    f.nuR = (g_hi && !g_lo) ? nuN : A.nu_c;
+}
+
+// Phase B part of load_nb_x: the ends read from the neighbour slots' LDS
+// copies (xsl: this element's x-line (b=i, c=j) start, padded layout), and a
+// second outside end from global memory.
+template <int P, typename T, bool NUF>
+__device__ __forceinline__ void finish_nb_x(const ApplyArgs<T> &A, int el, int ex, int nx,
+                                            const T *xsl, const T *nsl, int E3, int off,
+                                            bool in_lo, bool in_hi, bool far_hi, LineNb<T> &f)
+{
+    constexpr int n = P + 1, N3 = n * n * n;
+    const EoTab<P, T> &tb = c_eo<P, T>;
+    if (in_lo) {
+        T v[n];
+#pragma unroll
+        for (int a = 0; a < n; ++a) v[a] = xsl[a - E3];
+        T s = 0;
+#pragma unroll
+        for (int a = 0; a < n; ++a) s = fma(tb.DP[a], v[a], s);
+        f.uL = v[P];
+        f.sL = s;
+        if constexpr (NUF) f.nuL = nsl[P - E3];
+    }
+    if (in_hi) {
+        T v[n];
+#pragma unroll
+        for (int a = 0; a < n; ++a) v[a] = xsl[a + E3];
+        T s = 0;
+#pragma unroll
+        for (int a = 0; a < n; ++a) s = fma(tb.D0[a], v[a], s);
+        f.uR = v[0];
+        f.sR = s;
+        if constexpr (NUF) f.nuR = nsl[E3];
+    }
+    if (far_hi) {
+        int kR;
+        face_kind(ex, nx, A.geo.bc[0], true, kR);
+        const size_t b = (size_t)(el + (kR - ex)) * N3 + off;
+        nb_line<P, T>(A.x + b, 1, 0, f.uR, f.sR);
+        if constexpr (NUF) f.nuR = A.nu[b];
+    }
+}
+
 // Per-element geometry shared through LDS: extents, reciprocals and the
 // ratios rho = h / h_N of every face neighbour.
 template <typename T>
@@ -458,11 +551,20 @@ __device__ __forceinline__ void apply_group(const ApplyArgs<T> &A, int grp, T *x
     // z-line (a=i,b=j)) are requested up front so their latency overlaps
     T uz[n], nz_l[n];
     LineNb<T> fx, fy, fz;
+    // FP64: group-internal x-neighbours from LDS (measured faster at every
+    // degree; for FP32, whose lines are half as many bytes, the extra LDS
+    // reads cost more than the saved loads)
+    constexpr bool XL = sizeof(T) == 8;
+    bool x_in_lo = false, x_in_hi = false, x_far_hi = false;
     if (active) {
 #pragma unroll
         for (int c = 0; c < n; ++c) uz[c] = xe[c * NL + l];
         if constexpr (!LAZY) {
-            load_nb<P, T, NUF>(A, el, ex, nx, A.geo.bc[0], 1, j * NL + i * n, 1, fx);
+            if constexpr (XL)
+                load_nb_x<P, T, NUF>(A, el, ex, nx, el_loc, EB, j * NL + i * n, x_in_lo, x_in_hi,
+                                     x_far_hi, fx);
+            else
+                load_nb<P, T, NUF>(A, el, ex, nx, A.geo.bc[0], 1, j * NL + i * n, 1, fx);
             load_nb<P, T, NUF>(A, el, ey, ny, A.geo.bc[1], nx, j * NL + i, n, fy);
             load_nb<P, T, NUF>(A, el, ez, nz, A.geo.bc[2], nx * ny, l, NL, fz);
         }
@@ -495,7 +597,15 @@ __device__ __forceinline__ void apply_group(const ApplyArgs<T> &A, int grp, T *x
 
     // phase B: x-lines (b=i, c=j)
     if (active) {
-        if constexpr (LAZY) load_nb<P, T, NUF>(A, el, ex, nx, A.geo.bc[0], 1, j * NL + i * n, 1, fx);
+        if constexpr (XL) {
+            if constexpr (LAZY)
+                load_nb_x<P, T, NUF>(A, el, ex, nx, el_loc, EB, j * NL + i * n, x_in_lo, x_in_hi,
+                                     x_far_hi, fx);
+            finish_nb_x<P, T, NUF>(A, el, ex, nx, xsl + i * SB + j * SC, nsl + i * SB + j * SC,
+                                   E3, j * NL + i * n, x_in_lo, x_in_hi, x_far_hi, fx);
+        } else if constexpr (LAZY) {
+            load_nb<P, T, NUF>(A, el, ex, nx, A.geo.bc[0], 1, j * NL + i * n, 1, fx);
+        }
         T u[n], nl[n], out[n];
 #pragma unroll
         for (int a = 0; a < n; ++a) {
