@@ -98,6 +98,19 @@ constexpr EoTab<P, T> make_eo_tab()
 template <int P, typename T>
 __constant__ EoTab<P, T> c_eo = make_eo_tab<P, T>();
 
+// The same table through a pointer the compiler cannot see through.  A
+// persistent loop that takes the table from here at each use re-reads the
+// entries with scalar loads close to where they are needed, instead of
+// hoisting every entry out of the loop and spilling the scalar registers that
+// hold them (each spilled value then costs a VALU readlane per use).
+template <int P, typename T>
+__device__ __forceinline__ const EoTab<P, T> &eo_fresh()
+{
+    auto p = (const __attribute__((address_space(4))) EoTab<P, T> *)&c_eo<P, T>;
+    asm volatile("" : "+s"(p));
+    return *(const EoTab<P, T> *)p;
+}
+
 // E, O halves of y = A u for the even-odd table M
 template <int P, typename T, int S>
 __device__ __forceinline__ void eo_apply(const EoMat<P, T> &M, const T (&u)[P + 1],
@@ -175,10 +188,10 @@ __device__ __forceinline__ void eo_combine(const T (&E)[(P + 2) / 2], const T (&
 // per line.
 template <int P, typename T>
 __device__ __forceinline__ void line_const(const T (&u)[P + 1], int klo, int khi, T rhoL, T rhoR,
-                                           T uL, T sL, T uR, T sR, T (&y)[P + 1])
+                                           T uL, T sL, T uR, T sR, T (&y)[P + 1],
+                                           const EoTab<P, T> &tb = c_eo<P, T>)
 {
     constexpr int n = P + 1, hh = (P + 2) / 2;
-    const EoTab<P, T> &tb = c_eo<P, T>;
     T E[hh], O[hh];
     eo_apply<P, T, 1>(tb.K0, u, E, O);
     const T halfpen = (T)(0.5 * n * n);
@@ -242,10 +255,10 @@ __device__ __forceinline__ void line_const(const T (&u)[P + 1], int klo, int khi
 template <int P, typename T>
 __device__ __forceinline__ void line_nodal(const T (&u)[P + 1], const T (&nl)[P + 1], int klo,
                                            int khi, T rhoL, T rhoR, T uL, T sL, T nuL, T uR, T sR,
-                                           T nuR, T (&y)[P + 1])
+                                           T nuR, T (&y)[P + 1],
+                                           const EoTab<P, T> &tb = c_eo<P, T>)
 {
     constexpr int n = P + 1, hh = (P + 2) / 2;
-    const EoTab<P, T> &tb = c_eo<P, T>;
     T E[hh], O[hh], t[n];
     eo_apply<P, T, -1>(tb.D, u, E, O);
     eo_combine<P, T, -1>(E, O, t);
@@ -279,13 +292,12 @@ __device__ __forceinline__ void line_nodal(const T (&u)[P + 1], const T (&nl)[P 
 // neighbour line: trace at `layer` and the raw derivative sum D_layer . v
 template <int P, typename T>
 __device__ __forceinline__ void nb_line(const T *__restrict__ base, int stride, int layer,
-                                        T &uN, T &sN)
+                                        T &uN, T &sN, const EoTab<P, T> &tb = c_eo<P, T>)
 {
     constexpr int n = P + 1;
     T v[n];
 #pragma unroll
     for (int k = 0; k < n; ++k) v[k] = base[k * stride];
-    const EoTab<P, T> &tb = c_eo<P, T>;
     T s = 0;
 #pragma unroll
     for (int k = 0; k < n; ++k) s = fma(layer == 0 ? tb.D0[k] : tb.DP[k], v[k], s);
@@ -340,7 +352,8 @@ struct LineNb {
 // discards it) so that all of them can be in flight at once.
 template <int P, typename T, bool NUF>
 __device__ __forceinline__ void load_nb(const ApplyArgs<T> &A, int el, int k, int nk, int bc,
-                                        int estr, int off, int ls, LineNb<T> &f)
+                                        int estr, int off, int ls, LineNb<T> &f,
+                                        const EoTab<P, T> &tb = c_eo<P, T>)
 {
     constexpr int n = P + 1, N3 = n * n * n;
     int kL, kR;
@@ -359,7 +372,6 @@ __device__ __forceinline__ void load_nb(const ApplyArgs<T> &A, int el, int k, in
         nuL = A.nu[bL + P * ls];
         nuR = A.nu[bR];
     }
-    const EoTab<P, T> &tb = c_eo<P, T>;
     T sL = 0, sR = 0;
 #pragma unroll
     for (int q = 0; q < n; ++q) {
@@ -387,7 +399,7 @@ __device__ __forceinline__ void load_nb(const ApplyArgs<T> &A, int el, int k, in
 template <int P, typename T, bool NUF>
 __device__ __forceinline__ void load_nb_x(const ApplyArgs<T> &A, int el, int ex, int nx, int el_loc,
                                           int EB, int off, bool &in_lo, bool &in_hi, bool &far_hi,
-                                          LineNb<T> &f)
+                                          LineNb<T> &f, const EoTab<P, T> &tb = c_eo<P, T>)
 {
     constexpr int n = P + 1, N3 = n * n * n;
     int kL, kR;
@@ -411,7 +423,6 @@ __device__ __forceinline__ void load_nb_x(const ApplyArgs<T> &A, int el, int ex,
     for (int q = 0; q < n; ++q) v[q] = A.x[b + q * st];
     T nuN = A.nu_c;
     if constexpr (NUF) nuN = A.nu[b + (g_lo ? P : 0)];
-    const EoTab<P, T> &tb = c_eo<P, T>;
     T sP = 0, s0 = 0;
 #pragma unroll
     for (int q = 0; q < n; ++q) {
@@ -432,10 +443,10 @@ __device__ __forceinline__ void load_nb_x(const ApplyArgs<T> &A, int el, int ex,
 template <int P, typename T, bool NUF>
 __device__ __forceinline__ void finish_nb_x(const ApplyArgs<T> &A, int el, int ex, int nx,
                                             const T *xsl, const T *nsl, int E3, int off,
-                                            bool in_lo, bool in_hi, bool far_hi, LineNb<T> &f)
+                                            bool in_lo, bool in_hi, bool far_hi, LineNb<T> &f,
+                                            const EoTab<P, T> &tb = c_eo<P, T>)
 {
     constexpr int n = P + 1, N3 = n * n * n;
-    const EoTab<P, T> &tb = c_eo<P, T>;
     if (in_lo) {
         T v[n];
 #pragma unroll
@@ -462,7 +473,7 @@ __device__ __forceinline__ void finish_nb_x(const ApplyArgs<T> &A, int el, int e
         int kR;
         face_kind(ex, nx, A.geo.bc[0], true, kR);
         const size_t b = (size_t)(el + (kR - ex)) * N3 + off;
-        nb_line<P, T>(A.x + b, 1, 0, f.uR, f.sR);
+        nb_line<P, T>(A.x + b, 1, 0, f.uR, f.sR, tb);
         if constexpr (NUF) f.nuR = A.nu[b];
     }
 }
@@ -480,7 +491,7 @@ template <int P, typename T, bool NUF>
 __device__ __forceinline__ void line_apply(const ApplyArgs<T> &A, const T (&u)[P + 1],
                                            const T (&nl)[P + 1], int d, int k, int nk,
                                            const ElGeo<T> &G, T wt, const LineNb<T> &f, T &vs,
-                                           T (&y)[P + 1])
+                                           T (&y)[P + 1], const EoTab<P, T> &tb = c_eo<P, T>)
 {
     int kL, kR;
     const int bc = A.geo.bc[d];
@@ -490,10 +501,10 @@ __device__ __forceinline__ void line_apply(const ApplyArgs<T> &A, const T (&u)[P
     vs = (T)0.5 * wt * G.h[t1] * G.h[t2] * G.ih[d];
     if constexpr (NUF) {
         line_nodal<P, T>(u, nl, klo, khi, G.rhoL[d], G.rhoR[d], f.uL, f.sL, f.nuL, f.uR, f.sR,
-                         f.nuR, y);
+                         f.nuR, y, tb);
     } else {
         vs *= A.nu_c;
-        line_const<P, T>(u, klo, khi, G.rhoL[d], G.rhoR[d], f.uL, f.sL, f.uR, f.sR, y);
+        line_const<P, T>(u, klo, khi, G.rhoL[d], G.rhoR[d], f.uL, f.sL, f.uR, f.sR, y, tb);
     }
 }
 
@@ -517,10 +528,18 @@ struct Lds {
 // then counting groups of EBX elements).  LAZY: load each direction's
 // neighbour lines just before its sweep instead of all up front (fewer
 // registers, less latency overlap).
-template <int P, typename T, bool NUF, int EPI, int EBX = Shape<P>::EB, bool LAZY = false>
+template <int P, typename T, bool NUF, int EPI, int EBX = Shape<P>::EB, bool LAZY = false,
+          bool FRESH = false>
 __device__ __forceinline__ void apply_group(const ApplyArgs<T> &A, int grp, T *xs, T *ys, T *nus,
                                             ElGeo<T> *geo, double (&red)[4])
 {
+    // the coefficient table, re-derived at each use inside a persistent loop
+    auto TB = []() -> const EoTab<P, T> & {
+        if constexpr (FRESH)
+            return eo_fresh<P, T>();
+        else
+            return c_eo<P, T>;
+    };
     using S = Shape<P>;
     constexpr int n = S::n, NL = S::NL, N3 = S::N3, EB = EBX, NT = EBX * NL;
     static_assert(EBX >= 1 && EBX <= S::EB, "group size");
@@ -562,11 +581,11 @@ __device__ __forceinline__ void apply_group(const ApplyArgs<T> &A, int grp, T *x
         if constexpr (!LAZY) {
             if constexpr (XL)
                 load_nb_x<P, T, NUF>(A, el, ex, nx, el_loc, EB, j * NL + i * n, x_in_lo, x_in_hi,
-                                     x_far_hi, fx);
+                                     x_far_hi, fx, TB());
             else
-                load_nb<P, T, NUF>(A, el, ex, nx, A.geo.bc[0], 1, j * NL + i * n, 1, fx);
-            load_nb<P, T, NUF>(A, el, ey, ny, A.geo.bc[1], nx, j * NL + i, n, fy);
-            load_nb<P, T, NUF>(A, el, ez, nz, A.geo.bc[2], nx * ny, l, NL, fz);
+                load_nb<P, T, NUF>(A, el, ex, nx, A.geo.bc[0], 1, j * NL + i * n, 1, fx, TB());
+            load_nb<P, T, NUF>(A, el, ey, ny, A.geo.bc[1], nx, j * NL + i, n, fy, TB());
+            load_nb<P, T, NUF>(A, el, ez, nz, A.geo.bc[2], nx * ny, l, NL, fz, TB());
         }
         // the element's geometry (every thread loads it, one writes it)
         const int ke[3] = {ex, ey, ez};
@@ -600,11 +619,11 @@ __device__ __forceinline__ void apply_group(const ApplyArgs<T> &A, int grp, T *x
         if constexpr (XL) {
             if constexpr (LAZY)
                 load_nb_x<P, T, NUF>(A, el, ex, nx, el_loc, EB, j * NL + i * n, x_in_lo, x_in_hi,
-                                     x_far_hi, fx);
+                                     x_far_hi, fx, TB());
             finish_nb_x<P, T, NUF>(A, el, ex, nx, xsl + i * SB + j * SC, nsl + i * SB + j * SC,
-                                   E3, j * NL + i * n, x_in_lo, x_in_hi, x_far_hi, fx);
+                                   E3, j * NL + i * n, x_in_lo, x_in_hi, x_far_hi, fx, TB());
         } else if constexpr (LAZY) {
-            load_nb<P, T, NUF>(A, el, ex, nx, A.geo.bc[0], 1, j * NL + i * n, 1, fx);
+            load_nb<P, T, NUF>(A, el, ex, nx, A.geo.bc[0], 1, j * NL + i * n, 1, fx, TB());
         }
         T u[n], nl[n], out[n];
 #pragma unroll
@@ -613,7 +632,7 @@ __device__ __forceinline__ void apply_group(const ApplyArgs<T> &A, int grp, T *x
             nl[a] = NUF ? nsl[a + i * SB + j * SC] : (T)0;
         }
         T vs;
-        line_apply<P, T, NUF>(A, u, nl, 0, ex, nx, geo[el_loc], wt, fx, vs, out);
+        line_apply<P, T, NUF>(A, u, nl, 0, ex, nx, geo[el_loc], wt, fx, vs, out, TB());
 #pragma unroll
         for (int a = 0; a < n; ++a) ysl[a + i * SB + j * SC] = vs * out[a];
     }
@@ -621,7 +640,8 @@ __device__ __forceinline__ void apply_group(const ApplyArgs<T> &A, int grp, T *x
 
     // phase C: y-lines (a=i, c=j)
     if (active) {
-        if constexpr (LAZY) load_nb<P, T, NUF>(A, el, ey, ny, A.geo.bc[1], nx, j * NL + i, n, fy);
+        if constexpr (LAZY)
+            load_nb<P, T, NUF>(A, el, ey, ny, A.geo.bc[1], nx, j * NL + i, n, fy, TB());
         T u[n], nl[n], out[n];
 #pragma unroll
         for (int b = 0; b < n; ++b) {
@@ -629,7 +649,7 @@ __device__ __forceinline__ void apply_group(const ApplyArgs<T> &A, int grp, T *x
             nl[b] = NUF ? nsl[i + b * SB + j * SC] : (T)0;
         }
         T vs;
-        line_apply<P, T, NUF>(A, u, nl, 1, ey, ny, geo[el_loc], wt, fy, vs, out);
+        line_apply<P, T, NUF>(A, u, nl, 1, ey, ny, geo[el_loc], wt, fy, vs, out, TB());
 #pragma unroll
         for (int b = 0; b < n; ++b) ysl[i + b * SB + j * SC] = fma(vs, out[b], ysl[i + b * SB + j * SC]);
     }
@@ -637,11 +657,12 @@ __device__ __forceinline__ void apply_group(const ApplyArgs<T> &A, int grp, T *x
 
     // phase D: z-lines (a=i, b=j), mass term, epilogue
     if (active) {
-        if constexpr (LAZY) load_nb<P, T, NUF>(A, el, ez, nz, A.geo.bc[2], nx * ny, l, NL, fz);
+        if constexpr (LAZY)
+            load_nb<P, T, NUF>(A, el, ez, nz, A.geo.bc[2], nx * ny, l, NL, fz, TB());
         T out[n];
         T vs;
         const ElGeo<T> &G = geo[el_loc];
-        line_apply<P, T, NUF>(A, uz, nz_l, 2, ez, nz, G, wt, fz, vs, out);
+        line_apply<P, T, NUF>(A, uz, nz_l, 2, ez, nz, G, wt, fz, vs, out, TB());
         const T Jw = G.h[0] * G.h[1] * G.h[2] * (T)0.125 * wt;
         const double iJw = EPI == EPI_RESID ? 1.0 / (double)Jw : 0.0;
         T *__restrict__ ye = A.y + (size_t)el * N3;

@@ -557,9 +557,9 @@ __device__ __forceinline__ void batched_body(BArgs<TI> &B)
             double red[4];
             constexpr bool LZ = apply_lazy<P, TI>();
             if (Y.nu)
-                apply_group<P, TI, true, EPI_CG, S::EB, LZ>(a, g, xs, ys, nus, geo, red);
+                apply_group<P, TI, true, EPI_CG, S::EB, LZ, true>(a, g, xs, ys, nus, geo, red);
             else
-                apply_group<P, TI, false, EPI_CG, S::EB, LZ>(a, g, xs, ys, nus, geo, red);
+                apply_group<P, TI, false, EPI_CG, S::EB, LZ, true>(a, g, xs, ys, nus, geo, red);
             double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, red[0], red[1]};
             add_acc(v, slot);
         });
@@ -660,9 +660,9 @@ __device__ __forceinline__ void batched_body(BArgs<TI> &B)
                                                                  Y.r64, Y.nu64, Y.lambda, Y.b64);
                     double red[4];
                     if (Y.nu64)
-                        apply_group<P, double, true, EPI_RESID, EBH, true>(a, g, xd, yd, nd, gd, red);
+                        apply_group<P, double, true, EPI_RESID, EBH, true, true>(a, g, xd, yd, nd, gd, red);
                     else
-                        apply_group<P, double, false, EPI_RESID, EBH, true>(a, g, xd, yd, nd, gd, red);
+                        apply_group<P, double, false, EPI_RESID, EBH, true, true>(a, g, xd, yd, nd, gd, red);
                     add_acc(red, slot);
                 }
             }
