@@ -101,6 +101,7 @@ def bench_solve(dg, torch, spec, lam, seed, reps, poisson=False):
     x = torch.zeros_like(f)
     times, infos = [], []
     for _ in range(reps):
+        x.zero_()  # x is the initial guess: every timed solve starts from zero
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         if poisson:
@@ -153,12 +154,16 @@ def bench_mixed_small(dg, torch, reps=20):
         row = {}
         for name, prec in (("fp64", dg.DG_FP64), ("mixed", dg.DG_MIXED)):
             o = dg.default_opts(precision=prec)
+            x.zero_()
             dg.helmholtz_solve(mesh, lam, None, 1.0, f, x, o)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
+            ts = []
             for _ in range(reps):
+                x.zero_()  # x is the initial guess: every timed solve starts from zero
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
                 info = dg.helmholtz_solve(mesh, lam, None, 1.0, f, x, o)
-            t = (time.perf_counter() - t0) / reps
+                ts.append(time.perf_counter() - t0)
+            t = float(np.median(ts))
             row[name] = dict(ms=t * 1e3, iters=info["iters"], outer=info["outer_iters"],
                              true_rel_res=info["true_rel_res"])
         out["lambda=%g" % lam] = row
@@ -183,9 +188,10 @@ def bench_mixed_large(dg, torch, spec, lam, poisson=False):
         return dg.helmholtz_solve(mesh, lam, None, 1.0, f, x, o)
 
     solve()
-    torch.cuda.synchronize()
     ts = []
     for _ in range(1 if poisson else 5):
+        x.zero_()  # x is the initial guess: every timed solve starts from zero
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         info = solve()
         ts.append(time.perf_counter() - t0)
@@ -220,6 +226,8 @@ def bench_batched(dg, torch):
     o64 = dg.default_opts()
 
     def sequential(o):
+        for xk in xs:
+            xk.zero_()  # x is the initial guess of the single solves: start from zero
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         seq = []

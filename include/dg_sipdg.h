@@ -138,8 +138,10 @@ int helmholtz_diag(dg_mesh *m, double lambda, const void *nu_field, double nu_co
    FP64 iterative refinement around FP32 Jacobi-PCG inner solves (DG_MIXED;
    FP64 residuals, updates and dot products).  lambda >= 0; nu_field: device
    double nodal viscosity or NULL for nu_const.  rhs: device double, the
-   nodal f (b = M f) unless opts->rhs_is_weak.  x: device double, output (the
-   initial guess is zero).  If lambda = 0 and the mesh has no Dirichlet axis
+   nodal f (b = M f) unless opts->rhs_is_weak.  x: device double, in: the
+   initial guess (the solve starts from r = b - A x; pass zeros for none),
+   out: the solution (if b = 0, x = 0 whatever the guess).  The stopping test
+   stays relative to ||M^-1 b||.  If lambda = 0 and the mesh has no Dirichlet axis
    the problem is singular: b is projected to mean zero and x is returned
    with M-weighted mean zero.  opts may be NULL (defaults), info may be NULL. */
 int helmholtz_solve(dg_mesh *m, double lambda, const double *nu_field, double nu_const,
@@ -148,7 +150,9 @@ int helmholtz_solve(dg_mesh *m, double lambda, const double *nu_field, double nu
 /* The pressure Poisson problem of the projection substep (Alg. 3): lambda = 0,
    nu = 1, and every Dirichlet axis of the mesh becomes a natural Neumann
    axis (the pressure carries Neumann data).  The system is then singular
-   (constants): rhs is projected, x is returned with M-weighted mean zero. */
+   (constants): rhs is projected, x is returned with M-weighted mean zero.
+   rhs, x (in: initial guess, out: solution), opts and info as in
+   helmholtz_solve. */
 int poisson_solve(dg_mesh *m, const double *rhs, double *x, const dg_solve_opts *opts,
                   dg_solve_info *info);
 
@@ -159,7 +163,8 @@ int poisson_solve(dg_mesh *m, const double *rhs, double *x, const dg_solve_opts 
    FP32 with FP64 residual replacement (as in helmholtz_solve), with DG_FP64
    it is FP64 throughout.  lambdas[i], nu_fields[i] (device double nodal or
    NULL for nu = 1), is_poisson[i] (1: lambda ignored, Poisson as in
-   poisson_solve), rhs[i], x[i] (device double, output).  infos[nsys] may be
+   poisson_solve), rhs[i], x[i] (device double, output only: the batched
+   solve starts every system from zero).  infos[nsys] may be
    NULL.  nsys <= 8.  The launch shape (resident work-groups per CU) is
    autotuned per (device, P, precision, nsys, mesh size) on first use.
    Returns the worst status over the systems; DG_ERR_DEVICE if the device

@@ -94,8 +94,10 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_setup1(CgVecArgs<T> A)
     publish_partials<2>(red, A.partial, gridDim.x, sh);
 }
 
-// set-up, stage 2: project b (singular), r = b, x = 0, z = r/d, p = z and the
-// initial norms.  d == nullptr: outer refinement loop (no z, p).
+// set-up, stage 2: project b (singular), r = b, x = 0 (unless keep_x: the
+// caller's initial guess stays, and the solver recomputes r = b - A x and
+// restarts from it), z = r/d, p = z and the initial norms.  d == nullptr:
+// outer refinement loop (no z, p).
 template <int P, typename T, bool SING>
 __global__ void __launch_bounds__(Shape<P>::NTP) k_setup2(CgVecArgs<T> A)
 {
@@ -114,7 +116,7 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_setup2(CgVecArgs<T> A)
                 A.bvec[gi] = b;
             }
             A.r[gi] = b;
-            A.x[gi] = (T)0;
+            if (!A.keep_x) A.x[gi] = (T)0;
             const double im = c.iJw * inv_w<P>(k);
             const double rm = (double)b * im;
             red[1] += rm * rm;
@@ -289,9 +291,10 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_ir_replace(CgVecArgs<float> A
     publish_partials<4>(red, A.partial, gridDim.x, sh);
 }
 
-// FP64 CG restarted from a given residual (the continuation of a mixed solve
-// whose FP32 recurrence stalls): r = r - mean_r (singular), p = r/diag; sums
-// for rho = r.p, ||M^-1 r||^2, sum 1/diag, sum 1/M^2.  x keeps its value.
+// FP64 CG restarted from a given residual (the start from the caller's
+// initial guess, and the continuation of a mixed solve whose FP32 recurrence
+// stalls): r = r - mean_r (singular), p = r/diag; sums for rho = r.p,
+// ||M^-1 r||^2, sum 1/diag, sum 1/M^2.  x keeps its value.
 template <int P, bool SING>
 __global__ void __launch_bounds__(Shape<P>::NTP) k_restart64(CgVecArgs<double> A)
 {
@@ -344,7 +347,7 @@ __global__ void __launch_bounds__(1024) k_finish_restart64(const double *partial
     if (!isfinite(t[0]) || !isfinite(t[1])) {
         sc->status = DG_ERR_NONFINITE;
         sc->done = 1;
-    } else if (t[1] <= sc->tol2) {
+    } else if (t[1] == 0.0 || (sc->fixed_iters <= 0 && t[1] <= sc->tol2)) {
         sc->done = 1;
     }
 }

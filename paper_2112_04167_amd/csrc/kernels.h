@@ -88,6 +88,7 @@ struct CgVecArgs {
     int n[3];
     int nel, ngroups;
     int weak;
+    int keep_x;         // set-up: leave x (the caller's initial guess) as it is
     bool singular;      // host-side: selects the singular (projected) kernels
     double *partial;
     CgScalars *sc;
@@ -96,7 +97,7 @@ struct CgVecArgs {
 const GllTables &gll_cached(int P);
 
 template <typename T>
-int cg_setup(const MeshDev &m, CgVecArgs<T> a, hipStream_t s);   // b, r, z, p, x = 0, norms
+int cg_setup(const MeshDev &m, CgVecArgs<T> a, hipStream_t s);   // b, r, z, p, x = 0 (unless keep_x), norms
 template <typename T>
 int cg_update(const MeshDev &m, CgVecArgs<T> a, hipStream_t s);  // x, r and the new rho
 template <typename T>

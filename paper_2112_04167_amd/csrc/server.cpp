@@ -399,6 +399,12 @@ private:
             hipLaunchKernelGGL(k_splitmix_uniform, dim3(std::max(1u, blocks)), dim3(256), 0, S.stream,
                                rhs, N, (unsigned long long)q->d.rhs_seed);
         }
+        // the solvers start from the given x: start from zero
+        if (hipMemsetAsync(x, 0, N * sizeof(double), S.stream) != hipSuccess) {
+            dg_mesh_destroy(m);
+            set_error("clearing x failed");
+            return DG_ERR_DEVICE;
+        }
         dg_solve_opts o;
         dg_default_opts(&o);
         o.tol = q->d.tol;

@@ -242,7 +242,25 @@ int solve_fp64(dg_mesh *m, const int bc[3], double lambda, const double *nu, dou
     a.src = rhs;
     a.bvec = w.b64;
     a.weak = o.rhs_is_weak;
+    a.keep_x = 1;
     if ((rc = cg_setup<double>(md, a, s))) return rc;
+    // b = 0: the solution is x = 0 whatever the initial guess
+    DG_HIP_CHECK(hipMemcpyAsync(w.host_sc, w.sc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
+    DG_HIP_CHECK(hipStreamSynchronize(s));
+    if (w.host_sc->status >= 0 && w.host_sc->bnorm2 == 0.0) {
+        DG_HIP_CHECK(hipMemsetAsync(x, 0, md.ndof * sizeof(double), s));
+        DG_HIP_CHECK(hipStreamSynchronize(s));
+        info.iters = 0;
+        info.outer_iters = 0;
+        info.status = DG_OK;
+        info.rel_res = info.true_rel_res = 0.0;
+        return DG_OK;
+    }
+    // start from the caller's x: r = b - A x (projected), then restart CG from r
+    if ((rc = launch_resid<double>(md, bc, lambda, nu, nu_c, x, w.b64, w.r64, w.partial, w.sc,
+                                   s)))
+        return rc;
+    if ((rc = cg_restart64(md, a, s))) return rc;
     const int cap = o.fixed_iters > 0 ? o.fixed_iters : o.maxit;
     if ((rc = cg_iterate<double>(m, bc, lambda, nu, nu_c, a, w.sc, w.host_sc, cap))) return rc;
     if ((rc = cg_finish<double>(md, a, s))) return rc;
@@ -303,7 +321,12 @@ int solve_mixed(dg_mesh *m, const int bc[3], double lambda, const double *nu, do
     oa.src = rhs;
     oa.bvec = w.b64;
     oa.weak = o.rhs_is_weak;
+    oa.keep_x = 1;
     if ((rc = cg_setup<double>(md, oa, s))) return rc;
+    // start from the caller's x: r64 = b - A x (projected)
+    if ((rc = launch_resid<double>(md, bc, lambda, nu, nu_c, x, w.b64, w.r64, w.partial, osc,
+                                   s)))
+        return rc;
     // first inner right-hand side r32 = r64 / scale, then the inner set-up
     CgVecArgs<float> ia = vec_args<float>(w, singular, osc);
     ia.src64 = w.r64;
@@ -329,11 +352,20 @@ int solve_mixed(dg_mesh *m, const int bc[3], double lambda, const double *nu, do
     const double bnorm2 = hosc->bnorm2;
     const double tol2 = hosc->tol2;  // tol^2 ||M^-1 b||^2
     int status = hosc->status;
-    double res2 = bnorm2;
+    if (status >= 0 && bnorm2 == 0.0) {  // b = 0: x = 0 whatever the initial guess
+        DG_HIP_CHECK(hipMemsetAsync(x, 0, md.ndof * sizeof(double), s));
+        DG_HIP_CHECK(hipStreamSynchronize(s));
+        info.iters = 0;
+        info.outer_iters = 0;
+        info.status = DG_OK;
+        info.rel_res = info.true_rel_res = 0.0;
+        return DG_OK;
+    }
+    double res2 = hosc->true_res2;  // ||M^-1 (b - A x0)||^2
     int outer = 0;
     int inner_iters = 0, fp64_iters = 0;
     bool fp64_continue = false;
-    double cycle_start = bnorm2;  // ||M^-1 r||^2 at the start of the FP32 cycle
+    double cycle_start = res2;  // ||M^-1 r||^2 at the start of the FP32 cycle
     int first_cycle = -1;         // FP32 iterations of the first cycle
     ia.r = w.r32;
     while (status == DG_OK && bnorm2 > 0.0 && res2 > tol2) {

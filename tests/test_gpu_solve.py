@@ -10,6 +10,8 @@ Checks (rule: ||M^-1 r|| <= tol ||M^-1 b||, tol = 1e-10, Sec. 4 of the paper):
   * mixed precision: held to the refinement tolerance on the residual
     recomputed by the oracle (x 1.2 for the recomputation's rounding), and
     to <= 1e-9 in error against x*;
+  * x on entry is the initial guess: the same rule from any guess, fewer
+    iterations from a close one, none from x* itself, x = 0 for b = 0;
   * status codes of the failure modes."""
 import numpy as np
 import pytest
@@ -22,12 +24,12 @@ from tests.helpers import make_spec, ndof, manufactured_u, channel_nu
 pytestmark = pytest.mark.gpu
 
 
-def gpu_solve(spec, lam, nu, f, poisson=False, **opts):
+def gpu_solve(spec, lam, nu, f, poisson=False, x0=None, **opts):
     import paper_2112_04167_amd as dg
     torch, dev = torch_dev()
     mesh = dg.mesh_from_spec(spec)
     fd = to_dev(f)
-    xd = torch.zeros_like(fd)
+    xd = torch.zeros_like(fd) if x0 is None else to_dev(np.asarray(x0, dtype=np.float64))
     o = dg.default_opts(**opts)
     if poisson:
         info = dg.poisson_solve(mesh, fd, xd, o, raise_on_error=False)
@@ -254,3 +256,59 @@ def test_stretched_large_helmholtz_full_size():
     assert 30 <= info["iters"] <= 45
     xs = kron.FDM(spec, lam).solve(dense.mass_diag(spec) * f)
     assert rel(x, xs) <= 1e-10
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_initial_guess_helmholtz(precision):
+    spec = make_spec((3, 2, 3), 5, (0, 1, 0), True)
+    lam = 3.0
+    N = ndof(spec)
+    f = synth.uniform_field(N, 91)
+    M = dense.mass_diag(spec)
+    xs = kron.FDM(spec, lam).solve(M * f)
+    op = naive.Operator(spec, lam, 1.0)
+    bar = 1e-10 if precision == 0 else 1e-9
+    _, i0 = gpu_solve(spec, lam, 1.0, f, precision=precision)
+    # a guess close to x*: same rule, fewer iterations than from zero
+    near = xs * (1.0 + 1e-4 * synth.uniform_field(N, 92))
+    xn, inear = gpu_solve(spec, lam, 1.0, f, precision=precision, x0=near)
+    say("guess near", precision, i0["iters"], inear)
+    assert inear["status"] == 0 and inear["iters"] < i0["iters"]
+    assert pcg.true_rel_res(op.apply, xn, M * f, M) <= 1.2e-10 and rel(xn, xs) <= bar
+    # x* itself (exact to rounding): no iterations, x unchanged to rounding
+    xe, iex = gpu_solve(spec, lam, 1.0, f, precision=precision, x0=xs)
+    assert iex["status"] == 0 and iex["iters"] == 0 and rel(xe, xs) <= 1e-12
+    # a guess far from x*: the same solution as from zero
+    far = 10.0 * synth.uniform_field(N, 93)
+    xf, ifar = gpu_solve(spec, lam, 1.0, f, precision=precision, x0=far)
+    assert ifar["status"] == 0
+    assert pcg.true_rel_res(op.apply, xf, M * f, M) <= 1.2e-10 and rel(xf, xs) <= bar
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_initial_guess_singular_poisson(precision):
+    # a guess with a large constant component: the result is still the
+    # M-mean-zero solution
+    spec = make_spec((3, 3, 2), 3, (0, 1, 0), True)
+    N = ndof(spec)
+    f = synth.uniform_field(N, 3)
+    pspec = dict(spec)
+    pspec["bc"] = (0, 2, 0)
+    M = dense.mass_diag(pspec)
+    xs = kron.FDM(pspec, 0.0).solve(M * f)
+    guess = xs + 5.0 + 0.1 * synth.uniform_field(N, 94)
+    x, info = gpu_solve(spec, 0.0, 1.0, f, poisson=True, precision=precision, x0=guess, tol=1e-11)
+    say("poisson guess", precision, info)
+    assert info["status"] == 0
+    assert rel(x, xs) <= 1e-8
+    assert abs(np.dot(M, x)) <= 1e-12 * np.linalg.norm(x)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_initial_guess_zero_rhs(precision):
+    spec = make_spec((2, 2, 2), 4, (0, 1, 0), False)
+    N = ndof(spec)
+    x, info = gpu_solve(spec, 2.0, 1.0, np.zeros(N), precision=precision,
+                        x0=synth.uniform_field(N, 95))
+    assert info["status"] == 0 and info["iters"] == 0
+    assert np.all(x == 0.0)
