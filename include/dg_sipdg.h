@@ -174,6 +174,20 @@ int helmholtz_solve_batched(dg_mesh *m, int nsys, const double *lambdas,
                             const double *const *rhs, double *const *x,
                             const dg_solve_opts *opts, dg_solve_info *infos);
 
+/* helmholtz_solve_batched with flags.  DG_BATCH_HANDOFF: once a single system
+   is left unconverged (the others have retired), the persistent launch ends
+   and that system is finished by the single-system solver (helmholtz_solve /
+   poisson_solve with the same options), starting from its current solution.
+   With one system left, ordinary kernel launches cost less per iteration
+   than the launch's two grid barriers.  The system's info then counts the
+   iterations and replacements of both parts.  flags = 0 is
+   helmholtz_solve_batched. */
+enum { DG_BATCH_HANDOFF = 1 };
+int helmholtz_solve_batched_ex(dg_mesh *m, int nsys, const double *lambdas,
+                               const double *const *nu_fields, const int *is_poisson,
+                               const double *const *rhs, double *const *x,
+                               const dg_solve_opts *opts, dg_solve_info *infos, int flags);
+
 /* ------------------------------------------------------------- serving --
  * A request server for the implicit-stage solves: solves of different mesh
  * sizes, degrees and lambda arrive at any time.  A request is admitted when

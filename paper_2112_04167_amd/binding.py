@@ -17,6 +17,7 @@ DG_ERR_ARG, DG_ERR_OOM, DG_ERR_DEVICE, DG_ERR_NOT_SPD, DG_ERR_NONFINITE, DG_ERR_
     -1, -2, -3, -4, -5, -6
 DG_BC_PERIODIC, DG_BC_DIRICHLET, DG_BC_NEUMANN = 0, 1, 2
 DG_FP64, DG_FP32, DG_MIXED = 0, 1, 1
+DG_BATCH_HANDOFF = 1
 
 STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", 2: "PENDING", -1: "ERR_ARG", -2: "ERR_OOM",
                 -3: "ERR_DEVICE", -4: "ERR_NOT_SPD", -5: "ERR_NONFINITE", -6: "ERR_BUDGET"}
@@ -84,6 +85,11 @@ _SIGS = {
                                  ctypes.POINTER(_VP), ctypes.POINTER(_VP),
                                  ctypes.POINTER(dg_solve_opts), ctypes.POINTER(dg_solve_info)],
                                 ctypes.c_int),
+    "helmholtz_solve_batched_ex": ([_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(_VP), ctypes.POINTER(ctypes.c_int),
+                                    ctypes.POINTER(_VP), ctypes.POINTER(_VP),
+                                    ctypes.POINTER(dg_solve_opts), ctypes.POINTER(dg_solve_info),
+                                    ctypes.c_int], ctypes.c_int),
     "dg_server_create": ([ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(_VP)], ctypes.c_int),
     "dg_server_submit": ([_VP, ctypes.POINTER(dg_request), ctypes.POINTER(ctypes.c_int64)],
                          ctypes.c_int),
@@ -255,7 +261,7 @@ def poisson_solve(mesh, rhs, x, opts=None, raise_on_error=True):
 
 
 def helmholtz_solve_batched(mesh, lambdas, nu_fields, is_poisson, rhs, xs, opts=None,
-                            raise_on_error=True):
+                            raise_on_error=True, handoff=False):
     import torch
     n = len(rhs)
     lam = (ctypes.c_double * n)(*[float(v) for v in lambdas])
@@ -265,8 +271,9 @@ def helmholtz_solve_batched(mesh, lambdas, nu_fields, is_poisson, rhs, xs, opts=
     rr = (ctypes.c_void_p * n)(*[_dptr(v, torch.float64, mesh.ndof) for v in rhs])
     xx = (ctypes.c_void_p * n)(*[_dptr(v, torch.float64, mesh.ndof) for v in xs])
     infos = (dg_solve_info * n)()
-    rc = lib().helmholtz_solve_batched(mesh.handle, n, lam, nus, pois, rr, xx,
-                                       ctypes.byref(opts) if opts is not None else None, infos)
+    rc = lib().helmholtz_solve_batched_ex(mesh.handle, n, lam, nus, pois, rr, xx,
+                                          ctypes.byref(opts) if opts is not None else None, infos,
+                                          DG_BATCH_HANDOFF if handoff else 0)
     if raise_on_error:
         _check(rc, allow_warning=True)
     return rc, [i.as_dict() for i in infos]

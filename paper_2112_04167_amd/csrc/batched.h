@@ -10,6 +10,7 @@ constexpr int kMaxBatch = 8;
 constexpr int kBatchMaxBlocks = 4096;           // resident work-groups at most
 constexpr int kBatchNC = 8;                     // reduction components per system and phase
 constexpr int kBatchSlots = kBatchNC * kMaxBatch;
+constexpr int kBatchHandoff = 3;                // result status: left to the single-system solver
 
 struct BatchSysDesc {
     double *x64, *b64, *r64;            // solution (caller), load, FP64 residual
@@ -33,6 +34,8 @@ struct BatchRequest {
     int maxit;        // cap on inner iterations (per system)
     int max_replace;  // cap on FP64 residual replacements (per system)
     int weak;
+    int handoff;      // end the launch once a single system is left unconverged (its x64
+                      // then holds the current solution; result status kBatchHandoff)
     bool inner_fp32;
 };
 

@@ -225,7 +225,7 @@ struct BArgs {
     Geo<double> g64;
     Geo<TI> gi;
     const int *order;
-    int nel, ngroups, nsys, weak, maxit, max_replace;
+    int nel, ngroups, nsys, weak, maxit, max_replace, handoff;
     double tol, delta, mass_mean;
 };
 
@@ -492,6 +492,35 @@ __device__ __forceinline__ void batched_body(BArgs<TI> &B)
         // the device flag in their own waits
         n = make_list([](const SysSt &y) { return !y.done; });
         if (n == 0 || bc.err) break;
+        if (B.handoff && n == 1 && B.nsys > 1) {
+            // a single system left: its iterations are cheaper as ordinary
+            // kernels than behind two grid barriers each, so the launch ends
+            // here.  Flush its correction into x_64 (the current solution, from
+            // which the caller continues) and report it as handed off.
+            items(1, [&](int, int s, int g) {
+                const BSys<TI> &Y = B.sys[s];
+                const double sc = st[s].s;
+                group_lines<P>(g, nel, B.g64, [&](size_t base, double) {
+                    constexpr int n = S::n, NL = S::NL;
+                    double xd[n];
+                    TI xv[n];
+#pragma unroll
+                    for (int c = 0; c < n; ++c) {
+                        xd[c] = Y.x64[base + (size_t)c * NL];
+                        xv[c] = Y.x[base + (size_t)c * NL];
+                    }
+#pragma unroll
+                    for (int c = 0; c < n; ++c) Y.x64[base + (size_t)c * NL] = fma(sc, (double)xv[c], xd[c]);
+                });
+            });
+            barrier();
+            if (tid == 0) {
+                st[list[0]].status = kBatchHandoff;
+                st[list[0]].done = 1;
+            }
+            __syncthreads();
+            break;
+        }
         clear_acc();
 
         // ---- p = u + beta p, s = (w - mean w) + beta s, x += alpha p,
@@ -825,6 +854,7 @@ template <typename TI>
 void fill_args(BArgs<TI> &B, const MeshDev &m, const BatchRequest &req)
 {
     B.nsys = req.nsys;
+    B.handoff = req.handoff;
     B.res = (BResult *)req.results;
     B.sa = (SyncArea *)req.sync;
     B.partial = req.partial;

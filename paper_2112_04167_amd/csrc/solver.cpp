@@ -555,7 +555,7 @@ size_t batched_footprint(const MeshDev &m, int precision, int nsys)
 
 int solve_batched(dg_mesh *m, int nsys, const double *lambdas, const double *const *nu_fields,
                   const int *is_poisson, const double *const *rhs, double *const *x,
-                  const dg_solve_opts &o, dg_solve_info *infos)
+                  const dg_solve_opts &o, dg_solve_info *infos, int flags)
 {
     const MeshDev &md = m->dev;
     hipStream_t s = m->stream;
@@ -595,6 +595,7 @@ int solve_batched(dg_mesh *m, int nsys, const double *lambdas, const double *con
     rq.maxit = o.inner_maxit;
     rq.max_replace = std::max(1, std::min(o.maxit, 1000));
     rq.weak = o.rhs_is_weak;
+    rq.handoff = (flags & DG_BATCH_HANDOFF) ? 1 : 0;
     rq.inner_fp32 = f32;
     {
         double vol = 1.0;
@@ -651,12 +652,26 @@ int solve_batched(dg_mesh *m, int nsys, const double *lambdas, const double *con
     for (int k = 0; k < nsys; ++k) {
         BatchSysResult r{};
         batched_read_results(hs, k, &r);
+        dg_solve_info ci{};
+        if (r.status == kBatchHandoff) {
+            // the last unconverged system: continue from its current solution
+            // with the single-system solver (same operator, options and rule)
+            const BatchSysDesc &D = rq.sys[k];
+            const int rc2 = f32 ? solve_mixed(m, D.bc, D.lambda, D.nu64, 1.0, rhs[k], x[k], o, ci)
+                                : solve_fp64(m, D.bc, D.lambda, D.nu64, 1.0, rhs[k], x[k], o, ci);
+            r.status = rc2 < 0 ? rc2 : ci.status;
+        }
         if (infos) {
-            infos[k].iters = r.iters;
-            infos[k].outer_iters = r.replaced;
+            infos[k].iters = r.iters + ci.iters;
+            infos[k].outer_iters = r.replaced + ci.outer_iters;
             infos[k].status = r.status;
-            infos[k].rel_res = r.bnorm2 > 0 ? std::sqrt(r.res64 / r.bnorm2) : 0.0;
-            infos[k].true_rel_res = infos[k].rel_res;
+            if (ci.iters || ci.outer_iters) {
+                infos[k].rel_res = ci.rel_res;
+                infos[k].true_rel_res = ci.true_rel_res;
+            } else {
+                infos[k].rel_res = r.bnorm2 > 0 ? std::sqrt(r.res64 / r.bnorm2) : 0.0;
+                infos[k].true_rel_res = infos[k].rel_res;
+            }
         }
         if (r.status < 0 && (worst >= 0 || r.status < worst)) worst = r.status;
         else if (r.status > 0 && worst == DG_OK) worst = r.status;
@@ -892,6 +907,15 @@ int helmholtz_solve_batched(dg_mesh *m, int nsys, const double *lambdas,
                             const double *const *rhs, double *const *x, const dg_solve_opts *opts,
                             dg_solve_info *infos)
 {
+    return helmholtz_solve_batched_ex(m, nsys, lambdas, nu_fields, is_poisson, rhs, x, opts, infos,
+                                      0);
+}
+
+int helmholtz_solve_batched_ex(dg_mesh *m, int nsys, const double *lambdas,
+                               const double *const *nu_fields, const int *is_poisson,
+                               const double *const *rhs, double *const *x,
+                               const dg_solve_opts *opts, dg_solve_info *infos, int flags)
+{
     const double t0 = now();
     if (int rc = check_mesh(m)) return rc;
     if (nsys < 1 || nsys > kMaxBatch || !rhs || !x) {
@@ -923,7 +947,11 @@ int helmholtz_solve_batched(dg_mesh *m, int nsys, const double *lambdas,
                 return DG_ERR_ARG;
             }
     }
-    int rc = solve_batched(m, nsys, lambdas, nu_fields, is_poisson, rhs, x, o, infos);
+    if (flags & ~DG_BATCH_HANDOFF) {
+        set_error("unknown batched-solve flags");
+        return DG_ERR_ARG;
+    }
+    int rc = solve_batched(m, nsys, lambdas, nu_fields, is_poisson, rhs, x, o, infos, flags);
     if (infos)
         for (int k = 0; k < nsys; ++k) infos[k].seconds = now() - t0;
     return rc;

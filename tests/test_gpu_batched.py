@@ -22,7 +22,7 @@ def rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
-def run_batched(spec, lams, nus, pois, fs, precision=1, **kw):
+def run_batched(spec, lams, nus, pois, fs, precision=1, handoff=False, **kw):
     import paper_2112_04167_amd as dg
     torch, dev = torch_dev()
     mesh = dg.mesh_from_spec(spec)
@@ -30,7 +30,8 @@ def run_batched(spec, lams, nus, pois, fs, precision=1, **kw):
     xs = [torch.zeros_like(r) for r in rhs]
     nud = [None if v is None else to_dev(v) for v in nus]
     o = dg.default_opts(precision=precision, **kw)
-    rc, infos = dg.helmholtz_solve_batched(mesh, lams, nud, pois, rhs, xs, o, raise_on_error=False)
+    rc, infos = dg.helmholtz_solve_batched(mesh, lams, nud, pois, rhs, xs, o, raise_on_error=False,
+                                           handoff=handoff)
     if rc < 0:
         say("batched solve returned", rc, dg.last_error())
     out = [x.cpu().numpy() for x in xs]
@@ -47,11 +48,14 @@ def stage_problem(spec):
     return [lam, lam, lam, 0.0], [nu, nu, nu, None], [0, 0, 0, 1], fs, nu, lam
 
 
+@pytest.mark.parametrize("handoff", [False, True])
 @pytest.mark.parametrize("precision", [1, 0])
-def test_batched_small_against_exact(precision):
+def test_batched_small_against_exact(precision, handoff):
+    # handoff: the launch ends once the Poisson system is the only one left,
+    # which is then finished by the single-system solver from its current x
     spec = make_spec((2, 3, 2), 5, (0, 0, 1), False)
     lams, nus, pois, fs, nu, lam = stage_problem(spec)
-    rc, infos, xs = run_batched(spec, lams, nus, pois, fs, precision=precision)
+    rc, infos, xs = run_batched(spec, lams, nus, pois, fs, precision=precision, handoff=handoff)
     say("batched small", rc, infos)
     assert rc == 0
     M = dense.mass_diag(spec)
@@ -96,12 +100,14 @@ def test_batched_equals_solo():
     mesh.destroy()
 
 
-def test_batched_retirement_and_iteration_counts():
+@pytest.mark.parametrize("handoff", [False, True])
+def test_batched_retirement_and_iteration_counts(handoff):
     # the Poisson system needs far more inner iterations than the velocity
-    # systems; each system reports its own counts
+    # systems; each system reports its own counts (after a handoff: those of
+    # the launch plus those of the single-system continuation)
     spec = make_spec((3, 3, 3), 5, (0, 0, 1), False)
     lams, nus, pois, fs, nu, lam = stage_problem(spec)
-    rc, infos, xs = run_batched(spec, lams, nus, pois, fs)
+    rc, infos, xs = run_batched(spec, lams, nus, pois, fs, handoff=handoff)
     assert rc == 0
     vel = [infos[k]["iters"] for k in range(3)]
     assert infos[3]["iters"] > 3 * max(vel)
@@ -119,15 +125,18 @@ def test_batched_single_system_and_errors():
     assert rel(xs[0], kron.FDM(spec, 5.0).solve(M * f)) <= 1e-10
     bad = f.copy()
     bad[3] = np.inf
-    rc, infos, _ = run_batched(spec, [5.0, 5.0], [None, None], [0, 0], [f, bad])
-    assert rc == dg.DG_ERR_NONFINITE
-    assert infos[0]["status"] == 0 and infos[1]["status"] == dg.DG_ERR_NONFINITE
+    for handoff in (False, True):
+        rc, infos, xs = run_batched(spec, [5.0, 5.0], [None, None], [0, 0], [f, bad], handoff=handoff)
+        assert rc == dg.DG_ERR_NONFINITE
+        assert infos[0]["status"] == 0 and infos[1]["status"] == dg.DG_ERR_NONFINITE
+        assert rel(xs[0], kron.FDM(spec, 5.0).solve(M * f)) <= 1e-9
 
 
-def test_batched_channel_full_size():
+@pytest.mark.parametrize("handoff", [False, True])
+def test_batched_channel_full_size(handoff):
     spec = synth.mesh_spec("batched_channel")   # 24^3, P=5, 3.0M nodes per field
     lams, nus, pois, fs, nu, lam = stage_problem(spec)
-    rc, infos, xs = run_batched(spec, lams, nus, pois, fs)
+    rc, infos, xs = run_batched(spec, lams, nus, pois, fs, handoff=handoff)
     say("batched channel", rc, infos)
     assert rc == 0
     M = dense.mass_diag(spec)
