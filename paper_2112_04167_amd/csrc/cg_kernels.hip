@@ -36,6 +36,13 @@ namespace dg {
 
 namespace {
 
+// The diagonal is computed on the fly in the FP64 kernels only: in the FP32
+// inner solve of the mixed mode it measured no faster than the stored one
+// (the update kernel lost what the p-update gained), so the FP32 kernels
+// keep the plain load.
+template <typename T>
+constexpr bool kDiagFly = sizeof(T) == 8;
+
 // per-thread line context
 template <int P, typename T>
 struct LineCtx {
@@ -43,6 +50,9 @@ struct LineCtx {
     size_t base;  // index of node (a,b,0)
     T Jw;         // J w_a w_b
     double iJw;   // 1 / (J w_a w_b)
+    // on-the-fly diagonal (A.dtab): diag(a,b,c) = w_c dQ + dR Tz[c]
+    T dQ, dR;
+    const T *tz;
 };
 
 // 1/w_c (a compile-time constant)
@@ -68,8 +78,33 @@ __device__ __forceinline__ LineCtx<P, T> line_ctx(const CgVecArgs<T> &A)
         c.Jw = A.hx[ex] * A.hy[ey] * A.hz[ez] * (T)0.125 * (T)kGll<P>.w[l % S::n] *
                (T)kGll<P>.w[l / S::n];
         c.iJw = 1.0 / (double)c.Jw;
+        if (kDiagFly<T> && A.dtab) {
+            // the constant-nu operator on a Cartesian grid is a sum of 1D
+            // operators along the axes, each scaled by the tangential GLL
+            // mass, so its diagonal at node (a,b,c) is
+            //   lambda J W + hy hz w_b w_c Tx[ex][a] + hx hz w_a w_c Ty[ey][b]
+            //              + hx hy w_a w_b Tz[ez][c]
+            // with Tx etc. the 1D diagonals (volume and face terms)
+            const int a = l % S::n, b = l / S::n;
+            const T hx = A.hx[ex], hy = A.hy[ey], hz = A.hz[ez];
+            const T wa = (T)kGll<P>.w[a], wb = (T)kGll<P>.w[b];
+            const T *tx = A.dtab + (size_t)ex * S::n;
+            const T *ty = A.dtab + (size_t)(A.n[0] + ey) * S::n;
+            c.tz = A.dtab + (size_t)(A.n[0] + A.n[1] + ez) * S::n;
+            c.dQ = (T)A.lam * c.Jw + hy * hz * wb * tx[a] + hx * hz * wa * ty[b];
+            c.dR = hx * hy * wa * wb;
+        }
     }
     return c;
+}
+
+// 1/diag of node k of this thread's line: computed (A.dtab) or stored (A.d)
+template <int P, typename T>
+__device__ __forceinline__ T inv_diag(const CgVecArgs<T> &A, const LineCtx<P, T> &c, int k, size_t gi)
+{
+    if constexpr (kDiagFly<T>)
+        if (A.dtab) return (T)1 / fma(c.dR, c.tz[k], (T)kGll<P>.w[k] * c.dQ);
+    return A.d[gi];
 }
 
 // set-up, stage 1: b = M f (or b = f if weak), sum b and sum b^2
@@ -121,8 +156,8 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_setup2(CgVecArgs<T> A)
             const double rm = (double)b * im;
             red[1] += rm * rm;
             red[3] += im * im;
-            if (A.d) {  // A.d holds 1/diag(A)
-                const T di = A.d[gi];
+            if (A.d || A.dtab) {  // 1/diag(A), stored or computed
+                const T di = inv_diag<P, T>(A, c, k, gi);
                 const T z = b * di;
                 A.p[gi] = z;
                 red[0] += (double)b * (double)z;
@@ -154,7 +189,7 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_update(CgVecArgs<T> A)
             A.x[gi] = fma(alpha, p, A.x[gi]);
             const T r = fma(-alpha, A.q[gi], A.r[gi]);
             A.r[gi] = r;
-            const double rd = (double)r * (double)A.d[gi];
+            const double rd = (double)r * (double)inv_diag<P, T>(A, c, k, gi);
             const double im = c.iJw * inv_w<P>(k);
             const double rm = (double)r * im;
             if (SING) {
@@ -190,7 +225,7 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_pupdate(CgVecArgs<T> A)
             r = (T)((double)r - mr);
             A.r[gi] = r;
         }
-        A.p[gi] = fma(beta, A.p[gi], r * A.d[gi]);
+        A.p[gi] = fma(beta, A.p[gi], r * inv_diag<P, T>(A, c, k, gi));
     }
 }
 
@@ -280,7 +315,7 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_ir_replace(CgVecArgs<float> A
             const float r = (float)((A.src64[gi] - mr) * inv);
             A.r[gi] = r;
             A.x[gi] = 0.0f;
-            const double z = (double)r * (double)A.d[gi];
+            const double z = (double)r * (double)inv_diag<P, float>(A, c, k, gi);
             const double rm = (double)r * (c.iJw * inv_w<P>(k));
             red[0] += (double)r * z;
             red[1] += rm * rm;
@@ -308,7 +343,7 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_restart64(CgVecArgs<double> A
 #pragma unroll
         for (int k = 0; k < S::n; ++k) {
             rv[k] = A.r[c.base + (size_t)k * S::NL];
-            dv[k] = A.d[c.base + (size_t)k * S::NL];
+            dv[k] = inv_diag<P, double>(A, c, k, c.base + (size_t)k * S::NL);
         }
 #pragma unroll
         for (int k = 0; k < S::n; ++k) {

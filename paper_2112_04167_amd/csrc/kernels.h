@@ -89,6 +89,10 @@ struct CgVecArgs {
     int nel, ngroups;
     int weak;
     int keep_x;         // set-up: leave x (the caller's initial guess) as it is
+    // Jacobi diagonal computed on the fly (constant nu) instead of read from d:
+    // per-axis 1D terms [nx | ny | nz][P+1] (see diag_tables) and lambda
+    const T *dtab;
+    double lam;
     bool singular;      // host-side: selects the singular (projected) kernels
     double *partial;
     CgScalars *sc;

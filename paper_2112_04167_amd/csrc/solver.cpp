@@ -49,6 +49,8 @@ struct Workspace {
     float *x32 = nullptr, *r32 = nullptr, *p32 = nullptr, *q32 = nullptr, *d32 = nullptr,
           *b32 = nullptr, *nu32 = nullptr;
     double *partial = nullptr;
+    double *dtab64 = nullptr;     // per-axis 1D diagonal terms (constant nu)
+    std::vector<double> htab64;   // host copy (alive until the next solve's upload)
     CgScalars *sc = nullptr;      // [0] outer / FP64, [1] inner FP32
     CgScalars *host_sc = nullptr; // pinned
     bool external = false;        // memory lent by the caller (never freed here)
@@ -78,6 +80,8 @@ size_t partial_doubles(const MeshDev &m) { return (size_t)apply_groups(m.P, m.ne
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+size_t diag_table_len(const MeshDev &m) { return (size_t)(m.n[0] + m.n[1] + m.n[2]) * (m.P + 1); }
+
 size_t footprint(const MeshDev &m, int precision)
 {
     const size_t N = (size_t)m.ndof;
@@ -85,6 +89,7 @@ size_t footprint(const MeshDev &m, int precision)
     b += 5 * align256(N * sizeof(double));  // r, p, q, d, b (FP64)
     if (precision == DG_MIXED) b += 7 * align256(N * sizeof(float));
     b += align256(partial_doubles(m) * sizeof(double));
+    b += align256(diag_table_len(m) * sizeof(double));
     b += align256(2 * sizeof(CgScalars));
     return b;
 }
@@ -143,6 +148,8 @@ int ensure_workspace(dg_mesh *m, int precision)
         w.x32 = w.r32 = w.p32 = w.q32 = w.d32 = w.b32 = w.nu32 = nullptr;
     }
     w.partial = (double *)take(partial_doubles(m->dev) * 8);
+    w.dtab64 = (double *)take(diag_table_len(m->dev) * sizeof(double));
+
     w.sc = (CgScalars *)take(2 * sizeof(CgScalars));
     return DG_OK;
 }
@@ -219,6 +226,72 @@ int check_mesh(dg_mesh *m)
     return DG_OK;
 }
 
+// The 1D diagonal terms of the constant-nu operator (arXiv 2112.04167,
+// Sec. 3.3: SIP on a Cartesian product grid, GLL quadrature).  The operator
+// is lambda M plus, per axis d, the 1D SIP operator along d scaled by the
+// tangential GLL mass, so its diagonal at node (a,b,c) of element
+// (ex,ey,ez) is lambda J W + hy hz w_b w_c T_x[ex][a] + ... with
+//   T_d[k][a] = nu K1_aa / (2 h_k) + (face terms at a = 0, P) / 4,
+// the face terms being those of the interior-penalty form with
+// sigma = nu (P+1)^2 / min(h_k, h_N) (interior, periodic) or nu (P+1)^2 / h_k
+// (Dirichlet).  The same terms as the stored diagonal, in another order.
+void diag_tables(const MeshDev &md, const int bc[3], double nu, std::vector<double> &t)
+{
+    const GllTables &g = gll_cached(md.P);
+    const int P = md.P, n = P + 1;
+    const double pen = (double)n * n;
+    t.assign(diag_table_len(md), 0.0);
+    size_t off = 0;
+    for (int d = 0; d < 3; ++d) {
+        const int nk = md.n[d];
+        auto h = [&](int k) { return md.v[d][k + 1] - md.v[d][k]; };
+        for (int k = 0; k < nk; ++k) {
+            const double hk = h(k), gk = 2.0 / hk;
+            for (int a = 0; a < n; ++a) {
+                double T = nu * g.K1[a * n + a] / (2.0 * hk);
+                if (a == 0 || a == P) {
+                    const bool high = (a == P);
+                    int kn = k, kind;
+                    if (!high && k > 0) {
+                        kn = k - 1;
+                        kind = 1;
+                    } else if (high && k < nk - 1) {
+                        kn = k + 1;
+                        kind = 1;
+                    } else if (bc[d] == DG_BC_PERIODIC) {
+                        kn = high ? 0 : nk - 1;
+                        kind = 1;
+                    } else {
+                        kind = bc[d] == DG_BC_DIRICHLET ? 2 : 0;
+                    }
+                    const double Daa = g.D[a * n + a], sgn = high ? -1.0 : 1.0;
+                    double f = 0.0;
+                    if (kind == 1) {
+                        f = nu * pen / std::min(hk, h(kn)) + sgn * nu * gk * Daa;
+                        if (kn == k)  // a single periodic element is its own neighbour
+                            f += high ? -nu * gk * g.D[0 * n + P] : nu * gk * g.D[P * n + 0];
+                    } else if (kind == 2) {
+                        f = nu * pen / hk + 2.0 * sgn * nu * gk * Daa;
+                    }
+                    T += 0.25 * f;
+                }
+                t[off + (size_t)k * n + a] = T;
+            }
+        }
+        off += (size_t)nk * n;
+    }
+}
+
+// upload the tables of this solve on the solve's stream
+int upload_diag_tables(dg_mesh *m, const int bc[3], double nu)
+{
+    Workspace &w = m->ws;
+    diag_tables(m->dev, bc, nu, w.htab64);
+    DG_HIP_CHECK(hipMemcpyAsync(w.dtab64, w.htab64.data(), w.htab64.size() * sizeof(double),
+                                hipMemcpyHostToDevice, m->stream));
+    return DG_OK;
+}
+
 // FP64 Jacobi-PCG
 int solve_fp64(dg_mesh *m, const int bc[3], double lambda, const double *nu, double nu_c,
                const double *rhs, double *x, const dg_solve_opts &o, dg_solve_info &info)
@@ -232,13 +305,19 @@ int solve_fp64(dg_mesh *m, const int bc[3], double lambda, const double *nu, dou
     CgScalars init = init_scalars(md, o.tol, o.maxit, o.fixed_iters, singular);
     *w.host_sc = init;
     DG_HIP_CHECK(hipMemcpyAsync(w.sc, w.host_sc, sizeof(CgScalars), hipMemcpyHostToDevice, s));
-    if ((rc = launch_diag<double>(md, bc, lambda, nu, nu_c, w.d64, s, true))) return rc;
     CgVecArgs<double> a = vec_args<double>(w, singular, w.sc);
+    if (nu) {
+        if ((rc = launch_diag<double>(md, bc, lambda, nu, nu_c, w.d64, s, true))) return rc;
+        a.d = w.d64;
+    } else {  // constant nu: the diagonal is computed where it is used
+        if ((rc = upload_diag_tables(m, bc, nu_c))) return rc;
+        a.dtab = w.dtab64;
+        a.lam = lambda;
+    }
     a.x = x;
     a.r = w.r64;
     a.p = w.p64;
     a.q = w.q64;
-    a.d = w.d64;
     a.src = rhs;
     a.bvec = w.b64;
     a.weak = o.rhs_is_weak;
@@ -307,7 +386,16 @@ int solve_mixed(dg_mesh *m, const int bc[3], double lambda, const double *nu, do
         if ((rc = convert_f64_to_f32(nu, w.nu32, N, s))) return rc;
         nu32 = w.nu32;
     }
+    // the Jacobi diagonal: stored for the FP32 inner solve (computing it there
+    // measured no faster); for the FP64 continuation of a constant-nu solve it
+    // is computed where it is used, as in solve_fp64
     if ((rc = launch_diag<float>(md, bc, lambda, nu32, nu_c, w.d32, s, true))) return rc;
+    const float *d32 = w.d32;
+    const double *tab64 = nullptr;
+    if (!nu) {
+        if ((rc = upload_diag_tables(m, bc, nu_c))) return rc;
+        tab64 = w.dtab64;
+    }
 
     // outer set-up: b (projected), r = b, x = 0, ||M^-1 b||
     *hosc = init_scalars(md, o.tol, o.maxit, 0, singular);
@@ -332,7 +420,7 @@ int solve_mixed(dg_mesh *m, const int bc[3], double lambda, const double *nu, do
     ia.src64 = w.r64;
     ia.r = w.b32;
     ia.x = w.x32;
-    ia.d = w.d32;
+    ia.d = d32;
     if ((rc = ir_scale(md, ia, s))) return rc;
     if ((rc = ir_to_inner(md, ia, s))) return rc;
     *hisc = init_scalars(md, o.inner_tol, o.inner_maxit, 0, singular);
@@ -342,7 +430,7 @@ int solve_mixed(dg_mesh *m, const int bc[3], double lambda, const double *nu, do
     ca.r = w.r32;
     ca.p = w.p32;
     ca.q = w.q32;
-    ca.d = w.d32;
+    ca.d = d32;
     ca.src = w.b32;
     ca.bvec = w.b32;  // in place (already weak)
     ca.weak = 1;
@@ -414,13 +502,15 @@ int solve_mixed(dg_mesh *m, const int bc[3], double lambda, const double *nu, do
     }
     if (fp64_continue && status == DG_OK) {
         // FP64 PCG from x, starting at the residual r64 just computed
-        if ((rc = launch_diag<double>(md, bc, lambda, nu, nu_c, w.d64, s, true))) return rc;
+        if (nu && (rc = launch_diag<double>(md, bc, lambda, nu, nu_c, w.d64, s, true))) return rc;
         CgVecArgs<double> fa = vec_args<double>(w, singular, osc);
+        fa.dtab = tab64;
+        fa.lam = lambda;
         fa.x = x;
         fa.r = w.r64;
         fa.p = w.p64;
         fa.q = w.q64;
-        fa.d = w.d64;
+        fa.d = nu ? w.d64 : nullptr;
         if ((rc = cg_restart64(md, fa, s))) return rc;
         if ((rc = cg_iterate<double>(m, bc, lambda, nu, nu_c, fa, osc, hosc, o.maxit))) return rc;
         fp64_iters = hosc->iter;
