@@ -116,7 +116,9 @@ int64_t dg_mesh_ndof(const dg_mesh *m);                      /* E (P+1)^3 */
    layout: device double arrays X, Y, Z of dg_mesh_ndof values each (any of
    them may be NULL).  Asynchronous on `stream` (NULL = the mesh's stream). */
 int dg_mesh_coordinates(dg_mesh *m, double *X, double *Y, double *Z, void *stream);
-/* Bytes of device workspace a solve allocates (for admission control). */
+/* Bytes of device workspace a solve allocates (for admission control).
+   nrhs > 1: that of helmholtz_solve_batched; a batched solve with
+   DG_BATCH_HANDOFF may also allocate that of nrhs = 1 (the continuation). */
 size_t dg_solve_footprint(const dg_mesh *m, int precision, int nrhs);
 
 /* y = (lambda M + K_nu) x  -- the matrix-free, sum-factorised SIP-DG apply

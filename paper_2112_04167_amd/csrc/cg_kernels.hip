@@ -338,7 +338,11 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_restart64(CgVecArgs<double> A
     const LineCtx<P, double> c = line_ctx<P, double>(A);
     const double mr = A.sc->mean_r;
     double red[4] = {0.0, 0.0, 0.0, 0.0};
-    if (c.active) {
+    if (A.sc->bnorm2 == 0.0) {  // b = 0: the solution is x = 0 whatever the start
+        if (c.active)
+#pragma unroll
+            for (int k = 0; k < S::n; ++k) A.x[c.base + (size_t)k * S::NL] = 0.0;
+    } else if (c.active) {
         double rv[S::n], dv[S::n];
 #pragma unroll
         for (int k = 0; k < S::n; ++k) {
@@ -382,7 +386,7 @@ __global__ void __launch_bounds__(1024) k_finish_restart64(const double *partial
     if (!isfinite(t[0]) || !isfinite(t[1])) {
         sc->status = DG_ERR_NONFINITE;
         sc->done = 1;
-    } else if (t[1] == 0.0 || (sc->fixed_iters <= 0 && t[1] <= sc->tol2)) {
+    } else if (sc->bnorm2 == 0.0 || t[1] == 0.0 || (sc->fixed_iters <= 0 && t[1] <= sc->tol2)) {
         sc->done = 1;
     }
 }

@@ -312,3 +312,23 @@ def test_initial_guess_zero_rhs(precision):
                         x0=synth.uniform_field(N, 95))
     assert info["status"] == 0 and info["iters"] == 0
     assert np.all(x == 0.0)
+
+
+@pytest.mark.parametrize("case", [((1, 2, 3), 4, (0, 0, 0), 0.37, 2.0),
+                                  ((2, 1, 2), 7, (1, 0, 2), 1.9, 0.5),
+                                  ((3, 3, 1), 3, (2, 1, 0), 0.05, 40.0)],
+                         ids=["n1x_periodic", "n1y_periodic_P7", "nz1_neumann"])
+def test_iteration_locked_constant_nu_diagonal(case):
+    # the FP64 solver computes the Jacobi diagonal of a constant-nu operator
+    # from per-axis 1D terms; locked to the oracle's PCG, which reads the
+    # assembled diagonal, on single-element periodic axes (an element that is
+    # its own neighbour), every BC kind and nu != 1
+    n, P, bc, nu, lam = case
+    spec = make_spec(n, P, bc, True)
+    f = synth.uniform_field(ndof(spec), 17)
+    x, info = gpu_solve(spec, lam, nu, f, fixed_iters=12)
+    assert info["iters"] == 12
+    op = naive.Operator(spec, lam, nu)
+    M = dense.mass_diag(spec)
+    xo, _ = pcg.pcg(op.apply, M * f, op.diag(), M, fixed_iters=12)
+    assert rel(x, xo) <= 1e-11
