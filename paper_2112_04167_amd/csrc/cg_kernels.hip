@@ -177,6 +177,7 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_update(CgVecArgs<T> A)
     __shared__ double sh[16 * NC];
     if (A.sc->done) return;
     const T alpha = (T)A.sc->alpha;
+    const double mr = SING ? A.sc->mean_r : 0.0;  // singular: r is stored before projection
     const LineCtx<P, T> c = line_ctx<P, T>(A);
     double red[NC];
 #pragma unroll
@@ -187,7 +188,9 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_update(CgVecArgs<T> A)
             const size_t gi = c.base + (size_t)k * S::NL;
             const T p = A.p[gi];
             A.x[gi] = fma(alpha, p, A.x[gi]);
-            const T r = fma(-alpha, A.q[gi], A.r[gi]);
+            T r0 = A.r[gi];
+            if (SING) r0 = (T)((double)r0 - mr);
+            const T r = fma(-alpha, A.q[gi], r0);
             A.r[gi] = r;
             const double rd = (double)r * (double)inv_diag<P, T>(A, c, k, gi);
             const double im = c.iJw * inv_w<P>(k);
@@ -207,7 +210,9 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_update(CgVecArgs<T> A)
     publish_partials<NC>(red, A.partial, gridDim.x, sh);
 }
 
-// (singular: r -= mean r)  p = r/d + beta p
+// p = r/d + beta p; singular: with r - mean r, the projection of r, which is
+// not stored back: the next update subtracts the same mean (sc->mean_r stays
+// until then) when it reads r, so r in memory minus mean_r is the residual
 template <int P, typename T, bool SING>
 __global__ void __launch_bounds__(Shape<P>::NTP) k_pupdate(CgVecArgs<T> A)
 {
@@ -221,10 +226,7 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_pupdate(CgVecArgs<T> A)
     for (int k = 0; k < S::n; ++k) {
         const size_t gi = c.base + (size_t)k * S::NL;
         T r = A.r[gi];
-        if (SING) {
-            r = (T)((double)r - mr);
-            A.r[gi] = r;
-        }
+        if (SING) r = (T)((double)r - mr);
         A.p[gi] = fma(beta, A.p[gi], r * inv_diag<P, T>(A, c, k, gi));
     }
 }
