@@ -117,8 +117,10 @@ def bench_solve(dg, torch, spec, lam, seed, reps, poisson=False):
     return dict(seconds_median=t, solves_per_s=1.0 / t, iters=it, status=infos[-1]["status"],
                 true_rel_res=infos[-1]["true_rel_res"], ndof=N,
                 gdof_iter_per_s=N * it / t / 1e9,
-                bytes_per_dof_iter=104.0,
-                frac_of_solve_bound=(N * it * 104.0 / t) / (HBM_PEAK_GBS * 1e9))
+                # FP64 CG with a constant nu: apply 16, update 48, p-update 24 B/node
+                # (the diagonal is computed, not read)
+                bytes_per_dof_iter=88.0,
+                frac_of_solve_bound=(N * it * 88.0 / t) / (HBM_PEAK_GBS * 1e9))
 
 
 def cpu_baseline(spec, lam, budget_s=12.0):
