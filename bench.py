@@ -40,28 +40,40 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 APPLY_BYTES_PER_DOF_FP64 = 16.0   # read x once, write y once
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "apply_p7_fp64_stretched32.md")
+COUNTER_FILE = os.path.join(ROOT, "profiles", "apply_p7_fp64_stretched32_counters.md")
+FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def measured_traffic():
-    """Per-launch HBM traffic (bytes) of the apply kernel from the committed
-    rocprofv3 counter summary, or None if the kernel source changed since the
-    counters were taken."""
+def profile_value(path, key):
+    """A per-launch figure of the apply kernel from a committed rocprofv3
+    counter summary, or None if the kernel source changed since the counters
+    were taken."""
     from paper_2112_04167_amd.prof_summary import kernel_sha
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             kv = dict(l.strip().split(": ", 1) for l in fh if ": " in l and l.startswith("    "))
     except OSError:
         return None
     if kv.get("kernel_sha") != kernel_sha():
         return None
     try:
-        return float(kv["traffic_bytes_per_launch"])
+        return float(kv[key])
     except (KeyError, ValueError):
         return None
+
+
+def measured_traffic():
+    """Per-launch HBM traffic (bytes) of the apply kernel (FETCH_SIZE + WRITE_SIZE)."""
+    return profile_value(TRAFFIC_FILE, "traffic_bytes_per_launch")
+
+
+def measured_flops():
+    """Per-launch FP64 FLOPs of the apply kernel (SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes)."""
+    return profile_value(COUNTER_FILE, "flops_per_launch")
 
 
 def bench_apply(dg, torch, spec, lam, steps, warmup, npairs=5):
@@ -370,6 +382,13 @@ def main():
                      "kernel_avg_us": avg * 1e6, "kernel_min_us": float(durs.min()) * 1e6,
                      "algorithmic_bytes_per_launch": APPLY_BYTES_PER_DOF_FP64 * N},
     }
+    flops = measured_flops()
+    if flops is not None:
+        # the FP64 rate of the same kernel against the chip's FP64 vector peak
+        tf = flops / avg / 1e12
+        out["flops"] = {"achieved": tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": tf / FP64_PEAK_TFLOPS, "flops_per_launch": flops,
+                        "counter": "SQ_INSTS_VALU_FLOPS_FP64 x 64"}
     legs = set(("solve", "poisson", "solve_mixed", "poisson_mixed", "mixed_small", "batched", "serving")
                if args.legs == "all" else args.legs.split(","))
     if not args.quick:
