@@ -166,6 +166,7 @@ def bench_mixed_small(dg, torch, reps=20):
     out = {}
     for lam in (1e2, 1e4, 1e6):
         row = {}
+        sols = {}
         for name, prec in (("fp64", dg.DG_FP64), ("mixed", dg.DG_MIXED)):
             o = dg.default_opts(precision=prec)
             x.zero_()
@@ -180,6 +181,11 @@ def bench_mixed_small(dg, torch, reps=20):
             t = float(np.median(ts))
             row[name] = dict(ms=t * 1e3, iters=info["iters"], outer=info["outer_iters"],
                              true_rel_res=info["true_rel_res"])
+            sols[name] = x.clone()
+        # error of the mixed result against the FP64 one (which the GPU tests
+        # hold to 1e-10 of the exact discrete solution)
+        row["mixed"]["rel_err_vs_fp64"] = float(torch.linalg.vector_norm(sols["mixed"] - sols["fp64"]) /
+                                                torch.linalg.vector_norm(sols["fp64"]))
         out["lambda=%g" % lam] = row
     mesh.destroy()
     return out
@@ -209,10 +215,18 @@ def bench_mixed_large(dg, torch, spec, lam, poisson=False):
         t0 = time.perf_counter()
         info = solve()
         ts.append(time.perf_counter() - t0)
+    # error against the FP64 solve of the same problem (untimed)
+    x64 = torch.zeros_like(f)
+    if poisson:
+        dg.poisson_solve(mesh, f, x64)
+    else:
+        dg.helmholtz_solve(mesh, lam, None, 1.0, f, x64)
+    err = float(torch.linalg.vector_norm(x - x64) / torch.linalg.vector_norm(x64))
     mesh.destroy()
     t = float(np.median(ts))
     return dict(seconds_median=t, solves_per_s=1.0 / t, inner_iters=info["iters"],
-                outer_iters=info["outer_iters"], true_rel_res=info["true_rel_res"])
+                outer_iters=info["outer_iters"], true_rel_res=info["true_rel_res"],
+                rel_err_vs_fp64=err)
 
 
 def bench_batched(dg, torch):
@@ -237,6 +251,7 @@ def bench_batched(dg, torch):
     t0 = time.perf_counter()
     rc, infos = dg.helmholtz_solve_batched(mesh, lams, nus, pois, fs, xs, o)
     tb = time.perf_counter() - t0
+    x_pure = [x.clone() for x in xs]
     # the same launch, ended once only the Poisson system is left, which the
     # single-system mixed solver then finishes from its current solution
     dg.helmholtz_solve_batched(mesh, lams, nus, pois, fs, xs, o, handoff=True)   # warm
@@ -244,6 +259,7 @@ def bench_batched(dg, torch):
     t0 = time.perf_counter()
     rch, infosh = dg.helmholtz_solve_batched(mesh, lams, nus, pois, fs, xs, o, handoff=True)
     th = time.perf_counter() - t0
+    x_hand = [x.clone() for x in xs]
     o64 = dg.default_opts()
 
     def sequential(o):
@@ -260,6 +276,11 @@ def bench_batched(dg, torch):
         return time.perf_counter() - t0, seq
 
     ts, seq = sequential(o64)
+
+    def errs(xm):  # error of each mixed result against the FP64 solve of its system
+        return [float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)) for a, b in zip(xm, xs)]
+
+    err_pure, err_hand = errs(x_pure), errs(x_hand)
     tm, seqm = sequential(o)
     mesh.destroy()
     return dict(ndof_per_field=N, batched_seconds=tb, batched_solves_per_s=4.0 / tb,
@@ -271,6 +292,7 @@ def bench_batched(dg, torch):
                 handoff_true_rel_res=[i["true_rel_res"] for i in infosh],
                 inner_iters=[i["iters"] for i in infos], outer_iters=[i["outer_iters"] for i in infos],
                 true_rel_res=[i["true_rel_res"] for i in infos],
+                rel_err_vs_fp64=err_pure, handoff_rel_err_vs_fp64=err_hand,
                 fp64_iters=[i["iters"] for i in seq],
                 sequential_mixed_iters=[i["iters"] for i in seqm],
                 sequential_mixed_true_rel_res=[i["true_rel_res"] for i in seqm])
