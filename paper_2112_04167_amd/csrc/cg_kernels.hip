@@ -231,6 +231,193 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_pupdate(CgVecArgs<T> A)
     }
 }
 
+// ---- FP32 update and p-update on 16-byte chunks (4 divides P+1: P = 3, 7)
+//
+// The kernels above give each lane one node per access (4 bytes in FP32), so
+// a wave's load covers 256 bytes.  Here thread t < (P+1)^2 of an element
+// takes the chunk of 4 consecutive nodes a0..a0+3 of row b in plane c0
+// (4t = a0 + (P+1) b + (P+1)^2 c0) and the chunks 4 planes further on, so
+// that consecutive lanes read consecutive 16-byte chunks: one access of a
+// wave covers 1 KiB, with a quarter of the memory instructions.  Same grid,
+// partial-sum slots and arithmetic per node as k_update / k_pupdate.
+
+template <int P>
+constexpr bool kQuad = (P + 1) % 4 == 0;
+
+// 1/w_i of the GLL weights, for runtime indices
+template <int P>
+struct InvW {
+    double v[P + 1];
+};
+template <int P>
+constexpr InvW<P> make_invw()
+{
+    InvW<P> t{};
+    for (int i = 0; i <= P; ++i) t.v[i] = 1.0 / kGll<P>.w[i];
+    return t;
+}
+template <int P>
+__constant__ InvW<P> c_invw = make_invw<P>();
+
+template <int P>
+struct QuadCtx {
+    bool active;
+    size_t base;  // first node of the first chunk; chunk r starts at base + r Q
+    int a0, c0;
+    double iJb;   // 1 / (J w_b)
+    static constexpr int Q = 4 * Shape<P>::NL;  // nodes between a thread's chunks (4 planes)
+    static constexpr int NR = (P + 1) / 4;      // chunks per thread
+};
+
+template <int P>
+__device__ __forceinline__ QuadCtx<P> quad_ctx(const CgVecArgs<float> &A)
+{
+    using S = Shape<P>;
+    constexpr int n = S::n;
+    QuadCtx<P> q;
+    const int tid = threadIdx.x;
+    const int el_loc = tid / S::NL;
+    const int t = tid - el_loc * S::NL;
+    const int el = blockIdx.x * S::EB + el_loc;
+    const int f = 4 * t;
+    q.active = (tid < S::NT) && (el < A.nel);
+    q.a0 = f % n;
+    q.c0 = f / (n * n);
+    q.base = (size_t)el * S::N3 + f;
+    q.iJb = 0.0;
+    if (q.active) {
+        const int nx = A.n[0], ny = A.n[1];
+        const int ex = el % nx, r = el / nx, ey = r % ny, ez = r / ny;
+        const float J = A.hx[ex] * A.hy[ey] * A.hz[ez] * 0.125f;
+        q.iJb = c_invw<P>.v[(f / n) % n] / (double)J;
+    }
+    return q;
+}
+
+__device__ __forceinline__ float4 ld4(const float *p) { return *reinterpret_cast<const float4 *>(p); }
+__device__ __forceinline__ void st4(float *p, float4 v) { *reinterpret_cast<float4 *>(p) = v; }
+__device__ __forceinline__ float f4(const float4 &v, int k)
+{
+    return k == 0 ? v.x : k == 1 ? v.y : k == 2 ? v.z : v.w;
+}
+
+template <int P, bool SING>
+__global__ void __launch_bounds__(Shape<P>::NTP) k_update_q(CgVecArgs<float> A)
+{
+    using Q = QuadCtx<P>;
+    constexpr int NC = SING ? 5 : 2, NR = Q::NR;
+    __shared__ double sh[16 * NC];
+    if (A.sc->done) return;
+    const float alpha = (float)A.sc->alpha;
+    const double mr = SING ? A.sc->mean_r : 0.0;  // singular: r is stored before projection
+    const Q c = quad_ctx<P>(A);
+    double red[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) red[k] = 0.0;
+    if (c.active) {
+        float4 pv[NR], xv[NR], rv[NR], qv[NR], dv[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const size_t i = c.base + (size_t)r * Q::Q;
+            pv[r] = ld4(A.p + i);
+            xv[r] = ld4(A.x + i);
+            rv[r] = ld4(A.r + i);
+            qv[r] = ld4(A.q + i);
+            dv[r] = ld4(A.d + i);
+        }
+        float4 xo[NR], ro[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            float xn[4], rn[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                xn[k] = fmaf(alpha, f4(pv[r], k), f4(xv[r], k));
+                float r0 = f4(rv[r], k);
+                if (SING) r0 = (float)((double)r0 - mr);
+                rn[k] = fmaf(-alpha, f4(qv[r], k), r0);
+            }
+            xo[r] = make_float4(xn[0], xn[1], xn[2], xn[3]);
+            ro[r] = make_float4(rn[0], rn[1], rn[2], rn[3]);
+        }
+#pragma unroll
+        for (int r = 0; r < NR; ++r) st4(A.x + c.base + (size_t)r * Q::Q, xo[r]);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) st4(A.r + c.base + (size_t)r * Q::Q, ro[r]);
+        double iwa[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) iwa[k] = c_invw<P>.v[c.a0 + k];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const double iJbc = c.iJb * c_invw<P>.v[c.c0 + 4 * r];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float rk = f4(ro[r], k);
+                const double rd = (double)rk * (double)f4(dv[r], k);
+                const double im = iJbc * iwa[k];
+                const double rm = (double)rk * im;
+                if (SING) {
+                    red[0] += (double)rk;
+                    red[1] += (double)rk * rd;
+                    red[2] += rd;
+                    red[3] += rm * rm;
+                    red[4] += rm * im;
+                } else {
+                    red[0] += (double)rk * rd;
+                    red[1] += rm * rm;
+                }
+            }
+        }
+    }
+    publish_partials<NC>(red, A.partial, gridDim.x, sh);
+}
+
+template <int P, bool SING>
+__global__ void __launch_bounds__(Shape<P>::NTP) k_pupdate_q(CgVecArgs<float> A)
+{
+    using Q = QuadCtx<P>;
+    constexpr int NR = Q::NR;
+    if (A.sc->done) return;
+    const float beta = (float)A.sc->beta;
+    const double mr = A.sc->mean_r;
+    const Q c = quad_ctx<P>(A);
+    if (!c.active) return;
+    float4 rv[NR], pv[NR], dv[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const size_t i = c.base + (size_t)r * Q::Q;
+        rv[r] = ld4(A.r + i);
+        pv[r] = ld4(A.p + i);
+        dv[r] = ld4(A.d + i);
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        float o[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            float rk = f4(rv[r], k);
+            if (SING) rk = (float)((double)rk - mr);
+            o[k] = fmaf(beta, f4(pv[r], k), rk * f4(dv[r], k));
+        }
+        st4(A.p + c.base + (size_t)r * Q::Q, make_float4(o[0], o[1], o[2], o[3]));
+    }
+}
+
+// chunked kernels apply: FP32, 4 | P+1, a stored 1/diag, 16-byte aligned
+// vectors
+template <typename T>
+bool use_quad(int P, const CgVecArgs<T> &a, bool update)
+{
+    if constexpr (sizeof(T) != 4) {
+        return false;
+    } else {
+        if ((P + 1) % 4 != 0 || !a.d) return false;
+        auto al = [](const void *p) { return ((uintptr_t)p & 15) == 0; };
+        bool ok = al(a.r) && al(a.p) && al(a.d);
+        if (update) ok = ok && al(a.x) && al(a.q);
+        return ok;
+    }
+}
+
 // singular: shift = sum(M x) / sum(M)
 template <int P, typename T>
 __global__ void __launch_bounds__(Shape<P>::NTP) k_mean_x(CgVecArgs<T> A)
@@ -606,7 +793,14 @@ int cg_update(const MeshDev &m, CgVecArgs<T> a, hipStream_t s)
         with_bool(a.singular, [&](auto SC) {
             constexpr bool SG = decltype(SC)::value;
             const int nb = apply_groups(P, m.nel);
-            hipLaunchKernelGGL((k_update<P, T, SG>), DG_GRID(PC), 0, s, a);
+            if constexpr (std::is_same<T, float>::value && kQuad<P>) {
+                if (use_quad<T>(P, a, true))
+                    hipLaunchKernelGGL((k_update_q<P, SG>), DG_GRID(PC), 0, s, a);
+                else
+                    hipLaunchKernelGGL((k_update<P, T, SG>), DG_GRID(PC), 0, s, a);
+            } else {
+                hipLaunchKernelGGL((k_update<P, T, SG>), DG_GRID(PC), 0, s, a);
+            }
             hipLaunchKernelGGL((k_finish<SG ? 5 : 2, FIN_UPDATE>), dim3(1), dim3(1024), 0, s,
                                a.partial, nb, a.sc);
         });
@@ -621,7 +815,14 @@ int cg_pupdate(const MeshDev &m, CgVecArgs<T> a, hipStream_t s)
         constexpr int P = decltype(PC)::value;
         with_bool(a.singular, [&](auto SC) {
             constexpr bool SG = decltype(SC)::value;
-            hipLaunchKernelGGL((k_pupdate<P, T, SG>), DG_GRID(PC), 0, s, a);
+            if constexpr (std::is_same<T, float>::value && kQuad<P>) {
+                if (use_quad<T>(P, a, false))
+                    hipLaunchKernelGGL((k_pupdate_q<P, SG>), DG_GRID(PC), 0, s, a);
+                else
+                    hipLaunchKernelGGL((k_pupdate<P, T, SG>), DG_GRID(PC), 0, s, a);
+            } else {
+                hipLaunchKernelGGL((k_pupdate<P, T, SG>), DG_GRID(PC), 0, s, a);
+            }
         });
     });
 }

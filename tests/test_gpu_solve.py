@@ -233,8 +233,12 @@ def test_mixed_precision_fp64_continuation():
     assert abs(np.dot(M, xp)) <= 1e-12 * np.linalg.norm(xp)
 
 
-def test_mixed_precision_poisson():
-    spec = make_spec((3, 3, 3), 5, (0, 1, 0), False)
+# P = 3 and 7 run the FP32 update / p-update on 16-byte chunks (4 | P+1),
+# P = 5 the per-line kernels; 27 elements leave the last work-group partly
+# empty for every P
+@pytest.mark.parametrize("P", [5, 3, 7])
+def test_mixed_precision_poisson(P):
+    spec = make_spec((3, 3, 3), P, (0, 1, 0), False)
     f = synth.uniform_field(ndof(spec), 44)
     x, info = gpu_solve(spec, 0.0, 1.0, f, poisson=True, precision=1)
     pspec = dict(spec)
@@ -244,6 +248,20 @@ def test_mixed_precision_poisson():
     say("mixed poisson", info, rel(x, xs))
     assert info["status"] == 0
     assert rel(x, xs) <= 1e-8
+
+
+@pytest.mark.parametrize("P", [3, 7])
+def test_mixed_precision_helmholtz_chunked(P):
+    # ragged element counts on a stretched mesh with a Dirichlet axis
+    spec = make_spec((5, 3, 7), P, (0, 0, 1), True)
+    lam = 30.0
+    f = synth.uniform_field(ndof(spec), 91 + P)
+    x, info = gpu_solve(spec, lam, 1.0, f, precision=1)
+    M = dense.mass_diag(spec)
+    say("mixed helmholtz P=%d" % P, info)
+    assert info["status"] == 0 and info["outer_iters"] >= 1
+    assert pcg.true_rel_res(naive.Operator(spec, lam, 1.0).apply, x, M * f, M) <= 1.2e-10
+    assert rel(x, kron.FDM(spec, lam).solve(M * f)) <= 1e-9
 
 
 def test_stretched_large_helmholtz_full_size():
