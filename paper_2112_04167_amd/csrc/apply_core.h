@@ -389,13 +389,14 @@ __device__ __forceinline__ void load_nb(const ApplyArgs<T> &A, int el, int k, in
 // x-neighbour lines of a work-group of consecutive elements.  A face whose
 // neighbour is the adjacent element of the same group (same row) is read from
 // LDS in phase B (in_lo / in_hi).  Of the other ends, at most one is read here
-// (the low one if it lies outside the group, else the high one) with an
-// unconditional load (a thread with no such end reads one address in every
-// lane), so it is in flight with the other neighbour lines; a second outside
-// end (a group starting at the last element of a row, or nx = 1) is flagged
-// in far_hi and read in phase B.  Inside a group only its two end elements
-// need a line from global memory, which saves most of this access's L1
-// traffic (its lanes touch one cache line each).
+// (the low one if it lies outside the group, else the high one), in flight
+// with the other neighbour lines; a second outside end (a group starting at
+// the last element of a row, or nx = 1) is flagged in far_hi and read in
+// phase B.  Inside a group only its two end elements need a line from global
+// memory, which saves most of this access's L1 traffic (its lanes touch one
+// cache line each).  Threads with no outside end issue no load (at P = 7 a
+// wave is one element, so whole waves skip it), and a line's nodes are
+// contiguous, so its loads merge into 16-byte ones.
 template <int P, typename T, bool NUF>
 __device__ __forceinline__ void load_nb_x(const ApplyArgs<T> &A, int el, int ex, int nx, int el_loc,
                                           int EB, int off, bool &in_lo, bool &in_hi, bool &far_hi,
@@ -409,20 +410,16 @@ __device__ __forceinline__ void load_nb_x(const ApplyArgs<T> &A, int el, int ex,
     in_hi = khi == 1 && ex < nx - 1 && el_loc + 1 < EB;
     const bool g_lo = klo == 1 && !in_lo, g_hi = khi == 1 && !in_hi;
     far_hi = g_lo && g_hi;
-    size_t b = 0;
-    int st = 0;
-    if (g_lo) {
-        b = (size_t)(el + (kL - ex)) * N3 + off;
-        st = 1;
-    } else if (g_hi) {
-        b = (size_t)(el + (kR - ex)) * N3 + off;
-        st = 1;
-    }
     T v[n];
 #pragma unroll
-    for (int q = 0; q < n; ++q) v[q] = A.x[b + q * st];
+    for (int q = 0; q < n; ++q) v[q] = 0;
     T nuN = A.nu_c;
-    if constexpr (NUF) nuN = A.nu[b + (g_lo ? P : 0)];
+    if (g_lo || g_hi) {
+        const size_t b = (size_t)(el + ((g_lo ? kL : kR) - ex)) * N3 + off;
+#pragma unroll
+        for (int q = 0; q < n; ++q) v[q] = A.x[b + q];
+        if constexpr (NUF) nuN = A.nu[b + (g_lo ? P : 0)];
+    }
     T sP = 0, s0 = 0;
 #pragma unroll
     for (int q = 0; q < n; ++q) {
@@ -587,8 +584,15 @@ __device__ __forceinline__ void apply_group(const ApplyArgs<T> &A, int grp, T *x
             load_nb<P, T, NUF>(A, el, ey, ny, A.geo.bc[1], nx, j * NL + i, n, fy, TB());
             load_nb<P, T, NUF>(A, el, ez, nz, A.geo.bc[2], nx * ny, l, NL, fz, TB());
         }
-        // the element's geometry (every thread loads it, one writes it)
-        const int ke[3] = {ex, ey, ez};
+        // the element's geometry (every thread loads it, one writes it).
+        // When a wave holds exactly one element (P = 7) its indices are made
+        // wave-uniform, so the loads become scalar loads instead of vector
+        // loads that each cost the address path a full wave instruction.
+        int ke[3] = {ex, ey, ez};
+        if constexpr (NL == 64) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) ke[d] = __builtin_amdgcn_readfirstlane(ke[d]);
+        }
         ElGeo<T> g;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
