@@ -505,6 +505,18 @@ __device__ __forceinline__ void line_apply(const ApplyArgs<T> &A, const T (&u)[P
     }
 }
 
+// Whole-element 16-byte chunks: possible when all lines of an element lie in
+// one wave (64 a multiple of (P+1)^2: P = 3, 7) and a line splits into
+// 16-byte chunks.  The own element is then loaded, and y stored, as chunks
+// that consecutive lanes take in order (a quarter or half of the memory
+// instructions of one node per lane), transposed through the element's LDS
+// slot by the wave itself.
+template <int P, typename T>
+constexpr bool chunk_ok()
+{
+    return (64 % ((P + 1) * (P + 1)) == 0) && ((P + 1) % (16 / (int)sizeof(T)) == 0);
+}
+
 // LDS layout of an element: node (a,b,c) at a + b*SB + c*SC with an odd row
 // stride, so that the x-, y- and z-line access patterns of a wave fall on
 // distinct banks.
@@ -526,7 +538,7 @@ struct Lds {
 // neighbour lines just before its sweep instead of all up front (fewer
 // registers, less latency overlap).
 template <int P, typename T, bool NUF, int EPI, int EBX = Shape<P>::EB, bool LAZY = false,
-          bool FRESH = false>
+          bool FRESH = false, bool CHUNK = false>
 __device__ __forceinline__ void apply_group(const ApplyArgs<T> &A, int grp, T *xs, T *ys, T *nus,
                                             ElGeo<T> *geo, double (&red)[4])
 {
@@ -540,6 +552,11 @@ __device__ __forceinline__ void apply_group(const ApplyArgs<T> &A, int grp, T *x
     using S = Shape<P>;
     constexpr int n = S::n, NL = S::NL, N3 = S::N3, EB = EBX, NT = EBX * NL;
     static_assert(EBX >= 1 && EBX <= S::EB, "group size");
+    static_assert(!CHUNK || (chunk_ok<P, T>() && EPI != EPI_RESID), "chunked layout");
+    constexpr int V = 16 / (int)sizeof(T);  // nodes per 16-byte chunk
+    using VT = T __attribute__((ext_vector_type(16 / sizeof(T))));
+    // the GLL weights, for the tangential weight product of each thread
+    __shared__ T s_w[S::n];
     constexpr int SB = Lds<P>::SB, SC = Lds<P>::SC, E3 = Lds<P>::E3;
     red[0] = red[1] = red[2] = red[3] = 0.0;
     const int tid = threadIdx.x;
@@ -560,7 +577,10 @@ __device__ __forceinline__ void apply_group(const ApplyArgs<T> &A, int grp, T *x
     T *xsl = xs + el_loc * E3;
     T *ysl = ys + el_loc * E3;
     T *nsl = nus + (NUF ? el_loc * E3 : 0);
-    const T wt = Wm<P, T>(i) * Wm<P, T>(j);
+    if (tid == 0) {
+#pragma unroll
+        for (int k = 0; k < n; ++k) s_w[k] = (T)kGll<P>.w[k];
+    }
 
     // phase A: own z-line (a=i, b=j) into registers and LDS; all neighbour
     // lines this thread will need (x-line (b=i,c=j), y-line (a=i,c=j),
@@ -573,8 +593,10 @@ __device__ __forceinline__ void apply_group(const ApplyArgs<T> &A, int grp, T *x
     constexpr bool XL = sizeof(T) == 8;
     bool x_in_lo = false, x_in_hi = false, x_far_hi = false;
     if (active) {
+        if constexpr (!CHUNK) {
 #pragma unroll
-        for (int c = 0; c < n; ++c) uz[c] = xe[c * NL + l];
+            for (int c = 0; c < n; ++c) uz[c] = xe[c * NL + l];
+        }
         if constexpr (!LAZY) {
             if constexpr (XL)
                 load_nb_x<P, T, NUF>(A, el, ex, nx, el_loc, EB, j * NL + i * n, x_in_lo, x_in_hi,
@@ -605,18 +627,36 @@ __device__ __forceinline__ void apply_group(const ApplyArgs<T> &A, int grp, T *x
             g.rhoR[d] = g.h[d] * A.geo.ih[d][kR];
         }
         if (l == 0) geo[el_loc] = g;
+        if constexpr (CHUNK) {
+            // chunk r of this thread: nodes f..f+V-1 of the element, one row
 #pragma unroll
-        for (int c = 0; c < n; ++c) {
-            xsl[i + j * SB + c * SC] = uz[c];
-            if constexpr (NUF) {
-                nz_l[c] = A.nu[(size_t)el * N3 + c * NL + l];
-                nsl[i + j * SB + c * SC] = nz_l[c];
-            } else {
-                nz_l[c] = 0;
+            for (int r = 0; r < n / V; ++r) {
+                const int f = V * (l + NL * r);
+                const int o = f % n + ((f / n) % n) * SB + (f / NL) * SC;
+                const VT v = *reinterpret_cast<const VT *>(xe + f);
+#pragma unroll
+                for (int k = 0; k < V; ++k) xsl[o + k] = v[k];
+                if constexpr (NUF) {
+                    const VT w = *reinterpret_cast<const VT *>(A.nu + (size_t)el * N3 + f);
+#pragma unroll
+                    for (int k = 0; k < V; ++k) nsl[o + k] = w[k];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < n; ++c) {
+                xsl[i + j * SB + c * SC] = uz[c];
+                if constexpr (NUF) {
+                    nz_l[c] = A.nu[(size_t)el * N3 + c * NL + l];
+                    nsl[i + j * SB + c * SC] = nz_l[c];
+                } else {
+                    nz_l[c] = 0;
+                }
             }
         }
     }
     __syncthreads();
+    const T wt = s_w[i] * s_w[j];  // product of the two tangential GLL weights
 
     // phase B: x-lines (b=i, c=j)
     if (active) {
@@ -663,6 +703,13 @@ __device__ __forceinline__ void apply_group(const ApplyArgs<T> &A, int grp, T *x
     if (active) {
         if constexpr (LAZY)
             load_nb<P, T, NUF>(A, el, ez, nz, A.geo.bc[2], nx * ny, l, NL, fz, TB());
+        if constexpr (CHUNK) {
+#pragma unroll
+            for (int c = 0; c < n; ++c) {
+                uz[c] = xsl[i + j * SB + c * SC];
+                nz_l[c] = NUF ? nsl[i + j * SB + c * SC] : (T)0;
+            }
+        }
         T out[n];
         T vs;
         const ElGeo<T> &G = geo[el_loc];
@@ -670,6 +717,31 @@ __device__ __forceinline__ void apply_group(const ApplyArgs<T> &A, int grp, T *x
         const T Jw = G.h[0] * G.h[1] * G.h[2] * (T)0.125 * wt;
         const double iJw = EPI == EPI_RESID ? 1.0 / (double)Jw : 0.0;
         T *__restrict__ ye = A.y + (size_t)el * N3;
+        if constexpr (CHUNK) {
+            // y of this thread's z-line into its own accumulator slots, then
+            // out as chunks; the element's lines are all in this wave, whose
+            // LDS accesses complete in order, so no barrier is needed
+#pragma unroll
+            for (int c = 0; c < n; ++c) {
+                const T m = Jw * Wm<P, T>(c);
+                T v = fma(vs, out[c], ysl[i + j * SB + c * SC]);
+                v = fma(A.lambda * m, uz[c], v);
+                ysl[i + j * SB + c * SC] = v;
+                if constexpr (EPI == EPI_CG) {
+                    red[0] += (double)uz[c] * (double)v;
+                    red[1] += (double)v;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < n / V; ++r) {
+                const int f = V * (l + NL * r);
+                const int o = f % n + ((f / n) % n) * SB + (f / NL) * SC;
+                VT v;
+#pragma unroll
+                for (int k = 0; k < V; ++k) v[k] = ysl[o + k];
+                __builtin_nontemporal_store(v, reinterpret_cast<VT *>(ye + f));
+            }
+        } else {
 #pragma unroll
         for (int c = 0; c < n; ++c) {
             const T m = Jw * Wm<P, T>(c);
@@ -692,6 +764,7 @@ __device__ __forceinline__ void apply_group(const ApplyArgs<T> &A, int grp, T *x
                 red[2] += rm * im;
                 red[3] += im * im;
             }
+        }
         }
     }
 }

@@ -44,7 +44,7 @@
 
 namespace dg {
 
-template <int P, typename T, bool NUF, int EPI>
+template <int P, typename T, bool NUF, int EPI, bool CH>
 __global__ void __launch_bounds__(Shape<P>::NTP) k_apply(ApplyArgs<T> A)
 {
     using S = Shape<P>;
@@ -61,7 +61,8 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_apply(ApplyArgs<T> A)
     const int slot = xcd_remap(blockIdx.x, A.ngroups);
     const int grp = A.order ? A.order[slot] : slot;
     double red[4];
-    apply_group<P, T, NUF, EPI, Shape<P>::EB, apply_lazy<P, T>()>(A, grp, xs, ys, nus, geo, red);
+    apply_group<P, T, NUF, EPI, Shape<P>::EB, apply_lazy<P, T>(), false, CH>(A, grp, xs, ys, nus,
+                                                                            geo, red);
     if constexpr (EPI == EPI_CG) {
         double red2[2] = {red[0], red[1]};
         publish_partials<2>(red2, A.partial, gridDim.x, red_sh);
@@ -222,14 +223,37 @@ static ApplyArgs<T> make_args(const MeshDev &m, const int bc[3], double lambda, 
     return a;
 }
 
+// The own element is loaded and y stored in 16-byte chunks where the degree
+// allows it (chunk_ok), the vectors are 16-byte aligned, and the epilogue
+// stores y as computed (not the residual form).
+template <int P, typename T, int EPI>
+static bool use_chunks(const ApplyArgs<T> &a)
+{
+    if constexpr (!chunk_ok<P, T>() || EPI == EPI_RESID) {
+        return false;
+    } else {
+        auto al = [](const void *p) { return ((uintptr_t)p & 15) == 0; };
+        return al(a.x) && al(a.y) && (a.nu == nullptr || al(a.nu));
+    }
+}
+
 template <int P, typename T, int EPI>
 static void launch_apply_P(const ApplyArgs<T> &a, bool nuf, hipStream_t s)
 {
     dim3 grid(a.ngroups), block(Shape<P>::NTP);
+    if constexpr (chunk_ok<P, T>() && EPI != EPI_RESID) {
+        if (use_chunks<P, T, EPI>(a)) {
+            if (nuf)
+                hipLaunchKernelGGL((k_apply<P, T, true, EPI, true>), grid, block, 0, s, a);
+            else
+                hipLaunchKernelGGL((k_apply<P, T, false, EPI, true>), grid, block, 0, s, a);
+            return;
+        }
+    }
     if (nuf)
-        hipLaunchKernelGGL((k_apply<P, T, true, EPI>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_apply<P, T, true, EPI, false>), grid, block, 0, s, a);
     else
-        hipLaunchKernelGGL((k_apply<P, T, false, EPI>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_apply<P, T, false, EPI, false>), grid, block, 0, s, a);
 }
 
 template <typename T, int EPI>

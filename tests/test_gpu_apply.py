@@ -143,3 +143,41 @@ def test_mesh_coordinates():
     for a, b in ((X, Xr), (Y, Yr), (Z, Zr)):
         assert np.abs(a - b).max() <= 1e-15
     mesh.destroy()
+
+
+@pytest.mark.parametrize("P", [3, 7])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_apply_unaligned_vectors(P, prec):
+    # at P = 3 and 7 aligned vectors take the 16-byte chunk path for the own
+    # element and y; vectors offset by one value (not 16-byte aligned) take
+    # the per-line path.  Both must agree with each other bitwise (the same
+    # arithmetic per node) and with the oracle.
+    import paper_2112_04167_amd as dg
+    torch, dev = torch_dev()
+    spec = make_spec((3, 2, 3), P, (0, 0, 1), True)
+    N = ndof(spec)
+    dt = torch.float64 if prec == 0 else torch.float32
+    x = synth.uniform_field(N, 23)
+    nuv = np.random.default_rng(3).uniform(0.5, 2.0, N)
+    mesh = dg.mesh_from_spec(spec)
+    for nu in (None, nuv):
+        xa = torch.from_numpy(x).to(dev, dt)
+        nua = None if nu is None else torch.from_numpy(nu).to(dev, dt)
+        ya = torch.zeros(N, dtype=dt, device=dev)
+        dg.helmholtz_apply(mesh, 2.5, nua, 1.3, xa, ya, precision=prec)
+        big_x = torch.zeros(N + 1, dtype=dt, device=dev)
+        big_y = torch.zeros(N + 1, dtype=dt, device=dev)
+        big_x[1:] = xa
+        nub = None
+        if nua is not None:
+            nub = torch.zeros(N + 1, dtype=dt, device=dev)
+            nub[1:] = nua
+        assert big_x[1:].data_ptr() % 16 != 0
+        dg.helmholtz_apply(mesh, 2.5, None if nub is None else nub[1:], 1.3, big_x[1:], big_y[1:],
+                           precision=prec)
+        torch.cuda.synchronize()
+        assert torch.equal(ya, big_y[1:]), "chunked and per-line paths differ"
+        if prec == 0:
+            yr = naive.Operator(spec, 2.5, 1.3 if nu is None else nu).apply(x)
+            assert np.abs(ya.cpu().numpy() - yr).max() <= 1e-12 * np.abs(yr).max()
+    mesh.destroy()
