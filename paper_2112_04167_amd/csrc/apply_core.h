@@ -743,28 +743,28 @@ __device__ __forceinline__ void apply_group(const ApplyArgs<T> &A, int grp, T *x
             }
         } else {
 #pragma unroll
-        for (int c = 0; c < n; ++c) {
-            const T m = Jw * Wm<P, T>(c);
-            T v = fma(vs, out[c], ysl[i + j * SB + c * SC]);
-            v = fma(A.lambda * m, uz[c], v);
-            if constexpr (EPI == EPI_STORE) {
-                __builtin_nontemporal_store(v, &ye[c * NL + l]);
-            } else if constexpr (EPI == EPI_CG) {
-                __builtin_nontemporal_store(v, &ye[c * NL + l]);
-                red[0] += (double)uz[c] * (double)v;
-                red[1] += (double)v;
-            } else {  // EPI_RESID: y = b - A x
-                const T bv = A.b[(size_t)el * N3 + c * NL + l];
-                const T r = bv - v;
-                ye[c * NL + l] = r;
-                const double im = iJw * (1.0 / kGll<P>.w[c]);  // 1 / M
-                const double rm = (double)r * im;
-                red[0] += rm * rm;
-                red[1] += (double)r;
-                red[2] += rm * im;
-                red[3] += im * im;
+            for (int c = 0; c < n; ++c) {
+                const T m = Jw * Wm<P, T>(c);
+                T v = fma(vs, out[c], ysl[i + j * SB + c * SC]);
+                v = fma(A.lambda * m, uz[c], v);
+                if constexpr (EPI == EPI_STORE) {
+                    __builtin_nontemporal_store(v, &ye[c * NL + l]);
+                } else if constexpr (EPI == EPI_CG) {
+                    __builtin_nontemporal_store(v, &ye[c * NL + l]);
+                    red[0] += (double)uz[c] * (double)v;
+                    red[1] += (double)v;
+                } else {  // EPI_RESID: y = b - A x
+                    const T bv = A.b[(size_t)el * N3 + c * NL + l];
+                    const T r = bv - v;
+                    ye[c * NL + l] = r;
+                    const double im = iJw * (1.0 / kGll<P>.w[c]);  // 1 / M
+                    const double rm = (double)r * im;
+                    red[0] += rm * rm;
+                    red[1] += (double)r;
+                    red[2] += rm * im;
+                    red[3] += im * im;
+                }
             }
-        }
         }
     }
 }
