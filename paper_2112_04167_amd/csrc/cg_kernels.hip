@@ -231,18 +231,21 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_pupdate(CgVecArgs<T> A)
     }
 }
 
-// ---- FP32 update and p-update on 16-byte chunks (4 divides P+1: P = 3, 7)
+// ---- FP32 update and p-update on chunks of V nodes (V = 4 where 4 divides
+// P+1: P = 3, 7; V = 2 where only 2 does: P = 5)
 //
 // The kernels above give each lane one node per access (4 bytes in FP32), so
 // a wave's load covers 256 bytes.  Here thread t < (P+1)^2 of an element
-// takes the chunk of 4 consecutive nodes a0..a0+3 of row b in plane c0
-// (4t = a0 + (P+1) b + (P+1)^2 c0) and the chunks 4 planes further on, so
-// that consecutive lanes read consecutive 16-byte chunks: one access of a
-// wave covers 1 KiB, with a quarter of the memory instructions.  Same grid,
+// takes the chunk of V consecutive nodes a0..a0+V-1 of row b in plane c0
+// (V t = a0 + (P+1) b + (P+1)^2 c0) and the chunks V planes further on, so
+// that consecutive lanes read consecutive 4V-byte chunks: one access of a
+// wave covers 256 V bytes, with 1/V of the memory instructions.  Same grid,
 // partial-sum slots and arithmetic per node as k_update / k_pupdate.
 
 template <int P>
-constexpr bool kQuad = (P + 1) % 4 == 0;
+constexpr int kChunkV = (P + 1) % 4 == 0 ? 4 : ((P + 1) % 2 == 0 ? 2 : 1);
+template <int P>
+constexpr bool kQuad = kChunkV<P> > 1;
 
 // 1/w_i of the GLL weights, for runtime indices
 template <int P>
@@ -265,8 +268,10 @@ struct QuadCtx {
     size_t base;  // first node of the first chunk; chunk r starts at base + r Q
     int a0, c0;
     double iJb;   // 1 / (J w_b)
-    static constexpr int Q = 4 * Shape<P>::NL;  // nodes between a thread's chunks (4 planes)
-    static constexpr int NR = (P + 1) / 4;      // chunks per thread
+    static constexpr int V = kChunkV<P>;        // nodes per chunk
+    static constexpr int Q = V * Shape<P>::NL;  // nodes between a thread's chunks (V planes)
+    static constexpr int NR = (P + 1) / V;      // chunks per thread
+    using VF = float __attribute__((ext_vector_type(kChunkV<P>)));
 };
 
 template <int P>
@@ -279,7 +284,7 @@ __device__ __forceinline__ QuadCtx<P> quad_ctx(const CgVecArgs<float> &A)
     const int el_loc = tid / S::NL;
     const int t = tid - el_loc * S::NL;
     const int el = blockIdx.x * S::EB + el_loc;
-    const int f = 4 * t;
+    const int f = QuadCtx<P>::V * t;
     q.active = (tid < S::NT) && (el < A.nel);
     q.a0 = f % n;
     q.c0 = f / (n * n);
@@ -294,18 +299,17 @@ __device__ __forceinline__ QuadCtx<P> quad_ctx(const CgVecArgs<float> &A)
     return q;
 }
 
-__device__ __forceinline__ float4 ld4(const float *p) { return *reinterpret_cast<const float4 *>(p); }
-__device__ __forceinline__ void st4(float *p, float4 v) { *reinterpret_cast<float4 *>(p) = v; }
-__device__ __forceinline__ float f4(const float4 &v, int k)
-{
-    return k == 0 ? v.x : k == 1 ? v.y : k == 2 ? v.z : v.w;
-}
+template <typename VF>
+__device__ __forceinline__ VF ldv(const float *p) { return *reinterpret_cast<const VF *>(p); }
+template <typename VF>
+__device__ __forceinline__ void stv(float *p, VF v) { *reinterpret_cast<VF *>(p) = v; }
 
 template <int P, bool SING>
 __global__ void __launch_bounds__(Shape<P>::NTP) k_update_q(CgVecArgs<float> A)
 {
     using Q = QuadCtx<P>;
-    constexpr int NC = SING ? 5 : 2, NR = Q::NR;
+    using VF = typename Q::VF;
+    constexpr int NC = SING ? 5 : 2, NR = Q::NR, V = Q::V;
     __shared__ double sh[16 * NC];
     if (A.sc->done) return;
     const float alpha = (float)A.sc->alpha;
@@ -315,44 +319,41 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_update_q(CgVecArgs<float> A)
 #pragma unroll
     for (int k = 0; k < NC; ++k) red[k] = 0.0;
     if (c.active) {
-        float4 pv[NR], xv[NR], rv[NR], qv[NR], dv[NR];
+        VF pv[NR], xv[NR], rv[NR], qv[NR], dv[NR];
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             const size_t i = c.base + (size_t)r * Q::Q;
-            pv[r] = ld4(A.p + i);
-            xv[r] = ld4(A.x + i);
-            rv[r] = ld4(A.r + i);
-            qv[r] = ld4(A.q + i);
-            dv[r] = ld4(A.d + i);
+            pv[r] = ldv<VF>(A.p + i);
+            xv[r] = ldv<VF>(A.x + i);
+            rv[r] = ldv<VF>(A.r + i);
+            qv[r] = ldv<VF>(A.q + i);
+            dv[r] = ldv<VF>(A.d + i);
         }
-        float4 xo[NR], ro[NR];
+        VF xo[NR], ro[NR];
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            float xn[4], rn[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                xn[k] = fmaf(alpha, f4(pv[r], k), f4(xv[r], k));
-                float r0 = f4(rv[r], k);
+            for (int k = 0; k < V; ++k) {
+                xo[r][k] = fmaf(alpha, pv[r][k], xv[r][k]);
+                float r0 = rv[r][k];
                 if (SING) r0 = (float)((double)r0 - mr);
-                rn[k] = fmaf(-alpha, f4(qv[r], k), r0);
+                ro[r][k] = fmaf(-alpha, qv[r][k], r0);
             }
-            xo[r] = make_float4(xn[0], xn[1], xn[2], xn[3]);
-            ro[r] = make_float4(rn[0], rn[1], rn[2], rn[3]);
         }
 #pragma unroll
-        for (int r = 0; r < NR; ++r) st4(A.x + c.base + (size_t)r * Q::Q, xo[r]);
+        for (int r = 0; r < NR; ++r) stv<VF>(A.x + c.base + (size_t)r * Q::Q, xo[r]);
 #pragma unroll
-        for (int r = 0; r < NR; ++r) st4(A.r + c.base + (size_t)r * Q::Q, ro[r]);
-        double iwa[4];
+        for (int r = 0; r < NR; ++r) stv<VF>(A.r + c.base + (size_t)r * Q::Q, ro[r]);
+        double iwa[V];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) iwa[k] = c_invw<P>.v[c.a0 + k];
+        for (int k = 0; k < V; ++k) iwa[k] = c_invw<P>.v[c.a0 + k];
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            const double iJbc = c.iJb * c_invw<P>.v[c.c0 + 4 * r];
+            const double iJbc = c.iJb * c_invw<P>.v[c.c0 + V * r];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const float rk = f4(ro[r], k);
-                const double rd = (double)rk * (double)f4(dv[r], k);
+            for (int k = 0; k < V; ++k) {
+                const float rk = ro[r][k];
+                const double rd = (double)rk * (double)dv[r][k];
                 const double im = iJbc * iwa[k];
                 const double rm = (double)rk * im;
                 if (SING) {
@@ -375,34 +376,35 @@ template <int P, bool SING>
 __global__ void __launch_bounds__(Shape<P>::NTP) k_pupdate_q(CgVecArgs<float> A)
 {
     using Q = QuadCtx<P>;
-    constexpr int NR = Q::NR;
+    using VF = typename Q::VF;
+    constexpr int NR = Q::NR, V = Q::V;
     if (A.sc->done) return;
     const float beta = (float)A.sc->beta;
     const double mr = A.sc->mean_r;
     const Q c = quad_ctx<P>(A);
     if (!c.active) return;
-    float4 rv[NR], pv[NR], dv[NR];
+    VF rv[NR], pv[NR], dv[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         const size_t i = c.base + (size_t)r * Q::Q;
-        rv[r] = ld4(A.r + i);
-        pv[r] = ld4(A.p + i);
-        dv[r] = ld4(A.d + i);
+        rv[r] = ldv<VF>(A.r + i);
+        pv[r] = ldv<VF>(A.p + i);
+        dv[r] = ldv<VF>(A.d + i);
     }
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-        float o[4];
+        VF o;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            float rk = f4(rv[r], k);
+        for (int k = 0; k < V; ++k) {
+            float rk = rv[r][k];
             if (SING) rk = (float)((double)rk - mr);
-            o[k] = fmaf(beta, f4(pv[r], k), rk * f4(dv[r], k));
+            o[k] = fmaf(beta, pv[r][k], rk * dv[r][k]);
         }
-        st4(A.p + c.base + (size_t)r * Q::Q, make_float4(o[0], o[1], o[2], o[3]));
+        stv<VF>(A.p + c.base + (size_t)r * Q::Q, o);
     }
 }
 
-// chunked kernels apply: FP32, 4 | P+1, a stored 1/diag, 16-byte aligned
+// chunked kernels apply: FP32, 2 | P+1, a stored 1/diag, 16-byte aligned
 // vectors
 template <typename T>
 bool use_quad(int P, const CgVecArgs<T> &a, bool update)
@@ -410,7 +412,7 @@ bool use_quad(int P, const CgVecArgs<T> &a, bool update)
     if constexpr (sizeof(T) != 4) {
         return false;
     } else {
-        if ((P + 1) % 4 != 0 || !a.d) return false;
+        if ((P + 1) % 2 != 0 || !a.d) return false;
         auto al = [](const void *p) { return ((uintptr_t)p & 15) == 0; };
         bool ok = al(a.r) && al(a.p) && al(a.d);
         if (update) ok = ok && al(a.x) && al(a.q);

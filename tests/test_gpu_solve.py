@@ -234,9 +234,9 @@ def test_mixed_precision_fp64_continuation():
 
 
 # P = 3 and 7 run the FP32 update / p-update on 16-byte chunks (4 | P+1),
-# P = 5 the per-line kernels; 27 elements leave the last work-group partly
-# empty for every P
-@pytest.mark.parametrize("P", [5, 3, 7])
+# P = 5 on 8-byte chunks (2 | P+1), P = 4 the per-line kernels; 27 elements
+# leave the last work-group partly empty for every P
+@pytest.mark.parametrize("P", [5, 3, 7, 4])
 def test_mixed_precision_poisson(P):
     spec = make_spec((3, 3, 3), P, (0, 1, 0), False)
     f = synth.uniform_field(ndof(spec), 44)
@@ -250,7 +250,7 @@ def test_mixed_precision_poisson(P):
     assert rel(x, xs) <= 1e-8
 
 
-@pytest.mark.parametrize("P", [3, 7])
+@pytest.mark.parametrize("P", [3, 5, 7])
 def test_mixed_precision_helmholtz_chunked(P):
     # ragged element counts on a stretched mesh with a Dirichlet axis
     spec = make_spec((5, 3, 7), P, (0, 0, 1), True)
