@@ -558,12 +558,39 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_restart64(CgVecArgs<double> A
     publish_partials<4>(red, A.partial, gridDim.x, sh);
 }
 
+// Sums of NC partial-sum arrays partial[c * nblk + 0..nblk) taken by the
+// calling work-group, this thread's share in t[c].  The loads of all
+// components are issued together (summing one component after another would
+// wait for one L2 round trip per component); two accumulators per component,
+// combined in a fixed order, so the result does not depend on timing.
+template <int NC>
+__device__ __forceinline__ void sum_partials(const double *partial, int nblk, double (&t)[NC])
+{
+    double a[NC], b[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) a[c] = b[c] = 0.0;
+    const int B = blockDim.x;
+    int k = threadIdx.x;
+    for (; k + B < nblk; k += 2 * B) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            a[c] += partial[(size_t)c * nblk + k];
+            b[c] += partial[(size_t)c * nblk + k + B];
+        }
+    }
+    if (k < nblk) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) a[c] += partial[(size_t)c * nblk + k];
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) t[c] = a[c] + b[c];
+}
+
 __global__ void __launch_bounds__(1024) k_finish_restart64(const double *partial, int nblk, CgScalars *sc)
 {
     __shared__ double sh[16 * 4];
     double t[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) t[c] = sum_strided(partial + (size_t)c * nblk, nblk);
+    sum_partials<4>(partial, nblk, t);
     block_sum<4>(t, sh);
     if (threadIdx.x != 0) return;
     sc->rho = t[0];
@@ -588,8 +615,7 @@ __global__ void __launch_bounds__(1024) k_finish_replace(const double *partial, 
 {
     __shared__ double sh[16 * 4];
     double t[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) t[c] = sum_strided(partial + (size_t)c * nblk, nblk);
+    sum_partials<4>(partial, nblk, t);
     block_sum<4>(t, sh);
     if (threadIdx.x != 0) return;
     double rz = t[0], mr = 0.0;
@@ -650,8 +676,7 @@ __global__ void __launch_bounds__(1024) k_finish(const double *partial, int nblk
     __shared__ double sh[16 * NC];
     if ((OP == FIN_APPLY || OP == FIN_UPDATE) && sc->done) return;
     double tot[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) tot[c] = sum_strided(partial + (size_t)c * nblk, nblk);
+    sum_partials<NC>(partial, nblk, tot);
     block_sum<NC>(tot, sh);
     if (threadIdx.x != 0) return;
     if constexpr (OP == FIN_APPLY) {
