@@ -128,9 +128,9 @@ size_t dg_solve_footprint(const dg_mesh *m, int precision, int nrhs);
    (DG_FP32), x != y.  nu_field: device nodal viscosity of the same type, or
    NULL for the constant nu_const (> 0).  stream: HIP stream (NULL = the
    mesh's stream).  Asynchronous: returns once the kernel is enqueued.
-   Performance only: at P = 3 and 7, 16-byte-aligned x, y and nu_field (as
-   hipMalloc and torch return them) take a faster path of wide loads and
-   stores; any other alignment is accepted and gives the same y to rounding. */
+   Performance only: in FP64 at P = 3 and 7, 16-byte-aligned x, y and
+   nu_field (as hipMalloc and torch return them) take a faster path of wide
+   loads and stores; any other alignment is accepted and gives the same y. */
 int helmholtz_apply(dg_mesh *m, double lambda, const void *nu_field, double nu_const,
                     const void *x, void *y, int precision, void *stream);
 

@@ -508,13 +508,14 @@ __device__ __forceinline__ void line_apply(const ApplyArgs<T> &A, const T (&u)[P
 // Whole-element 16-byte chunks: possible when all lines of an element lie in
 // one wave (64 a multiple of (P+1)^2: P = 3, 7) and a line splits into
 // 16-byte chunks.  The own element is then loaded, and y stored, as chunks
-// that consecutive lanes take in order (a quarter or half of the memory
-// instructions of one node per lane), transposed through the element's LDS
-// slot by the wave itself.
+// that consecutive lanes take in order (half the memory instructions of one
+// node per lane), transposed through the element's LDS slot by the wave
+// itself.  FP64 only: in FP32 the transposes measured 1-2 % slower than the
+// per-line loads and stores they replace.
 template <int P, typename T>
 constexpr bool chunk_ok()
 {
-    return (64 % ((P + 1) * (P + 1)) == 0) && ((P + 1) % (16 / (int)sizeof(T)) == 0);
+    return sizeof(T) == 8 && (64 % ((P + 1) * (P + 1)) == 0) && ((P + 1) % 2 == 0);
 }
 
 // LDS layout of an element: node (a,b,c) at a + b*SB + c*SC with an odd row

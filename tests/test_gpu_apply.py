@@ -148,10 +148,10 @@ def test_mesh_coordinates():
 @pytest.mark.parametrize("P", [3, 7])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_apply_unaligned_vectors(P, prec):
-    # at P = 3 and 7 aligned vectors take the 16-byte chunk path for the own
-    # element and y; vectors offset by one value (not 16-byte aligned) take
-    # the per-line path.  Both must agree with each other bitwise (the same
-    # arithmetic per node) and with the oracle.
+    # at P = 3 and 7 aligned FP64 vectors take the 16-byte chunk path for the
+    # own element and y; vectors offset by one value (not 16-byte aligned)
+    # take the per-line path (as FP32 always does).  Both must agree with
+    # each other bitwise (the same arithmetic per node) and with the oracle.
     import paper_2112_04167_amd as dg
     torch, dev = torch_dev()
     spec = make_spec((3, 2, 3), P, (0, 0, 1), True)
