@@ -73,25 +73,6 @@ __device__ __forceinline__ void block_sum(double (&v)[NC], double *sh /* >= 16*N
     __syncthreads();
 }
 
-// Sum of p[0..n) taken by the calling work-group: thread t adds the entries
-// t, t + B, t + 2B, ... (B = blockDim.x) into four interleaved accumulators
-// (independent loads in flight) and combines them in a fixed order, so the
-// result does not depend on timing.  Valid in every thread for its share.
-__device__ __forceinline__ double sum_strided(const double *p, int n)
-{
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    const int B = blockDim.x;
-    int k = threadIdx.x;
-    for (; k + 3 * B < n; k += 4 * B) {
-        a0 += p[k];
-        a1 += p[k + B];
-        a2 += p[k + 2 * B];
-        a3 += p[k + 3 * B];
-    }
-    for (; k < n; k += B) a0 += p[k];
-    return (a0 + a1) + (a2 + a3);
-}
-
 // Write this work-group's sums to partial[c * nblk + blockIdx.x] (plain
 // stores: the consumer is a later kernel).
 template <int NC>
