@@ -588,10 +588,9 @@ __device__ __forceinline__ void apply_group(const ApplyArgs<T> &A, int grp, T *x
     // z-line (a=i,b=j)) are requested up front so their latency overlaps
     T uz[n], nz_l[n];
     LineNb<T> fx, fy, fz;
-    // FP64: group-internal x-neighbours from LDS (measured faster at every
-    // degree; for FP32, whose lines are half as many bytes, the extra LDS
-    // reads cost more than the saved loads)
-    constexpr bool XL = sizeof(T) == 8;
+    // group-internal x-neighbours are read from LDS in phase B (measured
+    // faster in FP64 at every degree, and in FP32 once the other ends stopped
+    // issuing loads of their own)
     bool x_in_lo = false, x_in_hi = false, x_far_hi = false;
     if (active) {
         if constexpr (!CHUNK) {
@@ -599,11 +598,8 @@ __device__ __forceinline__ void apply_group(const ApplyArgs<T> &A, int grp, T *x
             for (int c = 0; c < n; ++c) uz[c] = xe[c * NL + l];
         }
         if constexpr (!LAZY) {
-            if constexpr (XL)
-                load_nb_x<P, T, NUF>(A, el, ex, nx, el_loc, EB, j * NL + i * n, x_in_lo, x_in_hi,
-                                     x_far_hi, fx, TB());
-            else
-                load_nb<P, T, NUF>(A, el, ex, nx, A.geo.bc[0], 1, j * NL + i * n, 1, fx, TB());
+            load_nb_x<P, T, NUF>(A, el, ex, nx, el_loc, EB, j * NL + i * n, x_in_lo, x_in_hi,
+                                 x_far_hi, fx, TB());
             load_nb<P, T, NUF>(A, el, ey, ny, A.geo.bc[1], nx, j * NL + i, n, fy, TB());
             load_nb<P, T, NUF>(A, el, ez, nz, A.geo.bc[2], nx * ny, l, NL, fz, TB());
         }
@@ -661,15 +657,11 @@ __device__ __forceinline__ void apply_group(const ApplyArgs<T> &A, int grp, T *x
 
     // phase B: x-lines (b=i, c=j)
     if (active) {
-        if constexpr (XL) {
-            if constexpr (LAZY)
-                load_nb_x<P, T, NUF>(A, el, ex, nx, el_loc, EB, j * NL + i * n, x_in_lo, x_in_hi,
-                                     x_far_hi, fx, TB());
-            finish_nb_x<P, T, NUF>(A, el, ex, nx, xsl + i * SB + j * SC, nsl + i * SB + j * SC,
-                                   E3, j * NL + i * n, x_in_lo, x_in_hi, x_far_hi, fx, TB());
-        } else if constexpr (LAZY) {
-            load_nb<P, T, NUF>(A, el, ex, nx, A.geo.bc[0], 1, j * NL + i * n, 1, fx, TB());
-        }
+        if constexpr (LAZY)
+            load_nb_x<P, T, NUF>(A, el, ex, nx, el_loc, EB, j * NL + i * n, x_in_lo, x_in_hi,
+                                 x_far_hi, fx, TB());
+        finish_nb_x<P, T, NUF>(A, el, ex, nx, xsl + i * SB + j * SC, nsl + i * SB + j * SC, E3,
+                               j * NL + i * n, x_in_lo, x_in_hi, x_far_hi, fx, TB());
         T u[n], nl[n], out[n];
 #pragma unroll
         for (int a = 0; a < n; ++a) {
