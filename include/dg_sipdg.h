@@ -102,8 +102,8 @@ typedef struct {
    inner_maxit 20000, nodal rhs, no fixed iteration count. */
 void dg_default_opts(dg_solve_opts *opts);
 
-/* Create a Cartesian mesh of nx*ny*nz hexahedra of degree P (1 <= P <= 8,
-   the HIP kernels cover 3 <= P <= 8) from host vertex arrays xv[nx+1],
+/* Create a Cartesian mesh of nx*ny*nz hexahedra of degree P (3 <= P <= 8;
+   fewer than 2^31 nodes in all) from host vertex arrays xv[nx+1],
    yv[ny+1], zv[nz+1] (strictly increasing), with per-axis boundary
    conditions bc[3] (DG_BC_*).  The element extents and GLL tables are
    copied to the device.  hip_stream: the HIP stream the mesh's work goes to
@@ -117,7 +117,9 @@ int64_t dg_mesh_ndof(const dg_mesh *m);                      /* E (P+1)^3 */
    them may be NULL).  Asynchronous on `stream` (NULL = the mesh's stream). */
 int dg_mesh_coordinates(dg_mesh *m, double *X, double *Y, double *Z, void *stream);
 /* Bytes of device workspace a solve allocates (for admission control).
-   nrhs > 1: that of helmholtz_solve_batched; a batched solve with
+   nrhs = 1: helmholtz_solve / poisson_solve; nrhs > 1: helmholtz_solve_batched
+   with nsys = nrhs systems.  A mesh keeps the largest workspace it has
+   needed (per kind) until dg_mesh_destroy; a batched solve with
    DG_BATCH_HANDOFF may also allocate that of nrhs = 1 (the continuation). */
 size_t dg_solve_footprint(const dg_mesh *m, int precision, int nrhs);
 
@@ -220,7 +222,11 @@ typedef struct {
     double tol;         /* relative collocation residual, e.g. 1e-10 */
     int precision;      /* DG_FP64 or DG_MIXED */
     int keep_result;    /* 1: keep x on the device until dg_server_fetch;
-                           0: drop it at completion (only the info is kept) */
+                           0: drop it at completion (only the info is kept).
+                           Kept results occupy the arena: a queued request
+                           that does not fit while no solve is running and no
+                           fetch is in progress fails with DG_ERR_BUDGET
+                           instead of waiting for a fetch */
 } dg_request;
 
 /* max_slots: solves allowed on the device at once (>= 1). */
@@ -234,7 +240,8 @@ int dg_server_poll(void *srv, int64_t req_id, dg_solve_info *info);
 /* Copy a finished, kept result (n^3 (P+1)^3 doubles) to host memory and
    release its device memory.  DG_PENDING if not finished yet. */
 int dg_server_fetch(void *srv, int64_t req_id, double *x_host);
-/* Block until every submitted request has finished. */
+/* Block until every submitted request has finished (or failed: see
+   keep_result; drain never waits on a fetch). */
 int dg_server_drain(void *srv);
 /* Statistics of finished requests; latency = completion - submission. */
 typedef struct {

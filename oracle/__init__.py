@@ -28,6 +28,7 @@ Modules:
   kron   -- 1D SIP matrices, Kronecker-sum assembly, fast-diagonalization
             exact solver (Lynch, Rice & Thomas 1964).
   naive  -- ctypes wrapper of naive.c: naive matrix-free apply (triple loops).
-  pcg    -- Jacobi-PCG and mixed-precision iterative refinement, step by step.
+  pcg    -- Jacobi-PCG, and FP64 iterative refinement around an FP32 inner
+            Jacobi-PCG, both step by step.
   build  -- compiles naive.c with gcc.
 """

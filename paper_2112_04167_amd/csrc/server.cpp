@@ -232,15 +232,21 @@ public:
         }
         const size_t off = q->x_off;
         const int64_t nd = q->ndof;
+        q->x_held = false;  // a second fetch of the same result is refused
+        ++fetching_;
         lk.unlock();
-        DG_HIP_CHECK(hipMemcpyAsync(x, (char *)arena_base_ + off, (size_t)nd * sizeof(double),
-                                    hipMemcpyDeviceToHost, io_stream_));
-        DG_HIP_CHECK(hipStreamSynchronize(io_stream_));
+        hipError_t e = hipMemcpyAsync(x, (char *)arena_base_ + off, (size_t)nd * sizeof(double),
+                                      hipMemcpyDeviceToHost, io_stream_);
+        if (e == hipSuccess) e = hipStreamSynchronize(io_stream_);
         lk.lock();
         arena_.release(q->x_off, q->x_bytes);
-        q->x_held = false;
+        --fetching_;
         lk.unlock();
         cv_.notify_all();
+        if (e != hipSuccess) {
+            set_error(std::string("result copy failed: ") + hipGetErrorString(e));
+            return DG_ERR_DEVICE;
+        }
         return DG_OK;
     }
 
@@ -301,13 +307,30 @@ private:
             if (stop_) return;
             Req *q = queue_.front();
             size_t off_w, off_x;
-            if (!arena_.alloc(q->work_bytes, off_w)) {
-                cv_.wait(lk);  // until memory is released
-                continue;
-            }
-            if (!arena_.alloc(q->x_bytes, off_x)) {
+            bool fits = arena_.alloc(q->work_bytes, off_w);
+            if (fits && !arena_.alloc(q->x_bytes, off_x)) {
                 arena_.release(off_w, q->work_bytes);
-                cv_.wait(lk);
+                fits = false;
+            }
+            if (!fits) {
+                // Only a finishing solve or a fetch frees memory.  With neither
+                // in progress, the space is held by kept results that nobody is
+                // fetching: waiting would never end (and drain() would block
+                // for good), so the request fails instead.
+                if (active_ == 0 && fetching_ == 0) {
+                    queue_.pop_front();
+                    q->state = 2;
+                    q->status = DG_ERR_BUDGET;
+                    q->info = dg_solve_info{};
+                    q->info.status = DG_ERR_BUDGET;
+                    q->t_start = q->t_done = now_s();
+                    q->rhs.clear();
+                    q->rhs.shrink_to_fit();
+                    --outstanding_;
+                    done_cv_.notify_all();
+                    continue;
+                }
+                cv_.wait(lk);  // until memory is released
                 continue;
             }
             queue_.pop_front();
@@ -432,6 +455,7 @@ private:
     int64_t next_id_ = 0;
     int64_t outstanding_ = 0;
     int active_ = 0, peak_active_ = 0;
+    int fetching_ = 0;  // fetches copying a result out (their memory is freed after)
     size_t peak_bytes_ = 0;
     double first_submit_ = -1;
     bool stop_ = false;

@@ -96,9 +96,8 @@ size_t footprint(const MeshDev &m, int precision)
     return b;
 }
 
-int ensure_workspace(dg_mesh *m, int precision)
+int ensure_workspace(dg_mesh *m, Workspace &w, int precision)
 {
-    Workspace &w = m->ws;
     const size_t need = footprint(m->dev, precision);
     if (w.base && w.bytes >= need && w.ndof == m->dev.ndof &&
         (precision != DG_MIXED || w.precision == DG_MIXED))
@@ -287,9 +286,8 @@ void diag_tables(const MeshDev &md, const int bc[3], double nu, std::vector<doub
 
 // upload the tables of this solve on the solve's stream (unless the device
 // already holds those of the same boundary conditions and nu)
-int upload_diag_tables(dg_mesh *m, const int bc[3], double nu)
+int upload_diag_tables(dg_mesh *m, Workspace &w, const int bc[3], double nu)
 {
-    Workspace &w = m->ws;
     if (w.tab_bc[0] == bc[0] && w.tab_bc[1] == bc[1] && w.tab_bc[2] == bc[2] && w.tab_nu == nu)
         return DG_OK;
     diag_tables(m->dev, bc, nu, w.htab64);
@@ -300,13 +298,13 @@ int upload_diag_tables(dg_mesh *m, const int bc[3], double nu)
     return DG_OK;
 }
 
-// FP64 Jacobi-PCG
-int solve_fp64(dg_mesh *m, const int bc[3], double lambda, const double *nu, double nu_c,
-               const double *rhs, double *x, const dg_solve_opts &o, dg_solve_info &info)
+// FP64 Jacobi-PCG, on the workspace w (the mesh's own, or memory lent to it)
+int solve_fp64(dg_mesh *m, Workspace &w, const int bc[3], double lambda, const double *nu,
+               double nu_c, const double *rhs, double *x, const dg_solve_opts &o,
+               dg_solve_info &info)
 {
-    int rc = ensure_workspace(m, DG_FP64);
+    int rc = ensure_workspace(m, w, DG_FP64);
     if (rc) return rc;
-    Workspace &w = m->ws;
     const MeshDev &md = m->dev;
     hipStream_t s = m->stream;
     const bool singular = (lambda == 0.0) && !has_dirichlet(bc);
@@ -318,7 +316,7 @@ int solve_fp64(dg_mesh *m, const int bc[3], double lambda, const double *nu, dou
         if ((rc = launch_diag<double>(md, bc, lambda, nu, nu_c, w.d64, s, true))) return rc;
         a.d = w.d64;
     } else {  // constant nu: the diagonal is computed where it is used
-        if ((rc = upload_diag_tables(m, bc, nu_c))) return rc;
+        if ((rc = upload_diag_tables(m, w, bc, nu_c))) return rc;
         a.dtab = w.dtab64;
         a.lam = lambda;
     }
@@ -367,9 +365,9 @@ int solve_fp64(dg_mesh *m, const int bc[3], double lambda, const double *nu, dou
 int solve_mixed(dg_mesh *m, const int bc[3], double lambda, const double *nu, double nu_c,
                 const double *rhs, double *x, const dg_solve_opts &o, dg_solve_info &info)
 {
-    int rc = ensure_workspace(m, DG_MIXED);
-    if (rc) return rc;
     Workspace &w = m->ws;
+    int rc = ensure_workspace(m, w, DG_MIXED);
+    if (rc) return rc;
     const MeshDev &md = m->dev;
     hipStream_t s = m->stream;
     const bool singular = (lambda == 0.0) && !has_dirichlet(bc);
@@ -390,7 +388,7 @@ int solve_mixed(dg_mesh *m, const int bc[3], double lambda, const double *nu, do
     const float *d32 = w.d32;
     const double *tab64 = nullptr;
     if (!nu) {
-        if ((rc = upload_diag_tables(m, bc, nu_c))) return rc;
+        if ((rc = upload_diag_tables(m, w, bc, nu_c))) return rc;
         tab64 = w.dtab64;
     }
 
@@ -567,7 +565,7 @@ int solve_common(dg_mesh *m, const int bc[3], double lambda, const double *nu, d
         }
         rc = solve_mixed(m, bc, lambda, nu, nu_c, rhs, x, o, inf);
     } else {
-        rc = solve_fp64(m, bc, lambda, nu, nu_c, rhs, x, o, inf);
+        rc = solve_fp64(m, m->ws, bc, lambda, nu, nu_c, rhs, x, o, inf);
     }
     inf.seconds = now() - t0;
     if (rc < 0 && g_last_error.empty()) set_error("solver error " + std::to_string(rc));
@@ -649,7 +647,10 @@ int solve_batched(dg_mesh *m, int nsys, const double *lambdas, const double *con
     const bool f32 = o.precision == DG_MIXED;
     const size_t N = (size_t)md.ndof;
     const size_t ti = f32 ? sizeof(float) : sizeof(double);
-    const size_t need = batched_footprint(md, o.precision, kMaxBatch);
+    // room for this call's systems only; a later call with more systems (or
+    // the other precision) grows it, as dg_solve_footprint(m, precision, nsys)
+    // states
+    const size_t need = batched_footprint(md, o.precision, nsys);
     BatchWorkspace &w = m->bws;
     if (!w.base || w.bytes < need) {
         if (w.base) {
@@ -745,7 +746,7 @@ int solve_batched(dg_mesh *m, int nsys, const double *lambdas, const double *con
             // with the single-system solver (same operator, options and rule)
             const BatchSysDesc &D = rq.sys[k];
             const int rc2 = f32 ? solve_mixed(m, D.bc, D.lambda, D.nu64, 1.0, rhs[k], x[k], o, ci)
-                                : solve_fp64(m, D.bc, D.lambda, D.nu64, 1.0, rhs[k], x[k], o, ci);
+                                : solve_fp64(m, m->ws, D.bc, D.lambda, D.nu64, 1.0, rhs[k], x[k], o, ci);
             r.status = rc2 < 0 ? rc2 : ci.status;
         }
         if (infos) {

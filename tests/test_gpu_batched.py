@@ -4,9 +4,12 @@ FP64 refinement) against the oracle, and against the same systems solved
 one at a time.
 
 Bars: every system's collocation residual recomputed by the oracle
-<= 1e-10 (x 1.2 for the recomputation's own rounding); velocity results vs
-the exact discrete solution (dense Cholesky) <= 1e-10 relative; pressure
-(singular, kappa ~ 1e5..1e6) vs fast diagonalisation <= 1e-8 relative."""
+<= 1e-10 (x 1.2 for the recomputation's own rounding); every result vs the
+exact discrete solution (dense Cholesky, fast diagonalisation) or the
+oracle's PCG <= 1e-10 relative.  One exception, stated with its kappa and
+measured value: the full-size pressure system (kappa(M^-1 A) = 2.86e5) at
+the rule's tolerance 1e-10 lands at 4-7e-10 from x*; at tol 1e-12 (the
+paper's own tolerance, Sec. 4) it is held to 1e-10."""
 import numpy as np
 import pytest
 
@@ -71,7 +74,10 @@ def test_batched_small_against_exact(precision, handoff):
     Mp = dense.mass_diag(pspec)
     xp = kron.FDM(pspec, 0.0).solve(Mp * fs[3])
     assert infos[3]["status"] == 0
-    assert rel(xs[3], xp) <= 1e-8
+    # kappa = 2.0e3; solo solves of this system measured 1.7e-11 (FP64) and
+    # 1.5e-11 (mixed) from x*
+    say("batched small pressure err vs x*", rel(xs[3], xp))
+    assert rel(xs[3], xp) <= 1e-10
     assert abs(np.dot(Mp, xs[3])) <= 1e-12 * np.linalg.norm(xs[3])
     opp = naive.Operator(pspec, 0.0, 1.0)
     assert pcg.true_rel_res(opp.apply, xs[3], Mp * fs[3], Mp, singular=True) <= 1.2e-10
@@ -91,12 +97,11 @@ def test_batched_equals_solo():
         xd = torch.zeros_like(fd)
         if pois[k]:
             info = dg.poisson_solve(mesh, fd, xd, o)
-            tol = 1e-8
         else:
             info = dg.helmholtz_solve(mesh, lams[k], to_dev(nus[k]), 0.0, fd, xd, o)
-            tol = 2e-10
         assert info["status"] == 0
-        assert rel(xb[k], xd.cpu().numpy()) <= tol, k
+        say("batched vs solo", k, rel(xb[k], xd.cpu().numpy()))
+        assert rel(xb[k], xd.cpu().numpy()) <= 1e-10, k
     mesh.destroy()
 
 
@@ -143,9 +148,77 @@ def test_batched_channel_full_size(handoff):
     opv = naive.Operator(spec, lam, nu)
     for k in range(3):
         assert pcg.true_rel_res(opv.apply, xs[k], M * fs[k], M) <= 1.2e-10
+        # the oracle's Jacobi-PCG with the nodal viscosity (kappa <= 2.84,
+        # about 15 iterations) on the same system
+        xo, io = pcg.pcg(opv.apply, M * fs[k], opv.diag(), M, tol=1e-10)
+        say("velocity", k, "oracle iters", io["iters"], "err vs oracle PCG", rel(xs[k], xo))
+        assert io["status"] == 0 and rel(xs[k], xo) <= 1e-10
     pspec = dict(spec)
     pspec["bc"] = (0, 0, 2)
     opp = naive.Operator(pspec, 0.0, 1.0)
     assert pcg.true_rel_res(opp.apply, xs[3], M * fs[3], M, singular=True) <= 1.2e-10
     xp = kron.FDM(pspec, 0.0).solve(M * fs[3])
-    assert rel(xs[3], xp) <= 1e-8
+    # kappa(M^-1 A) = 2.86e5: at tol 1e-10 the solo solves measured 1.1e-10
+    # (FP64) and 5.7e-10 (mixed) from x*; bound with a margin
+    say("pressure err vs x* at tol 1e-10", rel(xs[3], xp))
+    assert rel(xs[3], xp) <= 1e-9
+
+
+def test_batched_channel_pressure_tight_tolerance():
+    # the same stage at the paper's own tolerance (1e-12, Sec. 4): the
+    # pressure system then meets the 1e-10 parity bar (solo mixed: 5.6e-12)
+    spec = synth.mesh_spec("batched_channel")
+    lams, nus, pois, fs, nu, lam = stage_problem(spec)
+    rc, infos, xs = run_batched(spec, lams, nus, pois, fs, handoff=True, tol=1e-12)
+    say("batched channel tol 1e-12", rc, infos)
+    assert rc == 0
+    pspec = dict(spec)
+    pspec["bc"] = (0, 0, 2)
+    M = dense.mass_diag(pspec)
+    xp = kron.FDM(pspec, 0.0).solve(M * fs[3])
+    say("pressure err vs x* at tol 1e-12", rel(xs[3], xp))
+    assert rel(xs[3], xp) <= 1e-10
+
+
+def test_footprint_matches_device_allocation():
+    # dg_solve_footprint is what the solves allocate (the server admits by it):
+    # compared with the drop in free device memory across each first solve
+    import paper_2112_04167_amd as dg
+    torch, dev = torch_dev()
+    spec = make_spec((16, 16, 16), 5, (0, 0, 1), False)      # 885k nodes per field
+    lams, nus, pois, fs, nu, lam = stage_problem(spec)
+    rhs = [to_dev(f) for f in fs]
+    xs = [torch.zeros_like(r) for r in rhs]
+    nud = [None if v is None else to_dev(v) for v in nus]
+    o = dg.default_opts(precision=1)
+    # warm-up on another mesh: loads the kernels and tunes the batched launch
+    warm = dg.mesh_from_spec(spec)
+    dg.helmholtz_solve_batched(warm, lams, nud, pois, rhs, xs, o)
+    dg.helmholtz_solve(warm, lam, nud[0], 0.0, rhs[0], xs[0], o)
+    warm.destroy()
+    torch.cuda.synchronize()
+
+    def free():
+        torch.cuda.synchronize()
+        return torch.cuda.mem_get_info()[0]
+
+    slack = 8 << 20   # allocation granularity of the device allocator
+    mesh = dg.mesh_from_spec(spec)
+    for nsys in (2, 4):
+        f0 = free()
+        rc, infos = dg.helmholtz_solve_batched(mesh, lams[:nsys], nud[:nsys], pois[:nsys],
+                                               rhs[:nsys], xs[:nsys], o)
+        used = f0 - free()
+        fp = mesh.footprint(dg.DG_MIXED, nsys)
+        say("batched nsys", nsys, "footprint", fp, "allocated", used)
+        assert rc == 0
+        # the workspace grows from the 2-system size to the 4-system size
+        prev = mesh.footprint(dg.DG_MIXED, 2) if nsys == 4 else 0
+        assert fp - prev <= used + slack and used <= fp - prev + slack
+    f0 = free()
+    dg.helmholtz_solve(mesh, lam, nud[0], 0.0, rhs[0], xs[0], o)
+    used = f0 - free()
+    fp = mesh.footprint(dg.DG_MIXED, 1)
+    say("single footprint", fp, "allocated", used)
+    assert fp <= used + slack and used <= fp + slack
+    mesh.destroy()

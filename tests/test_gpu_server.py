@@ -1,10 +1,11 @@
 """GPU tests of the continuous-batching request server.
 
   * results match the oracle's exact discrete solution (fast diagonalisation;
-    periodic cube, nu = 1): <= 1e-10 relative for Helmholtz, <= 1e-8 for
-    the singular Poisson requests; mixed-precision results are held to the
+    periodic cube, nu = 1) to <= 1e-10 relative, Helmholtz and singular
+    Poisson requests alike; mixed-precision results are held to the
     refinement tolerance on the oracle-recomputed collocation residual
-    (<= 1e-10, x 1.2 for the recomputation's rounding) and <= 1e-9 in error;
+    (<= 1e-10, x 1.2 for the recomputation's rounding) and, in error, to the
+    measured value with a margin, kappa stated (1.55e-10 at kappa = 3.5e3);
   * the device right-hand-side generator (SplitMix64) reproduces the host
     implementation of the same published generator bit for bit;
   * a request's result is the same alone and in a mix of concurrent
@@ -33,6 +34,11 @@ def exact(n, P, lam, f):
     return kron.FDM(spec, lam).solve(M * f)
 
 
+def kappa(n, P, lam):
+    ev = kron.FDM(make_spec(n, P, (0, 0, 0)), lam).eigenvalues_generalized()
+    return ev[-1] / ev[0]
+
+
 def server(budget=8 << 30, slots=4):
     import paper_2112_04167_amd as dg
     torch_dev()
@@ -54,8 +60,8 @@ def test_server_results_against_oracle():
         assert rc == 0, (k, info)
         x = srv.fetch(ids[k], n ** 3 * (P + 1) ** 3)
         e = rel(x, exact(n, P, lam, fs[k]))
-        say("server req", k, info["iters"], e)
-        assert e <= (1e-8 if pois else 1e-10)
+        say("server req", k, info["iters"], "kappa", kappa(n, P, lam), "err vs x*", e)
+        assert e <= 1e-10
     st = srv.stats()
     assert st["completed"] == len(reqs) and st["p99"] >= st["p50"] > 0
     srv.destroy()
@@ -112,7 +118,11 @@ def test_server_same_alone_and_in_the_mix(precision):
         M = dense.mass_diag(spec)
         op = naive.Operator(spec, lam, 1.0)
         assert pcg.true_rel_res(op.apply, mixed, M * f, M) <= 1.2e-10
-        assert rel(mixed, exact(n, P, lam, f)) <= 1e-9
+        # kappa(M^-1 A) = 3.5e3: at the 1e-10 residual the mixed result is
+        # measured 1.55e-10 from x* (its FP32 recurrence leaves more of the
+        # residual in low modes than FP64 CG does); bound with a margin
+        say("mixed in the mix: kappa", kappa(n, P, lam), "err vs x*", rel(mixed, exact(n, P, lam, f)))
+        assert rel(mixed, exact(n, P, lam, f)) <= 2.5e-10
     srv.destroy()
 
 
@@ -137,4 +147,42 @@ def test_server_admission_budget():
     with pytest.raises(dg.DGError) as e:
         srv.submit(40, 8, 1.0, None, rhs_seed=1)
     assert e.value.status == dg.DG_ERR_BUDGET
+    srv.destroy()
+
+
+def test_server_held_results_do_not_stall_drain():
+    # kept results fill the arena: a request that no longer fits while nothing
+    # runs fails with DG_ERR_BUDGET instead of waiting for a fetch, so drain()
+    # returns; after a fetch frees memory the same request is served again
+    import paper_2112_04167_amd as dg
+    n, P = 6, 5
+    N = n ** 3 * (P + 1) ** 3
+    xb = ((N * 8 + 255) // 256) * 256
+    probe = dg.mesh_from_spec(make_spec(n, P, (0, 0, 0)))
+    ws = probe.footprint(dg.DG_FP64)
+    probe.destroy()
+    # one request takes geometry + workspace + rhs + x (= ws + 2 xb + small);
+    # every finished request keeps its x (xb): two results fit, a third does not
+    budget = ws + int(3.5 * xb) + (1 << 16)
+    srv = server(budget=budget, slots=1)
+    ids = [srv.submit(n, P, 10.0 + k, None, rhs_seed=k, keep_result=True) for k in range(3)]
+    srv.drain()
+    def status(i):
+        try:
+            return srv.poll(i)[0]
+        except dg.DGError as e:   # the binding raises on a failed request
+            return e.status
+
+    st = [status(i) for i in ids]
+    say("held-result statuses", st, budget)
+    assert st[0] == 0 and st[1] == 0 and st[2] == dg.DG_ERR_BUDGET
+    x0 = srv.fetch(ids[0], N)
+    assert np.all(np.isfinite(x0))
+    with pytest.raises(dg.DGError):   # fetched once: no second copy
+        srv.fetch(ids[0], N)
+    rid = srv.submit(n, P, 12.0, None, rhs_seed=2, keep_result=True)
+    srv.drain()
+    assert srv.poll(rid)[0] == 0
+    f = synth.splitmix64_uniform(N, 2)
+    assert rel(srv.fetch(rid, N), exact(n, P, 12.0, f)) <= 1e-10
     srv.destroy()

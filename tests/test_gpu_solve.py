@@ -3,13 +3,18 @@ mixed-precision refinement against the oracle.
 
 Checks (rule: ||M^-1 r|| <= tol ||M^-1 b||, tol = 1e-10, Sec. 4 of the paper):
   * against the exact discrete solution x* (fast diagonalisation or dense
-    Cholesky): ||x - x*|| <= 1e-10 ||x*|| where the conditioning allows it;
+    Cholesky): ||x - x*|| <= 1e-10 ||x*||, FP64 and mixed alike, with one
+    exception: at the rule's own tolerance the two Poisson systems with
+    kappa(M^-1 A) ~ 6e6 and 3e5 land a little above 1e-10.  Their tests
+    state kappa and the measured error, bound the error by that value with a
+    margin, and show <= 1e-10 at the tighter tolerances the paper itself
+    uses (it solves to 1e-12, Sec. 4);
   * against the oracle's own PCG: same iteration count (+-1) and, in the
     iteration-locked mode (fixed_iters), ||x - x_oracle|| <= 1e-11 ||x_oracle||;
   * the true residual recomputed from x;
   * mixed precision: held to the refinement tolerance on the residual
     recomputed by the oracle (x 1.2 for the recomputation's rounding), and
-    to <= 1e-9 in error against x*;
+    to the same 1e-10 in error against x* as FP64;
   * x on entry is the initial guess: the same rule from any guess, fewer
     iterations from a close one, none from x* itself, x = 0 for b = 0;
   * status codes of the failure modes."""
@@ -44,6 +49,12 @@ def gpu_solve(spec, lam, nu, f, poisson=False, x0=None, **opts):
 
 def rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def kappa(spec, lam):
+    """kappa(M^-1 A) of a constant-nu system (zero mode excluded)."""
+    ev = kron.FDM(spec, lam).eigenvalues_generalized()
+    return ev[-1] / ev[0]
 
 
 def test_small_periodic_manufactured():
@@ -129,12 +140,14 @@ def test_singular_poisson_small():
     pspec["bc"] = (0, 2, 0)
     M = dense.mass_diag(pspec)
     xs = kron.FDM(pspec, 0.0).solve(M * f)
-    assert rel(x, xs) <= 1e-8
+    # kappa = 682; measured 6.0e-12 at tol 1e-11 (7.2e-11 at tol 1e-10)
+    say("poisson small kappa", kappa(pspec, 0.0), "err vs x*", rel(x, xs))
+    assert rel(x, xs) <= 1e-10
     assert abs(np.dot(M, x)) <= 1e-12 * np.linalg.norm(x)
     op = naive.Operator(pspec, 0.0, 1.0)
     xo, io = pcg.pcg(op.apply, M * f, op.diag(), M, tol=1e-11, singular=True)
     assert abs(info["iters"] - io["iters"]) <= 2
-    assert rel(x, xo) <= 1e-9
+    assert rel(x, xo) <= 1e-10
 
 
 def test_singular_poisson_iteration_locked():
@@ -203,14 +216,18 @@ def test_mixed_precision_small(lam):
     M = dense.mass_diag(spec)
     xs = kron.FDM(spec, lam).solve(M * f)
     e = rel(x, xs)
-    say("mixed lam=%g" % lam, info, "err vs x*", e)
+    say("mixed lam=%g" % lam, info, "kappa", kappa(spec, lam), "err vs x*", e)
     assert info["status"] == 0 and info["outer_iters"] >= 1
     assert info["true_rel_res"] <= 1e-10
-    # the refinement tolerance, on the residual recomputed by the oracle; the
-    # error follows through the conditioning of the operator
+    # the refinement tolerance, on the residual recomputed by the oracle, and
+    # the FP64 bar on the error: kappa = 2.5e3, 26, 1.25; measured 4.7e-12,
+    # 1.0e-11, 6.4e-12
     op = naive.Operator(spec, lam, 1.0)
     assert pcg.true_rel_res(op.apply, x, M * f, M) <= 1.2e-10
-    assert e <= 1e-9
+    assert e <= 1e-10
+    # the oracle's step-by-step refinement (FP32 inner PCG) reaches the same x*
+    xi, ii = pcg.iterative_refinement(op.apply, M * f, op.diag(), M, tol=1e-10)
+    assert ii["status"] == 0 and rel(x, xi) <= 1e-10
 
 
 def test_mixed_precision_fp64_continuation():
@@ -225,12 +242,17 @@ def test_mixed_precision_fp64_continuation():
     M = dense.mass_diag(spec)
     op = naive.Operator(spec, lam, 1.0)
     assert pcg.true_rel_res(op.apply, x, M * f, M) <= 1.2e-10
-    assert rel(x, kron.FDM(spec, lam).solve(M * f)) <= 1e-9
+    e = rel(x, kron.FDM(spec, lam).solve(M * f))
+    say("continuation kappa", kappa(spec, lam), "err vs x*", e)
+    assert e <= 1e-10
     # the singular (Poisson) path of the continuation
     xp, infop = gpu_solve(spec, 0.0, 1.0, f, poisson=True, precision=1, inner_maxit=10)
     assert infop["status"] == 0
     assert pcg.true_rel_res(naive.Operator(spec, 0.0, 1.0).apply, xp, M * f, M, singular=True) <= 1.2e-10
     assert abs(np.dot(M, xp)) <= 1e-12 * np.linalg.norm(xp)
+    ep = rel(xp, kron.FDM(spec, 0.0).solve(M * f))
+    say("continuation poisson kappa", kappa(spec, 0.0), "err vs x*", ep)
+    assert ep <= 1e-10
 
 
 # P = 3 and 7 run the FP32 update / p-update on 16-byte chunks (4 | P+1),
@@ -245,9 +267,11 @@ def test_mixed_precision_poisson(P):
     pspec["bc"] = (0, 2, 0)
     M = dense.mass_diag(pspec)
     xs = kron.FDM(pspec, 0.0).solve(M * f)
-    say("mixed poisson", info, rel(x, xs))
+    # kappa = 4.4e3, 832, 1.4e4, 2.1e3 for P = 5, 3, 7, 4; measured
+    # 4.2e-11, 2.6e-11, 4.3e-11, 4.6e-11
+    say("mixed poisson", info, "kappa", kappa(pspec, 0.0), "err vs x*", rel(x, xs))
     assert info["status"] == 0
-    assert rel(x, xs) <= 1e-8
+    assert rel(x, xs) <= 1e-10
 
 
 @pytest.mark.parametrize("P", [3, 5, 7])
@@ -261,7 +285,10 @@ def test_mixed_precision_helmholtz_chunked(P):
     say("mixed helmholtz P=%d" % P, info)
     assert info["status"] == 0 and info["outer_iters"] >= 1
     assert pcg.true_rel_res(naive.Operator(spec, lam, 1.0).apply, x, M * f, M) <= 1.2e-10
-    assert rel(x, kron.FDM(spec, lam).solve(M * f)) <= 1e-9
+    # kappa = 1.8e3, 9.5e3, 3.1e4 for P = 3, 5, 7; measured 4.9e-11, 4.0e-11, 5.1e-11
+    e = rel(x, kron.FDM(spec, lam).solve(M * f))
+    say("mixed helmholtz P=%d kappa" % P, kappa(spec, lam), "err vs x*", e)
+    assert e <= 1e-10
 
 
 def test_stretched_large_helmholtz_full_size():
@@ -285,7 +312,7 @@ def test_initial_guess_helmholtz(precision):
     M = dense.mass_diag(spec)
     xs = kron.FDM(spec, lam).solve(M * f)
     op = naive.Operator(spec, lam, 1.0)
-    bar = 1e-10 if precision == 0 else 1e-9
+    bar = 1e-10   # kappa = 3.7e3; measured from zero: 2.2e-11 (FP64), 2.6e-11 (mixed)
     _, i0 = gpu_solve(spec, lam, 1.0, f, precision=precision)
     # a guess close to x*: same rule, fewer iterations than from zero
     near = xs * (1.0 + 1e-4 * synth.uniform_field(N, 92))
@@ -316,9 +343,10 @@ def test_initial_guess_singular_poisson(precision):
     xs = kron.FDM(pspec, 0.0).solve(M * f)
     guess = xs + 5.0 + 0.1 * synth.uniform_field(N, 94)
     x, info = gpu_solve(spec, 0.0, 1.0, f, poisson=True, precision=precision, x0=guess, tol=1e-11)
-    say("poisson guess", precision, info)
+    # kappa = 682; from zero at tol 1e-11: 6.0e-12 (FP64), 1.2e-11 (mixed)
+    say("poisson guess", precision, info, "err vs x*", rel(x, xs))
     assert info["status"] == 0
-    assert rel(x, xs) <= 1e-8
+    assert rel(x, xs) <= 1e-10
     assert abs(np.dot(M, x)) <= 1e-12 * np.linalg.norm(x)
 
 
@@ -350,3 +378,47 @@ def test_iteration_locked_constant_nu_diagonal(case):
     M = dense.mass_diag(spec)
     xo, _ = pcg.pcg(op.apply, M * f, op.diag(), M, fixed_iters=12)
     assert rel(x, xo) <= 1e-11
+
+
+# The pressure Poisson problem of the 32^3, P = 7 stretched mesh at full size
+# (16.8M nodes, Neumann z, periodic x, y; kappa(M^-1 A) = 5.86e6).  Measured
+# errors against x* at the rule's tolerance 1e-10: 1.3e-10 (FP64, 2738
+# iterations) and 2.3e-10 (mixed, 3455 FP32 iterations); at tol 1e-11:
+# 4.1e-11 and 7.6e-11.  The error of a residual-rule stop scales with kappa,
+# so at 1e-10 the bound is the measured value with a margin; at 1e-11 it is
+# the 1e-10 parity bar.
+@pytest.mark.parametrize("precision", [0, 1])
+def test_stretched_large_poisson_full_size(precision):
+    spec = synth.mesh_spec("stretched_large")
+    f = synth.uniform_field(ndof(spec), synth.SEEDS["large_poisson"])
+    pspec = dict(spec)
+    pspec["bc"] = (0, 0, 2)
+    M = dense.mass_diag(pspec)
+    xs = kron.FDM(pspec, 0.0).solve(M * f)
+    bound = {0: 2e-10, 1: 3.5e-10}[precision]
+    for tol, bar in ((1e-10, bound), (1e-11, 1e-10)):
+        x, info = gpu_solve(spec, 0.0, 1.0, f, poisson=True, precision=precision, tol=tol)
+        e = rel(x, xs)
+        say("large poisson prec", precision, "tol", tol, info, "err vs x*", e)
+        assert info["status"] == 0 and info["true_rel_res"] <= tol
+        assert 2000 <= info["iters"] <= 5000
+        assert abs(np.dot(M, x)) <= 1e-12 * np.linalg.norm(x)
+        assert e <= bar
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_indefinite_operator_reports_not_spd(precision):
+    # a nodal viscosity of -1 with lambda = 0 makes A = -K negative definite:
+    # the first p^T A p is negative and the solve must stop with
+    # DG_ERR_NOT_SPD (the oracle's PCG says the same)
+    spec = make_spec((2, 2, 2), 4, (0, 0, 1), False)
+    N = ndof(spec)
+    nu = -np.ones(N)
+    f = synth.uniform_field(N, 5)
+    _, info = gpu_solve(spec, 0.0, nu, f, precision=precision)
+    say("indefinite", precision, info)
+    assert info["rc"] == -4 and info["status"] == -4
+    op = naive.Operator(spec, 0.0, nu)
+    M = dense.mass_diag(spec)
+    _, io = pcg.pcg(op.apply, M * f, op.diag(), M)
+    assert io["status"] == pcg.ERR_NOT_SPD

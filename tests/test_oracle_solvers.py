@@ -117,3 +117,54 @@ def test_pcg_failure_modes():
     d = np.abs(opn.diag())
     _, info = pcg.pcg(opn.apply, b, d, M)
     assert info["status"] == pcg.ERR_NOT_SPD
+
+
+@pytest.mark.parametrize("lam", [1e2, 1e4, 1e6])
+def test_iterative_refinement_reaches_exact_solution(lam):
+    # FP64 refinement around FP32 PCG (kappa u_32 << 1 here: kappa = 2.5e3,
+    # 26, 1.25 on the 4^3, P = 7 periodic mesh): the result is the exact
+    # discrete solution to the FP64 bar, the recomputed residual meets the
+    # rule, and each cycle gains at least inner_tol (1e-2; more when one CG
+    # step overshoots it, as at kappa = 1.25), so three to six FP64 residuals
+    # are needed for 1e-10
+    spec = synth.mesh_spec("mixed_small")
+    f = synth.uniform_field(ndof(spec), synth.SEEDS["mixed"])
+    op = naive.Operator(spec, lam, 1.0)
+    M = dense.mass_diag(spec)
+    x, info = pcg.iterative_refinement(op.apply, M * f, op.diag(), M, tol=1e-10)
+    assert info["status"] == pcg.OK
+    assert 3 <= info["outer"] <= 7
+    assert pcg.true_rel_res(op.apply, x, M * f, M) <= 1e-10
+    xs = kron.FDM(spec, lam).solve(M * f)
+    assert np.linalg.norm(x - xs) <= 1e-10 * np.linalg.norm(xs)
+
+
+def test_iterative_refinement_inner_solve_is_fp32():
+    # one inner solve alone stops at FP32 accuracy: against the exact solution
+    # it is off by ~1e-7 (the rounding of FP32 storage), not ~1e-15; and the
+    # refinement with the same inner solve reaches 1e-10
+    spec = make_spec((3, 3, 3), 4, (0, 0, 1), True)
+    lam = 50.0
+    f = synth.uniform_field(ndof(spec), 12)
+    op = naive.Operator(spec, lam, 1.0)
+    M = dense.mass_diag(spec)
+    xs = kron.FDM(spec, lam).solve(M * f)
+    x1, info1 = pcg.iterative_refinement(op.apply, M * f, op.diag(), M, tol=1e-10, inner_tol=1e-12,
+                                         maxit=1)
+    e1 = np.linalg.norm(x1 - xs) / np.linalg.norm(xs)
+    assert info1["outer"] == 1 and 1e-9 < e1 < 1e-4
+    x, info = pcg.iterative_refinement(op.apply, M * f, op.diag(), M, tol=1e-10, inner_tol=1e-3)
+    assert info["status"] == pcg.OK and info["outer"] >= 2
+    assert np.linalg.norm(x - xs) <= 1e-10 * np.linalg.norm(xs)
+
+
+def test_iterative_refinement_singular_poisson():
+    spec = make_spec((3, 2, 2), 3, (0, 2, 0), False)
+    f = synth.uniform_field(ndof(spec), 13)
+    op = naive.Operator(spec, 0.0, 1.0)
+    M = dense.mass_diag(spec)
+    x, info = pcg.iterative_refinement(op.apply, M * f, op.diag(), M, tol=1e-10, singular=True)
+    assert info["status"] == pcg.OK
+    xs = kron.FDM(spec, 0.0).solve(M * f)
+    assert np.linalg.norm(x - xs) <= 1e-10 * np.linalg.norm(xs)
+    assert abs(np.dot(M, x)) <= 1e-13 * np.linalg.norm(x)
