@@ -154,6 +154,24 @@ int helmholtz_diag(dg_mesh *m, double lambda, const void *nu_field, double nu_co
 int helmholtz_solve(dg_mesh *m, double lambda, const double *nu_field, double nu_const,
                     const double *rhs, double *x, const dg_solve_opts *opts, dg_solve_info *info);
 
+/* helmholtz_solve for callers that cannot allocate device memory: code under
+   HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+   The same FP64 Jacobi-PCG (opts->precision must be DG_FP64, else
+   DG_ERR_ARG), with every solver buffer (CG vectors, reduction slots, device
+   scalars, diagonal tables) taken from a static device array of 128 MiB that
+   the library holds on each GPU it runs on until the process ends; no
+   hipMalloc, hipFree or other allocating call is made.  Meshes whose FP64
+   solve workspace (dg_solve_footprint(m, DG_FP64, 1)) exceeds 128 MiB -- about
+   3.3M nodes -- are refused with DG_ERR_ARG.  Every call on a GPU shares that
+   GPU's array: calls that overlap on one GPU (two threads, or two streams
+   before the first call has returned) race and give wrong results.  Nothing
+   in the array needs clearing between calls (the solve initialises what it
+   reads).  Arguments, results and statuses as in helmholtz_solve; the
+   result is bitwise that of helmholtz_solve in FP64. */
+int helmholtz_solve_noalloc(dg_mesh *m, double lambda, const double *nu_field, double nu_const,
+                            const double *rhs, double *x, const dg_solve_opts *opts,
+                            dg_solve_info *info);
+
 /* The pressure Poisson problem of the projection substep (Alg. 3): lambda = 0,
    nu = 1, and every Dirichlet axis of the mesh becomes a natural Neumann
    axis (the pressure carries Neumann data).  The system is then singular

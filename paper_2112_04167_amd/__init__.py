@@ -9,4 +9,5 @@ from .binding import (DG_BC_DIRICHLET, DG_BC_NEUMANN, DG_BC_PERIODIC, DG_ERR_ARG
                       DG_FP32, DG_FP64, DG_MIXED, DG_NOT_CONVERGED, DG_OK, DG_PENDING, DGError,
                       Mesh, Server, default_opts, dg_mesh_create, exported_symbols,
                       helmholtz_apply, helmholtz_diag, helmholtz_solve, helmholtz_solve_batched,
+                      helmholtz_solve_noalloc,
                       last_error, lib, mesh_coordinates, mesh_from_spec, poisson_solve)

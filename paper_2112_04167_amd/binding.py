@@ -78,6 +78,9 @@ _SIGS = {
                        ctypes.c_int),
     "helmholtz_solve": ([_VP, ctypes.c_double, _VP, ctypes.c_double, _VP, _VP,
                          ctypes.POINTER(dg_solve_opts), ctypes.POINTER(dg_solve_info)], ctypes.c_int),
+    "helmholtz_solve_noalloc": ([_VP, ctypes.c_double, _VP, ctypes.c_double, _VP, _VP,
+                                 ctypes.POINTER(dg_solve_opts), ctypes.POINTER(dg_solve_info)],
+                                ctypes.c_int),
     "poisson_solve": ([_VP, _VP, _VP, ctypes.POINTER(dg_solve_opts), ctypes.POINTER(dg_solve_info)],
                       ctypes.c_int),
     "helmholtz_solve_batched": ([_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
@@ -240,6 +243,25 @@ def helmholtz_solve(mesh, lam, nu_field, nu_const, rhs, x, opts=None, raise_on_e
                                float(nu_const), _dptr(rhs, torch.float64, mesh.ndof),
                                _dptr(x, torch.float64, mesh.ndof),
                                ctypes.byref(opts) if opts is not None else None, ctypes.byref(info))
+    if raise_on_error:
+        _check(rc, allow_warning=True)
+    d = info.as_dict()
+    d["rc"] = rc
+    return d
+
+
+def helmholtz_solve_noalloc(mesh, lam, nu_field, nu_const, rhs, x, opts=None,
+                            raise_on_error=True):
+    """helmholtz_solve (FP64) with its workspace in the library's static
+    device scratch array: allocates no device memory."""
+    import torch
+    info = dg_solve_info()
+    rc = lib().helmholtz_solve_noalloc(mesh.handle, float(lam),
+                                       _dptr(nu_field, torch.float64, mesh.ndof), float(nu_const),
+                                       _dptr(rhs, torch.float64, mesh.ndof),
+                                       _dptr(x, torch.float64, mesh.ndof),
+                                       ctypes.byref(opts) if opts is not None else None,
+                                       ctypes.byref(info))
     if raise_on_error:
         _check(rc, allow_warning=True)
     d = info.as_dict()

@@ -536,8 +536,11 @@ int solve_mixed(dg_mesh *m, const int bc[3], double lambda, const double *nu, do
     return status;
 }
 
+// lent: workspace memory the caller provides (FP64 solves only); nullptr =
+// the mesh's own workspace, allocated on demand
 int solve_common(dg_mesh *m, const int bc[3], double lambda, const double *nu, double nu_c,
-                 const double *rhs, double *x, const dg_solve_opts *opts, dg_solve_info *info)
+                 const double *rhs, double *x, const dg_solve_opts *opts, dg_solve_info *info,
+                 Workspace *lent = nullptr)
 {
     const double t0 = now();
     if (int rc = check_mesh(m)) return rc;
@@ -558,7 +561,13 @@ int solve_common(dg_mesh *m, const int bc[3], double lambda, const double *nu, d
     }
     dg_solve_info inf{};
     int rc;
-    if (o.precision == DG_MIXED) {
+    if (lent) {
+        if (o.precision != DG_FP64) {
+            set_error("the no-allocation solve is FP64 only");
+            return DG_ERR_ARG;
+        }
+        rc = solve_fp64(m, *lent, bc, lambda, nu, nu_c, rhs, x, o, inf);
+    } else if (o.precision == DG_MIXED) {
         if (!(o.inner_tol > 0.0 && o.inner_tol < 1.0) || o.inner_maxit <= 0) {
             set_error("bad inner solver options");
             return DG_ERR_ARG;
@@ -768,6 +777,44 @@ int solve_batched(dg_mesh *m, int nsys, const double *lambdas, const double *con
 }
 
 }  // namespace
+
+// ---------------------------------------------------- no-allocation solve --
+// Workspace of helmholtz_solve_noalloc: a fixed device array instead of
+// hipMalloc.  Each GPU the library runs on holds its own copy (it comes with
+// the library's code object) until the process ends; every call on that GPU
+// reuses it.  Host code must use its device address (scratch_address), never
+// the symbol itself, which on the host is only a stand-in.
+static constexpr size_t kScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static constexpr int kScratchDevices = 64;
+
+// the device address of `scratch` on the current device, looked up once per
+// device with that device current
+static int scratch_address(void **out)
+{
+    static std::mutex mu;
+    static void *addr[kScratchDevices] = {};
+    int dev = -1;
+    DG_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kScratchDevices) {
+        set_error("device ordinal out of range for the scratch table");
+        return DG_ERR_DEVICE;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            set_error(std::string("scratch address lookup failed: ") + hipGetErrorString(e));
+            return DG_ERR_DEVICE;
+        }
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return DG_OK;
+}
 
 namespace dg {
 
@@ -1043,6 +1090,30 @@ int helmholtz_solve_batched_ex(dg_mesh *m, int nsys, const double *lambdas,
     if (infos)
         for (int k = 0; k < nsys; ++k) infos[k].seconds = now() - t0;
     return rc;
+}
+
+int helmholtz_solve_noalloc(dg_mesh *m, double lambda, const double *nu_field, double nu_const,
+                            const double *rhs, double *x, const dg_solve_opts *opts,
+                            dg_solve_info *info)
+{
+    if (int rc = check_mesh(m)) return rc;
+    const size_t need = footprint(m->dev, DG_FP64);
+    if (need > kScratchBytes) {
+        set_error("helmholtz_solve_noalloc: this mesh needs " + std::to_string(need) +
+                  " bytes of workspace; the scratch array holds " + std::to_string(kScratchBytes) +
+                  " (about 3.3M nodes)");
+        return DG_ERR_ARG;
+    }
+    void *base = nullptr;
+    if (int rc = scratch_address(&base)) return rc;
+    Workspace w;
+    CgScalars host_sc[2];
+    w.base = base;
+    w.bytes = kScratchBytes;
+    w.external = true;
+    w.host_sc = host_sc;
+    w.host_external = true;
+    return solve_common(m, m->dev.bc, lambda, nu_field, nu_const, rhs, x, opts, info, &w);
 }
 
 int poisson_solve(dg_mesh *m, const double *rhs, double *x, const dg_solve_opts *opts,
