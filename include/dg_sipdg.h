@@ -73,6 +73,15 @@ enum {
 
 enum { DG_BC_PERIODIC = 0, DG_BC_DIRICHLET = 1, DG_BC_NEUMANN = 2 };  /* per axis */
 enum { DG_FP64 = 0, DG_FP32 = 1, DG_MIXED = 1 };  /* apply: FP32 data; solve: FP32 inner + FP64 IR */
+/* preconditioner of the CG solves:
+   DG_PC_JACOBI  diag(A) (point Jacobi);
+   DG_PC_FDM     the fast-diagonalisation inverse of the constant-nu operator
+                 on the Cartesian mesh (see helmholtz_fdm_apply): exact for a
+                 constant nu, so CG stops after one or two steps; with a nodal
+                 nu field it uses nu_ref = sqrt(min nu max nu), and CG then
+                 converges at a rate set by max nu / min nu.  FP64 only; needs
+                 at most 512 nodes per mesh line (n_d (P+1) <= 512). */
+enum { DG_PC_JACOBI = 0, DG_PC_FDM = 1 };
 
 typedef struct dg_mesh dg_mesh;  /* opaque */
 
@@ -86,6 +95,7 @@ typedef struct {
     int inner_maxit;    /* mixed (and batched): cap on FP32 CG iterations in total */
     int rhs_is_weak;    /* 0: rhs is the nodal f (b = M f); 1: rhs is b itself */
     int fixed_iters;    /* > 0: run exactly this many CG iterations, no stopping test */
+    int precond;        /* DG_PC_JACOBI (default) or DG_PC_FDM */
 } dg_solve_opts;
 
 typedef struct {
@@ -99,7 +109,7 @@ typedef struct {
 } dg_solve_info;
 
 /* Default options: tol 1e-10, maxit 100000, FP64, inner_tol 1e-2,
-   inner_maxit 20000, nodal rhs, no fixed iteration count. */
+   inner_maxit 20000, nodal rhs, no fixed iteration count, Jacobi. */
 void dg_default_opts(dg_solve_opts *opts);
 
 /* Create a Cartesian mesh of nx*ny*nz hexahedra of degree P (3 <= P <= 8;
@@ -140,6 +150,26 @@ int helmholtz_apply(dg_mesh *m, double lambda, const void *nu_field, double nu_c
    (the Jacobi preconditioner). */
 int helmholtz_diag(dg_mesh *m, double lambda, const void *nu_field, double nu_const, void *d,
                    int precision, void *stream);
+
+/* x = (lambda M + nu K)^-1 b for a constant nu, by fast diagonalisation
+   (Lynch, Rice & Thomas 1964): on the Cartesian product mesh the operator is
+   the Kronecker sum lambda Mz(x)My(x)Mx + nu (Mz(x)My(x)Kx + Mz(x)Ky(x)Mx +
+   Kz(x)My(x)Mx) of the 1D SIP matrices K_d and GLL masses M_d of the axes
+   (Sec. 3.3: every volume and face integral of the GLL-collocated form
+   factorises), so with K_d S_d = M_d S_d Lam_d, S_d^T M_d S_d = I,
+       x = (Sz(x)Sy(x)Sx) (lambda + nu (Lx (+) Ly (+) Lz))^-1 (Sz(x)Sy(x)Sx)^T b.
+   The three 1D transforms each way run as FP64 matrix-core (MFMA)
+   contractions along the mesh lines; the 1D eigenproblems are solved on the
+   host at first use and cached.  b, x: device double arrays (ABI layout),
+   b the weak load vector (b = M f), x != b.  is_poisson: lambda = 0, nu = 1
+   and the mesh's Dirichlet axes become Neumann axes, as in poisson_solve.  If
+   the operator is singular (lambda = 0, no Dirichlet axis) the constant mode
+   is dropped: pass b with zero sum; x then has zero M-weighted mean.
+   Uses the mesh's workspace (allocated on first use).  Asynchronous on
+   `stream` (NULL = the mesh's stream).  DG_ERR_ARG if a mesh line has more
+   than 512 nodes. */
+int helmholtz_fdm_apply(dg_mesh *m, double lambda, double nu_const, int is_poisson,
+                        const double *b, double *x, void *stream);
 
 /* Solve (lambda M + K_nu) x = b by Jacobi-preconditioned CG (FP64), or by
    FP64 iterative refinement around FP32 Jacobi-PCG inner solves (DG_MIXED;
@@ -245,6 +275,7 @@ typedef struct {
                            that does not fit while no solve is running and no
                            fetch is in progress fails with DG_ERR_BUDGET
                            instead of waiting for a fetch */
+    int precond;        /* DG_PC_JACOBI or DG_PC_FDM (FP64 precision only) */
 } dg_request;
 
 /* max_slots: solves allowed on the device at once (>= 1). */

@@ -145,6 +145,15 @@ class FDM:
             x = x - np.dot(m, x) / m.sum()
         return x
 
+    def apply_inverse(self, r):
+        """(Sz(x)Sy(x)Sx) (lambda + Lx(+)Ly(+)Lz)^-1 (Sz(x)Sy(x)Sx)^T r, the
+        zero mode dropped when singular, with no projection or shift: the
+        fast-diagonalisation preconditioner as defined (ABI layout in and out)."""
+        R = abi_to_global(self.spec, np.asarray(r, dtype=np.float64))
+        Sx, Sy, Sz = self.S
+        T = self._apply_tensor(R, Sx.T, Sy.T, Sz.T) / self.den
+        return global_to_abi(self.spec, self._apply_tensor(T, Sx, Sy, Sz))
+
     def eigenvalues_generalized(self):
         """Spectrum of M^-1 A: lambda + Lx(+)Ly(+)Lz (zero mode excluded if singular)."""
         ev = self.den.reshape(-1)

@@ -28,11 +28,14 @@ import numpy as np
 OK, NOT_CONVERGED, ERR_NOT_SPD, ERR_NONFINITE = 0, 1, -4, -5
 
 
-def pcg(apply, b, d, Mdiag, tol=1e-10, maxit=10000, singular=False, x0=None, fixed_iters=0):
+def pcg(apply, b, d, Mdiag, tol=1e-10, maxit=10000, singular=False, x0=None, fixed_iters=0,
+        precond=None):
     """Returns (x, info) with info = dict(iters, rel_res, status, history).
 
-    apply: x -> A x;  d = diag(A);  Mdiag = diagonal mass.
+    apply: x -> A x;  d = diag(A) (the Jacobi preconditioner z = r/d);
+    precond: r -> z replaces it when given;  Mdiag = diagonal mass.
     fixed_iters > 0 runs exactly that many iterations (no stopping test)."""
+    prec = precond if precond is not None else (lambda v: v / d)
     b = np.array(b, dtype=np.float64)
     if not np.all(np.isfinite(b)):
         return np.zeros_like(b), dict(iters=0, rel_res=np.nan, status=ERR_NONFINITE, history=[])
@@ -43,7 +46,7 @@ def pcg(apply, b, d, Mdiag, tol=1e-10, maxit=10000, singular=False, x0=None, fix
     if singular:
         r = r - r.mean()
     bnorm = np.linalg.norm(b / Mdiag)
-    z = r / d
+    z = prec(r)
     p = z.copy()
     rho = float(np.dot(r, z))
     k = 0
@@ -74,7 +77,7 @@ def pcg(apply, b, d, Mdiag, tol=1e-10, maxit=10000, singular=False, x0=None, fix
         r -= alpha * q
         if singular:
             r -= r.mean()
-        z = r / d
+        z = prec(r)
         rho_new = float(np.dot(r, z))
         p = z + (rho_new / rho) * p
         rho = rho_new

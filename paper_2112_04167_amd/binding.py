@@ -18,6 +18,7 @@ DG_ERR_ARG, DG_ERR_OOM, DG_ERR_DEVICE, DG_ERR_NOT_SPD, DG_ERR_NONFINITE, DG_ERR_
 DG_BC_PERIODIC, DG_BC_DIRICHLET, DG_BC_NEUMANN = 0, 1, 2
 DG_FP64, DG_FP32, DG_MIXED = 0, 1, 1
 DG_BATCH_HANDOFF = 1
+DG_PC_JACOBI, DG_PC_FDM = 0, 1
 
 STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", 2: "PENDING", -1: "ERR_ARG", -2: "ERR_OOM",
                 -3: "ERR_DEVICE", -4: "ERR_NOT_SPD", -5: "ERR_NONFINITE", -6: "ERR_BUDGET"}
@@ -32,7 +33,8 @@ class DGError(RuntimeError):
 class dg_solve_opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int), ("precision", ctypes.c_int),
                 ("inner_tol", ctypes.c_double), ("inner_maxit", ctypes.c_int),
-                ("rhs_is_weak", ctypes.c_int), ("fixed_iters", ctypes.c_int)]
+                ("rhs_is_weak", ctypes.c_int), ("fixed_iters", ctypes.c_int),
+                ("precond", ctypes.c_int)]
 
 
 class dg_solve_info(ctypes.Structure):
@@ -48,7 +50,8 @@ class dg_request(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("P", ctypes.c_int), ("is_poisson", ctypes.c_int),
                 ("lam", ctypes.c_double), ("rhs", ctypes.POINTER(ctypes.c_double)),
                 ("rhs_seed", ctypes.c_uint64), ("tol", ctypes.c_double),
-                ("precision", ctypes.c_int), ("keep_result", ctypes.c_int)]
+                ("precision", ctypes.c_int), ("keep_result", ctypes.c_int),
+                ("precond", ctypes.c_int)]
 
 
 class dg_server_stats(ctypes.Structure):
@@ -74,6 +77,8 @@ _SIGS = {
     "dg_mesh_coordinates": ([_VP, _VP, _VP, _VP, _VP], ctypes.c_int),
     "helmholtz_apply": ([_VP, ctypes.c_double, _VP, ctypes.c_double, _VP, _VP, ctypes.c_int, _VP],
                         ctypes.c_int),
+    "helmholtz_fdm_apply": ([_VP, ctypes.c_double, ctypes.c_double, ctypes.c_int, _VP, _VP, _VP],
+                            ctypes.c_int),
     "helmholtz_diag": ([_VP, ctypes.c_double, _VP, ctypes.c_double, _VP, ctypes.c_int, _VP],
                        ctypes.c_int),
     "helmholtz_solve": ([_VP, ctypes.c_double, _VP, ctypes.c_double, _VP, _VP,
@@ -229,6 +234,14 @@ def helmholtz_apply(mesh, lam, nu_field, nu_const, x, y, precision=DG_FP64, stre
                                  precision, _stream_ptr(stream)))
 
 
+def helmholtz_fdm_apply(mesh, lam, nu_const, b, x, is_poisson=False, stream=None):
+    """x = A^-1 b for a constant nu by fast diagonalisation (b: weak load)."""
+    import torch
+    _check(lib().helmholtz_fdm_apply(mesh.handle, float(lam), float(nu_const), int(is_poisson),
+                                     _dptr(b, torch.float64, mesh.ndof), _dptr(x, torch.float64, mesh.ndof),
+                                     _stream_ptr(stream)))
+
+
 def helmholtz_diag(mesh, lam, nu_field, nu_const, d, precision=DG_FP64, stream=None):
     dt = _dtype(precision)
     _check(lib().helmholtz_diag(mesh.handle, float(lam), _dptr(nu_field, dt, mesh.ndof),
@@ -311,10 +324,11 @@ class Server:
         self._keep = {}
 
     def submit(self, n, P, lam, rhs_host=None, is_poisson=False, tol=1e-10, precision=DG_FP64,
-               rhs_seed=0, keep_result=False):
+               rhs_seed=0, keep_result=False, precond=DG_PC_JACOBI):
         """Queue one solve; rhs_host None -> f generated on the device from rhs_seed."""
         req = dg_request(n=n, P=P, is_poisson=int(is_poisson), lam=float(lam), rhs_seed=int(rhs_seed),
-                         tol=tol, precision=precision, keep_result=int(keep_result))
+                         tol=tol, precision=precision, keep_result=int(keep_result),
+                         precond=int(precond))
         if rhs_host is not None:
             rhs = np.ascontiguousarray(rhs_host, dtype=np.float64)
             if rhs.size != n ** 3 * (P + 1) ** 3:

@@ -558,6 +558,112 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_restart64(CgVecArgs<double> A
     publish_partials<4>(red, A.partial, gridDim.x, sh);
 }
 
+// ---- CG preconditioned by the fast-diagonalisation inverse (FP64) --------
+//
+// z = F r is formed by the transform kernels (fdm.hip) between the update
+// and the r.z reduction, so one step is: apply (q = A p, alpha), update
+// (x, r, residual norm, stopping test), F, r.z (beta), p-update.
+
+// x += alpha p, r -= alpha q; sums of (r/M)^2 (singular: also r and r/M^2,
+// for the norm of the projected residual)
+template <int P, bool SING>
+__global__ void __launch_bounds__(Shape<P>::NTP) k_update_fdm(CgVecArgs<double> A)
+{
+    using S = Shape<P>;
+    constexpr int NC = SING ? 3 : 1;
+    __shared__ double sh[16 * NC];
+    if (A.sc->done) return;
+    const double alpha = A.sc->alpha;
+    const double mr = SING ? A.sc->mean_r : 0.0;
+    const LineCtx<P, double> c = line_ctx<P, double>(A);
+    double red[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) red[k] = 0.0;
+    if (c.active) {
+#pragma unroll
+        for (int k = 0; k < S::n; ++k) {
+            const size_t gi = c.base + (size_t)k * S::NL;
+            A.x[gi] = fma(alpha, A.p[gi], A.x[gi]);
+            const double r = fma(-alpha, A.q[gi], A.r[gi] - mr);
+            A.r[gi] = r;
+            const double im = c.iJw * inv_w<P>(k);
+            const double rm = r * im;
+            if (SING) {
+                red[0] += r;
+                red[1] += rm * rm;
+                red[2] += rm * im;
+            } else {
+                red[0] += rm * rm;
+            }
+        }
+    }
+    publish_partials<NC>(red, A.partial, gridDim.x, sh);
+}
+
+// sum (r - mean_r) z
+template <int P>
+__global__ void __launch_bounds__(Shape<P>::NTP) k_rz(CgVecArgs<double> A)
+{
+    using S = Shape<P>;
+    __shared__ double sh[16];
+    if (A.sc->done) return;
+    const double mr = A.sc->mean_r;
+    const LineCtx<P, double> c = line_ctx<P, double>(A);
+    double red[1] = {0.0};
+    if (c.active) {
+#pragma unroll
+        for (int k = 0; k < S::n; ++k) {
+            const size_t gi = c.base + (size_t)k * S::NL;
+            red[0] += (A.r[gi] - mr) * A.z[gi];
+        }
+    }
+    publish_partials<1>(red, A.partial, gridDim.x, sh);
+}
+
+template <int P, bool START>
+__global__ void __launch_bounds__(Shape<P>::NTP) k_pupdate_fdm(CgVecArgs<double> A)
+{
+    using S = Shape<P>;
+    if (A.sc->done) return;
+    const double beta = A.sc->beta;
+    const LineCtx<P, double> c = line_ctx<P, double>(A);
+    if (!c.active) return;
+#pragma unroll
+    for (int k = 0; k < S::n; ++k) {
+        const size_t gi = c.base + (size_t)k * S::NL;
+        A.p[gi] = START ? A.z[gi] : fma(beta, A.p[gi], A.z[gi]);
+    }
+}
+
+// start from r = b - A x: x = 0 if b = 0
+template <int P>
+__global__ void __launch_bounds__(Shape<P>::NTP) k_fdm_zero_x(CgVecArgs<double> A)
+{
+    using S = Shape<P>;
+    if (A.sc->bnorm2 != 0.0) return;
+    const LineCtx<P, double> c = line_ctx<P, double>(A);
+    if (!c.active) return;
+#pragma unroll
+    for (int k = 0; k < S::n; ++k) A.x[c.base + (size_t)k * S::NL] = 0.0;
+}
+
+__global__ void k_fdm_start_scalars(CgScalars *sc)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double res2 = sc->true_res2;
+    sc->res2 = res2;
+    sc->iter = 0;
+    sc->status = DG_OK;
+    sc->done = 0;
+    sc->rho = 0.0;
+    if (!isfinite(res2)) {
+        sc->status = DG_ERR_NONFINITE;
+        sc->done = 1;
+    } else if (sc->bnorm2 == 0.0 || res2 == 0.0 || (sc->fixed_iters <= 0 && res2 <= sc->tol2)) {
+        sc->done = 1;
+    }
+}
+
 // Sums of NC partial-sum arrays partial[c * nblk + 0..nblk) taken by the
 // calling work-group, this thread's share in t[c].  The loads of all
 // components are issued together (summing one component after another would
@@ -674,7 +780,9 @@ template <int NC, int OP>
 __global__ void __launch_bounds__(1024) k_finish(const double *partial, int nblk, CgScalars *sc)
 {
     __shared__ double sh[16 * NC];
-    if ((OP == FIN_APPLY || OP == FIN_UPDATE) && sc->done) return;
+    if ((OP == FIN_APPLY || OP == FIN_UPDATE || OP == FIN_UPDATE_FDM || OP == FIN_RZ ||
+         OP == FIN_RZ_START) && sc->done)
+        return;
     double tot[NC];
     sum_partials<NC>(partial, nblk, tot);
     block_sum<NC>(tot, sh);
@@ -732,6 +840,39 @@ __global__ void __launch_bounds__(1024) k_finish(const double *partial, int nblk
             sc->done = 1;
         } else if (sc->iter >= sc->maxit) {
             sc->status = DG_NOT_CONVERGED;
+            sc->done = 1;
+        }
+    } else if constexpr (OP == FIN_UPDATE_FDM) {
+        double res2;
+        if (NC == 3) {  // singular: norm of r - mean r
+            const double mr = tot[0] / (double)sc->ndof;
+            res2 = tot[1] - 2.0 * mr * tot[NC - 1] + mr * mr * sc->sum_invM2;
+            sc->mean_r = mr;
+        } else {
+            res2 = tot[0];
+            sc->mean_r = 0.0;
+        }
+        if (res2 < 0.0) res2 = 0.0;
+        sc->res2 = res2;
+        sc->iter += 1;
+        if (!isfinite(res2)) {
+            sc->status = DG_ERR_NONFINITE;
+            sc->done = 1;
+        } else if (sc->fixed_iters > 0) {
+            if (sc->iter >= sc->fixed_iters) sc->done = 1;
+        } else if (res2 <= sc->tol2) {
+            sc->done = 1;
+        } else if (sc->iter >= sc->maxit) {
+            sc->status = DG_NOT_CONVERGED;
+            sc->done = 1;
+        }
+    } else if constexpr (OP == FIN_RZ || OP == FIN_RZ_START) {
+        const double rz = tot[0];
+        sc->beta = OP == FIN_RZ_START ? 0.0 : rz / sc->rho;
+        sc->rho_prev = sc->rho;
+        sc->rho = rz;
+        if (!isfinite(rz)) {
+            sc->status = DG_ERR_NONFINITE;
             sc->done = 1;
         }
     } else if constexpr (OP == FIN_MEANX) {
@@ -944,6 +1085,56 @@ int launch_finish_resid(double *partial, int nblk, CgScalars *sc, hipStream_t s)
     hipLaunchKernelGGL((k_finish<4, FIN_RESID>), dim3(1), dim3(1024), 0, s, partial, nblk, sc);
     DG_HIP_CHECK(hipGetLastError());
     return DG_OK;
+}
+
+int cg_fdm_start(const MeshDev &m, CgVecArgs<double> a, hipStream_t s)
+{
+    prep(m, a);
+    return with_P(m.P, [&](auto PC) {
+        constexpr int P = decltype(PC)::value;
+        hipLaunchKernelGGL((k_fdm_zero_x<P>), DG_GRID(PC), 0, s, a);
+        hipLaunchKernelGGL(k_fdm_start_scalars, dim3(1), dim3(64), 0, s, a.sc);
+    });
+}
+
+int cg_update_fdm(const MeshDev &m, CgVecArgs<double> a, hipStream_t s)
+{
+    prep(m, a);
+    return with_P(m.P, [&](auto PC) {
+        constexpr int P = decltype(PC)::value;
+        const int nb = apply_groups(P, m.nel);
+        with_bool(a.singular, [&](auto SC) {
+            constexpr bool SG = decltype(SC)::value;
+            hipLaunchKernelGGL((k_update_fdm<P, SG>), DG_GRID(PC), 0, s, a);
+            hipLaunchKernelGGL((k_finish<SG ? 3 : 1, FIN_UPDATE_FDM>), dim3(1), dim3(1024), 0, s,
+                               a.partial, nb, a.sc);
+        });
+    });
+}
+
+int cg_rz(const MeshDev &m, CgVecArgs<double> a, bool start, hipStream_t s)
+{
+    prep(m, a);
+    return with_P(m.P, [&](auto PC) {
+        constexpr int P = decltype(PC)::value;
+        const int nb = apply_groups(P, m.nel);
+        hipLaunchKernelGGL((k_rz<P>), DG_GRID(PC), 0, s, a);
+        if (start)
+            hipLaunchKernelGGL((k_finish<1, FIN_RZ_START>), dim3(1), dim3(1024), 0, s, a.partial, nb, a.sc);
+        else
+            hipLaunchKernelGGL((k_finish<1, FIN_RZ>), dim3(1), dim3(1024), 0, s, a.partial, nb, a.sc);
+    });
+}
+
+int cg_pupdate_fdm(const MeshDev &m, CgVecArgs<double> a, bool start, hipStream_t s)
+{
+    prep(m, a);
+    return with_P(m.P, [&](auto PC) {
+        constexpr int P = decltype(PC)::value;
+        with_bool(start, [&](auto SC) {
+            hipLaunchKernelGGL((k_pupdate_fdm<P, decltype(SC)::value>), DG_GRID(PC), 0, s, a);
+        });
+    });
 }
 
 template int cg_setup<double>(const MeshDev &, CgVecArgs<double>, hipStream_t);

@@ -34,6 +34,7 @@ struct GllTables {
     std::vector<double> K1;        // D^T diag(w) D (1D stiffness on [-1,1] without the 2/h factor)
 };
 GllTables make_gll(int P);
+const GllTables &gll_cached(int P);  // one table per P for the process
 
 // Geometry / BC description the kernels read (device pointers).
 template <typename T>

@@ -1,0 +1,409 @@
+// Fast-diagonalisation preconditioner on the GPU: the three 1D transforms of
+// z = (S (x) S (x) S) (lambda + nu Lam)^-1 (S (x) S (x) S)^T r as FP64 MFMA
+// contractions along the mesh axes (gfx950, v_mfma_f64_16x16x4f64).
+//
+// A mesh line along axis d has L = n_d (P+1) nodes, global 1D index
+// g = e (P+1) + a.  Every line along d is multiplied by the same dense L x L
+// matrix, so one transform is a product OUT = G^T IN with IN of L rows and one
+// column per mesh line.  A work-group takes one bundle -- the n_d elements of
+// an element column along d, whose (P+1)^2 lines it holds completely -- or a
+// chunk of its columns: it stages the bundle (all L rows, NTC*16 columns) in
+// LDS with coalesced loads (an element is n^3 consecutive values in the
+// element-major layout), forms the products with MFMA tiles of 16 output rows
+// x 16 columns (the A operand, G, streams from L2: the matrices are shared by
+// all work-groups), writes the tiles back to LDS and stores the bundle with
+// coalesced stores.  The z transform runs forward, divides by the eigenvalue
+// sums and runs backward in one launch, since its bundle holds every z index
+// of its columns.
+//
+// Arithmetic per node and transform: 2 L flops, against 16 bytes of HBM
+// traffic (read + write), so the kernels are bound by the FP64 matrix rate
+// (78.6 TFLOP/s), not by HBM, for L > ~40.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "fdm.h"
+#include "kernels.h"
+
+namespace dg {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+struct FdmArgs {
+    const double *in;
+    double *out;
+    const double *G;    // [k][i'] Lp x Lp (the z launch: forward)
+    const double *G2;   // z launch: backward matrix
+    const double *lam[3];
+    double lambda, nu;
+    const CgScalars *sc;  // done flag and mean_r (may be null)
+    int sub_mean;         // subtract sc->mean_r from the input (singular residual)
+    int singular;         // drop the (0,0,0) mode
+    int n, nd, L, Lp;
+    int nx, ny, nz;
+    int F, NBc, nchunk;   // columns per bundle, per chunk, chunks per bundle
+    int rs;               // LDS row stride (doubles)
+};
+
+// element-local offset o (memory order) -> (g_local = a along the axis, column f)
+template <int AXIS>
+__device__ __forceinline__ void split_o(int o, int n, int &ga, int &f)
+{
+    if (AXIS == 0) {  // o = f n + a, f = c n + b
+        ga = o % n;
+        f = o / n;
+    } else if (AXIS == 1) {  // o = c n^2 + b n + a: g part b, f = c n + a
+        const int a = o % n, q = o / n;
+        ga = q % n;
+        f = (q / n) * n + a;
+    } else {  // o = c n^2 + f: g part c, f = b n + a
+        ga = o / (n * n);
+        f = o - ga * n * n;
+    }
+}
+
+// bundle -> (first node of element 0 of the bundle, element stride along the axis)
+template <int AXIS>
+__device__ __forceinline__ void bundle_base(const FdmArgs &A, int bundle, size_t &base, size_t &se,
+                                            int &i0, int &i1)
+{
+    const size_t n3 = (size_t)A.n * A.n * A.n;
+    if (AXIS == 0) {  // bundle = ez ny + ey
+        base = (size_t)bundle * A.nx * n3;
+        se = n3;
+        i0 = bundle % A.ny;  // ey
+        i1 = bundle / A.ny;  // ez
+    } else if (AXIS == 1) {  // bundle = ez nx + ex
+        const int ex = bundle % A.nx, ez = bundle / A.nx;
+        base = ((size_t)ez * A.ny * A.nx + ex) * n3;
+        se = (size_t)A.nx * n3;
+        i0 = ex;
+        i1 = ez;
+    } else {  // bundle = ey nx + ex
+        base = (size_t)bundle * n3;
+        se = (size_t)A.nx * A.ny * n3;
+        i0 = bundle % A.nx;  // ex
+        i1 = bundle / A.nx;  // ey
+    }
+}
+
+// OUT tiles (MW per wave, NTC columns tiles) = G^T B, B = the LDS bundle.
+// Wave w owns the output row tiles w, w + 4, w + 8, ...
+template <int NTC, int MW>
+__device__ __forceinline__ void gemm_bundle(const double *__restrict__ G, const double *Bs, int rs,
+                                            int Lp, d4 (&acc)[MW][NTC])
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int mt_n = (Lp / 16 - w + 3) / 4;  // row tiles of this wave
+#pragma unroll
+    for (int mt = 0; mt < MW; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NTC; ++nt) acc[mt][nt] = d4{0.0, 0.0, 0.0, 0.0};
+    // A operand: lane (li, lk) takes G[k0 + lk][16 T + li]
+    const double *gcol = G + 16 * w + li;
+    constexpr int U = 4;  // K steps per group
+    const int ngrp = Lp / (4 * U);
+    double a0[U][MW], a1[U][MW];
+    auto load_grp = [&](int g, double (&a)[U][MW]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const size_t k = (size_t)(g * 4 * U + 4 * u + lk) * Lp;
+#pragma unroll
+            for (int mt = 0; mt < MW; ++mt) a[u][mt] = (mt < mt_n) ? gcol[k + 64 * mt] : 0.0;
+        }
+    };
+    auto mma_grp = [&](int g, const double (&a)[U][MW]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = g * 4 * U + 4 * u + lk;
+            double b[NTC];
+#pragma unroll
+            for (int nt = 0; nt < NTC; ++nt) b[nt] = Bs[k * rs + 16 * nt + li];
+#pragma unroll
+            for (int mt = 0; mt < MW; ++mt)
+                if (mt < mt_n)
+#pragma unroll
+                    for (int nt = 0; nt < NTC; ++nt)
+                        acc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][mt], b[nt], acc[mt][nt], 0, 0, 0);
+        }
+    };
+    load_grp(0, a0);
+    int g = 0;
+    for (; g + 2 <= ngrp; g += 2) {
+        load_grp(g + 1, a1);
+        mma_grp(g, a0);
+        if (g + 2 < ngrp) load_grp(g + 2, a0);
+        mma_grp(g + 1, a1);
+    }
+    if (g < ngrp) mma_grp(g, a0);
+}
+
+// accumulator element r of a lane -> (row, column) within the 16 x 16 tile
+// (v_mfma_f64_16x16x4f64, checked with an in-bounds probe: A operand
+// A[lane % 16][lane / 16], B operand B[lane / 16][lane % 16])
+__device__ __forceinline__ int acc_row(int lane, int r) { return 4 * r + (lane >> 4); }
+__device__ __forceinline__ int acc_col(int lane) { return lane & 15; }
+
+template <int NTC, int MW>
+__device__ __forceinline__ void acc_to_lds(const d4 (&acc)[MW][NTC], double *Bs, int rs, int Lp)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int mt_n = (Lp / 16 - w + 3) / 4;
+#pragma unroll
+    for (int mt = 0; mt < MW; ++mt)
+        if (mt < mt_n) {
+            const int row0 = 16 * (w + 4 * mt);
+#pragma unroll
+            for (int nt = 0; nt < NTC; ++nt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    Bs[(row0 + acc_row(lane, r)) * rs + 16 * nt + acc_col(lane)] = acc[mt][nt][r];
+        }
+}
+
+// MODE 0: plain transform.  MODE 1 (z axis): forward transform, division by
+// lambda + nu (Lx_i + Ly_j + Lz_k), backward transform.
+template <int AXIS, int NTC, int MODE>
+__global__ void __launch_bounds__(256) k_fdm_axis(FdmArgs A)
+{
+    constexpr int MW = 16 / NTC;  // row tiles per wave: Lp <= 4 * 16 * MW
+    extern __shared__ double Bs[];
+    if (A.sc && A.sc->done) return;
+    const int bundle = blockIdx.x / A.nchunk;
+    const int chunk = blockIdx.x - bundle * A.nchunk;
+    const int f0 = chunk * A.NBc;
+    const int ncol = min(A.NBc, A.F - f0);
+    const int n = A.n, n3 = n * n * n, rs = A.rs;
+    size_t base, se;
+    int i0, i1;
+    bundle_base<AXIS>(A, bundle, base, se, i0, i1);
+    const double mr = (A.sub_mean && A.sc) ? A.sc->mean_r : 0.0;
+
+    // stage the bundle: zero padding rows and columns, then the values
+    for (int i = threadIdx.x; i < A.Lp * rs; i += blockDim.x) Bs[i] = 0.0;
+    __syncthreads();
+    const int tot = A.nd * n3;
+    for (int i = threadIdx.x; i < tot; i += blockDim.x) {
+        const int e = i / n3, o = i - e * n3;
+        int ga, f;
+        split_o<AXIS>(o, n, ga, f);
+        const int c = f - f0;
+        if (c >= 0 && c < ncol) Bs[(e * n + ga) * rs + c] = A.in[base + e * se + o] - mr;
+    }
+    __syncthreads();
+
+    d4 acc[MW][NTC];
+    gemm_bundle<NTC, MW>(A.G, Bs, rs, A.Lp, acc);
+    __syncthreads();  // every wave is done reading the bundle
+    acc_to_lds<NTC, MW>(acc, Bs, rs, A.Lp);
+    __syncthreads();
+
+    if (MODE == 1) {
+        // divide by the eigenvalue sums; row = z index k, column f -> (b, a)
+        for (int i = threadIdx.x; i < A.L * ncol; i += blockDim.x) {
+            const int k = i / ncol, c = i - k * ncol;
+            const int f = f0 + c, b = f / n, a = f - b * n;
+            const int gx = i0 * n + a, gy = i1 * n + b;
+            const double den = A.lambda + A.nu * (A.lam[0][gx] + A.lam[1][gy] + A.lam[2][k]);
+            const bool zero_mode = A.singular && gx == 0 && gy == 0 && k == 0;
+            Bs[k * rs + c] = zero_mode ? 0.0 : Bs[k * rs + c] / den;
+        }
+        __syncthreads();
+        gemm_bundle<NTC, MW>(A.G2, Bs, rs, A.Lp, acc);
+        __syncthreads();
+        acc_to_lds<NTC, MW>(acc, Bs, rs, A.Lp);
+        __syncthreads();
+    }
+
+    for (int i = threadIdx.x; i < tot; i += blockDim.x) {
+        const int e = i / n3, o = i - e * n3;
+        int ga, f;
+        split_o<AXIS>(o, n, ga, f);
+        const int c = f - f0;
+        if (c >= 0 && c < ncol) A.out[base + e * se + o] = Bs[(e * n + ga) * rs + c];
+    }
+}
+
+// columns per work-group: 4 tiles when the bundle fits, else 2
+int pick_ntc(int Lp) { return Lp <= 256 ? 4 : 2; }
+
+template <int AXIS, int MODE>
+int launch_axis(const MeshDev &m, const FdmDev &f, FdmArgs a, hipStream_t s)
+{
+    const FdmDevAxis &ax = f.ax[AXIS];
+    const int n = m.P + 1;
+    a.n = n;
+    a.nd = m.n[AXIS];
+    a.L = ax.L;
+    a.Lp = ax.Lp;
+    a.nx = m.n[0];
+    a.ny = m.n[1];
+    a.nz = m.n[2];
+    a.F = n * n;
+    const int ntc = pick_ntc(ax.Lp);
+    a.NBc = ntc * 16;
+    a.nchunk = (a.F + a.NBc - 1) / a.NBc;
+    a.rs = a.NBc + 1;  // odd stride in doubles: consecutive rows start on different banks
+    const int nbundle = (int)(m.nel / m.n[AXIS]);
+    const size_t lds = (size_t)a.Lp * a.rs * sizeof(double);
+    const dim3 grid((unsigned)(nbundle * a.nchunk)), block(256);
+    if (ntc == 4)
+        hipLaunchKernelGGL((k_fdm_axis<AXIS, 4, MODE>), grid, block, lds, s, a);
+    else
+        hipLaunchKernelGGL((k_fdm_axis<AXIS, 2, MODE>), grid, block, lds, s, a);
+    DG_HIP_CHECK(hipGetLastError());
+    return DG_OK;
+}
+
+// per-work-group min and max of a nodal field
+constexpr int kRangeBlocks = 32;
+__global__ void __launch_bounds__(256) k_range(const double *__restrict__ v, size_t N, double *partial)
+{
+    __shared__ double smin[4], smax[4];
+    double lo = INFINITY, hi = -INFINITY;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (size_t)gridDim.x * blockDim.x) {
+        const double x = v[i];
+        lo = fmin(lo, x);
+        hi = fmax(hi, x);
+        if (x != x) lo = hi = x;  // a NaN is reported, not skipped
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const double ol = __shfl_down(lo, off, 64), oh = __shfl_down(hi, off, 64);
+        lo = (ol != ol || lo != lo) ? (lo != lo ? lo : ol) : fmin(lo, ol);
+        hi = (oh != oh || hi != hi) ? (hi != hi ? hi : oh) : fmax(hi, oh);
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+        smin[wid] = lo;
+        smax[wid] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
+            lo = (smin[k] != smin[k]) ? smin[k] : (lo != lo ? lo : fmin(lo, smin[k]));
+            hi = (smax[k] != smax[k]) ? smax[k] : (hi != hi ? hi : fmax(hi, smax[k]));
+        }
+        partial[blockIdx.x] = lo;
+        partial[gridDim.x + blockIdx.x] = hi;
+    }
+}
+
+}  // namespace
+
+int field_range(const double *v, size_t N, double *partial_dev, double &lo, double &hi, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_range, dim3(kRangeBlocks), dim3(256), 0, s, v, N, partial_dev);
+    DG_HIP_CHECK(hipGetLastError());
+    double h[2 * kRangeBlocks];
+    DG_HIP_CHECK(hipMemcpyAsync(h, partial_dev, sizeof(h), hipMemcpyDeviceToHost, s));
+    DG_HIP_CHECK(hipStreamSynchronize(s));
+    lo = h[0];
+    hi = h[kRangeBlocks];
+    for (int k = 1; k < kRangeBlocks; ++k) {
+        lo = std::fmin(lo, h[k]);
+        hi = std::fmax(hi, h[kRangeBlocks + k]);
+        if (h[k] != h[k] || h[kRangeBlocks + k] != h[kRangeBlocks + k]) lo = hi = NAN;
+    }
+    if (h[0] != h[0] || h[kRangeBlocks] != h[kRangeBlocks]) lo = hi = NAN;
+    return DG_OK;
+}
+
+size_t fdm_table_bytes(const int n[3], int P)
+{
+    size_t b = 0;
+    for (int d = 0; d < 3; ++d)
+        if (n[d] * (P + 1) > kFdmMaxL) return 0;  // no fast diagonalisation on this mesh
+    for (int d = 0; d < 3; ++d) {
+        const size_t Lp = (size_t)fdm_pad(n[d] * (P + 1));
+        b += (2 * Lp * Lp + Lp) * sizeof(double);
+    }
+    return b;
+}
+
+int fdm_build_tables(const MeshDev &m, const int bc[3], std::vector<double> &img)
+{
+    img.assign(fdm_table_bytes(m.n, m.P) / sizeof(double), 0.0);
+    size_t off = 0;
+    for (int d = 0; d < 3; ++d) {
+        int rc = DG_OK;
+        const std::shared_ptr<const FdmAxis> ax = fdm_axis_cached(m.v[d], m.P, bc[d], &rc);
+        if (!ax) return rc ? rc : DG_ERR_DEVICE;
+        const int L = ax->L, Lp = fdm_pad(L);
+        double *gf = img.data() + off, *gb = gf + (size_t)Lp * Lp, *lam = gb + (size_t)Lp * Lp;
+        for (int k = 0; k < L; ++k)
+            for (int i = 0; i < L; ++i) {
+                gf[(size_t)k * Lp + i] = ax->S[(size_t)k * L + i];
+                gb[(size_t)k * Lp + i] = ax->S[(size_t)i * L + k];
+            }
+        for (int i = 0; i < L; ++i) lam[i] = ax->lam[i];
+        for (int i = L; i < Lp; ++i) lam[i] = 1.0;  // padding rows are never read
+        off += 2 * (size_t)Lp * Lp + Lp;
+    }
+    return DG_OK;
+}
+
+void fdm_bind(const int n[3], int P, const double *dev, FdmDev &f)
+{
+    size_t off = 0;
+    for (int d = 0; d < 3; ++d) {
+        const int L = n[d] * (P + 1), Lp = fdm_pad(L);
+        f.ax[d].L = L;
+        f.ax[d].Lp = Lp;
+        f.ax[d].Gf = dev + off;
+        f.ax[d].Gb = dev + off + (size_t)Lp * Lp;
+        f.ax[d].lam = dev + off + 2 * (size_t)Lp * Lp;
+        off += 2 * (size_t)Lp * Lp + Lp;
+    }
+}
+
+int fdm_apply(const MeshDev &m, const FdmDev &f, double lambda, double nu, bool singular,
+              const double *r, double *z, double *tmp, const void *sc, hipStream_t s)
+{
+    for (int d = 0; d < 3; ++d)
+        if (f.ax[d].L > kFdmMaxL) {
+            set_error("fast diagonalisation: a mesh line has more than 512 nodes");
+            return DG_ERR_ARG;
+        }
+    FdmArgs a{};
+    a.lam[0] = f.ax[0].lam;
+    a.lam[1] = f.ax[1].lam;
+    a.lam[2] = f.ax[2].lam;
+    a.lambda = lambda;
+    a.nu = nu;
+    a.sc = (const CgScalars *)sc;
+    a.singular = singular ? 1 : 0;
+    int rc;
+    // forward x (r - mean_r -> z), forward y (z -> tmp), z forward + scale +
+    // backward (tmp -> z), backward y (z -> tmp), backward x (tmp -> z)
+    a.in = r;
+    a.out = z;
+    a.G = f.ax[0].Gf;
+    a.sub_mean = singular ? 1 : 0;
+    if ((rc = launch_axis<0, 0>(m, f, a, s))) return rc;
+    a.sub_mean = 0;
+    a.in = z;
+    a.out = tmp;
+    a.G = f.ax[1].Gf;
+    if ((rc = launch_axis<1, 0>(m, f, a, s))) return rc;
+    a.in = tmp;
+    a.out = z;
+    a.G = f.ax[2].Gf;
+    a.G2 = f.ax[2].Gb;
+    if ((rc = launch_axis<2, 1>(m, f, a, s))) return rc;
+    a.in = z;
+    a.out = tmp;
+    a.G = f.ax[1].Gb;
+    if ((rc = launch_axis<1, 0>(m, f, a, s))) return rc;
+    a.in = tmp;
+    a.out = z;
+    a.G = f.ax[0].Gb;
+    return launch_axis<0, 0>(m, f, a, s);
+}
+
+}  // namespace dg

@@ -61,7 +61,8 @@ __device__ inline void resid_finish(CgScalars *sc, const double (&t)[4])
 }
 
 // reductions finished by a one-work-group kernel after the producer
-enum { FIN_APPLY = 0, FIN_RESID, FIN_SETUP1, FIN_SETUP2, FIN_UPDATE, FIN_MEANX, FIN_IRSCALE };
+enum { FIN_APPLY = 0, FIN_RESID, FIN_SETUP1, FIN_SETUP2, FIN_UPDATE, FIN_MEANX, FIN_IRSCALE,
+       FIN_UPDATE_FDM, FIN_RZ, FIN_RZ_START };
 int launch_finish_apply(double *partial, int nblk, CgScalars *sc, hipStream_t s);
 int launch_finish_resid(double *partial, int nblk, CgScalars *sc, hipStream_t s);
 
@@ -93,6 +94,7 @@ struct CgVecArgs {
     // per-axis 1D terms [nx | ny | nz][P+1] (see diag_tables) and lambda
     const T *dtab;
     double lam;
+    const T *z;         // FDM-PCG: the preconditioned residual
     bool singular;      // host-side: selects the singular (projected) kernels
     double *partial;
     CgScalars *sc;
@@ -123,5 +125,18 @@ int ir_replace(const MeshDev &m, CgVecArgs<float> a, CgScalars *inner, double de
 // FP64 CG restarted from the residual in a.r (mean a.sc->mean_r removed if
 // singular): p = r/diag, rho, residual norm; a.sc->tol2 is kept.
 int cg_restart64(const MeshDev &m, CgVecArgs<double> a, hipStream_t s);
+
+// CG preconditioned by the fast-diagonalisation inverse (FP64).  The
+// residual in memory minus sc->mean_r is the (projected) residual; z = the
+// preconditioned residual in a.z.
+// start: after r = b - A x (launch_resid): x = 0 if b = 0, the residual norm
+// and the stopping test, iteration count 0
+int cg_fdm_start(const MeshDev &m, CgVecArgs<double> a, hipStream_t s);
+// x += alpha p, r -= alpha q, ||M^-1 r|| and the stopping test
+int cg_update_fdm(const MeshDev &m, CgVecArgs<double> a, hipStream_t s);
+// rho' = (r - mean_r).z; beta = rho'/rho (start: beta = 0)
+int cg_rz(const MeshDev &m, CgVecArgs<double> a, bool start, hipStream_t s);
+// p = z + beta p (start: p = z)
+int cg_pupdate_fdm(const MeshDev &m, CgVecArgs<double> a, bool start, hipStream_t s);
 
 }  // namespace dg

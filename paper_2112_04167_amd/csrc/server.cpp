@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "dg_internal.h"
+#include "fdm.h"
 #include "kernels.h"
 
 namespace dg {
@@ -166,6 +167,8 @@ public:
     {
         if (!r || !id || r->n < 1 || r->P < kMinPKernel || r->P > kMaxPKernel || !(r->tol > 0.0) ||
             (r->precision != DG_FP64 && r->precision != DG_MIXED) ||
+            (r->precond != DG_PC_JACOBI && r->precond != DG_PC_FDM) ||
+            (r->precond == DG_PC_FDM && (r->precision != DG_FP64 || r->n * (r->P + 1) > kFdmMaxL)) ||
             (!r->is_poisson && !(r->lambda > 0.0 && std::isfinite(r->lambda)))) {
             set_error("bad request");
             return DG_ERR_ARG;
@@ -432,6 +435,7 @@ private:
         dg_default_opts(&o);
         o.tol = q->d.tol;
         o.precision = q->d.precision;
+        o.precond = q->d.precond;
         if (q->d.is_poisson)
             rc = poisson_solve(m, rhs, x, &o, &info);
         else

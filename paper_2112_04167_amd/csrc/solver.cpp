@@ -17,6 +17,7 @@
 
 #include "batched.h"
 #include "dg_internal.h"
+#include "fdm.h"
 #include "kernels.h"
 
 namespace dg {
@@ -53,6 +54,9 @@ struct Workspace {
     std::vector<double> htab64;   // host copy (alive until the next solve's upload)
     int tab_bc[3] = {-1, -1, -1}; // boundary conditions and nu the device tables hold
     double tab_nu = 0.0;
+    double *fdm = nullptr;        // fast-diagonalisation tables (fdm_table_bytes)
+    std::vector<double> fdm_img;  // host image (alive until the next upload)
+    int fdm_bc[3] = {-1, -1, -1}; // boundary conditions the device tables hold
     CgScalars *sc = nullptr;      // [0] outer / FP64, [1] inner FP32
     CgScalars *host_sc = nullptr; // pinned
     bool external = false;        // memory lent by the caller (never freed here)
@@ -92,6 +96,7 @@ size_t footprint(const MeshDev &m, int precision)
     if (precision == DG_MIXED) b += 7 * align256(N * sizeof(float));
     b += align256(partial_doubles(m) * sizeof(double));
     b += align256(diag_table_len(m) * sizeof(double));
+    b += align256(fdm_table_bytes(m.n, m.P));
     b += align256(2 * sizeof(CgScalars));
     return b;
 }
@@ -151,6 +156,8 @@ int ensure_workspace(dg_mesh *m, Workspace &w, int precision)
     w.partial = (double *)take(partial_doubles(m->dev) * 8);
     w.dtab64 = (double *)take(diag_table_len(m->dev) * sizeof(double));
     w.tab_bc[0] = w.tab_bc[1] = w.tab_bc[2] = -1;
+    w.fdm = (double *)take(fdm_table_bytes(m->dev.n, m->dev.P));
+    w.fdm_bc[0] = w.fdm_bc[1] = w.fdm_bc[2] = -1;
 
     w.sc = (CgScalars *)take(2 * sizeof(CgScalars));
     return DG_OK;
@@ -341,6 +348,104 @@ int solve_fp64(dg_mesh *m, Workspace &w, const int bc[3], double lambda, const d
     // true residual from x
     if ((rc = launch_resid<double>(md, bc, lambda, nu, nu_c, x, w.b64, w.q64, w.partial,
                                    w.sc, s)))
+        return rc;
+    DG_HIP_CHECK(hipMemcpyAsync(w.host_sc, w.sc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
+    DG_HIP_CHECK(hipStreamSynchronize(s));
+    const CgScalars &h = *w.host_sc;
+    info.iters = h.iter;
+    info.outer_iters = 0;
+    info.status = h.status;
+    info.rel_res = h.bnorm2 > 0 ? std::sqrt(h.res2 / h.bnorm2) : 0.0;
+    info.true_rel_res = h.bnorm2 > 0 ? std::sqrt(h.true_res2 / h.bnorm2) : 0.0;
+    return h.status;
+}
+
+// the fast-diagonalisation tables of the mesh for these BCs, uploaded on the
+// mesh's stream unless the workspace already holds them
+int ensure_fdm_tables(dg_mesh *m, Workspace &w, const int bc[3], FdmDev &f)
+{
+    if (fdm_table_bytes(m->dev.n, m->dev.P) == 0) {
+        set_error("fast diagonalisation needs at most 512 nodes per mesh line (n_d (P+1) <= 512)");
+        return DG_ERR_ARG;
+    }
+    if (!(w.fdm_bc[0] == bc[0] && w.fdm_bc[1] == bc[1] && w.fdm_bc[2] == bc[2])) {
+        if (int rc = fdm_build_tables(m->dev, bc, w.fdm_img)) return rc;
+        DG_HIP_CHECK(hipMemcpyAsync(w.fdm, w.fdm_img.data(), w.fdm_img.size() * sizeof(double),
+                                    hipMemcpyHostToDevice, m->stream));
+        for (int d = 0; d < 3; ++d) w.fdm_bc[d] = bc[d];
+    }
+    fdm_bind(m->dev.n, m->dev.P, w.fdm, f);
+    return DG_OK;
+}
+
+// CG preconditioned by the fast-diagonalisation inverse of the constant-nu
+// operator (FP64).  For a constant nu that inverse is exact, and CG stops
+// after one or two steps (rounding); for a nodal nu the preconditioner uses
+// nu_ref = sqrt(min nu * max nu), which bounds the preconditioned condition
+// number by max nu / min nu.
+int solve_fdm(dg_mesh *m, Workspace &w, const int bc[3], double lambda, const double *nu,
+              double nu_c, const double *rhs, double *x, const dg_solve_opts &o, dg_solve_info &info)
+{
+    int rc = ensure_workspace(m, w, DG_FP64);
+    if (rc) return rc;
+    const MeshDev &md = m->dev;
+    hipStream_t s = m->stream;
+    const bool singular = (lambda == 0.0) && !has_dirichlet(bc);
+    FdmDev f;
+    if ((rc = ensure_fdm_tables(m, w, bc, f))) return rc;
+    double nu_ref = nu_c;
+    if (nu) {
+        double lo = 0.0, hi = 0.0;
+        if ((rc = field_range(nu, (size_t)md.ndof, w.partial, lo, hi, s))) return rc;
+        if (!(lo > 0.0) || !std::isfinite(hi)) {
+            set_error("the fast-diagonalisation preconditioner needs a positive, finite nu field");
+            return lo != lo || hi != hi ? DG_ERR_NONFINITE : DG_ERR_ARG;
+        }
+        nu_ref = std::sqrt(lo * hi);
+    }
+    *w.host_sc = init_scalars(md, o.tol, o.maxit, o.fixed_iters, singular);
+    DG_HIP_CHECK(hipMemcpyAsync(w.sc, w.host_sc, sizeof(CgScalars), hipMemcpyHostToDevice, s));
+    CgVecArgs<double> a = vec_args<double>(w, singular, w.sc);
+    a.x = x;
+    a.r = w.r64;
+    a.p = w.p64;
+    a.q = w.q64;
+    a.z = w.d64;  // the diagonal slot holds z (no Jacobi diagonal here)
+    a.src = rhs;
+    a.bvec = w.b64;
+    a.weak = o.rhs_is_weak;
+    a.keep_x = 1;
+    if ((rc = cg_setup<double>(md, a, s))) return rc;  // b, norms (no diagonal: d, dtab null)
+    // r = b - A x from the caller's x, its norm and the stopping test
+    if ((rc = launch_resid<double>(md, bc, lambda, nu, nu_c, x, w.b64, w.r64, w.partial, w.sc, s)))
+        return rc;
+    if ((rc = cg_fdm_start(md, a, s))) return rc;
+    if ((rc = fdm_apply(md, f, lambda, nu_ref, singular, w.r64, w.d64, w.q64, w.sc, s))) return rc;
+    if ((rc = cg_rz(md, a, true, s))) return rc;
+    if ((rc = cg_pupdate_fdm(md, a, true, s))) return rc;
+    const int cap = o.fixed_iters > 0 ? o.fixed_iters : o.maxit;
+    int chunk = 2, launched = 0;
+    for (;;) {
+        for (int k = 0; k < chunk; ++k) {
+            if ((rc = launch_apply_cg<double>(md, bc, lambda, nu, nu_c, a.p, w.q64, w.partial, w.sc, s)))
+                return rc;
+            if ((rc = cg_update_fdm(md, a, s))) return rc;
+            if ((rc = fdm_apply(md, f, lambda, nu_ref, singular, w.r64, w.d64, w.q64, w.sc, s))) return rc;
+            if ((rc = cg_rz(md, a, false, s))) return rc;
+            if ((rc = cg_pupdate_fdm(md, a, false, s))) return rc;
+        }
+        launched += chunk;
+        DG_HIP_CHECK(hipMemcpyAsync(w.host_sc, w.sc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
+        DG_HIP_CHECK(hipStreamSynchronize(s));
+        if (w.host_sc->done) break;
+        if (launched > cap + 64) {
+            set_error("CG did not flag completion");
+            return DG_ERR_DEVICE;
+        }
+        chunk = std::min(chunk * 2, 16);
+    }
+    if ((rc = cg_finish<double>(md, a, s))) return rc;
+    if ((rc = launch_resid<double>(md, bc, lambda, nu, nu_c, x, w.b64, w.q64, w.partial, w.sc, s)))
         return rc;
     DG_HIP_CHECK(hipMemcpyAsync(w.host_sc, w.sc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
     DG_HIP_CHECK(hipStreamSynchronize(s));
@@ -561,11 +666,22 @@ int solve_common(dg_mesh *m, const int bc[3], double lambda, const double *nu, d
     }
     dg_solve_info inf{};
     int rc;
-    if (lent) {
-        if (o.precision != DG_FP64) {
-            set_error("the no-allocation solve is FP64 only");
-            return DG_ERR_ARG;
-        }
+    if (o.precond != DG_PC_JACOBI && o.precond != DG_PC_FDM) {
+        set_error("unknown preconditioner");
+        return DG_ERR_ARG;
+    }
+    if (o.precond == DG_PC_FDM && o.precision != DG_FP64) {
+        set_error("the fast-diagonalisation preconditioner runs in FP64 only");
+        return DG_ERR_ARG;
+    }
+    Workspace &wk = lent ? *lent : m->ws;
+    if (lent && o.precision != DG_FP64) {
+        set_error("the no-allocation solve is FP64 only");
+        return DG_ERR_ARG;
+    }
+    if (o.precond == DG_PC_FDM) {
+        rc = solve_fdm(m, wk, bc, lambda, nu, nu_c, rhs, x, o, inf);
+    } else if (lent) {
         rc = solve_fp64(m, *lent, bc, lambda, nu, nu_c, rhs, x, o, inf);
     } else if (o.precision == DG_MIXED) {
         if (!(o.inner_tol > 0.0 && o.inner_tol < 1.0) || o.inner_maxit <= 0) {
@@ -754,8 +870,11 @@ int solve_batched(dg_mesh *m, int nsys, const double *lambdas, const double *con
             // the last unconverged system: continue from its current solution
             // with the single-system solver (same operator, options and rule)
             const BatchSysDesc &D = rq.sys[k];
-            const int rc2 = f32 ? solve_mixed(m, D.bc, D.lambda, D.nu64, 1.0, rhs[k], x[k], o, ci)
-                                : solve_fp64(m, m->ws, D.bc, D.lambda, D.nu64, 1.0, rhs[k], x[k], o, ci);
+            // (FP64 with the fast-diagonalisation preconditioner if asked for)
+            const int rc2 =
+                o.precond == DG_PC_FDM ? solve_fdm(m, m->ws, D.bc, D.lambda, D.nu64, 1.0, rhs[k], x[k], o, ci)
+                : f32                 ? solve_mixed(m, D.bc, D.lambda, D.nu64, 1.0, rhs[k], x[k], o, ci)
+                                      : solve_fp64(m, m->ws, D.bc, D.lambda, D.nu64, 1.0, rhs[k], x[k], o, ci);
             r.status = rc2 < 0 ? rc2 : ci.status;
         }
         if (infos) {
@@ -933,6 +1052,7 @@ void dg_default_opts(dg_solve_opts *o)
     o->inner_maxit = 20000;
     o->rhs_is_weak = 0;
     o->fixed_iters = 0;
+    o->precond = DG_PC_JACOBI;
 }
 
 int dg_mesh_create(int nx, int ny, int nz, int P, const double *xv, const double *yv,
@@ -1086,6 +1206,10 @@ int helmholtz_solve_batched_ex(dg_mesh *m, int nsys, const double *lambdas,
         set_error("unknown batched-solve flags");
         return DG_ERR_ARG;
     }
+    if (o.precond != DG_PC_JACOBI && o.precond != DG_PC_FDM) {
+        set_error("unknown preconditioner");
+        return DG_ERR_ARG;
+    }
     int rc = solve_batched(m, nsys, lambdas, nu_fields, is_poisson, rhs, x, o, infos, flags);
     if (infos)
         for (int k = 0; k < nsys; ++k) infos[k].seconds = now() - t0;
@@ -1114,6 +1238,36 @@ int helmholtz_solve_noalloc(dg_mesh *m, double lambda, const double *nu_field, d
     w.host_sc = host_sc;
     w.host_external = true;
     return solve_common(m, m->dev.bc, lambda, nu_field, nu_const, rhs, x, opts, info, &w);
+}
+
+int helmholtz_fdm_apply(dg_mesh *m, double lambda, double nu_const, int is_poisson, const double *b,
+                        double *x, void *stream)
+{
+    if (int rc = check_mesh(m)) return rc;
+    if (!b || !x || (const void *)b == (const void *)x) {
+        set_error("b and x must be distinct device arrays");
+        return DG_ERR_ARG;
+    }
+    int bc[3];
+    for (int d = 0; d < 3; ++d)
+        bc[d] = (is_poisson && m->dev.bc[d] == DG_BC_DIRICHLET) ? DG_BC_NEUMANN : m->dev.bc[d];
+    if (is_poisson) {
+        lambda = 0.0;
+        nu_const = 1.0;
+    }
+    if (!(lambda >= 0.0) || !std::isfinite(lambda) || !(nu_const > 0.0) || !std::isfinite(nu_const)) {
+        set_error("lambda must be >= 0 and nu_const > 0");
+        return DG_ERR_ARG;
+    }
+    Workspace &w = m->ws;
+    int rc = ensure_workspace(m, w, DG_FP64);
+    if (rc) return rc;
+    FdmDev f;
+    if ((rc = ensure_fdm_tables(m, w, bc, f))) return rc;
+    hipStream_t s = stream ? (hipStream_t)stream : m->stream;
+    if (s != m->stream) DG_HIP_CHECK(hipStreamSynchronize(m->stream));  // the table upload
+    const bool singular = lambda == 0.0 && !has_dirichlet(bc);
+    return fdm_apply(m->dev, f, lambda, nu_const, singular, b, x, w.q64, nullptr, s);
 }
 
 int poisson_solve(dg_mesh *m, const double *rhs, double *x, const dg_solve_opts *opts,
