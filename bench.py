@@ -22,6 +22,13 @@ Also reported on the same JSON line (each measured after the timed steps):
                 persistent launch vs the same 4 systems solved one after the
                 other by the plain FP64 solver (and by the mixed solver)
   serving       the request stream (Poisson arrivals), p50/p99 latency
+  fdm           the fast-diagonalisation inverse of the same mesh (three FP64
+                MFMA transforms each way along the mesh lines): time per
+                application and FP64 matrix rate against the 78.6 TFLOP/s peak
+  solve_fdm     the Helmholtz and Poisson solves of the same mesh with CG
+  poisson_fdm   preconditioned by that inverse (same 1e-10 rule)
+  (batched and serving also report the stage and the full 2000-request
+  stream with the fast-diagonalisation preconditioner)
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
                        [--legs solve,poisson,...] [--no-cpu]
@@ -104,35 +111,80 @@ def bench_apply(dg, torch, spec, lam, steps, warmup, npairs=5):
     return N, t1 - t0, durs
 
 
-def bench_solve(dg, torch, spec, lam, seed, reps, poisson=False):
+def bench_solve(dg, torch, spec, lam, seed, reps, poisson=False, precond=0, ref=None):
+    """Median wall time of a solve from x = 0; with ref (a solution of the
+    same system) also the relative difference to it."""
     import synth
     dev = torch.device("cuda:0")
     mesh = dg.mesh_from_spec(spec)
     N = mesh.ndof
     f = torch.from_numpy(synth.uniform_field(N, seed)).to(dev)
     x = torch.zeros_like(f)
+    o = dg.default_opts(precond=precond)
     times, infos = [], []
+    if precond:   # untimed first solve: the host eigendecompositions (cached afterwards)
+        (dg.poisson_solve(mesh, f, x, o) if poisson else dg.helmholtz_solve(mesh, lam, None, 1.0, f, x, o))
     for _ in range(reps):
         x.zero_()  # x is the initial guess: every timed solve starts from zero
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         if poisson:
-            info = dg.poisson_solve(mesh, f, x)
+            info = dg.poisson_solve(mesh, f, x, o)
         else:
-            info = dg.helmholtz_solve(mesh, lam, None, 1.0, f, x)
+            info = dg.helmholtz_solve(mesh, lam, None, 1.0, f, x, o)
         t1 = time.perf_counter()
         times.append(t1 - t0)
         infos.append(info)
     mesh.destroy()
     t = float(np.median(times))
     it = infos[-1]["iters"]
-    return dict(seconds_median=t, solves_per_s=1.0 / t, iters=it, status=infos[-1]["status"],
-                true_rel_res=infos[-1]["true_rel_res"], ndof=N,
-                gdof_iter_per_s=N * it / t / 1e9,
-                # FP64 CG with a constant nu: apply 16, update 48, p-update 24 B/node
-                # (the diagonal is computed, not read)
-                bytes_per_dof_iter=88.0,
-                frac_of_solve_bound=(N * it * 88.0 / t) / (HBM_PEAK_GBS * 1e9))
+    out = dict(seconds_median=t, solves_per_s=1.0 / t, iters=it, status=infos[-1]["status"],
+               true_rel_res=infos[-1]["true_rel_res"], ndof=N)
+    if not precond:
+        # FP64 CG with a constant nu: apply 16, update 48, p-update 24 B/node
+        # (the diagonal is computed, not read)
+        out.update(gdof_iter_per_s=N * it / t / 1e9, bytes_per_dof_iter=88.0,
+                   frac_of_solve_bound=(N * it * 88.0 / t) / (HBM_PEAK_GBS * 1e9))
+    if ref is not None:
+        out["rel_diff_vs_jacobi_fp64"] = float(torch.linalg.vector_norm(x - ref) / torch.linalg.vector_norm(ref))
+    out["x"] = x
+    return out
+
+
+FP64_MATRIX_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix (MFMA)
+
+
+def bench_fdm(dg, torch, spec, lam, reps=20):
+    """The fast-diagonalisation inverse alone: HIP-event time per application
+    on its stream; algorithmic flops 2 L N per transform, forward and
+    backward along three axes: 4 N (Lx + Ly + Lz)."""
+    import synth
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    mesh = dg.mesh_from_spec(spec, stream=stream)
+    N = mesh.ndof
+    b = torch.from_numpy(synth.uniform_field(N, 7)).to(dev)
+    x = torch.empty_like(b)
+    dg.helmholtz_fdm_apply(mesh, lam, 1.0, b, x, stream=stream)   # tables
+    for _ in range(3):
+        dg.helmholtz_fdm_apply(mesh, lam, 1.0, b, x, stream=stream)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in ev:
+        e0.record(stream)
+        dg.helmholtz_fdm_apply(mesh, lam, 1.0, b, x, stream=stream)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    durs = np.array([a.elapsed_time(c) * 1e-3 for a, c in ev])
+    P = spec["P"]
+    Ls = [spec[k] * (P + 1) for k in ("nx", "ny", "nz")]
+    flops = 4.0 * N * sum(Ls)
+    mesh.destroy()
+    t = float(np.median(durs))
+    return {"bound": "mfma", "achieved": flops / t / 1e12, "peak": FP64_MATRIX_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": flops / t / 1e12 / FP64_MATRIX_PEAK_TFLOPS,
+            "flops_per_application": flops, "us_median": t * 1e6, "us_min": float(durs.min()) * 1e6,
+            "kernels": "k_fdm_axis x5 (x, y, z fwd+scale+bwd, y, x)", "line_lengths": Ls}
 
 
 def cpu_baseline(spec, lam, budget_s=12.0):
@@ -261,6 +313,7 @@ def bench_batched(dg, torch):
     th = time.perf_counter() - t0
     x_hand = [x.clone() for x in xs]
     o64 = dg.default_opts()
+    ofdm = dg.default_opts(precond=dg.DG_PC_FDM)
 
     def sequential(o):
         for xk in xs:
@@ -276,12 +329,20 @@ def bench_batched(dg, torch):
         return time.perf_counter() - t0, seq
 
     ts, seq = sequential(o64)
+    x_ref64 = [x.clone() for x in xs]
+
+    def errs_to(xm, ref):
+        return [float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)) for a, b in zip(xm, ref)]
 
     def errs(xm):  # error of each mixed result against the FP64 solve of its system
-        return [float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)) for a, b in zip(xm, xs)]
+        return errs_to(xm, xs)
 
     err_pure, err_hand = errs(x_pure), errs(x_hand)
     tm, seqm = sequential(o)
+    x_mixed = [x.clone() for x in xs]
+    sequential(ofdm)   # untimed: the host eigendecompositions of both BC sets
+    tf, seqf = sequential(ofdm)
+    err_fdm = errs_to([x.clone() for x in xs], x_ref64)
     mesh.destroy()
     return dict(ndof_per_field=N, batched_seconds=tb, batched_solves_per_s=4.0 / tb,
                 sequential_fp64_seconds=ts, sequential_fp64_solves_per_s=4.0 / ts,
@@ -295,10 +356,17 @@ def bench_batched(dg, torch):
                 rel_err_vs_fp64=err_pure, handoff_rel_err_vs_fp64=err_hand,
                 fp64_iters=[i["iters"] for i in seq],
                 sequential_mixed_iters=[i["iters"] for i in seqm],
-                sequential_mixed_true_rel_res=[i["true_rel_res"] for i in seqm])
+                sequential_mixed_true_rel_res=[i["true_rel_res"] for i in seqm],
+                # the 4 systems one after another, CG preconditioned by the
+                # fast-diagonalisation inverse (FP64; nu_ref for the nodal nu)
+                sequential_fdm_seconds=tf, sequential_fdm_solves_per_s=4.0 / tf,
+                sequential_fdm_speedup_vs_fp64=ts / tf,
+                sequential_fdm_iters=[i["iters"] for i in seqf],
+                sequential_fdm_true_rel_res=[i["true_rel_res"] for i in seqf],
+                sequential_fdm_rel_diff_vs_jacobi_fp64=err_fdm)
 
 
-def bench_serving(dg, nreq, slots, precision, budget=96 << 30):
+def bench_serving(dg, nreq, slots, precision, budget=96 << 30, precond=0):
     """Real-time replay of the request stream (Poisson arrivals, 200/s)."""
     import synth
     stream = synth.serving_stream()[:nreq]
@@ -310,7 +378,7 @@ def bench_serving(dg, nreq, slots, precision, budget=96 << 30):
         if wait > 0:
             time.sleep(wait)
         ids.append(srv.submit(r["n"], r["P"], r["lam"], None, is_poisson=r["poisson"],
-                              rhs_seed=r["rhs_seed"], precision=precision))
+                              rhs_seed=r["rhs_seed"], precision=precision, precond=precond))
     # wait for the backlog, reporting progress
     last = time.perf_counter()
     while srv.stats()["completed"] < len(ids) and time.perf_counter() - t0 < 3600.0:
@@ -334,6 +402,7 @@ def bench_serving(dg, nreq, slots, precision, budget=96 << 30):
     srv.destroy()
     ndof = sum(r["n"] ** 3 * (r["P"] + 1) ** 3 for r in stream)
     st.update(requests=nreq, slots=slots, precision="mixed" if precision else "fp64",
+              precond="fdm" if precond else "jacobi",
               solves_per_s=nreq / st["makespan"], failed=len(bad), failures=bad[:20],
               offered_per_s=nreq / max(stream[-1]["t_arrival"], 1e-9), mean_ndof=ndof / nreq)
     return st
@@ -351,8 +420,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=60,
                     help="prefix of the 2000-request stream replayed per serving mode")
-    ap.add_argument("--serving-modes", default="fifo_fp64,continuous_fp64,continuous_mixed",
+    ap.add_argument("--serving-modes", default="fifo_fp64,continuous_fp64,continuous_mixed,continuous_fdm",
                     help="serving modes to replay")
+    ap.add_argument("--serving-fdm-requests", type=int, default=2000,
+                    help="requests replayed in the fast-diagonalisation serving mode")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -411,16 +482,40 @@ def main():
         out["flops"] = {"achieved": tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                         "frac": tf / FP64_PEAK_TFLOPS, "flops_per_launch": flops,
                         "counter": "SQ_INSTS_VALU_FLOPS_FP64 x 64"}
-    legs = set(("solve", "poisson", "solve_mixed", "poisson_mixed", "mixed_small", "batched", "serving")
+    legs = set(("fdm", "solve", "poisson", "solve_fdm", "poisson_fdm", "solve_mixed", "poisson_mixed",
+                "mixed_small", "batched", "serving")
                if args.legs == "all" else args.legs.split(","))
     if not args.quick:
+        if "fdm" in legs:
+            log("fast-diagonalisation inverse")
+            out["fdm"] = bench_fdm(dg, torch, spec, lam)
+        xref = {}
         if "solve" in legs:
             log("FP64 Helmholtz solve")
             out["solve"] = bench_solve(dg, torch, spec, lam, synth.SEEDS["large_helmholtz"], reps=5)
+            xref["solve"] = out["solve"].pop("x")
         if "poisson" in legs:
             log("Poisson solve")
             out["poisson"] = bench_solve(dg, torch, spec, 0.0, synth.SEEDS["large_poisson"], reps=1,
                                          poisson=True)
+            xref["poisson"] = out["poisson"].pop("x")
+        if "solve_fdm" in legs:
+            log("Helmholtz solve, fast-diagonalisation preconditioner")
+            out["solve_fdm"] = bench_solve(dg, torch, spec, lam, synth.SEEDS["large_helmholtz"], reps=10,
+                                           precond=dg.DG_PC_FDM, ref=xref.get("solve"))
+            out["solve_fdm"].pop("x")
+            if "solve" in out:
+                out["solve_fdm"]["speedup_vs_jacobi_fp64"] = (out["solve"]["seconds_median"] /
+                                                              out["solve_fdm"]["seconds_median"])
+        if "poisson_fdm" in legs:
+            log("Poisson solve, fast-diagonalisation preconditioner")
+            out["poisson_fdm"] = bench_solve(dg, torch, spec, 0.0, synth.SEEDS["large_poisson"], reps=10,
+                                             poisson=True, precond=dg.DG_PC_FDM, ref=xref.get("poisson"))
+            out["poisson_fdm"].pop("x")
+            if "poisson" in out:
+                out["poisson_fdm"]["speedup_vs_jacobi_fp64"] = (out["poisson"]["seconds_median"] /
+                                                                out["poisson_fdm"]["seconds_median"])
+        xref.clear()
         if "solve_mixed" in legs:
             log("mixed-precision Helmholtz solve (same mesh)")
             out["solve_mixed"] = bench_mixed_large(dg, torch, spec, lam)
@@ -435,12 +530,15 @@ def main():
             out["batched"] = bench_batched(dg, torch)
         if args.serving_requests > 0 and "serving" in legs:
             out["serving"] = {}
-            for name, slots, prec in (("fifo_fp64", 1, dg.DG_FP64), ("continuous_fp64", 8, dg.DG_FP64),
-                                      ("continuous_mixed", 8, dg.DG_MIXED)):
-                if name not in args.serving_modes.split(","):
+            for name, slots, prec, pc, nreq in (
+                    ("fifo_fp64", 1, dg.DG_FP64, 0, args.serving_requests),
+                    ("continuous_fp64", 8, dg.DG_FP64, 0, args.serving_requests),
+                    ("continuous_mixed", 8, dg.DG_MIXED, 0, args.serving_requests),
+                    ("continuous_fdm", 8, dg.DG_FP64, dg.DG_PC_FDM, args.serving_fdm_requests)):
+                if name not in args.serving_modes.split(",") or nreq <= 0:
                     continue
-                log("serving:", name)
-                out["serving"][name] = bench_serving(dg, args.serving_requests, slots, prec)
+                log("serving:", name, nreq, "requests")
+                out["serving"][name] = bench_serving(dg, nreq, slots, prec, precond=pc)
         if not args.no_cpu:
             log("CPU oracle baseline")
             out["cpu_baseline"] = cpu_baseline(spec, lam)

@@ -222,3 +222,25 @@ def test_footprint_matches_device_allocation():
     say("single footprint", fp, "allocated", used)
     assert fp <= used + slack and used <= fp + slack
     mesh.destroy()
+
+
+def test_batched_handoff_with_fdm_continuation():
+    # the launch hands the last system (the pressure) to CG preconditioned by
+    # the fast-diagonalisation inverse, which finishes it in a step or two
+    import paper_2112_04167_amd as dg
+    spec = make_spec((3, 3, 3), 5, (0, 0, 1), False)
+    lams, nus, pois, fs, nu, lam = stage_problem(spec)
+    rc, infos, xs = run_batched(spec, lams, nus, pois, fs, handoff=True, precond=dg.DG_PC_FDM)
+    say("batched handoff fdm", rc, infos)
+    assert rc == 0
+    M = dense.mass_diag(spec)
+    opv = naive.Operator(spec, lam, nu)
+    for k in range(3):
+        assert pcg.true_rel_res(opv.apply, xs[k], M * fs[k], M) <= 1.2e-10
+    pspec = dict(spec)
+    pspec["bc"] = (0, 0, 2)
+    Mp = dense.mass_diag(pspec)
+    xp = kron.FDM(pspec, 0.0).solve(Mp * fs[3])
+    say("pressure via fdm continuation, err vs x*", rel(xs[3], xp))
+    assert rel(xs[3], xp) <= 1e-10
+    assert infos[3]["iters"] < 60   # launch iterations + the FDM continuation

@@ -186,3 +186,28 @@ def test_server_held_results_do_not_stall_drain():
     f = synth.splitmix64_uniform(N, 2)
     assert rel(srv.fetch(rid, N), exact(n, P, 12.0, f)) <= 1e-10
     srv.destroy()
+
+
+def test_server_fdm_requests_against_oracle():
+    # requests solved by CG with the fast-diagonalisation preconditioner
+    # (FP64): Helmholtz and singular Poisson requests within 1e-10 of x*, in
+    # one or two iterations; a mixed-precision FDM request is refused
+    import paper_2112_04167_amd as dg
+    srv = server(slots=4)
+    reqs = [(3, 4, 10.0, False), (5, 3, 0.0, True), (4, 7, 1e4, False), (6, 8, 0.0, True), (2, 5, 1.0, False)]
+    ids, fs = [], []
+    for k, (n, P, lam, pois) in enumerate(reqs):
+        f = synth.uniform_field(n ** 3 * (P + 1) ** 3, 200 + k)
+        fs.append(f)
+        ids.append(srv.submit(n, P, lam, f, is_poisson=pois, keep_result=True, precond=dg.DG_PC_FDM))
+    srv.drain()
+    for k, (n, P, lam, pois) in enumerate(reqs):
+        rc, info = srv.poll(ids[k])
+        assert rc == 0, (k, info)
+        x = srv.fetch(ids[k], n ** 3 * (P + 1) ** 3)
+        e = rel(x, exact(n, P, lam, fs[k]))
+        say("server fdm req", k, info["iters"], "err vs x*", e)
+        assert info["iters"] <= 2 and e <= 1e-10
+    with pytest.raises(dg.DGError):
+        srv.submit(3, 4, 1.0, None, precision=dg.DG_MIXED, precond=dg.DG_PC_FDM)
+    srv.destroy()
