@@ -23,7 +23,16 @@
 
 #include <algorithm>
 #include <cmath>
+#include <array>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <string>
+
+#include <sys/stat.h>
 
 #include "fdm.h"
 #include "kernels.h"
@@ -169,32 +178,44 @@ __device__ __forceinline__ void acc_to_lds(const d4 (&acc)[MW][NTC], double *Bs,
 
 // MODE 0: plain transform.  MODE 1 (z axis): forward transform, division by
 // lambda + nu (Lx_i + Ly_j + Lz_k), backward transform.
+//
+// Staging: thread t takes the element-local offsets o = t, t + 256, ...
+// (consecutive threads read consecutive addresses) and the same offsets of
+// every element of the bundle, so the index arithmetic (o -> row within the
+// element, column) is done once per offset, not once per value.
 template <int AXIS, int NTC, int MODE>
 __global__ void __launch_bounds__(256) k_fdm_axis(FdmArgs A)
 {
     constexpr int MW = 16 / NTC;  // row tiles per wave: Lp <= 4 * 16 * MW
+    constexpr int NB = 16 * NTC;  // columns per work-group
     extern __shared__ double Bs[];
     if (A.sc && A.sc->done) return;
     const int bundle = blockIdx.x / A.nchunk;
     const int chunk = blockIdx.x - bundle * A.nchunk;
-    const int f0 = chunk * A.NBc;
-    const int ncol = min(A.NBc, A.F - f0);
-    const int n = A.n, n3 = n * n * n, rs = A.rs;
+    const int f0 = chunk * NB;
+    const int ncol = min(NB, A.F - f0);
+    const int n = A.n, n3 = n * n * n, rs = A.rs, L = A.L, nd = A.nd;
     size_t base, se;
     int i0, i1;
     bundle_base<AXIS>(A, bundle, base, se, i0, i1);
     const double mr = (A.sub_mean && A.sc) ? A.sc->mean_r : 0.0;
 
-    // stage the bundle: zero padding rows and columns, then the values
-    for (int i = threadIdx.x; i < A.Lp * rs; i += blockDim.x) Bs[i] = 0.0;
-    __syncthreads();
-    const int tot = A.nd * n3;
-    for (int i = threadIdx.x; i < tot; i += blockDim.x) {
-        const int e = i / n3, o = i - e * n3;
+    // zero what the products read but the bundle does not fill: rows L..Lp-1
+    // and the columns past the chunk's last one
+    for (int i = L * rs + threadIdx.x; i < A.Lp * rs; i += blockDim.x) Bs[i] = 0.0;
+    if (ncol < NB)
+        for (int i = threadIdx.x; i < L * (NB - ncol); i += blockDim.x) {
+            const int k = i / (NB - ncol);
+            Bs[k * rs + ncol + (i - k * (NB - ncol))] = 0.0;
+        }
+    for (int o = threadIdx.x; o < n3; o += blockDim.x) {
         int ga, f;
         split_o<AXIS>(o, n, ga, f);
         const int c = f - f0;
-        if (c >= 0 && c < ncol) Bs[(e * n + ga) * rs + c] = A.in[base + e * se + o] - mr;
+        if (c < 0 || c >= ncol) continue;
+        const double *src = A.in + base + o;
+        double *dst = Bs + ga * rs + c;
+        for (int e = 0; e < nd; ++e) dst[e * n * rs] = src[e * se] - mr;
     }
     __syncthreads();
 
@@ -205,14 +226,19 @@ __global__ void __launch_bounds__(256) k_fdm_axis(FdmArgs A)
     __syncthreads();
 
     if (MODE == 1) {
-        // divide by the eigenvalue sums; row = z index k, column f -> (b, a)
-        for (int i = threadIdx.x; i < A.L * ncol; i += blockDim.x) {
-            const int k = i / ncol, c = i - k * ncol;
+        // divide by the eigenvalue sums: column c -> (a, b) -> x and y
+        // indices, row -> z index
+        constexpr int RSTEP = 256 / NB;
+        const int c = threadIdx.x % NB, k0 = threadIdx.x / NB;
+        if (c < ncol) {
             const int f = f0 + c, b = f / n, a = f - b * n;
             const int gx = i0 * n + a, gy = i1 * n + b;
-            const double den = A.lambda + A.nu * (A.lam[0][gx] + A.lam[1][gy] + A.lam[2][k]);
-            const bool zero_mode = A.singular && gx == 0 && gy == 0 && k == 0;
-            Bs[k * rs + c] = zero_mode ? 0.0 : Bs[k * rs + c] / den;
+            const double cxy = A.lambda + A.nu * (A.lam[0][gx] + A.lam[1][gy]);
+            const bool zero_col = A.singular && gx == 0 && gy == 0;
+            for (int k = k0; k < L; k += RSTEP) {
+                const double den = cxy + A.nu * A.lam[2][k];
+                Bs[k * rs + c] = (zero_col && k == 0) ? 0.0 : Bs[k * rs + c] / den;
+            }
         }
         __syncthreads();
         gemm_bundle<NTC, MW>(A.G2, Bs, rs, A.Lp, acc);
@@ -221,20 +247,27 @@ __global__ void __launch_bounds__(256) k_fdm_axis(FdmArgs A)
         __syncthreads();
     }
 
-    for (int i = threadIdx.x; i < tot; i += blockDim.x) {
-        const int e = i / n3, o = i - e * n3;
+    for (int o = threadIdx.x; o < n3; o += blockDim.x) {
         int ga, f;
         split_o<AXIS>(o, n, ga, f);
         const int c = f - f0;
-        if (c >= 0 && c < ncol) A.out[base + e * se + o] = Bs[(e * n + ga) * rs + c];
+        if (c < 0 || c >= ncol) continue;
+        double *dst = A.out + base + o;
+        const double *src = Bs + ga * rs + c;
+        for (int e = 0; e < nd; ++e) dst[e * se] = src[e * n * rs];
     }
 }
 
-// columns per work-group: 4 tiles when the bundle fits, else 2
-int pick_ntc(int Lp) { return Lp <= 256 ? 4 : 2; }
+// a work-group of NTC column tiles covers Lp rows (4 waves x 16/NTC row
+// tiles) and its bundle fits the 160 KB of LDS
+bool ntc_valid(int ntc, int Lp)
+{
+    const int lds = Lp * (16 * ntc + 1) * (int)sizeof(double);
+    return 4 * (16 / ntc) * 16 >= Lp && lds <= 160 * 1024;
+}
 
 template <int AXIS, int MODE>
-int launch_axis(const MeshDev &m, const FdmDev &f, FdmArgs a, hipStream_t s)
+int launch_axis(const MeshDev &m, const FdmDev &f, FdmArgs a, int ntc, hipStream_t s)
 {
     const FdmDevAxis &ax = f.ax[AXIS];
     const int n = m.P + 1;
@@ -246,8 +279,11 @@ int launch_axis(const MeshDev &m, const FdmDev &f, FdmArgs a, hipStream_t s)
     a.ny = m.n[1];
     a.nz = m.n[2];
     a.F = n * n;
-    const int ntc = pick_ntc(ax.Lp);
     a.NBc = ntc * 16;
+    if (!ntc_valid(ntc, ax.Lp)) {
+        set_error("fast diagonalisation: tile shape does not fit this mesh line");
+        return DG_ERR_ARG;
+    }
     a.nchunk = (a.F + a.NBc - 1) / a.NBc;
     a.rs = a.NBc + 1;  // odd stride in doubles: consecutive rows start on different banks
     const int nbundle = (int)(m.nel / m.n[AXIS]);
@@ -255,9 +291,149 @@ int launch_axis(const MeshDev &m, const FdmDev &f, FdmArgs a, hipStream_t s)
     const dim3 grid((unsigned)(nbundle * a.nchunk)), block(256);
     if (ntc == 4)
         hipLaunchKernelGGL((k_fdm_axis<AXIS, 4, MODE>), grid, block, lds, s, a);
-    else
+    else if (ntc == 2)
         hipLaunchKernelGGL((k_fdm_axis<AXIS, 2, MODE>), grid, block, lds, s, a);
+    else
+        hipLaunchKernelGGL((k_fdm_axis<AXIS, 1, MODE>), grid, block, lds, s, a);
     DG_HIP_CHECK(hipGetLastError());
+    return DG_OK;
+}
+
+// ---- tile-shape autotuner ------------------------------------------------
+//
+// The column tiles per work-group (NTC = 1, 2 or 4: 16, 32 or 64 mesh lines)
+// trade the reuse of each transform matrix fragment read from L2 (more
+// columns) against LDS per work-group and the padding of the last chunk of
+// a bundle ((P+1)^2 columns per bundle).  Which is fastest depends on the
+// degree and the line lengths, so every transform kernel of a new
+// (architecture, P, nx, ny, nz) is timed once with each valid NTC on the
+// actual data, and the choice is kept in memory and in a cache file (one
+// line per mesh shape: "fdm <arch> <P> <nx> <ny> <nz> <ntc_x> <ntc_y> <ntc_z>"),
+// $DG_TUNE_CACHE or ~/.cache/dg_sipdg_tune.txt.
+
+std::mutex g_tune_mu;
+std::map<std::string, std::array<int, 3>> g_tune;
+bool g_tune_loaded = false;
+
+std::string tune_path()
+{
+    if (const char *e = std::getenv("DG_TUNE_CACHE")) return e;
+    const char *h = std::getenv("HOME");
+    return h ? std::string(h) + "/.cache/dg_sipdg_tune.txt" : std::string();
+}
+
+void tune_load_locked()
+{
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const std::string path = tune_path();
+    if (path.empty()) return;
+    std::ifstream in(path);
+    std::string kind, arch;
+    int P, nx, ny, nz, a, b, c;
+    while (in >> kind >> arch >> P >> nx >> ny >> nz >> a >> b >> c)
+        if (kind == "fdm") {
+            char key[160];
+            std::snprintf(key, sizeof key, "%s %d %d %d %d", arch.c_str(), P, nx, ny, nz);
+            g_tune[key] = {a, b, c};
+        }
+}
+
+void tune_store(const std::string &key, const std::array<int, 3> &v)
+{
+    const std::string path = tune_path();
+    if (path.empty()) return;
+    const size_t slash = path.rfind('/');
+    if (slash != std::string::npos) {  // ~/.cache may not exist yet
+        const std::string dir = path.substr(0, slash);
+        (void)mkdir(dir.c_str(), 0755);
+    }
+    std::ofstream out(path, std::ios::app);
+    if (out) out << "fdm " << key << " " << v[0] << " " << v[1] << " " << v[2] << "\n";
+}
+
+std::string device_arch()
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string a = prop.gcnArchName;
+    for (char &ch : a)
+        if (ch == ' ') ch = '_';
+    return a;
+}
+
+template <int AXIS, int MODE>
+int time_axis(const MeshDev &m, const FdmDev &f, FdmArgs a, int ntc, hipStream_t s, hipEvent_t e0,
+              hipEvent_t e1, float &ms)
+{
+    int rc = launch_axis<AXIS, MODE>(m, f, a, ntc, s);  // warm
+    if (rc) return rc;
+    DG_HIP_CHECK(hipEventRecord(e0, s));
+    for (int k = 0; k < 2; ++k)
+        if ((rc = launch_axis<AXIS, MODE>(m, f, a, ntc, s))) return rc;
+    DG_HIP_CHECK(hipEventRecord(e1, s));
+    DG_HIP_CHECK(hipEventSynchronize(e1));
+    DG_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+    return DG_OK;
+}
+
+// the NTC of the x, y and z transform kernels for this mesh (tuned at first
+// use); in / out: any two distinct vectors of ndof doubles (out is written)
+int tile_choice(const MeshDev &m, const FdmDev &f, const FdmArgs &base, const double *in, double *out,
+                hipStream_t s, std::array<int, 3> &ntc)
+{
+    char key[160];
+    std::snprintf(key, sizeof key, "%s %d %d %d %d", device_arch().c_str(), m.P, m.n[0], m.n[1], m.n[2]);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_load_locked();
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            bool ok = true;
+            for (int d = 0; d < 3; ++d) ok = ok && ntc_valid(it->second[d], f.ax[d].Lp);
+            if (ok) {
+                ntc = it->second;
+                return DG_OK;
+            }
+        }
+    }
+    hipEvent_t e0, e1;
+    DG_HIP_CHECK(hipEventCreate(&e0));
+    DG_HIP_CHECK(hipEventCreate(&e1));
+    FdmArgs a = base;
+    a.sc = nullptr;  // time the work itself, never a finished solve's early exit
+    a.sub_mean = 0;
+    a.in = in;
+    a.out = out;
+    int rc = DG_OK;
+    for (int d = 0; d < 3 && rc == DG_OK; ++d) {
+        float best = 1e30f;
+        ntc[d] = 0;
+        for (int c : {4, 2, 1}) {
+            if (!ntc_valid(c, f.ax[d].Lp)) continue;
+            float ms = 0.f;
+            a.G = f.ax[d].Gf;
+            a.G2 = f.ax[d].Gb;
+            rc = d == 0 ? time_axis<0, 0>(m, f, a, c, s, e0, e1, ms)
+                 : d == 1 ? time_axis<1, 0>(m, f, a, c, s, e0, e1, ms)
+                          : time_axis<2, 1>(m, f, a, c, s, e0, e1, ms);
+            if (rc) break;
+            if (ms < best) {
+                best = ms;
+                ntc[d] = c;
+            }
+        }
+        if (rc == DG_OK && ntc[d] == 0) {
+            set_error("fast diagonalisation: no transform tile shape fits this mesh line");
+            rc = DG_ERR_ARG;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (g_tune.emplace(key, ntc).second) tune_store(key, ntc);
     return DG_OK;
 }
 
@@ -378,32 +554,34 @@ int fdm_apply(const MeshDev &m, const FdmDev &f, double lambda, double nu, bool 
     a.nu = nu;
     a.sc = (const CgScalars *)sc;
     a.singular = singular ? 1 : 0;
-    int rc;
+    std::array<int, 3> ntc;
+    int rc = tile_choice(m, f, a, r, z, s, ntc);
+    if (rc) return rc;
     // forward x (r - mean_r -> z), forward y (z -> tmp), z forward + scale +
     // backward (tmp -> z), backward y (z -> tmp), backward x (tmp -> z)
     a.in = r;
     a.out = z;
     a.G = f.ax[0].Gf;
     a.sub_mean = singular ? 1 : 0;
-    if ((rc = launch_axis<0, 0>(m, f, a, s))) return rc;
+    if ((rc = launch_axis<0, 0>(m, f, a, ntc[0], s))) return rc;
     a.sub_mean = 0;
     a.in = z;
     a.out = tmp;
     a.G = f.ax[1].Gf;
-    if ((rc = launch_axis<1, 0>(m, f, a, s))) return rc;
+    if ((rc = launch_axis<1, 0>(m, f, a, ntc[1], s))) return rc;
     a.in = tmp;
     a.out = z;
     a.G = f.ax[2].Gf;
     a.G2 = f.ax[2].Gb;
-    if ((rc = launch_axis<2, 1>(m, f, a, s))) return rc;
+    if ((rc = launch_axis<2, 1>(m, f, a, ntc[2], s))) return rc;
     a.in = z;
     a.out = tmp;
     a.G = f.ax[1].Gb;
-    if ((rc = launch_axis<1, 0>(m, f, a, s))) return rc;
+    if ((rc = launch_axis<1, 0>(m, f, a, ntc[1], s))) return rc;
     a.in = tmp;
     a.out = z;
     a.G = f.ax[0].Gb;
-    return launch_axis<0, 0>(m, f, a, s);
+    return launch_axis<0, 0>(m, f, a, ntc[0], s);
 }
 
 }  // namespace dg
