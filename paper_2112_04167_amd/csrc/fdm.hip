@@ -24,6 +24,7 @@
 #include <algorithm>
 #include <cmath>
 #include <array>
+#include <type_traits>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -101,56 +102,68 @@ __device__ __forceinline__ void bundle_base(const FdmArgs &A, int bundle, size_t
     }
 }
 
-// OUT tiles (MW per wave, NTC columns tiles) = G^T B, B = the LDS bundle.
-// Wave w owns the output row tiles w, w + 4, w + 8, ...
-template <int NTC, int MW>
+// OUT tiles (MT row tiles per wave, NTC column tiles) = G^T B, B = the LDS
+// bundle.  Wave w owns the row tiles w, w + 4, ..., w + 4 (MT - 1); a tile
+// past the last row (when Lp / 16 is not a multiple of 4) reads a valid row
+// of G and its result is discarded, so the loop has no branches and the
+// compiler can keep the next group's fragment loads in flight while the
+// current group's MFMAs run (a branch per tile made it wait for every load).
+// The K loop runs in groups of 16 (4 MFMA steps of K = 4), A (from L2) and
+// B (from LDS) fragments double-buffered by group.
+template <int NTC, int MT>
 __device__ __forceinline__ void gemm_bundle(const double *__restrict__ G, const double *Bs, int rs,
-                                            int Lp, d4 (&acc)[MW][NTC])
+                                            int Lp, d4 (&acc)[MT][NTC])
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
-    const int mt_n = (Lp / 16 - w + 3) / 4;  // row tiles of this wave
 #pragma unroll
-    for (int mt = 0; mt < MW; ++mt)
+    for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int nt = 0; nt < NTC; ++nt) acc[mt][nt] = d4{0.0, 0.0, 0.0, 0.0};
-    // A operand: lane (li, lk) takes G[k0 + lk][16 T + li]
-    const double *gcol = G + 16 * w + li;
-    constexpr int U = 4;  // K steps per group
-    const int ngrp = Lp / (4 * U);
-    double a0[U][MW], a1[U][MW];
-    auto load_grp = [&](int g, double (&a)[U][MW]) {
+    int col[MT];  // A operand column of this lane per row tile: G[k][16 T + li]
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const size_t k = (size_t)(g * 4 * U + 4 * u + lk) * Lp;
-#pragma unroll
-            for (int mt = 0; mt < MW; ++mt) a[u][mt] = (mt < mt_n) ? gcol[k + 64 * mt] : 0.0;
-        }
-    };
-    auto mma_grp = [&](int g, const double (&a)[U][MW]) {
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int k = g * 4 * U + 4 * u + lk;
-            double b[NTC];
-#pragma unroll
-            for (int nt = 0; nt < NTC; ++nt) b[nt] = Bs[k * rs + 16 * nt + li];
-#pragma unroll
-            for (int mt = 0; mt < MW; ++mt)
-                if (mt < mt_n)
-#pragma unroll
-                    for (int nt = 0; nt < NTC; ++nt)
-                        acc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][mt], b[nt], acc[mt][nt], 0, 0, 0);
-        }
-    };
-    load_grp(0, a0);
-    int g = 0;
-    for (; g + 2 <= ngrp; g += 2) {
-        load_grp(g + 1, a1);
-        mma_grp(g, a0);
-        if (g + 2 < ngrp) load_grp(g + 2, a0);
-        mma_grp(g + 1, a1);
+    for (int mt = 0; mt < MT; ++mt) {
+        const int T = w + 4 * mt;
+        col[mt] = (16 * T < Lp ? 16 * T : 0) + li;
     }
-    if (g < ngrp) mma_grp(g, a0);
+    constexpr int U = 4;
+    const int ngrp = Lp / 16;
+    double a0[U][MT], a1[U][MT], b0[U][NTC], b1[U][NTC];
+    auto load = [&](int g, double (&a)[U][MT], double (&b)[U][NTC]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = 16 * g + 4 * u + lk;
+            const double *gr = G + (size_t)k * Lp;
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) a[u][mt] = gr[col[mt]];
+#pragma unroll
+            for (int nt = 0; nt < NTC; ++nt) b[u][nt] = Bs[k * rs + 16 * nt + li];
+        }
+    };
+    auto mma = [&](const double (&a)[U][MT], const double (&b)[U][NTC]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < NTC; ++nt)
+                    acc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][mt], b[u][nt], acc[mt][nt], 0, 0, 0);
+    };
+    load(0, a0, b0);
+    int g = 0;
+    for (; g + 3 <= ngrp; g += 2) {  // groups g, g + 1; g + 2 exists
+        load(g + 1, a1, b1);
+        mma(a0, b0);
+        load(g + 2, a0, b0);
+        mma(a1, b1);
+    }
+    if (g + 2 == ngrp) {
+        load(g + 1, a1, b1);
+        mma(a0, b0);
+        mma(a1, b1);
+    } else {
+        mma(a0, b0);
+    }
 }
 
 // accumulator element r of a lane -> (row, column) within the 16 x 16 tile
@@ -159,14 +172,13 @@ __device__ __forceinline__ void gemm_bundle(const double *__restrict__ G, const 
 __device__ __forceinline__ int acc_row(int lane, int r) { return 4 * r + (lane >> 4); }
 __device__ __forceinline__ int acc_col(int lane) { return lane & 15; }
 
-template <int NTC, int MW>
-__device__ __forceinline__ void acc_to_lds(const d4 (&acc)[MW][NTC], double *Bs, int rs, int Lp)
+template <int NTC, int MT>
+__device__ __forceinline__ void acc_to_lds(const d4 (&acc)[MT][NTC], double *Bs, int rs, int Lp)
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int mt_n = (Lp / 16 - w + 3) / 4;
 #pragma unroll
-    for (int mt = 0; mt < MW; ++mt)
-        if (mt < mt_n) {
+    for (int mt = 0; mt < MT; ++mt)
+        if (16 * (w + 4 * mt) < Lp) {
             const int row0 = 16 * (w + 4 * mt);
 #pragma unroll
             for (int nt = 0; nt < NTC; ++nt)
@@ -183,11 +195,10 @@ __device__ __forceinline__ void acc_to_lds(const d4 (&acc)[MW][NTC], double *Bs,
 // (consecutive threads read consecutive addresses) and the same offsets of
 // every element of the bundle, so the index arithmetic (o -> row within the
 // element, column) is done once per offset, not once per value.
-template <int AXIS, int NTC, int MODE>
+template <int AXIS, int NTC, int MT, int MODE>
 __global__ void __launch_bounds__(256) k_fdm_axis(FdmArgs A)
 {
-    constexpr int MW = 16 / NTC;  // row tiles per wave: Lp <= 4 * 16 * MW
-    constexpr int NB = 16 * NTC;  // columns per work-group
+    constexpr int NB = 16 * NTC;  // columns per work-group; rows: 4 waves x MT tiles of 16
     extern __shared__ double Bs[];
     if (A.sc && A.sc->done) return;
     const int bundle = blockIdx.x / A.nchunk;
@@ -219,10 +230,10 @@ __global__ void __launch_bounds__(256) k_fdm_axis(FdmArgs A)
     }
     __syncthreads();
 
-    d4 acc[MW][NTC];
-    gemm_bundle<NTC, MW>(A.G, Bs, rs, A.Lp, acc);
+    d4 acc[MT][NTC];
+    gemm_bundle<NTC, MT>(A.G, Bs, rs, A.Lp, acc);
     __syncthreads();  // every wave is done reading the bundle
-    acc_to_lds<NTC, MW>(acc, Bs, rs, A.Lp);
+    acc_to_lds<NTC, MT>(acc, Bs, rs, A.Lp);
     __syncthreads();
 
     if (MODE == 1) {
@@ -241,9 +252,9 @@ __global__ void __launch_bounds__(256) k_fdm_axis(FdmArgs A)
             }
         }
         __syncthreads();
-        gemm_bundle<NTC, MW>(A.G2, Bs, rs, A.Lp, acc);
+        gemm_bundle<NTC, MT>(A.G2, Bs, rs, A.Lp, acc);
         __syncthreads();
-        acc_to_lds<NTC, MW>(acc, Bs, rs, A.Lp);
+        acc_to_lds<NTC, MT>(acc, Bs, rs, A.Lp);
         __syncthreads();
     }
 
@@ -260,10 +271,16 @@ __global__ void __launch_bounds__(256) k_fdm_axis(FdmArgs A)
 
 // a work-group of NTC column tiles covers Lp rows (4 waves x 16/NTC row
 // tiles) and its bundle fits the 160 KB of LDS
+// LDS row stride of a bundle of NTC column tiles: 16 doubles of padding put
+// consecutive rows half the 64 banks apart, so the 4 rows of a B fragment
+// read take the minimum two passes
+int lds_stride(int ntc) { return 16 * ntc + 16; }
+int row_tiles(int Lp) { return (Lp / 16 + 3) / 4; }  // per wave
 bool ntc_valid(int ntc, int Lp)
 {
-    const int lds = Lp * (16 * ntc + 1) * (int)sizeof(double);
-    return 4 * (16 / ntc) * 16 >= Lp && lds <= 160 * 1024;
+    if (ntc != 2 && ntc != 4) return false;
+    const int lds = Lp * lds_stride(ntc) * (int)sizeof(double);
+    return row_tiles(Lp) <= 16 / ntc && lds <= 160 * 1024;
 }
 
 template <int AXIS, int MODE>
@@ -285,23 +302,42 @@ int launch_axis(const MeshDev &m, const FdmDev &f, FdmArgs a, int ntc, hipStream
         return DG_ERR_ARG;
     }
     a.nchunk = (a.F + a.NBc - 1) / a.NBc;
-    a.rs = a.NBc + 1;  // odd stride in doubles: consecutive rows start on different banks
+    a.rs = lds_stride(ntc);
     const int nbundle = (int)(m.nel / m.n[AXIS]);
     const size_t lds = (size_t)a.Lp * a.rs * sizeof(double);
     const dim3 grid((unsigned)(nbundle * a.nchunk)), block(256);
-    if (ntc == 4)
-        hipLaunchKernelGGL((k_fdm_axis<AXIS, 4, MODE>), grid, block, lds, s, a);
-    else if (ntc == 2)
-        hipLaunchKernelGGL((k_fdm_axis<AXIS, 2, MODE>), grid, block, lds, s, a);
-    else
-        hipLaunchKernelGGL((k_fdm_axis<AXIS, 1, MODE>), grid, block, lds, s, a);
+    const int mt = row_tiles(ax.Lp);
+    auto go = [&](auto NT, auto MTc) {
+        hipLaunchKernelGGL((k_fdm_axis<AXIS, decltype(NT)::value, decltype(MTc)::value, MODE>), grid, block,
+                           lds, s, a);
+    };
+    using std::integral_constant;
+    if (ntc == 4) {
+        switch (mt) {
+            case 1: go(integral_constant<int, 4>{}, integral_constant<int, 1>{}); break;
+            case 2: go(integral_constant<int, 4>{}, integral_constant<int, 2>{}); break;
+            case 3: go(integral_constant<int, 4>{}, integral_constant<int, 3>{}); break;
+            default: go(integral_constant<int, 4>{}, integral_constant<int, 4>{}); break;
+        }
+    } else {
+        switch (mt) {
+            case 1: go(integral_constant<int, 2>{}, integral_constant<int, 1>{}); break;
+            case 2: go(integral_constant<int, 2>{}, integral_constant<int, 2>{}); break;
+            case 3: go(integral_constant<int, 2>{}, integral_constant<int, 3>{}); break;
+            case 4: go(integral_constant<int, 2>{}, integral_constant<int, 4>{}); break;
+            case 5: go(integral_constant<int, 2>{}, integral_constant<int, 5>{}); break;
+            case 6: go(integral_constant<int, 2>{}, integral_constant<int, 6>{}); break;
+            case 7: go(integral_constant<int, 2>{}, integral_constant<int, 7>{}); break;
+            default: go(integral_constant<int, 2>{}, integral_constant<int, 8>{}); break;
+        }
+    }
     DG_HIP_CHECK(hipGetLastError());
     return DG_OK;
 }
 
 // ---- tile-shape autotuner ------------------------------------------------
 //
-// The column tiles per work-group (NTC = 1, 2 or 4: 16, 32 or 64 mesh lines)
+// The column tiles per work-group (NTC = 2 or 4: 32 or 64 mesh lines)
 // trade the reuse of each transform matrix fragment read from L2 (more
 // columns) against LDS per work-group and the padding of the last chunk of
 // a bundle ((P+1)^2 columns per bundle).  Which is fastest depends on the
@@ -352,14 +388,23 @@ void tune_store(const std::string &key, const std::array<int, 3> &v)
     if (out) out << "fdm " << key << " " << v[0] << " " << v[1] << " " << v[2] << "\n";
 }
 
+// architecture name of the current device, looked up once per device
+// (hipGetDeviceProperties costs about a millisecond: far too much per call)
 std::string device_arch()
 {
+    static std::mutex mu;
+    static std::map<int, std::string> names;
     int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return "unknown";
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = names.find(dev);
+    if (it != names.end()) return it->second;
     hipDeviceProp_t prop;
-    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
-    std::string a = prop.gcnArchName;
+    std::string a = "unknown";
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) a = prop.gcnArchName;
     for (char &ch : a)
         if (ch == ' ') ch = '_';
+    names[dev] = a;
     return a;
 }
 
@@ -410,7 +455,7 @@ int tile_choice(const MeshDev &m, const FdmDev &f, const FdmArgs &base, const do
     for (int d = 0; d < 3 && rc == DG_OK; ++d) {
         float best = 1e30f;
         ntc[d] = 0;
-        for (int c : {4, 2, 1}) {
+        for (int c : {4, 2}) {
             if (!ntc_valid(c, f.ax[d].Lp)) continue;
             float ms = 0.f;
             a.G = f.ax[d].Gf;
@@ -418,6 +463,13 @@ int tile_choice(const MeshDev &m, const FdmDev &f, const FdmArgs &base, const do
             rc = d == 0 ? time_axis<0, 0>(m, f, a, c, s, e0, e1, ms)
                  : d == 1 ? time_axis<1, 0>(m, f, a, c, s, e0, e1, ms)
                           : time_axis<2, 1>(m, f, a, c, s, e0, e1, ms);
+            if (rc == DG_ERR_DEVICE && hipStreamSynchronize(s) == hipSuccess) {
+                // this shape could not be launched here (a resource limit):
+                // not a candidate
+                (void)hipGetLastError();
+                rc = DG_OK;
+                continue;
+            }
             if (rc) break;
             if (ms < best) {
                 best = ms;
