@@ -211,6 +211,44 @@ int helmholtz_solve_noalloc(dg_mesh *m, double lambda, const double *nu_field, d
 int poisson_solve(dg_mesh *m, const double *rhs, double *x, const dg_solve_opts *opts,
                   dg_solve_info *info);
 
+/* ------------------------------------------------------ projection --
+ * The projection substep of Alg. 3: with the predicted velocity v' (degree
+ * P, three nodal components) and the boundary velocity v_b,
+ *     solve  lap(psi) = div v',  d_n psi = n.(v' - v_b) on the boundary;
+ *     v'' = v' - grad psi,
+ * the pressure psi at degree P-1 (Sec. 3.3).  Discretisation (DG, all
+ * integrals by the (P+1)-point GLL rule of the velocity, exact here):
+ *   D(v; v_b)_q = - sum_K int_K v.grad q + sum_F(interior) int_F {v}.n [q]
+ *                 + sum_F(boundary) int_F (v_b.n_out) q        (weak divergence),
+ *   (G psi, w)  = sum_K int_K grad psi.w - sum_F(interior) int_F [psi] n.{w},
+ * so G is minus the adjoint of D(.; 0) under the GLL masses; the pressure
+ * problem is the SIP Poisson problem of degree P-1 with natural boundaries
+ * (poisson_solve on the pressure mesh) with the load -D(v'; v_b): the
+ * Neumann data n.(v' - v_b) is folded into it.
+ * mv: velocity mesh, degree P = 4..8; mp: pressure mesh with the same
+ * elements, vertices and BCs and degree P-1 (DG_ERR_ARG otherwise).  All
+ * arrays are device doubles in the ABI layout of their mesh. */
+
+/* b = D(v; v_b), a weak vector on the pressure basis.  vbx, vby, vbz: the
+   boundary velocity components as nodal velocity fields (only their values
+   on boundary faces are read), or NULL for v_b = 0.  Asynchronous on
+   `stream` (NULL = the velocity mesh's stream). */
+int dg_divergence(dg_mesh *mv, dg_mesh *mp, const double *vx, const double *vy, const double *vz,
+                  const double *vbx, const double *vby, const double *vbz, double *b, void *stream);
+/* (gx, gy, gz) = G psi at the velocity nodes (nodal values: the derivative of
+   the pressure interpolant minus the lifted face jumps).  Asynchronous. */
+int dg_gradient(dg_mesh *mv, dg_mesh *mp, const double *psi, double *gx, double *gy, double *gz,
+                void *stream);
+/* The substep: load -D(v'; v_b), poisson_solve on mp (opts as there, e.g.
+   precond DG_PC_FDM; the load is weak), v <- v - G psi in place.  psi: in,
+   the initial guess of the pressure solve (zeros, or the previous stage's
+   psi); out, the pressure (M-weighted mean zero).  info: that of the
+   pressure solve, seconds for the whole substep.  Allocates one pressure
+   vector on mp at first use (freed with mp); synchronises mp's stream. */
+int dg_project(dg_mesh *mv, dg_mesh *mp, double *vx, double *vy, double *vz, const double *vbx,
+               const double *vby, const double *vbz, double *psi, const dg_solve_opts *opts,
+               dg_solve_info *info);
+
 /* nsys systems on one mesh, solved together in one persistent, cooperative
    launch: the 3 velocity Helmholtz problems and the pressure Poisson problem
    of one implicit stage (Alg. 3).  Each system runs Jacobi-PCG with its own

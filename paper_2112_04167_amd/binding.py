@@ -86,6 +86,10 @@ _SIGS = {
     "helmholtz_solve_noalloc": ([_VP, ctypes.c_double, _VP, ctypes.c_double, _VP, _VP,
                                  ctypes.POINTER(dg_solve_opts), ctypes.POINTER(dg_solve_info)],
                                 ctypes.c_int),
+    "dg_divergence": ([_VP] * 10, ctypes.c_int),
+    "dg_gradient": ([_VP] * 7, ctypes.c_int),
+    "dg_project": ([_VP] * 9 + [ctypes.POINTER(dg_solve_opts), ctypes.POINTER(dg_solve_info)],
+                   ctypes.c_int),
     "poisson_solve": ([_VP, _VP, _VP, ctypes.POINTER(dg_solve_opts), ctypes.POINTER(dg_solve_info)],
                       ctypes.c_int),
     "helmholtz_solve_batched": ([_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
@@ -275,6 +279,37 @@ def helmholtz_solve_noalloc(mesh, lam, nu_field, nu_const, rhs, x, opts=None,
                                        _dptr(x, torch.float64, mesh.ndof),
                                        ctypes.byref(opts) if opts is not None else None,
                                        ctypes.byref(info))
+    if raise_on_error:
+        _check(rc, allow_warning=True)
+    d = info.as_dict()
+    d["rc"] = rc
+    return d
+
+
+def dg_divergence(mv, mp, v, b, vb=None, stream=None):
+    """b = D(v; v_b) on the pressure mesh mp (degree P-1): weak divergence."""
+    import torch
+    vv = [_dptr(c, torch.float64, mv.ndof) for c in v]
+    bb = [None, None, None] if vb is None else [_dptr(c, torch.float64, mv.ndof) for c in vb]
+    _check(lib().dg_divergence(mv.handle, mp.handle, *vv, *bb, _dptr(b, torch.float64, mp.ndof),
+                               _stream_ptr(stream)))
+
+
+def dg_gradient(mv, mp, psi, g, stream=None):
+    """g = G psi at the velocity nodes (three tensors)."""
+    import torch
+    _check(lib().dg_gradient(mv.handle, mp.handle, _dptr(psi, torch.float64, mp.ndof),
+                             *[_dptr(c, torch.float64, mv.ndof) for c in g], _stream_ptr(stream)))
+
+
+def dg_project(mv, mp, v, psi, vb=None, opts=None, raise_on_error=True):
+    """The projection substep: v <- v - G psi with psi the pressure (in: guess)."""
+    import torch
+    info = dg_solve_info()
+    vv = [_dptr(c, torch.float64, mv.ndof) for c in v]
+    bb = [None, None, None] if vb is None else [_dptr(c, torch.float64, mv.ndof) for c in vb]
+    rc = lib().dg_project(mv.handle, mp.handle, *vv, *bb, _dptr(psi, torch.float64, mp.ndof),
+                          ctypes.byref(opts) if opts is not None else None, ctypes.byref(info))
     if raise_on_error:
         _check(rc, allow_warning=True)
     d = info.as_dict()

@@ -1,0 +1,380 @@
+// Projection substep of Alg. 3 (arXiv 2112.04167) with the pressure at
+// degree P-1 and the velocity at degree P (Sec. 3.3): the DG divergence of a
+// velocity field, the DG gradient of a pressure field, and the velocity
+// update v'' = v' - grad psi (gfx950).
+//
+// Both operators use the (P+1)-point GLL rule of the velocity, which is
+// exact for the products involved (degree 2P-1 per direction):
+//
+//   D(v; v_b)_q = - sum_K int_K v . grad q + sum_F(interior) int_F {v}.n [q]
+//                 + sum_F(boundary) int_F (v_b . n_out) q,
+//   (G psi, w)  = sum_K int_K grad psi . w - sum_F(interior) int_F [psi] n.{w},
+//
+// q ranging over the pressure basis (tensor-product Lagrange polynomials of
+// degree P-1 on its own GLL nodes) and w over the velocity basis; G is minus
+// the adjoint of D without boundary data under the GLL masses.  With
+// collocation at the velocity nodes, G psi at a node is the derivative of the
+// pressure interpolant there, minus, on each interior face through the node,
+// the jump of psi across the face divided by (w_face h) -- the face integral
+// of the lifted jump over the node's mass.
+//
+// One work-group per element: the element's data is staged in LDS and the
+// 1D factors (interpolation Vq and derivative dVq of the pressure basis at
+// the velocity nodes) are applied one direction at a time.  The face terms
+// read the neighbour's face layer from global memory.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "device_common.h"
+#include "dg_internal.h"
+#include "projection.h"
+
+namespace dg {
+
+namespace {
+
+constexpr int kN = kMaxN;      // velocity nodes per direction, at most 9
+constexpr int kM = kMaxN - 1;  // pressure nodes per direction
+
+struct ProjTables {
+    double Vq[kN][kM];   // pressure basis value at velocity node:  Vq[a][i] = l_i(xi_a)
+    double dVq[kN][kM];  // its derivative on [-1, 1]
+    double w[kN];        // velocity GLL weights
+};
+
+struct ProjArgs {
+    ProjTables t;
+    const double *v[3];   // velocity (div) / update input (grad)
+    const double *vb[3];  // boundary data (div; null: v_b = 0)
+    const double *psi;    // pressure (grad)
+    double *out;          // weak divergence (div)
+    double *g[3];         // gradient or updated velocity (grad)
+    const double *h[3];   // element extents per axis
+    int n[3], bc[3];
+    double scale;         // div: factor on the weak vector
+    int update;           // grad: g = v - G psi instead of G psi
+};
+
+// neighbour of element index k along an axis: -1 on a non-periodic boundary
+__device__ __forceinline__ int neighbour(int k, int nk, int bc, bool high)
+{
+    int kn = high ? k + 1 : k - 1;
+    if (kn < 0 || kn >= nk) {
+        if (bc != DG_BC_PERIODIC) return -1;
+        kn = (kn + nk) % nk;
+    }
+    return kn;
+}
+
+// element-major offset of element (ex, ey, ez)
+__device__ __forceinline__ size_t elem_base(const ProjArgs &A, int ex, int ey, int ez, int nodes)
+{
+    return ((size_t)(ez * A.n[1] + ey) * A.n[0] + ex) * nodes;
+}
+
+// index of node (a, b, c) [x fastest] and of the node at position (s, t) of
+// the face layer `layer` normal to axis d (s: the lower tangential axis)
+template <int n>
+__device__ __forceinline__ int node3(int a, int b, int c) { return (c * n + b) * n + a; }
+template <int n>
+__device__ __forceinline__ int face_node(int d, int layer, int s, int t)
+{
+    return d == 0 ? node3<n>(layer, s, t) : d == 1 ? node3<n>(s, layer, t) : node3<n>(s, t, layer);
+}
+
+// ---------------------------------------------------------- divergence --
+template <int P>
+__global__ void __launch_bounds__(256) k_divergence(ProjArgs A)
+{
+    constexpr int n = P + 1, m = P, n3 = n * n * n, m3 = m * m * m;
+    __shared__ double tv[n3];       // scaled velocity component
+    __shared__ double s1[n * n * m];
+    __shared__ double s2[n * m * m];
+    __shared__ double acc[m3];
+    __shared__ double fs[n * n], fq[n * m];
+    const int el = blockIdx.x;
+    const int ex = el % A.n[0], ey = (el / A.n[0]) % A.n[1], ez = el / (A.n[0] * A.n[1]);
+    const int e3[3] = {ex, ey, ez};
+    const double hx = A.h[0][ex], hy = A.h[1][ey], hz = A.h[2][ez];
+    const double hh[3] = {hx, hy, hz};
+    const double J = hx * hy * hz * 0.125;
+    const size_t vb0 = elem_base(A, ex, ey, ez, n3);
+    for (int i = threadIdx.x; i < m3; i += blockDim.x) acc[i] = 0.0;
+    // volume: acc -= (A2 (x) A1 (x) A0)^T (W J v_d), A_d = (2/h_d) dVq, others Vq
+    for (int d = 0; d < 3; ++d) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < n3; i += blockDim.x) {
+            const int a = i % n, b = (i / n) % n, c = i / (n * n);
+            tv[i] = A.t.w[a] * A.t.w[b] * A.t.w[c] * J * A.v[d][vb0 + i];
+        }
+        __syncthreads();
+        const double gd = 2.0 / hh[d];
+        // over a (x): s1[c][b][ix]
+        for (int i = threadIdx.x; i < n * n * m; i += blockDim.x) {
+            const int ix = i % m, cb = i / m;
+            double s = 0.0;
+            for (int a = 0; a < n; ++a) s += (d == 0 ? gd * A.t.dVq[a][ix] : A.t.Vq[a][ix]) * tv[cb * n + a];
+            s1[i] = s;
+        }
+        __syncthreads();
+        // over b (y): s2[c][iy][ix]
+        for (int i = threadIdx.x; i < n * m * m; i += blockDim.x) {
+            const int ix = i % m, iy = (i / m) % m, c = i / (m * m);
+            double s = 0.0;
+            for (int b = 0; b < n; ++b)
+                s += (d == 1 ? gd * A.t.dVq[b][iy] : A.t.Vq[b][iy]) * s1[(c * n + b) * m + ix];
+            s2[i] = s;
+        }
+        __syncthreads();
+        // over c (z)
+        for (int i = threadIdx.x; i < m3; i += blockDim.x) {
+            const int ix = i % m, iy = (i / m) % m, iz = i / (m * m);
+            double s = 0.0;
+            for (int c = 0; c < n; ++c)
+                s += (d == 2 ? gd * A.t.dVq[c][iz] : A.t.Vq[c][iz]) * s2[(c * m + iy) * m + ix];
+            acc[i] -= s;
+        }
+    }
+    // faces: +- sum over the face nodes of omega f q, f = {v_d} or v_b,d
+    for (int d = 0; d < 3; ++d) {
+        const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+        for (int hi = 0; hi < 2; ++hi) {
+            const bool high = hi == 1;
+            const int kn = neighbour(e3[d], A.n[d], A.bc[d], high);
+            if (kn < 0 && !A.vb[d]) continue;  // boundary with v_b = 0: no term
+            int en[3] = {ex, ey, ez};
+            if (kn >= 0) en[d] = kn;
+            const size_t nb0 = elem_base(A, en[0], en[1], en[2], n3);
+            const int layer = high ? n - 1 : 0, nlayer = high ? 0 : n - 1;
+            const double omega0 = hh[t1] * hh[t2] * 0.25, sgn = high ? 1.0 : -1.0;
+            __syncthreads();
+            for (int i = threadIdx.x; i < n * n; i += blockDim.x) {
+                const int s = i % n, t = i / n;
+                const int own = face_node<n>(d, layer, s, t);
+                double f;
+                if (kn >= 0)
+                    f = 0.5 * (A.v[d][vb0 + own] + A.v[d][nb0 + face_node<n>(d, nlayer, s, t)]);
+                else
+                    f = A.vb[d][vb0 + own];
+                fs[i] = sgn * omega0 * A.t.w[s] * A.t.w[t] * f;  // [t][s]
+            }
+            __syncthreads();
+            for (int i = threadIdx.x; i < n * m; i += blockDim.x) {  // over s: fq[t][is]
+                const int is = i % m, t = i / m;
+                double sum = 0.0;
+                for (int s = 0; s < n; ++s) sum += A.t.Vq[s][is] * fs[t * n + s];
+                fq[i] = sum;
+            }
+            __syncthreads();
+            const int ip = high ? m - 1 : 0;
+            for (int i = threadIdx.x; i < m * m; i += blockDim.x) {  // over t
+                const int is = i % m, it = i / m;
+                double sum = 0.0;
+                for (int t = 0; t < n; ++t) sum += A.t.Vq[t][it] * fq[t * m + is];
+                const int q = d == 0 ? (it * m + is) * m + ip : d == 1 ? (it * m + ip) * m + is
+                                                                        : (ip * m + it) * m + is;
+                acc[q] += sum;
+            }
+        }
+    }
+    __syncthreads();
+    const size_t pb = (size_t)el * m3;
+    for (int i = threadIdx.x; i < m3; i += blockDim.x) A.out[pb + i] = A.scale * acc[i];
+}
+
+// ------------------------------------------------------------ gradient --
+template <int P>
+__global__ void __launch_bounds__(256) k_gradient(ProjArgs A)
+{
+    constexpr int n = P + 1, m = P, n3 = n * n * n, m3 = m * m * m;
+    __shared__ double q[m3];
+    __shared__ double s1[m * m * n];
+    __shared__ double s2[m * n * n];
+    __shared__ double g[n3];
+    __shared__ double jf[m * m], jt[n * m], jump[n * n];
+    const int el = blockIdx.x;
+    const int ex = el % A.n[0], ey = (el / A.n[0]) % A.n[1], ez = el / (A.n[0] * A.n[1]);
+    const int e3[3] = {ex, ey, ez};
+    const double hh[3] = {A.h[0][ex], A.h[1][ey], A.h[2][ez]};
+    const size_t vbase = elem_base(A, ex, ey, ez, n3), pbase = elem_base(A, ex, ey, ez, m3);
+    for (int i = threadIdx.x; i < m3; i += blockDim.x) q[i] = A.psi[pbase + i];
+    for (int d = 0; d < 3; ++d) {
+        const double gd = 2.0 / hh[d];
+        __syncthreads();
+        for (int i = threadIdx.x; i < m * m * n; i += blockDim.x) {  // over ix: s1[iz][iy][a]
+            const int a = i % n, r = i / n;
+            double s = 0.0;
+            for (int ix = 0; ix < m; ++ix) s += (d == 0 ? gd * A.t.dVq[a][ix] : A.t.Vq[a][ix]) * q[r * m + ix];
+            s1[i] = s;
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < m * n * n; i += blockDim.x) {  // over iy: s2[iz][b][a]
+            const int a = i % n, b = (i / n) % n, iz = i / (n * n);
+            double s = 0.0;
+            for (int iy = 0; iy < m; ++iy)
+                s += (d == 1 ? gd * A.t.dVq[b][iy] : A.t.Vq[b][iy]) * s1[(iz * m + iy) * n + a];
+            s2[i] = s;
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < n3; i += blockDim.x) {  // over iz: g[c][b][a]
+            const int a = i % n, b = (i / n) % n, c = i / (n * n);
+            double s = 0.0;
+            for (int iz = 0; iz < m; ++iz)
+                s += (d == 2 ? gd * A.t.dVq[c][iz] : A.t.Vq[c][iz]) * s2[(iz * n + b) * n + a];
+            g[i] = s;
+        }
+        // interior faces: g_d -= [psi] / (w_face h_d) on the face's nodes
+        for (int hi = 0; hi < 2; ++hi) {
+            const bool high = hi == 1;
+            const int kn = neighbour(e3[d], A.n[d], A.bc[d], high);
+            if (kn < 0) continue;
+            int en[3] = {ex, ey, ez};
+            en[d] = kn;
+            const size_t nbase = elem_base(A, en[0], en[1], en[2], m3);
+            // L = the element on the low side of the face, R the high side
+            const int pl = m - 1, pr = 0;
+            __syncthreads();
+            for (int i = threadIdx.x; i < m * m; i += blockDim.x) {
+                const int is = i % m, it = i / m;
+                auto at = [&](int layer, int s, int t) {
+                    return d == 0 ? (t * m + s) * m + layer : d == 1 ? (t * m + layer) * m + s
+                                                                     : (layer * m + t) * m + s;
+                };
+                const double own = q[at(high ? pl : pr, is, it)];
+                const double oth = A.psi[nbase + at(high ? pr : pl, is, it)];
+                jf[i] = high ? own - oth : oth - own;  // psi_L - psi_R on pressure face nodes
+            }
+            __syncthreads();
+            for (int i = threadIdx.x; i < n * m; i += blockDim.x) {  // over is: jt[it][s]
+                const int s = i % n, it = i / n;
+                double sum = 0.0;
+                for (int is = 0; is < m; ++is) sum += A.t.Vq[s][is] * jf[it * m + is];
+                jt[i] = sum;
+            }
+            __syncthreads();
+            for (int i = threadIdx.x; i < n * n; i += blockDim.x) {  // over it: jump[t][s]
+                const int s = i % n, t = i / n;
+                double sum = 0.0;
+                for (int it = 0; it < m; ++it) sum += A.t.Vq[t][it] * jt[it * n + s];
+                jump[i] = sum;
+            }
+            __syncthreads();
+            const int layer = high ? n - 1 : 0;
+            const double f = 1.0 / (A.t.w[layer] * hh[d]);
+            for (int i = threadIdx.x; i < n * n; i += blockDim.x) {
+                const int s = i % n, t = i / n;
+                g[face_node<n>(d, layer, s, t)] -= f * jump[i];
+            }
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < n3; i += blockDim.x)
+            A.g[d][vbase + i] = A.update ? A.v[d][vbase + i] - g[i] : g[i];
+    }
+}
+
+ProjTables make_tables(int P)
+{
+    ProjTables t{};
+    const GllTables &gv = gll_cached(P);
+    const GllTables &gp = gll_cached(P - 1);
+    const int n = P + 1, m = P;
+    for (int a = 0; a < n; ++a) {
+        t.w[a] = gv.w[a];
+        const double x = gv.xi[a];
+        for (int i = 0; i < m; ++i) {
+            // Lagrange basis l_i of the pressure nodes and its derivative at x
+            double l = 1.0, dl = 0.0;
+            for (int k = 0; k < m; ++k) {
+                if (k == i) continue;
+                const double r = 1.0 / (gp.xi[i] - gp.xi[k]);
+                dl = dl * (x - gp.xi[k]) * r + l * r;
+                l *= (x - gp.xi[k]) * r;
+            }
+            t.Vq[a][i] = l;
+            t.dVq[a][i] = dl;
+        }
+    }
+    return t;
+}
+
+template <typename F>
+int with_Pv(int P, F &&f)
+{
+    switch (P) {
+        case 4: f(std::integral_constant<int, 4>{}); break;
+        case 5: f(std::integral_constant<int, 5>{}); break;
+        case 6: f(std::integral_constant<int, 6>{}); break;
+        case 7: f(std::integral_constant<int, 7>{}); break;
+        case 8: f(std::integral_constant<int, 8>{}); break;
+        default: set_error("the projection needs a velocity degree 4..8 (pressure 3..7)"); return DG_ERR_ARG;
+    }
+    DG_HIP_CHECK(hipGetLastError());
+    return DG_OK;
+}
+
+int check_pair(const MeshDev &mv, const MeshDev &mp)
+{
+    if (mp.P != mv.P - 1) {
+        set_error("the pressure mesh must have degree P-1 of the velocity mesh");
+        return DG_ERR_ARG;
+    }
+    for (int d = 0; d < 3; ++d)
+        if (mp.n[d] != mv.n[d] || mp.v[d] != mv.v[d] || mp.bc[d] != mv.bc[d]) {
+            set_error("the pressure and velocity meshes must share elements, vertices and BCs");
+            return DG_ERR_ARG;
+        }
+    return DG_OK;
+}
+
+ProjArgs base_args(const MeshDev &mv)
+{
+    ProjArgs a{};
+    a.t = make_tables(mv.P);
+    for (int d = 0; d < 3; ++d) {
+        a.n[d] = mv.n[d];
+        a.bc[d] = mv.bc[d];
+    }
+    a.h[0] = mv.h64;
+    a.h[1] = mv.h64 + mv.n[0];
+    a.h[2] = mv.h64 + mv.n[0] + mv.n[1];
+    return a;
+}
+
+}  // namespace
+
+int launch_divergence(const MeshDev &mv, const MeshDev &mp, const double *const v[3],
+                      const double *const vb[3], double scale, double *out, hipStream_t s)
+{
+    if (int rc = check_pair(mv, mp)) return rc;
+    ProjArgs a = base_args(mv);
+    for (int d = 0; d < 3; ++d) {
+        a.v[d] = v[d];
+        a.vb[d] = vb ? vb[d] : nullptr;
+    }
+    a.out = out;
+    a.scale = scale;
+    return with_Pv(mv.P, [&](auto PC) {
+        hipLaunchKernelGGL((k_divergence<decltype(PC)::value>), dim3((unsigned)mv.nel), dim3(256), 0, s, a);
+    });
+}
+
+int launch_gradient(const MeshDev &mv, const MeshDev &mp, const double *psi, const double *const v[3],
+                    double *const g[3], hipStream_t s)
+{
+    if (int rc = check_pair(mv, mp)) return rc;
+    ProjArgs a = base_args(mv);
+    a.psi = psi;
+    a.update = v ? 1 : 0;
+    for (int d = 0; d < 3; ++d) {
+        a.v[d] = v ? v[d] : nullptr;
+        a.g[d] = g[d];
+    }
+    return with_Pv(mv.P, [&](auto PC) {
+        hipLaunchKernelGGL((k_gradient<decltype(PC)::value>), dim3((unsigned)mv.nel), dim3(256), 0, s, a);
+    });
+}
+
+}  // namespace dg

@@ -19,6 +19,7 @@
 #include "dg_internal.h"
 #include "fdm.h"
 #include "kernels.h"
+#include "projection.h"
 
 namespace dg {
 
@@ -78,6 +79,7 @@ struct dg_mesh {
     BatchWorkspace bws;
     void *geo_block = nullptr;  // device: extents, reciprocals, visiting order
     bool geo_external = false;
+    double *aux = nullptr;      // device: the projection's pressure load (ndof doubles)
 };
 
 namespace {
@@ -1070,6 +1072,7 @@ int dg_mesh_destroy(dg_mesh *m)
     if (m->bws.base) (void)hipFree(m->bws.base);
     if (m->bws.host_state) (void)hipHostFree(m->bws.host_state);
     if (m->geo_block && !m->geo_external) (void)hipFree(m->geo_block);
+    if (m->aux) (void)hipFree(m->aux);
     delete m;
     return DG_OK;
 }
@@ -1268,6 +1271,79 @@ int helmholtz_fdm_apply(dg_mesh *m, double lambda, double nu_const, int is_poiss
     if (s != m->stream) DG_HIP_CHECK(hipStreamSynchronize(m->stream));  // the table upload
     const bool singular = lambda == 0.0 && !has_dirichlet(bc);
     return fdm_apply(m->dev, f, lambda, nu_const, singular, b, x, w.q64, nullptr, s);
+}
+
+int dg_divergence(dg_mesh *mv, dg_mesh *mp, const double *vx, const double *vy, const double *vz,
+                  const double *vbx, const double *vby, const double *vbz, double *b, void *stream)
+{
+    if (int rc = check_mesh(mv)) return rc;
+    if (int rc = check_mesh(mp)) return rc;
+    if (!vx || !vy || !vz || !b) {
+        set_error("null velocity or output array");
+        return DG_ERR_ARG;
+    }
+    const double *v[3] = {vx, vy, vz}, *vb[3] = {vbx, vby, vbz};
+    hipStream_t s = stream ? (hipStream_t)stream : mv->stream;
+    return launch_divergence(mv->dev, mp->dev, v, vb, 1.0, b, s);
+}
+
+int dg_gradient(dg_mesh *mv, dg_mesh *mp, const double *psi, double *gx, double *gy, double *gz,
+                void *stream)
+{
+    if (int rc = check_mesh(mv)) return rc;
+    if (int rc = check_mesh(mp)) return rc;
+    if (!psi || !gx || !gy || !gz) {
+        set_error("null pressure or output array");
+        return DG_ERR_ARG;
+    }
+    double *g[3] = {gx, gy, gz};
+    hipStream_t s = stream ? (hipStream_t)stream : mv->stream;
+    return launch_gradient(mv->dev, mp->dev, psi, nullptr, g, s);
+}
+
+int dg_project(dg_mesh *mv, dg_mesh *mp, double *vx, double *vy, double *vz, const double *vbx,
+               const double *vby, const double *vbz, double *psi, const dg_solve_opts *opts,
+               dg_solve_info *info)
+{
+    const double t0 = now();
+    if (int rc = check_mesh(mv)) return rc;
+    if (int rc = check_mesh(mp)) return rc;
+    if (!vx || !vy || !vz || !psi) {
+        set_error("null velocity or pressure array");
+        return DG_ERR_ARG;
+    }
+    // the pressure load -D(v'; v_b), a weak vector, in the pressure mesh's
+    // own buffer, on the pressure mesh's stream after the velocity's work
+    if (!mp->aux) {
+        hipError_t e = hipMalloc((void **)&mp->aux, (size_t)mp->dev.ndof * sizeof(double));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            mp->aux = nullptr;
+            set_error("projection load allocation failed");
+            return DG_ERR_OOM;
+        }
+    }
+    if (mv->stream != mp->stream) DG_HIP_CHECK(hipStreamSynchronize(mv->stream));
+    const double *v[3] = {vx, vy, vz}, *vb[3] = {vbx, vby, vbz};
+    int rc = launch_divergence(mv->dev, mp->dev, v, vb, -1.0, mp->aux, mp->stream);
+    if (rc) return rc;
+    dg_solve_opts o;
+    dg_default_opts(&o);
+    if (opts) o = *opts;
+    o.rhs_is_weak = 1;
+    dg_solve_info pinfo{};
+    rc = poisson_solve(mp, mp->aux, psi, &o, &pinfo);
+    if (rc < 0) {
+        if (info) *info = pinfo;
+        return rc;
+    }
+    double *g[3] = {vx, vy, vz};
+    const int rc2 = launch_gradient(mv->dev, mp->dev, psi, v, g, mp->stream);
+    if (rc2) return rc2;
+    DG_HIP_CHECK(hipStreamSynchronize(mp->stream));
+    pinfo.seconds = now() - t0;
+    if (info) *info = pinfo;
+    return rc;
 }
 
 int poisson_solve(dg_mesh *m, const double *rhs, double *x, const dg_solve_opts *opts,
