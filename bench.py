@@ -29,6 +29,9 @@ Also reported on the same JSON line (each measured after the timed steps):
   poisson_fdm   preconditioned by that inverse (same 1e-10 rule)
   (batched and serving also report the stage and the full 2000-request
   stream with the fast-diagonalisation preconditioner)
+  stage         one implicit stage of Alg. 3 on the 24^3 channel mesh: the
+                projection substep (pressure at P-1 = 4, FDM-PCG) followed by
+                the three velocity Helmholtz solves (P = 5, nodal nu)
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
                        [--legs solve,poisson,...] [--no-cpu]
@@ -366,6 +369,56 @@ def bench_batched(dg, torch):
                 sequential_fdm_rel_diff_vs_jacobi_fp64=err_fdm)
 
 
+def bench_stage(dg, torch, reps=5):
+    """One implicit stage of Alg. 3 on the 24^3 channel mesh: project the
+    predicted velocity v' (pressure of degree P-1 = 4, natural boundaries,
+    v_b = 0, FDM-PCG), then solve v - dt a_ii div(nu grad v) = v'' for the
+    three components (degree 5, nodal nu, Dirichlet walls).  The Helmholtz
+    problem is passed divided by lambda = 1/(dt a_ii): operator M + K_{nu /
+    lambda}, load M v'' (the same solution, with no arithmetic outside the
+    library in the timed region)."""
+    import synth
+    dev = torch.device("cuda:0")
+    spec = synth.mesh_spec("batched_channel")
+    ps = dict(spec)
+    ps["P"] = spec["P"] - 1
+    mv, mp = dg.mesh_from_spec(spec), dg.mesh_from_spec(ps)
+    N = mv.ndof
+    X, Y, _ = dg.mesh_coordinates(mv)
+    lam = synth.batched_lambda()
+    nu_s = (1e-3 * (1.0 + 0.5 * torch.sin(2 * np.pi * X) * torch.cos(2 * np.pi * Y)) / lam).contiguous()
+    v0 = [torch.from_numpy(synth.uniform_field(N, s)).to(dev) for s in synth.SEEDS["batched_velocity"]]
+    xs = [torch.zeros_like(v0[0]) for _ in range(3)]
+    psi = torch.zeros(mp.ndof, dtype=torch.float64, device=dev)
+    op = dg.default_opts(precond=dg.DG_PC_FDM)
+    out = {"ndof_velocity": N, "ndof_pressure": mp.ndof}
+    for name, ov in (("fp64", dg.default_opts()), ("mixed", dg.default_opts(precision=dg.DG_MIXED))):
+        times, tproj = [], []
+        for r in range(reps + 1):
+            v = [c.clone() for c in v0]
+            psi.zero_()
+            for x in xs:
+                x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ip = dg.dg_project(mv, mp, v, psi, opts=op)
+            t1 = time.perf_counter()
+            iv = [dg.helmholtz_solve(mv, 1.0, nu_s, 0.0, v[k], xs[k], ov) for k in range(3)]
+            t2 = time.perf_counter()
+            if r > 0:   # the first stage builds the pressure tables and tunes
+                times.append(t2 - t0)
+                tproj.append(t1 - t0)
+        t = float(np.median(times))
+        out[name] = dict(stage_ms=t * 1e3, projection_ms=float(np.median(tproj)) * 1e3,
+                         pressure_iters=ip["iters"], pressure_true_rel_res=ip["true_rel_res"],
+                         velocity_iters=[i["iters"] for i in iv],
+                         velocity_true_rel_res=[i["true_rel_res"] for i in iv],
+                         stages_per_s=1.0 / t)
+    mv.destroy()
+    mp.destroy()
+    return out
+
+
 def bench_serving(dg, nreq, slots, precision, budget=96 << 30, precond=0):
     """Real-time replay of the request stream (Poisson arrivals, 200/s)."""
     import synth
@@ -483,7 +536,7 @@ def main():
                         "frac": tf / FP64_PEAK_TFLOPS, "flops_per_launch": flops,
                         "counter": "SQ_INSTS_VALU_FLOPS_FP64 x 64"}
     legs = set(("fdm", "solve", "poisson", "solve_fdm", "poisson_fdm", "solve_mixed", "poisson_mixed",
-                "mixed_small", "batched", "serving")
+                "mixed_small", "batched", "stage", "serving")
                if args.legs == "all" else args.legs.split(","))
     if not args.quick:
         if "fdm" in legs:
@@ -528,6 +581,9 @@ def main():
         if "batched" in legs:
             log("batched stage solve")
             out["batched"] = bench_batched(dg, torch)
+        if "stage" in legs:
+            log("implicit stage: projection + three velocity solves")
+            out["stage"] = bench_stage(dg, torch)
         if args.serving_requests > 0 and "serving" in legs:
             out["serving"] = {}
             for name, slots, prec, pc, nreq in (
