@@ -32,6 +32,10 @@ Also reported on the same JSON line (each measured after the timed steps):
   stage         one implicit stage of Alg. 3 on the 24^3 channel mesh: the
                 projection substep (pressure at P-1 = 4, FDM-PCG) followed by
                 the three velocity Helmholtz solves (P = 5, nodal nu)
+  stage_varnu   the same stage with the variable viscosity of Alg. 3:
+                nu_i = nu(v''_i) = nu0 + nu1 (|v''|/v_ref)^2, the earlier
+                stage's F_d1 = div(nu grad v) and F_d3 = -grad(nu div v), the
+                load g_i, and the three solves with the new nodal nu
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
                        [--legs solve,poisson,...] [--no-cpu]
@@ -419,6 +423,64 @@ def bench_stage(dg, torch, reps=5):
     return out
 
 
+def bench_stage_varnu(dg, torch, reps=5):
+    """One variable-viscosity implicit stage (Alg. 3, stage i = 2 of an
+    SDIRK-type scheme) on the 24^3 channel mesh: projection (pressure P-1 =
+    4, FDM-PCG), nu_2 = nu(v''), F_d1 and F_d3 of the first stage's velocity
+    u_1 with nu_1 = nu(u_1), load g = v'' + dt [(aI - aE) F_d1 - aE F_d3]
+    (times lambda = 1/(dt gamma)), three Helmholtz solves with the nodal
+    nu_2 (Jacobi-PCG, FP64 and mixed).  nu0 = nu1 = 1e-3, v_ref = 2,
+    dt = 1e-3, gamma = 0.4358665, aI = 0.2820667, aE = gamma."""
+    import synth
+    dev = torch.device("cuda:0")
+    spec = synth.mesh_spec("batched_channel")
+    ps = dict(spec)
+    ps["P"] = spec["P"] - 1
+    mv, mp = dg.mesh_from_spec(spec), dg.mesh_from_spec(ps)
+    N = mv.ndof
+    dt, gamma, aI, aE = 1e-3, 0.4358665, 0.2820667, 0.4358665
+    lam = 1.0 / (dt * gamma)
+    v0 = [torch.from_numpy(synth.uniform_field(N, s)).to(dev) for s in synth.SEEDS["batched_velocity"]]
+    u1 = [torch.from_numpy(synth.uniform_field(N, 100 + s)).to(dev) for s in synth.SEEDS["batched_velocity"]]
+    nu1, nu2 = torch.empty_like(v0[0]), torch.empty_like(v0[0])
+    F1 = [torch.empty_like(v0[0]) for _ in range(3)]
+    F3 = [torch.empty_like(v0[0]) for _ in range(3)]
+    g = [torch.empty_like(v0[0]) for _ in range(3)]
+    xs = [torch.zeros_like(v0[0]) for _ in range(3)]
+    psi = torch.zeros(mp.ndof, dtype=torch.float64, device=dev)
+    op = dg.default_opts(precond=dg.DG_PC_FDM)
+    out = {"ndof_velocity": N, "ndof_pressure": mp.ndof}
+    for name, ov in (("fp64", dg.default_opts()), ("mixed", dg.default_opts(precision=dg.DG_MIXED))):
+        times, tterms = [], []
+        for r in range(reps + 1):
+            v = [c.clone() for c in v0]
+            psi.zero_()
+            for x in xs:
+                x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ip = dg.dg_project(mv, mp, v, psi, opts=op)
+            dg.dg_viscosity(mv, v, 1e-3, 1e-3, 2.0, nu2)
+            dg.dg_viscosity(mv, u1, 1e-3, 1e-3, 2.0, nu1)
+            dg.dg_viscous_terms(mv, nu1, u1, fd1=F1, fd3=F3)
+            for k in range(3):
+                dg.dg_lincomb(g[k], None, [lam, lam * dt * (aI - aE), -lam * dt * aE], [v[k], F1[k], F3[k]])
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            iv = [dg.helmholtz_solve(mv, lam, nu2, 0.0, g[k], xs[k], ov) for k in range(3)]
+            t2 = time.perf_counter()
+            if r > 0:
+                times.append(t2 - t0)
+                tterms.append(t1 - t0)
+        t = float(np.median(times))
+        out[name] = dict(stage_ms=t * 1e3, projection_and_terms_ms=float(np.median(tterms)) * 1e3,
+                         pressure_iters=ip["iters"], velocity_iters=[i["iters"] for i in iv],
+                         velocity_true_rel_res=[i["true_rel_res"] for i in iv], stages_per_s=1.0 / t)
+    mv.destroy()
+    mp.destroy()
+    return out
+
+
 def bench_serving(dg, nreq, slots, precision, budget=96 << 30, precond=0):
     """Real-time replay of the request stream (Poisson arrivals, 200/s)."""
     import synth
@@ -536,7 +598,7 @@ def main():
                         "frac": tf / FP64_PEAK_TFLOPS, "flops_per_launch": flops,
                         "counter": "SQ_INSTS_VALU_FLOPS_FP64 x 64"}
     legs = set(("fdm", "solve", "poisson", "solve_fdm", "poisson_fdm", "solve_mixed", "poisson_mixed",
-                "mixed_small", "batched", "stage", "serving")
+                "mixed_small", "batched", "stage", "stage_varnu", "serving")
                if args.legs == "all" else args.legs.split(","))
     if not args.quick:
         if "fdm" in legs:
@@ -584,6 +646,9 @@ def main():
         if "stage" in legs:
             log("implicit stage: projection + three velocity solves")
             out["stage"] = bench_stage(dg, torch)
+        if "stage_varnu" in legs:
+            log("variable-viscosity implicit stage")
+            out["stage_varnu"] = bench_stage_varnu(dg, torch)
         if args.serving_requests > 0 and "serving" in legs:
             out["serving"] = {}
             for name, slots, prec, pc, nreq in (

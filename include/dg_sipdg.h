@@ -249,6 +249,36 @@ int dg_project(dg_mesh *mv, dg_mesh *mp, double *vx, double *vy, double *vz, con
                const double *vby, const double *vbz, double *psi, const dg_solve_opts *opts,
                dg_solve_info *info);
 
+/* ------------------------------------------- variable viscosity terms --
+ * The variable-viscosity part of an implicit stage (Alg. 3): the viscosity
+ * at the projected velocity, nu_i = nu(v''_i), and the explicit terms
+ *     F_d1 = div(nu grad v),   F_d3 = -grad(nu div v)
+ * that the stage's Helmholtz load takes from the earlier stages:
+ *     g_i = v''_i + dt sum_{j<i} [ (a^I_ij - a^E_ij) F_d1,j - a^E_ij F_d3,j ].
+ * Discretisation: F_d1 per component is the nodal field -M^-1 K_nu v with
+ * K_nu the SIP operator of the Helmholtz solves at lambda = 0 (nodal nu, the
+ * mesh's BCs: homogeneous Dirichlet data on Dirichlet axes); F_d3 = -G w,
+ * w = nu M^-1 D(v; v_b), with D and G the divergence and gradient of the
+ * projection substep taken on the velocity basis itself (equal order). */
+
+/* nu = nu0 + nu1 (|v| / vref)^2 at every node (the viscosity model of the
+   variable-viscosity test cases, Sec. 4).  vref > 0.  Asynchronous. */
+int dg_viscosity(dg_mesh *m, const double *vx, const double *vy, const double *vz, double nu0,
+                 double nu1, double vref, double *nu, void *stream);
+/* F_d1 (fd1x, fd1y, fd1z) and F_d3 (fd3x, fd3y, fd3z) of the velocity v with
+   the nodal viscosity nu; either triple may be all NULL to skip that term.
+   vbx, vby, vbz: boundary velocity for the divergence in F_d3, or NULL
+   (v_b = 0).  Allocates one scratch vector on m at the first F_d3 (freed
+   with m).  Asynchronous on `stream` (NULL = the mesh's stream). */
+int dg_viscous_terms(dg_mesh *m, const double *nu, const double *vx, const double *vy, const double *vz,
+                     const double *vbx, const double *vby, const double *vbz, double *fd1x, double *fd1y,
+                     double *fd1z, double *fd3x, double *fd3y, double *fd3z, void *stream);
+/* y = x0 + sum_{j<k} coef[j] xs[j] over n device doubles (x0 may be NULL:
+   zero; y may be x0); k <= 16; coef and xs are host arrays.  For the stage
+   load g_i above.  Asynchronous on `stream` (NULL = the default stream). */
+int dg_lincomb(int64_t n, const double *x0, int k, const double *coef, const double *const *xs, double *y,
+               void *stream);
+
 /* nsys systems on one mesh, solved together in one persistent, cooperative
    launch: the 3 velocity Helmholtz problems and the pressure Poisson problem
    of one implicit stage (Alg. 3).  Each system runs Jacobi-PCG with its own

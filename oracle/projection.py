@@ -54,11 +54,13 @@ def pressure_spec(spec):
     return p
 
 
-def _tables(P):
-    """Velocity GLL nodes/weights (degree P) and the pressure Lagrange basis
-    (degree P-1) with its derivative at the velocity nodes: Vq[a, i], dVq[a, i]."""
+def _tables(P, Q):
+    """Velocity GLL nodes/weights (degree P) and the Lagrange basis of the
+    scalar space (degree Q: P-1 for the pressure, P for the equal-order
+    operators of the variable-viscosity terms) with its derivative at the
+    velocity nodes: Vq[a, i], dVq[a, i]."""
     xv, wv = gll.nodes(P), gll.weights(P)
-    xp = gll.nodes(P - 1)
+    xp = gll.nodes(Q)
     Vq, dVq = dense.lagrange_eval(xp, xv)
     return xv, wv, Vq, dVq
 
@@ -74,13 +76,14 @@ def _elements(spec):
                 yield (ex, ey, ez), (ez * spec["ny"] + ey) * spec["nx"] + ex
 
 
-def divergence(spec, v, vb=None):
+def divergence(spec, v, vb=None, q_degree=None):
     """Weak divergence D(v; v_b) on the pressure basis (ABI layout of the
-    degree P-1 mesh).  v, vb: three nodal arrays (ABI layout, degree P);
-    vb None means v_b = 0."""
+    degree P-1 mesh; q_degree = P: on the velocity basis itself).  v, vb:
+    three nodal arrays (ABI layout, degree P); vb None means v_b = 0."""
     P = spec["P"]
-    n, m = P + 1, P
-    xv, wv, Vq, dVq = _tables(P)
+    Q = P - 1 if q_degree is None else q_degree
+    n, m = P + 1, Q + 1
+    xv, wv, Vq, dVq = _tables(P, Q)
     h = _extents(spec)
     nn = (spec["nx"], spec["ny"], spec["nz"])
     nel = nn[0] * nn[1] * nn[2]
@@ -148,12 +151,14 @@ def _add_face(arr, d, layer, val):
         arr[layer, :, :] += val
 
 
-def gradient(spec, psi):
+def gradient(spec, psi, q_degree=None):
     """Nodal gradient G psi on the velocity nodes: three arrays (ABI layout,
-    degree P), psi in the ABI layout of the degree P-1 mesh."""
+    degree P), psi in the ABI layout of the degree P-1 mesh (q_degree = P:
+    of the velocity mesh itself)."""
     P = spec["P"]
-    n, m = P + 1, P
-    xv, wv, Vq, dVq = _tables(P)
+    Q = P - 1 if q_degree is None else q_degree
+    n, m = P + 1, Q + 1
+    xv, wv, Vq, dVq = _tables(P, Q)
     h = _extents(spec)
     nn = (spec["nx"], spec["ny"], spec["nz"])
     nel = nn[0] * nn[1] * nn[2]

@@ -8,7 +8,8 @@ from .binding import (DG_BC_DIRICHLET, DG_BC_NEUMANN, DG_BC_PERIODIC, DG_ERR_ARG
                       DG_ERR_BUDGET, DG_ERR_DEVICE, DG_ERR_NONFINITE, DG_ERR_NOT_SPD, DG_ERR_OOM,
                       DG_FP32, DG_FP64, DG_MIXED, DG_NOT_CONVERGED, DG_OK, DG_PC_FDM, DG_PC_JACOBI,
                       DG_PENDING, DGError,
-                      Mesh, Server, default_opts, dg_divergence, dg_gradient, dg_mesh_create, dg_project,
+                      Mesh, Server, default_opts, dg_divergence, dg_gradient, dg_lincomb, dg_mesh_create,
+                      dg_project, dg_viscosity, dg_viscous_terms,
                       exported_symbols,
                       helmholtz_apply, helmholtz_diag, helmholtz_fdm_apply, helmholtz_solve, helmholtz_solve_batched,
                       helmholtz_solve_noalloc,

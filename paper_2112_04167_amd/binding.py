@@ -90,6 +90,10 @@ _SIGS = {
     "dg_gradient": ([_VP] * 7, ctypes.c_int),
     "dg_project": ([_VP] * 9 + [ctypes.POINTER(dg_solve_opts), ctypes.POINTER(dg_solve_info)],
                    ctypes.c_int),
+    "dg_viscosity": ([_VP] * 4 + [ctypes.c_double] * 3 + [_VP, _VP], ctypes.c_int),
+    "dg_viscous_terms": ([_VP] * 15, ctypes.c_int),
+    "dg_lincomb": ([ctypes.c_int64, _VP, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                    ctypes.POINTER(_VP), _VP, _VP], ctypes.c_int),
     "poisson_solve": ([_VP, _VP, _VP, ctypes.POINTER(dg_solve_opts), ctypes.POINTER(dg_solve_info)],
                       ctypes.c_int),
     "helmholtz_solve_batched": ([_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
@@ -315,6 +319,33 @@ def dg_project(mv, mp, v, psi, vb=None, opts=None, raise_on_error=True):
     d = info.as_dict()
     d["rc"] = rc
     return d
+
+
+def dg_viscosity(mesh, v, nu0, nu1, vref, nu, stream=None):
+    """nu = nu0 + nu1 (|v|/vref)^2 at every node."""
+    import torch
+    _check(lib().dg_viscosity(mesh.handle, *[_dptr(c, torch.float64, mesh.ndof) for c in v], float(nu0),
+                              float(nu1), float(vref), _dptr(nu, torch.float64, mesh.ndof),
+                              _stream_ptr(stream)))
+
+
+def dg_viscous_terms(mesh, nu, v, fd1=None, fd3=None, vb=None, stream=None):
+    """F_d1 = div(nu grad v) and F_d3 = -grad(nu div v) into the given tensors."""
+    import torch
+    p = lambda t: _dptr(t, torch.float64, mesh.ndof)
+    trip = lambda ts: [None] * 3 if ts is None else [p(t) for t in ts]
+    _check(lib().dg_viscous_terms(mesh.handle, p(nu), *[p(c) for c in v], *trip(vb), *trip(fd1), *trip(fd3),
+                                  _stream_ptr(stream)))
+
+
+def dg_lincomb(y, x0, coefs, xs, stream=None):
+    """y = x0 + sum coef_j xs_j (device tensors of equal length; x0 may be None)."""
+    n = y.numel()
+    k = len(xs)
+    c = (ctypes.c_double * max(k, 1))(*[float(v) for v in coefs])
+    pp = (ctypes.c_void_p * max(k, 1))(*[_dptr(t, None, n) for t in xs])
+    _check(lib().dg_lincomb(n, _dptr(x0, None, n) if x0 is not None else None, k, c, pp, _dptr(y, None, n),
+                            _stream_ptr(stream)))
 
 
 def poisson_solve(mesh, rhs, x, opts=None, raise_on_error=True):

@@ -36,12 +36,13 @@ namespace dg {
 
 namespace {
 
-constexpr int kN = kMaxN;      // velocity nodes per direction, at most 9
-constexpr int kM = kMaxN - 1;  // pressure nodes per direction
+constexpr int kN = kMaxN;  // velocity nodes per direction, at most 9
 
+// The scalar space is the pressure (degree Q = P - 1) or, for the
+// variable-viscosity terms, the velocity space itself (Q = P).
 struct ProjTables {
-    double Vq[kN][kM];   // pressure basis value at velocity node:  Vq[a][i] = l_i(xi_a)
-    double dVq[kN][kM];  // its derivative on [-1, 1]
+    double Vq[kN][kN];   // scalar basis value at velocity node:  Vq[a][i] = l_i(xi_a)
+    double dVq[kN][kN];  // its derivative on [-1, 1]
     double w[kN];        // velocity GLL weights
 };
 
@@ -54,8 +55,8 @@ struct ProjArgs {
     double *g[3];         // gradient or updated velocity (grad)
     const double *h[3];   // element extents per axis
     int n[3], bc[3];
-    double scale;         // div: factor on the weak vector
-    int update;           // grad: g = v - G psi instead of G psi
+    double scale;         // div: factor on the weak vector; grad: factor on G psi
+    int update;           // grad: g = v + scale G psi instead of scale G psi
 };
 
 // neighbour of element index k along an axis: -1 on a non-periodic boundary
@@ -86,10 +87,10 @@ __device__ __forceinline__ int face_node(int d, int layer, int s, int t)
 }
 
 // ---------------------------------------------------------- divergence --
-template <int P>
+template <int P, int Q>
 __global__ void __launch_bounds__(256) k_divergence(ProjArgs A)
 {
-    constexpr int n = P + 1, m = P, n3 = n * n * n, m3 = m * m * m;
+    constexpr int n = P + 1, m = Q + 1, n3 = n * n * n, m3 = m * m * m;
     __shared__ double tv[n3];       // scaled velocity component
     __shared__ double s1[n * n * m];
     __shared__ double s2[n * m * m];
@@ -186,10 +187,10 @@ __global__ void __launch_bounds__(256) k_divergence(ProjArgs A)
 }
 
 // ------------------------------------------------------------ gradient --
-template <int P>
+template <int P, int Q>
 __global__ void __launch_bounds__(256) k_gradient(ProjArgs A)
 {
-    constexpr int n = P + 1, m = P, n3 = n * n * n, m3 = m * m * m;
+    constexpr int n = P + 1, m = Q + 1, n3 = n * n * n, m3 = m * m * m;
     __shared__ double q[m3];
     __shared__ double s1[m * m * n];
     __shared__ double s2[m * n * n];
@@ -271,16 +272,16 @@ __global__ void __launch_bounds__(256) k_gradient(ProjArgs A)
         }
         __syncthreads();
         for (int i = threadIdx.x; i < n3; i += blockDim.x)
-            A.g[d][vbase + i] = A.update ? A.v[d][vbase + i] - g[i] : g[i];
+            A.g[d][vbase + i] = A.update ? A.v[d][vbase + i] + A.scale * g[i] : A.scale * g[i];
     }
 }
 
-ProjTables make_tables(int P)
+ProjTables make_tables(int P, int Q)
 {
     ProjTables t{};
     const GllTables &gv = gll_cached(P);
-    const GllTables &gp = gll_cached(P - 1);
-    const int n = P + 1, m = P;
+    const GllTables &gp = gll_cached(Q);
+    const int n = P + 1, m = Q + 1;
     for (int a = 0; a < n; ++a) {
         t.w[a] = gv.w[a];
         const double x = gv.xi[a];
@@ -300,16 +301,31 @@ ProjTables make_tables(int P)
     return t;
 }
 
+// the (velocity degree, scalar degree) pairs: (P, P - 1) for P = 4..8 and
+// (P, P) for P = 3..8
 template <typename F>
-int with_Pv(int P, F &&f)
+int with_pair(int P, int Q, F &&f)
 {
-    switch (P) {
-        case 4: f(std::integral_constant<int, 4>{}); break;
-        case 5: f(std::integral_constant<int, 5>{}); break;
-        case 6: f(std::integral_constant<int, 6>{}); break;
-        case 7: f(std::integral_constant<int, 7>{}); break;
-        case 8: f(std::integral_constant<int, 8>{}); break;
-        default: set_error("the projection needs a velocity degree 4..8 (pressure 3..7)"); return DG_ERR_ARG;
+    using std::integral_constant;
+    if (Q == P - 1) {
+        switch (P) {
+            case 4: f(integral_constant<int, 4>{}, integral_constant<int, 3>{}); break;
+            case 5: f(integral_constant<int, 5>{}, integral_constant<int, 4>{}); break;
+            case 6: f(integral_constant<int, 6>{}, integral_constant<int, 5>{}); break;
+            case 7: f(integral_constant<int, 7>{}, integral_constant<int, 6>{}); break;
+            case 8: f(integral_constant<int, 8>{}, integral_constant<int, 7>{}); break;
+            default: set_error("the projection needs a velocity degree 4..8 (pressure 3..7)"); return DG_ERR_ARG;
+        }
+    } else {
+        switch (P) {
+            case 3: f(integral_constant<int, 3>{}, integral_constant<int, 3>{}); break;
+            case 4: f(integral_constant<int, 4>{}, integral_constant<int, 4>{}); break;
+            case 5: f(integral_constant<int, 5>{}, integral_constant<int, 5>{}); break;
+            case 6: f(integral_constant<int, 6>{}, integral_constant<int, 6>{}); break;
+            case 7: f(integral_constant<int, 7>{}, integral_constant<int, 7>{}); break;
+            case 8: f(integral_constant<int, 8>{}, integral_constant<int, 8>{}); break;
+            default: set_error("degree outside 3..8"); return DG_ERR_ARG;
+        }
     }
     DG_HIP_CHECK(hipGetLastError());
     return DG_OK;
@@ -317,8 +333,8 @@ int with_Pv(int P, F &&f)
 
 int check_pair(const MeshDev &mv, const MeshDev &mp)
 {
-    if (mp.P != mv.P - 1) {
-        set_error("the pressure mesh must have degree P-1 of the velocity mesh");
+    if (mp.P != mv.P - 1 && mp.P != mv.P) {
+        set_error("the scalar mesh must have degree P-1 (pressure) or P of the velocity mesh");
         return DG_ERR_ARG;
     }
     for (int d = 0; d < 3; ++d)
@@ -329,10 +345,10 @@ int check_pair(const MeshDev &mv, const MeshDev &mp)
     return DG_OK;
 }
 
-ProjArgs base_args(const MeshDev &mv)
+ProjArgs base_args(const MeshDev &mv, const MeshDev &mp)
 {
     ProjArgs a{};
-    a.t = make_tables(mv.P);
+    a.t = make_tables(mv.P, mp.P);
     for (int d = 0; d < 3; ++d) {
         a.n[d] = mv.n[d];
         a.bc[d] = mv.bc[d];
@@ -349,32 +365,150 @@ int launch_divergence(const MeshDev &mv, const MeshDev &mp, const double *const 
                       const double *const vb[3], double scale, double *out, hipStream_t s)
 {
     if (int rc = check_pair(mv, mp)) return rc;
-    ProjArgs a = base_args(mv);
+    ProjArgs a = base_args(mv, mp);
     for (int d = 0; d < 3; ++d) {
         a.v[d] = v[d];
         a.vb[d] = vb ? vb[d] : nullptr;
     }
     a.out = out;
     a.scale = scale;
-    return with_Pv(mv.P, [&](auto PC) {
-        hipLaunchKernelGGL((k_divergence<decltype(PC)::value>), dim3((unsigned)mv.nel), dim3(256), 0, s, a);
+    return with_pair(mv.P, mp.P, [&](auto PC, auto QC) {
+        hipLaunchKernelGGL((k_divergence<decltype(PC)::value, decltype(QC)::value>), dim3((unsigned)mv.nel),
+                           dim3(256), 0, s, a);
     });
 }
 
 int launch_gradient(const MeshDev &mv, const MeshDev &mp, const double *psi, const double *const v[3],
-                    double *const g[3], hipStream_t s)
+                    double scale, double *const g[3], hipStream_t s)
 {
     if (int rc = check_pair(mv, mp)) return rc;
-    ProjArgs a = base_args(mv);
+    ProjArgs a = base_args(mv, mp);
     a.psi = psi;
     a.update = v ? 1 : 0;
+    a.scale = scale;
     for (int d = 0; d < 3; ++d) {
         a.v[d] = v ? v[d] : nullptr;
         a.g[d] = g[d];
     }
-    return with_Pv(mv.P, [&](auto PC) {
-        hipLaunchKernelGGL((k_gradient<decltype(PC)::value>), dim3((unsigned)mv.nel), dim3(256), 0, s, a);
+    return with_pair(mv.P, mp.P, [&](auto PC, auto QC) {
+        hipLaunchKernelGGL((k_gradient<decltype(PC)::value, decltype(QC)::value>), dim3((unsigned)mv.nel),
+                           dim3(256), 0, s, a);
     });
+}
+
+// ----------------------------------------------------- nodal kernels --
+namespace {
+
+struct NodalArgs {
+    const double *h[3];
+    double w[kN];
+    int n[3], P;
+    size_t N;
+};
+
+NodalArgs nodal_args(const MeshDev &m)
+{
+    NodalArgs a{};
+    const GllTables &g = gll_cached(m.P);
+    for (int i = 0; i <= m.P; ++i) a.w[i] = g.w[i];
+    a.h[0] = m.h64;
+    a.h[1] = m.h64 + m.n[0];
+    a.h[2] = m.h64 + m.n[0] + m.n[1];
+    for (int d = 0; d < 3; ++d) a.n[d] = m.n[d];
+    a.P = m.P;
+    a.N = (size_t)m.ndof;
+    return a;
+}
+
+// the GLL mass J w_a w_b w_c of node i
+__device__ __forceinline__ double node_mass(const NodalArgs &A, size_t i)
+{
+    const int n = A.P + 1, n3 = n * n * n;
+    const size_t el = i / n3;
+    const int loc = (int)(i - el * n3);
+    const int a = loc % n, b = (loc / n) % n, c = loc / (n * n);
+    const int ex = (int)(el % A.n[0]), ey = (int)((el / A.n[0]) % A.n[1]), ez = (int)(el / ((size_t)A.n[0] * A.n[1]));
+    return A.h[0][ex] * A.h[1][ey] * A.h[2][ez] * 0.125 * A.w[a] * A.w[b] * A.w[c];
+}
+
+// out = s * x * (f or 1) / M   (weak vector -> scaled nodal field)
+__global__ void k_weak_to_nodal(NodalArgs A, const double *x, const double *f, double s, double *out)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < A.N; i += (size_t)gridDim.x * blockDim.x) {
+        const double v = s * x[i] / node_mass(A, i);
+        out[i] = f ? v * f[i] : v;
+    }
+}
+
+__global__ void k_viscosity(const double *vx, const double *vy, const double *vz, size_t N, double nu0,
+                            double nu1, double ivref2, double *nu)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (size_t)gridDim.x * blockDim.x) {
+        const double x = vx[i], y = vy[i], z = vz[i];
+        nu[i] = nu0 + nu1 * (x * x + y * y + z * z) * ivref2;
+    }
+}
+
+constexpr int kMaxComb = 16;
+struct CombArgs {
+    const double *x0;
+    const double *x[kMaxComb];
+    double c[kMaxComb];
+    int k;
+    size_t N;
+    double *y;
+};
+
+__global__ void k_lincomb(CombArgs A)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < A.N; i += (size_t)gridDim.x * blockDim.x) {
+        double s = A.x0 ? A.x0[i] : 0.0;
+        for (int j = 0; j < A.k; ++j) s = fma(A.c[j], A.x[j][i], s);
+        A.y[i] = s;
+    }
+}
+
+dim3 flat_grid(size_t N) { return dim3((unsigned)std::max<size_t>(1, std::min<size_t>((N + 255) / 256, 8192))); }
+
+}  // namespace
+
+int launch_weak_to_nodal(const MeshDev &m, const double *x, const double *f, double s, double *out,
+                         hipStream_t st)
+{
+    hipLaunchKernelGGL(k_weak_to_nodal, flat_grid((size_t)m.ndof), dim3(256), 0, st, nodal_args(m), x, f, s, out);
+    DG_HIP_CHECK(hipGetLastError());
+    return DG_OK;
+}
+
+int launch_viscosity(const MeshDev &m, const double *const v[3], double nu0, double nu1, double vref,
+                     double *nu, hipStream_t st)
+{
+    const size_t N = (size_t)m.ndof;
+    hipLaunchKernelGGL(k_viscosity, flat_grid(N), dim3(256), 0, st, v[0], v[1], v[2], N, nu0, nu1,
+                       1.0 / (vref * vref), nu);
+    DG_HIP_CHECK(hipGetLastError());
+    return DG_OK;
+}
+
+int launch_lincomb(size_t N, const double *x0, int k, const double *c, const double *const *xs, double *y,
+                   hipStream_t st)
+{
+    if (k < 0 || k > kMaxComb) {
+        set_error("at most 16 terms in a linear combination");
+        return DG_ERR_ARG;
+    }
+    CombArgs a{};
+    a.x0 = x0;
+    a.k = k;
+    a.N = N;
+    a.y = y;
+    for (int j = 0; j < k; ++j) {
+        a.c[j] = c[j];
+        a.x[j] = xs[j];
+    }
+    hipLaunchKernelGGL(k_lincomb, flat_grid(N), dim3(256), 0, st, a);
+    DG_HIP_CHECK(hipGetLastError());
+    return DG_OK;
 }
 
 }  // namespace dg

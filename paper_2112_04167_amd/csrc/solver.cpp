@@ -1298,7 +1298,7 @@ int dg_gradient(dg_mesh *mv, dg_mesh *mp, const double *psi, double *gx, double 
     }
     double *g[3] = {gx, gy, gz};
     hipStream_t s = stream ? (hipStream_t)stream : mv->stream;
-    return launch_gradient(mv->dev, mp->dev, psi, nullptr, g, s);
+    return launch_gradient(mv->dev, mp->dev, psi, nullptr, 1.0, g, s);
 }
 
 int dg_project(dg_mesh *mv, dg_mesh *mp, double *vx, double *vy, double *vz, const double *vbx,
@@ -1338,12 +1338,82 @@ int dg_project(dg_mesh *mv, dg_mesh *mp, double *vx, double *vy, double *vz, con
         return rc;
     }
     double *g[3] = {vx, vy, vz};
-    const int rc2 = launch_gradient(mv->dev, mp->dev, psi, v, g, mp->stream);
+    const int rc2 = launch_gradient(mv->dev, mp->dev, psi, v, -1.0, g, mp->stream);
     if (rc2) return rc2;
     DG_HIP_CHECK(hipStreamSynchronize(mp->stream));
     pinfo.seconds = now() - t0;
     if (info) *info = pinfo;
     return rc;
+}
+
+int dg_viscosity(dg_mesh *m, const double *vx, const double *vy, const double *vz, double nu0,
+                 double nu1, double vref, double *nu, void *stream)
+{
+    if (int rc = check_mesh(m)) return rc;
+    if (!vx || !vy || !vz || !nu || !(vref > 0.0) || !std::isfinite(nu0) || !std::isfinite(nu1)) {
+        set_error("null array or bad viscosity coefficients (vref > 0)");
+        return DG_ERR_ARG;
+    }
+    const double *v[3] = {vx, vy, vz};
+    return launch_viscosity(m->dev, v, nu0, nu1, vref, nu, stream ? (hipStream_t)stream : m->stream);
+}
+
+int dg_viscous_terms(dg_mesh *m, const double *nu, const double *vx, const double *vy, const double *vz,
+                     const double *vbx, const double *vby, const double *vbz, double *fd1x, double *fd1y,
+                     double *fd1z, double *fd3x, double *fd3y, double *fd3z, void *stream)
+{
+    if (int rc = check_mesh(m)) return rc;
+    if (!nu || !vx || !vy || !vz) {
+        set_error("null viscosity or velocity array");
+        return DG_ERR_ARG;
+    }
+    const MeshDev &md = m->dev;
+    hipStream_t s = stream ? (hipStream_t)stream : m->stream;
+    const double *v[3] = {vx, vy, vz}, *vb[3] = {vbx, vby, vbz};
+    double *f1[3] = {fd1x, fd1y, fd1z}, *f3[3] = {fd3x, fd3y, fd3z};
+    int rc;
+    // F_d1 = div(nu grad v_d) = -M^-1 K_nu v_d (the SIP operator at lambda = 0)
+    for (int d = 0; d < 3; ++d) {
+        if (!f1[d]) continue;
+        if ((rc = launch_apply<double>(md, md.bc, 0.0, nu, 0.0, v[d], f1[d], s))) return rc;
+        if ((rc = launch_weak_to_nodal(md, f1[d], nullptr, -1.0, f1[d], s))) return rc;
+    }
+    // F_d3 = -grad(nu div v): w = nu M^-1 D(v; v_b) (equal order), F_d3 = -G w
+    if (f3[0] || f3[1] || f3[2]) {
+        if (!(f3[0] && f3[1] && f3[2])) {
+            set_error("F_d3 needs all three output components");
+            return DG_ERR_ARG;
+        }
+        if (!m->aux) {
+            if (stream && s != m->stream) DG_HIP_CHECK(hipStreamSynchronize(s));
+            hipError_t e = hipMalloc((void **)&m->aux, (size_t)md.ndof * sizeof(double));
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                m->aux = nullptr;
+                set_error("viscous-term scratch allocation failed");
+                return DG_ERR_OOM;
+            }
+        }
+        if ((rc = launch_divergence(md, md, v, vb, 1.0, m->aux, s))) return rc;
+        if ((rc = launch_weak_to_nodal(md, m->aux, nu, 1.0, m->aux, s))) return rc;
+        if ((rc = launch_gradient(md, md, m->aux, nullptr, -1.0, f3, s))) return rc;
+    }
+    return DG_OK;
+}
+
+int dg_lincomb(int64_t n, const double *x0, int k, const double *coef, const double *const *xs, double *y,
+               void *stream)
+{
+    if (n < 0 || !y || k < 0 || (k > 0 && (!coef || !xs))) {
+        set_error("bad linear-combination arguments");
+        return DG_ERR_ARG;
+    }
+    for (int j = 0; j < k; ++j)
+        if (!xs[j]) {
+            set_error("null term in a linear combination");
+            return DG_ERR_ARG;
+        }
+    return launch_lincomb((size_t)n, x0, k, coef, xs, y, (hipStream_t)stream);
 }
 
 int poisson_solve(dg_mesh *m, const double *rhs, double *x, const dg_solve_opts *opts,
