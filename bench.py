@@ -481,6 +481,86 @@ def bench_stage_varnu(dg, torch, reps=5):
     return out
 
 
+def convection_flops(P):
+    """Algorithmic FP64 flops of the convective term per element (2 per
+    multiply-add of the sum-factorised contractions): interpolation of three
+    components to the Q^3 Gauss points, the nine transposed (i, k) passes back
+    to the nodes, and per face the interpolation of six traces and the
+    projection of three fluxes, Q = floor(3P/2) + 1."""
+    n, Q = P + 1, 3 * P // 2 + 1
+    interp = 3 * (n * n * Q * n + n * Q * Q * n + Q ** 3 * n)
+    vol = 9 * (n * Q * Q * Q + n * n * Q * Q + n ** 3 * Q)
+    faces = 6 * (6 * (n * Q * n + Q * Q * n) + 3 * (Q * n * Q + n * n * Q))
+    return 2.0 * (interp + vol + faces)
+
+
+def bench_imex_step(dg, torch, reps=3):
+    """One full IMEX-RK step (Alg. 3) of the VVP vortex array on 16^3
+    elements of degree 7 (pressure degree 6): RK-ARS3 and RK-CB3e,
+    nu(v) = 0.01 + 0.01 (|v|/2)^2, dt = 2^-8 from the exact velocity at
+    t = 0, the manufactured forcing at the stage times (evaluated once,
+    before timing), the final projection, every solve FDM-preconditioned
+    to 1e-10.  Also the convective term alone (HIP events on its stream)
+    against the FP64 vector peak."""
+    import synth
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    spec = synth.mesh_spec("vvp_large")
+    ps = dict(spec)
+    ps["P"] = spec["P"] - 1
+    mv, mp = dg.mesh_from_spec(spec, stream=stream), dg.mesh_from_spec(ps, stream=stream)
+    N = mv.ndof
+    X, Y, Z = dg.mesh_coordinates(mv)
+    nu0 = nu1 = 0.01
+    dt = 2.0 ** -8
+    v0 = [c.contiguous() for c in synth.vvp_velocity(X, Y, Z, 0.0, xp=torch)]
+    out = {"ndof_velocity": N, "ndof_pressure": mp.ndof, "elements": mv.nx * mv.ny * mv.nz, "dt": dt}
+    opts = dg.default_opts(precond=dg.DG_PC_FDM)
+    for method in ("RK-ARS3", "RK-CB3e"):
+        tab = dg.imex_tableau(method)
+        f = [[c.contiguous() for c in synth.vvp_forcing(X, Y, Z, tab.c[j] * dt, nu0, nu1, xp=torch)]
+             for j in range(tab.s)]
+        times, info = [], None
+        for r in range(reps + 1):
+            v = [c.clone() for c in v0]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = dg.dg_imex_step(mv, mp, tab, dt, nu0, nu1, synth.VVP_VMAX, v, forcing=f,
+                                   final_projection=True, opts=opts)
+            torch.cuda.synchronize()
+            if r > 0:
+                times.append(time.perf_counter() - t0)
+        ve = synth.vvp_velocity(X, Y, Z, dt, xp=torch)
+        err = max(float(torch.linalg.vector_norm(v[d] - ve[d]) / torch.linalg.vector_norm(ve[d]))
+                  for d in range(3))
+        t = float(np.median(times))
+        out[method] = dict(step_ms=t * 1e3, steps_per_s=1.0 / t, stages=tab.s, solves=info["solves"],
+                           pressure_iters=info["pressure_iters"], velocity_iters=info["velocity_iters"],
+                           rel_error_vs_exact_after_one_step=err)
+    # the convective term alone
+    o = [torch.empty_like(v0[0]) for _ in range(3)]
+    for _ in range(3):
+        dg.dg_convection(mv, v0, o, stream=stream)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(10)]
+    for e0, e1 in ev:
+        e0.record(stream)
+        dg.dg_convection(mv, v0, o, stream=stream)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    durs = np.array([a.elapsed_time(c) * 1e-3 for a, c in ev])
+    tc = float(np.median(durs))
+    nel = spec["nx"] * spec["ny"] * spec["nz"]
+    flops = convection_flops(spec["P"]) * nel
+    out["convection"] = {"bound": "alu", "achieved": flops / tc / 1e12, "peak": FP64_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": flops / tc / 1e12 / FP64_PEAK_TFLOPS,
+                         "flops_per_launch": flops, "us_median": tc * 1e6,
+                         "gauss_points_per_direction": 3 * spec["P"] // 2 + 1}
+    mv.destroy()
+    mp.destroy()
+    return out
+
+
 def bench_serving(dg, nreq, slots, precision, budget=96 << 30, precond=0):
     """Real-time replay of the request stream (Poisson arrivals, 200/s)."""
     import synth
@@ -598,7 +678,7 @@ def main():
                         "frac": tf / FP64_PEAK_TFLOPS, "flops_per_launch": flops,
                         "counter": "SQ_INSTS_VALU_FLOPS_FP64 x 64"}
     legs = set(("fdm", "solve", "poisson", "solve_fdm", "poisson_fdm", "solve_mixed", "poisson_mixed",
-                "mixed_small", "batched", "stage", "stage_varnu", "serving")
+                "mixed_small", "batched", "stage", "stage_varnu", "imex_step", "serving")
                if args.legs == "all" else args.legs.split(","))
     if not args.quick:
         if "fdm" in legs:
@@ -649,6 +729,9 @@ def main():
         if "stage_varnu" in legs:
             log("variable-viscosity implicit stage")
             out["stage_varnu"] = bench_stage_varnu(dg, torch)
+        if "imex_step" in legs:
+            log("full IMEX-RK step (VVP vortex array)")
+            out["imex_step"] = bench_imex_step(dg, torch)
         if args.serving_requests > 0 and "serving" in legs:
             out["serving"] = {}
             for name, slots, prec, pc, nreq in (

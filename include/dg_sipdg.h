@@ -274,10 +274,93 @@ int dg_viscous_terms(dg_mesh *m, const double *nu, const double *vx, const doubl
                      const double *vbx, const double *vby, const double *vbz, double *fd1x, double *fd1y,
                      double *fd1z, double *fd3x, double *fd3y, double *fd3z, void *stream);
 /* y = x0 + sum_{j<k} coef[j] xs[j] over n device doubles (x0 may be NULL:
-   zero; y may be x0); k <= 16; coef and xs are host arrays.  For the stage
+   zero; y may be x0); k <= 32; coef and xs are host arrays.  For the stage
    load g_i above.  Asynchronous on `stream` (NULL = the default stream). */
 int dg_lincomb(int64_t n, const double *x0, int k, const double *coef, const double *const *xs, double *y,
                void *stream);
+
+/* --------------------------------------------- the full IMEX-RK step --
+ * Alg. 3 of arXiv 2112.04167 for incompressible flow with the viscosity
+ * nu(v) = nu0 + nu1 (|v| / vref)^2, with the explicit terms
+ *     F_c = -div(v v),  F_d2 = div(nu (grad v)^T),  F_d3 = -grad(nu div v),
+ * the implicit F_d1 = div(nu grad v), and the forcing F_s = f.  Stage 1 is
+ * v_1 = v, nu_1 = nu(v); stage i = 2..s:
+ *   v'_i  = v + dt [ sum_{j<i} a^E_ij (F_c + F_d + F_d3)_j + sum_{j<=i} a^I_ij F_s,j ]
+ *   v''_i = projection of v'_i (dg_project with v_b = 0, pressure at P-1)
+ *   nu_i  = nu(v''_i)
+ *   g_i   = v''_i + dt sum_{j<i} [ (a^I_ij - a^E_ij) F_d1,j - a^E_ij F_d3,j ]
+ *   v_i   = solution of v_i - dt a^I_ii div(nu_i grad v_i) = g_i (walls: v = 0)
+ * and the step ends with
+ *   v <- v_s + dt sum_i [ (b^E_i - a^E_si)(F_c + F_d2 + F_d3)_i + (b^I_i - a^I_si)(F_d1 + F_s)_i ]
+ * (terms with vanishing factors are not evaluated), then, if asked, a final
+ * projection with d_n psi = 0.
+ * Discretisation: F_c by DG-SEM with local Lax-Friedrichs fluxes, the
+ * integrals by floor(3P/2)+1 Gauss points per direction ("consistent
+ * integration", Sec. 3.3): for each element K with outward normal n,
+ *   (M F_c,i)_phi = int_K sum_k v_k v_i d_k phi - int_dK H_i phi,
+ *   H_i = ((v-.n) v-_i + (v+.n) v+_i)/2 + alpha (v-_i - v+_i)/2,
+ *   alpha = 2 max(|v-.n|, |v+.n|),
+ * v+ the neighbour's trace or, on a wall, v_b (zero when not given); M the
+ * GLL mass.  F_d2,i = M^-1 D(nu (d_i v_0, d_i v_1, d_i v_2)) with the
+ * equal-order D and G of dg_viscous_terms (d_i v_k the i-th component of
+ * G v_k; the field's own trace as its boundary data).  Walls carry v_b = 0:
+ * the Helmholtz solves take homogeneous Dirichlet data. */
+
+enum { DG_RK_TR = 0, DG_RK_CB2 = 1, DG_RK_CB3C = 2, DG_RK_CB3E = 3, DG_RK_CB4 = 4, DG_RK_ARS3 = 5 };
+#define DG_RK_MAX_STAGES 8
+
+/* An IMEX Runge-Kutta tableau: s stages (2 <= s <= 8), abscissae c[s]
+   shared by both parts, implicit aI and explicit aE (row-major s x s in
+   8 x 8 arrays: a[i][j] at [i * 8 + j]), weights bI, bE.  The step needs
+   c[0] = 0, a first stage without implicit term (aI[0][0] = 0), aE strictly
+   lower triangular and aI lower triangular with aI[i][i] >= 0. */
+typedef struct {
+    int s;
+    double c[DG_RK_MAX_STAGES];
+    double aI[DG_RK_MAX_STAGES * DG_RK_MAX_STAGES], bI[DG_RK_MAX_STAGES];
+    double aE[DG_RK_MAX_STAGES * DG_RK_MAX_STAGES], bE[DG_RK_MAX_STAGES];
+} dg_tableau;
+
+/* The tableaux of App. A: RK-TR (3 stages, order 2), RK-CB2 (3, 2),
+   RK-CB3c (4, 3), RK-CB3e (4, 3), RK-CB4 (6, 4) and RK-ARS3 (5, 3; Ascher,
+   Ruuth & Spiteri's (4,4,3)).  DG_ERR_ARG for an unknown method. */
+int dg_imex_tableau(int method, dg_tableau *out);
+
+typedef struct {
+    int status;          /* worst status of the step's solves (DG_OK or DG_NOT_CONVERGED) */
+    int solves;          /* pressure + velocity solves run */
+    int pressure_iters;  /* CG iterations over the projections */
+    int velocity_iters;  /* CG iterations over the Helmholtz solves */
+    double seconds;      /* host wall time of the step */
+} dg_step_info;
+
+/* (ox, oy, oz) = scale F_c(v), or += scale F_c(v) when accumulate, as nodal
+   fields.  vbx, vby, vbz: the wall state (only boundary-face values read),
+   or NULL (zero).  Degree 3..8.  Asynchronous on `stream` (NULL = the mesh's
+   stream); the outputs must not alias v. */
+int dg_convection(dg_mesh *m, const double *vx, const double *vy, const double *vz, const double *vbx,
+                  const double *vby, const double *vbz, double scale, int accumulate, double *ox, double *oy,
+                  double *oz, void *stream);
+/* (ox, oy, oz) = F_d2(v) with the nodal viscosity nu.  Allocates ten scratch
+   vectors on m at first use (the mesh's step workspace, freed with m).
+   Asynchronous on `stream` (NULL = the mesh's stream); outputs must not
+   alias v or nu. */
+int dg_viscous_fd2(dg_mesh *m, const double *nu, const double *vx, const double *vy, const double *vz,
+                   double *ox, double *oy, double *oz, void *stream);
+/* One step of size dt > 0 in place on (vx, vy, vz) (device, velocity mesh
+   mv of degree 4..8; mp its pressure mesh of degree P-1, as for dg_project).
+   forcing: NULL (no forcing) or a host array of 3 s device pointers,
+   forcing[3 j + d] the d-th component of f(t + c_j dt) (each may be NULL:
+   zero).  final_projection: 1 to end with the projection with
+   d_n psi = 0 (for variable viscosity).  opts: the options of every
+   pressure and velocity solve (NULL: defaults; DG_PC_FDM recommended; the
+   velocity solves start from v''_i).  Allocates the mesh's step workspace
+   (about (9 s' + 15) N doubles, s' the stages whose terms the tableau uses)
+   at first use; synchronous.  Returns the first error of a kernel or solve,
+   else info->status. */
+int dg_imex_step(dg_mesh *mv, dg_mesh *mp, const dg_tableau *tab, double dt, double nu0, double nu1,
+                 double vref, double *vx, double *vy, double *vz, const double *const *forcing,
+                 int final_projection, const dg_solve_opts *opts, dg_step_info *info);
 
 /* nsys systems on one mesh, solved together in one persistent, cooperative
    launch: the 3 velocity Helmholtz problems and the pressure Poisson problem

@@ -54,6 +54,26 @@ class dg_request(ctypes.Structure):
                 ("precond", ctypes.c_int)]
 
 
+DG_RK_MAX_STAGES = 8
+DG_RK_TR, DG_RK_CB2, DG_RK_CB3C, DG_RK_CB3E, DG_RK_CB4, DG_RK_ARS3 = range(6)
+RK_METHODS = {"RK-TR": DG_RK_TR, "RK-CB2": DG_RK_CB2, "RK-CB3c": DG_RK_CB3C, "RK-CB3e": DG_RK_CB3E,
+              "RK-CB4": DG_RK_CB4, "RK-ARS3": DG_RK_ARS3}
+
+
+class dg_tableau(ctypes.Structure):
+    _S = DG_RK_MAX_STAGES
+    _fields_ = [("s", ctypes.c_int), ("c", ctypes.c_double * _S), ("aI", ctypes.c_double * (_S * _S)),
+                ("bI", ctypes.c_double * _S), ("aE", ctypes.c_double * (_S * _S)), ("bE", ctypes.c_double * _S)]
+
+
+class dg_step_info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("solves", ctypes.c_int), ("pressure_iters", ctypes.c_int),
+                ("velocity_iters", ctypes.c_int), ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class dg_server_stats(ctypes.Structure):
     _fields_ = [("completed", ctypes.c_int64), ("p50", ctypes.c_double), ("p99", ctypes.c_double),
                 ("mean", ctypes.c_double), ("max", ctypes.c_double), ("makespan", ctypes.c_double),
@@ -96,6 +116,12 @@ _SIGS = {
                     ctypes.POINTER(_VP), _VP, _VP], ctypes.c_int),
     "poisson_solve": ([_VP, _VP, _VP, ctypes.POINTER(dg_solve_opts), ctypes.POINTER(dg_solve_info)],
                       ctypes.c_int),
+    "dg_imex_tableau": ([ctypes.c_int, ctypes.POINTER(dg_tableau)], ctypes.c_int),
+    "dg_convection": ([_VP] * 7 + [ctypes.c_double, ctypes.c_int] + [_VP] * 4, ctypes.c_int),
+    "dg_viscous_fd2": ([_VP] * 9, ctypes.c_int),
+    "dg_imex_step": ([_VP, _VP, ctypes.POINTER(dg_tableau)] + [ctypes.c_double] * 4 + [_VP] * 3 +
+                     [ctypes.POINTER(_VP), ctypes.c_int, ctypes.POINTER(dg_solve_opts),
+                      ctypes.POINTER(dg_step_info)], ctypes.c_int),
     "helmholtz_solve_batched": ([_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(_VP), ctypes.POINTER(ctypes.c_int),
                                  ctypes.POINTER(_VP), ctypes.POINTER(_VP),
@@ -346,6 +372,59 @@ def dg_lincomb(y, x0, coefs, xs, stream=None):
     pp = (ctypes.c_void_p * max(k, 1))(*[_dptr(t, None, n) for t in xs])
     _check(lib().dg_lincomb(n, _dptr(x0, None, n) if x0 is not None else None, k, c, pp, _dptr(y, None, n),
                             _stream_ptr(stream)))
+
+
+def imex_tableau(method):
+    """The App. A tableau `method` (DG_RK_* or its name, e.g. "RK-ARS3")."""
+    if isinstance(method, str):
+        method = RK_METHODS[method]
+    t = dg_tableau()
+    _check(lib().dg_imex_tableau(int(method), ctypes.byref(t)))
+    return t
+
+
+def dg_convection(mesh, v, out, vb=None, scale=1.0, accumulate=False, stream=None):
+    """out = scale F_c(v) (or += with accumulate): -div(v v), LLF fluxes."""
+    import torch
+    p = lambda t: _dptr(t, torch.float64, mesh.ndof)
+    bb = [None] * 3 if vb is None else [p(c) for c in vb]
+    _check(lib().dg_convection(mesh.handle, *[p(c) for c in v], *bb, float(scale), int(bool(accumulate)),
+                               *[p(c) for c in out], _stream_ptr(stream)))
+
+
+def dg_viscous_fd2(mesh, nu, v, out, stream=None):
+    """out = F_d2(v) = div(nu (grad v)^T) with the nodal viscosity nu."""
+    import torch
+    p = lambda t: _dptr(t, torch.float64, mesh.ndof)
+    _check(lib().dg_viscous_fd2(mesh.handle, p(nu), *[p(c) for c in v], *[p(c) for c in out],
+                                _stream_ptr(stream)))
+
+
+def dg_imex_step(mv, mp, tableau, dt, nu0, nu1, vref, v, forcing=None, final_projection=False, opts=None,
+                 raise_on_error=True):
+    """One IMEX-RK step (Alg. 3) in place on the three velocity tensors v.
+    tableau: a dg_tableau or a method (see imex_tableau); forcing: None or a
+    list over the stages of three tensors (or None) each."""
+    import torch
+    tab = tableau if isinstance(tableau, dg_tableau) else imex_tableau(tableau)
+    fp = None
+    if forcing is not None:
+        flat = []
+        for j in range(tab.s):
+            fj = forcing[j] if j < len(forcing) else None
+            for d in range(3):
+                flat.append(None if fj is None or fj[d] is None else _dptr(fj[d], torch.float64, mv.ndof))
+        fp = (ctypes.c_void_p * len(flat))(*flat)
+    info = dg_step_info()
+    rc = lib().dg_imex_step(mv.handle, mp.handle, ctypes.byref(tab), float(dt), float(nu0), float(nu1),
+                            float(vref), *[_dptr(c, torch.float64, mv.ndof) for c in v], fp,
+                            int(bool(final_projection)), ctypes.byref(opts) if opts is not None else None,
+                            ctypes.byref(info))
+    if raise_on_error:
+        _check(rc, allow_warning=True)
+    d = info.as_dict()
+    d["rc"] = rc
+    return d
 
 
 def poisson_solve(mesh, rhs, x, opts=None, raise_on_error=True):

@@ -16,7 +16,7 @@ OUT = os.path.join(HERE, "_lib")
 OBJ = os.path.join(OUT, "obj")
 LIB = os.path.join(OUT, "libdgsipdg.so")
 SOURCES = ["gll_host.cpp", "kernels.hip", "cg_kernels.hip", "solver.cpp", "batched.hip", "server.cpp",
-           "fdm_host.cpp", "fdm.hip", "projection.hip"]
+           "fdm_host.cpp", "fdm.hip", "projection.hip", "convection.hip", "imex.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

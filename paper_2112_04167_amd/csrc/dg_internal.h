@@ -86,4 +86,11 @@ int launch_diag(const MeshDev &m, const int bc[3], double lambda, const T *nu, d
                 hipStream_t s, bool inverse = false);
 int apply_groups(int P, int64_t nel);  // number of work-groups of the apply grid
 
+// Mesh accessors for the step driver (solver.cpp): device description,
+// stream, and a grow-only device buffer of at least `doubles` values owned by
+// the mesh (freed with it; null and the error text set on failure).
+const MeshDev *mesh_device(dg_mesh *m);
+hipStream_t mesh_stream(dg_mesh *m);
+double *mesh_step_buffer(dg_mesh *m, size_t doubles);
+
 }  // namespace dg

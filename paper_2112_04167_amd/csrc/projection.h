@@ -12,11 +12,12 @@ namespace dg {
 // (v_b = 0) and each vb[d] may be null (that component's boundary flux zero)
 int launch_divergence(const MeshDev &mv, const MeshDev &mp, const double *const v[3],
                       const double *const vb[3], double scale, double *out, hipStream_t s);
-// g = scale G psi, or g = v + scale G psi when v is given (g may alias v).
-// mp: the pressure mesh (degree P-1) or, for the equal-order operators of
-// the variable-viscosity terms, the velocity mesh itself
+// g = scale fac G psi (fac a nodal factor of the velocity mesh, null: 1), or
+// g = v + scale fac G psi when v is given (g may alias v).  mp: the pressure
+// mesh (degree P-1) or, for the equal-order operators of the
+// variable-viscosity terms, the velocity mesh itself
 int launch_gradient(const MeshDev &mv, const MeshDev &mp, const double *psi, const double *const v[3],
-                    double scale, double *const g[3], hipStream_t s);
+                    double scale, double *const g[3], hipStream_t s, const double *fac = nullptr);
 // out = s x (f or 1) / M at every node (M the GLL mass): a weak vector to a
 // nodal field
 int launch_weak_to_nodal(const MeshDev &m, const double *x, const double *f, double s, double *out,
@@ -24,7 +25,7 @@ int launch_weak_to_nodal(const MeshDev &m, const double *x, const double *f, dou
 // nu = nu0 + nu1 |v|^2 / vref^2 at every node
 int launch_viscosity(const MeshDev &m, const double *const v[3], double nu0, double nu1, double vref,
                      double *nu, hipStream_t st);
-// y = (x0 or 0) + sum_j c[j] xs[j], k <= 16 terms (y may alias x0)
+// y = (x0 or 0) + sum_j c[j] xs[j], k <= 32 terms (y may alias x0)
 int launch_lincomb(size_t N, const double *x0, int k, const double *c, const double *const *xs, double *y,
                    hipStream_t st);
 

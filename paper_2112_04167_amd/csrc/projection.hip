@@ -57,6 +57,7 @@ struct ProjArgs {
     int n[3], bc[3];
     double scale;         // div: factor on the weak vector; grad: factor on G psi
     int update;           // grad: g = v + scale G psi instead of scale G psi
+    const double *fac;    // grad: nodal factor on scale G psi (null: 1)
 };
 
 // neighbour of element index k along an axis: -1 on a non-periodic boundary
@@ -271,8 +272,10 @@ __global__ void __launch_bounds__(256) k_gradient(ProjArgs A)
             }
         }
         __syncthreads();
-        for (int i = threadIdx.x; i < n3; i += blockDim.x)
-            A.g[d][vbase + i] = A.update ? A.v[d][vbase + i] + A.scale * g[i] : A.scale * g[i];
+        for (int i = threadIdx.x; i < n3; i += blockDim.x) {
+            const double gv = A.fac ? A.scale * g[i] * A.fac[vbase + i] : A.scale * g[i];
+            A.g[d][vbase + i] = A.update ? A.v[d][vbase + i] + gv : gv;
+        }
     }
 }
 
@@ -379,11 +382,12 @@ int launch_divergence(const MeshDev &mv, const MeshDev &mp, const double *const 
 }
 
 int launch_gradient(const MeshDev &mv, const MeshDev &mp, const double *psi, const double *const v[3],
-                    double scale, double *const g[3], hipStream_t s)
+                    double scale, double *const g[3], hipStream_t s, const double *fac)
 {
     if (int rc = check_pair(mv, mp)) return rc;
     ProjArgs a = base_args(mv, mp);
     a.psi = psi;
+    a.fac = fac;
     a.update = v ? 1 : 0;
     a.scale = scale;
     for (int d = 0; d < 3; ++d) {
@@ -449,7 +453,7 @@ __global__ void k_viscosity(const double *vx, const double *vy, const double *vz
     }
 }
 
-constexpr int kMaxComb = 16;
+constexpr int kMaxComb = 32;
 struct CombArgs {
     const double *x0;
     const double *x[kMaxComb];
@@ -494,7 +498,7 @@ int launch_lincomb(size_t N, const double *x0, int k, const double *c, const dou
                    hipStream_t st)
 {
     if (k < 0 || k > kMaxComb) {
-        set_error("at most 16 terms in a linear combination");
+        set_error("at most 32 terms in a linear combination");
         return DG_ERR_ARG;
     }
     CombArgs a{};

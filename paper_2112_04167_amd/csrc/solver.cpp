@@ -80,6 +80,8 @@ struct dg_mesh {
     void *geo_block = nullptr;  // device: extents, reciprocals, visiting order
     bool geo_external = false;
     double *aux = nullptr;      // device: the projection's pressure load (ndof doubles)
+    double *step_buf = nullptr; // device: the IMEX step's stage fields (grow-only)
+    size_t step_doubles = 0;
 };
 
 namespace {
@@ -1040,6 +1042,33 @@ __global__ void k_expand_coords(const double *tab, int nx, int ny, int nz, int n
 
 // ---------------------------------------------------------------- C-ABI --
 
+namespace dg {
+
+const MeshDev *mesh_device(dg_mesh *m) { return m ? &m->dev : nullptr; }
+hipStream_t mesh_stream(dg_mesh *m) { return m->stream; }
+
+double *mesh_step_buffer(dg_mesh *m, size_t doubles)
+{
+    if (m->step_buf && m->step_doubles >= doubles) return m->step_buf;
+    if (m->step_buf) {
+        (void)hipStreamSynchronize(m->stream);
+        (void)hipFree(m->step_buf);
+        m->step_buf = nullptr;
+        m->step_doubles = 0;
+    }
+    hipError_t e = hipMalloc((void **)&m->step_buf, doubles * sizeof(double));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        m->step_buf = nullptr;
+        set_error("step workspace allocation of " + std::to_string(doubles * sizeof(double)) + " bytes failed");
+        return nullptr;
+    }
+    m->step_doubles = doubles;
+    return m->step_buf;
+}
+
+}  // namespace dg
+
 extern "C" {
 
 const char *dg_last_error(void) { return g_last_error.c_str(); }
@@ -1073,6 +1102,7 @@ int dg_mesh_destroy(dg_mesh *m)
     if (m->bws.host_state) (void)hipHostFree(m->bws.host_state);
     if (m->geo_block && !m->geo_external) (void)hipFree(m->geo_block);
     if (m->aux) (void)hipFree(m->aux);
+    if (m->step_buf) (void)hipFree(m->step_buf);
     delete m;
     return DG_OK;
 }

@@ -16,6 +16,9 @@ pressure Poisson problem, on hexahedral GLL meshes, Sec. 3.3):
   mixed_small      the small_periodic mesh at P=7, lambda in {1e2,1e4,1e6}
   batched_channel  24^3, P=5, periodic x,y, Dirichlet z (velocity), Neumann z
                    (pressure); nu(x)=1e-3(1+0.5 sin(2 pi x) cos(2 pi y))
+  vvp_large        16^3 elements, P=7, periodic on [-1/2,1/2]^3: the VVP
+                   vortex array with nu(v) = 0.01 + 0.01 (|v|/2)^2 (one full
+                   IMEX-RK step, Alg. 3)
   serving_stream   2000 requests, Poisson arrivals at 200/s, n^3 cubes,
                    n~U{6..40}, P~U{3..8}, lambda log-uniform in [1,1e6],
                    20% Poisson (lambda=0)
@@ -86,6 +89,12 @@ def mesh_spec(name):
         n, P = 32, 7
         return dict(nx=n, ny=n, nz=n, P=P, xv=vertices_uniform(n), yv=vertices_uniform(n),
                     zv=vertices_tanh(n, 1.5), bc=(BC_PERIODIC, BC_PERIODIC, BC_DIRICHLET))
+    if name == "vvp_large":
+        # the VVP vortex array at scale: [-1/2, 1/2]^3, periodic, 16^3 elements
+        # of degree 7 (2.1M nodes per velocity component, pressure degree 6)
+        n, P = 16, 7
+        v = vertices_uniform(n, -0.5, 0.5)
+        return dict(nx=n, ny=n, nz=n, P=P, xv=v, yv=v.copy(), zv=v.copy(), bc=(BC_PERIODIC,) * 3)
     if name == "batched_channel":
         n, P = 24, 5
         return dict(nx=n, ny=n, nz=n, P=P, xv=vertices_uniform(n), yv=vertices_uniform(n),
@@ -137,3 +146,77 @@ def serving_stream(nreq=2000, rate=200.0, seed=SEEDS["serving_master"], nmin=6, 
                         poisson=bool(pois[i]), lam=0.0 if pois[i] else float(10.0 ** loglam[i]),
                         rhs_seed=SEEDS["serving_base"] + i))
     return out
+
+
+# ----------------------------------------------------------------------------
+# The 3D vortex array with velocity-dependent viscosity (test case VVP of
+# arXiv 2112.04167, Sec. 4.2): exact velocity and pressure on
+# [-1/2, 1/2]^3, periodic, and the forcing that makes them a solution of the
+# momentum equation with nu(v) = nu0 + nu1 (|v| / v_max)^2, v_max = 2.  The
+# forcing is problem data: written from the closed-form derivatives of the
+# exact solution (each velocity term is a product of two sines/cosines of
+# 2 pi (x_k + t), so its Laplacian is -8 pi^2 times itself and d/dt is the
+# sum of the three space derivatives).
+
+VVP_VMAX = 2.0
+
+
+def _vvp_parts(X, Y, Z, t, xp=np):
+    k = 2.0 * np.pi
+    sx, cx = xp.sin(k * (X + t)), xp.cos(k * (X + t))
+    sy, cy = xp.sin(k * (Y + t)), xp.cos(k * (Y + t))
+    sz, cz = xp.sin(k * (Z + t)), xp.cos(k * (Z + t))
+    v = [(sx + cy) * sz, (cx + sy) * sz, (cx + cy) * cz]
+    # J[i][m] = d v_i / d x_m
+    J = [[k * cx * sz, -k * sy * sz, k * (sx + cy) * cz],
+         [-k * sx * sz, k * cy * sz, k * (cx + sy) * cz],
+         [-k * sx * cz, -k * sy * cz, -k * (cx + cy) * sz]]
+    gp = [k * cx * sy * sz, k * sx * cy * sz, k * sx * sy * cz]
+    return v, J, gp
+
+
+def vvp_velocity(X, Y, Z, t, xp=np):
+    """Exact VVP velocity (three arrays) at time t (xp: numpy or torch)."""
+    return _vvp_parts(X, Y, Z, t, xp)[0]
+
+
+def vvp_pressure(X, Y, Z, t):
+    k = 2.0 * np.pi
+    return np.sin(k * (X + t)) * np.sin(k * (Y + t)) * np.sin(k * (Z + t))
+
+
+def vvp_forcing(X, Y, Z, t, nu0, nu1, vmax=VVP_VMAX, xp=np):
+    """f = d_t v + div(v v) - div(nu(v) (grad v + grad v^T)) + grad p for the
+    exact VVP fields (div v = 0); xp: numpy or torch."""
+    v, J, gp = _vvp_parts(X, Y, Z, t, xp)
+    nu = nu0 + nu1 * (v[0] ** 2 + v[1] ** 2 + v[2] ** 2) / (vmax * vmax)
+    dnu = [2.0 * nu1 / (vmax * vmax) * sum(v[m] * J[m][k] for m in range(3)) for k in range(3)]
+    lap = -8.0 * np.pi ** 2
+    f = []
+    for i in range(3):
+        dt_v = J[i][0] + J[i][1] + J[i][2]
+        conv = sum(v[k] * J[i][k] for k in range(3))
+        visc = sum(dnu[k] * (J[i][k] + J[k][i]) for k in range(3)) + nu * lap * v[i]
+        f.append(dt_v + conv - visc + gp[i])
+    return f
+
+
+# A shear flow v = (u(y, t), 0, 0), u = sin(2 pi (y + t)), with the same
+# viscosity law: divergence-free with no convective tendency (v.grad v = 0),
+# so the momentum equation reduces to d_t u = d_y(nu(u) d_y u) + f_x.  The
+# forcing below makes u the exact solution (problem data for the temporal
+# order of the IMEX-RK step with an exact projection).
+
+def shear_velocity(X, Y, Z, t, xp=np):
+    u = xp.sin(2.0 * np.pi * (Y + t))
+    return [u, 0.0 * u, 0.0 * u]
+
+
+def shear_forcing(X, Y, Z, t, nu0, nu1, vmax=VVP_VMAX, xp=np):
+    k = 2.0 * np.pi
+    u = xp.sin(k * (Y + t))
+    uy = k * xp.cos(k * (Y + t))
+    nu = nu0 + nu1 * u * u / (vmax * vmax)
+    nuy = 2.0 * nu1 * u * uy / (vmax * vmax)
+    fx = uy - (nuy * uy - nu * k * k * u)     # d_t u = d_y u here
+    return [fx, 0.0 * u, 0.0 * u]
