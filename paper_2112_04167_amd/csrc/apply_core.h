@@ -712,8 +712,9 @@ __device__ __forceinline__ void apply_group(const ApplyArgs<T> &A, int grp, T *x
         T *__restrict__ ye = A.y + (size_t)el * N3;
         if constexpr (CHUNK) {
             // y of this thread's z-line into its own accumulator slots, then
-            // out as chunks; the element's lines are all in this wave, whose
-            // LDS accesses complete in order, so no barrier is needed
+            // out as chunks; the element's lines are all in this wave, so a
+            // wavefront-scope fence (no work-group barrier) orders the
+            // exchange
 #pragma unroll
             for (int c = 0; c < n; ++c) {
                 const T m = Jw * Wm<P, T>(c);
@@ -725,6 +726,11 @@ __device__ __forceinline__ void apply_group(const ApplyArgs<T> &A, int grp, T *x
                     red[1] += (double)v;
                 }
             }
+            // the chunks below read lines other lanes of this wave wrote:
+            // order those LDS writes before the reads at wavefront scope
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
             for (int r = 0; r < n / V; ++r) {
                 const int f = V * (l + NL * r);
@@ -761,5 +767,6 @@ __device__ __forceinline__ void apply_group(const ApplyArgs<T> &A, int grp, T *x
         }
     }
 }
+
 
 }  // namespace dg

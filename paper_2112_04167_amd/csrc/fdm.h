@@ -56,7 +56,9 @@ int fdm_apply(const MeshDev &m, const FdmDev &f, double lambda, double nu, bool 
               const double *r, double *z, double *tmp, const void *sc, hipStream_t s);
 
 // min and max of a device field of N values (NaN if any is NaN); partial_dev
-// holds at least 64 doubles; synchronises the stream
-int field_range(const double *v, size_t N, double *partial_dev, double &lo, double &hi, hipStream_t s);
+// holds partial_cap >= 2 doubles (one min and one max per work-group);
+// synchronises the stream
+int field_range(const double *v, size_t N, double *partial_dev, size_t partial_cap, double &lo, double &hi,
+                hipStream_t s);
 
 }  // namespace dg

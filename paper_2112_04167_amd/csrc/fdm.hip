@@ -489,8 +489,9 @@ int tile_choice(const MeshDev &m, const FdmDev &f, const FdmArgs &base, const do
     return DG_OK;
 }
 
-// per-work-group min and max of a nodal field
-constexpr int kRangeBlocks = 32;
+// per-work-group min and max of a nodal field (grid-stride; up to
+// kRangeMaxBlocks work-groups, as many as the partial buffer holds)
+constexpr int kRangeMaxBlocks = 1024;
 __global__ void __launch_bounds__(256) k_range(const double *__restrict__ v, size_t N, double *partial)
 {
     __shared__ double smin[4], smax[4];
@@ -524,21 +525,25 @@ __global__ void __launch_bounds__(256) k_range(const double *__restrict__ v, siz
 
 }  // namespace
 
-int field_range(const double *v, size_t N, double *partial_dev, double &lo, double &hi, hipStream_t s)
+int field_range(const double *v, size_t N, double *partial_dev, size_t partial_cap, double &lo, double &hi,
+                hipStream_t s)
 {
-    hipLaunchKernelGGL(k_range, dim3(kRangeBlocks), dim3(256), 0, s, v, N, partial_dev);
+    const size_t want = std::min<size_t>((N + 255) / 256, (size_t)kRangeMaxBlocks);
+    const int nb = (int)std::max<size_t>(1, std::min(want, partial_cap / 2));
+    hipLaunchKernelGGL(k_range, dim3(nb), dim3(256), 0, s, v, N, partial_dev);
     DG_HIP_CHECK(hipGetLastError());
-    double h[2 * kRangeBlocks];
-    DG_HIP_CHECK(hipMemcpyAsync(h, partial_dev, sizeof(h), hipMemcpyDeviceToHost, s));
+    std::vector<double> h(2 * (size_t)nb);
+    DG_HIP_CHECK(hipMemcpyAsync(h.data(), partial_dev, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     DG_HIP_CHECK(hipStreamSynchronize(s));
     lo = h[0];
-    hi = h[kRangeBlocks];
-    for (int k = 1; k < kRangeBlocks; ++k) {
+    hi = h[nb];
+    bool nan = false;
+    for (int k = 0; k < nb; ++k) {
         lo = std::fmin(lo, h[k]);
-        hi = std::fmax(hi, h[kRangeBlocks + k]);
-        if (h[k] != h[k] || h[kRangeBlocks + k] != h[kRangeBlocks + k]) lo = hi = NAN;
+        hi = std::fmax(hi, h[nb + k]);
+        if (h[k] != h[k] || h[nb + k] != h[nb + k]) nan = true;
     }
-    if (h[0] != h[0] || h[kRangeBlocks] != h[kRangeBlocks]) lo = hi = NAN;
+    if (nan) lo = hi = NAN;
     return DG_OK;
 }
 

@@ -279,6 +279,131 @@ __global__ void __launch_bounds__(256) k_gradient(ProjArgs A)
     }
 }
 
+// ------------------------------------------------ equal-order variants --
+// With the scalar space equal to the velocity space (Q = P) the
+// interpolation factor Vq is the identity (exact zeros and ones from the
+// product formula), so only the derivative pass along each axis remains:
+// one 1D contraction per direction and node instead of three passes, and the
+// face terms act on the face nodes directly.  Same sums in the same order as
+// the general kernels above, so the results are bitwise theirs.
+template <int P>
+__global__ void __launch_bounds__(256) k_divergence_eq(ProjArgs A)
+{
+    constexpr int n = P + 1, n3 = n * n * n;
+    __shared__ double tv[3][n3];
+    const int el = blockIdx.x;
+    const int ex = el % A.n[0], ey = (el / A.n[0]) % A.n[1], ez = el / (A.n[0] * A.n[1]);
+    const int e3[3] = {ex, ey, ez};
+    const double hh[3] = {A.h[0][ex], A.h[1][ey], A.h[2][ez]};
+    const double J = hh[0] * hh[1] * hh[2] * 0.125;
+    const size_t vb0 = elem_base(A, ex, ey, ez, n3);
+    for (int r = threadIdx.x; r < 3 * n3; r += blockDim.x) {
+        const int d = r / n3, i = r - d * n3;
+        const int a = i % n, b = (i / n) % n, c = i / (n * n);
+        tv[d][i] = A.t.w[a] * A.t.w[b] * A.t.w[c] * J * A.v[d][vb0 + i];
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < n3; r += blockDim.x) {
+        const int a = r % n, b = (r / n) % n, c = r / (n * n);
+        const int co[3] = {a, b, c};
+        double acc = 0.0;
+        {
+            const double gd = 2.0 / hh[0];
+            double sum = 0.0;
+#pragma unroll
+            for (int k = 0; k < n; ++k) sum += gd * A.t.dVq[k][a] * tv[0][(c * n + b) * n + k];
+            acc -= sum;
+        }
+        {
+            const double gd = 2.0 / hh[1];
+            double sum = 0.0;
+#pragma unroll
+            for (int k = 0; k < n; ++k) sum += gd * A.t.dVq[k][b] * tv[1][(c * n + k) * n + a];
+            acc -= sum;
+        }
+        {
+            const double gd = 2.0 / hh[2];
+            double sum = 0.0;
+#pragma unroll
+            for (int k = 0; k < n; ++k) sum += gd * A.t.dVq[k][c] * tv[2][(k * n + b) * n + a];
+            acc -= sum;
+        }
+        for (int d = 0; d < 3; ++d) {
+            const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+            const int s = co[t1], t = co[t2];
+            for (int hi = 0; hi < 2; ++hi) {
+                const bool high = hi == 1;
+                const int layer = high ? n - 1 : 0;
+                if (co[d] != layer) continue;
+                const int kn = neighbour(e3[d], A.n[d], A.bc[d], high);
+                if (kn < 0 && !A.vb[d]) continue;
+                double f;
+                if (kn >= 0) {
+                    int en[3] = {ex, ey, ez};
+                    en[d] = kn;
+                    const size_t nb0 = elem_base(A, en[0], en[1], en[2], n3);
+                    f = 0.5 * (A.v[d][vb0 + r] + A.v[d][nb0 + face_node<n>(d, high ? 0 : n - 1, s, t)]);
+                } else {
+                    f = A.vb[d][vb0 + r];
+                }
+                const double omega0 = A.h[t1][e3[t1]] * A.h[t2][e3[t2]] * 0.25, sgn = high ? 1.0 : -1.0;
+                acc += sgn * omega0 * A.t.w[s] * A.t.w[t] * f;
+            }
+        }
+        A.out[vb0 + r] = A.scale * acc;
+    }
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) k_gradient_eq(ProjArgs A)
+{
+    constexpr int n = P + 1, n3 = n * n * n;
+    __shared__ double q[n3];
+    const int el = blockIdx.x;
+    const int ex = el % A.n[0], ey = (el / A.n[0]) % A.n[1], ez = el / (A.n[0] * A.n[1]);
+    const int e3[3] = {ex, ey, ez};
+    const double hh[3] = {A.h[0][ex], A.h[1][ey], A.h[2][ez]};
+    const size_t base = elem_base(A, ex, ey, ez, n3);
+    for (int r = threadIdx.x; r < n3; r += blockDim.x) q[r] = A.psi[base + r];
+    __syncthreads();
+    for (int r = threadIdx.x; r < n3; r += blockDim.x) {
+        const int a = r % n, b = (r / n) % n, c = r / (n * n);
+        const int co[3] = {a, b, c};
+        for (int d = 0; d < 3; ++d) {
+            const double gd = 2.0 / hh[d];
+            double g = 0.0;
+            if (d == 0) {
+#pragma unroll
+                for (int k = 0; k < n; ++k) g += gd * A.t.dVq[a][k] * q[(c * n + b) * n + k];
+            } else if (d == 1) {
+#pragma unroll
+                for (int k = 0; k < n; ++k) g += gd * A.t.dVq[b][k] * q[(c * n + k) * n + a];
+            } else {
+#pragma unroll
+                for (int k = 0; k < n; ++k) g += gd * A.t.dVq[c][k] * q[(k * n + b) * n + a];
+            }
+            for (int hi = 0; hi < 2; ++hi) {
+                const bool high = hi == 1;
+                const int layer = high ? n - 1 : 0;
+                if (co[d] != layer) continue;
+                const int kn = neighbour(e3[d], A.n[d], A.bc[d], high);
+                if (kn < 0) continue;
+                int en[3] = {ex, ey, ez};
+                en[d] = kn;
+                int cn[3] = {a, b, c};
+                cn[d] = high ? 0 : n - 1;
+                const double oth = A.psi[elem_base(A, en[0], en[1], en[2], n3) + (cn[2] * n + cn[1]) * n + cn[0]];
+                const double own = q[r];
+                const double jump = high ? own - oth : oth - own;
+                const double f = 1.0 / (A.t.w[layer] * hh[d]);
+                g -= f * jump;
+            }
+            const double gv = A.fac ? A.scale * g * A.fac[base + r] : A.scale * g;
+            A.g[d][base + r] = A.update ? A.v[d][base + r] + gv : gv;
+        }
+    }
+}
+
 ProjTables make_tables(int P, int Q)
 {
     ProjTables t{};
@@ -376,8 +501,11 @@ int launch_divergence(const MeshDev &mv, const MeshDev &mp, const double *const 
     a.out = out;
     a.scale = scale;
     return with_pair(mv.P, mp.P, [&](auto PC, auto QC) {
-        hipLaunchKernelGGL((k_divergence<decltype(PC)::value, decltype(QC)::value>), dim3((unsigned)mv.nel),
-                           dim3(256), 0, s, a);
+        constexpr int Pv = decltype(PC)::value, Qv = decltype(QC)::value;
+        if constexpr (Pv == Qv)
+            hipLaunchKernelGGL((k_divergence_eq<Pv>), dim3((unsigned)mv.nel), dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_divergence<Pv, Qv>), dim3((unsigned)mv.nel), dim3(256), 0, s, a);
     });
 }
 
@@ -395,8 +523,11 @@ int launch_gradient(const MeshDev &mv, const MeshDev &mp, const double *psi, con
         a.g[d] = g[d];
     }
     return with_pair(mv.P, mp.P, [&](auto PC, auto QC) {
-        hipLaunchKernelGGL((k_gradient<decltype(PC)::value, decltype(QC)::value>), dim3((unsigned)mv.nel),
-                           dim3(256), 0, s, a);
+        constexpr int Pv = decltype(PC)::value, Qv = decltype(QC)::value;
+        if constexpr (Pv == Qv)
+            hipLaunchKernelGGL((k_gradient_eq<Pv>), dim3((unsigned)mv.nel), dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_gradient<Pv, Qv>), dim3((unsigned)mv.nel), dim3(256), 0, s, a);
     });
 }
 

@@ -400,7 +400,7 @@ int solve_fdm(dg_mesh *m, Workspace &w, const int bc[3], double lambda, const do
     double nu_ref = nu_c;
     if (nu) {
         double lo = 0.0, hi = 0.0;
-        if ((rc = field_range(nu, (size_t)md.ndof, w.partial, lo, hi, s))) return rc;
+        if ((rc = field_range(nu, (size_t)md.ndof, w.partial, partial_doubles(md), lo, hi, s))) return rc;
         if (!(lo > 0.0) || !std::isfinite(hi)) {
             set_error("the fast-diagonalisation preconditioner needs a positive, finite nu field");
             return lo != lo || hi != hi ? DG_ERR_NONFINITE : DG_ERR_ARG;
