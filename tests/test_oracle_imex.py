@@ -247,3 +247,36 @@ def test_step_temporal_order_shear_flow(name):
     err = _shear_errors(name, [1 / 16, 1 / 32, 1 / 64, 1 / 128])
     eoc = [np.log2(err[i] / err[i + 1]) for i in range(2)]
     assert all(p - 0.2 <= e <= p + 0.4 for e in eoc), (err, eoc)
+
+
+def test_vvp_forcing_matches_finite_differences():
+    # the manufactured forcing of the VVP case (problem data in synth) against
+    # central differences of the exact velocity and pressure: d_t v +
+    # div(v v) - div(nu(v)(grad v + grad v^T)) + grad p at a few points
+    rng = np.random.default_rng(4)
+    nu0, nu1, vmax = 0.01, 0.01, synth.VVP_VMAX
+    e = 1e-4
+
+    def vel(p, t):
+        return np.array(synth.vvp_velocity(p[0], p[1], p[2], t))
+
+    def grad_v(p, t):  # G[i][k] = d_k v_i
+        return np.array([(vel(p + e * np.eye(3)[k], t) - vel(p - e * np.eye(3)[k], t)) / (2 * e)
+                         for k in range(3)]).T
+
+    def tau(p, t):
+        v = vel(p, t)
+        G = grad_v(p, t)
+        return (nu0 + nu1 * v.dot(v) / vmax ** 2) * (G + G.T)
+
+    for _ in range(4):
+        x, t = rng.uniform(-0.5, 0.5, 3), rng.uniform(0, 1)
+        f = np.array(synth.vvp_forcing(x[0], x[1], x[2], t, nu0, nu1))
+        fd = (vel(x, t + e) - vel(x, t - e)) / (2 * e)
+        for k in range(3):
+            dk = e * np.eye(3)[k]
+            vp, vm = vel(x + dk, t), vel(x - dk, t)
+            fd = fd + (vp[k] * vp - vm[k] * vm) / (2 * e)
+            fd = fd - (tau(x + dk, t)[:, k] - tau(x - dk, t)[:, k]) / (2 * e)
+            fd[k] += (synth.vvp_pressure(*(x + dk), t) - synth.vvp_pressure(*(x - dk), t)) / (2 * e)
+        assert np.max(np.abs(f - fd)) <= 1e-5 * (1 + np.max(np.abs(f)))
