@@ -207,10 +207,72 @@ def cpu_baseline(spec, lam, budget_s=12.0):
         if time.perf_counter() - t0 >= budget_s:
             break
     dt = time.perf_counter() - t0
-    return dict(value=op.N * reps / dt / 1e9, unit="GDOF/s", cores=naive.num_threads(),
-                kind="oracle",
-                sample="%d full applies of the 32^3 P=7 stretched mesh (%d nodes), %.1f s"
-                       % (reps, op.N, dt))
+    out = dict(value=op.N * reps / dt / 1e9, unit="GDOF/s", cores=naive.num_threads(),
+               kind="oracle",
+               sample="%d full applies of the 32^3 P=7 stretched mesh (%d nodes), %.1f s"
+                      % (reps, op.N, dt))
+    out["solves"] = cpu_solves()
+    return out
+
+
+def cpu_solves(sample_iters=5):
+    """The oracle's Jacobi-PCG (all host cores) on the solve configurations:
+    whole solves where they take seconds (4^3 P=4; the 4^3 P=7 mixed-case
+    systems in FP64; the 24^3 P=5 channel velocity system with nodal nu),
+    a fixed sample of iterations on the 32^3 P=7 systems (Helmholtz and
+    Poisson), reported as a rate and the implied time of the GPU's
+    iteration count."""
+    from oracle import dense, naive, pcg
+    import synth
+    res = {}
+
+    def run(name, spec, lam, nu, f, fixed=0, singular=False):
+        op = naive.Operator(spec, lam, nu)
+        M = dense.mass_diag(spec)
+        d = op.diag()
+        t0 = time.perf_counter()
+        _, info = pcg.pcg(op.apply, M * f, d, M, tol=1e-10, fixed_iters=fixed, singular=singular)
+        t = time.perf_counter() - t0
+        res[name] = dict(nodes=op.N, iters=info["iters"], seconds=t, seconds_per_iter=t / max(1, info["iters"]),
+                         whole_solve=fixed == 0)
+
+    s1 = synth.mesh_spec("small_periodic")
+    run("small_periodic_4x4x4_P4", s1, 1.0, 1.0, synth.uniform_field(s1["nx"] ** 3 * 125, 0))
+    s3 = synth.mesh_spec("mixed_small")
+    for lam in (1e2, 1e4, 1e6):
+        run("mixed_small_P7_lambda_%g_fp64" % lam, s3, lam, 1.0,
+            synth.uniform_field(s3["nx"] ** 3 * 512, synth.SEEDS["mixed"]))
+    s4 = synth.mesh_spec("batched_channel")
+    N4 = s4["nx"] ** 3 * 216
+    # the channel viscosity nu(x) = 1e-3 (1 + 0.5 sin 2 pi x cos 2 pi y) at the
+    # nodes (element-major layout; GLL nodes from the oracle)
+    from oracle import gll
+    xi = gll.nodes(s4["P"])
+    n4 = s4["P"] + 1
+
+    def c1(v):
+        v = np.asarray(v)
+        return v[:-1, None] + np.diff(v)[:, None] * (1.0 + xi[None, :]) / 2.0
+
+    shp = (s4["nz"], s4["ny"], s4["nx"], n4, n4, n4)
+    X = np.broadcast_to(c1(s4["xv"])[None, None, :, None, None, :], shp).reshape(-1)
+    Y = np.broadcast_to(c1(s4["yv"])[None, :, None, None, :, None], shp).reshape(-1)
+    nu4 = 1e-3 * (1.0 + 0.5 * np.sin(2 * np.pi * X) * np.cos(2 * np.pi * Y))
+    run("channel_24_P5_velocity_nodal_nu", s4, synth.batched_lambda(), nu4,
+        synth.uniform_field(N4, synth.SEEDS["batched_velocity"][0]))
+    s2 = synth.mesh_spec("stretched_large")
+    N2 = s2["nx"] ** 3 * 512
+    run("stretched_32_P7_helmholtz_%d_iters" % sample_iters, s2, synth.large_helmholtz_lambda(), 1.0,
+        synth.uniform_field(N2, synth.SEEDS["large_helmholtz"]), fixed=sample_iters)
+    res["stretched_32_P7_helmholtz_%d_iters" % sample_iters]["implied_36_iter_solve_s"] = \
+        36 * res["stretched_32_P7_helmholtz_%d_iters" % sample_iters]["seconds_per_iter"]
+    ps = dict(s2)
+    ps["bc"] = (0, 0, 2)
+    run("stretched_32_P7_poisson_%d_iters" % sample_iters, ps, 0.0, 1.0,
+        synth.uniform_field(N2, synth.SEEDS["large_poisson"]), fixed=sample_iters, singular=True)
+    res["stretched_32_P7_poisson_%d_iters" % sample_iters]["implied_2738_iter_solve_s"] = \
+        2738 * res["stretched_32_P7_poisson_%d_iters" % sample_iters]["seconds_per_iter"]
+    return res
 
 
 def bench_mixed_small(dg, torch, reps=20):
@@ -600,6 +662,9 @@ def bench_serving(dg, nreq, slots, precision, budget=96 << 30, precond=0):
               precond="fdm" if precond else "jacobi",
               solves_per_s=nreq / st["makespan"], failed=len(bad), failures=bad[:20],
               offered_per_s=nreq / max(stream[-1]["t_arrival"], 1e-9), mean_ndof=ndof / nreq)
+    # served rate over offered rate: below 1 the queue grew for the whole
+    # replay and solves_per_s is the capacity; near 1 the server kept up
+    st["served_over_offered"] = st["solves_per_s"] / st["offered_per_s"]
     return st
 
 
