@@ -4,8 +4,10 @@ Argument marshalling only: every step of the apply and the solves runs in the
 HIP library.  PyTorch supplies device memory and streams.  If the library has
 not been built the import fails loudly; there is no CPU fallback.
 """
+import atexit
 import ctypes
 import os
+import weakref
 
 import numpy as np
 
@@ -207,10 +209,27 @@ def default_opts(**kw):
     return o
 
 
+# Meshes and servers still alive when the interpreter exits are destroyed by
+# an atexit hook, while the HIP runtime (and any profiler wrapped around it)
+# is certainly still up, rather than by __del__ during interpreter teardown,
+# whose order relative to the runtime's own exit handlers is not defined.
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _destroy_live():
+    for obj in list(_live):
+        try:
+            obj.destroy()
+        except Exception:
+            pass
+
+
 class Mesh:
     """Owner of a dg_mesh handle."""
 
     def __init__(self, handle, nx, ny, nz, P, bc):
+        _live.add(self)
         self.handle = handle
         self.nx, self.ny, self.nz, self.P, self.bc = nx, ny, nz, P, tuple(bc)
         self.ndof = int(lib().dg_mesh_ndof(handle))
@@ -465,6 +484,7 @@ class Server:
     def __init__(self, hbm_budget_bytes, max_slots):
         h = ctypes.c_void_p()
         _check(lib().dg_server_create(int(hbm_budget_bytes), int(max_slots), ctypes.byref(h)))
+        _live.add(self)
         self.handle = h
         self._keep = {}
 
