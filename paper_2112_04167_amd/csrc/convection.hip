@@ -16,11 +16,13 @@
 //
 // One work-group of 256 threads per element.  The element's velocity is
 // interpolated to the Q^3 Gauss points (three 1D passes per component, in
-// LDS), the flux products are formed on the fly in the first of the three
-// transposed passes back to the nodes, and the six faces follow, each
-// element computing the fluxes of its own faces (no atomics: the neighbour
-// computes the same flux with the opposite sign).  LDS: 3 Q^3 + n^3 + n^2 Q
-// + n Q^2 + 3 n^3 doubles, 97 KB at P = 8.
+// LDS).  Per output component i the nine (i, k) flux passes back to the
+// nodes are factored into three: the z pass forms the three products
+// v_i v_k on the fly, the y pass combines the k = 1, 2 branches that share
+// B_x, the x pass the remaining two.  Then both faces of each axis at once,
+// each element computing the fluxes of its own faces (no atomics: the
+// neighbour computes the same flux with the opposite sign).  LDS at P = 7:
+// 79 KB (two work-groups per CU); at P = 8: 124 KB.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -61,9 +63,17 @@ __host__ __device__ constexpr int conv_q(int P) { return 3 * P / 2 + 1; }
 template <int P>
 struct ConvLds {
     static constexpr int n = P + 1, Q = conv_q(P);
-    static constexpr int vol = 3 * Q * Q * Q;
-    static constexpr int face = 6 * n * n + 6 * n * Q + 6 * Q * Q + 3 * Q * Q + 3 * Q * n;
-    static constexpr int big = vol > face ? vol : face;
+    // region A: the velocity at the Gauss points U[3][Q^3], later the face
+    // points' traces tg[12][Q^2] and weighted fluxes hw[6][Q^2]
+    static constexpr int vol = 3 * Q * Q * Q, fa = 18 * Q * Q;
+    static constexpr int A = vol > fa ? vol : fa;
+    // region S: interpolation scratch (n^3 + n^2 Q + n Q^2), then the
+    // transposed passes Z[3][n Q^2], Yb[2][n^2 Q], then the face-node
+    // buffers tr[12][n^2], tq[12][n Q], hq[6][Q n]
+    static constexpr int s_in = n * n * n + n * n * Q + n * Q * Q;
+    static constexpr int s_bk = 3 * n * Q * Q + 2 * n * n * Q;
+    static constexpr int s_fc = 12 * n * n + 12 * n * Q + 6 * Q * n;
+    static constexpr int S = s_in > s_bk ? (s_in > s_fc ? s_in : s_fc) : (s_bk > s_fc ? s_bk : s_fc);
 };
 
 __device__ __forceinline__ int nb_index(int k, int nk, int bc, bool high)
@@ -89,10 +99,9 @@ __global__ void __launch_bounds__(256) k_convection(ConvArgs A)
 {
     using L = ConvLds<P>;
     constexpr int n = L::n, Q = L::Q, n3 = n * n * n, Q2 = Q * Q, Q3 = Q * Q * Q;
-    __shared__ double big[L::big];  // U[3][Q^3] for the volume, the face buffers after it
-    __shared__ double X[n3];
-    __shared__ double Y1[n * n * Q];
-    __shared__ double Y2[n * Q * Q];
+    constexpr int nQ2 = n * Q2, n2Q = n * n * Q;
+    __shared__ double bufA[L::A];
+    __shared__ double bufS[L::S];
     __shared__ double acc[3][n3];
     const int tid = threadIdx.x, nth = blockDim.x;
     const int el = blockIdx.x;
@@ -101,153 +110,171 @@ __global__ void __launch_bounds__(256) k_convection(ConvArgs A)
     const double hh[3] = {A.h[0][ex], A.h[1][ey], A.h[2][ez]};
     const double J = hh[0] * hh[1] * hh[2] * 0.125;
     const size_t base = (size_t)el * n3;
-    double *U = big;
+    double *U = bufA;
 
     // ---- velocity at the Gauss points: U_k = (B (x) B (x) B) v_k
-    for (int k = 0; k < 3; ++k) {
-        for (int i = tid; i < n3; i += nth) X[i] = A.v[k][base + i];
-        __syncthreads();
-        for (int i = tid; i < n * n * Q; i += nth) {  // x: Y1[c][b][qx]
-            const int qx = i % Q, cb = i / Q;
-            double s = 0.0;
+    {
+        double *X = bufS, *Y1 = bufS + n3, *Y2 = bufS + n3 + n2Q;
+        for (int k = 0; k < 3; ++k) {
+            for (int i = tid; i < n3; i += nth) X[i] = A.v[k][base + i];
+            __syncthreads();
+            for (int i = tid; i < n2Q; i += nth) {  // x: Y1[c][b][qx]
+                const int qx = i % Q, cb = i / Q;
+                double sum = 0.0;
 #pragma unroll
-            for (int a = 0; a < n; ++a) s = fma(A.t.B[qx][a], X[cb * n + a], s);
-            Y1[i] = s;
-        }
-        __syncthreads();
-        for (int i = tid; i < n * Q2; i += nth) {  // y: Y2[c][qy][qx]
-            const int qx = i % Q, qy = (i / Q) % Q, c = i / Q2;
-            double s = 0.0;
+                for (int a = 0; a < n; ++a) sum = fma(A.t.B[qx][a], X[cb * n + a], sum);
+                Y1[i] = sum;
+            }
+            __syncthreads();
+            for (int i = tid; i < nQ2; i += nth) {  // y: Y2[c][qy][qx]
+                const int qx = i % Q, qy = (i / Q) % Q, c = i / Q2;
+                double sum = 0.0;
 #pragma unroll
-            for (int b = 0; b < n; ++b) s = fma(A.t.B[qy][b], Y1[(c * n + b) * Q + qx], s);
-            Y2[i] = s;
-        }
-        __syncthreads();
-        for (int i = tid; i < Q3; i += nth) {  // z: U_k[qz][qy][qx]
-            const int qxy = i % Q2, qz = i / Q2;
-            double s = 0.0;
+                for (int b = 0; b < n; ++b) sum = fma(A.t.B[qy][b], Y1[(c * n + b) * Q + qx], sum);
+                Y2[i] = sum;
+            }
+            __syncthreads();
+            for (int i = tid; i < Q3; i += nth) {  // z: U_k[qz][qy][qx]
+                const int qxy = i % Q2, qz = i / Q2;
+                double sum = 0.0;
 #pragma unroll
-            for (int c = 0; c < n; ++c) s = fma(A.t.B[qz][c], Y2[c * Q2 + qxy], s);
-            U[k * Q3 + i] = s;
+                for (int c = 0; c < n; ++c) sum = fma(A.t.B[qz][c], Y2[c * Q2 + qxy], sum);
+                U[k * Q3 + i] = sum;
+            }
+            __syncthreads();
         }
-        // X is rewritten only after the next barrier below
-        __syncthreads();
     }
     for (int i = tid; i < 3 * n3; i += nth) (&acc[0][0])[i] = 0.0;
 
-    // ---- volume: acc_i += sum_k (T_z (x) T_y (x) T_x)^T (W J v_i v_k),
-    //      T = (2/h_k) dB along direction k, B along the others
+    // ---- volume: acc_i = sum_k T_k^T (W J v_i v_k) with T_k = (2/h_k) dB along
+    //      k and B along the others, factored as
+    //      B_x^T [B_y^T dB_z^T F_i2 + dB_y^T B_z^T F_i1] + dB_x^T B_y^T B_z^T F_i0
+    double *Z = bufS, *Yb = bufS + 3 * nQ2;
+    const double g0 = 2.0 / hh[0], g1 = 2.0 / hh[1], g2 = 2.0 / hh[2];
     for (int i = 0; i < 3; ++i) {
-        for (int k = 0; k < 3; ++k) {
-            const double gk = 2.0 / hh[k];
-            __syncthreads();
-            for (int r = tid; r < n * Q2; r += nth) {  // z back: Y2[c][qy][qx]
-                const int qx = r % Q, qy = (r / Q) % Q, c = r / Q2;
-                const int qxy = qy * Q + qx;
-                double s = 0.0;
+        __syncthreads();
+        for (int r = tid; r < nQ2; r += nth) {  // z: Z_k[c][qy][qx]
+            const int qx = r % Q, qy = (r / Q) % Q, c = r / Q2;
+            const int qxy = qy * Q + qx;
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
 #pragma unroll
-                for (int qz = 0; qz < Q; ++qz) {
-                    const double tz = (k == 2 ? A.t.dB[qz][c] : A.t.B[qz][c]) * A.t.wg[qz];
-                    s = fma(tz, U[i * Q3 + qz * Q2 + qxy] * U[k * Q3 + qz * Q2 + qxy], s);
-                }
-                Y2[r] = s * A.t.wg[qx] * A.t.wg[qy] * J * gk;
+            for (int qz = 0; qz < Q; ++qz) {
+                const int q = qz * Q2 + qxy;
+                const double ui = U[i * Q3 + q] * A.t.wg[qz];
+                s0 = fma(A.t.B[qz][c], ui * U[q], s0);
+                s1 = fma(A.t.B[qz][c], ui * U[Q3 + q], s1);
+                s2 = fma(A.t.dB[qz][c], ui * U[2 * Q3 + q], s2);
             }
-            __syncthreads();
-            for (int r = tid; r < n * n * Q; r += nth) {  // y back: Y1[c][b][qx]
-                const int qx = r % Q, b = (r / Q) % n, c = r / (n * Q);
-                double s = 0.0;
+            const double f = A.t.wg[qx] * A.t.wg[qy] * J;
+            Z[r] = s0 * f * g0;
+            Z[nQ2 + r] = s1 * f * g1;
+            Z[2 * nQ2 + r] = s2 * f * g2;
+        }
+        __syncthreads();
+        for (int r = tid; r < n2Q; r += nth) {  // y: Yb_x = B_y^T Z_0, Yb_s = dB_y^T Z_1 + B_y^T Z_2
+            const int qx = r % Q, b = (r / Q) % n, c = r / (n * Q);
+            double sx = 0.0, ss = 0.0;
 #pragma unroll
-                for (int qy = 0; qy < Q; ++qy)
-                    s = fma(k == 1 ? A.t.dB[qy][b] : A.t.B[qy][b], Y2[(c * Q + qy) * Q + qx], s);
-                Y1[r] = s;
+            for (int qy = 0; qy < Q; ++qy) {
+                const int zi = (c * Q + qy) * Q + qx;
+                sx = fma(A.t.B[qy][b], Z[zi], sx);
+                ss = fma(A.t.dB[qy][b], Z[nQ2 + zi], ss);
+                ss = fma(A.t.B[qy][b], Z[2 * nQ2 + zi], ss);
             }
-            __syncthreads();
-            for (int r = tid; r < n3; r += nth) {  // x back: acc_i[c][b][a]
-                const int a = r % n, cb = r / n;
-                double s = 0.0;
+            Yb[r] = sx;
+            Yb[n2Q + r] = ss;
+        }
+        __syncthreads();
+        for (int r = tid; r < n3; r += nth) {  // x: acc_i[c][b][a]
+            const int a = r % n, cb = r / n;
+            double sum = 0.0;
 #pragma unroll
-                for (int qx = 0; qx < Q; ++qx)
-                    s = fma(k == 0 ? A.t.dB[qx][a] : A.t.B[qx][a], Y1[cb * Q + qx], s);
-                acc[i][r] += s;
+            for (int qx = 0; qx < Q; ++qx) {
+                sum = fma(A.t.dB[qx][a], Yb[cb * Q + qx], sum);
+                sum = fma(A.t.B[qx][a], Yb[n2Q + cb * Q + qx], sum);
             }
+            acc[i][r] += sum;
         }
     }
 
-    // ---- faces: acc_i -= int_F H_i phi over the element's six faces
-    double *tr = big;                 // [6][n*n]: own v_0..2, exterior v_0..2, [t][s]
-    double *tq = tr + 6 * n * n;      // [6][n*Q]: [t][qs]
-    double *tg = tq + 6 * n * Q;      // [6][Q*Q]: [qt][qs]
-    double *hw = tg + 6 * Q2;         // [3][Q*Q]
-    double *hq = hw + 3 * Q2;         // [3][Q*n]: [qt][s]
+    // ---- faces: acc_i -= int_F H_i phi, both faces of an axis at once
+    double *tr = bufS;                 // [12][n*n]: side*6 + (own v_0..2, exterior v_0..2), [t][s]
+    double *tq = tr + 12 * n * n;      // [12][n*Q]: [t][qs]
+    double *hq = tq + 12 * n * Q;      // [6][Q*n]: side*3 + i, [qt][s]
+    double *tg = bufA;                 // [12][Q*Q]: [qt][qs]
+    double *hw = bufA + 12 * Q2;       // [6][Q*Q]
     for (int d = 0; d < 3; ++d) {
         const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
         const double om0 = hh[t1] * hh[t2] * 0.25;
-        for (int hi = 0; hi < 2; ++hi) {
-            const bool high = hi == 1;
-            const int kn = nb_index(e3[d], A.n[d], A.bc[d], high);
-            int en[3] = {ex, ey, ez};
-            if (kn >= 0) en[d] = kn;
-            const size_t nbase = ((size_t)(en[2] * A.n[1] + en[1]) * A.n[0] + en[0]) * n3;
-            const int layer = high ? n - 1 : 0, nlayer = high ? 0 : n - 1;
-            const double sgn = high ? 1.0 : -1.0;
-            __syncthreads();  // the previous face's (or the volume's) readers are done
-            for (int r = tid; r < 6 * n * n; r += nth) {
-                const int comp = r / (n * n), st = r % (n * n), s = st % n, t = st / n;
-                double val;
-                if (comp < 3) {
-                    val = A.v[comp][base + layer_node<n>(d, layer, s, t)];
-                } else if (kn >= 0) {
-                    val = A.v[comp - 3][nbase + layer_node<n>(d, nlayer, s, t)];
+        __syncthreads();  // the previous phase's readers of these buffers are done
+        for (int r = tid; r < 12 * n * n; r += nth) {
+            const int slot = r / (n * n), st = r % (n * n), s = st % n, t = st / n;
+            const bool high = slot >= 6;
+            const int comp = slot % 6;
+            const int layer = high ? n - 1 : 0;
+            double val;
+            if (comp < 3) {
+                val = A.v[comp][base + layer_node<n>(d, layer, s, t)];
+            } else {
+                const int kn = nb_index(e3[d], A.n[d], A.bc[d], high);
+                if (kn >= 0) {
+                    int en[3] = {ex, ey, ez};
+                    en[d] = kn;
+                    const size_t nbase = ((size_t)(en[2] * A.n[1] + en[1]) * A.n[0] + en[0]) * n3;
+                    val = A.v[comp - 3][nbase + layer_node<n>(d, high ? 0 : n - 1, s, t)];
                 } else {
                     const double *wb = A.vb[comp - 3];
                     val = wb ? wb[base + layer_node<n>(d, layer, s, t)] : 0.0;
                 }
-                tr[r] = val;
             }
-            __syncthreads();
-            for (int r = tid; r < 6 * n * Q; r += nth) {  // along s
-                const int comp = r / (n * Q), q = r % Q, t = (r / Q) % n;
-                double sum = 0.0;
+            tr[r] = val;
+        }
+        __syncthreads();
+        for (int r = tid; r < 12 * n * Q; r += nth) {  // along s
+            const int slot = r / (n * Q), q = r % Q, t = (r / Q) % n;
+            double sum = 0.0;
 #pragma unroll
-                for (int s = 0; s < n; ++s) sum = fma(A.t.B[q][s], tr[comp * n * n + t * n + s], sum);
-                tq[r] = sum;
-            }
-            __syncthreads();
-            for (int r = tid; r < 6 * Q2; r += nth) {  // along t
-                const int comp = r / Q2, qs = r % Q, qt = (r / Q) % Q;
-                double sum = 0.0;
+            for (int s = 0; s < n; ++s) sum = fma(A.t.B[q][s], tr[slot * n * n + t * n + s], sum);
+            tq[r] = sum;
+        }
+        __syncthreads();
+        for (int r = tid; r < 12 * Q2; r += nth) {  // along t
+            const int slot = r / Q2, qs = r % Q, qt = (r / Q) % Q;
+            double sum = 0.0;
 #pragma unroll
-                for (int t = 0; t < n; ++t) sum = fma(A.t.B[qt][t], tq[comp * n * Q + t * Q + qs], sum);
-                tg[r] = sum;
-            }
-            __syncthreads();
-            for (int q = tid; q < Q2; q += nth) {
-                const int qs = q % Q, qt = q / Q;
-                const double vm = sgn * tg[d * Q2 + q], vp = sgn * tg[(3 + d) * Q2 + q];
-                const double alpha = 2.0 * fmax(fabs(vm), fabs(vp));
-                const double om = om0 * A.t.wg[qs] * A.t.wg[qt];
+            for (int t = 0; t < n; ++t) sum = fma(A.t.B[qt][t], tq[slot * n * Q + t * Q + qs], sum);
+            tg[r] = sum;
+        }
+        __syncthreads();
+        for (int r = tid; r < 2 * Q2; r += nth) {
+            const int side = r / Q2, q = r % Q2, qs = q % Q, qt = q / Q;
+            const double sgn = side ? 1.0 : -1.0;
+            const double *own = tg + side * 6 * Q2, *ext = own + 3 * Q2;
+            const double vm = sgn * own[d * Q2 + q], vp = sgn * ext[d * Q2 + q];
+            const double alpha = 2.0 * fmax(fabs(vm), fabs(vp));
+            const double om = om0 * A.t.wg[qs] * A.t.wg[qt];
 #pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    const double um = tg[i * Q2 + q], up = tg[(3 + i) * Q2 + q];
-                    hw[i * Q2 + q] = -om * (0.5 * (vm * um + vp * up) + 0.5 * alpha * (um - up));
-                }
+            for (int i = 0; i < 3; ++i) {
+                const double um = own[i * Q2 + q], up = ext[i * Q2 + q];
+                hw[(side * 3 + i) * Q2 + q] = -om * (0.5 * (vm * um + vp * up) + 0.5 * alpha * (um - up));
             }
-            __syncthreads();
-            for (int r = tid; r < 3 * Q * n; r += nth) {  // back along s: hq[i][qt][s]
-                const int i = r / (Q * n), s = r % n, qt = (r / n) % Q;
-                double sum = 0.0;
+        }
+        __syncthreads();
+        for (int r = tid; r < 6 * Q * n; r += nth) {  // back along s: hq[side*3+i][qt][s]
+            const int slot = r / (Q * n), s = r % n, qt = (r / n) % Q;
+            double sum = 0.0;
 #pragma unroll
-                for (int qs = 0; qs < Q; ++qs) sum = fma(A.t.B[qs][s], hw[i * Q2 + qt * Q + qs], sum);
-                hq[r] = sum;
-            }
-            __syncthreads();
-            for (int r = tid; r < 3 * n * n; r += nth) {  // back along t, onto the face layer
-                const int i = r / (n * n), s = r % n, t = (r / n) % n;
-                double sum = 0.0;
+            for (int qs = 0; qs < Q; ++qs) sum = fma(A.t.B[qs][s], hw[slot * Q2 + qt * Q + qs], sum);
+            hq[r] = sum;
+        }
+        __syncthreads();
+        for (int r = tid; r < 6 * n * n; r += nth) {  // back along t onto the two face layers
+            const int slot = r / (n * n), s = r % n, t = (r / n) % n;
+            const int side = slot / 3, i = slot % 3;
+            double sum = 0.0;
 #pragma unroll
-                for (int qt = 0; qt < Q; ++qt) sum = fma(A.t.B[qt][t], hq[i * Q * n + qt * n + s], sum);
-                acc[i][layer_node<n>(d, layer, s, t)] += sum;
-            }
+            for (int qt = 0; qt < Q; ++qt) sum = fma(A.t.B[qt][t], hq[slot * Q * n + qt * n + s], sum);
+            acc[i][layer_node<n>(d, side ? n - 1 : 0, s, t)] += sum;
         }
     }
     __syncthreads();
