@@ -40,6 +40,25 @@ def trace_stats(db, pattern):
     return out, sel
 
 
+def trace_since(db, since):
+    """Per-kernel totals over the dispatches from the first one whose name
+    contains `since` onward: [(name, calls, total_ns, avg_ns, pct)], and the
+    wall span of those dispatches in ns."""
+    c = sqlite3.connect(db)
+    rows = c.execute("select name, start, end, duration from kernels order by start").fetchall()
+    t0 = next(r[1] for r in rows if since in r[0])
+    sel = [r for r in rows if r[1] >= t0]
+    agg = {}
+    for name, st, en, d in sel:
+        a = agg.setdefault(name, [0, 0.0])
+        a[0] += 1
+        a[1] += d
+    tot = sum(a[1] for a in agg.values())
+    out = [(k, a[0], a[1], a[1] / a[0], 100.0 * a[1] / tot) for k, a in agg.items()]
+    out.sort(key=lambda r: -r[2])
+    return out, sel[-1][2] - sel[0][1]
+
+
 def counter(db, name, pattern, grid=None):
     c = sqlite3.connect(db)
     rows = c.execute("select kernel_name, grid_size, value from counters_collection "
@@ -60,8 +79,31 @@ def main():
     ap.add_argument("--algo-bytes", type=float, default=0.0)
     ap.add_argument("--cmd", action="append", default=[])
     ap.add_argument("--title", default="rocprofv3 summary")
+    ap.add_argument("--since", help="trace-only: dispatches from the first kernel containing this on")
+    ap.add_argument("--per", type=float, default=0.0, help="trace-only with --since: also per-unit totals")
     a = ap.parse_args()
 
+    if a.since:
+        rows, span = trace_since(a.trace, a.since)
+        tot = sum(r[2] for r in rows)
+        print("# %s" % a.title)
+        print()
+        print("Commands (from the repository root):")
+        print()
+        for c in a.cmd:
+            print("    " + c)
+        print()
+        print("## Kernel trace from the first `%s` dispatch on (rocprofv3 --kernel-trace --stats)" % a.since)
+        print()
+        print("kernel time %.3f ms over a wall span of %.3f ms" % (tot / 1e6, span / 1e6), end="")
+        print(" (per unit, %g units: %.3f ms)" % (a.per, tot / 1e6 / a.per) if a.per else "")
+        print()
+        print("| kernel | calls | total us | average us | % |")
+        print("|---|---|---|---|---|")
+        for name, calls, t, avg, pct in rows[:20]:
+            short = name if len(name) < 90 else name[:87] + "..."
+            print("| `%s` | %d | %.1f | %.2f | %.1f |" % (short, calls, t / 1e3, avg / 1e3, pct))
+        return
     allk, sel = trace_stats(a.trace, a.kernel)
     if not (a.fetch and a.write):
         print("# %s" % a.title)
