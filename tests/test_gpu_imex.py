@@ -229,3 +229,27 @@ def test_step_temporal_order_shear(method):
     say("shear order", method, err, eoc)
     p = imex.ORDER[method]
     assert all(e >= p - 0.3 for e in eoc), (err, eoc)
+
+
+@pytest.mark.parametrize("n,P,method,nsteps,fp", [((2, 2, 2), 5, "RK-CB3e", 2, True),
+                                                  ((1, 1, 2), 8, "RK-ARS3", 1, True),
+                                                  ((2, 1, 2), 6, "RK-CB4", 2, False)],
+                         ids=["P5_two_steps", "P8_one_step", "P6_two_steps_no_final_projection"])
+def test_steps_other_degrees_match_oracle(n, P, method, nsteps, fp):
+    # consecutive steps of the VVP case at other degrees (pressure P - 1),
+    # each against the oracle's step from the oracle's own previous state
+    spec = make_spec(n, P, (0, 0, 0), False, lo=-0.5, hi=0.5)
+    X, Y, Z = node_coords(spec)
+    t, dt, nu0, nu1 = 0.05, 1.0 / 64, 0.01, 0.01
+    f = lambda tt: synth.vvp_forcing(X, Y, Z, tt, nu0, nu1)
+    v_g = v_o = synth.vvp_velocity(X, Y, Z, t)
+    for k in range(nsteps):
+        v_g, info = _gpu_step(spec, v_g, t, dt, method, nu0, nu1, f, fp)
+        v_o, _ = imex.step(spec, v_o, t, dt, imex.TABLEAUX[method], nu0, nu1, synth.VVP_VMAX, f,
+                           final_projection=fp, solver="dense")
+        t += dt
+        assert info["status"] == 0
+        for d in range(3):
+            e = rel(v_g[d], v_o[d])
+            say("steps", P, method, k, d, e)
+            assert e <= 1e-10
