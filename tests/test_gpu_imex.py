@@ -253,3 +253,42 @@ def test_steps_other_degrees_match_oracle(n, P, method, nsteps, fp):
             e = rel(v_g[d], v_o[d])
             say("steps", P, method, k, d, e)
             assert e <= 1e-10
+
+
+def test_user_tableau_with_an_explicit_stage_matches_oracle():
+    # a caller's own 3-stage tableau whose middle stage has no implicit term
+    # (a^I_22 = 0: v_2 = g_2, no solve), through the dg_tableau struct
+    import paper_2112_04167_amd as dg
+    from fractions import Fraction as Fr
+    c = [0, Fr(1, 2), 1]
+    AI = [[0, 0, 0], [Fr(1, 2), 0, 0], [Fr(1, 4), Fr(1, 4), Fr(1, 2)]]
+    AE = [[0, 0, 0], [Fr(1, 2), 0, 0], [Fr(1, 2), Fr(1, 2), 0]]
+    bI, bE = [Fr(1, 4), Fr(1, 4), Fr(1, 2)], [Fr(1, 2), 0, Fr(1, 2)]
+    otab = dict(s=3, c=c, AI=AI, bI=bI, AE=AE, bE=bE)
+    t = dg.binding.dg_tableau()
+    t.s = 3
+    for i in range(3):
+        t.c[i], t.bI[i], t.bE[i] = float(c[i]), float(bI[i]), float(bE[i])
+        for j in range(3):
+            t.aI[i * 8 + j], t.aE[i * 8 + j] = float(AI[i][j]), float(AE[i][j])
+    torch, dev = torch_dev()
+    spec = make_spec((2, 2, 2), 4, (0, 0, 0), False, lo=-0.5, hi=0.5)
+    X, Y, Z = node_coords(spec)
+    tt, dt, nu0, nu1 = 0.0, 1.0 / 64, 0.01, 0.01
+    v = synth.vvp_velocity(X, Y, Z, tt)
+    f = lambda s_: synth.vvp_forcing(X, Y, Z, s_, nu0, nu1)
+    ps = dict(spec)
+    ps["P"] = 3
+    mv, mp = dg.mesh_from_spec(spec), dg.mesh_from_spec(ps)
+    vd = [to_dev(x) for x in v]
+    fd = [[to_dev(x) for x in f(tt + float(c[j]) * dt)] for j in range(3)]
+    info = dg.dg_imex_step(mv, mp, t, dt, nu0, nu1, synth.VVP_VMAX, vd, forcing=fd, final_projection=True,
+                           opts=dg.default_opts(tol=1e-13, precond=dg.DG_PC_FDM))
+    want, _ = imex.step(spec, v, tt, dt, otab, nu0, nu1, synth.VVP_VMAX, f, final_projection=True, solver="dense")
+    say("user tableau", info)
+    # two stage projections, three velocity solves (stage 3 only), the final projection
+    assert info["status"] == 0 and info["solves"] == 6
+    for d in range(3):
+        assert rel(vd[d].cpu().numpy(), want[d]) <= 1e-10
+    mv.destroy()
+    mp.destroy()
