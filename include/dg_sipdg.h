@@ -303,8 +303,9 @@ int dg_lincomb(int64_t n, const double *x0, int k, const double *coef, const dou
  * v+ the neighbour's trace or, on a wall, v_b (zero when not given); M the
  * GLL mass.  F_d2,i = M^-1 D(nu (d_i v_0, d_i v_1, d_i v_2)) with the
  * equal-order D and G of dg_viscous_terms (d_i v_k the i-th component of
- * G v_k; the field's own trace as its boundary data).  Walls carry v_b = 0:
- * the Helmholtz solves take homogeneous Dirichlet data. */
+ * G v_k; the field's own trace as its boundary data).  Walls carry the
+ * caller's v_b at the stage times (zero when not given), imposed in the
+ * Helmholtz solves by the Nitsche load of dg_dirichlet_load. */
 
 enum { DG_RK_TR = 0, DG_RK_CB2 = 1, DG_RK_CB3C = 2, DG_RK_CB3E = 3, DG_RK_CB4 = 4, DG_RK_ARS3 = 5 };
 #define DG_RK_MAX_STAGES 8
@@ -334,6 +335,18 @@ typedef struct {
     double seconds;      /* host wall time of the step */
 } dg_step_info;
 
+/* b += scale L(g): inhomogeneous Dirichlet data g for the SIP Helmholtz
+   problem (Alg. 3: the velocity solves take v_i = v_b on the walls).  With
+   n the outward normal of each face F of the mesh's Dirichlet axes and
+   sigma = nu (P+1)^2 / h as in the operator, L(g)_i = sum_F int_F
+   (sigma g phi_i - nu d_n(phi_i) g), by the GLL rule: solving
+   (lambda M + K_nu) x = M f + L(g) (helmholtz_solve with rhs_is_weak) gives
+   the discrete solution with x = g on those faces.  g: nodal field (only its
+   values on the Dirichlet faces are read); nu_field: nodal viscosity or
+   NULL for nu_const (> 0); b: weak vector, g != b.  Asynchronous on
+   `stream` (NULL = the mesh's stream). */
+int dg_dirichlet_load(dg_mesh *m, const double *nu_field, double nu_const, const double *g, double scale,
+                      double *b, void *stream);
 /* (ox, oy, oz) = scale F_c(v), or += scale F_c(v) when accumulate, as nodal
    fields.  vbx, vby, vbz: the wall state (only boundary-face values read),
    or NULL (zero).  Degree 3..8.  Asynchronous on `stream` (NULL = the mesh's
@@ -351,16 +364,22 @@ int dg_viscous_fd2(dg_mesh *m, const double *nu, const double *vx, const double 
    mv of degree 4..8; mp its pressure mesh of degree P-1, as for dg_project).
    forcing: NULL (no forcing) or a host array of 3 s device pointers,
    forcing[3 j + d] the d-th component of f(t + c_j dt) (each may be NULL:
-   zero).  final_projection: 1 to end with the projection with
-   d_n psi = 0 (for variable viscosity).  opts: the options of every
-   pressure and velocity solve (NULL: defaults; DG_PC_FDM recommended; the
-   velocity solves start from v''_i).  Allocates the mesh's step workspace
-   (about (9 s' + 15) N doubles, s' the stages whose terms the tableau uses)
-   at first use; synchronous.  Returns the first error of a kernel or solve,
-   else info->status. */
+   zero).  wall: NULL (no-slip walls) or a host array of 3 s device pointers,
+   wall[3 j + d] a nodal velocity field whose values on the faces of the
+   Dirichlet axes are v_b(t + c_j dt) (each may be NULL: zero); stage j uses
+   it as the Dirichlet data of its Helmholtz solves (dg_dirichlet_load),
+   in F_d1, in the projection's Neumann data and F_d3's divergence, and as
+   the exterior state of the convective flux.  final_projection: 1 to end
+   with the projection with d_n psi = 0 (for variable viscosity).  opts: the
+   options of every pressure and velocity solve (NULL: defaults; DG_PC_FDM
+   recommended; the velocity solves start from v''_i).  Allocates the mesh's
+   step workspace (about (9 s' + 15) N doubles, s' the stages whose terms the
+   tableau uses) at first use; synchronous.  Returns the first error of a
+   kernel or solve, else info->status. */
 int dg_imex_step(dg_mesh *mv, dg_mesh *mp, const dg_tableau *tab, double dt, double nu0, double nu1,
                  double vref, double *vx, double *vy, double *vz, const double *const *forcing,
-                 int final_projection, const dg_solve_opts *opts, dg_step_info *info);
+                 const double *const *wall, int final_projection, const dg_solve_opts *opts,
+                 dg_step_info *info);
 
 /* nsys systems on one mesh, solved together in one persistent, cooperative
    launch: the 3 velocity Helmholtz problems and the pressure Poisson problem

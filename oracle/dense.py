@@ -204,6 +204,55 @@ def assemble(spec, lam, nu=1.0):
     return A
 
 
+def dirichlet_load(spec, nu, g):
+    """Load vector of inhomogeneous Dirichlet data (Nitsche terms of the SIP
+    form): for every node i, sum over the Dirichlet faces F of
+        int_F sigma g phi_i - int_F nu d_n(phi_i) g,
+    sigma = nu (P+1)^2 / h as in the bilinear form, n the outward normal, all
+    face integrals by the GLL rule.  g: nodal field (ABI layout) whose values
+    at the Dirichlet face nodes are the data; nu: scalar or nodal field.
+    A x = M f + dirichlet_load(spec, nu, g) is the SIP problem with u = g on
+    the Dirichlet faces."""
+    P = spec["P"]
+    n = P + 1
+    ne = (spec["nx"], spec["ny"], spec["nz"])
+    xi = gll.nodes(P)
+    w = gll.weights(P)
+    nuv = _nu_nodal(spec, nu)
+    g = np.asarray(g, dtype=np.float64)
+    _, dVf = lagrange_eval(xi, [-1.0, 1.0])   # dVf[s, j] = l_j'(+-1)
+    L = np.zeros(g.size)
+    for d in range(3):
+        if spec["bc"][d] != DIRICHLET:
+            continue
+        t1, t2 = [k for k in range(3) if k != d]
+        for ez in range(ne[2]):
+            for ey in range(ne[1]):
+                for ex in range(ne[0]):
+                    e = (ex, ey, ez)
+                    for high in (False, True):
+                        if e[d] != (ne[d] - 1 if high else 0):
+                            continue
+                        h = _extent(spec, d, e[d])
+                        om_t = _extent(spec, t1, e[t1]) * _extent(spec, t2, e[t2]) / 4.0
+                        layer = P if high else 0
+                        sgn = 1.0 if high else -1.0
+                        for i2 in range(n):
+                            for i1 in range(n):
+                                a = [0, 0, 0]
+                                a[d], a[t1], a[t2] = layer, i1, i2
+                                f = abi_index(spec, e, a)
+                                om = w[i1] * w[i2] * om_t
+                                sigma = nuv[f] * n * n / h
+                                L[f] += om * sigma * g[f]
+                                for k in range(n):      # the normal line through the face node
+                                    a[d] = k
+                                    j = abi_index(spec, e, a)
+                                    dn = sgn * (2.0 / h) * dVf[1 if high else 0, k]
+                                    L[j] -= om * nuv[f] * dn * g[f]
+    return L
+
+
 def mass_diag(spec):
     """Diagonal GLL mass matrix J w_a w_b w_c in ABI layout."""
     P = spec["P"]

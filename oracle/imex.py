@@ -20,8 +20,11 @@ explicit / (a^I, b^I) implicit sharing the abscissae c (c_1 = 0):
   optional final projection with d_n psi = 0,
 
 where F_d = F_d1 + F_d2 + F_d3 and every term of stage j is evaluated at
-(v_j, nu_j), the forcing F_s,j = f(t + c_j dt).  Walls carry v_b = 0 (the
-Helmholtz problems of the hot path take homogeneous Dirichlet data).
+(v_j, nu_j), the forcing F_s,j = f(t + c_j dt).  The wall velocity of stage
+j, v_b(t + c_j dt) (zero when not given), is the Dirichlet data of the
+stage's Helmholtz problems and of F_d1 (dense.dirichlet_load), the Neumann
+data of its projection, the boundary data of F_d3's divergence and the
+exterior state of the convective flux.
 
 The tableaux are transcribed from App. A as exact fractions (the left array
 of each pair is the implicit part).  Terms are evaluated at every stage
@@ -113,35 +116,41 @@ def as_float(tab):
             f([float(x) for x in tab["bE"]]))
 
 
-def helmholtz_solve(spec, lam, nu, rhs_nodal, solver="pcg", tol=1e-14):
-    """u with lambda M u + K_nu u = M rhs (velocity BCs: homogeneous
-    Dirichlet on wall axes)."""
+def helmholtz_solve(spec, lam, nu, rhs_nodal, solver="pcg", tol=1e-14, g_wall=None):
+    """u with lambda M u + K_nu u = M rhs + L_nu(g_wall): the wall data
+    g_wall (None: zero) as Dirichlet data on the Dirichlet axes."""
     M = dense.mass_diag(spec)
+    b = M * rhs_nodal
+    if g_wall is not None:
+        b = b + dense.dirichlet_load(spec, nu, g_wall)
     if solver == "dense":
         A = dense.assemble(spec, lam, nu)
-        return dense.solve(spec, A, M * rhs_nodal, lam)
+        return dense.solve(spec, A, b, lam)
     op = naive.Operator(spec, lam, nu)
-    x, info = pcg.pcg(op.apply, M * rhs_nodal, op.diag(), M, tol=tol)
+    x, info = pcg.pcg(op.apply, b, op.diag(), M, tol=tol)
     assert info["status"] == pcg.OK, info
     return x
 
 
-def step(spec, v, t, dt, tab, nu0, nu1, vref, forcing=None, final_projection=False, solver="pcg"):
+def step(spec, v, t, dt, tab, nu0, nu1, vref, forcing=None, final_projection=False, solver="pcg", wall=None):
     """One IMEX-RK step (Alg. 3).  v: three nodal arrays (velocity, degree
-    P); forcing: t -> three nodal arrays, or None; nu = nu0 + nu1 |v|^2/vref^2.
-    Returns (v_new, info) with the per-stage quantities in info."""
+    P); forcing, wall: t -> three nodal arrays (the forcing; the wall
+    velocity v_b, read on the Dirichlet faces), or None (zero);
+    nu = nu0 + nu1 |v|^2/vref^2.  Returns (v_new, info) with the per-stage
+    quantities in info."""
     c, AI, bI, AE, bE = as_float(tab)
     s = len(c)
     v = [np.asarray(x, dtype=np.float64) for x in v]
     zero = [np.zeros_like(v[0]) for _ in range(3)]
     Fs = [forcing(t + c[j] * dt) if forcing is not None else zero for j in range(s)]
+    Vb = [wall(t + c[j] * dt) if wall is not None else None for j in range(s)]
     Fc, Fd1, Fd2, Fd3 = [None] * s, [None] * s, [None] * s, [None] * s
 
     def terms(j, vj, nuj):
-        Fc[j] = convection.convection(spec, vj)
-        Fd1[j] = viscous.fd1(spec, nuj, vj)
+        Fc[j] = convection.convection(spec, vj, Vb[j])
+        Fd1[j] = viscous.fd1(spec, nuj, vj, Vb[j])
         Fd2[j] = convection.fd2(spec, nuj, vj)
-        Fd3[j] = viscous.fd3(spec, nuj, vj)
+        Fd3[j] = viscous.fd3(spec, nuj, vj, Vb[j])
 
     stage_v = [v]
     terms(0, v, viscous.viscosity(v, nu0, nu1, vref))
@@ -154,7 +163,7 @@ def step(spec, v, t, dt, tab, nu0, nu1, vref, forcing=None, final_projection=Fal
             for j in range(i + 1):
                 acc += AI[i, j] * Fs[j][d]
             vp.append(v[d] + dt * acc)
-        vpp, _ = projection.project(spec, vp)
+        vpp, _ = projection.project(spec, vp, Vb[i])
         nui = viscous.viscosity(vpp, nu0, nu1, vref)
         vi = []
         for d in range(3):
@@ -165,7 +174,8 @@ def step(spec, v, t, dt, tab, nu0, nu1, vref, forcing=None, final_projection=Fal
                 vi.append(g)
             else:
                 lam = 1.0 / (dt * AI[i, i])
-                vi.append(helmholtz_solve(spec, lam, nui, lam * g, solver))
+                vi.append(helmholtz_solve(spec, lam, nui, lam * g, solver,
+                                          g_wall=None if Vb[i] is None else Vb[i][d]))
         stage_v.append(vi)
         terms(i, vi, nui)
     out = []

@@ -17,9 +17,10 @@ The viscosity model of the variable-viscosity test cases (Sec. 4) is
 nu(v) = nu_0 + nu_1 (|v| / v_ref)^2.
 
 Discretisation (the reading written out in the build's design notes):
-  * F_d1 per component: the nodal field -M^-1 A_nu v with A_nu the SIP
-    operator of the Helmholtz solves at lambda = 0 and the nodal nu (the
-    velocity's BCs: homogeneous Dirichlet on Dirichlet axes);
+  * F_d1 per component: the nodal field -M^-1 (A_nu v - L_nu(v_b)) with
+    A_nu the SIP operator of the Helmholtz solves at lambda = 0 and the
+    nodal nu, L_nu the Nitsche load of the wall data v_b on the Dirichlet
+    axes (zero when v_b is not given);
   * F_d3: w = nu M^-1 D(v; v_b) with D the weak DG divergence of the
     projection substep taken on the velocity basis itself (equal order),
     then F_d3 = -G w with G the matching DG gradient (minus the adjoint of
@@ -36,11 +37,19 @@ def viscosity(v, nu0, nu1, vref):
     return nu0 + nu1 * s / (vref * vref)
 
 
-def fd1(spec, nu, v):
-    """div(nu grad v_d) for each component, as nodal fields."""
+def fd1(spec, nu, v, vb=None):
+    """div(nu grad v_d) for each component, as nodal fields: -M^-1 (K_nu v_d
+    - L_nu(v_b,d)), the wall data v_b (None: zero) as the Dirichlet data of
+    the SIP form (dense.dirichlet_load)."""
     M = dense.mass_diag(spec)
     op = naive.Operator(spec, 0.0, nu)
-    return [-op.apply(np.asarray(c, dtype=np.float64)) / M for c in v]
+    out = []
+    for d, c in enumerate(v):
+        y = op.apply(np.asarray(c, dtype=np.float64))
+        if vb is not None and vb[d] is not None:
+            y = y - dense.dirichlet_load(spec, nu, vb[d])
+        out.append(-y / M)
+    return out
 
 
 def fd3(spec, nu, v, vb=None):

@@ -8,7 +8,7 @@ from .binding import (DG_BC_DIRICHLET, DG_BC_NEUMANN, DG_BC_PERIODIC, DG_ERR_ARG
                       DG_ERR_BUDGET, DG_ERR_DEVICE, DG_ERR_NONFINITE, DG_ERR_NOT_SPD, DG_ERR_OOM,
                       DG_FP32, DG_FP64, DG_MIXED, DG_NOT_CONVERGED, DG_OK, DG_PC_FDM, DG_PC_JACOBI,
                       DG_PENDING, DG_RK_ARS3, DG_RK_CB2, DG_RK_CB3C, DG_RK_CB3E, DG_RK_CB4, DG_RK_TR,
-                      DGError, RK_METHODS, dg_convection, dg_imex_step, dg_viscous_fd2, imex_tableau,
+                      DGError, RK_METHODS, dg_convection, dg_dirichlet_load, dg_imex_step, dg_viscous_fd2, imex_tableau,
                       Mesh, Server, default_opts, dg_divergence, dg_gradient, dg_lincomb, dg_mesh_create,
                       dg_project, dg_viscosity, dg_viscous_terms,
                       exported_symbols,

@@ -122,8 +122,9 @@ _SIGS = {
     "dg_convection": ([_VP] * 7 + [ctypes.c_double, ctypes.c_int] + [_VP] * 4, ctypes.c_int),
     "dg_viscous_fd2": ([_VP] * 9, ctypes.c_int),
     "dg_imex_step": ([_VP, _VP, ctypes.POINTER(dg_tableau)] + [ctypes.c_double] * 4 + [_VP] * 3 +
-                     [ctypes.POINTER(_VP), ctypes.c_int, ctypes.POINTER(dg_solve_opts),
+                     [ctypes.POINTER(_VP), ctypes.POINTER(_VP), ctypes.c_int, ctypes.POINTER(dg_solve_opts),
                       ctypes.POINTER(dg_step_info)], ctypes.c_int),
+    "dg_dirichlet_load": ([_VP, _VP, ctypes.c_double, _VP, ctypes.c_double, _VP, _VP], ctypes.c_int),
     "helmholtz_solve_batched": ([_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(_VP), ctypes.POINTER(ctypes.c_int),
                                  ctypes.POINTER(_VP), ctypes.POINTER(_VP),
@@ -419,24 +420,37 @@ def dg_viscous_fd2(mesh, nu, v, out, stream=None):
                                 _stream_ptr(stream)))
 
 
+def dg_dirichlet_load(mesh, nu, g, b, nu_const=1.0, scale=1.0, stream=None):
+    """b += scale L(g): the Nitsche load of Dirichlet data g (nodal field)."""
+    import torch
+    p = lambda t: _dptr(t, torch.float64, mesh.ndof)
+    _check(lib().dg_dirichlet_load(mesh.handle, p(nu) if nu is not None else None, float(nu_const), p(g),
+                                   float(scale), p(b), _stream_ptr(stream)))
+
+
 def dg_imex_step(mv, mp, tableau, dt, nu0, nu1, vref, v, forcing=None, final_projection=False, opts=None,
-                 raise_on_error=True):
+                 raise_on_error=True, wall=None):
     """One IMEX-RK step (Alg. 3) in place on the three velocity tensors v.
-    tableau: a dg_tableau or a method (see imex_tableau); forcing: None or a
-    list over the stages of three tensors (or None) each."""
+    tableau: a dg_tableau or a method (see imex_tableau); forcing, wall: None
+    or a list over the stages of three tensors (or None) each (the forcing
+    and the wall velocity at t + c_j dt)."""
     import torch
     tab = tableau if isinstance(tableau, dg_tableau) else imex_tableau(tableau)
-    fp = None
-    if forcing is not None:
+
+    def per_stage(fields):
+        if fields is None:
+            return None
         flat = []
         for j in range(tab.s):
-            fj = forcing[j] if j < len(forcing) else None
+            fj = fields[j] if j < len(fields) else None
             for d in range(3):
                 flat.append(None if fj is None or fj[d] is None else _dptr(fj[d], torch.float64, mv.ndof))
-        fp = (ctypes.c_void_p * len(flat))(*flat)
+        return (ctypes.c_void_p * len(flat))(*flat)
+
+    fp, wp = per_stage(forcing), per_stage(wall)
     info = dg_step_info()
     rc = lib().dg_imex_step(mv.handle, mp.handle, ctypes.byref(tab), float(dt), float(nu0), float(nu1),
-                            float(vref), *[_dptr(c, torch.float64, mv.ndof) for c in v], fp,
+                            float(vref), *[_dptr(c, torch.float64, mv.ndof) for c in v], fp, wp,
                             int(bool(final_projection)), ctypes.byref(opts) if opts is not None else None,
                             ctypes.byref(info))
     if raise_on_error:

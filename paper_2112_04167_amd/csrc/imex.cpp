@@ -178,23 +178,26 @@ int fd2_terms(const MeshDev &md, const double *nu, const double *const v[3], dou
     return DG_OK;
 }
 
-// F_d1 = -M^-1 K_nu v per component (the SIP operator at lambda = 0)
-int fd1_terms(const MeshDev &md, const double *nu, const double *const v[3], double *const out[3], hipStream_t s)
+// F_d1 = -M^-1 (K_nu v - L_nu(v_b)) per component: the SIP operator at
+// lambda = 0 with the wall data v_b (null: zero) as its Dirichlet data
+int fd1_terms(const MeshDev &md, const double *nu, const double *const v[3], const double *const vb[3],
+              double *const out[3], hipStream_t s)
 {
     int rc;
     for (int d = 0; d < 3; ++d) {
         if ((rc = launch_apply<double>(md, md.bc, 0.0, nu, 0.0, v[d], out[d], s))) return rc;
+        if (vb && vb[d] && (rc = launch_dirichlet_load(md, md.bc, nu, 0.0, vb[d], -1.0, out[d], s))) return rc;
         if ((rc = launch_weak_to_nodal(md, out[d], nullptr, -1.0, out[d], s))) return rc;
     }
     return DG_OK;
 }
 
-// F_d3 = -G(nu M^-1 D(v; 0)), equal order
-int fd3_terms(const MeshDev &md, const double *nu, const double *const v[3], double *weak, double *const out[3],
-              hipStream_t s)
+// F_d3 = -G(nu M^-1 D(v; v_b)), equal order
+int fd3_terms(const MeshDev &md, const double *nu, const double *const v[3], const double *const vb[3],
+              double *weak, double *const out[3], hipStream_t s)
 {
     int rc;
-    if ((rc = launch_divergence(md, md, v, nullptr, 1.0, weak, s))) return rc;
+    if ((rc = launch_divergence(md, md, v, vb, 1.0, weak, s))) return rc;
     if ((rc = launch_weak_to_nodal(md, weak, nu, 1.0, weak, s))) return rc;
     return launch_gradient(md, md, weak, nullptr, -1.0, out, s);
 }
@@ -219,6 +222,22 @@ int dg_imex_tableau(int method, dg_tableau *out)
     }
     fill(r, out);
     return DG_OK;
+}
+
+int dg_dirichlet_load(dg_mesh *m, const double *nu_field, double nu_const, const double *g, double scale,
+                      double *b, void *stream)
+{
+    const MeshDev *md = mesh_device(m);
+    if (!md || !g || !b || (const void *)g == (const void *)b) {
+        set_error("null mesh, data or load array, or data aliasing the load");
+        return DG_ERR_ARG;
+    }
+    if (!nu_field && !(nu_const > 0.0 && std::isfinite(nu_const))) {
+        set_error("nu_const must be > 0 without a nodal viscosity");
+        return DG_ERR_ARG;
+    }
+    return launch_dirichlet_load(*md, md->bc, nu_field, nu_const, g, scale, b,
+                                 stream ? (hipStream_t)stream : mesh_stream(m));
 }
 
 int dg_convection(dg_mesh *m, const double *vx, const double *vy, const double *vz, const double *vbx,
@@ -261,7 +280,7 @@ int dg_viscous_fd2(dg_mesh *m, const double *nu, const double *vx, const double 
 
 int dg_imex_step(dg_mesh *mv, dg_mesh *mp, const dg_tableau *tab, double dt, double nu0, double nu1,
                  double vref, double *vx, double *vy, double *vz, const double *const *forcing,
-                 int final_projection, const dg_solve_opts *opts, dg_step_info *info)
+                 const double *const *wall, int final_projection, const dg_solve_opts *opts, dg_step_info *info)
 {
     const double t0 = now_s();
     dg_step_info st{};
@@ -309,6 +328,13 @@ int dg_imex_step(dg_mesh *mv, dg_mesh *mp, const dg_tableau *tab, double dt, dou
     auto D1 = [&](int j, int d) { return terms + ((size_t)slot[j] * 9 + 3 + d) * N; };
     auto D3 = [&](int j, int d) { return terms + ((size_t)slot[j] * 9 + 6 + d) * N; };
     auto Fs = [&](int j, int d) -> const double * { return forcing ? forcing[3 * j + d] : nullptr; };
+    // wall data of stage j (null: no-slip walls)
+    bool has_dirichlet = false;
+    for (int d = 0; d < 3; ++d) has_dirichlet = has_dirichlet || md.bc[d] == DG_BC_DIRICHLET;
+    auto walls = [&](int j, const double *out[3]) -> const double *const * {
+        for (int d = 0; d < 3; ++d) out[d] = wall ? wall[3 * j + d] : nullptr;
+        return (wall && (out[0] || out[1] || out[2])) ? out : nullptr;
+    };
     double *V0[3] = {vx, vy, vz};
     hipStream_t sv = mesh_stream(mv);
     dg_solve_opts o;
@@ -319,15 +345,17 @@ int dg_imex_step(dg_mesh *mv, dg_mesh *mp, const dg_tableau *tab, double dt, dou
 
     auto stage_terms = [&](int j, const double *const v[3]) -> int {
         int r;
+        const double *wb[3];
+        const double *const *vb = walls(j, wb);
         if (needD1[j]) {
             double *out[3] = {D1(j, 0), D1(j, 1), D1(j, 2)};
-            if ((r = fd1_terms(md, nu, v, out, sv))) return r;
+            if ((r = fd1_terms(md, nu, v, vb, out, sv))) return r;
         }
         if (needC[j]) {
             double *c3[3] = {C(j, 0), C(j, 1), C(j, 2)}, *d3[3] = {D3(j, 0), D3(j, 1), D3(j, 2)};
             if ((r = fd2_terms(md, nu, v, T, weak, c3, sv))) return r;
-            if ((r = launch_convection(md, v, nullptr, 1.0, true, c3, sv))) return r;
-            if ((r = fd3_terms(md, nu, v, weak, d3, sv))) return r;
+            if ((r = launch_convection(md, v, vb, 1.0, true, c3, sv))) return r;
+            if ((r = fd3_terms(md, nu, v, vb, weak, d3, sv))) return r;
             for (int d = 0; d < 3; ++d) {
                 const double one = 1.0;
                 const double *x = d3[d];
@@ -336,11 +364,14 @@ int dg_imex_step(dg_mesh *mv, dg_mesh *mp, const dg_tableau *tab, double dt, dou
         }
         return DG_OK;
     };
-    auto project = [&](double *const v[3], bool own_trace) -> int {
+    // the projection with the wall data vb (null: v_b = 0), or with the
+    // velocity's own trace (d_n psi = 0) for the final projection
+    auto project = [&](double *const v[3], const double *const *vb, bool own_trace) -> int {
         if (int r = launch_lincomb(Np, nullptr, 0, nullptr, nullptr, psi, sv)) return r;  // psi = 0
         dg_solve_info pi{};
-        const int r = dg_project(mv, mp, v[0], v[1], v[2], own_trace ? v[0] : nullptr, own_trace ? v[1] : nullptr,
-                                 own_trace ? v[2] : nullptr, psi, &o, &pi);
+        const double *b3[3] = {nullptr, nullptr, nullptr};
+        for (int d = 0; d < 3; ++d) b3[d] = own_trace ? v[d] : (vb ? vb[d] : nullptr);
+        const int r = dg_project(mv, mp, v[0], v[1], v[2], b3[0], b3[1], b3[2], psi, &o, &pi);
         if (r < 0) return r;
         st.solves += 1;
         st.pressure_iters += pi.iters;
@@ -373,7 +404,9 @@ int dg_imex_step(dg_mesh *mv, dg_mesh *mp, const dg_tableau *tab, double dt, dou
             if ((rc = launch_lincomb(N, V0[d], (int)coef.size(), coef.data(), xs.data(), Vi[d], sv))) return rc;
         }
         // projection, viscosity at the projected velocity
-        if ((rc = project(Vi, false))) return rc;
+        const double *wb[3];
+        const double *const *vbi = walls(i, wb);
+        if ((rc = project(Vi, vbi, false))) return rc;
         if ((rc = launch_viscosity(md, Vi, nu0, nu1, vref, nu, sv))) return rc;
         // load and Helmholtz solve per component
         const double aii = aI(i, i);
@@ -396,8 +429,15 @@ int dg_imex_step(dg_mesh *mv, dg_mesh *mp, const dg_tableau *tab, double dt, dou
             }
             if (aii > 0.0) {
                 if ((rc = launch_lincomb(N, nullptr, (int)coef.size(), coef.data(), xs.data(), G, sv))) return rc;
+                dg_solve_opts od = o;
+                if (has_dirichlet && vbi && vbi[d]) {
+                    // weak load M (lambda g) + L_nu(v_b): the wall data as Dirichlet data
+                    if ((rc = launch_mass(md, G, 1.0, false, G, sv))) return rc;
+                    if ((rc = launch_dirichlet_load(md, md.bc, nu, 0.0, vbi[d], 1.0, G, sv))) return rc;
+                    od.rhs_is_weak = 1;
+                }
                 dg_solve_info hi{};
-                rc = helmholtz_solve(mv, lam, nu, 0.0, G, Vi[d], &o, &hi);
+                rc = helmholtz_solve(mv, lam, nu, 0.0, G, Vi[d], &od, &hi);
                 if (rc < 0) return rc;
                 st.solves += 1;
                 st.velocity_iters += hi.iters;
@@ -430,7 +470,7 @@ int dg_imex_step(dg_mesh *mv, dg_mesh *mp, const dg_tableau *tab, double dt, dou
         }
         if ((rc = launch_lincomb(N, Vi[d], (int)coef.size(), coef.data(), xs.data(), V0[d], sv))) return rc;
     }
-    if (final_projection && (rc = project(V0, true))) return rc;
+    if (final_projection && (rc = project(V0, nullptr, true))) return rc;
     DG_HIP_CHECK(hipStreamSynchronize(sv));
     st.seconds = now_s() - t0;
     if (info) *info = st;

@@ -22,6 +22,13 @@ int launch_gradient(const MeshDev &mv, const MeshDev &mp, const double *psi, con
 // nodal field
 int launch_weak_to_nodal(const MeshDev &m, const double *x, const double *f, double s, double *out,
                          hipStream_t st);
+// out = (out or 0) + s M x at every node (a nodal field to a weak vector)
+int launch_mass(const MeshDev &m, const double *x, double s, bool accumulate, double *out, hipStream_t st);
+// b += scale L(g): the Nitsche load of the Dirichlet data g (nodal field,
+// its values on the faces of the Dirichlet axes of bc are read) with the
+// viscosity nu (nodal, or nu_c when null)
+int launch_dirichlet_load(const MeshDev &m, const int bc[3], const double *nu, double nu_c, const double *g,
+                          double scale, double *b, hipStream_t st);
 // nu = nu0 + nu1 |v|^2 / vref^2 at every node
 int launch_viscosity(const MeshDev &m, const double *const v[3], double nu0, double nu1, double vref,
                      double *nu, hipStream_t st);

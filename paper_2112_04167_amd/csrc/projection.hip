@@ -584,6 +584,64 @@ __global__ void k_viscosity(const double *vx, const double *vy, const double *vz
     }
 }
 
+// out = (out or 0) + s M x  (nodal field -> weak vector, M the GLL mass)
+__global__ void k_mass(NodalArgs A, const double *x, double s, int accumulate, double *out)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < A.N; i += (size_t)gridDim.x * blockDim.x) {
+        const double v = s * x[i] * node_mass(A, i);
+        out[i] = accumulate ? out[i] + v : v;
+    }
+}
+
+// Nitsche load of Dirichlet data g on the faces of one side of axis d:
+// b += scale [ int_F sigma g phi - int_F nu d_n(phi) g ], sigma = nu (P+1)^2 / h
+// (the SIP form's Dirichlet face), GLL rule on the face.  One thread per face
+// node: the penalty term lands on the node itself, the consistency term on
+// the node's normal line (d_n phi_k = +-(2/h) l_k'(+-1)), so the threads of
+// one launch touch disjoint nodes.
+struct DirArgs {
+    const double *h[3];
+    double w[kN], D0[kN], DP[kN];  // GLL weights, l_k'(-1), l_k'(+1)
+    int n[3], d, high;
+    const double *nu;
+    double nu_c;
+    const double *g;
+    double scale;
+    double *b;
+};
+
+template <int P>
+__global__ void k_dirichlet_load(DirArgs A)
+{
+    constexpr int n = P + 1, n3 = n * n * n;
+    const int d = A.d, t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+    const size_t total = (size_t)A.n[t1] * A.n[t2] * n * n;
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (size_t)gridDim.x * blockDim.x) {
+        const int st = (int)(idx % (n * n));
+        const size_t q = idx / (n * n);
+        const int s = st % n, t = st / n;
+        int e[3];
+        e[d] = A.high ? A.n[d] - 1 : 0;
+        e[t1] = (int)(q % A.n[t1]);
+        e[t2] = (int)(q / A.n[t1]);
+        const size_t base = ((size_t)(e[2] * A.n[1] + e[1]) * A.n[0] + e[0]) * n3;
+        const int layer = A.high ? n - 1 : 0;
+        const int f = face_node<n>(d, layer, s, t);
+        const double h = A.h[d][e[d]];
+        const double omega = A.w[s] * A.w[t] * A.h[t1][e[t1]] * A.h[t2][e[t2]] * 0.25;
+        const double nuf = A.nu ? A.nu[base + f] : A.nu_c;
+        const double gf = A.g[base + f];
+        A.b[base + f] += A.scale * omega * (nuf * n * n / h) * gf;
+        const double sgn = A.high ? 2.0 / h : -2.0 / h;
+#pragma unroll
+        for (int k = 0; k < n; ++k) {
+            const double dn = sgn * (A.high ? A.DP[k] : A.D0[k]);
+            A.b[base + face_node<n>(d, k, s, t)] -= A.scale * omega * nuf * dn * gf;
+        }
+    }
+}
+
 constexpr int kMaxComb = 32;
 struct CombArgs {
     const double *x0;
@@ -622,6 +680,57 @@ int launch_viscosity(const MeshDev &m, const double *const v[3], double nu0, dou
     hipLaunchKernelGGL(k_viscosity, flat_grid(N), dim3(256), 0, st, v[0], v[1], v[2], N, nu0, nu1,
                        1.0 / (vref * vref), nu);
     DG_HIP_CHECK(hipGetLastError());
+    return DG_OK;
+}
+
+int launch_mass(const MeshDev &m, const double *x, double s, bool accumulate, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_mass, flat_grid((size_t)m.ndof), dim3(256), 0, st, nodal_args(m), x, s,
+                       accumulate ? 1 : 0, out);
+    DG_HIP_CHECK(hipGetLastError());
+    return DG_OK;
+}
+
+int launch_dirichlet_load(const MeshDev &m, const int bc[3], const double *nu, double nu_c, const double *g,
+                          double scale, double *b, hipStream_t st)
+{
+    DirArgs a{};
+    const GllTables &gt = gll_cached(m.P);
+    const int n = m.P + 1;
+    for (int k = 0; k < n; ++k) {
+        a.w[k] = gt.w[k];
+        a.D0[k] = gt.D[0 * n + k];
+        a.DP[k] = gt.D[(n - 1) * n + k];
+    }
+    a.h[0] = m.h64;
+    a.h[1] = m.h64 + m.n[0];
+    a.h[2] = m.h64 + m.n[0] + m.n[1];
+    for (int d = 0; d < 3; ++d) a.n[d] = m.n[d];
+    a.nu = nu;
+    a.nu_c = nu_c;
+    a.g = g;
+    a.scale = scale;
+    a.b = b;
+    for (int d = 0; d < 3; ++d) {
+        if (bc[d] != DG_BC_DIRICHLET) continue;
+        const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+        const size_t total = (size_t)m.n[t1] * m.n[t2] * n * n;
+        const dim3 grid((unsigned)std::max<size_t>(1, std::min<size_t>((total + 255) / 256, 8192)));
+        for (int hi = 0; hi < 2; ++hi) {  // one side per launch: their normal lines may share nodes
+            a.d = d;
+            a.high = hi;
+            switch (m.P) {
+                case 3: hipLaunchKernelGGL(k_dirichlet_load<3>, grid, dim3(256), 0, st, a); break;
+                case 4: hipLaunchKernelGGL(k_dirichlet_load<4>, grid, dim3(256), 0, st, a); break;
+                case 5: hipLaunchKernelGGL(k_dirichlet_load<5>, grid, dim3(256), 0, st, a); break;
+                case 6: hipLaunchKernelGGL(k_dirichlet_load<6>, grid, dim3(256), 0, st, a); break;
+                case 7: hipLaunchKernelGGL(k_dirichlet_load<7>, grid, dim3(256), 0, st, a); break;
+                case 8: hipLaunchKernelGGL(k_dirichlet_load<8>, grid, dim3(256), 0, st, a); break;
+                default: set_error("degree outside 3..8"); return DG_ERR_ARG;
+            }
+            DG_HIP_CHECK(hipGetLastError());
+        }
+    }
     return DG_OK;
 }
 

@@ -1051,7 +1051,9 @@ double *mesh_step_buffer(dg_mesh *m, size_t doubles)
 {
     if (m->step_buf && m->step_doubles >= doubles) return m->step_buf;
     if (m->step_buf) {
-        (void)hipStreamSynchronize(m->stream);
+        // a caller's stream may still use the old buffer (dg_viscous_fd2
+        // takes any stream): wait for the whole device before freeing it
+        (void)hipDeviceSynchronize();
         (void)hipFree(m->step_buf);
         m->step_buf = nullptr;
         m->step_doubles = 0;

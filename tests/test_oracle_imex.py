@@ -280,3 +280,24 @@ def test_vvp_forcing_matches_finite_differences():
             fd = fd - (tau(x + dk, t)[:, k] - tau(x - dk, t)[:, k]) / (2 * e)
             fd[k] += (synth.vvp_pressure(*(x + dk), t) - synth.vvp_pressure(*(x - dk), t)) / (2 * e)
         assert np.max(np.abs(f - fd)) <= 1e-5 * (1 + np.max(np.abs(f)))
+
+
+def test_step_keeps_couette_flow():
+    # plane Couette flow v = (z, 0, 0) between the wall z = 0 at rest and the
+    # wall z = 1 moving at (1, 0, 0), constant viscosity, no forcing: a steady
+    # solution (v.grad v = 0, div v = 0, lap v = 0) that every stage
+    # represents exactly, so the step keeps it to rounding.  It checks the
+    # wall data in all the places it enters: the Nitsche load of the solves
+    # and of F_d1, the projection's Neumann data, F_d3 and the convective
+    # wall state
+    spec = make_spec((1, 1, 3), 4, (0, 0, 1), True)
+    X, Y, Z = node_coords(spec)
+    v = [Z.copy(), 0 * Z, 0 * Z]
+    wall = lambda t: [Z.copy(), 0 * Z, 0 * Z]
+    for name in ("RK-ARS3", "RK-CB3e"):
+        out, _ = imex.step(spec, v, 0.0, 0.05, imex.TABLEAUX[name], 0.02, 0.0, synth.VVP_VMAX,
+                           wall=wall, final_projection=True)
+        assert max(np.max(np.abs(out[d] - v[d])) for d in range(3)) <= 1e-12
+    # a moving wall the step does not know about (no wall data) is not kept
+    out, _ = imex.step(spec, v, 0.0, 0.05, imex.TABLEAUX["RK-CB3e"], 0.02, 0.0, synth.VVP_VMAX)
+    assert np.max(np.abs(out[0] - v[0])) > 1e-3
