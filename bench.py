@@ -562,8 +562,9 @@ def bench_imex_step(dg, torch, reps=3):
     nu(v) = 0.01 + 0.01 (|v|/2)^2, dt = 2^-8 from the exact velocity at
     t = 0, the manufactured forcing at the stage times (evaluated once,
     before timing), the final projection, every solve FDM-preconditioned
-    to 1e-10.  Also the convective term alone (HIP events on its stream)
-    against the FP64 vector peak."""
+    to 1e-10; RK-ARS3 again with walls on every face carrying the exact
+    velocity (VVD).  Also the convective term alone (HIP events on its
+    stream) against the FP64 vector peak."""
     import synth
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
@@ -599,6 +600,35 @@ def bench_imex_step(dg, torch, reps=3):
         out[method] = dict(step_ms=t * 1e3, steps_per_s=1.0 / t, stages=tab.s, solves=info["solves"],
                            pressure_iters=info["pressure_iters"], velocity_iters=info["velocity_iters"],
                            rel_error_vs_exact_after_one_step=err)
+    # the same step with walls on every face carrying the exact velocity
+    # (the VVD case): RK-ARS3 on the same elements with Dirichlet axes
+    sw = dict(spec)
+    sw["bc"] = (1, 1, 1)
+    pw = dict(sw)
+    pw["P"] = sw["P"] - 1
+    mvw, mpw = dg.mesh_from_spec(sw, stream=stream), dg.mesh_from_spec(pw, stream=stream)
+    tab = dg.imex_tableau("RK-ARS3")
+    f = [[c.contiguous() for c in synth.vvp_forcing(X, Y, Z, tab.c[j] * dt, nu0, nu1, xp=torch)]
+         for j in range(tab.s)]
+    wl = [[c.contiguous() for c in synth.vvp_velocity(X, Y, Z, tab.c[j] * dt, xp=torch)] for j in range(tab.s)]
+    times = []
+    for r in range(reps + 1):
+        v = [c.clone() for c in v0]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = dg.dg_imex_step(mvw, mpw, tab, dt, nu0, nu1, synth.VVP_VMAX, v, forcing=f, wall=wl,
+                               final_projection=True, opts=opts)
+        torch.cuda.synchronize()
+        if r > 0:
+            times.append(time.perf_counter() - t0)
+    ve = synth.vvp_velocity(X, Y, Z, dt, xp=torch)
+    err = max(float(torch.linalg.vector_norm(v[d] - ve[d]) / torch.linalg.vector_norm(ve[d])) for d in range(3))
+    t = float(np.median(times))
+    out["RK-ARS3_walls"] = dict(step_ms=t * 1e3, steps_per_s=1.0 / t, stages=tab.s, solves=info["solves"],
+                                pressure_iters=info["pressure_iters"], velocity_iters=info["velocity_iters"],
+                                rel_error_vs_exact_after_one_step=err)
+    mvw.destroy()
+    mpw.destroy()
     # the convective term alone
     o = [torch.empty_like(v0[0]) for _ in range(3)]
     for _ in range(3):
