@@ -103,6 +103,9 @@ __global__ void __launch_bounds__(256) k_convection(ConvArgs A)
     __shared__ double bufA[L::A];
     __shared__ double bufS[L::S];
     __shared__ double acc[3][n3];
+    // the 1D tables in LDS, compacted to Q x n: their lane-dependent rows
+    // would otherwise be vector loads from the kernel arguments
+    __shared__ double tB[Q * n], tdB[Q * n], twg[Q], tw[n];
     const int tid = threadIdx.x, nth = blockDim.x;
     const int el = blockIdx.x;
     const int ex = el % A.n[0], ey = (el / A.n[0]) % A.n[1], ez = el / (A.n[0] * A.n[1]);
@@ -111,6 +114,13 @@ __global__ void __launch_bounds__(256) k_convection(ConvArgs A)
     const double J = hh[0] * hh[1] * hh[2] * 0.125;
     const size_t base = (size_t)el * n3;
     double *U = bufA;
+    for (int i = threadIdx.x; i < Q * n; i += blockDim.x) {
+        tB[i] = A.t.B[i / n][i % n];
+        tdB[i] = A.t.dB[i / n][i % n];
+    }
+    for (int i = threadIdx.x; i < Q; i += blockDim.x) twg[i] = A.t.wg[i];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = A.t.w[i];
+    __syncthreads();
 
     // ---- velocity at the Gauss points: U_k = (B (x) B (x) B) v_k
     {
@@ -122,7 +132,7 @@ __global__ void __launch_bounds__(256) k_convection(ConvArgs A)
                 const int qx = i % Q, cb = i / Q;
                 double sum = 0.0;
 #pragma unroll
-                for (int a = 0; a < n; ++a) sum = fma(A.t.B[qx][a], X[cb * n + a], sum);
+                for (int a = 0; a < n; ++a) sum = fma(tB[(qx) * n + (a)], X[cb * n + a], sum);
                 Y1[i] = sum;
             }
             __syncthreads();
@@ -130,7 +140,7 @@ __global__ void __launch_bounds__(256) k_convection(ConvArgs A)
                 const int qx = i % Q, qy = (i / Q) % Q, c = i / Q2;
                 double sum = 0.0;
 #pragma unroll
-                for (int b = 0; b < n; ++b) sum = fma(A.t.B[qy][b], Y1[(c * n + b) * Q + qx], sum);
+                for (int b = 0; b < n; ++b) sum = fma(tB[(qy) * n + (b)], Y1[(c * n + b) * Q + qx], sum);
                 Y2[i] = sum;
             }
             __syncthreads();
@@ -138,7 +148,7 @@ __global__ void __launch_bounds__(256) k_convection(ConvArgs A)
                 const int qxy = i % Q2, qz = i / Q2;
                 double sum = 0.0;
 #pragma unroll
-                for (int c = 0; c < n; ++c) sum = fma(A.t.B[qz][c], Y2[c * Q2 + qxy], sum);
+                for (int c = 0; c < n; ++c) sum = fma(tB[(qz) * n + (c)], Y2[c * Q2 + qxy], sum);
                 U[k * Q3 + i] = sum;
             }
             __syncthreads();
@@ -160,12 +170,12 @@ __global__ void __launch_bounds__(256) k_convection(ConvArgs A)
 #pragma unroll
             for (int qz = 0; qz < Q; ++qz) {
                 const int q = qz * Q2 + qxy;
-                const double ui = U[i * Q3 + q] * A.t.wg[qz];
-                s0 = fma(A.t.B[qz][c], ui * U[q], s0);
-                s1 = fma(A.t.B[qz][c], ui * U[Q3 + q], s1);
-                s2 = fma(A.t.dB[qz][c], ui * U[2 * Q3 + q], s2);
+                const double ui = U[i * Q3 + q] * twg[qz];
+                s0 = fma(tB[(qz) * n + (c)], ui * U[q], s0);
+                s1 = fma(tB[(qz) * n + (c)], ui * U[Q3 + q], s1);
+                s2 = fma(tdB[(qz) * n + (c)], ui * U[2 * Q3 + q], s2);
             }
-            const double f = A.t.wg[qx] * A.t.wg[qy] * J;
+            const double f = twg[qx] * twg[qy] * J;
             Z[r] = s0 * f * g0;
             Z[nQ2 + r] = s1 * f * g1;
             Z[2 * nQ2 + r] = s2 * f * g2;
@@ -177,9 +187,9 @@ __global__ void __launch_bounds__(256) k_convection(ConvArgs A)
 #pragma unroll
             for (int qy = 0; qy < Q; ++qy) {
                 const int zi = (c * Q + qy) * Q + qx;
-                sx = fma(A.t.B[qy][b], Z[zi], sx);
-                ss = fma(A.t.dB[qy][b], Z[nQ2 + zi], ss);
-                ss = fma(A.t.B[qy][b], Z[2 * nQ2 + zi], ss);
+                sx = fma(tB[(qy) * n + (b)], Z[zi], sx);
+                ss = fma(tdB[(qy) * n + (b)], Z[nQ2 + zi], ss);
+                ss = fma(tB[(qy) * n + (b)], Z[2 * nQ2 + zi], ss);
             }
             Yb[r] = sx;
             Yb[n2Q + r] = ss;
@@ -190,8 +200,8 @@ __global__ void __launch_bounds__(256) k_convection(ConvArgs A)
             double sum = 0.0;
 #pragma unroll
             for (int qx = 0; qx < Q; ++qx) {
-                sum = fma(A.t.dB[qx][a], Yb[cb * Q + qx], sum);
-                sum = fma(A.t.B[qx][a], Yb[n2Q + cb * Q + qx], sum);
+                sum = fma(tdB[(qx) * n + (a)], Yb[cb * Q + qx], sum);
+                sum = fma(tB[(qx) * n + (a)], Yb[n2Q + cb * Q + qx], sum);
             }
             acc[i][r] += sum;
         }
@@ -234,7 +244,7 @@ __global__ void __launch_bounds__(256) k_convection(ConvArgs A)
             const int slot = r / (n * Q), q = r % Q, t = (r / Q) % n;
             double sum = 0.0;
 #pragma unroll
-            for (int s = 0; s < n; ++s) sum = fma(A.t.B[q][s], tr[slot * n * n + t * n + s], sum);
+            for (int s = 0; s < n; ++s) sum = fma(tB[(q) * n + (s)], tr[slot * n * n + t * n + s], sum);
             tq[r] = sum;
         }
         __syncthreads();
@@ -242,7 +252,7 @@ __global__ void __launch_bounds__(256) k_convection(ConvArgs A)
             const int slot = r / Q2, qs = r % Q, qt = (r / Q) % Q;
             double sum = 0.0;
 #pragma unroll
-            for (int t = 0; t < n; ++t) sum = fma(A.t.B[qt][t], tq[slot * n * Q + t * Q + qs], sum);
+            for (int t = 0; t < n; ++t) sum = fma(tB[(qt) * n + (t)], tq[slot * n * Q + t * Q + qs], sum);
             tg[r] = sum;
         }
         __syncthreads();
@@ -252,7 +262,7 @@ __global__ void __launch_bounds__(256) k_convection(ConvArgs A)
             const double *own = tg + side * 6 * Q2, *ext = own + 3 * Q2;
             const double vm = sgn * own[d * Q2 + q], vp = sgn * ext[d * Q2 + q];
             const double alpha = 2.0 * fmax(fabs(vm), fabs(vp));
-            const double om = om0 * A.t.wg[qs] * A.t.wg[qt];
+            const double om = om0 * twg[qs] * twg[qt];
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
                 const double um = own[i * Q2 + q], up = ext[i * Q2 + q];
@@ -264,7 +274,7 @@ __global__ void __launch_bounds__(256) k_convection(ConvArgs A)
             const int slot = r / (Q * n), s = r % n, qt = (r / n) % Q;
             double sum = 0.0;
 #pragma unroll
-            for (int qs = 0; qs < Q; ++qs) sum = fma(A.t.B[qs][s], hw[slot * Q2 + qt * Q + qs], sum);
+            for (int qs = 0; qs < Q; ++qs) sum = fma(tB[(qs) * n + (s)], hw[slot * Q2 + qt * Q + qs], sum);
             hq[r] = sum;
         }
         __syncthreads();
@@ -273,14 +283,14 @@ __global__ void __launch_bounds__(256) k_convection(ConvArgs A)
             const int side = slot / 3, i = slot % 3;
             double sum = 0.0;
 #pragma unroll
-            for (int qt = 0; qt < Q; ++qt) sum = fma(A.t.B[qt][t], hq[slot * Q * n + qt * n + s], sum);
+            for (int qt = 0; qt < Q; ++qt) sum = fma(tB[(qt) * n + (t)], hq[slot * Q * n + qt * n + s], sum);
             acc[i][layer_node<n>(d, side ? n - 1 : 0, s, t)] += sum;
         }
     }
     __syncthreads();
     for (int r = tid; r < n3; r += nth) {
         const int a = r % n, b = (r / n) % n, c = r / (n * n);
-        const double f = A.scale / (J * A.t.w[a] * A.t.w[b] * A.t.w[c]);
+        const double f = A.scale / (J * tw[a] * tw[b] * tw[c]);
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             const double val = f * acc[i][r];

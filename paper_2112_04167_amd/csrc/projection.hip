@@ -92,6 +92,15 @@ template <int P, int Q>
 __global__ void __launch_bounds__(256) k_divergence(ProjArgs A)
 {
     constexpr int n = P + 1, m = Q + 1, n3 = n * n * n, m3 = m * m * m;
+    // the 1D tables in LDS: their lane-dependent rows would otherwise be
+    // vector loads from the kernel arguments, one per multiply-add
+    __shared__ double tV[n * m], tdV[n * m], tw[n];
+    for (int i = threadIdx.x; i < n * m; i += blockDim.x) {
+        tV[i] = A.t.Vq[i / m][i % m];
+        tdV[i] = A.t.dVq[i / m][i % m];
+    }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = A.t.w[i];
+    __syncthreads();
     __shared__ double tv[n3];       // scaled velocity component
     __shared__ double s1[n * n * m];
     __shared__ double s2[n * m * m];
@@ -110,7 +119,7 @@ __global__ void __launch_bounds__(256) k_divergence(ProjArgs A)
         __syncthreads();
         for (int i = threadIdx.x; i < n3; i += blockDim.x) {
             const int a = i % n, b = (i / n) % n, c = i / (n * n);
-            tv[i] = A.t.w[a] * A.t.w[b] * A.t.w[c] * J * A.v[d][vb0 + i];
+            tv[i] = tw[a] * tw[b] * tw[c] * J * A.v[d][vb0 + i];
         }
         __syncthreads();
         const double gd = 2.0 / hh[d];
@@ -118,7 +127,7 @@ __global__ void __launch_bounds__(256) k_divergence(ProjArgs A)
         for (int i = threadIdx.x; i < n * n * m; i += blockDim.x) {
             const int ix = i % m, cb = i / m;
             double s = 0.0;
-            for (int a = 0; a < n; ++a) s += (d == 0 ? gd * A.t.dVq[a][ix] : A.t.Vq[a][ix]) * tv[cb * n + a];
+            for (int a = 0; a < n; ++a) s += (d == 0 ? gd * tdV[(a) * m + (ix)] : tV[(a) * m + (ix)]) * tv[cb * n + a];
             s1[i] = s;
         }
         __syncthreads();
@@ -127,7 +136,7 @@ __global__ void __launch_bounds__(256) k_divergence(ProjArgs A)
             const int ix = i % m, iy = (i / m) % m, c = i / (m * m);
             double s = 0.0;
             for (int b = 0; b < n; ++b)
-                s += (d == 1 ? gd * A.t.dVq[b][iy] : A.t.Vq[b][iy]) * s1[(c * n + b) * m + ix];
+                s += (d == 1 ? gd * tdV[(b) * m + (iy)] : tV[(b) * m + (iy)]) * s1[(c * n + b) * m + ix];
             s2[i] = s;
         }
         __syncthreads();
@@ -136,7 +145,7 @@ __global__ void __launch_bounds__(256) k_divergence(ProjArgs A)
             const int ix = i % m, iy = (i / m) % m, iz = i / (m * m);
             double s = 0.0;
             for (int c = 0; c < n; ++c)
-                s += (d == 2 ? gd * A.t.dVq[c][iz] : A.t.Vq[c][iz]) * s2[(c * m + iy) * m + ix];
+                s += (d == 2 ? gd * tdV[(c) * m + (iz)] : tV[(c) * m + (iz)]) * s2[(c * m + iy) * m + ix];
             acc[i] -= s;
         }
     }
@@ -161,13 +170,13 @@ __global__ void __launch_bounds__(256) k_divergence(ProjArgs A)
                     f = 0.5 * (A.v[d][vb0 + own] + A.v[d][nb0 + face_node<n>(d, nlayer, s, t)]);
                 else
                     f = A.vb[d][vb0 + own];
-                fs[i] = sgn * omega0 * A.t.w[s] * A.t.w[t] * f;  // [t][s]
+                fs[i] = sgn * omega0 * tw[s] * tw[t] * f;  // [t][s]
             }
             __syncthreads();
             for (int i = threadIdx.x; i < n * m; i += blockDim.x) {  // over s: fq[t][is]
                 const int is = i % m, t = i / m;
                 double sum = 0.0;
-                for (int s = 0; s < n; ++s) sum += A.t.Vq[s][is] * fs[t * n + s];
+                for (int s = 0; s < n; ++s) sum += tV[(s) * m + (is)] * fs[t * n + s];
                 fq[i] = sum;
             }
             __syncthreads();
@@ -175,7 +184,7 @@ __global__ void __launch_bounds__(256) k_divergence(ProjArgs A)
             for (int i = threadIdx.x; i < m * m; i += blockDim.x) {  // over t
                 const int is = i % m, it = i / m;
                 double sum = 0.0;
-                for (int t = 0; t < n; ++t) sum += A.t.Vq[t][it] * fq[t * m + is];
+                for (int t = 0; t < n; ++t) sum += tV[(t) * m + (it)] * fq[t * m + is];
                 const int q = d == 0 ? (it * m + is) * m + ip : d == 1 ? (it * m + ip) * m + is
                                                                         : (ip * m + it) * m + is;
                 acc[q] += sum;
@@ -192,6 +201,15 @@ template <int P, int Q>
 __global__ void __launch_bounds__(256) k_gradient(ProjArgs A)
 {
     constexpr int n = P + 1, m = Q + 1, n3 = n * n * n, m3 = m * m * m;
+    // the 1D tables in LDS: their lane-dependent rows would otherwise be
+    // vector loads from the kernel arguments, one per multiply-add
+    __shared__ double tV[n * m], tdV[n * m], tw[n];
+    for (int i = threadIdx.x; i < n * m; i += blockDim.x) {
+        tV[i] = A.t.Vq[i / m][i % m];
+        tdV[i] = A.t.dVq[i / m][i % m];
+    }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = A.t.w[i];
+    __syncthreads();
     __shared__ double q[m3];
     __shared__ double s1[m * m * n];
     __shared__ double s2[m * n * n];
@@ -209,7 +227,7 @@ __global__ void __launch_bounds__(256) k_gradient(ProjArgs A)
         for (int i = threadIdx.x; i < m * m * n; i += blockDim.x) {  // over ix: s1[iz][iy][a]
             const int a = i % n, r = i / n;
             double s = 0.0;
-            for (int ix = 0; ix < m; ++ix) s += (d == 0 ? gd * A.t.dVq[a][ix] : A.t.Vq[a][ix]) * q[r * m + ix];
+            for (int ix = 0; ix < m; ++ix) s += (d == 0 ? gd * tdV[(a) * m + (ix)] : tV[(a) * m + (ix)]) * q[r * m + ix];
             s1[i] = s;
         }
         __syncthreads();
@@ -217,7 +235,7 @@ __global__ void __launch_bounds__(256) k_gradient(ProjArgs A)
             const int a = i % n, b = (i / n) % n, iz = i / (n * n);
             double s = 0.0;
             for (int iy = 0; iy < m; ++iy)
-                s += (d == 1 ? gd * A.t.dVq[b][iy] : A.t.Vq[b][iy]) * s1[(iz * m + iy) * n + a];
+                s += (d == 1 ? gd * tdV[(b) * m + (iy)] : tV[(b) * m + (iy)]) * s1[(iz * m + iy) * n + a];
             s2[i] = s;
         }
         __syncthreads();
@@ -225,7 +243,7 @@ __global__ void __launch_bounds__(256) k_gradient(ProjArgs A)
             const int a = i % n, b = (i / n) % n, c = i / (n * n);
             double s = 0.0;
             for (int iz = 0; iz < m; ++iz)
-                s += (d == 2 ? gd * A.t.dVq[c][iz] : A.t.Vq[c][iz]) * s2[(iz * n + b) * n + a];
+                s += (d == 2 ? gd * tdV[(c) * m + (iz)] : tV[(c) * m + (iz)]) * s2[(iz * n + b) * n + a];
             g[i] = s;
         }
         // interior faces: g_d -= [psi] / (w_face h_d) on the face's nodes
@@ -253,19 +271,19 @@ __global__ void __launch_bounds__(256) k_gradient(ProjArgs A)
             for (int i = threadIdx.x; i < n * m; i += blockDim.x) {  // over is: jt[it][s]
                 const int s = i % n, it = i / n;
                 double sum = 0.0;
-                for (int is = 0; is < m; ++is) sum += A.t.Vq[s][is] * jf[it * m + is];
+                for (int is = 0; is < m; ++is) sum += tV[(s) * m + (is)] * jf[it * m + is];
                 jt[i] = sum;
             }
             __syncthreads();
             for (int i = threadIdx.x; i < n * n; i += blockDim.x) {  // over it: jump[t][s]
                 const int s = i % n, t = i / n;
                 double sum = 0.0;
-                for (int it = 0; it < m; ++it) sum += A.t.Vq[t][it] * jt[it * n + s];
+                for (int it = 0; it < m; ++it) sum += tV[(t) * m + (it)] * jt[it * n + s];
                 jump[i] = sum;
             }
             __syncthreads();
             const int layer = high ? n - 1 : 0;
-            const double f = 1.0 / (A.t.w[layer] * hh[d]);
+            const double f = 1.0 / (tw[layer] * hh[d]);
             for (int i = threadIdx.x; i < n * n; i += blockDim.x) {
                 const int s = i % n, t = i / n;
                 g[face_node<n>(d, layer, s, t)] -= f * jump[i];
@@ -290,6 +308,10 @@ template <int P>
 __global__ void __launch_bounds__(256) k_divergence_eq(ProjArgs A)
 {
     constexpr int n = P + 1, n3 = n * n * n;
+    __shared__ double tdV[n * n], tw[n];  // the 1D tables in LDS (see k_divergence)
+    for (int i = threadIdx.x; i < n * n; i += blockDim.x) tdV[i] = A.t.dVq[i / n][i % n];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = A.t.w[i];
+    __syncthreads();
     __shared__ double tv[3][n3];
     const int el = blockIdx.x;
     const int ex = el % A.n[0], ey = (el / A.n[0]) % A.n[1], ez = el / (A.n[0] * A.n[1]);
@@ -300,7 +322,7 @@ __global__ void __launch_bounds__(256) k_divergence_eq(ProjArgs A)
     for (int r = threadIdx.x; r < 3 * n3; r += blockDim.x) {
         const int d = r / n3, i = r - d * n3;
         const int a = i % n, b = (i / n) % n, c = i / (n * n);
-        tv[d][i] = A.t.w[a] * A.t.w[b] * A.t.w[c] * J * A.v[d][vb0 + i];
+        tv[d][i] = tw[a] * tw[b] * tw[c] * J * A.v[d][vb0 + i];
     }
     __syncthreads();
     for (int r = threadIdx.x; r < n3; r += blockDim.x) {
@@ -311,21 +333,21 @@ __global__ void __launch_bounds__(256) k_divergence_eq(ProjArgs A)
             const double gd = 2.0 / hh[0];
             double sum = 0.0;
 #pragma unroll
-            for (int k = 0; k < n; ++k) sum += gd * A.t.dVq[k][a] * tv[0][(c * n + b) * n + k];
+            for (int k = 0; k < n; ++k) sum += gd * tdV[(k) * n + (a)] * tv[0][(c * n + b) * n + k];
             acc -= sum;
         }
         {
             const double gd = 2.0 / hh[1];
             double sum = 0.0;
 #pragma unroll
-            for (int k = 0; k < n; ++k) sum += gd * A.t.dVq[k][b] * tv[1][(c * n + k) * n + a];
+            for (int k = 0; k < n; ++k) sum += gd * tdV[(k) * n + (b)] * tv[1][(c * n + k) * n + a];
             acc -= sum;
         }
         {
             const double gd = 2.0 / hh[2];
             double sum = 0.0;
 #pragma unroll
-            for (int k = 0; k < n; ++k) sum += gd * A.t.dVq[k][c] * tv[2][(k * n + b) * n + a];
+            for (int k = 0; k < n; ++k) sum += gd * tdV[(k) * n + (c)] * tv[2][(k * n + b) * n + a];
             acc -= sum;
         }
         for (int d = 0; d < 3; ++d) {
@@ -347,7 +369,7 @@ __global__ void __launch_bounds__(256) k_divergence_eq(ProjArgs A)
                     f = A.vb[d][vb0 + r];
                 }
                 const double omega0 = A.h[t1][e3[t1]] * A.h[t2][e3[t2]] * 0.25, sgn = high ? 1.0 : -1.0;
-                acc += sgn * omega0 * A.t.w[s] * A.t.w[t] * f;
+                acc += sgn * omega0 * tw[s] * tw[t] * f;
             }
         }
         A.out[vb0 + r] = A.scale * acc;
@@ -358,6 +380,10 @@ template <int P>
 __global__ void __launch_bounds__(256) k_gradient_eq(ProjArgs A)
 {
     constexpr int n = P + 1, n3 = n * n * n;
+    __shared__ double tdV[n * n], tw[n];  // the 1D tables in LDS (see k_divergence)
+    for (int i = threadIdx.x; i < n * n; i += blockDim.x) tdV[i] = A.t.dVq[i / n][i % n];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = A.t.w[i];
+    __syncthreads();
     __shared__ double q[n3];
     const int el = blockIdx.x;
     const int ex = el % A.n[0], ey = (el / A.n[0]) % A.n[1], ez = el / (A.n[0] * A.n[1]);
@@ -374,13 +400,13 @@ __global__ void __launch_bounds__(256) k_gradient_eq(ProjArgs A)
             double g = 0.0;
             if (d == 0) {
 #pragma unroll
-                for (int k = 0; k < n; ++k) g += gd * A.t.dVq[a][k] * q[(c * n + b) * n + k];
+                for (int k = 0; k < n; ++k) g += gd * tdV[(a) * n + (k)] * q[(c * n + b) * n + k];
             } else if (d == 1) {
 #pragma unroll
-                for (int k = 0; k < n; ++k) g += gd * A.t.dVq[b][k] * q[(c * n + k) * n + a];
+                for (int k = 0; k < n; ++k) g += gd * tdV[(b) * n + (k)] * q[(c * n + k) * n + a];
             } else {
 #pragma unroll
-                for (int k = 0; k < n; ++k) g += gd * A.t.dVq[c][k] * q[(k * n + b) * n + a];
+                for (int k = 0; k < n; ++k) g += gd * tdV[(c) * n + (k)] * q[(k * n + b) * n + a];
             }
             for (int hi = 0; hi < 2; ++hi) {
                 const bool high = hi == 1;
@@ -395,7 +421,7 @@ __global__ void __launch_bounds__(256) k_gradient_eq(ProjArgs A)
                 const double oth = A.psi[elem_base(A, en[0], en[1], en[2], n3) + (cn[2] * n + cn[1]) * n + cn[0]];
                 const double own = q[r];
                 const double jump = high ? own - oth : oth - own;
-                const double f = 1.0 / (A.t.w[layer] * hh[d]);
+                const double f = 1.0 / (tw[layer] * hh[d]);
                 g -= f * jump;
             }
             const double gv = A.fac ? A.scale * g * A.fac[base + r] : A.scale * g;
