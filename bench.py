@@ -685,10 +685,11 @@ def bench_imex_step(dg, torch, reps=3):
     return out
 
 
-def bench_serving(dg, nreq, slots, precision, budget=96 << 30, precond=0):
-    """Real-time replay of the request stream (Poisson arrivals, 200/s)."""
+def bench_serving(dg, nreq, slots, precision, budget=96 << 30, precond=0, rate=200.0):
+    """Real-time replay of the request stream (Poisson arrivals, 200/s; a
+    larger rate replays the same requests faster, to find the capacity)."""
     import synth
-    stream = synth.serving_stream()[:nreq]
+    stream = synth.serving_stream(rate=rate)[:nreq]
     srv = dg.Server(budget, slots)
     t0 = time.perf_counter()
     ids = []
@@ -742,7 +743,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=60,
                     help="prefix of the 2000-request stream replayed per serving mode")
-    ap.add_argument("--serving-modes", default="fifo_fp64,continuous_fp64,continuous_mixed,continuous_fdm",
+    ap.add_argument("--serving-modes",
+                    default="fifo_fp64,continuous_fp64,continuous_mixed,continuous_fdm,continuous_fdm_10x_rate",
                     help="serving modes to replay")
     ap.add_argument("--serving-fdm-requests", type=int, default=2000,
                     help="requests replayed in the fast-diagonalisation serving mode")
@@ -865,11 +867,13 @@ def main():
                     ("fifo_fp64", 1, dg.DG_FP64, 0, args.serving_requests),
                     ("continuous_fp64", 8, dg.DG_FP64, 0, args.serving_requests),
                     ("continuous_mixed", 8, dg.DG_MIXED, 0, args.serving_requests),
-                    ("continuous_fdm", 8, dg.DG_FP64, dg.DG_PC_FDM, args.serving_fdm_requests)):
+                    ("continuous_fdm", 8, dg.DG_FP64, dg.DG_PC_FDM, args.serving_fdm_requests),
+                    ("continuous_fdm_10x_rate", 8, dg.DG_FP64, dg.DG_PC_FDM, args.serving_fdm_requests)):
                 if name not in args.serving_modes.split(",") or nreq <= 0:
                     continue
                 log("serving:", name, nreq, "requests")
-                out["serving"][name] = bench_serving(dg, nreq, slots, prec, precond=pc)
+                out["serving"][name] = bench_serving(dg, nreq, slots, prec, precond=pc,
+                                                     rate=2000.0 if name.endswith("10x_rate") else 200.0)
         if not args.no_cpu:
             log("CPU oracle baseline")
             out["cpu_baseline"] = cpu_baseline(spec, lam)
