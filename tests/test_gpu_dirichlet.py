@@ -151,3 +151,25 @@ def test_step_vvd_error_falls_with_resolution():
         mp.destroy()
     say("vvd spatial errors", errs)
     assert errs[0] / errs[1] >= 4 and errs[1] / errs[2] >= 4, errs
+
+
+def test_step_full_size_couette():
+    # the channel at the batched configuration's size (24^3 elements, P = 5,
+    # walls in z): plane Couette flow kept by one RK-CB3e step
+    import paper_2112_04167_amd as dg
+    torch, dev = torch_dev()
+    spec = synth.mesh_spec("batched_channel")
+    ps = dict(spec)
+    ps["P"] = spec["P"] - 1
+    mv, mp = dg.mesh_from_spec(spec), dg.mesh_from_spec(ps)
+    X, Y, Z = dg.mesh_coordinates(mv)
+    v = [Z.clone(), torch.zeros_like(Z), torch.zeros_like(Z)]
+    tab = dg.imex_tableau("RK-CB3e")
+    wall = [[Z, None, None] for _ in range(tab.s)]
+    info = dg.dg_imex_step(mv, mp, tab, 1e-3, 0.02, 0.0, 2.0, v, wall=wall, final_projection=True,
+                           opts=dg.default_opts(tol=1e-12, precond=dg.DG_PC_FDM))
+    err = max(float((v[0] - Z).abs().max()), float(v[1].abs().max()), float(v[2].abs().max()))
+    say("full-size couette", info, err)
+    assert info["status"] == 0 and err <= 1e-10
+    mv.destroy()
+    mp.destroy()

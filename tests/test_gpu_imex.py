@@ -292,3 +292,33 @@ def test_user_tableau_with_an_explicit_stage_matches_oracle():
         assert rel(vd[d].cpu().numpy(), want[d]) <= 1e-10
     mv.destroy()
     mp.destroy()
+
+
+@pytest.mark.parametrize("method", ["RK-ARS3", "RK-CB3e"])
+def test_step_full_size_vvp(method):
+    # the bench's step at its own size (16^3 elements, P = 7, dt = 2^-8,
+    # FDM-preconditioned solves to 1e-10, the final projection): one step
+    # from the exact vortex-array state stays within 1e-6 of the exact
+    # solution (measured 2.0e-7 / 2.7e-7; the spatial and temporal errors
+    # of this resolution), with the solver counts of a healthy step
+    import paper_2112_04167_amd as dg
+    torch, dev = torch_dev()
+    spec = synth.mesh_spec("vvp_large")
+    ps = dict(spec)
+    ps["P"] = spec["P"] - 1
+    mv, mp = dg.mesh_from_spec(spec), dg.mesh_from_spec(ps)
+    X, Y, Z = dg.mesh_coordinates(mv)
+    dt, nu0, nu1 = 2.0 ** -8, 0.01, 0.01
+    tab = dg.imex_tableau(method)
+    v = [c.contiguous() for c in synth.vvp_velocity(X, Y, Z, 0.0, xp=torch)]
+    f = [[c.contiguous() for c in synth.vvp_forcing(X, Y, Z, tab.c[j] * dt, nu0, nu1, xp=torch)]
+         for j in range(tab.s)]
+    info = dg.dg_imex_step(mv, mp, tab, dt, nu0, nu1, synth.VVP_VMAX, v, forcing=f, final_projection=True,
+                           opts=dg.default_opts(precond=dg.DG_PC_FDM))
+    ve = synth.vvp_velocity(X, Y, Z, dt, xp=torch)
+    err = max(float(torch.linalg.vector_norm(v[d] - ve[d]) / torch.linalg.vector_norm(ve[d])) for d in range(3))
+    say("full-size step", method, info, err)
+    assert info["status"] == 0 and err <= 1e-6
+    assert info["pressure_iters"] <= 2 * (tab.s - 1) + 2 and info["velocity_iters"] <= 6 * 3 * (tab.s - 1)
+    mv.destroy()
+    mp.destroy()
