@@ -40,14 +40,22 @@ def trace_stats(db, pattern):
     return out, sel
 
 
-def trace_since(db, since):
+def trace_since(db, since, until=None, exclude=None):
     """Per-kernel totals over the dispatches from the first one whose name
-    contains `since` onward: [(name, calls, total_ns, avg_ns, pct)], and the
-    wall span of those dispatches in ns."""
+    contains `since` onward (up to, not including, the first later one whose
+    name contains `until`; leaving out names that contain `exclude`):
+    [(name, calls, total_ns, avg_ns, pct)], and the wall span of the window
+    in ns."""
     c = sqlite3.connect(db)
     rows = c.execute("select name, start, end, duration from kernels order by start").fetchall()
     t0 = next(r[1] for r in rows if since in r[0])
     sel = [r for r in rows if r[1] >= t0]
+    if until:
+        stop = next((i for i, r in enumerate(sel) if until in r[0]), len(sel))
+        sel = sel[:stop]
+    span = sel[-1][2] - sel[0][1]
+    if exclude:
+        sel = [r for r in sel if exclude not in r[0]]
     agg = {}
     for name, st, en, d in sel:
         a = agg.setdefault(name, [0, 0.0])
@@ -56,7 +64,7 @@ def trace_since(db, since):
     tot = sum(a[1] for a in agg.values())
     out = [(k, a[0], a[1], a[1] / a[0], 100.0 * a[1] / tot) for k, a in agg.items()]
     out.sort(key=lambda r: -r[2])
-    return out, sel[-1][2] - sel[0][1]
+    return out, span
 
 
 def counter(db, name, pattern, grid=None):
@@ -80,11 +88,13 @@ def main():
     ap.add_argument("--cmd", action="append", default=[])
     ap.add_argument("--title", default="rocprofv3 summary")
     ap.add_argument("--since", help="trace-only: dispatches from the first kernel containing this on")
+    ap.add_argument("--until", help="trace-only with --since: stop before the first later kernel containing this")
+    ap.add_argument("--exclude", help="trace-only with --since: leave out kernels whose names contain this")
     ap.add_argument("--per", type=float, default=0.0, help="trace-only with --since: also per-unit totals")
     a = ap.parse_args()
 
     if a.since:
-        rows, span = trace_since(a.trace, a.since)
+        rows, span = trace_since(a.trace, a.since, a.until, a.exclude)
         tot = sum(r[2] for r in rows)
         print("# %s" % a.title)
         print()
@@ -93,7 +103,9 @@ def main():
         for c in a.cmd:
             print("    " + c)
         print()
-        print("## Kernel trace from the first `%s` dispatch on (rocprofv3 --kernel-trace --stats)" % a.since)
+        print("## Kernel trace from the first `%s` dispatch on%s%s (rocprofv3 --kernel-trace --stats)"
+              % (a.since, " up to the first `%s`" % a.until if a.until else "",
+                 ", without `%s`" % a.exclude if a.exclude else ""))
         print()
         print("kernel time %.3f ms over a wall span of %.3f ms" % (tot / 1e6, span / 1e6), end="")
         print(" (per unit, %g units: %.3f ms)" % (a.per, tot / 1e6 / a.per) if a.per else "")
