@@ -15,14 +15,15 @@
 // (degree 3P per direction) exactly; M is the diagonal GLL mass.
 //
 // One work-group of 256 threads per element.  The element's velocity is
-// interpolated to the Q^3 Gauss points (three 1D passes per component, in
-// LDS).  Per output component i the nine (i, k) flux passes back to the
-// nodes are factored into three: the z pass forms the three products
-// v_i v_k on the fly, the y pass combines the k = 1, 2 branches that share
-// B_x, the x pass the remaining two.  Then both faces of each axis at once,
-// each element computing the fluxes of its own faces (no atomics: the
-// neighbour computes the same flux with the opposite sign).  LDS at P = 7:
-// 79 KB (two work-groups per CU); at P = 8: 124 KB.
+// interpolated to the Q^3 Gauss points (three 1D passes, the three
+// components together, in LDS).  Per output component i the nine (i, k)
+// flux passes back to the nodes are factored into three: the z pass forms
+// the three products v_i v_k on the fly, the y pass combines the k = 1, 2
+// branches that share B_x, the x pass the remaining two.  Then both faces of
+// each axis at once, each element computing the fluxes of its own faces (no
+// atomics: the neighbour computes the same flux with the opposite sign).
+// In every pass a thread owns whole 1D lines (see the line contractions
+// below).  LDS at P = 7: 78 KB (two work-groups per CU); at P = 8: 121 KB.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -32,23 +33,71 @@
 #include "convection.h"
 #include "device_common.h"
 #include "dg_internal.h"
+#include "gll_constexpr.h"
 
 namespace dg {
 
 namespace {
 
-constexpr int kN = kMaxN;         // velocity nodes per direction, at most 9
-constexpr int kMaxQ = 3 * 8 / 2 + 1;  // Gauss points per direction, at most 13
 
-struct ConvTables {
-    double B[kMaxQ][kN];   // B[q][a] = l_a(x_q): GLL basis at the Gauss points
-    double dB[kMaxQ][kN];  // its derivative on [-1, 1]
-    double wg[kMaxQ];      // Gauss weights
-    double w[kN];          // GLL weights (the mass)
+__host__ __device__ constexpr int conv_q(int P) { return 3 * P / 2 + 1; }
+
+// Compile-time tables of degree P: the GLL basis l_a and its derivative at
+// the Q Gauss-Legendre points, the Gauss weights and the GLL weights (the
+// mass).  The Gauss points are the roots of L_Q, by Newton's method on the
+// Legendre recurrence from the starting points -cos(pi (j + 3/4) / (Q + 1/2)),
+// then symmetrised; the weights are 2 / ((1 - x^2) L_Q'(x)^2).  Kept in
+// __constant__ memory: with compile-time indices the kernel reads them with
+// wide scalar loads.
+template <int P>
+struct ConvTab {
+    static constexpr int n = P + 1, Q = conv_q(P);
+    double B[Q][n];   // B[q][a] = l_a(x_q)
+    double dB[Q][n];  // its derivative on [-1, 1]
+    double wg[Q];     // Gauss weights
+    double w[n];      // GLL weights
+
+    constexpr ConvTab() : B(), dB(), wg(), w()
+    {
+        const double pi = 3.14159265358979323846;
+        double x0[Q] = {};
+        for (int j = 0; j < Q; ++j) {
+            double x = -cx::cos0(pi * (j + 0.75) / (Q + 0.5));
+            for (int it = 0; it < 100; ++it) {
+                const cx::Leg L = cx::legendre(Q, x);
+                const double dx = L.l / L.dl;
+                x -= dx;
+                if (cx::abs(dx) < 1e-16) break;
+            }
+            x0[j] = x;
+        }
+        double xg[Q] = {};
+        for (int j = 0; j < Q; ++j) xg[j] = 0.5 * (x0[j] - x0[Q - 1 - j]);
+        for (int j = 0; j < Q; ++j) {
+            const double dl = cx::legendre(Q, xg[j]).dl;
+            wg[j] = 2.0 / ((1.0 - xg[j] * xg[j]) * dl * dl);
+        }
+        const GllC<P> &g = kGll<P>;
+        for (int a = 0; a < n; ++a) w[a] = g.w[a];
+        for (int q = 0; q < Q; ++q)
+            for (int a = 0; a < n; ++a) {
+                double l = 1.0, dl = 0.0;
+                for (int k = 0; k < n; ++k) {
+                    if (k == a) continue;
+                    const double r = 1.0 / (g.xi[a] - g.xi[k]);
+                    dl = dl * (xg[q] - g.xi[k]) * r + l * r;
+                    l *= (xg[q] - g.xi[k]) * r;
+                }
+                B[q][a] = l;
+                dB[q][a] = dl;
+            }
+    }
 };
 
+template <int P>
+__constant__ ConvTab<P> c_conv = ConvTab<P>();
+
 struct ConvArgs {
-    ConvTables t;
     const double *v[3];
     const double *vb[3];   // wall state (null: zero)
     double *out[3];
@@ -58,22 +107,20 @@ struct ConvArgs {
     int accumulate;        // out += scale F_c instead of out = scale F_c
 };
 
-__host__ __device__ constexpr int conv_q(int P) { return 3 * P / 2 + 1; }
-
 template <int P>
 struct ConvLds {
     static constexpr int n = P + 1, Q = conv_q(P);
-    // region A: the velocity at the Gauss points U[3][Q^3], later the face
-    // points' traces tg[12][Q^2] and weighted fluxes hw[6][Q^2]
+    // region A: the first interpolation pass Y1[3][n^2 Q], then the velocity
+    // at the Gauss points U[3][Q^3], then the face points' traces
+    // tg[12][Q^2] and weighted fluxes hw[6][Q^2]
     static constexpr int vol = 3 * Q * Q * Q, fa = 18 * Q * Q;
     static constexpr int A = vol > fa ? vol : fa;
-    // region S: interpolation scratch (n^3 + n^2 Q + n Q^2), then the
-    // transposed passes Z[3][n Q^2], Yb[2][n^2 Q], then the face-node
-    // buffers tr[12][n^2], tq[12][n Q], hq[6][Q n]
-    static constexpr int s_in = n * n * n + n * n * Q + n * Q * Q;
+    // region S: the second interpolation pass Y2[3][n Q^2], then the
+    // transposed passes Z[3][n Q^2], Yb[2][n^2 Q], then the face buffers
+    // tq[12][n Q], hq[6][Q n]
     static constexpr int s_bk = 3 * n * Q * Q + 2 * n * n * Q;
-    static constexpr int s_fc = 12 * n * n + 12 * n * Q + 6 * Q * n;
-    static constexpr int S = s_in > s_bk ? (s_in > s_fc ? s_in : s_fc) : (s_bk > s_fc ? s_bk : s_fc);
+    static constexpr int s_fc = 18 * n * Q;
+    static constexpr int S = s_bk > s_fc ? s_bk : s_fc;
 };
 
 __device__ __forceinline__ int nb_index(int k, int nk, int bc, bool high)
@@ -94,169 +141,299 @@ __device__ __forceinline__ int layer_node(int d, int layer, int s, int t)
     return d == 0 ? (t * n + s) * n + layer : d == 1 ? (t * n + layer) * n + s : (layer * n + t) * n + s;
 }
 
+// Line contractions with the 1D tables.  Each thread owns whole lines and
+// every loop over a table is unrolled, so the table entries have
+// compile-time indices and are read with scalar loads from the kernel
+// arguments; only the data lines go through LDS (or come from global
+// memory).  Work split across threads by a compile-time range (C0, CN) is
+// chosen per group of whole waves, so that both halves keep compile-time
+// indices without divergence.
+
+// y[q] = sum_a B[q][a] x[a]: nodes to Gauss points
+template <int P, int n = P + 1, int Q = conv_q(P)>
+__device__ __forceinline__ void to_gauss(const ConvTab<P> &T, const double (&x)[n], double (&y)[Q])
+{
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        double s = 0.0;
+#pragma unroll
+        for (int a = 0; a < n; ++a) s = fma(T.B[q][a], x[a], s);
+        y[q] = s;
+    }
+}
+
+// y[a] = sum_q B[q][a] x[q]: Gauss points back to nodes (B^T)
+template <int P, int n = P + 1, int Q = conv_q(P)>
+__device__ __forceinline__ void to_nodes(const ConvTab<P> &T, const double (&x)[Q], double (&y)[n])
+{
+#pragma unroll
+    for (int a = 0; a < n; ++a) {
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) s = fma(T.B[q][a], x[q], s);
+        y[a] = s;
+    }
+}
+
+// z pass of the volume term for output component i, Gauss column qxy, node
+// layers c in [C0, C0 + CN): Z_k[c][qxy] = f_k sum_qz T_k[qz][c] wg_qz U_i U_k
+// with T_0 = T_1 = B, T_2 = dB
+template <int P, int C0, int CN>
+__device__ __forceinline__ void vol_z(const ConvTab<P> &T, const double *U, int i, int qxy, double f0,
+                                      double f1, double f2, double *Z)
+{
+    constexpr int n = P + 1, Q = conv_q(P);
+    constexpr int Q2 = Q * Q, Q3 = Q2 * Q, nQ2 = n * Q2;
+    if constexpr (CN > 0) {
+        double s0[CN], s1[CN], s2[CN];
+#pragma unroll
+        for (int cc = 0; cc < CN; ++cc) s0[cc] = s1[cc] = s2[cc] = 0.0;
+#pragma unroll
+        for (int qz = 0; qz < Q; ++qz) {
+            const int q = qz * Q2 + qxy;
+            const double u0 = U[q], u1 = U[Q3 + q], u2 = U[2 * Q3 + q];
+            const double ui = (i == 0 ? u0 : i == 1 ? u1 : u2) * T.wg[qz];
+            const double p0 = ui * u0, p1 = ui * u1, p2 = ui * u2;
+#pragma unroll
+            for (int cc = 0; cc < CN; ++cc) {
+                s0[cc] = fma(T.B[qz][C0 + cc], p0, s0[cc]);
+                s1[cc] = fma(T.B[qz][C0 + cc], p1, s1[cc]);
+                s2[cc] = fma(T.dB[qz][C0 + cc], p2, s2[cc]);
+            }
+        }
+#pragma unroll
+        for (int cc = 0; cc < CN; ++cc) {
+            const int c = C0 + cc;
+            Z[c * Q2 + qxy] = s0[cc] * f0;
+            Z[nQ2 + c * Q2 + qxy] = s1[cc] * f1;
+            Z[2 * nQ2 + c * Q2 + qxy] = s2[cc] * f2;
+        }
+    }
+}
+
+// y pass, line (c, qx), node rows b in [B0, B0 + BN):
+// Yx = B_y^T Z_0, Ys = dB_y^T Z_1 + B_y^T Z_2
+template <int P, int B0, int BN>
+__device__ __forceinline__ void vol_y(const ConvTab<P> &T, const double *Z, int c, int qx, double *Yb)
+{
+    constexpr int n = P + 1, Q = conv_q(P);
+    constexpr int nQ2 = n * Q * Q, n2Q = n * n * Q;
+    if constexpr (BN > 0) {
+        double sx[BN], ss[BN];
+#pragma unroll
+        for (int bb = 0; bb < BN; ++bb) sx[bb] = ss[bb] = 0.0;
+#pragma unroll
+        for (int qy = 0; qy < Q; ++qy) {
+            const int zi = (c * Q + qy) * Q + qx;
+            const double z0 = Z[zi], z1 = Z[nQ2 + zi], z2 = Z[2 * nQ2 + zi];
+#pragma unroll
+            for (int bb = 0; bb < BN; ++bb) {
+                sx[bb] = fma(T.B[qy][B0 + bb], z0, sx[bb]);
+                ss[bb] = fma(T.dB[qy][B0 + bb], z1, fma(T.B[qy][B0 + bb], z2, ss[bb]));
+            }
+        }
+#pragma unroll
+        for (int bb = 0; bb < BN; ++bb) {
+            const int o = (c * n + B0 + bb) * Q + qx;
+            Yb[o] = sx[bb];
+            Yb[n2Q + o] = ss[bb];
+        }
+    }
+}
+
+// x pass, line (c, b) = cb, nodes a in [A0, A0 + AN): acc = dB_x^T Yx + B_x^T Ys
+template <int P, int A0, int AN>
+__device__ __forceinline__ void vol_x(const ConvTab<P> &T, const double *Yb, int cb, double *acc)
+{
+    constexpr int n = P + 1, Q = conv_q(P);
+    constexpr int n2Q = n * n * Q;
+    if constexpr (AN > 0) {
+        double s[AN];
+#pragma unroll
+        for (int aa = 0; aa < AN; ++aa) s[aa] = 0.0;
+#pragma unroll
+        for (int qx = 0; qx < Q; ++qx) {
+            const double yx = Yb[cb * Q + qx], ys = Yb[n2Q + cb * Q + qx];
+#pragma unroll
+            for (int aa = 0; aa < AN; ++aa) s[aa] = fma(T.dB[qx][A0 + aa], yx, fma(T.B[qx][A0 + aa], ys, s[aa]));
+        }
+#pragma unroll
+        for (int aa = 0; aa < AN; ++aa) acc[cb * n + A0 + aa] = s[aa];
+    }
+}
+
 template <int P>
 __global__ void __launch_bounds__(256) k_convection(ConvArgs A)
 {
     using L = ConvLds<P>;
-    constexpr int n = L::n, Q = L::Q, n3 = n * n * n, Q2 = Q * Q, Q3 = Q * Q * Q;
-    constexpr int nQ2 = n * Q2, n2Q = n * n * Q;
+    constexpr int n = L::n, Q = L::Q, n2 = n * n, n3 = n2 * n, Q2 = Q * Q;
+    constexpr int nQ2 = n * Q2, n2Q = n2 * Q;
+    constexpr int NT = 256;                    // threads per work-group (the launch's block size)
+    constexpr int H = (n + 1) / 2;             // the two halves of a node range: [0, H), [H, n)
+    constexpr int WZ = (Q2 + 63) / 64 * 64;    // thread slots per half of a pass, whole waves
+    constexpr int WY = (n * Q + 63) / 64 * 64;
+    constexpr int WX = (n2 + 63) / 64 * 64;
     __shared__ double bufA[L::A];
     __shared__ double bufS[L::S];
     __shared__ double acc[3][n3];
-    // the 1D tables in LDS, compacted to Q x n: their lane-dependent rows
-    // would otherwise be vector loads from the kernel arguments
-    __shared__ double tB[Q * n], tdB[Q * n], twg[Q], tw[n];
-    const int tid = threadIdx.x, nth = blockDim.x;
+    // the weights used with lane-dependent indices
+    __shared__ double twg[Q], tw[n];
+    const int tid = threadIdx.x;
     const int el = blockIdx.x;
     const int ex = el % A.n[0], ey = (el / A.n[0]) % A.n[1], ez = el / (A.n[0] * A.n[1]);
     const int e3[3] = {ex, ey, ez};
     const double hh[3] = {A.h[0][ex], A.h[1][ey], A.h[2][ez]};
     const double J = hh[0] * hh[1] * hh[2] * 0.125;
     const size_t base = (size_t)el * n3;
-    double *U = bufA;
-    for (int i = threadIdx.x; i < Q * n; i += blockDim.x) {
-        tB[i] = A.t.B[i / n][i % n];
-        tdB[i] = A.t.dB[i / n][i % n];
-    }
-    for (int i = threadIdx.x; i < Q; i += blockDim.x) twg[i] = A.t.wg[i];
-    for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = A.t.w[i];
-    __syncthreads();
+    const ConvTab<P> &T = c_conv<P>;
+    if (tid < Q) twg[tid] = T.wg[tid];
+    if (tid < n) tw[tid] = T.w[tid];
 
-    // ---- velocity at the Gauss points: U_k = (B (x) B (x) B) v_k
-    {
-        double *X = bufS, *Y1 = bufS + n3, *Y2 = bufS + n3 + n2Q;
-        for (int k = 0; k < 3; ++k) {
-            for (int i = tid; i < n3; i += nth) X[i] = A.v[k][base + i];
-            __syncthreads();
-            for (int i = tid; i < n2Q; i += nth) {  // x: Y1[c][b][qx]
-                const int qx = i % Q, cb = i / Q;
-                double sum = 0.0;
+    // ---- velocity at the Gauss points, U_k = (B (x) B (x) B) v_k, the three
+    //      components together: x lines from global memory into Y1 (region
+    //      A), y lines into Y2 (region S), z lines into U (region A again)
+    double *Y1 = bufA, *Y2 = bufS, *U = bufA;
+    for (int r = tid; r < 3 * n2; r += NT) {  // Y1[k][c][b][qx]
+        const int k = r / n2, cb = r - k * n2;
+        const double *src = (k == 0 ? A.v[0] : k == 1 ? A.v[1] : A.v[2]) + base + (size_t)cb * n;
+        double x[n], y[Q];
 #pragma unroll
-                for (int a = 0; a < n; ++a) sum = fma(tB[(qx) * n + (a)], X[cb * n + a], sum);
-                Y1[i] = sum;
-            }
-            __syncthreads();
-            for (int i = tid; i < nQ2; i += nth) {  // y: Y2[c][qy][qx]
-                const int qx = i % Q, qy = (i / Q) % Q, c = i / Q2;
-                double sum = 0.0;
+        for (int a = 0; a < n; ++a) x[a] = src[a];
+        to_gauss<P>(T, x, y);
 #pragma unroll
-                for (int b = 0; b < n; ++b) sum = fma(tB[(qy) * n + (b)], Y1[(c * n + b) * Q + qx], sum);
-                Y2[i] = sum;
-            }
-            __syncthreads();
-            for (int i = tid; i < Q3; i += nth) {  // z: U_k[qz][qy][qx]
-                const int qxy = i % Q2, qz = i / Q2;
-                double sum = 0.0;
+        for (int q = 0; q < Q; ++q) Y1[r * Q + q] = y[q];
+    }
+    __syncthreads();
+    for (int r = tid; r < 3 * H * Q; r += NT) {  // Y2[k][c][qy][qx], lines c and c + H
+        const int qx = r % Q, kh = r / Q, k = kh / H, c0 = kh - k * H;
 #pragma unroll
-                for (int c = 0; c < n; ++c) sum = fma(tB[(qz) * n + (c)], Y2[c * Q2 + qxy], sum);
-                U[k * Q3 + i] = sum;
+        for (int h = 0; h < 2; ++h) {
+            const int c = c0 + h * H;
+            if (c < n) {
+                const int kc = k * n + c;
+                double x[n], y[Q];
+#pragma unroll
+                for (int b = 0; b < n; ++b) x[b] = Y1[(kc * n + b) * Q + qx];
+                to_gauss<P>(T, x, y);
+#pragma unroll
+                for (int q = 0; q < Q; ++q) Y2[(kc * Q + q) * Q + qx] = y[q];
             }
-            __syncthreads();
         }
     }
-    for (int i = tid; i < 3 * n3; i += nth) (&acc[0][0])[i] = 0.0;
+    __syncthreads();
+    constexpr int HQ = (Q2 + 1) / 2;
+    for (int r = tid; r < 3 * HQ; r += NT) {  // U[k][qz][qy][qx], columns p and p + HQ
+        const int k = r / HQ, p = r - k * HQ;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int qxy = p + h * HQ;
+            if (qxy < Q2) {
+                double x[n], y[Q];
+#pragma unroll
+                for (int c = 0; c < n; ++c) x[c] = Y2[(k * n + c) * Q2 + qxy];
+                to_gauss<P>(T, x, y);
+#pragma unroll
+                for (int q = 0; q < Q; ++q) U[(k * Q + q) * Q2 + qxy] = y[q];
+            }
+        }
+    }
+    __syncthreads();
 
     // ---- volume: acc_i = sum_k T_k^T (W J v_i v_k) with T_k = (2/h_k) dB along
     //      k and B along the others, factored as
-    //      B_x^T [B_y^T dB_z^T F_i2 + dB_y^T B_z^T F_i1] + dB_x^T B_y^T B_z^T F_i0
+    //      B_x^T [B_y^T dB_z^T F_i2 + dB_y^T B_z^T F_i1] + dB_x^T B_y^T B_z^T F_i0.
+    //      Z (region S) and Yb (region S, after Z) do not overlap, so the x
+    //      pass of component i and the z pass of i + 1 need no barrier
+    //      between them.
     double *Z = bufS, *Yb = bufS + 3 * nQ2;
     const double g0 = 2.0 / hh[0], g1 = 2.0 / hh[1], g2 = 2.0 / hh[2];
     for (int i = 0; i < 3; ++i) {
-        __syncthreads();
-        for (int r = tid; r < nQ2; r += nth) {  // z: Z_k[c][qy][qx]
-            const int qx = r % Q, qy = (r / Q) % Q, c = r / Q2;
-            const int qxy = qy * Q + qx;
-            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-#pragma unroll
-            for (int qz = 0; qz < Q; ++qz) {
-                const int q = qz * Q2 + qxy;
-                const double ui = U[i * Q3 + q] * twg[qz];
-                s0 = fma(tB[(qz) * n + (c)], ui * U[q], s0);
-                s1 = fma(tB[(qz) * n + (c)], ui * U[Q3 + q], s1);
-                s2 = fma(tdB[(qz) * n + (c)], ui * U[2 * Q3 + q], s2);
+        for (int r = tid; r < 2 * WZ; r += NT) {
+            const int hf = r / WZ, qxy = r - hf * WZ;
+            if (qxy < Q2) {
+                const double f = twg[qxy % Q] * twg[qxy / Q] * J;
+                if (hf == 0)
+                    vol_z<P, 0, H>(T, U, i, qxy, f * g0, f * g1, f * g2, Z);
+                else
+                    vol_z<P, H, n - H>(T, U, i, qxy, f * g0, f * g1, f * g2, Z);
             }
-            const double f = twg[qx] * twg[qy] * J;
-            Z[r] = s0 * f * g0;
-            Z[nQ2 + r] = s1 * f * g1;
-            Z[2 * nQ2 + r] = s2 * f * g2;
         }
         __syncthreads();
-        for (int r = tid; r < n2Q; r += nth) {  // y: Yb_x = B_y^T Z_0, Yb_s = dB_y^T Z_1 + B_y^T Z_2
-            const int qx = r % Q, b = (r / Q) % n, c = r / (n * Q);
-            double sx = 0.0, ss = 0.0;
-#pragma unroll
-            for (int qy = 0; qy < Q; ++qy) {
-                const int zi = (c * Q + qy) * Q + qx;
-                sx = fma(tB[(qy) * n + (b)], Z[zi], sx);
-                ss = fma(tdB[(qy) * n + (b)], Z[nQ2 + zi], ss);
-                ss = fma(tB[(qy) * n + (b)], Z[2 * nQ2 + zi], ss);
+        for (int r = tid; r < 2 * WY; r += NT) {
+            const int hf = r / WY, cq = r - hf * WY;
+            if (cq < n * Q) {
+                if (hf == 0)
+                    vol_y<P, 0, H>(T, Z, cq / Q, cq % Q, Yb);
+                else
+                    vol_y<P, H, n - H>(T, Z, cq / Q, cq % Q, Yb);
             }
-            Yb[r] = sx;
-            Yb[n2Q + r] = ss;
         }
         __syncthreads();
-        for (int r = tid; r < n3; r += nth) {  // x: acc_i[c][b][a]
-            const int a = r % n, cb = r / n;
-            double sum = 0.0;
-#pragma unroll
-            for (int qx = 0; qx < Q; ++qx) {
-                sum = fma(tdB[(qx) * n + (a)], Yb[cb * Q + qx], sum);
-                sum = fma(tB[(qx) * n + (a)], Yb[n2Q + cb * Q + qx], sum);
+        for (int r = tid; r < 2 * WX; r += NT) {
+            const int hf = r / WX, cb = r - hf * WX;
+            if (cb < n2) {
+                if (hf == 0)
+                    vol_x<P, 0, H>(T, Yb, cb, acc[i]);
+                else
+                    vol_x<P, H, n - H>(T, Yb, cb, acc[i]);
             }
-            acc[i][r] += sum;
         }
     }
 
-    // ---- faces: acc_i -= int_F H_i phi, both faces of an axis at once
-    double *tr = bufS;                 // [12][n*n]: side*6 + (own v_0..2, exterior v_0..2), [t][s]
-    double *tq = tr + 12 * n * n;      // [12][n*Q]: [t][qs]
-    double *hq = tq + 12 * n * Q;      // [6][Q*n]: side*3 + i, [qt][s]
-    double *tg = bufA;                 // [12][Q*Q]: [qt][qs]
-    double *hw = bufA + 12 * Q2;       // [6][Q*Q]
+    // ---- faces: acc_i -= int_F H_i phi, both faces of an axis at once.
+    //      Slots: side * 6 + (own v_0..2, exterior v_0..2); side 0 the low
+    //      face, 1 the high one.
+    double *tq = bufS;               // [12][n][Q]: face lines along s at the Gauss points (t, qs)
+    double *hq = bufS + 12 * n * Q;  // [6][Q][n]: side * 3 + i, (qt, s)
+    double *tg = bufA;               // [12][Q][Q]: (qt, qs)
+    double *hw = bufA + 12 * Q2;     // [6][Q][Q]
     for (int d = 0; d < 3; ++d) {
         const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
         const double om0 = hh[t1] * hh[t2] * 0.25;
-        __syncthreads();  // the previous phase's readers of these buffers are done
-        for (int r = tid; r < 12 * n * n; r += nth) {
-            const int slot = r / (n * n), st = r % (n * n), s = st % n, t = st / n;
+        // tq of this axis overwrites what the previous axis's second pass
+        // read (three barriers ago); at d = 0 it overwrites the volume's Yb
+        if (d == 0) __syncthreads();
+        for (int r = tid; r < 12 * n; r += NT) {  // the face lines along s, to the Gauss points
+            const int slot = r / n, t = r % n;
             const bool high = slot >= 6;
-            const int comp = slot % 6;
+            const int comp = slot % 6, c3 = comp % 3;
             const int layer = high ? n - 1 : 0;
-            double val;
+            const double *src = nullptr;
+            int lay = layer;
             if (comp < 3) {
-                val = A.v[comp][base + layer_node<n>(d, layer, s, t)];
+                src = (c3 == 0 ? A.v[0] : c3 == 1 ? A.v[1] : A.v[2]) + base;
             } else {
                 const int kn = nb_index(e3[d], A.n[d], A.bc[d], high);
                 if (kn >= 0) {
                     int en[3] = {ex, ey, ez};
                     en[d] = kn;
-                    const size_t nbase = ((size_t)(en[2] * A.n[1] + en[1]) * A.n[0] + en[0]) * n3;
-                    val = A.v[comp - 3][nbase + layer_node<n>(d, high ? 0 : n - 1, s, t)];
+                    src = (c3 == 0 ? A.v[0] : c3 == 1 ? A.v[1] : A.v[2]) +
+                          ((size_t)(en[2] * A.n[1] + en[1]) * A.n[0] + en[0]) * n3;
+                    lay = high ? 0 : n - 1;
                 } else {
-                    const double *wb = A.vb[comp - 3];
-                    val = wb ? wb[base + layer_node<n>(d, layer, s, t)] : 0.0;
+                    const double *wb = c3 == 0 ? A.vb[0] : c3 == 1 ? A.vb[1] : A.vb[2];
+                    src = wb ? wb + base : nullptr;
                 }
             }
-            tr[r] = val;
-        }
-        __syncthreads();
-        for (int r = tid; r < 12 * n * Q; r += nth) {  // along s
-            const int slot = r / (n * Q), q = r % Q, t = (r / Q) % n;
-            double sum = 0.0;
+            double x[n], y[Q];
 #pragma unroll
-            for (int s = 0; s < n; ++s) sum = fma(tB[(q) * n + (s)], tr[slot * n * n + t * n + s], sum);
-            tq[r] = sum;
-        }
-        __syncthreads();
-        for (int r = tid; r < 12 * Q2; r += nth) {  // along t
-            const int slot = r / Q2, qs = r % Q, qt = (r / Q) % Q;
-            double sum = 0.0;
+            for (int s = 0; s < n; ++s) x[s] = src ? src[layer_node<n>(d, lay, s, t)] : 0.0;
+            to_gauss<P>(T, x, y);
 #pragma unroll
-            for (int t = 0; t < n; ++t) sum = fma(tB[(qt) * n + (t)], tq[slot * n * Q + t * Q + qs], sum);
-            tg[r] = sum;
+            for (int q = 0; q < Q; ++q) tq[(slot * n + t) * Q + q] = y[q];
         }
         __syncthreads();
-        for (int r = tid; r < 2 * Q2; r += nth) {
+        for (int r = tid; r < 12 * Q; r += NT) {  // along t
+            const int slot = r / Q, qs = r % Q;
+            double x[n], y[Q];
+#pragma unroll
+            for (int t = 0; t < n; ++t) x[t] = tq[(slot * n + t) * Q + qs];
+            to_gauss<P>(T, x, y);
+#pragma unroll
+            for (int q = 0; q < Q; ++q) tg[(slot * Q + q) * Q + qs] = y[q];
+        }
+        __syncthreads();
+        for (int r = tid; r < 2 * Q2; r += NT) {  // the fluxes, weighted
             const int side = r / Q2, q = r % Q2, qs = q % Q, qt = q / Q;
             const double sgn = side ? 1.0 : -1.0;
             const double *own = tg + side * 6 * Q2, *ext = own + 3 * Q2;
@@ -270,26 +447,30 @@ __global__ void __launch_bounds__(256) k_convection(ConvArgs A)
             }
         }
         __syncthreads();
-        for (int r = tid; r < 6 * Q * n; r += nth) {  // back along s: hq[side*3+i][qt][s]
-            const int slot = r / (Q * n), s = r % n, qt = (r / n) % Q;
-            double sum = 0.0;
+        for (int r = tid; r < 6 * Q; r += NT) {  // back along s: hq[side*3+i][qt][s]
+            const int slot = r / Q, qt = r % Q;
+            double x[Q], y[n];
 #pragma unroll
-            for (int qs = 0; qs < Q; ++qs) sum = fma(tB[(qs) * n + (s)], hw[slot * Q2 + qt * Q + qs], sum);
-            hq[r] = sum;
+            for (int q = 0; q < Q; ++q) x[q] = hw[(slot * Q + qt) * Q + q];
+            to_nodes<P>(T, x, y);
+#pragma unroll
+            for (int s = 0; s < n; ++s) hq[(slot * Q + qt) * n + s] = y[s];
         }
         __syncthreads();
-        for (int r = tid; r < 6 * n * n; r += nth) {  // back along t onto the two face layers
-            const int slot = r / (n * n), s = r % n, t = (r / n) % n;
+        for (int r = tid; r < 6 * n; r += NT) {  // back along t onto the two face layers
+            const int slot = r / n, s = r % n;
             const int side = slot / 3, i = slot % 3;
-            double sum = 0.0;
+            double x[Q], y[n];
 #pragma unroll
-            for (int qt = 0; qt < Q; ++qt) sum = fma(tB[(qt) * n + (t)], hq[slot * Q * n + qt * n + s], sum);
-            acc[i][layer_node<n>(d, side ? n - 1 : 0, s, t)] += sum;
+            for (int q = 0; q < Q; ++q) x[q] = hq[(slot * Q + q) * n + s];
+            to_nodes<P>(T, x, y);
+#pragma unroll
+            for (int t = 0; t < n; ++t) acc[i][layer_node<n>(d, side ? n - 1 : 0, s, t)] += y[t];
         }
     }
     __syncthreads();
-    for (int r = tid; r < n3; r += nth) {
-        const int a = r % n, b = (r / n) % n, c = r / (n * n);
+    for (int r = tid; r < n3; r += NT) {
+        const int a = r % n, b = (r / n) % n, c = r / n2;
         const double f = A.scale / (J * tw[a] * tw[b] * tw[c]);
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
@@ -299,70 +480,12 @@ __global__ void __launch_bounds__(256) k_convection(ConvArgs A)
     }
 }
 
-// Gauss-Legendre nodes and weights on [-1, 1] by Newton's method on P_Q
-// (three-term recurrence for P_Q and its derivative), started from the
-// Chebyshev-like guesses cos(pi (j + 3/4) / (Q + 1/2)).
-void gauss_legendre(int Q, double *x, double *w)
-{
-    for (int j = 0; j < Q; ++j) {
-        double z = std::cos(M_PI * (j + 0.75) / (Q + 0.5)), dp = 1.0;
-        for (int it = 0; it < 100; ++it) {
-            double p0 = 1.0, p1 = z;
-            for (int k = 2; k <= Q; ++k) {
-                const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
-                p0 = p1;
-                p1 = p2;
-            }
-            if (Q == 1) p0 = 1.0;
-            dp = Q * (z * p1 - p0) / (z * z - 1.0);
-            const double dz = p1 / dp;
-            z -= dz;
-            if (std::fabs(dz) < 1e-16) break;
-        }
-        double p0 = 1.0, p1 = z;
-        for (int k = 2; k <= Q; ++k) {
-            const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
-            p0 = p1;
-            p1 = p2;
-        }
-        dp = Q * (z * p1 - p0) / (z * z - 1.0);
-        x[Q - 1 - j] = z;
-        w[Q - 1 - j] = 2.0 / ((1.0 - z * z) * dp * dp);
-    }
-}
-
-ConvTables make_conv_tables(int P)
-{
-    ConvTables t{};
-    const GllTables &g = gll_cached(P);
-    const int n = P + 1, Q = conv_q(P);
-    double xg[kMaxQ];
-    gauss_legendre(Q, xg, t.wg);
-    for (int a = 0; a < n; ++a) t.w[a] = g.w[a];
-    for (int q = 0; q < Q; ++q) {
-        const double x = xg[q];
-        for (int a = 0; a < n; ++a) {
-            double l = 1.0, dl = 0.0;
-            for (int k = 0; k < n; ++k) {
-                if (k == a) continue;
-                const double r = 1.0 / (g.xi[a] - g.xi[k]);
-                dl = dl * (x - g.xi[k]) * r + l * r;
-                l *= (x - g.xi[k]) * r;
-            }
-            t.B[q][a] = l;
-            t.dB[q][a] = dl;
-        }
-    }
-    return t;
-}
-
 }  // namespace
 
 int launch_convection(const MeshDev &m, const double *const v[3], const double *const vb[3], double scale,
                       bool accumulate, double *const out[3], hipStream_t s)
 {
     ConvArgs a{};
-    a.t = make_conv_tables(m.P);
     for (int d = 0; d < 3; ++d) {
         a.v[d] = v[d];
         a.vb[d] = vb ? vb[d] : nullptr;
