@@ -372,10 +372,14 @@ int dg_viscous_fd2(dg_mesh *m, const double *nu, const double *vx, const double 
    the exterior state of the convective flux.  final_projection: 1 to end
    with the projection with d_n psi = 0 (for variable viscosity).  opts: the
    options of every pressure and velocity solve (NULL: defaults; DG_PC_FDM
-   recommended; the velocity solves start from v''_i).  Allocates the mesh's
-   step workspace (about (9 s' + 15) N doubles, s' the stages whose terms the
-   tableau uses) at first use; synchronous.  Returns the first error of a
-   kernel or solve, else info->status. */
+   recommended; the velocity solves start from v''_i).  With DG_PC_FDM the
+   three velocity solves of a stage, which share their operator, run at once
+   on the mesh's stream and two more streams (non-blocking, default
+   priority), each with its own FP64 solve workspace; the streams and
+   workspaces are created at first use and kept with the mesh.  Allocates
+   the mesh's step workspace (about (9 s' + 14) N doubles, s' the stages
+   whose terms the tableau uses) at first use; synchronous.  Returns the
+   first error of a kernel or solve, else info->status. */
 int dg_imex_step(dg_mesh *mv, dg_mesh *mp, const dg_tableau *tab, double dt, double nu0, double nu1,
                  double vref, double *vx, double *vy, double *vz, const double *const *forcing,
                  const double *const *wall, int final_projection, const dg_solve_opts *opts,

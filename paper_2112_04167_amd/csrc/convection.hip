@@ -111,16 +111,16 @@ template <int P>
 struct ConvLds {
     static constexpr int n = P + 1, Q = conv_q(P);
     // region A: the first interpolation pass Y1[3][n^2 Q], then the velocity
-    // at the Gauss points U[3][Q^3], then the face points' traces
-    // tg[12][Q^2] and weighted fluxes hw[6][Q^2]
-    static constexpr int vol = 3 * Q * Q * Q, fa = 18 * Q * Q;
-    static constexpr int A = vol > fa ? vol : fa;
-    // region S: the second interpolation pass Y2[3][n Q^2], then the
-    // transposed passes Z[3][n Q^2], Yb[2][n^2 Q], then the face buffers
-    // tq[12][n Q], hq[6][Q n]
-    static constexpr int s_bk = 3 * n * Q * Q + 2 * n * n * Q;
-    static constexpr int s_fc = 18 * n * Q;
-    static constexpr int S = s_bk > s_fc ? s_bk : s_fc;
+    // at the Gauss points U[3][Q^3]
+    static constexpr int A = 3 * Q * Q * Q;
+    // region S, after A: the second interpolation pass Y2[3][n Q^2], then the
+    // transposed passes Z[3][n Q^2], Yb[2][n^2 Q]
+    static constexpr int S = 3 * n * Q * Q + 2 * n * n * Q;
+    // the face passes, all three axes at once: tg[3][12][Q^2] with, after
+    // it, tq[3][12][n Q] and later hw[3][6][Q^2]; then hq[3][6][Q n] and
+    // FB[3][6][n^2] from the start
+    static constexpr int F = 36 * Q * Q + (36 * n * Q > 18 * Q * Q ? 36 * n * Q : 18 * Q * Q);
+    static constexpr int ARENA = A + S > F ? A + S : F;
 };
 
 __device__ __forceinline__ int nb_index(int k, int nk, int bc, bool high)
@@ -273,8 +273,8 @@ __global__ void __launch_bounds__(256) k_convection(ConvArgs A)
     constexpr int WZ = (Q2 + 63) / 64 * 64;    // thread slots per half of a pass, whole waves
     constexpr int WY = (n * Q + 63) / 64 * 64;
     constexpr int WX = (n2 + 63) / 64 * 64;
-    __shared__ double bufA[L::A];
-    __shared__ double bufS[L::S];
+    __shared__ double arena[L::ARENA];
+    double *bufA = arena, *bufS = arena + L::A;
     __shared__ double acc[3][n3];
     // the weights used with lane-dependent indices
     __shared__ double twg[Q], tw[n];
@@ -380,93 +380,91 @@ __global__ void __launch_bounds__(256) k_convection(ConvArgs A)
         }
     }
 
-    // ---- faces: acc_i -= int_F H_i phi, both faces of an axis at once.
-    //      Slots: side * 6 + (own v_0..2, exterior v_0..2); side 0 the low
-    //      face, 1 the high one.
-    double *tq = bufS;               // [12][n][Q]: face lines along s at the Gauss points (t, qs)
-    double *hq = bufS + 12 * n * Q;  // [6][Q][n]: side * 3 + i, (qt, s)
-    double *tg = bufA;               // [12][Q][Q]: (qt, qs)
-    double *hw = bufA + 12 * Q2;     // [6][Q][Q]
-    for (int d = 0; d < 3; ++d) {
-        const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-        const double om0 = hh[t1] * hh[t2] * 0.25;
-        // tq of this axis overwrites what the previous axis's second pass
-        // read (three barriers ago); at d = 0 it overwrites the volume's Yb
-        if (d == 0) __syncthreads();
-        for (int r = tid; r < 12 * n; r += NT) {  // the face lines along s, to the Gauss points
-            const int slot = r / n, t = r % n;
-            const bool high = slot >= 6;
-            const int comp = slot % 6, c3 = comp % 3;
-            const int layer = high ? n - 1 : 0;
-            const double *src = nullptr;
-            int lay = layer;
-            if (comp < 3) {
-                src = (c3 == 0 ? A.v[0] : c3 == 1 ? A.v[1] : A.v[2]) + base;
+    // ---- faces: acc_i -= int_F H_i phi, the six faces at once.  Slots:
+    //      side * 6 + (own v_0..2, exterior v_0..2) per axis d, side 0 the
+    //      low face and 1 the high one.  The two face layers of each axis
+    //      receive their contributions in FB, added to acc in the output
+    //      pass (the layers of different axes share edge nodes).
+    constexpr int FS = 36 * Q2;                  // tg [3][12][Q][Q], then hq [3][6][Q][n] and FB
+    double *tg = arena;                          // (qt, qs)
+    double *tq = arena + FS;                     // [3][12][n][Q]: (t, qs)
+    double *hw = arena + FS;                     // [3][6][Q][Q], after tq
+    double *hq = arena;                          // [3][6][Q][n], after tg: (qt, s)
+    double *FB = arena + 18 * Q * n;             // [3][6][n][n]: (t, s)
+    __syncthreads();  // tq overwrites the volume's Yb
+    for (int r = tid; r < 36 * n; r += NT) {  // the face lines along s, to the Gauss points
+        const int d = r / (12 * n), slot = (r / n) % 12, t = r % n;
+        const bool high = slot >= 6;
+        const int comp = slot % 6, c3 = comp % 3;
+        const double *src = nullptr;
+        int lay = high ? n - 1 : 0;
+        if (comp < 3) {
+            src = (c3 == 0 ? A.v[0] : c3 == 1 ? A.v[1] : A.v[2]) + base;
+        } else {
+            const int kn = nb_index(e3[d], A.n[d], A.bc[d], high);
+            if (kn >= 0) {
+                int en[3] = {ex, ey, ez};
+                en[d] = kn;
+                src = (c3 == 0 ? A.v[0] : c3 == 1 ? A.v[1] : A.v[2]) +
+                      ((size_t)(en[2] * A.n[1] + en[1]) * A.n[0] + en[0]) * n3;
+                lay = high ? 0 : n - 1;
             } else {
-                const int kn = nb_index(e3[d], A.n[d], A.bc[d], high);
-                if (kn >= 0) {
-                    int en[3] = {ex, ey, ez};
-                    en[d] = kn;
-                    src = (c3 == 0 ? A.v[0] : c3 == 1 ? A.v[1] : A.v[2]) +
-                          ((size_t)(en[2] * A.n[1] + en[1]) * A.n[0] + en[0]) * n3;
-                    lay = high ? 0 : n - 1;
-                } else {
-                    const double *wb = c3 == 0 ? A.vb[0] : c3 == 1 ? A.vb[1] : A.vb[2];
-                    src = wb ? wb + base : nullptr;
-                }
-            }
-            double x[n], y[Q];
-#pragma unroll
-            for (int s = 0; s < n; ++s) x[s] = src ? src[layer_node<n>(d, lay, s, t)] : 0.0;
-            to_gauss<P>(T, x, y);
-#pragma unroll
-            for (int q = 0; q < Q; ++q) tq[(slot * n + t) * Q + q] = y[q];
-        }
-        __syncthreads();
-        for (int r = tid; r < 12 * Q; r += NT) {  // along t
-            const int slot = r / Q, qs = r % Q;
-            double x[n], y[Q];
-#pragma unroll
-            for (int t = 0; t < n; ++t) x[t] = tq[(slot * n + t) * Q + qs];
-            to_gauss<P>(T, x, y);
-#pragma unroll
-            for (int q = 0; q < Q; ++q) tg[(slot * Q + q) * Q + qs] = y[q];
-        }
-        __syncthreads();
-        for (int r = tid; r < 2 * Q2; r += NT) {  // the fluxes, weighted
-            const int side = r / Q2, q = r % Q2, qs = q % Q, qt = q / Q;
-            const double sgn = side ? 1.0 : -1.0;
-            const double *own = tg + side * 6 * Q2, *ext = own + 3 * Q2;
-            const double vm = sgn * own[d * Q2 + q], vp = sgn * ext[d * Q2 + q];
-            const double alpha = 2.0 * fmax(fabs(vm), fabs(vp));
-            const double om = om0 * twg[qs] * twg[qt];
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                const double um = own[i * Q2 + q], up = ext[i * Q2 + q];
-                hw[(side * 3 + i) * Q2 + q] = -om * (0.5 * (vm * um + vp * up) + 0.5 * alpha * (um - up));
+                const double *wb = c3 == 0 ? A.vb[0] : c3 == 1 ? A.vb[1] : A.vb[2];
+                src = wb ? wb + base : nullptr;
             }
         }
-        __syncthreads();
-        for (int r = tid; r < 6 * Q; r += NT) {  // back along s: hq[side*3+i][qt][s]
-            const int slot = r / Q, qt = r % Q;
-            double x[Q], y[n];
+        double x[n], y[Q];
 #pragma unroll
-            for (int q = 0; q < Q; ++q) x[q] = hw[(slot * Q + qt) * Q + q];
-            to_nodes<P>(T, x, y);
+        for (int s = 0; s < n; ++s) x[s] = src ? src[layer_node<n>(d, lay, s, t)] : 0.0;
+        to_gauss<P>(T, x, y);
 #pragma unroll
-            for (int s = 0; s < n; ++s) hq[(slot * Q + qt) * n + s] = y[s];
+        for (int q = 0; q < Q; ++q) tq[r * Q + q] = y[q];
+    }
+    __syncthreads();
+    for (int r = tid; r < 36 * Q; r += NT) {  // along t: line (d, slot, qs)
+        const int ds = r / Q, qs = r % Q;
+        double x[n], y[Q];
+#pragma unroll
+        for (int t = 0; t < n; ++t) x[t] = tq[(ds * n + t) * Q + qs];
+        to_gauss<P>(T, x, y);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) tg[(ds * Q + q) * Q + qs] = y[q];
+    }
+    __syncthreads();
+    for (int r = tid; r < 6 * Q2; r += NT) {  // the fluxes, weighted: point (d, side, q)
+        const int ds = r / Q2, q = r % Q2, qs = q % Q, qt = q / Q;
+        const int d = ds / 2, side = ds % 2;
+        const double om0 = (d == 0 ? hh[1] * hh[2] : d == 1 ? hh[0] * hh[2] : hh[0] * hh[1]) * 0.25;
+        const double sgn = side ? 1.0 : -1.0;
+        const double *own = tg + (d * 12 + side * 6) * Q2, *ext = own + 3 * Q2;
+        const double vm = sgn * own[d * Q2 + q], vp = sgn * ext[d * Q2 + q];
+        const double alpha = 2.0 * fmax(fabs(vm), fabs(vp));
+        const double om = om0 * twg[qs] * twg[qt];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const double um = own[i * Q2 + q], up = ext[i * Q2 + q];
+            hw[(ds * 3 + i) * Q2 + q] = -om * (0.5 * (vm * um + vp * up) + 0.5 * alpha * (um - up));
         }
-        __syncthreads();
-        for (int r = tid; r < 6 * n; r += NT) {  // back along t onto the two face layers
-            const int slot = r / n, s = r % n;
-            const int side = slot / 3, i = slot % 3;
-            double x[Q], y[n];
+    }
+    __syncthreads();
+    for (int r = tid; r < 18 * Q; r += NT) {  // back along s: line (d, side*3+i, qt)
+        const int slot = r / Q, qt = r % Q;
+        double x[Q], y[n];
 #pragma unroll
-            for (int q = 0; q < Q; ++q) x[q] = hq[(slot * Q + q) * n + s];
-            to_nodes<P>(T, x, y);
+        for (int q = 0; q < Q; ++q) x[q] = hw[(slot * Q + qt) * Q + q];
+        to_nodes<P>(T, x, y);
 #pragma unroll
-            for (int t = 0; t < n; ++t) acc[i][layer_node<n>(d, side ? n - 1 : 0, s, t)] += y[t];
-        }
+        for (int s = 0; s < n; ++s) hq[(slot * Q + qt) * n + s] = y[s];
+    }
+    __syncthreads();
+    for (int r = tid; r < 18 * n; r += NT) {  // back along t onto the face layers: line (d, side*3+i, s)
+        const int slot = r / n, s = r % n;
+        double x[Q], y[n];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) x[q] = hq[(slot * Q + q) * n + s];
+        to_nodes<P>(T, x, y);
+#pragma unroll
+        for (int t = 0; t < n; ++t) FB[(slot * n + t) * n + s] = y[t];
     }
     __syncthreads();
     for (int r = tid; r < n3; r += NT) {
@@ -474,7 +472,11 @@ __global__ void __launch_bounds__(256) k_convection(ConvArgs A)
         const double f = A.scale / (J * tw[a] * tw[b] * tw[c]);
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            const double val = f * acc[i][r];
+            double sum = acc[i][r];
+            if (a == 0 || a == n - 1) sum += FB[((0 * 6 + (a ? 3 : 0) + i) * n + c) * n + b];
+            if (b == 0 || b == n - 1) sum += FB[((1 * 6 + (b ? 3 : 0) + i) * n + c) * n + a];
+            if (c == 0 || c == n - 1) sum += FB[((2 * 6 + (c ? 3 : 0) + i) * n + b) * n + a];
+            const double val = f * sum;
             A.out[i][base + r] = A.accumulate ? A.out[i][base + r] + val : val;
         }
     }

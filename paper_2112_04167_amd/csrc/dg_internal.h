@@ -93,4 +93,16 @@ const MeshDev *mesh_device(dg_mesh *m);
 hipStream_t mesh_stream(dg_mesh *m);
 double *mesh_step_buffer(dg_mesh *m, size_t doubles);
 
+// Up to kMaxConcurrent FP64 solves preconditioned by fast diagonalisation,
+// of one Helmholtz operator (lambda, nu field or nu_c, the mesh's BCs) with
+// different right-hand sides rhs[k] (weak[k]: a weak load) and initial
+// guesses / solutions x[k], run at once on separate streams from this
+// thread (solver.cpp).  The first runs on the mesh's stream; the others
+// start after the work enqueued there so far.  Returns when all have ended,
+// with the worst status; info[k] per solve.  Options are not checked here.
+constexpr int kMaxConcurrent = 3;
+int solve_fdm_concurrent(dg_mesh *m, int nsys, double lambda, const double *nu, double nu_c,
+                         const double *const *rhs, double *const *x, const int *weak,
+                         const dg_solve_opts &o, dg_solve_info *info);
+
 }  // namespace dg

@@ -312,18 +312,19 @@ int dg_imex_step(dg_mesh *mv, dg_mesh *mp, const dg_tableau *tab, double dt, dou
         if (tab->bE[j] - aE(s - 1, j) != 0.0) needC[j] = 1;
         if (tab->bI[j] - aI(s - 1, j) != 0.0) needD1[j] = 1;
     }
-    // workspace: stage velocity (3N), load (N), nu (N), F_d2 scratch (9N),
-    // weak scratch (N), per used stage C, D1, D3 (9N), the pressure (Np)
+    // workspace: stage velocity (3N), nu (N), F_d2 scratch and the three
+    // Helmholtz loads (9N), weak scratch (N), per used stage C, D1, D3 (9N),
+    // the pressure (Np)
     const size_t N = (size_t)md.ndof, Np = (size_t)mesh_device(mp)->ndof;
     std::vector<int> slot(s, -1);
     int nslots = 0;
     for (int j = 0; j < s; ++j)
         if (needC[j] || needD1[j]) slot[j] = nslots++;
-    double *buf = mesh_step_buffer(mv, (15 + 9 * (size_t)nslots) * N + Np);
+    double *buf = mesh_step_buffer(mv, (14 + 9 * (size_t)nslots) * N + Np);
     if (!buf) return DG_ERR_OOM;
     double *Vi[3] = {buf, buf + N, buf + 2 * N};
-    double *G = buf + 3 * N, *nu = buf + 4 * N, *T = buf + 5 * N, *weak = buf + 14 * N;
-    double *terms = buf + 15 * N, *psi = terms + 9 * (size_t)nslots * N;
+    double *nu = buf + 3 * N, *T = buf + 4 * N, *weak = buf + 13 * N;
+    double *terms = buf + 14 * N, *psi = terms + 9 * (size_t)nslots * N;
     auto C = [&](int j, int d) { return terms + ((size_t)slot[j] * 9 + d) * N; };
     auto D1 = [&](int j, int d) { return terms + ((size_t)slot[j] * 9 + 3 + d) * N; };
     auto D3 = [&](int j, int d) { return terms + ((size_t)slot[j] * 9 + 6 + d) * N; };
@@ -341,6 +342,12 @@ int dg_imex_step(dg_mesh *mv, dg_mesh *mp, const dg_tableau *tab, double dt, dou
     dg_default_opts(&o);
     if (opts) o = *opts;
     o.rhs_is_weak = 0;
+    if (!(o.tol > 0.0) || o.maxit < 0 || (o.precision != DG_FP64 && o.precision != DG_MIXED) ||
+        (o.precond != DG_PC_JACOBI && o.precond != DG_PC_FDM) ||
+        (o.precond == DG_PC_FDM && o.precision != DG_FP64)) {
+        set_error("bad solver options");
+        return DG_ERR_ARG;
+    }
     int rc;
 
     auto stage_terms = [&](int j, const double *const v[3]) -> int {
@@ -408,9 +415,14 @@ int dg_imex_step(dg_mesh *mv, dg_mesh *mp, const dg_tableau *tab, double dt, dou
         const double *const *vbi = walls(i, wb);
         if ((rc = project(Vi, vbi, false))) return rc;
         if ((rc = launch_viscosity(md, Vi, nu0, nu1, vref, nu, sv))) return rc;
-        // load and Helmholtz solve per component
+        // load and Helmholtz solve per component.  The three loads go to
+        // the F_d2 scratch T (free until this stage's terms), and with the
+        // fast-diagonalisation preconditioner the three solves, which share
+        // their operator, run at once on separate streams.
         const double aii = aI(i, i);
         const double lam = aii > 0.0 ? 1.0 / (dt * aii) : 1.0;
+        double *Gd[3] = {T, T + N, T + 2 * N};
+        int weakd[3] = {0, 0, 0};
         for (int d = 0; d < 3; ++d) {
             coef.clear();
             xs.clear();
@@ -428,23 +440,38 @@ int dg_imex_step(dg_mesh *mv, dg_mesh *mp, const dg_tableau *tab, double dt, dou
                 }
             }
             if (aii > 0.0) {
-                if ((rc = launch_lincomb(N, nullptr, (int)coef.size(), coef.data(), xs.data(), G, sv))) return rc;
-                dg_solve_opts od = o;
+                if ((rc = launch_lincomb(N, nullptr, (int)coef.size(), coef.data(), xs.data(), Gd[d], sv)))
+                    return rc;
                 if (has_dirichlet && vbi && vbi[d]) {
                     // weak load M (lambda g) + L_nu(v_b): the wall data as Dirichlet data
-                    if ((rc = launch_mass(md, G, 1.0, false, G, sv))) return rc;
-                    if ((rc = launch_dirichlet_load(md, md.bc, nu, 0.0, vbi[d], 1.0, G, sv))) return rc;
-                    od.rhs_is_weak = 1;
+                    if ((rc = launch_mass(md, Gd[d], 1.0, false, Gd[d], sv))) return rc;
+                    if ((rc = launch_dirichlet_load(md, md.bc, nu, 0.0, vbi[d], 1.0, Gd[d], sv))) return rc;
+                    weakd[d] = 1;
                 }
-                dg_solve_info hi{};
-                rc = helmholtz_solve(mv, lam, nu, 0.0, G, Vi[d], &od, &hi);
-                if (rc < 0) return rc;
-                st.solves += 1;
-                st.velocity_iters += hi.iters;
-                if (rc > st.status) st.status = rc;
             } else {  // no implicit term in this stage: v_i = g_i
                 if ((rc = launch_lincomb(N, Vi[d], (int)coef.size() - 1, coef.data() + 1, xs.data() + 1, Vi[d], sv)))
                     return rc;
+            }
+        }
+        if (aii > 0.0) {
+            dg_solve_info hi[3] = {};
+            if (o.precond == DG_PC_FDM && o.precision == DG_FP64) {
+                rc = solve_fdm_concurrent(mv, 3, lam, nu, 0.0, Gd, Vi, weakd, o, hi);
+                if (rc < 0) return rc;
+                if (rc > st.status) st.status = rc;
+            } else {
+                for (int d = 0; d < 3; ++d) {
+                    dg_solve_opts od = o;
+                    od.rhs_is_weak = weakd[d];
+                    rc = helmholtz_solve(mv, lam, nu, 0.0, Gd[d], Vi[d], &od, &hi[d]);
+                    if (rc < 0) return rc;
+                    if (rc > st.status) st.status = rc;
+                }
+            }
+            for (int d = 0; d < 3; ++d) {
+                st.solves += 1;
+                st.velocity_iters += hi[d].iters;
+                if (hi[d].status > st.status) st.status = hi[d].status;
             }
         }
         if ((rc = stage_terms(i, Vi))) return rc;

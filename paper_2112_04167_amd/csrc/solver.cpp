@@ -82,6 +82,11 @@ struct dg_mesh {
     double *aux = nullptr;      // device: the projection's pressure load (ndof doubles)
     double *step_buf = nullptr; // device: the IMEX step's stage fields (grow-only)
     size_t step_doubles = 0;
+    // concurrent solves: the workspaces and streams of the second and third
+    // solve (created on first use), and the event the streams start from
+    Workspace alt_ws[kMaxConcurrent - 1];
+    hipStream_t alt_stream[kMaxConcurrent - 1] = {};
+    hipEvent_t alt_event = nullptr;
 };
 
 namespace {
@@ -387,69 +392,129 @@ int ensure_fdm_tables(dg_mesh *m, Workspace &w, const int bc[3], FdmDev &f)
 // after one or two steps (rounding); for a nodal nu the preconditioner uses
 // nu_ref = sqrt(min nu * max nu), which bounds the preconditioned condition
 // number by max nu / min nu.
-int solve_fdm(dg_mesh *m, Workspace &w, const int bc[3], double lambda, const double *nu,
-              double nu_c, const double *rhs, double *x, const dg_solve_opts &o, dg_solve_info &info)
+//
+// The solve is split into phases (prepare, start, chunks of iterations with a
+// poll of the device state after each, end) so that one host thread can run
+// several such solves at once on separate streams; each solve does the same
+// arithmetic whether it runs alone or beside others.
+struct FdmRun {
+    Workspace *w = nullptr;
+    hipStream_t s = nullptr;
+    const int *bc = nullptr;
+    double lambda = 0.0, nu_c = 0.0, nu_ref = 0.0;
+    const double *nu = nullptr, *rhs = nullptr;
+    double *x = nullptr;
+    bool singular = false, done = false;
+    FdmDev f{};
+    CgVecArgs<double> a{};
+    int cap = 0, chunk = 2, launched = 0;
+};
+
+// nu_ref of the preconditioner (one host synchronisation for a nodal nu)
+int fdm_nu_ref(dg_mesh *m, Workspace &w, const double *nu, double nu_c, double &nu_ref)
 {
-    int rc = ensure_workspace(m, w, DG_FP64);
-    if (rc) return rc;
-    const MeshDev &md = m->dev;
-    hipStream_t s = m->stream;
-    const bool singular = (lambda == 0.0) && !has_dirichlet(bc);
-    FdmDev f;
-    if ((rc = ensure_fdm_tables(m, w, bc, f))) return rc;
-    double nu_ref = nu_c;
-    if (nu) {
-        double lo = 0.0, hi = 0.0;
-        if ((rc = field_range(nu, (size_t)md.ndof, w.partial, partial_doubles(md), lo, hi, s))) return rc;
-        if (!(lo > 0.0) || !std::isfinite(hi)) {
-            set_error("the fast-diagonalisation preconditioner needs a positive, finite nu field");
-            return lo != lo || hi != hi ? DG_ERR_NONFINITE : DG_ERR_ARG;
-        }
-        nu_ref = std::sqrt(lo * hi);
+    nu_ref = nu_c;
+    if (!nu) return DG_OK;
+    double lo = 0.0, hi = 0.0;
+    if (int rc = field_range(nu, (size_t)m->dev.ndof, w.partial, partial_doubles(m->dev), lo, hi, m->stream))
+        return rc;
+    if (!(lo > 0.0) || !std::isfinite(hi)) {
+        set_error("the fast-diagonalisation preconditioner needs a positive, finite nu field");
+        return lo != lo || hi != hi ? DG_ERR_NONFINITE : DG_ERR_ARG;
     }
-    *w.host_sc = init_scalars(md, o.tol, o.maxit, o.fixed_iters, singular);
+    nu_ref = std::sqrt(lo * hi);
+    return DG_OK;
+}
+
+// the workspace and its tables (uploads on the mesh's stream)
+int fdm_prepare(dg_mesh *m, FdmRun &R)
+{
+    if (int rc = ensure_workspace(m, *R.w, DG_FP64)) return rc;
+    return ensure_fdm_tables(m, *R.w, R.bc, R.f);
+}
+
+// b, r = b - A x from the caller's x, the first preconditioned direction
+int fdm_start(dg_mesh *m, FdmRun &R, const dg_solve_opts &o)
+{
+    const MeshDev &md = m->dev;
+    Workspace &w = *R.w;
+    hipStream_t s = R.s;
+    int rc;
+    R.singular = (R.lambda == 0.0) && !has_dirichlet(R.bc);
+    *w.host_sc = init_scalars(md, o.tol, o.maxit, o.fixed_iters, R.singular);
     DG_HIP_CHECK(hipMemcpyAsync(w.sc, w.host_sc, sizeof(CgScalars), hipMemcpyHostToDevice, s));
-    CgVecArgs<double> a = vec_args<double>(w, singular, w.sc);
-    a.x = x;
+    CgVecArgs<double> &a = R.a;
+    a = vec_args<double>(w, R.singular, w.sc);
+    a.x = R.x;
     a.r = w.r64;
     a.p = w.p64;
     a.q = w.q64;
     a.z = w.d64;  // the diagonal slot holds z (no Jacobi diagonal here)
-    a.src = rhs;
+    a.src = R.rhs;
     a.bvec = w.b64;
     a.weak = o.rhs_is_weak;
     a.keep_x = 1;
     if ((rc = cg_setup<double>(md, a, s))) return rc;  // b, norms (no diagonal: d, dtab null)
     // r = b - A x from the caller's x, its norm and the stopping test
-    if ((rc = launch_resid<double>(md, bc, lambda, nu, nu_c, x, w.b64, w.r64, w.partial, w.sc, s)))
+    if ((rc = launch_resid<double>(md, R.bc, R.lambda, R.nu, R.nu_c, R.x, w.b64, w.r64, w.partial, w.sc, s)))
         return rc;
     if ((rc = cg_fdm_start(md, a, s))) return rc;
-    if ((rc = fdm_apply(md, f, lambda, nu_ref, singular, w.r64, w.d64, w.q64, w.sc, s))) return rc;
+    if ((rc = fdm_apply(md, R.f, R.lambda, R.nu_ref, R.singular, w.r64, w.d64, w.q64, w.sc, s))) return rc;
     if ((rc = cg_rz(md, a, true, s))) return rc;
     if ((rc = cg_pupdate_fdm(md, a, true, s))) return rc;
-    const int cap = o.fixed_iters > 0 ? o.fixed_iters : o.maxit;
-    int chunk = 2, launched = 0;
-    for (;;) {
-        for (int k = 0; k < chunk; ++k) {
-            if ((rc = launch_apply_cg<double>(md, bc, lambda, nu, nu_c, a.p, w.q64, w.partial, w.sc, s)))
-                return rc;
-            if ((rc = cg_update_fdm(md, a, s))) return rc;
-            if ((rc = fdm_apply(md, f, lambda, nu_ref, singular, w.r64, w.d64, w.q64, w.sc, s))) return rc;
-            if ((rc = cg_rz(md, a, false, s))) return rc;
-            if ((rc = cg_pupdate_fdm(md, a, false, s))) return rc;
-        }
-        launched += chunk;
-        DG_HIP_CHECK(hipMemcpyAsync(w.host_sc, w.sc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
-        DG_HIP_CHECK(hipStreamSynchronize(s));
-        if (w.host_sc->done) break;
-        if (launched > cap + 64) {
-            set_error("CG did not flag completion");
-            return DG_ERR_DEVICE;
-        }
-        chunk = std::min(chunk * 2, 16);
+    R.cap = o.fixed_iters > 0 ? o.fixed_iters : o.maxit;
+    R.chunk = 2;
+    R.launched = 0;
+    R.done = false;
+    return DG_OK;
+}
+
+// one chunk of iterations (they do nothing once the device has flagged
+// completion) and the copy of the device state back to the host
+int fdm_chunk(dg_mesh *m, FdmRun &R)
+{
+    const MeshDev &md = m->dev;
+    Workspace &w = *R.w;
+    hipStream_t s = R.s;
+    int rc;
+    for (int k = 0; k < R.chunk; ++k) {
+        if ((rc = launch_apply_cg<double>(md, R.bc, R.lambda, R.nu, R.nu_c, R.a.p, w.q64, w.partial, w.sc, s)))
+            return rc;
+        if ((rc = cg_update_fdm(md, R.a, s))) return rc;
+        if ((rc = fdm_apply(md, R.f, R.lambda, R.nu_ref, R.singular, w.r64, w.d64, w.q64, w.sc, s))) return rc;
+        if ((rc = cg_rz(md, R.a, false, s))) return rc;
+        if ((rc = cg_pupdate_fdm(md, R.a, false, s))) return rc;
     }
-    if ((rc = cg_finish<double>(md, a, s))) return rc;
-    if ((rc = launch_resid<double>(md, bc, lambda, nu, nu_c, x, w.b64, w.q64, w.partial, w.sc, s)))
+    R.launched += R.chunk;
+    DG_HIP_CHECK(hipMemcpyAsync(w.host_sc, w.sc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
+    return DG_OK;
+}
+
+// wait for the chunk; R.done once the device has flagged completion
+int fdm_poll(FdmRun &R)
+{
+    DG_HIP_CHECK(hipStreamSynchronize(R.s));
+    if (R.w->host_sc->done) {
+        R.done = true;
+        return DG_OK;
+    }
+    if (R.launched > R.cap + 64) {
+        set_error("CG did not flag completion");
+        return DG_ERR_DEVICE;
+    }
+    R.chunk = std::min(R.chunk * 2, 16);
+    return DG_OK;
+}
+
+// the singular mean shift, the true residual, and the result
+int fdm_end(dg_mesh *m, FdmRun &R, dg_solve_info &info)
+{
+    const MeshDev &md = m->dev;
+    Workspace &w = *R.w;
+    hipStream_t s = R.s;
+    int rc;
+    if ((rc = cg_finish<double>(md, R.a, s))) return rc;
+    if ((rc = launch_resid<double>(md, R.bc, R.lambda, R.nu, R.nu_c, R.x, w.b64, w.q64, w.partial, w.sc, s)))
         return rc;
     DG_HIP_CHECK(hipMemcpyAsync(w.host_sc, w.sc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
     DG_HIP_CHECK(hipStreamSynchronize(s));
@@ -460,6 +525,94 @@ int solve_fdm(dg_mesh *m, Workspace &w, const int bc[3], double lambda, const do
     info.rel_res = h.bnorm2 > 0 ? std::sqrt(h.res2 / h.bnorm2) : 0.0;
     info.true_rel_res = h.bnorm2 > 0 ? std::sqrt(h.true_res2 / h.bnorm2) : 0.0;
     return h.status;
+}
+
+int solve_fdm(dg_mesh *m, Workspace &w, const int bc[3], double lambda, const double *nu,
+              double nu_c, const double *rhs, double *x, const dg_solve_opts &o, dg_solve_info &info)
+{
+    FdmRun R;
+    R.w = &w;
+    R.s = m->stream;
+    R.bc = bc;
+    R.lambda = lambda;
+    R.nu = nu;
+    R.nu_c = nu_c;
+    R.rhs = rhs;
+    R.x = x;
+    int rc;
+    if ((rc = fdm_prepare(m, R))) return rc;
+    if ((rc = fdm_nu_ref(m, w, nu, nu_c, R.nu_ref))) return rc;
+    if ((rc = fdm_start(m, R, o))) return rc;
+    while (!R.done) {
+        if ((rc = fdm_chunk(m, R))) return rc;
+        if ((rc = fdm_poll(R))) return rc;
+    }
+    return fdm_end(m, R, info);
+}
+
+// Up to kMaxConcurrent FDM-PCG solves of one operator (lambda, nu, the
+// mesh's BCs) with different right-hand sides (weak[k]: rhs k is a weak
+// load; null: as o says), run at once: the first on the mesh's stream with
+// its workspace, the others on streams and workspaces of their own (created
+// on first use, kept with the mesh), all driven by this thread.  Returns when
+// every solve has ended.
+int fdm_concurrent(dg_mesh *m, int nsys, double lambda, const double *nu, double nu_c,
+                   const double *const *rhs, double *const *x, const int *weak, const dg_solve_opts &o,
+                   dg_solve_info *info)
+{
+    if (nsys < 1 || nsys > kMaxConcurrent) {
+        set_error("concurrent solves: need 1 <= nsys <= 3");
+        return DG_ERR_ARG;
+    }
+    FdmRun R[kMaxConcurrent];
+    int rc;
+    for (int k = 0; k < nsys; ++k) {
+        if (k > 0 && !m->alt_stream[k - 1])
+            DG_HIP_CHECK(hipStreamCreateWithFlags(&m->alt_stream[k - 1], hipStreamNonBlocking));
+        R[k].w = k == 0 ? &m->ws : &m->alt_ws[k - 1];
+        R[k].s = k == 0 ? m->stream : m->alt_stream[k - 1];
+        R[k].bc = m->dev.bc;
+        R[k].lambda = lambda;
+        R[k].nu = nu;
+        R[k].nu_c = nu_c;
+        R[k].rhs = rhs[k];
+        R[k].x = x[k];
+        if ((rc = fdm_prepare(m, R[k]))) return rc;
+    }
+    double nu_ref = 0.0;
+    if ((rc = fdm_nu_ref(m, m->ws, nu, nu_c, nu_ref))) return rc;
+    // the other streams start after the mesh's stream has done its work so
+    // far (the right-hand sides, the tables)
+    if (nsys > 1) {
+        if (!m->alt_event) DG_HIP_CHECK(hipEventCreateWithFlags(&m->alt_event, hipEventDisableTiming));
+        DG_HIP_CHECK(hipEventRecord(m->alt_event, m->stream));
+        for (int k = 1; k < nsys; ++k) DG_HIP_CHECK(hipStreamWaitEvent(R[k].s, m->alt_event, 0));
+    }
+    for (int k = 0; k < nsys; ++k) {
+        R[k].nu_ref = nu_ref;
+        dg_solve_opts ok = o;
+        if (weak) ok.rhs_is_weak = weak[k];
+        if ((rc = fdm_start(m, R[k], ok))) return rc;
+    }
+    for (;;) {
+        bool all = true;
+        for (int k = 0; k < nsys; ++k)
+            if (!R[k].done && (rc = fdm_chunk(m, R[k]))) return rc;
+        for (int k = 0; k < nsys; ++k) {
+            if (!R[k].done && (rc = fdm_poll(R[k]))) return rc;
+            all = all && R[k].done;
+        }
+        if (all) break;
+    }
+    int worst = DG_OK;
+    for (int k = 0; k < nsys; ++k) {
+        dg_solve_info ik{};
+        rc = fdm_end(m, R[k], ik);
+        if (info) info[k] = ik;
+        if (rc < 0 && (worst >= 0 || rc < worst)) worst = rc;
+        else if (rc > 0 && worst == DG_OK) worst = rc;
+    }
+    return worst;
 }
 
 // FP64 refinement around FP32 Jacobi-PCG with residual replacement: the FP32
@@ -941,6 +1094,14 @@ static int scratch_address(void **out)
 
 namespace dg {
 
+int solve_fdm_concurrent(dg_mesh *m, int nsys, double lambda, const double *nu, double nu_c,
+                         const double *const *rhs, double *const *x, const int *weak,
+                         const dg_solve_opts &o, dg_solve_info *info)
+{
+    if (int rc = check_mesh(m)) return rc;
+    return fdm_concurrent(m, nsys, lambda, nu, nu_c, rhs, x, weak, o, info);
+}
+
 int mesh_create_impl(int nx, int ny, int nz, int P, const double *xv, const double *yv,
                      const double *zv, const int bc[3], void *hip_stream, void *geo_mem,
                      dg_mesh **out)
@@ -1105,6 +1266,15 @@ int dg_mesh_destroy(dg_mesh *m)
     if (m->geo_block && !m->geo_external) (void)hipFree(m->geo_block);
     if (m->aux) (void)hipFree(m->aux);
     if (m->step_buf) (void)hipFree(m->step_buf);
+    for (int k = 0; k < kMaxConcurrent - 1; ++k) {
+        if (m->alt_stream[k]) {
+            (void)hipStreamSynchronize(m->alt_stream[k]);
+            (void)hipStreamDestroy(m->alt_stream[k]);
+        }
+        if (m->alt_ws[k].base) (void)hipFree(m->alt_ws[k].base);
+        if (m->alt_ws[k].host_sc) (void)hipHostFree(m->alt_ws[k].host_sc);
+    }
+    if (m->alt_event) (void)hipEventDestroy(m->alt_event);
     delete m;
     return DG_OK;
 }
