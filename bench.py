@@ -562,9 +562,10 @@ def bench_imex_step(dg, torch, reps=3):
     nu(v) = 0.01 + 0.01 (|v|/2)^2, dt = 2^-8 from the exact velocity at
     t = 0, the manufactured forcing at the stage times (evaluated once,
     before timing), the final projection, every solve FDM-preconditioned
-    to 1e-10; RK-ARS3 again with walls on every face carrying the exact
-    velocity (VVD).  Also the convective term alone (HIP events on its
-    stream) against the FP64 vector peak."""
+    to 1e-10 (FP64 transforms; the *_fdm32 entries: FP32 transforms, CG
+    still FP64 with the same stopping test); RK-ARS3 again with walls on
+    every face carrying the exact velocity (VVD).  Also the convective term
+    alone (HIP events on its stream) against the FP64 vector peak."""
     import synth
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
@@ -579,8 +580,9 @@ def bench_imex_step(dg, torch, reps=3):
     v0 = [c.contiguous() for c in synth.vvp_velocity(X, Y, Z, 0.0, xp=torch)]
     out = {"ndof_velocity": N, "ndof_pressure": mp.ndof, "elements": mv.nx * mv.ny * mv.nz, "dt": dt}
     opts = dg.default_opts(precond=dg.DG_PC_FDM)
-    for method in ("RK-ARS3", "RK-CB3e"):
-        tab = dg.imex_tableau(method)
+    opts32 = dg.default_opts(precond=dg.DG_PC_FDM, precision=dg.DG_MIXED)
+    for method in ("RK-ARS3", "RK-CB3e", "RK-ARS3_fdm32", "RK-CB3e_fdm32"):
+        tab = dg.imex_tableau(method.split("_")[0])
         f = [[c.contiguous() for c in synth.vvp_forcing(X, Y, Z, tab.c[j] * dt, nu0, nu1, xp=torch)]
              for j in range(tab.s)]
         times, info = [], None
@@ -588,8 +590,8 @@ def bench_imex_step(dg, torch, reps=3):
             v = [c.clone() for c in v0]
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            info = dg.dg_imex_step(mv, mp, tab, dt, nu0, nu1, synth.VVP_VMAX, v, forcing=f,
-                                   final_projection=True, opts=opts)
+            info = dg.dg_imex_step(mv, mp, tab, dt, nu0, nu1, synth.VVP_VMAX, v, forcing=f, final_projection=True,
+                                   opts=opts32 if method.endswith("_fdm32") else opts)
             torch.cuda.synchronize()
             if r > 0:
                 times.append(time.perf_counter() - t0)

@@ -79,8 +79,13 @@ enum { DG_FP64 = 0, DG_FP32 = 1, DG_MIXED = 1 };  /* apply: FP32 data; solve: FP
                  on the Cartesian mesh (see helmholtz_fdm_apply): exact for a
                  constant nu, so CG stops after one or two steps; with a nodal
                  nu field it uses nu_ref = sqrt(min nu max nu), and CG then
-                 converges at a rate set by max nu / min nu.  FP64 only; needs
-                 at most 512 nodes per mesh line (n_d (P+1) <= 512). */
+                 converges at a rate set by max nu / min nu.  Needs at most
+                 512 nodes per mesh line (n_d (P+1) <= 512).  With precision
+                 DG_FP64 the transforms are FP64; with DG_MIXED they are FP32
+                 (FP32 matrices, MFMA arithmetic and intermediates, at twice
+                 the FP64 matrix rate) while CG stays FP64 with the same
+                 stopping test: the preconditioner is then no longer exact,
+                 and a constant-nu solve takes a few iterations. */
 enum { DG_PC_JACOBI = 0, DG_PC_FDM = 1 };
 
 typedef struct dg_mesh dg_mesh;  /* opaque */
@@ -373,6 +378,9 @@ int dg_viscous_fd2(dg_mesh *m, const double *nu, const double *vx, const double 
    with the projection with d_n psi = 0 (for variable viscosity).  opts: the
    options of every pressure and velocity solve (NULL: defaults; DG_PC_FDM
    recommended; the velocity solves start from v''_i).  With DG_PC_FDM the
+   pressure solves always use the FP64 transforms (exact for the constant-
+   coefficient Poisson problem), and precision DG_MIXED selects the FP32
+   transforms for the velocity solves only.  With DG_PC_FDM the
    three velocity solves of a stage, which share their operator, run at once
    on the mesh's stream and two more streams (non-blocking, default
    priority), each with its own FP64 solve workspace; the streams and

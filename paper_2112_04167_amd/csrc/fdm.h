@@ -28,12 +28,15 @@ constexpr int kFdmMaxL = 512;  // longest mesh line (n_d (P+1)) the kernels take
 
 // Device tables of one axis: the forward and backward contraction matrices,
 // padded to Lp = L rounded up to 16, stored [k][i'] (input row k, output row
-// i') as the kernels read them, and the eigenvalues.
+// i') as the kernels read them, and the eigenvalues; FP32 copies of the
+// matrices follow the FP64 tables of all three axes.
 struct FdmDevAxis {
     int L = 0, Lp = 0;
     const double *Gf = nullptr;   // Gf[k][i'] = S[k][i']   (t = S^T r)
     const double *Gb = nullptr;   // Gb[k][i'] = S[i'][k]   (z = S t)
     const double *lam = nullptr;  // Lp values
+    const float *Gf32 = nullptr;  // FP32 copies of Gf and Gb
+    const float *Gb32 = nullptr;
 };
 
 struct FdmDev {
@@ -54,6 +57,11 @@ void fdm_bind(const int n[3], int P, const double *dev, FdmDev &f);
 // when sc->done is set (sc may be null: always run).
 int fdm_apply(const MeshDev &m, const FdmDev &f, double lambda, double nu, bool singular,
               const double *r, double *z, double *tmp, const void *sc, hipStream_t s);
+// The same with FP32 transforms (FP32 matrices, MFMA arithmetic and
+// intermediates; r read and z written in FP64): the FP32 preconditioner.
+// tmp: 2 ndof floats of scratch.
+int fdm_apply32(const MeshDev &m, const FdmDev &f, double lambda, double nu, bool singular,
+                const double *r, double *z, float *tmp, const void *sc, hipStream_t s);
 
 // min and max of a device field of N values (NaN if any is NaN); partial_dev
 // holds partial_cap >= 2 doubles (one min and one max per work-group);

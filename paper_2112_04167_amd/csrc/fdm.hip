@@ -1,6 +1,8 @@
 // Fast-diagonalisation preconditioner on the GPU: the three 1D transforms of
 // z = (S (x) S (x) S) (lambda + nu Lam)^-1 (S (x) S (x) S)^T r as FP64 MFMA
-// contractions along the mesh axes (gfx950, v_mfma_f64_16x16x4f64).
+// contractions along the mesh axes (gfx950, v_mfma_f64_16x16x4f64), or as
+// FP32 MFMA contractions (v_mfma_f32_16x16x4f32, twice the FP64 matrix rate)
+// with FP32 intermediates for the FP32 preconditioner.
 //
 // A mesh line along axis d has L = n_d (P+1) nodes, global 1D index
 // g = e (P+1) + a.  Every line along d is multiplied by the same dense L x L
@@ -43,12 +45,20 @@ namespace dg {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
+// accumulator tile of one MFMA: 4 values per lane
+template <typename TC>
+using acc4 = typename std::conditional<std::is_same<TC, double>::value, d4, f4>::type;
+
+// Element types of a transform launch: TI of the input vector, TO of the
+// output vector, TC of the bundle in LDS, the matrices and the MFMA
+// arithmetic (FP64, or FP32 for the FP32 preconditioner).
 struct FdmArgs {
-    const double *in;
-    double *out;
-    const double *G;    // [k][i'] Lp x Lp (the z launch: forward)
-    const double *G2;   // z launch: backward matrix
+    const void *in;     // TI
+    void *out;          // TO
+    const void *G;      // TC [k][i'] Lp x Lp (the z launch: forward)
+    const void *G2;     // TC, z launch: backward matrix
     const double *lam[3];
     double lambda, nu;
     const CgScalars *sc;  // done flag and mean_r (may be null)
@@ -110,16 +120,16 @@ __device__ __forceinline__ void bundle_base(const FdmArgs &A, int bundle, size_t
 // current group's MFMAs run (a branch per tile made it wait for every load).
 // The K loop runs in groups of 16 (4 MFMA steps of K = 4), A (from L2) and
 // B (from LDS) fragments double-buffered by group.
-template <int NTC, int MT>
-__device__ __forceinline__ void gemm_bundle(const double *__restrict__ G, const double *Bs, int rs,
-                                            int Lp, d4 (&acc)[MT][NTC])
+template <int NTC, int MT, typename TC>
+__device__ __forceinline__ void gemm_bundle(const TC *__restrict__ G, const TC *Bs, int rs, int Lp,
+                                            acc4<TC> (&acc)[MT][NTC])
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-        for (int nt = 0; nt < NTC; ++nt) acc[mt][nt] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int nt = 0; nt < NTC; ++nt) acc[mt][nt] = acc4<TC>{0, 0, 0, 0};
     int col[MT];  // A operand column of this lane per row tile: G[k][16 T + li]
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
@@ -128,26 +138,30 @@ __device__ __forceinline__ void gemm_bundle(const double *__restrict__ G, const 
     }
     constexpr int U = 4;
     const int ngrp = Lp / 16;
-    double a0[U][MT], a1[U][MT], b0[U][NTC], b1[U][NTC];
-    auto load = [&](int g, double (&a)[U][MT], double (&b)[U][NTC]) {
+    TC a0[U][MT], a1[U][MT], b0[U][NTC], b1[U][NTC];
+    auto load = [&](int g, TC (&a)[U][MT], TC (&b)[U][NTC]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int k = 16 * g + 4 * u + lk;
-            const double *gr = G + (size_t)k * Lp;
+            const TC *gr = G + (size_t)k * Lp;
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) a[u][mt] = gr[col[mt]];
 #pragma unroll
             for (int nt = 0; nt < NTC; ++nt) b[u][nt] = Bs[k * rs + 16 * nt + li];
         }
     };
-    auto mma = [&](const double (&a)[U][MT], const double (&b)[U][NTC]) {
+    auto mma = [&](const TC (&a)[U][MT], const TC (&b)[U][NTC]) {
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-                for (int nt = 0; nt < NTC; ++nt)
-                    acc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][mt], b[u][nt], acc[mt][nt], 0, 0, 0);
+                for (int nt = 0; nt < NTC; ++nt) {
+                    if constexpr (std::is_same<TC, double>::value)
+                        acc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][mt], b[u][nt], acc[mt][nt], 0, 0, 0);
+                    else
+                        acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][mt], b[u][nt], acc[mt][nt], 0, 0, 0);
+                }
     };
     load(0, a0, b0);
     int g = 0;
@@ -166,14 +180,19 @@ __device__ __forceinline__ void gemm_bundle(const double *__restrict__ G, const 
     }
 }
 
-// accumulator element r of a lane -> (row, column) within the 16 x 16 tile
-// (v_mfma_f64_16x16x4f64, checked with an in-bounds probe: A operand
-// A[lane % 16][lane / 16], B operand B[lane / 16][lane % 16])
-__device__ __forceinline__ int acc_row(int lane, int r) { return 4 * r + (lane >> 4); }
+// accumulator element r of a lane -> (row, column) within the 16 x 16 tile,
+// checked with in-bounds probes (A operand A[lane % 16][lane / 16], B operand
+// B[lane / 16][lane % 16] in both): v_mfma_f64_16x16x4f64 holds rows
+// lane / 16 + 4 r, v_mfma_f32_16x16x4f32 rows 4 (lane / 16) + r
+template <typename TC>
+__device__ __forceinline__ int acc_row(int lane, int r)
+{
+    return std::is_same<TC, double>::value ? 4 * r + (lane >> 4) : 4 * (lane >> 4) + r;
+}
 __device__ __forceinline__ int acc_col(int lane) { return lane & 15; }
 
-template <int NTC, int MT>
-__device__ __forceinline__ void acc_to_lds(const d4 (&acc)[MT][NTC], double *Bs, int rs, int Lp)
+template <int NTC, int MT, typename TC>
+__device__ __forceinline__ void acc_to_lds(const acc4<TC> (&acc)[MT][NTC], TC *Bs, int rs, int Lp)
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
@@ -184,7 +203,7 @@ __device__ __forceinline__ void acc_to_lds(const d4 (&acc)[MT][NTC], double *Bs,
             for (int nt = 0; nt < NTC; ++nt)
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    Bs[(row0 + acc_row(lane, r)) * rs + 16 * nt + acc_col(lane)] = acc[mt][nt][r];
+                    Bs[(row0 + acc_row<TC>(lane, r)) * rs + 16 * nt + acc_col(lane)] = acc[mt][nt][r];
         }
 }
 
@@ -195,11 +214,12 @@ __device__ __forceinline__ void acc_to_lds(const d4 (&acc)[MT][NTC], double *Bs,
 // (consecutive threads read consecutive addresses) and the same offsets of
 // every element of the bundle, so the index arithmetic (o -> row within the
 // element, column) is done once per offset, not once per value.
-template <int AXIS, int NTC, int MT, int MODE>
+template <int AXIS, int NTC, int MT, int MODE, typename TI, typename TO, typename TC>
 __global__ void __launch_bounds__(256) k_fdm_axis(FdmArgs A)
 {
     constexpr int NB = 16 * NTC;  // columns per work-group; rows: 4 waves x MT tiles of 16
-    extern __shared__ double Bs[];
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    TC *Bs = (TC *)lds_raw;
     if (A.sc && A.sc->done) return;
     const int bundle = blockIdx.x / A.nchunk;
     const int chunk = blockIdx.x - bundle * A.nchunk;
@@ -213,27 +233,28 @@ __global__ void __launch_bounds__(256) k_fdm_axis(FdmArgs A)
 
     // zero what the products read but the bundle does not fill: rows L..Lp-1
     // and the columns past the chunk's last one
-    for (int i = L * rs + threadIdx.x; i < A.Lp * rs; i += blockDim.x) Bs[i] = 0.0;
+    for (int i = L * rs + threadIdx.x; i < A.Lp * rs; i += blockDim.x) Bs[i] = 0;
     if (ncol < NB)
         for (int i = threadIdx.x; i < L * (NB - ncol); i += blockDim.x) {
             const int k = i / (NB - ncol);
-            Bs[k * rs + ncol + (i - k * (NB - ncol))] = 0.0;
+            Bs[k * rs + ncol + (i - k * (NB - ncol))] = 0;
         }
+    const TI *in = (const TI *)A.in;
     for (int o = threadIdx.x; o < n3; o += blockDim.x) {
         int ga, f;
         split_o<AXIS>(o, n, ga, f);
         const int c = f - f0;
         if (c < 0 || c >= ncol) continue;
-        const double *src = A.in + base + o;
-        double *dst = Bs + ga * rs + c;
-        for (int e = 0; e < nd; ++e) dst[e * n * rs] = src[e * se] - mr;
+        const TI *src = in + base + o;
+        TC *dst = Bs + ga * rs + c;
+        for (int e = 0; e < nd; ++e) dst[e * n * rs] = (TC)((double)src[e * se] - mr);
     }
     __syncthreads();
 
-    d4 acc[MT][NTC];
-    gemm_bundle<NTC, MT>(A.G, Bs, rs, A.Lp, acc);
+    acc4<TC> acc[MT][NTC];
+    gemm_bundle<NTC, MT, TC>((const TC *)A.G, Bs, rs, A.Lp, acc);
     __syncthreads();  // every wave is done reading the bundle
-    acc_to_lds<NTC, MT>(acc, Bs, rs, A.Lp);
+    acc_to_lds<NTC, MT, TC>(acc, Bs, rs, A.Lp);
     __syncthreads();
 
     if (MODE == 1) {
@@ -248,24 +269,25 @@ __global__ void __launch_bounds__(256) k_fdm_axis(FdmArgs A)
             const bool zero_col = A.singular && gx == 0 && gy == 0;
             for (int k = k0; k < L; k += RSTEP) {
                 const double den = cxy + A.nu * A.lam[2][k];
-                Bs[k * rs + c] = (zero_col && k == 0) ? 0.0 : Bs[k * rs + c] / den;
+                Bs[k * rs + c] = (zero_col && k == 0) ? (TC)0 : (TC)((double)Bs[k * rs + c] / den);
             }
         }
         __syncthreads();
-        gemm_bundle<NTC, MT>(A.G2, Bs, rs, A.Lp, acc);
+        gemm_bundle<NTC, MT, TC>((const TC *)A.G2, Bs, rs, A.Lp, acc);
         __syncthreads();
-        acc_to_lds<NTC, MT>(acc, Bs, rs, A.Lp);
+        acc_to_lds<NTC, MT, TC>(acc, Bs, rs, A.Lp);
         __syncthreads();
     }
 
+    TO *out = (TO *)A.out;
     for (int o = threadIdx.x; o < n3; o += blockDim.x) {
         int ga, f;
         split_o<AXIS>(o, n, ga, f);
         const int c = f - f0;
         if (c < 0 || c >= ncol) continue;
-        double *dst = A.out + base + o;
-        const double *src = Bs + ga * rs + c;
-        for (int e = 0; e < nd; ++e) dst[e * se] = src[e * n * rs];
+        TO *dst = out + base + o;
+        const TC *src = Bs + ga * rs + c;
+        for (int e = 0; e < nd; ++e) dst[e * se] = (TO)src[e * n * rs];
     }
 }
 
@@ -283,7 +305,7 @@ bool ntc_valid(int ntc, int Lp)
     return row_tiles(Lp) <= 16 / ntc && lds <= 160 * 1024;
 }
 
-template <int AXIS, int MODE>
+template <int AXIS, int MODE, typename TI = double, typename TO = double, typename TC = double>
 int launch_axis(const MeshDev &m, const FdmDev &f, FdmArgs a, int ntc, hipStream_t s)
 {
     const FdmDevAxis &ax = f.ax[AXIS];
@@ -304,12 +326,12 @@ int launch_axis(const MeshDev &m, const FdmDev &f, FdmArgs a, int ntc, hipStream
     a.nchunk = (a.F + a.NBc - 1) / a.NBc;
     a.rs = lds_stride(ntc);
     const int nbundle = (int)(m.nel / m.n[AXIS]);
-    const size_t lds = (size_t)a.Lp * a.rs * sizeof(double);
+    const size_t lds = (size_t)a.Lp * a.rs * sizeof(TC);
     const dim3 grid((unsigned)(nbundle * a.nchunk)), block(256);
     const int mt = row_tiles(ax.Lp);
     auto go = [&](auto NT, auto MTc) {
-        hipLaunchKernelGGL((k_fdm_axis<AXIS, decltype(NT)::value, decltype(MTc)::value, MODE>), grid, block,
-                           lds, s, a);
+        hipLaunchKernelGGL((k_fdm_axis<AXIS, decltype(NT)::value, decltype(MTc)::value, MODE, TI, TO, TC>), grid,
+                           block, lds, s, a);
     };
     using std::integral_constant;
     if (ntc == 4) {
@@ -554,7 +576,7 @@ size_t fdm_table_bytes(const int n[3], int P)
         if (n[d] * (P + 1) > kFdmMaxL) return 0;  // no fast diagonalisation on this mesh
     for (int d = 0; d < 3; ++d) {
         const size_t Lp = (size_t)fdm_pad(n[d] * (P + 1));
-        b += (2 * Lp * Lp + Lp) * sizeof(double);
+        b += (2 * Lp * Lp + Lp) * sizeof(double) + 2 * Lp * Lp * sizeof(float);
     }
     return b;
 }
@@ -578,6 +600,16 @@ int fdm_build_tables(const MeshDev &m, const int bc[3], std::vector<double> &img
         for (int i = L; i < Lp; ++i) lam[i] = 1.0;  // padding rows are never read
         off += 2 * (size_t)Lp * Lp + Lp;
     }
+    // the FP32 copies of the matrices, after the FP64 tables of all axes
+    float *f32 = (float *)(img.data() + off);
+    off = 0;
+    for (int d = 0; d < 3; ++d) {
+        const int L = m.n[d] * (m.P + 1), Lp = fdm_pad(L);
+        const double *gf = img.data() + off;
+        for (size_t i = 0; i < 2 * (size_t)Lp * Lp; ++i) f32[i] = (float)gf[i];
+        f32 += 2 * (size_t)Lp * Lp;
+        off += 2 * (size_t)Lp * Lp + Lp;
+    }
     return DG_OK;
 }
 
@@ -592,6 +624,13 @@ void fdm_bind(const int n[3], int P, const double *dev, FdmDev &f)
         f.ax[d].Gb = dev + off + (size_t)Lp * Lp;
         f.ax[d].lam = dev + off + 2 * (size_t)Lp * Lp;
         off += 2 * (size_t)Lp * Lp + Lp;
+    }
+    const float *f32 = (const float *)(dev + off);
+    for (int d = 0; d < 3; ++d) {
+        const size_t Lp = (size_t)f.ax[d].Lp;
+        f.ax[d].Gf32 = f32;
+        f.ax[d].Gb32 = f32 + Lp * Lp;
+        f32 += 2 * Lp * Lp;
     }
 }
 
@@ -639,6 +678,54 @@ int fdm_apply(const MeshDev &m, const FdmDev &f, double lambda, double nu, bool 
     a.out = z;
     a.G = f.ax[0].Gb;
     return launch_axis<0, 0>(m, f, a, ntc[0], s);
+}
+
+int fdm_apply32(const MeshDev &m, const FdmDev &f, double lambda, double nu, bool singular,
+                const double *r, double *z, float *tmp, const void *sc, hipStream_t s)
+{
+    for (int d = 0; d < 3; ++d)
+        if (f.ax[d].L > kFdmMaxL) {
+            set_error("fast diagonalisation: a mesh line has more than 512 nodes");
+            return DG_ERR_ARG;
+        }
+    FdmArgs a{};
+    a.lam[0] = f.ax[0].lam;
+    a.lam[1] = f.ax[1].lam;
+    a.lam[2] = f.ax[2].lam;
+    a.lambda = lambda;
+    a.nu = nu;
+    a.sc = (const CgScalars *)sc;
+    a.singular = singular ? 1 : 0;
+    std::array<int, 3> ntc;  // the tile shapes tuned for the FP64 kernels
+    int rc = tile_choice(m, f, a, r, z, s, ntc);
+    if (rc) return rc;
+    float *t0 = tmp, *t1 = tmp + m.ndof;
+    // forward x (r - mean_r -> t0, to FP32), forward y (t0 -> t1), z forward +
+    // scale + backward (t1 -> t0), backward y (t0 -> t1), backward x (t1 -> z,
+    // to FP64)
+    a.in = r;
+    a.out = t0;
+    a.G = f.ax[0].Gf32;
+    a.sub_mean = singular ? 1 : 0;
+    if ((rc = launch_axis<0, 0, double, float, float>(m, f, a, ntc[0], s))) return rc;
+    a.sub_mean = 0;
+    a.in = t0;
+    a.out = t1;
+    a.G = f.ax[1].Gf32;
+    if ((rc = launch_axis<1, 0, float, float, float>(m, f, a, ntc[1], s))) return rc;
+    a.in = t1;
+    a.out = t0;
+    a.G = f.ax[2].Gf32;
+    a.G2 = f.ax[2].Gb32;
+    if ((rc = launch_axis<2, 1, float, float, float>(m, f, a, ntc[2], s))) return rc;
+    a.in = t0;
+    a.out = t1;
+    a.G = f.ax[1].Gb32;
+    if ((rc = launch_axis<1, 0, float, float, float>(m, f, a, ntc[1], s))) return rc;
+    a.in = t1;
+    a.out = z;
+    a.G = f.ax[0].Gb32;
+    return launch_axis<0, 0, float, double, float>(m, f, a, ntc[0], s);
 }
 
 }  // namespace dg

@@ -343,11 +343,16 @@ int dg_imex_step(dg_mesh *mv, dg_mesh *mp, const dg_tableau *tab, double dt, dou
     if (opts) o = *opts;
     o.rhs_is_weak = 0;
     if (!(o.tol > 0.0) || o.maxit < 0 || (o.precision != DG_FP64 && o.precision != DG_MIXED) ||
-        (o.precond != DG_PC_JACOBI && o.precond != DG_PC_FDM) ||
-        (o.precond == DG_PC_FDM && o.precision != DG_FP64)) {
+        (o.precond != DG_PC_JACOBI && o.precond != DG_PC_FDM)) {
         set_error("bad solver options");
         return DG_ERR_ARG;
     }
+    // the pressure solves: with the fast-diagonalisation preconditioner always
+    // its FP64 transforms, which are exact for the constant-coefficient
+    // Poisson problem (one iteration); DG_MIXED then applies to the velocity
+    // solves only (FP32 transforms for their variable-nu operator)
+    dg_solve_opts op = o;
+    if (op.precond == DG_PC_FDM) op.precision = DG_FP64;
     int rc;
 
     auto stage_terms = [&](int j, const double *const v[3]) -> int {
@@ -378,7 +383,7 @@ int dg_imex_step(dg_mesh *mv, dg_mesh *mp, const dg_tableau *tab, double dt, dou
         dg_solve_info pi{};
         const double *b3[3] = {nullptr, nullptr, nullptr};
         for (int d = 0; d < 3; ++d) b3[d] = own_trace ? v[d] : (vb ? vb[d] : nullptr);
-        const int r = dg_project(mv, mp, v[0], v[1], v[2], b3[0], b3[1], b3[2], psi, &o, &pi);
+        const int r = dg_project(mv, mp, v[0], v[1], v[2], b3[0], b3[1], b3[2], psi, &op, &pi);
         if (r < 0) return r;
         st.solves += 1;
         st.pressure_iters += pi.iters;
@@ -455,7 +460,7 @@ int dg_imex_step(dg_mesh *mv, dg_mesh *mp, const dg_tableau *tab, double dt, dou
         }
         if (aii > 0.0) {
             dg_solve_info hi[3] = {};
-            if (o.precond == DG_PC_FDM && o.precision == DG_FP64) {
+            if (o.precond == DG_PC_FDM) {
                 rc = solve_fdm_concurrent(mv, 3, lam, nu, 0.0, Gd, Vi, weakd, o, hi);
                 if (rc < 0) return rc;
                 if (rc > st.status) st.status = rc;

@@ -405,6 +405,7 @@ struct FdmRun {
     const double *nu = nullptr, *rhs = nullptr;
     double *x = nullptr;
     bool singular = false, done = false;
+    bool f32 = false;  // FP32 transforms (fdm_apply32)
     FdmDev f{};
     CgVecArgs<double> a{};
     int cap = 0, chunk = 2, launched = 0;
@@ -433,6 +434,16 @@ int fdm_prepare(dg_mesh *m, FdmRun &R)
     return ensure_fdm_tables(m, *R.w, R.bc, R.f);
 }
 
+// z = the preconditioner applied to r (q as scratch: N doubles, or 2 N
+// floats for the FP32 transforms)
+int fdm_precond(const MeshDev &md, FdmRun &R)
+{
+    Workspace &w = *R.w;
+    if (R.f32)
+        return fdm_apply32(md, R.f, R.lambda, R.nu_ref, R.singular, w.r64, w.d64, (float *)w.q64, w.sc, R.s);
+    return fdm_apply(md, R.f, R.lambda, R.nu_ref, R.singular, w.r64, w.d64, w.q64, w.sc, R.s);
+}
+
 // b, r = b - A x from the caller's x, the first preconditioned direction
 int fdm_start(dg_mesh *m, FdmRun &R, const dg_solve_opts &o)
 {
@@ -459,7 +470,7 @@ int fdm_start(dg_mesh *m, FdmRun &R, const dg_solve_opts &o)
     if ((rc = launch_resid<double>(md, R.bc, R.lambda, R.nu, R.nu_c, R.x, w.b64, w.r64, w.partial, w.sc, s)))
         return rc;
     if ((rc = cg_fdm_start(md, a, s))) return rc;
-    if ((rc = fdm_apply(md, R.f, R.lambda, R.nu_ref, R.singular, w.r64, w.d64, w.q64, w.sc, s))) return rc;
+    if ((rc = fdm_precond(md, R))) return rc;
     if ((rc = cg_rz(md, a, true, s))) return rc;
     if ((rc = cg_pupdate_fdm(md, a, true, s))) return rc;
     R.cap = o.fixed_iters > 0 ? o.fixed_iters : o.maxit;
@@ -481,7 +492,7 @@ int fdm_chunk(dg_mesh *m, FdmRun &R)
         if ((rc = launch_apply_cg<double>(md, R.bc, R.lambda, R.nu, R.nu_c, R.a.p, w.q64, w.partial, w.sc, s)))
             return rc;
         if ((rc = cg_update_fdm(md, R.a, s))) return rc;
-        if ((rc = fdm_apply(md, R.f, R.lambda, R.nu_ref, R.singular, w.r64, w.d64, w.q64, w.sc, s))) return rc;
+        if ((rc = fdm_precond(md, R))) return rc;
         if ((rc = cg_rz(md, R.a, false, s))) return rc;
         if ((rc = cg_pupdate_fdm(md, R.a, false, s))) return rc;
     }
@@ -527,10 +538,13 @@ int fdm_end(dg_mesh *m, FdmRun &R, dg_solve_info &info)
     return h.status;
 }
 
+// f32: the preconditioner's transforms in FP32 (CG itself stays FP64)
 int solve_fdm(dg_mesh *m, Workspace &w, const int bc[3], double lambda, const double *nu,
-              double nu_c, const double *rhs, double *x, const dg_solve_opts &o, dg_solve_info &info)
+              double nu_c, const double *rhs, double *x, const dg_solve_opts &o, dg_solve_info &info,
+              bool f32 = false)
 {
     FdmRun R;
+    R.f32 = f32;
     R.w = &w;
     R.s = m->stream;
     R.bc = bc;
@@ -577,6 +591,7 @@ int fdm_concurrent(dg_mesh *m, int nsys, double lambda, const double *nu, double
         R[k].nu_c = nu_c;
         R[k].rhs = rhs[k];
         R[k].x = x[k];
+        R[k].f32 = o.precision == DG_MIXED;
         if ((rc = fdm_prepare(m, R[k]))) return rc;
     }
     double nu_ref = 0.0;
@@ -827,17 +842,13 @@ int solve_common(dg_mesh *m, const int bc[3], double lambda, const double *nu, d
         set_error("unknown preconditioner");
         return DG_ERR_ARG;
     }
-    if (o.precond == DG_PC_FDM && o.precision != DG_FP64) {
-        set_error("the fast-diagonalisation preconditioner runs in FP64 only");
-        return DG_ERR_ARG;
-    }
     Workspace &wk = lent ? *lent : m->ws;
     if (lent && o.precision != DG_FP64) {
         set_error("the no-allocation solve is FP64 only");
         return DG_ERR_ARG;
     }
     if (o.precond == DG_PC_FDM) {
-        rc = solve_fdm(m, wk, bc, lambda, nu, nu_c, rhs, x, o, inf);
+        rc = solve_fdm(m, wk, bc, lambda, nu, nu_c, rhs, x, o, inf, o.precision == DG_MIXED);
     } else if (lent) {
         rc = solve_fp64(m, *lent, bc, lambda, nu, nu_c, rhs, x, o, inf);
     } else if (o.precision == DG_MIXED) {

@@ -1,13 +1,15 @@
 """GPU parity of the fast-diagonalisation inverse (helmholtz_fdm_apply, FP64
 MFMA transforms along the mesh lines) and of CG preconditioned by it
-(opts.precond = DG_PC_FDM) against the oracle.
+(opts.precond = DG_PC_FDM, with FP64 or, for precision DG_MIXED, FP32
+transforms) against the oracle.
 
 Bars: the inverse against the oracle's own fast diagonalisation (numpy
 eigendecompositions, independent of the library's host eigensolver)
 <= 1e-11 relative, on shapes whose line lengths L = n_d (P+1) are and are not
 multiples of the 16-row MFMA tiles; solves against the exact discrete
-solution x* <= 1e-10; iteration-locked runs with a nodal nu against the
-oracle's PCG with the same preconditioner <= 1e-11."""
+solution x* <= 1e-10 (with either precision of the transforms: CG is FP64
+with the same stopping test); iteration-locked runs with a nodal nu against
+the oracle's PCG with the same preconditioner <= 1e-11."""
 import numpy as np
 import pytest
 
@@ -184,8 +186,76 @@ def test_fdm_pcg_initial_guess_and_errors():
     assert ie["status"] == 0 and ie["iters"] == 0 and rel(xe, xs) <= 1e-12
     xf, iff = gpu_solve(spec, lam, 1.0, f, x0=10.0 * synth.uniform_field(ndof(spec), 93))
     assert iff["status"] == 0 and rel(xf, xs) <= 1e-10
-    _, im = gpu_solve(spec, lam, 1.0, f, precision=1)
-    assert im["rc"] == dg.DG_ERR_ARG                       # FP64 only
+    xm, im = gpu_solve(spec, lam, 1.0, f, precision=1)       # FP32 transforms
+    assert im["status"] == 0 and rel(xm, xs) <= 1e-10
     long_line = make_spec((65, 1, 1), 7, (0, 0, 0), False)  # 520 nodes on an x line
     _, il = gpu_solve(long_line, lam, 1.0, synth.uniform_field(ndof(long_line), 1))
     assert il["rc"] == dg.DG_ERR_ARG
+
+
+# the FP32 transforms: every CASES shape (line lengths from 5 to 63, all BC
+# kinds, the P = 8 chunked bundles), plus the singular Poisson problem
+@pytest.mark.parametrize("case", CASES, ids=["P4_periodic", "P7_stretched", "P5_mixed_bc", "P8_chunks",
+                                             "P3_n1", "P6_dirichlet_lam0"])
+def test_fdm32_pcg_matches_exact_solution(case):
+    n, P, bc, st, lam, nu = case
+    spec = make_spec(n, P, bc, st)
+    f = synth.uniform_field(ndof(spec), 70 + P)
+    x, info = gpu_solve(spec, lam, nu, f, precision=1)
+    xs = kron.FDM(spec, lam, nu).solve(dense.mass_diag(spec) * f)
+    say("fdm32 pcg", case, info, rel(x, xs))
+    # FP32 transforms: no longer exact, but within a few iterations
+    assert info["status"] == 0 and 2 <= info["iters"] <= 8
+    assert info["true_rel_res"] <= 1e-10 and rel(x, xs) <= 1e-10
+
+
+def test_fdm32_pcg_singular_poisson():
+    spec = make_spec((3, 3, 2), 6, (0, 1, 0), False)
+    f = synth.uniform_field(ndof(spec), 62)
+    x, info = gpu_solve(spec, 0.0, 1.0, f, poisson=True, precision=1)
+    pspec = dict(spec)
+    pspec["bc"] = (0, 2, 0)
+    M = dense.mass_diag(pspec)
+    xs = kron.FDM(pspec, 0.0).solve(M * f)
+    say("fdm32 singular", info, rel(x, xs))
+    assert info["status"] == 0 and info["iters"] <= 8
+    assert rel(x, xs) <= 1e-10
+    assert abs(np.dot(M, x)) <= 1e-12 * np.linalg.norm(x) * np.sqrt(M.sum())
+
+
+@pytest.mark.parametrize("poisson", [False, True])
+def test_fdm32_pcg_stretched_large_full_size(poisson):
+    # the 32^3, P = 7 systems (L = 256 per axis) with FP32 transforms
+    spec = synth.mesh_spec("stretched_large")
+    if poisson:
+        f = synth.uniform_field(ndof(spec), synth.SEEDS["large_poisson"])
+        lam = 0.0
+        pspec = dict(spec)
+        pspec["bc"] = (0, 0, 2)
+    else:
+        f = synth.uniform_field(ndof(spec), synth.SEEDS["large_helmholtz"])
+        lam = synth.large_helmholtz_lambda()
+        pspec = spec
+    x, info = gpu_solve(spec, lam, 1.0, f, poisson=poisson, precision=1)
+    M = dense.mass_diag(pspec)
+    xs = kron.FDM(pspec, lam).solve(M * f)
+    say("fdm32 pcg large poisson=%s" % poisson, info, "err vs x*", rel(x, xs))
+    assert info["status"] == 0 and info["iters"] <= 8
+    assert info["true_rel_res"] <= 1e-10 and rel(x, xs) <= 1e-10
+
+
+def test_fdm32_pcg_channel_velocity_full_size():
+    # nodal nu (max/min = 3): the FP32 transforms cost at most one more
+    # iteration than the FP64 ones here
+    spec = synth.mesh_spec("batched_channel")
+    nu = channel_nu(spec)
+    lam = synth.batched_lambda()
+    f = synth.uniform_field(ndof(spec), synth.SEEDS["batched_velocity"][0])
+    x64, i64 = gpu_solve(spec, lam, nu, f)
+    x32, i32 = gpu_solve(spec, lam, nu, f, precision=1)
+    op = naive.Operator(spec, lam, nu)
+    M = dense.mass_diag(spec)
+    say("fdm32 channel velocity", i64["iters"], i32["iters"], rel(x32, x64))
+    assert i32["status"] == 0 and i32["iters"] <= i64["iters"] + 1
+    assert pcg.true_rel_res(op.apply, x32, M * f, M) <= 1.2e-10
+    assert rel(x32, x64) <= 2e-10

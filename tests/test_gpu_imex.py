@@ -83,7 +83,7 @@ def test_fd2_matches_oracle(case):
     m.destroy()
 
 
-def _gpu_step(spec, v, t, dt, method, nu0, nu1, forcing, final_projection, tol=1e-13):
+def _gpu_step(spec, v, t, dt, method, nu0, nu1, forcing, final_projection, tol=1e-13, precision=0):
     import paper_2112_04167_amd as dg
     torch, dev = torch_dev()
     ps = dict(spec)
@@ -96,7 +96,7 @@ def _gpu_step(spec, v, t, dt, method, nu0, nu1, forcing, final_projection, tol=1
         f = [[to_dev(c) for c in forcing(t + tab.c[j] * dt)] for j in range(tab.s)]
     info = dg.dg_imex_step(mv, mp, tab, dt, nu0, nu1, synth.VVP_VMAX, vd, forcing=f,
                            final_projection=final_projection,
-                           opts=dg.default_opts(tol=tol, precond=dg.DG_PC_FDM))
+                           opts=dg.default_opts(tol=tol, precond=dg.DG_PC_FDM, precision=precision))
     out = [c.cpu().numpy() for c in vd]
     mv.destroy()
     mp.destroy()
@@ -121,6 +121,27 @@ def test_step_vvp_matches_oracle(method):
     for d in range(3):
         e = rel(got[d], want[d])
         say("step", method, d, e)
+        assert e <= 1e-10
+
+
+@pytest.mark.parametrize("method", ["RK-CB3e", "RK-ARS3"])
+def test_step_vvp_fp32_preconditioner_matches_oracle(method):
+    # the same step with every solve preconditioned by the FP32 transforms
+    # (precision DG_MIXED): CG stays FP64 with the same stopping test, so the
+    # step meets the same bar
+    spec = make_spec((2, 2, 2), 4, (0, 0, 0), False, lo=-0.5, hi=0.5)
+    X, Y, Z = node_coords(spec)
+    t, dt, nu0, nu1 = 0.1, 1.0 / 32, 0.01, 0.01
+    v = synth.vvp_velocity(X, Y, Z, t)
+    f = lambda tt: synth.vvp_forcing(X, Y, Z, tt, nu0, nu1)
+    got, info = _gpu_step(spec, v, t, dt, method, nu0, nu1, f, True, precision=1)
+    want, _ = imex.step(spec, v, t, dt, imex.TABLEAUX[method], nu0, nu1, synth.VVP_VMAX, f,
+                        final_projection=True, solver="dense")
+    say("step fp32 preconditioner", method, info)
+    assert info["status"] == 0
+    for d in range(3):
+        e = rel(got[d], want[d])
+        say("step fp32 preconditioner", method, d, e)
         assert e <= 1e-10
 
 
