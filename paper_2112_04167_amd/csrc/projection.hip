@@ -101,11 +101,15 @@ __global__ void __launch_bounds__(256) k_divergence(ProjArgs A)
     }
     for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = A.t.w[i];
     __syncthreads();
-    __shared__ double tv[n3];       // scaled velocity component
+    __shared__ double tv3[3][n3];   // scaled velocity components
     __shared__ double s1[n * n * m];
     __shared__ double s2[n * m * m];
     __shared__ double acc[m3];
     __shared__ double fs[n * n], fq[n * m];
+    // the face values f = {v_d} or v_b,d of the six faces (axis d, side),
+    // [t][s], staged with the velocity so that every global load of the
+    // element is in flight before the first barrier
+    __shared__ double fv[6][n * n];
     const int el = blockIdx.x;
     const int ex = el % A.n[0], ey = (el / A.n[0]) % A.n[1], ez = el / (A.n[0] * A.n[1]);
     const int e3[3] = {ex, ey, ez};
@@ -114,14 +118,32 @@ __global__ void __launch_bounds__(256) k_divergence(ProjArgs A)
     const double J = hx * hy * hz * 0.125;
     const size_t vb0 = elem_base(A, ex, ey, ez, n3);
     for (int i = threadIdx.x; i < m3; i += blockDim.x) acc[i] = 0.0;
+    for (int r = threadIdx.x; r < 3 * n3; r += blockDim.x) {
+        const int d = r / n3, i = r - d * n3;
+        const int a = i % n, b = (i / n) % n, c = i / (n * n);
+        tv3[d][i] = tw[a] * tw[b] * tw[c] * J * A.v[d][vb0 + i];
+    }
+    for (int r = threadIdx.x; r < 6 * n * n; r += blockDim.x) {
+        const int face = r / (n * n), i = r - face * n * n, sn = i % n, tn = i / n;
+        const int d = face >> 1;
+        const bool high = (face & 1) != 0;
+        const int kn = neighbour(e3[d], A.n[d], A.bc[d], high);
+        const int own = face_node<n>(d, high ? n - 1 : 0, sn, tn);
+        double f = 0.0;
+        if (kn >= 0) {
+            int en[3] = {ex, ey, ez};
+            en[d] = kn;
+            const size_t nb0 = elem_base(A, en[0], en[1], en[2], n3);
+            f = 0.5 * (A.v[d][vb0 + own] + A.v[d][nb0 + face_node<n>(d, high ? 0 : n - 1, sn, tn)]);
+        } else if (A.vb[d]) {
+            f = A.vb[d][vb0 + own];
+        }
+        fv[face][i] = f;
+    }
     // volume: acc -= (A2 (x) A1 (x) A0)^T (W J v_d), A_d = (2/h_d) dVq, others Vq
     for (int d = 0; d < 3; ++d) {
         __syncthreads();
-        for (int i = threadIdx.x; i < n3; i += blockDim.x) {
-            const int a = i % n, b = (i / n) % n, c = i / (n * n);
-            tv[i] = tw[a] * tw[b] * tw[c] * J * A.v[d][vb0 + i];
-        }
-        __syncthreads();
+        const double *tv = tv3[d];
         const double gd = 2.0 / hh[d];
         // over a (x): s1[c][b][ix]
         for (int i = threadIdx.x; i < n * n * m; i += blockDim.x) {
@@ -156,21 +178,11 @@ __global__ void __launch_bounds__(256) k_divergence(ProjArgs A)
             const bool high = hi == 1;
             const int kn = neighbour(e3[d], A.n[d], A.bc[d], high);
             if (kn < 0 && !A.vb[d]) continue;  // boundary with v_b = 0: no term
-            int en[3] = {ex, ey, ez};
-            if (kn >= 0) en[d] = kn;
-            const size_t nb0 = elem_base(A, en[0], en[1], en[2], n3);
-            const int layer = high ? n - 1 : 0, nlayer = high ? 0 : n - 1;
             const double omega0 = hh[t1] * hh[t2] * 0.25, sgn = high ? 1.0 : -1.0;
             __syncthreads();
             for (int i = threadIdx.x; i < n * n; i += blockDim.x) {
                 const int s = i % n, t = i / n;
-                const int own = face_node<n>(d, layer, s, t);
-                double f;
-                if (kn >= 0)
-                    f = 0.5 * (A.v[d][vb0 + own] + A.v[d][nb0 + face_node<n>(d, nlayer, s, t)]);
-                else
-                    f = A.vb[d][vb0 + own];
-                fs[i] = sgn * omega0 * tw[s] * tw[t] * f;  // [t][s]
+                fs[i] = sgn * omega0 * tw[s] * tw[t] * fv[2 * d + hi][i];  // [t][s]
             }
             __syncthreads();
             for (int i = threadIdx.x; i < n * m; i += blockDim.x) {  // over s: fq[t][is]
@@ -215,12 +227,32 @@ __global__ void __launch_bounds__(256) k_gradient(ProjArgs A)
     __shared__ double s2[m * n * n];
     __shared__ double g[n3];
     __shared__ double jf[m * m], jt[n * m], jump[n * n];
+    // the neighbours' pressure traces on the six faces (axis d, side),
+    // [it][is], staged with psi so that every global load is in flight
+    // before the first barrier
+    __shared__ double qn[6][m * m];
     const int el = blockIdx.x;
     const int ex = el % A.n[0], ey = (el / A.n[0]) % A.n[1], ez = el / (A.n[0] * A.n[1]);
     const int e3[3] = {ex, ey, ez};
     const double hh[3] = {A.h[0][ex], A.h[1][ey], A.h[2][ez]};
     const size_t vbase = elem_base(A, ex, ey, ez, n3), pbase = elem_base(A, ex, ey, ez, m3);
+    auto at = [&](int d, int layer, int s, int t) {
+        return d == 0 ? (t * m + s) * m + layer : d == 1 ? (t * m + layer) * m + s : (layer * m + t) * m + s;
+    };
     for (int i = threadIdx.x; i < m3; i += blockDim.x) q[i] = A.psi[pbase + i];
+    for (int r = threadIdx.x; r < 6 * m * m; r += blockDim.x) {
+        const int face = r / (m * m), i = r - face * m * m, is = i % m, it = i / m;
+        const int d = face >> 1;
+        const bool high = (face & 1) != 0;
+        const int kn = neighbour(e3[d], A.n[d], A.bc[d], high);
+        double oth = 0.0;
+        if (kn >= 0) {
+            int en[3] = {ex, ey, ez};
+            en[d] = kn;
+            oth = A.psi[elem_base(A, en[0], en[1], en[2], m3) + at(d, high ? 0 : m - 1, is, it)];
+        }
+        qn[face][i] = oth;
+    }
     for (int d = 0; d < 3; ++d) {
         const double gd = 2.0 / hh[d];
         __syncthreads();
@@ -251,20 +283,13 @@ __global__ void __launch_bounds__(256) k_gradient(ProjArgs A)
             const bool high = hi == 1;
             const int kn = neighbour(e3[d], A.n[d], A.bc[d], high);
             if (kn < 0) continue;
-            int en[3] = {ex, ey, ez};
-            en[d] = kn;
-            const size_t nbase = elem_base(A, en[0], en[1], en[2], m3);
             // L = the element on the low side of the face, R the high side
             const int pl = m - 1, pr = 0;
             __syncthreads();
             for (int i = threadIdx.x; i < m * m; i += blockDim.x) {
                 const int is = i % m, it = i / m;
-                auto at = [&](int layer, int s, int t) {
-                    return d == 0 ? (t * m + s) * m + layer : d == 1 ? (t * m + layer) * m + s
-                                                                     : (layer * m + t) * m + s;
-                };
-                const double own = q[at(high ? pl : pr, is, it)];
-                const double oth = A.psi[nbase + at(high ? pr : pl, is, it)];
+                const double own = q[at(d, high ? pl : pr, is, it)];
+                const double oth = qn[2 * d + hi][i];
                 jf[i] = high ? own - oth : oth - own;  // psi_L - psi_R on pressure face nodes
             }
             __syncthreads();
@@ -307,12 +332,16 @@ __global__ void __launch_bounds__(256) k_gradient(ProjArgs A)
 template <int P>
 __global__ void __launch_bounds__(256) k_divergence_eq(ProjArgs A)
 {
-    constexpr int n = P + 1, n3 = n * n * n;
+    constexpr int n = P + 1, n2 = n * n, n3 = n2 * n;
     __shared__ double tdV[n * n], tw[n];  // the 1D tables in LDS (see k_divergence)
     for (int i = threadIdx.x; i < n * n; i += blockDim.x) tdV[i] = A.t.dVq[i / n][i % n];
     for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = A.t.w[i];
     __syncthreads();
     __shared__ double tv[3][n3];
+    // the face values f of the six faces (axis d, side), [t][s]: the mean of
+    // the two traces, the wall data, or 0 (no term), staged with the volume
+    // data so that all global loads are in flight before the first barrier
+    __shared__ double fv[6][n2];
     const int el = blockIdx.x;
     const int ex = el % A.n[0], ey = (el / A.n[0]) % A.n[1], ez = el / (A.n[0] * A.n[1]);
     const int e3[3] = {ex, ey, ez};
@@ -323,6 +352,23 @@ __global__ void __launch_bounds__(256) k_divergence_eq(ProjArgs A)
         const int d = r / n3, i = r - d * n3;
         const int a = i % n, b = (i / n) % n, c = i / (n * n);
         tv[d][i] = tw[a] * tw[b] * tw[c] * J * A.v[d][vb0 + i];
+    }
+    for (int r = threadIdx.x; r < 6 * n2; r += blockDim.x) {
+        const int face = r / n2, st = r - face * n2, s = st % n, t = st / n;
+        const int d = face >> 1;
+        const bool high = (face & 1) != 0;
+        const int layer = high ? n - 1 : 0;
+        const int kn = neighbour(e3[d], A.n[d], A.bc[d], high);
+        double f = 0.0;
+        if (kn >= 0) {
+            int en[3] = {ex, ey, ez};
+            en[d] = kn;
+            const size_t nb0 = elem_base(A, en[0], en[1], en[2], n3);
+            f = 0.5 * (A.v[d][vb0 + face_node<n>(d, layer, s, t)] + A.v[d][nb0 + face_node<n>(d, high ? 0 : n - 1, s, t)]);
+        } else if (A.vb[d]) {
+            f = A.vb[d][vb0 + face_node<n>(d, layer, s, t)];
+        }
+        fv[face][st] = f;
     }
     __syncthreads();
     for (int r = threadIdx.x; r < n3; r += blockDim.x) {
@@ -350,26 +396,16 @@ __global__ void __launch_bounds__(256) k_divergence_eq(ProjArgs A)
             for (int k = 0; k < n; ++k) sum += gd * tdV[(k) * n + (c)] * tv[2][(k * n + b) * n + a];
             acc -= sum;
         }
+#pragma unroll
         for (int d = 0; d < 3; ++d) {
             const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
             const int s = co[t1], t = co[t2];
+#pragma unroll
             for (int hi = 0; hi < 2; ++hi) {
                 const bool high = hi == 1;
-                const int layer = high ? n - 1 : 0;
-                if (co[d] != layer) continue;
-                const int kn = neighbour(e3[d], A.n[d], A.bc[d], high);
-                if (kn < 0 && !A.vb[d]) continue;
-                double f;
-                if (kn >= 0) {
-                    int en[3] = {ex, ey, ez};
-                    en[d] = kn;
-                    const size_t nb0 = elem_base(A, en[0], en[1], en[2], n3);
-                    f = 0.5 * (A.v[d][vb0 + r] + A.v[d][nb0 + face_node<n>(d, high ? 0 : n - 1, s, t)]);
-                } else {
-                    f = A.vb[d][vb0 + r];
-                }
-                const double omega0 = A.h[t1][e3[t1]] * A.h[t2][e3[t2]] * 0.25, sgn = high ? 1.0 : -1.0;
-                acc += sgn * omega0 * tw[s] * tw[t] * f;
+                if (co[d] != (high ? n - 1 : 0)) continue;
+                const double omega0 = hh[t1] * hh[t2] * 0.25, sgn = high ? 1.0 : -1.0;
+                acc += sgn * omega0 * tw[s] * tw[t] * fv[2 * d + hi][t * n + s];
             }
         }
         A.out[vb0 + r] = A.scale * acc;
@@ -379,18 +415,37 @@ __global__ void __launch_bounds__(256) k_divergence_eq(ProjArgs A)
 template <int P>
 __global__ void __launch_bounds__(256) k_gradient_eq(ProjArgs A)
 {
-    constexpr int n = P + 1, n3 = n * n * n;
+    constexpr int n = P + 1, n2 = n * n, n3 = n2 * n;
     __shared__ double tdV[n * n], tw[n];  // the 1D tables in LDS (see k_divergence)
     for (int i = threadIdx.x; i < n * n; i += blockDim.x) tdV[i] = A.t.dVq[i / n][i % n];
     for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = A.t.w[i];
     __syncthreads();
-    __shared__ double q[n3];
+    // psi of the element, the neighbours' traces on the six faces (axis d,
+    // side; [t][s]) and the nodal factor, all staged before the first
+    // barrier so that their global loads are in flight together
+    __shared__ double q[n3], qn[6][n2], fq[n3];
     const int el = blockIdx.x;
     const int ex = el % A.n[0], ey = (el / A.n[0]) % A.n[1], ez = el / (A.n[0] * A.n[1]);
     const int e3[3] = {ex, ey, ez};
     const double hh[3] = {A.h[0][ex], A.h[1][ey], A.h[2][ez]};
     const size_t base = elem_base(A, ex, ey, ez, n3);
-    for (int r = threadIdx.x; r < n3; r += blockDim.x) q[r] = A.psi[base + r];
+    for (int r = threadIdx.x; r < n3; r += blockDim.x) {
+        q[r] = A.psi[base + r];
+        if (A.fac) fq[r] = A.fac[base + r];
+    }
+    for (int r = threadIdx.x; r < 6 * n2; r += blockDim.x) {
+        const int face = r / n2, st = r - face * n2, s = st % n, t = st / n;
+        const int d = face >> 1;
+        const bool high = (face & 1) != 0;
+        const int kn = neighbour(e3[d], A.n[d], A.bc[d], high);
+        double oth = 0.0;
+        if (kn >= 0) {
+            int en[3] = {ex, ey, ez};
+            en[d] = kn;
+            oth = A.psi[elem_base(A, en[0], en[1], en[2], n3) + face_node<n>(d, high ? 0 : n - 1, s, t)];
+        }
+        qn[face][st] = oth;
+    }
     __syncthreads();
     for (int r = threadIdx.x; r < n3; r += blockDim.x) {
         const int a = r % n, b = (r / n) % n, c = r / (n * n);
@@ -408,23 +463,19 @@ __global__ void __launch_bounds__(256) k_gradient_eq(ProjArgs A)
 #pragma unroll
                 for (int k = 0; k < n; ++k) g += gd * tdV[(c) * n + (k)] * q[(k * n + b) * n + a];
             }
+            const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
             for (int hi = 0; hi < 2; ++hi) {
                 const bool high = hi == 1;
                 const int layer = high ? n - 1 : 0;
                 if (co[d] != layer) continue;
-                const int kn = neighbour(e3[d], A.n[d], A.bc[d], high);
-                if (kn < 0) continue;
-                int en[3] = {ex, ey, ez};
-                en[d] = kn;
-                int cn[3] = {a, b, c};
-                cn[d] = high ? 0 : n - 1;
-                const double oth = A.psi[elem_base(A, en[0], en[1], en[2], n3) + (cn[2] * n + cn[1]) * n + cn[0]];
+                if (neighbour(e3[d], A.n[d], A.bc[d], high) < 0) continue;
+                const double oth = qn[2 * d + hi][co[t2] * n + co[t1]];
                 const double own = q[r];
                 const double jump = high ? own - oth : oth - own;
                 const double f = 1.0 / (tw[layer] * hh[d]);
                 g -= f * jump;
             }
-            const double gv = A.fac ? A.scale * g * A.fac[base + r] : A.scale * g;
+            const double gv = A.fac ? A.scale * g * fq[r] : A.scale * g;
             A.g[d][base + r] = A.update ? A.v[d][base + r] + gv : gv;
         }
     }
