@@ -101,14 +101,14 @@ __global__ void __launch_bounds__(256) k_divergence(ProjArgs A)
     }
     for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = A.t.w[i];
     __syncthreads();
-    __shared__ double tv3[3][n3];   // scaled velocity components
+    __shared__ double tv[n3];       // scaled velocity component
     __shared__ double s1[n * n * m];
     __shared__ double s2[n * m * m];
     __shared__ double acc[m3];
     __shared__ double fs[n * n], fq[n * m];
     // the face values f = {v_d} or v_b,d of the six faces (axis d, side),
-    // [t][s], staged with the velocity so that every global load of the
-    // element is in flight before the first barrier
+    // [t][s], staged at the start so that their global loads are in flight
+    // with the first component's
     __shared__ double fv[6][n * n];
     const int el = blockIdx.x;
     const int ex = el % A.n[0], ey = (el / A.n[0]) % A.n[1], ez = el / (A.n[0] * A.n[1]);
@@ -118,11 +118,6 @@ __global__ void __launch_bounds__(256) k_divergence(ProjArgs A)
     const double J = hx * hy * hz * 0.125;
     const size_t vb0 = elem_base(A, ex, ey, ez, n3);
     for (int i = threadIdx.x; i < m3; i += blockDim.x) acc[i] = 0.0;
-    for (int r = threadIdx.x; r < 3 * n3; r += blockDim.x) {
-        const int d = r / n3, i = r - d * n3;
-        const int a = i % n, b = (i / n) % n, c = i / (n * n);
-        tv3[d][i] = tw[a] * tw[b] * tw[c] * J * A.v[d][vb0 + i];
-    }
     for (int r = threadIdx.x; r < 6 * n * n; r += blockDim.x) {
         const int face = r / (n * n), i = r - face * n * n, sn = i % n, tn = i / n;
         const int d = face >> 1;
@@ -143,7 +138,11 @@ __global__ void __launch_bounds__(256) k_divergence(ProjArgs A)
     // volume: acc -= (A2 (x) A1 (x) A0)^T (W J v_d), A_d = (2/h_d) dVq, others Vq
     for (int d = 0; d < 3; ++d) {
         __syncthreads();
-        const double *tv = tv3[d];
+        for (int i = threadIdx.x; i < n3; i += blockDim.x) {
+            const int a = i % n, b = (i / n) % n, c = i / (n * n);
+            tv[i] = tw[a] * tw[b] * tw[c] * J * A.v[d][vb0 + i];
+        }
+        __syncthreads();
         const double gd = 2.0 / hh[d];
         // over a (x): s1[c][b][ix]
         for (int i = threadIdx.x; i < n * n * m; i += blockDim.x) {
