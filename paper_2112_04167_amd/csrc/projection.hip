@@ -631,23 +631,39 @@ NodalArgs nodal_args(const MeshDev &m)
     return a;
 }
 
-// the GLL mass J w_a w_b w_c of node i
-__device__ __forceinline__ double node_mass(const NodalArgs &A, size_t i)
+// One work-group per element for the GLL-mass kernels: the node's position
+// in the element and the element's extents come from 32-bit block and thread
+// indices (no 64-bit division per node), and the weights from LDS (read
+// from the kernel arguments with lane-dependent indices they would be
+// vector loads).  The mass of node (a, b, c) is J w_a w_b w_c, J the
+// element's h_x h_y h_z / 8.
+template <int P>
+__device__ __forceinline__ void element_mass_setup(const NodalArgs &A, double (&tw)[P + 1], double &J,
+                                                   size_t &base)
 {
-    const int n = A.P + 1, n3 = n * n * n;
-    const size_t el = i / n3;
-    const int loc = (int)(i - el * n3);
-    const int a = loc % n, b = (loc / n) % n, c = loc / (n * n);
-    const int ex = (int)(el % A.n[0]), ey = (int)((el / A.n[0]) % A.n[1]), ez = (int)(el / ((size_t)A.n[0] * A.n[1]));
-    return A.h[0][ex] * A.h[1][ey] * A.h[2][ez] * 0.125 * A.w[a] * A.w[b] * A.w[c];
+    constexpr int n = P + 1;
+    if (threadIdx.x < n) tw[threadIdx.x] = A.w[threadIdx.x];
+    const int el = blockIdx.x;
+    const int ex = el % A.n[0], ey = (el / A.n[0]) % A.n[1], ez = el / (A.n[0] * A.n[1]);
+    J = A.h[0][ex] * A.h[1][ey] * A.h[2][ez] * 0.125;
+    base = (size_t)el * (n * n * n);
+    __syncthreads();
 }
 
 // out = s * x * (f or 1) / M   (weak vector -> scaled nodal field)
-__global__ void k_weak_to_nodal(NodalArgs A, const double *x, const double *f, double s, double *out)
+template <int P>
+__global__ void __launch_bounds__(256) k_weak_to_nodal(NodalArgs A, const double *x, const double *f, double s,
+                                                       double *out)
 {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < A.N; i += (size_t)gridDim.x * blockDim.x) {
-        const double v = s * x[i] / node_mass(A, i);
-        out[i] = f ? v * f[i] : v;
+    constexpr int n = P + 1, n3 = n * n * n;
+    __shared__ double tw[n];
+    double J;
+    size_t base;
+    element_mass_setup<P>(A, tw, J, base);
+    for (int r = threadIdx.x; r < n3; r += blockDim.x) {
+        const int a = r % n, b = (r / n) % n, c = r / (n * n);
+        const double v = s * x[base + r] / (J * tw[a] * tw[b] * tw[c]);
+        out[base + r] = f ? v * f[base + r] : v;
     }
 }
 
@@ -661,11 +677,18 @@ __global__ void k_viscosity(const double *vx, const double *vy, const double *vz
 }
 
 // out = (out or 0) + s M x  (nodal field -> weak vector, M the GLL mass)
-__global__ void k_mass(NodalArgs A, const double *x, double s, int accumulate, double *out)
+template <int P>
+__global__ void __launch_bounds__(256) k_mass(NodalArgs A, const double *x, double s, int accumulate, double *out)
 {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < A.N; i += (size_t)gridDim.x * blockDim.x) {
-        const double v = s * x[i] * node_mass(A, i);
-        out[i] = accumulate ? out[i] + v : v;
+    constexpr int n = P + 1, n3 = n * n * n;
+    __shared__ double tw[n];
+    double J;
+    size_t base;
+    element_mass_setup<P>(A, tw, J, base);
+    for (int r = threadIdx.x; r < n3; r += blockDim.x) {
+        const int a = r % n, b = (r / n) % n, c = r / (n * n);
+        const double v = s * x[base + r] * (J * tw[a] * tw[b] * tw[c]);
+        out[base + r] = accumulate ? out[base + r] + v : v;
     }
 }
 
@@ -737,6 +760,48 @@ __global__ void k_lincomb(CombArgs A)
     }
 }
 
+// the same two values per thread with 16-byte accesses (N even, every
+// vector 16-byte aligned); the same arithmetic per value
+__global__ void k_lincomb2(CombArgs A)
+{
+    typedef double dv2 __attribute__((ext_vector_type(2)));
+    const size_t N2 = A.N / 2;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N2; i += (size_t)gridDim.x * blockDim.x) {
+        dv2 s = A.x0 ? ((const dv2 *)A.x0)[i] : dv2{0.0, 0.0};
+        for (int j = 0; j < A.k; ++j) {
+            const dv2 xj = ((const dv2 *)A.x[j])[i];
+            s.x = fma(A.c[j], xj.x, s.x);
+            s.y = fma(A.c[j], xj.y, s.y);
+        }
+        ((dv2 *)A.y)[i] = s;
+    }
+}
+
+// launch a kernel templated on the degree (3..8)
+template <template <int> class K, typename... Args>
+int launch_by_degree(int P, dim3 grid, hipStream_t st, Args... args)
+{
+    switch (P) {
+        case 3: hipLaunchKernelGGL(K<3>::fn, grid, dim3(256), 0, st, args...); break;
+        case 4: hipLaunchKernelGGL(K<4>::fn, grid, dim3(256), 0, st, args...); break;
+        case 5: hipLaunchKernelGGL(K<5>::fn, grid, dim3(256), 0, st, args...); break;
+        case 6: hipLaunchKernelGGL(K<6>::fn, grid, dim3(256), 0, st, args...); break;
+        case 7: hipLaunchKernelGGL(K<7>::fn, grid, dim3(256), 0, st, args...); break;
+        case 8: hipLaunchKernelGGL(K<8>::fn, grid, dim3(256), 0, st, args...); break;
+        default: set_error("degree outside 3..8"); return DG_ERR_ARG;
+    }
+    DG_HIP_CHECK(hipGetLastError());
+    return DG_OK;
+}
+template <int P>
+struct WeakToNodalK {
+    static constexpr auto fn = k_weak_to_nodal<P>;
+};
+template <int P>
+struct MassK {
+    static constexpr auto fn = k_mass<P>;
+};
+
 dim3 flat_grid(size_t N) { return dim3((unsigned)std::max<size_t>(1, std::min<size_t>((N + 255) / 256, 8192))); }
 
 }  // namespace
@@ -744,9 +809,8 @@ dim3 flat_grid(size_t N) { return dim3((unsigned)std::max<size_t>(1, std::min<si
 int launch_weak_to_nodal(const MeshDev &m, const double *x, const double *f, double s, double *out,
                          hipStream_t st)
 {
-    hipLaunchKernelGGL(k_weak_to_nodal, flat_grid((size_t)m.ndof), dim3(256), 0, st, nodal_args(m), x, f, s, out);
-    DG_HIP_CHECK(hipGetLastError());
-    return DG_OK;
+    if (m.nel == 0) return DG_OK;
+    return launch_by_degree<WeakToNodalK>(m.P, dim3((unsigned)m.nel), st, nodal_args(m), x, f, s, out);
 }
 
 int launch_viscosity(const MeshDev &m, const double *const v[3], double nu0, double nu1, double vref,
@@ -761,10 +825,8 @@ int launch_viscosity(const MeshDev &m, const double *const v[3], double nu0, dou
 
 int launch_mass(const MeshDev &m, const double *x, double s, bool accumulate, double *out, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_mass, flat_grid((size_t)m.ndof), dim3(256), 0, st, nodal_args(m), x, s,
-                       accumulate ? 1 : 0, out);
-    DG_HIP_CHECK(hipGetLastError());
-    return DG_OK;
+    if (m.nel == 0) return DG_OK;
+    return launch_by_degree<MassK>(m.P, dim3((unsigned)m.nel), st, nodal_args(m), x, s, accumulate ? 1 : 0, out);
 }
 
 int launch_dirichlet_load(const MeshDev &m, const int bc[3], const double *nu, double nu_c, const double *g,
@@ -822,11 +884,16 @@ int launch_lincomb(size_t N, const double *x0, int k, const double *c, const dou
     a.k = k;
     a.N = N;
     a.y = y;
+    bool vec = N % 2 == 0 && ((uintptr_t)y % 16) == 0 && ((uintptr_t)x0 % 16) == 0;
     for (int j = 0; j < k; ++j) {
         a.c[j] = c[j];
         a.x[j] = xs[j];
+        vec = vec && ((uintptr_t)xs[j] % 16) == 0;
     }
-    hipLaunchKernelGGL(k_lincomb, flat_grid(N), dim3(256), 0, st, a);
+    if (vec)
+        hipLaunchKernelGGL(k_lincomb2, flat_grid(N / 2), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_lincomb, flat_grid(N), dim3(256), 0, st, a);
     DG_HIP_CHECK(hipGetLastError());
     return DG_OK;
 }
