@@ -205,16 +205,56 @@ double now()
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+// Iterations to enqueue before the next look at the device state.  The
+// chunks double (from `first`, up to `cap`) while no convergence rate is
+// known; once two residual norms are known, the reduction per iteration
+// between them predicts the iterations still needed to reach tol2, and the
+// next chunk is 1.25 times that plus one (never more than the doubling
+// schedule would give).  Iterations enqueued past convergence return at once
+// but still cost a launch each; too short a chunk costs a host round trip, so
+// the prediction errs long.  The iteration-0 norm is the device's last true
+// residual when `from_true` (the solve started with r = b - A x).
+struct ChunkPlan {
+    int chunk, cap;
+    bool from_true;
+    double res2 = -1.0;
+    int iter = 0;
+    ChunkPlan(int first, int cap_, bool from_true_) : chunk(first), cap(cap_), from_true(from_true_) {}
+    void next(const CgScalars &h)
+    {
+        const int doubled = std::min(chunk * 2, cap);
+        int pred = doubled;
+        double r0 = res2;
+        int i0 = iter;
+        if (r0 < 0.0 && from_true) {
+            r0 = h.true_res2;
+            i0 = 0;
+        }
+        if (h.fixed_iters > 0) {
+            pred = std::max(1, h.fixed_iters - h.iter);
+        } else if (r0 > 0.0 && h.res2 > 0.0 && h.res2 < r0 && h.iter > i0 && h.tol2 > 0.0 && h.tol2 < h.res2) {
+            const double per = std::log(h.res2 / r0) / (h.iter - i0);  // < 0
+            const double need = std::log(h.tol2 / h.res2) / per;      // > 0
+            if (std::isfinite(need) && need < 1e6) pred = (int)std::ceil(1.25 * need) + 1;
+        }
+        res2 = h.res2;
+        iter = h.iter;
+        chunk = std::max(1, std::min(pred, doubled));
+    }
+};
+
 // Run CG iterations until the device flags completion.  T: vector type.
+// from_true: the device's true residual holds the starting residual norm.
 template <typename T>
 int cg_iterate(dg_mesh *m, const int bc[3], double lambda, const T *nu, double nu_c,
-               CgVecArgs<T> a, CgScalars *dev_sc, CgScalars *host_sc, int cap_hint)
+               CgVecArgs<T> a, CgScalars *dev_sc, CgScalars *host_sc, int cap_hint, bool from_true = false)
 {
     const MeshDev &md = m->dev;
     hipStream_t s = m->stream;
-    int chunk = 4;
+    ChunkPlan plan(4, 64, from_true);
     int launched = 0;
     for (;;) {
+        const int chunk = plan.chunk;
         for (int k = 0; k < chunk; ++k) {
             int rc = launch_apply_cg<T>(md, bc, lambda, nu, nu_c, a.p, const_cast<T *>(a.q),
                                         a.partial, dev_sc, s);
@@ -230,7 +270,7 @@ int cg_iterate(dg_mesh *m, const int bc[3], double lambda, const T *nu, double n
             set_error("CG did not flag completion");
             return DG_ERR_DEVICE;
         }
-        chunk = std::min(chunk * 2, 64);
+        plan.next(*host_sc);
     }
     return DG_OK;
 }
@@ -352,7 +392,7 @@ int solve_fp64(dg_mesh *m, Workspace &w, const int bc[3], double lambda, const d
         return rc;
     if ((rc = cg_restart64(md, a, s))) return rc;
     const int cap = o.fixed_iters > 0 ? o.fixed_iters : o.maxit;
-    if ((rc = cg_iterate<double>(m, bc, lambda, nu, nu_c, a, w.sc, w.host_sc, cap))) return rc;
+    if ((rc = cg_iterate<double>(m, bc, lambda, nu, nu_c, a, w.sc, w.host_sc, cap, true))) return rc;
     if ((rc = cg_finish<double>(md, a, s))) return rc;
     // true residual from x
     if ((rc = launch_resid<double>(md, bc, lambda, nu, nu_c, x, w.b64, w.q64, w.partial,
@@ -408,7 +448,8 @@ struct FdmRun {
     bool f32 = false;  // FP32 transforms (fdm_apply32)
     FdmDev f{};
     CgVecArgs<double> a{};
-    int cap = 0, chunk = 2, launched = 0;
+    int cap = 0, launched = 0;
+    ChunkPlan plan{2, 16, true};
 };
 
 // nu_ref of the preconditioner (one host synchronisation for a nodal nu)
@@ -474,7 +515,7 @@ int fdm_start(dg_mesh *m, FdmRun &R, const dg_solve_opts &o)
     if ((rc = cg_rz(md, a, true, s))) return rc;
     if ((rc = cg_pupdate_fdm(md, a, true, s))) return rc;
     R.cap = o.fixed_iters > 0 ? o.fixed_iters : o.maxit;
-    R.chunk = 2;
+    R.plan = ChunkPlan(2, 16, true);
     R.launched = 0;
     R.done = false;
     return DG_OK;
@@ -488,7 +529,7 @@ int fdm_chunk(dg_mesh *m, FdmRun &R)
     Workspace &w = *R.w;
     hipStream_t s = R.s;
     int rc;
-    for (int k = 0; k < R.chunk; ++k) {
+    for (int k = 0; k < R.plan.chunk; ++k) {
         if ((rc = launch_apply_cg<double>(md, R.bc, R.lambda, R.nu, R.nu_c, R.a.p, w.q64, w.partial, w.sc, s)))
             return rc;
         if ((rc = cg_update_fdm(md, R.a, s))) return rc;
@@ -496,7 +537,7 @@ int fdm_chunk(dg_mesh *m, FdmRun &R)
         if ((rc = cg_rz(md, R.a, false, s))) return rc;
         if ((rc = cg_pupdate_fdm(md, R.a, false, s))) return rc;
     }
-    R.launched += R.chunk;
+    R.launched += R.plan.chunk;
     DG_HIP_CHECK(hipMemcpyAsync(w.host_sc, w.sc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
     return DG_OK;
 }
@@ -513,7 +554,7 @@ int fdm_poll(FdmRun &R)
         set_error("CG did not flag completion");
         return DG_ERR_DEVICE;
     }
-    R.chunk = std::min(R.chunk * 2, 16);
+    R.plan.next(*R.w->host_sc);
     return DG_OK;
 }
 
