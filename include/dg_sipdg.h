@@ -383,8 +383,9 @@ int dg_viscous_fd2(dg_mesh *m, const double *nu, const double *vx, const double 
    transforms for the velocity solves only.  With DG_PC_FDM the
    three velocity solves of a stage, which share their operator, run at once
    on the mesh's stream and two more streams (non-blocking, default
-   priority), each with its own FP64 solve workspace; the streams and
-   workspaces are created at first use and kept with the mesh.  Allocates
+   priority; one pair per device, shared by all meshes, created at first use
+   and kept until the process ends), each with its own FP64 solve workspace
+   (created at first use and kept with the mesh).  Allocates
    the mesh's step workspace (about (9 s' + 14) N doubles, s' the stages
    whose terms the tableau uses) at first use; synchronous.  Returns the
    first error of a kernel or solve, else info->status. */

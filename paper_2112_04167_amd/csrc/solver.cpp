@@ -82,10 +82,10 @@ struct dg_mesh {
     double *aux = nullptr;      // device: the projection's pressure load (ndof doubles)
     double *step_buf = nullptr; // device: the IMEX step's stage fields (grow-only)
     size_t step_doubles = 0;
-    // concurrent solves: the workspaces and streams of the second and third
-    // solve (created on first use), and the event the streams start from
+    // concurrent solves: the workspaces of the second and third solve
+    // (created on first use; their streams are shared by all meshes, see
+    // concurrent_streams), and the event those streams start from
     Workspace alt_ws[kMaxConcurrent - 1];
-    hipStream_t alt_stream[kMaxConcurrent - 1] = {};
     hipEvent_t alt_event = nullptr;
 };
 
@@ -611,6 +611,33 @@ int solve_fdm(dg_mesh *m, Workspace &w, const int bc[3], double lambda, const do
 // its workspace, the others on streams and workspaces of their own (created
 // on first use, kept with the mesh), all driven by this thread.  Returns when
 // every solve has ended.
+// The streams of the second and third concurrent solve: one set per device
+// for the whole process (non-blocking, default priority, created on first
+// use and kept until the process ends), shared by every mesh, so that
+// meshes do not each hold hardware queues of their own.  Concurrent solves
+// of two meshes from two host threads then share these streams: their work
+// is ordered on them, which is correct and only less concurrent.
+int concurrent_streams(hipStream_t (&out)[kMaxConcurrent - 1], bool create)
+{
+    static std::mutex mu;
+    static std::map<int, std::array<hipStream_t, kMaxConcurrent - 1>> pool;
+    int dev = 0;
+    DG_HIP_CHECK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = pool.find(dev);
+    if (it == pool.end()) {
+        if (!create) {
+            for (auto &x : out) x = nullptr;
+            return DG_OK;
+        }
+        std::array<hipStream_t, kMaxConcurrent - 1> a{};
+        for (auto &x : a) DG_HIP_CHECK(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+        it = pool.emplace(dev, a).first;
+    }
+    for (int k = 0; k < kMaxConcurrent - 1; ++k) out[k] = it->second[k];
+    return DG_OK;
+}
+
 int fdm_concurrent(dg_mesh *m, int nsys, double lambda, const double *nu, double nu_c,
                    const double *const *rhs, double *const *x, const int *weak, const dg_solve_opts &o,
                    dg_solve_info *info)
@@ -621,11 +648,11 @@ int fdm_concurrent(dg_mesh *m, int nsys, double lambda, const double *nu, double
     }
     FdmRun R[kMaxConcurrent];
     int rc;
+    hipStream_t alt[kMaxConcurrent - 1] = {};
+    if (nsys > 1 && (rc = concurrent_streams(alt, true))) return rc;
     for (int k = 0; k < nsys; ++k) {
-        if (k > 0 && !m->alt_stream[k - 1])
-            DG_HIP_CHECK(hipStreamCreateWithFlags(&m->alt_stream[k - 1], hipStreamNonBlocking));
         R[k].w = k == 0 ? &m->ws : &m->alt_ws[k - 1];
-        R[k].s = k == 0 ? m->stream : m->alt_stream[k - 1];
+        R[k].s = k == 0 ? m->stream : alt[k - 1];
         R[k].bc = m->dev.bc;
         R[k].lambda = lambda;
         R[k].nu = nu;
@@ -1318,11 +1345,11 @@ int dg_mesh_destroy(dg_mesh *m)
     if (m->geo_block && !m->geo_external) (void)hipFree(m->geo_block);
     if (m->aux) (void)hipFree(m->aux);
     if (m->step_buf) (void)hipFree(m->step_buf);
+    hipStream_t alt[kMaxConcurrent - 1] = {};
+    if (m->alt_ws[0].base && concurrent_streams(alt, false) == DG_OK)
+        for (hipStream_t x : alt)
+            if (x) (void)hipStreamSynchronize(x);
     for (int k = 0; k < kMaxConcurrent - 1; ++k) {
-        if (m->alt_stream[k]) {
-            (void)hipStreamSynchronize(m->alt_stream[k]);
-            (void)hipStreamDestroy(m->alt_stream[k]);
-        }
         if (m->alt_ws[k].base) (void)hipFree(m->alt_ws[k].base);
         if (m->alt_ws[k].host_sc) (void)hipHostFree(m->alt_ws[k].host_sc);
     }
