@@ -100,9 +100,10 @@ double *mesh_step_buffer(dg_mesh *m, size_t doubles);
 // thread (solver.cpp).  The first runs on the mesh's stream; the others
 // start after the work enqueued there so far.  Returns when all have ended,
 // with the worst status; info[k] per solve.  Options are not checked here.
+// true_resid = false: no final b - A x (info true_rel_res = rel_res).
 constexpr int kMaxConcurrent = 3;
 int solve_fdm_concurrent(dg_mesh *m, int nsys, double lambda, const double *nu, double nu_c,
                          const double *const *rhs, double *const *x, const int *weak,
-                         const dg_solve_opts &o, dg_solve_info *info);
+                         const dg_solve_opts &o, dg_solve_info *info, bool true_resid = true);
 
 }  // namespace dg

@@ -461,7 +461,8 @@ int dg_imex_step(dg_mesh *mv, dg_mesh *mp, const dg_tableau *tab, double dt, dou
         if (aii > 0.0) {
             dg_solve_info hi[3] = {};
             if (o.precond == DG_PC_FDM) {
-                rc = solve_fdm_concurrent(mv, 3, lam, nu, 0.0, Gd, Vi, weakd, o, hi);
+                // (the step reports no true residuals: no final b - A x)
+                rc = solve_fdm_concurrent(mv, 3, lam, nu, 0.0, Gd, Vi, weakd, o, hi, false);
                 if (rc < 0) return rc;
                 if (rc > st.status) st.status = rc;
             } else {

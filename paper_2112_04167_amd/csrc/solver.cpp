@@ -445,7 +445,8 @@ struct FdmRun {
     const double *nu = nullptr, *rhs = nullptr;
     double *x = nullptr;
     bool singular = false, done = false;
-    bool f32 = false;  // FP32 transforms (fdm_apply32)
+    bool f32 = false;         // FP32 transforms (fdm_apply32)
+    bool true_resid = true;   // recompute b - A x at the end (info.true_rel_res)
     FdmDev f{};
     CgVecArgs<double> a{};
     int cap = 0, launched = 0;
@@ -566,7 +567,8 @@ int fdm_end(dg_mesh *m, FdmRun &R, dg_solve_info &info)
     hipStream_t s = R.s;
     int rc;
     if ((rc = cg_finish<double>(md, R.a, s))) return rc;
-    if ((rc = launch_resid<double>(md, R.bc, R.lambda, R.nu, R.nu_c, R.x, w.b64, w.q64, w.partial, w.sc, s)))
+    if (R.true_resid &&
+        (rc = launch_resid<double>(md, R.bc, R.lambda, R.nu, R.nu_c, R.x, w.b64, w.q64, w.partial, w.sc, s)))
         return rc;
     DG_HIP_CHECK(hipMemcpyAsync(w.host_sc, w.sc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
     DG_HIP_CHECK(hipStreamSynchronize(s));
@@ -575,7 +577,7 @@ int fdm_end(dg_mesh *m, FdmRun &R, dg_solve_info &info)
     info.outer_iters = 0;
     info.status = h.status;
     info.rel_res = h.bnorm2 > 0 ? std::sqrt(h.res2 / h.bnorm2) : 0.0;
-    info.true_rel_res = h.bnorm2 > 0 ? std::sqrt(h.true_res2 / h.bnorm2) : 0.0;
+    info.true_rel_res = R.true_resid ? (h.bnorm2 > 0 ? std::sqrt(h.true_res2 / h.bnorm2) : 0.0) : info.rel_res;
     return h.status;
 }
 
@@ -640,7 +642,7 @@ int concurrent_streams(hipStream_t (&out)[kMaxConcurrent - 1], bool create)
 
 int fdm_concurrent(dg_mesh *m, int nsys, double lambda, const double *nu, double nu_c,
                    const double *const *rhs, double *const *x, const int *weak, const dg_solve_opts &o,
-                   dg_solve_info *info)
+                   dg_solve_info *info, bool true_resid)
 {
     if (nsys < 1 || nsys > kMaxConcurrent) {
         set_error("concurrent solves: need 1 <= nsys <= 3");
@@ -660,6 +662,7 @@ int fdm_concurrent(dg_mesh *m, int nsys, double lambda, const double *nu, double
         R[k].rhs = rhs[k];
         R[k].x = x[k];
         R[k].f32 = o.precision == DG_MIXED;
+        R[k].true_resid = true_resid;
         if ((rc = fdm_prepare(m, R[k]))) return rc;
     }
     double nu_ref = 0.0;
@@ -1175,10 +1178,10 @@ namespace dg {
 
 int solve_fdm_concurrent(dg_mesh *m, int nsys, double lambda, const double *nu, double nu_c,
                          const double *const *rhs, double *const *x, const int *weak,
-                         const dg_solve_opts &o, dg_solve_info *info)
+                         const dg_solve_opts &o, dg_solve_info *info, bool true_resid)
 {
     if (int rc = check_mesh(m)) return rc;
-    return fdm_concurrent(m, nsys, lambda, nu, nu_c, rhs, x, weak, o, info);
+    return fdm_concurrent(m, nsys, lambda, nu, nu_c, rhs, x, weak, o, info, true_resid);
 }
 
 int mesh_create_impl(int nx, int ny, int nz, int P, const double *xv, const double *yv,
