@@ -386,7 +386,7 @@ int dg_viscous_fd2(dg_mesh *m, const double *nu, const double *vx, const double 
    priority; one pair per device, shared by all meshes, created at first use
    and kept until the process ends), each with its own FP64 solve workspace
    (created at first use and kept with the mesh).  Allocates
-   the mesh's step workspace (about (9 s' + 14) N doubles, s' the stages
+   the mesh's step workspace (about (9 s' + 15) N doubles, s' the stages
    whose terms the tableau uses) at first use; synchronous.  Returns the
    first error of a kernel or solve, else info->status. */
 int dg_imex_step(dg_mesh *mv, dg_mesh *mp, const dg_tableau *tab, double dt, double nu0, double nu1,

@@ -102,6 +102,9 @@ double *mesh_step_buffer(dg_mesh *m, size_t doubles);
 // with the worst status; info[k] per solve.  Options are not checked here.
 // true_resid = false: no final b - A x (info true_rel_res = rel_res).
 constexpr int kMaxConcurrent = 3;
+// the two extra streams of the concurrent solves (one pair per device,
+// shared by all meshes, created on first use; solver.cpp)
+int mesh_concurrent_streams(hipStream_t out[kMaxConcurrent - 1]);
 int solve_fdm_concurrent(dg_mesh *m, int nsys, double lambda, const double *nu, double nu_c,
                          const double *const *rhs, double *const *x, const int *weak,
                          const dg_solve_opts &o, dg_solve_info *info, bool true_resid = true);

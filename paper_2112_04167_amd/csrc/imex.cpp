@@ -202,6 +202,26 @@ int fd3_terms(const MeshDev &md, const double *nu, const double *const v[3], con
     return launch_gradient(md, md, weak, nullptr, -1.0, out, s);
 }
 
+// the events a step orders its streams with (destroyed with the object)
+struct StepEvents {
+    hipEvent_t e[3] = {};
+    int create()
+    {
+        for (hipEvent_t &x : e)
+            if (hipEventCreateWithFlags(&x, hipEventDisableTiming) != hipSuccess) {
+                x = nullptr;
+                set_error("event creation failed");
+                return DG_ERR_DEVICE;
+            }
+        return DG_OK;
+    }
+    ~StepEvents()
+    {
+        for (hipEvent_t x : e)
+            if (x) (void)hipEventDestroy(x);
+    }
+};
+
 }  // namespace
 }  // namespace dg
 
@@ -313,18 +333,18 @@ int dg_imex_step(dg_mesh *mv, dg_mesh *mp, const dg_tableau *tab, double dt, dou
         if (tab->bI[j] - aI(s - 1, j) != 0.0) needD1[j] = 1;
     }
     // workspace: stage velocity (3N), nu (N), F_d2 scratch and the three
-    // Helmholtz loads (9N), weak scratch (N), per used stage C, D1, D3 (9N),
-    // the pressure (Np)
+    // Helmholtz loads (9N), weak scratch of F_d2 and of F_d3 (2N), per used
+    // stage C, D1, D3 (9N), the pressure (Np)
     const size_t N = (size_t)md.ndof, Np = (size_t)mesh_device(mp)->ndof;
     std::vector<int> slot(s, -1);
     int nslots = 0;
     for (int j = 0; j < s; ++j)
         if (needC[j] || needD1[j]) slot[j] = nslots++;
-    double *buf = mesh_step_buffer(mv, (14 + 9 * (size_t)nslots) * N + Np);
+    double *buf = mesh_step_buffer(mv, (15 + 9 * (size_t)nslots) * N + Np);
     if (!buf) return DG_ERR_OOM;
     double *Vi[3] = {buf, buf + N, buf + 2 * N};
-    double *nu = buf + 3 * N, *T = buf + 4 * N, *weak = buf + 13 * N;
-    double *terms = buf + 14 * N, *psi = terms + 9 * (size_t)nslots * N;
+    double *nu = buf + 3 * N, *T = buf + 4 * N, *weak = buf + 13 * N, *weak3 = buf + 14 * N;
+    double *terms = buf + 15 * N, *psi = terms + 9 * (size_t)nslots * N;
     auto C = [&](int j, int d) { return terms + ((size_t)slot[j] * 9 + d) * N; };
     auto D1 = [&](int j, int d) { return terms + ((size_t)slot[j] * 9 + 3 + d) * N; };
     auto D3 = [&](int j, int d) { return terms + ((size_t)slot[j] * 9 + 6 + d) * N; };
@@ -355,25 +375,44 @@ int dg_imex_step(dg_mesh *mv, dg_mesh *mp, const dg_tableau *tab, double dt, dou
     if (op.precond == DG_PC_FDM) op.precision = DG_FP64;
     int rc;
 
+    // A stage's three groups of terms are independent: F_d1 runs on the first
+    // extra stream, F_d3 (with its own scratch) on the second, F_d2 and F_c
+    // on the mesh's stream, which then waits for the other two.
+    hipStream_t alt[kMaxConcurrent - 1] = {};
+    if ((rc = mesh_concurrent_streams(alt))) return rc;
+    StepEvents ev;
+    if ((rc = ev.create())) return rc;
     auto stage_terms = [&](int j, const double *const v[3]) -> int {
         int r;
         const double *wb[3];
         const double *const *vb = walls(j, wb);
+        DG_HIP_CHECK(hipEventRecord(ev.e[0], sv));
+        DG_HIP_CHECK(hipStreamWaitEvent(alt[0], ev.e[0], 0));
+        DG_HIP_CHECK(hipStreamWaitEvent(alt[1], ev.e[0], 0));
         if (needD1[j]) {
             double *out[3] = {D1(j, 0), D1(j, 1), D1(j, 2)};
-            if ((r = fd1_terms(md, nu, v, vb, out, sv))) return r;
+            if ((r = fd1_terms(md, nu, v, vb, out, alt[0]))) return r;
         }
+        double *c3[3] = {nullptr, nullptr, nullptr}, *d3[3] = {nullptr, nullptr, nullptr};
         if (needC[j]) {
-            double *c3[3] = {C(j, 0), C(j, 1), C(j, 2)}, *d3[3] = {D3(j, 0), D3(j, 1), D3(j, 2)};
+            for (int d = 0; d < 3; ++d) {
+                c3[d] = C(j, d);
+                d3[d] = D3(j, d);
+            }
+            if ((r = fd3_terms(md, nu, v, vb, weak3, d3, alt[1]))) return r;
             if ((r = fd2_terms(md, nu, v, T, weak, c3, sv))) return r;
             if ((r = launch_convection(md, v, vb, 1.0, true, c3, sv))) return r;
-            if ((r = fd3_terms(md, nu, v, vb, weak, d3, sv))) return r;
+        }
+        DG_HIP_CHECK(hipEventRecord(ev.e[1], alt[0]));
+        DG_HIP_CHECK(hipEventRecord(ev.e[2], alt[1]));
+        DG_HIP_CHECK(hipStreamWaitEvent(sv, ev.e[1], 0));
+        DG_HIP_CHECK(hipStreamWaitEvent(sv, ev.e[2], 0));
+        if (needC[j])
             for (int d = 0; d < 3; ++d) {
                 const double one = 1.0;
                 const double *x = d3[d];
                 if ((r = launch_lincomb(N, c3[d], 1, &one, &x, c3[d], sv))) return r;
             }
-        }
         return DG_OK;
     };
     // the projection with the wall data vb (null: v_b = 0), or with the

@@ -1176,6 +1176,14 @@ static int scratch_address(void **out)
 
 namespace dg {
 
+int mesh_concurrent_streams(hipStream_t out[kMaxConcurrent - 1])
+{
+    hipStream_t a[kMaxConcurrent - 1] = {};
+    if (int rc = concurrent_streams(a, true)) return rc;
+    for (int k = 0; k < kMaxConcurrent - 1; ++k) out[k] = a[k];
+    return DG_OK;
+}
+
 int solve_fdm_concurrent(dg_mesh *m, int nsys, double lambda, const double *nu, double nu_c,
                          const double *const *rhs, double *const *x, const int *weak,
                          const dg_solve_opts &o, dg_solve_info *info, bool true_resid)
