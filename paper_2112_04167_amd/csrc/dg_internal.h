@@ -101,6 +101,11 @@ double *mesh_step_buffer(dg_mesh *m, size_t doubles);
 // start after the work enqueued there so far.  Returns when all have ended,
 // with the worst status; info[k] per solve.  Options are not checked here.
 // true_resid = false: no final b - A x (info true_rel_res = rel_res).
+// The projection substep as dg_project does it; step_mode: no final b - A x
+// in the pressure solve, and no wait for the device at the end when both
+// meshes share a stream (solver.cpp).
+int project_impl(dg_mesh *mv, dg_mesh *mp, double *const v[3], const double *const vb[3], double *psi,
+                 const dg_solve_opts *opts, dg_solve_info *info, bool step_mode);
 constexpr int kMaxConcurrent = 3;
 // the two extra streams of the concurrent solves (one pair per device,
 // shared by all meshes, created on first use; solver.cpp)

@@ -422,7 +422,7 @@ int dg_imex_step(dg_mesh *mv, dg_mesh *mp, const dg_tableau *tab, double dt, dou
         dg_solve_info pi{};
         const double *b3[3] = {nullptr, nullptr, nullptr};
         for (int d = 0; d < 3; ++d) b3[d] = own_trace ? v[d] : (vb ? vb[d] : nullptr);
-        const int r = dg_project(mv, mp, v[0], v[1], v[2], b3[0], b3[1], b3[2], psi, &op, &pi);
+        const int r = project_impl(mv, mp, v, b3, psi, &op, &pi, true);
         if (r < 0) return r;
         st.solves += 1;
         st.pressure_iters += pi.iters;

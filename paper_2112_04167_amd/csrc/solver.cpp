@@ -584,10 +584,11 @@ int fdm_end(dg_mesh *m, FdmRun &R, dg_solve_info &info)
 // f32: the preconditioner's transforms in FP32 (CG itself stays FP64)
 int solve_fdm(dg_mesh *m, Workspace &w, const int bc[3], double lambda, const double *nu,
               double nu_c, const double *rhs, double *x, const dg_solve_opts &o, dg_solve_info &info,
-              bool f32 = false)
+              bool f32 = false, bool true_resid = true)
 {
     FdmRun R;
     R.f32 = f32;
+    R.true_resid = true_resid;
     R.w = &w;
     R.s = m->stream;
     R.bc = bc;
@@ -886,9 +887,11 @@ int solve_mixed(dg_mesh *m, const int bc[3], double lambda, const double *nu, do
 
 // lent: workspace memory the caller provides (FP64 solves only); nullptr =
 // the mesh's own workspace, allocated on demand
+// true_resid = false: the fast-diagonalisation solve skips its final
+// b - A x (info true_rel_res = rel_res)
 int solve_common(dg_mesh *m, const int bc[3], double lambda, const double *nu, double nu_c,
                  const double *rhs, double *x, const dg_solve_opts *opts, dg_solve_info *info,
-                 Workspace *lent = nullptr)
+                 Workspace *lent = nullptr, bool true_resid = true)
 {
     const double t0 = now();
     if (int rc = check_mesh(m)) return rc;
@@ -919,7 +922,7 @@ int solve_common(dg_mesh *m, const int bc[3], double lambda, const double *nu, d
         return DG_ERR_ARG;
     }
     if (o.precond == DG_PC_FDM) {
-        rc = solve_fdm(m, wk, bc, lambda, nu, nu_c, rhs, x, o, inf, o.precision == DG_MIXED);
+        rc = solve_fdm(m, wk, bc, lambda, nu, nu_c, rhs, x, o, inf, o.precision == DG_MIXED, true_resid);
     } else if (lent) {
         rc = solve_fp64(m, *lent, bc, lambda, nu, nu_c, rhs, x, o, inf);
     } else if (o.precision == DG_MIXED) {
@@ -1190,6 +1193,58 @@ int solve_fdm_concurrent(dg_mesh *m, int nsys, double lambda, const double *nu, 
 {
     if (int rc = check_mesh(m)) return rc;
     return fdm_concurrent(m, nsys, lambda, nu, nu_c, rhs, x, weak, o, info, true_resid);
+}
+
+// The projection substep (dg_project).  step_mode (the IMEX step): the
+// pressure solve skips its final b - A x, and the call returns without
+// waiting for the device when both meshes share a stream (the step's next
+// work is ordered after it there).
+int project_impl(dg_mesh *mv, dg_mesh *mp, double *const vv[3], const double *const vbv[3], double *psi,
+                 const dg_solve_opts *opts, dg_solve_info *info, bool step_mode)
+{
+    double *vx = vv[0], *vy = vv[1], *vz = vv[2];
+    const double t0 = now();
+    if (int rc = check_mesh(mv)) return rc;
+    if (int rc = check_mesh(mp)) return rc;
+    if (!vx || !vy || !vz || !psi) {
+        set_error("null velocity or pressure array");
+        return DG_ERR_ARG;
+    }
+    // the pressure load -D(v'; v_b), a weak vector, in the pressure mesh's
+    // own buffer, on the pressure mesh's stream after the velocity's work
+    if (!mp->aux) {
+        hipError_t e = hipMalloc((void **)&mp->aux, (size_t)mp->dev.ndof * sizeof(double));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            mp->aux = nullptr;
+            set_error("projection load allocation failed");
+            return DG_ERR_OOM;
+        }
+    }
+    if (mv->stream != mp->stream) DG_HIP_CHECK(hipStreamSynchronize(mv->stream));
+    const double *v[3] = {vx, vy, vz}, *vb[3] = {vbv[0], vbv[1], vbv[2]};
+    int rc = launch_divergence(mv->dev, mp->dev, v, vb, -1.0, mp->aux, mp->stream);
+    if (rc) return rc;
+    dg_solve_opts o;
+    dg_default_opts(&o);
+    if (opts) o = *opts;
+    o.rhs_is_weak = 1;
+    dg_solve_info pinfo{};
+    int pbc[3];
+    for (int d = 0; d < 3; ++d)
+        pbc[d] = mp->dev.bc[d] == DG_BC_DIRICHLET ? DG_BC_NEUMANN : mp->dev.bc[d];
+    rc = solve_common(mp, pbc, 0.0, nullptr, 1.0, mp->aux, psi, &o, &pinfo, nullptr, !step_mode);
+    if (rc < 0) {
+        if (info) *info = pinfo;
+        return rc;
+    }
+    double *g[3] = {vx, vy, vz};
+    const int rc2 = launch_gradient(mv->dev, mp->dev, psi, v, -1.0, g, mp->stream);
+    if (rc2) return rc2;
+    if (!step_mode || mv->stream != mp->stream) DG_HIP_CHECK(hipStreamSynchronize(mp->stream));
+    pinfo.seconds = now() - t0;
+    if (info) *info = pinfo;
+    return rc;
 }
 
 int mesh_create_impl(int nx, int ny, int nz, int P, const double *xv, const double *yv,
@@ -1597,45 +1652,9 @@ int dg_project(dg_mesh *mv, dg_mesh *mp, double *vx, double *vy, double *vz, con
                const double *vby, const double *vbz, double *psi, const dg_solve_opts *opts,
                dg_solve_info *info)
 {
-    const double t0 = now();
-    if (int rc = check_mesh(mv)) return rc;
-    if (int rc = check_mesh(mp)) return rc;
-    if (!vx || !vy || !vz || !psi) {
-        set_error("null velocity or pressure array");
-        return DG_ERR_ARG;
-    }
-    // the pressure load -D(v'; v_b), a weak vector, in the pressure mesh's
-    // own buffer, on the pressure mesh's stream after the velocity's work
-    if (!mp->aux) {
-        hipError_t e = hipMalloc((void **)&mp->aux, (size_t)mp->dev.ndof * sizeof(double));
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            mp->aux = nullptr;
-            set_error("projection load allocation failed");
-            return DG_ERR_OOM;
-        }
-    }
-    if (mv->stream != mp->stream) DG_HIP_CHECK(hipStreamSynchronize(mv->stream));
-    const double *v[3] = {vx, vy, vz}, *vb[3] = {vbx, vby, vbz};
-    int rc = launch_divergence(mv->dev, mp->dev, v, vb, -1.0, mp->aux, mp->stream);
-    if (rc) return rc;
-    dg_solve_opts o;
-    dg_default_opts(&o);
-    if (opts) o = *opts;
-    o.rhs_is_weak = 1;
-    dg_solve_info pinfo{};
-    rc = poisson_solve(mp, mp->aux, psi, &o, &pinfo);
-    if (rc < 0) {
-        if (info) *info = pinfo;
-        return rc;
-    }
-    double *g[3] = {vx, vy, vz};
-    const int rc2 = launch_gradient(mv->dev, mp->dev, psi, v, -1.0, g, mp->stream);
-    if (rc2) return rc2;
-    DG_HIP_CHECK(hipStreamSynchronize(mp->stream));
-    pinfo.seconds = now() - t0;
-    if (info) *info = pinfo;
-    return rc;
+    double *v[3] = {vx, vy, vz};
+    const double *vb[3] = {vbx, vby, vbz};
+    return project_impl(mv, mp, v, vb, psi, opts, info, false);
 }
 
 int dg_viscosity(dg_mesh *m, const double *vx, const double *vy, const double *vz, double nu0,
