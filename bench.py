@@ -412,6 +412,26 @@ def bench_batched(dg, torch):
     sequential(ofdm)   # untimed: the host eigendecompositions of both BC sets
     tf, seqf = sequential(ofdm)
     err_fdm = errs_to([x.clone() for x in xs], x_ref64)
+    # the 4 systems as ordinary solves at once on separate streams
+    # (DG_BATCH_CONCURRENT: the Poisson system FDM-preconditioned, the
+    # velocity systems Jacobi FP64), against the same solves one after another
+    dg.helmholtz_solve_batched(mesh, lams, nus, pois, fs, xs, o64, concurrent=True)   # warm: workspaces
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rcc, infosc = dg.helmholtz_solve_batched(mesh, lams, nus, pois, fs, xs, o64, concurrent=True)
+    tc = time.perf_counter() - t0
+    x_conc = [x.clone() for x in xs]
+    for xk in xs:
+        xk.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(4):
+        if pois[k]:
+            dg.poisson_solve(mesh, fs[k], xs[k], ofdm)
+        else:
+            dg.helmholtz_solve(mesh, lam, nu, 0.0, fs[k], xs[k], o64)
+    tcs = time.perf_counter() - t0
+    conc_same = all(bool(torch.equal(a, b)) for a, b in zip(x_conc, xs))
     mesh.destroy()
     return dict(ndof_per_field=N, batched_seconds=tb, batched_solves_per_s=4.0 / tb,
                 sequential_fp64_seconds=ts, sequential_fp64_solves_per_s=4.0 / ts,
@@ -426,6 +446,11 @@ def bench_batched(dg, torch):
                 fp64_iters=[i["iters"] for i in seq],
                 sequential_mixed_iters=[i["iters"] for i in seqm],
                 sequential_mixed_true_rel_res=[i["true_rel_res"] for i in seqm],
+                concurrent_seconds=tc, concurrent_solves_per_s=4.0 / tc, concurrent_status=rcc,
+                concurrent_iters=[i["iters"] for i in infosc],
+                concurrent_sequential_same_preconditioners_seconds=tcs,
+                concurrent_speedup_vs_sequential=tcs / tc, concurrent_speedup_vs_persistent=tb / tc,
+                concurrent_equals_sequential_bitwise=conc_same,
                 # the 4 systems one after another, CG preconditioned by the
                 # fast-diagonalisation inverse (FP64; nu_ref for the nodal nu)
                 sequential_fdm_seconds=tf, sequential_fdm_solves_per_s=4.0 / tf,

@@ -418,9 +418,19 @@ int helmholtz_solve_batched(dg_mesh *m, int nsys, const double *lambdas,
    poisson_solve with the same options), starting from its current solution.
    With one system left, ordinary kernel launches cost less per iteration
    than the launch's two grid barriers.  The system's info then counts the
-   iterations and replacements of both parts.  flags = 0 is
-   helmholtz_solve_batched. */
-enum { DG_BATCH_HANDOFF = 1 };
+   iterations and replacements of both parts.  DG_BATCH_CONCURRENT (nsys <=
+   4): no persistent launch; the systems run as ordinary single-system
+   solves at once, the first on the mesh's stream and the others on extra
+   streams (one set per device shared by all meshes, non-blocking, default
+   priority, kept until the process ends), each with an FP64 solve
+   workspace of its own (kept with the mesh).  Poisson systems use the FP64
+   fast-diagonalisation preconditioner (exact for their constant
+   coefficient); the others use opts.precond: DG_PC_JACOBI runs FP64
+   Jacobi-PCG (DG_ERR_ARG with DG_MIXED), DG_PC_FDM runs FDM-PCG with FP64
+   or, for DG_MIXED, FP32 transforms.  Each system gets the result of the
+   corresponding single-system solve started from zero, bit for bit.
+   flags = 0 is helmholtz_solve_batched. */
+enum { DG_BATCH_HANDOFF = 1, DG_BATCH_CONCURRENT = 2 };
 int helmholtz_solve_batched_ex(dg_mesh *m, int nsys, const double *lambdas,
                                const double *const *nu_fields, const int *is_poisson,
                                const double *const *rhs, double *const *x,

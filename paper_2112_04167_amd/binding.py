@@ -20,6 +20,7 @@ DG_ERR_ARG, DG_ERR_OOM, DG_ERR_DEVICE, DG_ERR_NOT_SPD, DG_ERR_NONFINITE, DG_ERR_
 DG_BC_PERIODIC, DG_BC_DIRICHLET, DG_BC_NEUMANN = 0, 1, 2
 DG_FP64, DG_FP32, DG_MIXED = 0, 1, 1
 DG_BATCH_HANDOFF = 1
+DG_BATCH_CONCURRENT = 2
 DG_PC_JACOBI, DG_PC_FDM = 0, 1
 
 STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", 2: "PENDING", -1: "ERR_ARG", -2: "ERR_OOM",
@@ -474,7 +475,7 @@ def poisson_solve(mesh, rhs, x, opts=None, raise_on_error=True):
 
 
 def helmholtz_solve_batched(mesh, lambdas, nu_fields, is_poisson, rhs, xs, opts=None,
-                            raise_on_error=True, handoff=False):
+                            raise_on_error=True, handoff=False, concurrent=False):
     import torch
     n = len(rhs)
     lam = (ctypes.c_double * n)(*[float(v) for v in lambdas])
@@ -486,7 +487,8 @@ def helmholtz_solve_batched(mesh, lambdas, nu_fields, is_poisson, rhs, xs, opts=
     infos = (dg_solve_info * n)()
     rc = lib().helmholtz_solve_batched_ex(mesh.handle, n, lam, nus, pois, rr, xx,
                                           ctypes.byref(opts) if opts is not None else None, infos,
-                                          DG_BATCH_HANDOFF if handoff else 0)
+                                          (DG_BATCH_HANDOFF if handoff else 0) |
+                                          (DG_BATCH_CONCURRENT if concurrent else 0))
     if raise_on_error:
         _check(rc, allow_warning=True)
     return rc, [i.as_dict() for i in infos]

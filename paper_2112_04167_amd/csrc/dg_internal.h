@@ -93,7 +93,7 @@ const MeshDev *mesh_device(dg_mesh *m);
 hipStream_t mesh_stream(dg_mesh *m);
 double *mesh_step_buffer(dg_mesh *m, size_t doubles);
 
-// Up to kMaxConcurrent FP64 solves preconditioned by fast diagonalisation,
+// Up to kMaxConcurrent FP64 CG solves preconditioned by fast diagonalisation,
 // of one Helmholtz operator (lambda, nu field or nu_c, the mesh's BCs) with
 // different right-hand sides rhs[k] (weak[k]: a weak load) and initial
 // guesses / solutions x[k], run at once on separate streams from this
@@ -106,7 +106,7 @@ double *mesh_step_buffer(dg_mesh *m, size_t doubles);
 // meshes share a stream (solver.cpp).
 int project_impl(dg_mesh *mv, dg_mesh *mp, double *const v[3], const double *const vb[3], double *psi,
                  const dg_solve_opts *opts, dg_solve_info *info, bool step_mode);
-constexpr int kMaxConcurrent = 3;
+constexpr int kMaxConcurrent = 4;
 // the two extra streams of the concurrent solves (one pair per device,
 // shared by all meshes, created on first use; solver.cpp)
 int mesh_concurrent_streams(hipStream_t out[kMaxConcurrent - 1]);

@@ -436,11 +436,14 @@ int ensure_fdm_tables(dg_mesh *m, Workspace &w, const int bc[3], FdmDev &f)
 // The solve is split into phases (prepare, start, chunks of iterations with a
 // poll of the device state after each, end) so that one host thread can run
 // several such solves at once on separate streams; each solve does the same
-// arithmetic whether it runs alone or beside others.
+// arithmetic whether it runs alone or beside others.  A run is FP64 CG
+// preconditioned by fast diagonalisation or, with `jacobi`, FP64 Jacobi-PCG
+// (the arithmetic of solve_fp64).
 struct FdmRun {
     Workspace *w = nullptr;
     hipStream_t s = nullptr;
     const int *bc = nullptr;
+    bool jacobi = false;
     double lambda = 0.0, nu_c = 0.0, nu_ref = 0.0;
     const double *nu = nullptr, *rhs = nullptr;
     double *x = nullptr;
@@ -473,6 +476,7 @@ int fdm_nu_ref(dg_mesh *m, Workspace &w, const double *nu, double nu_c, double &
 int fdm_prepare(dg_mesh *m, FdmRun &R)
 {
     if (int rc = ensure_workspace(m, *R.w, DG_FP64)) return rc;
+    if (R.jacobi) return R.nu ? DG_OK : upload_diag_tables(m, *R.w, R.bc, R.nu_c);
     return ensure_fdm_tables(m, *R.w, R.bc, R.f);
 }
 
@@ -486,9 +490,49 @@ int fdm_precond(const MeshDev &md, FdmRun &R)
     return fdm_apply(md, R.f, R.lambda, R.nu_ref, R.singular, w.r64, w.d64, w.q64, w.sc, R.s);
 }
 
+// Jacobi-PCG start: b, the diagonal (nodal nu) or its tables, r = b - A x
+// from the caller's x and the restart from r, as in solve_fp64
+int jacobi_start(dg_mesh *m, FdmRun &R, const dg_solve_opts &o)
+{
+    const MeshDev &md = m->dev;
+    Workspace &w = *R.w;
+    hipStream_t s = R.s;
+    int rc;
+    R.singular = (R.lambda == 0.0) && !has_dirichlet(R.bc);
+    *w.host_sc = init_scalars(md, o.tol, o.maxit, o.fixed_iters, R.singular);
+    DG_HIP_CHECK(hipMemcpyAsync(w.sc, w.host_sc, sizeof(CgScalars), hipMemcpyHostToDevice, s));
+    CgVecArgs<double> &a = R.a;
+    a = vec_args<double>(w, R.singular, w.sc);
+    if (R.nu) {
+        if ((rc = launch_diag<double>(md, R.bc, R.lambda, R.nu, R.nu_c, w.d64, s, true))) return rc;
+        a.d = w.d64;
+    } else {
+        a.dtab = w.dtab64;
+        a.lam = R.lambda;
+    }
+    a.x = R.x;
+    a.r = w.r64;
+    a.p = w.p64;
+    a.q = w.q64;
+    a.src = R.rhs;
+    a.bvec = w.b64;
+    a.weak = o.rhs_is_weak;
+    a.keep_x = 1;
+    if ((rc = cg_setup<double>(md, a, s))) return rc;
+    if ((rc = launch_resid<double>(md, R.bc, R.lambda, R.nu, R.nu_c, R.x, w.b64, w.r64, w.partial, w.sc, s)))
+        return rc;
+    if ((rc = cg_restart64(md, a, s))) return rc;
+    R.cap = o.fixed_iters > 0 ? o.fixed_iters : o.maxit;
+    R.plan = ChunkPlan(4, 64, true);
+    R.launched = 0;
+    R.done = false;
+    return DG_OK;
+}
+
 // b, r = b - A x from the caller's x, the first preconditioned direction
 int fdm_start(dg_mesh *m, FdmRun &R, const dg_solve_opts &o)
 {
+    if (R.jacobi) return jacobi_start(m, R, o);
     const MeshDev &md = m->dev;
     Workspace &w = *R.w;
     hipStream_t s = R.s;
@@ -530,6 +574,17 @@ int fdm_chunk(dg_mesh *m, FdmRun &R)
     Workspace &w = *R.w;
     hipStream_t s = R.s;
     int rc;
+    if (R.jacobi) {
+        for (int k = 0; k < R.plan.chunk; ++k) {
+            if ((rc = launch_apply_cg<double>(md, R.bc, R.lambda, R.nu, R.nu_c, R.a.p, w.q64, w.partial, w.sc, s)))
+                return rc;
+            if ((rc = cg_update<double>(md, R.a, s))) return rc;
+            if ((rc = cg_pupdate<double>(md, R.a, s))) return rc;
+        }
+        R.launched += R.plan.chunk;
+        DG_HIP_CHECK(hipMemcpyAsync(w.host_sc, w.sc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
+        return DG_OK;
+    }
     for (int k = 0; k < R.plan.chunk; ++k) {
         if ((rc = launch_apply_cg<double>(md, R.bc, R.lambda, R.nu, R.nu_c, R.a.p, w.q64, w.partial, w.sc, s)))
             return rc;
@@ -608,13 +663,7 @@ int solve_fdm(dg_mesh *m, Workspace &w, const int bc[3], double lambda, const do
     return fdm_end(m, R, info);
 }
 
-// Up to kMaxConcurrent FDM-PCG solves of one operator (lambda, nu, the
-// mesh's BCs) with different right-hand sides (weak[k]: rhs k is a weak
-// load; null: as o says), run at once: the first on the mesh's stream with
-// its workspace, the others on streams and workspaces of their own (created
-// on first use, kept with the mesh), all driven by this thread.  Returns when
-// every solve has ended.
-// The streams of the second and third concurrent solve: one set per device
+// The streams of the second to last concurrent solve: one set per device
 // for the whole process (non-blocking, default priority, created on first
 // use and kept until the process ends), shared by every mesh, so that
 // meshes do not each hold hardware queues of their own.  Concurrent solves
@@ -641,12 +690,29 @@ int concurrent_streams(hipStream_t (&out)[kMaxConcurrent - 1], bool create)
     return DG_OK;
 }
 
-int fdm_concurrent(dg_mesh *m, int nsys, double lambda, const double *nu, double nu_c,
-                   const double *const *rhs, double *const *x, const int *weak, const dg_solve_opts &o,
-                   dg_solve_info *info, bool true_resid)
+// One system of a concurrent run: its operator (BCs, lambda, nu field or
+// nu_c), right-hand side (weak: a weak load), solution, and preconditioner
+// (jacobi: Jacobi-PCG in FP64, else fast diagonalisation, FP32 transforms
+// when f32).
+struct ConcSys {
+    int bc[3];
+    double lambda;
+    const double *nu;
+    double nu_c;
+    const double *rhs;
+    double *x;
+    int weak;
+    bool jacobi, f32;
+};
+
+// Up to kMaxConcurrent solves at once: the first on the mesh's stream with
+// its workspace, the others on the shared extra streams with workspaces of
+// the mesh's own (created on first use).
+int conc_solve(dg_mesh *m, int nsys, const ConcSys *sys, const dg_solve_opts &o, dg_solve_info *info,
+               bool true_resid)
 {
     if (nsys < 1 || nsys > kMaxConcurrent) {
-        set_error("concurrent solves: need 1 <= nsys <= 3");
+        set_error("concurrent solves: need 1 <= nsys <= 4");
         return DG_ERR_ARG;
     }
     FdmRun R[kMaxConcurrent];
@@ -656,18 +722,27 @@ int fdm_concurrent(dg_mesh *m, int nsys, double lambda, const double *nu, double
     for (int k = 0; k < nsys; ++k) {
         R[k].w = k == 0 ? &m->ws : &m->alt_ws[k - 1];
         R[k].s = k == 0 ? m->stream : alt[k - 1];
-        R[k].bc = m->dev.bc;
-        R[k].lambda = lambda;
-        R[k].nu = nu;
-        R[k].nu_c = nu_c;
-        R[k].rhs = rhs[k];
-        R[k].x = x[k];
-        R[k].f32 = o.precision == DG_MIXED;
+        R[k].bc = sys[k].bc;
+        R[k].jacobi = sys[k].jacobi;
+        R[k].lambda = sys[k].lambda;
+        R[k].nu = sys[k].nu;
+        R[k].nu_c = sys[k].nu_c;
+        R[k].rhs = sys[k].rhs;
+        R[k].x = sys[k].x;
+        R[k].f32 = sys[k].f32;
         R[k].true_resid = true_resid;
         if ((rc = fdm_prepare(m, R[k]))) return rc;
     }
-    double nu_ref = 0.0;
-    if ((rc = fdm_nu_ref(m, m->ws, nu, nu_c, nu_ref))) return rc;
+    // nu_ref of the fast-diagonalisation runs, once per nu field
+    for (int k = 0; k < nsys; ++k) {
+        if (R[k].jacobi) continue;
+        int j = 0;
+        while (j < k && (R[j].jacobi || R[j].nu != R[k].nu || R[j].nu_c != R[k].nu_c)) ++j;
+        if (j < k)
+            R[k].nu_ref = R[j].nu_ref;
+        else if ((rc = fdm_nu_ref(m, m->ws, R[k].nu, R[k].nu_c, R[k].nu_ref)))
+            return rc;
+    }
     // the other streams start after the mesh's stream has done its work so
     // far (the right-hand sides, the tables)
     if (nsys > 1) {
@@ -676,9 +751,8 @@ int fdm_concurrent(dg_mesh *m, int nsys, double lambda, const double *nu, double
         for (int k = 1; k < nsys; ++k) DG_HIP_CHECK(hipStreamWaitEvent(R[k].s, m->alt_event, 0));
     }
     for (int k = 0; k < nsys; ++k) {
-        R[k].nu_ref = nu_ref;
         dg_solve_opts ok = o;
-        if (weak) ok.rhs_is_weak = weak[k];
+        ok.rhs_is_weak = sys[k].weak;
         if ((rc = fdm_start(m, R[k], ok))) return rc;
     }
     for (;;) {
@@ -700,6 +774,29 @@ int fdm_concurrent(dg_mesh *m, int nsys, double lambda, const double *nu, double
         else if (rc > 0 && worst == DG_OK) worst = rc;
     }
     return worst;
+}
+
+int fdm_concurrent(dg_mesh *m, int nsys, double lambda, const double *nu, double nu_c,
+                   const double *const *rhs, double *const *x, const int *weak, const dg_solve_opts &o,
+                   dg_solve_info *info, bool true_resid)
+{
+    if (nsys < 1 || nsys > kMaxConcurrent) {
+        set_error("concurrent solves: need 1 <= nsys <= 4");
+        return DG_ERR_ARG;
+    }
+    ConcSys sys[kMaxConcurrent];
+    for (int k = 0; k < nsys; ++k) {
+        for (int d = 0; d < 3; ++d) sys[k].bc[d] = m->dev.bc[d];
+        sys[k].lambda = lambda;
+        sys[k].nu = nu;
+        sys[k].nu_c = nu_c;
+        sys[k].rhs = rhs[k];
+        sys[k].x = x[k];
+        sys[k].weak = weak ? weak[k] : o.rhs_is_weak;
+        sys[k].jacobi = false;
+        sys[k].f32 = o.precision == DG_MIXED;
+    }
+    return conc_solve(m, nsys, sys, o, info, true_resid);
 }
 
 // FP64 refinement around FP32 Jacobi-PCG with residual replacement: the FP32
@@ -1552,7 +1649,7 @@ int helmholtz_solve_batched_ex(dg_mesh *m, int nsys, const double *lambdas,
                 return DG_ERR_ARG;
             }
     }
-    if (flags & ~DG_BATCH_HANDOFF) {
+    if (flags & ~(DG_BATCH_HANDOFF | DG_BATCH_CONCURRENT)) {
         set_error("unknown batched-solve flags");
         return DG_ERR_ARG;
     }
@@ -1560,7 +1657,42 @@ int helmholtz_solve_batched_ex(dg_mesh *m, int nsys, const double *lambdas,
         set_error("unknown preconditioner");
         return DG_ERR_ARG;
     }
-    int rc = solve_batched(m, nsys, lambdas, nu_fields, is_poisson, rhs, x, o, infos, flags);
+    int rc;
+    if (flags & DG_BATCH_CONCURRENT) {
+        // ordinary single-system solves at once on separate streams: the
+        // Poisson systems with the FP64 fast-diagonalisation inverse (exact
+        // for their constant coefficient), the Helmholtz systems with
+        // opts.precond (Jacobi: FP64 only; fast diagonalisation: FP32
+        // transforms with DG_MIXED); every x starts from zero
+        if (nsys > kMaxConcurrent) {
+            set_error("concurrent batched solve: at most 4 systems");
+            return DG_ERR_ARG;
+        }
+        ConcSys sys[kMaxConcurrent];
+        for (int k = 0; k < nsys; ++k) {
+            const bool pois = is_poisson && is_poisson[k];
+            for (int d = 0; d < 3; ++d)
+                sys[k].bc[d] = pois && m->dev.bc[d] == DG_BC_DIRICHLET ? DG_BC_NEUMANN : m->dev.bc[d];
+            sys[k].lambda = pois ? 0.0 : lambdas[k];
+            sys[k].nu = pois || !nu_fields ? nullptr : nu_fields[k];
+            sys[k].nu_c = 1.0;
+            sys[k].rhs = rhs[k];
+            sys[k].x = x[k];
+            sys[k].weak = o.rhs_is_weak;
+            sys[k].jacobi = !pois && o.precond == DG_PC_JACOBI;
+            sys[k].f32 = !pois && o.precond == DG_PC_FDM && o.precision == DG_MIXED;
+            if (sys[k].jacobi && o.precision != DG_FP64) {
+                set_error("concurrent batched solve: the Jacobi-preconditioned systems run in FP64 only");
+                return DG_ERR_ARG;
+            }
+        }
+        for (int k = 0; k < nsys; ++k)
+            if ((rc = launch_lincomb((size_t)m->dev.ndof, nullptr, 0, nullptr, nullptr, x[k], m->stream)))
+                return rc;
+        rc = conc_solve(m, nsys, sys, o, infos, true);
+    } else {
+        rc = solve_batched(m, nsys, lambdas, nu_fields, is_poisson, rhs, x, o, infos, flags);
+    }
     if (infos)
         for (int k = 0; k < nsys; ++k) infos[k].seconds = now() - t0;
     return rc;

@@ -25,7 +25,7 @@ def rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
-def run_batched(spec, lams, nus, pois, fs, precision=1, handoff=False, **kw):
+def run_batched(spec, lams, nus, pois, fs, precision=1, handoff=False, concurrent=False, **kw):
     import paper_2112_04167_amd as dg
     torch, dev = torch_dev()
     mesh = dg.mesh_from_spec(spec)
@@ -34,7 +34,7 @@ def run_batched(spec, lams, nus, pois, fs, precision=1, handoff=False, **kw):
     nud = [None if v is None else to_dev(v) for v in nus]
     o = dg.default_opts(precision=precision, **kw)
     rc, infos = dg.helmholtz_solve_batched(mesh, lams, nud, pois, rhs, xs, o, raise_on_error=False,
-                                           handoff=handoff)
+                                           handoff=handoff, concurrent=concurrent)
     if rc < 0:
         say("batched solve returned", rc, dg.last_error())
     out = [x.cpu().numpy() for x in xs]
@@ -244,3 +244,73 @@ def test_batched_handoff_with_fdm_continuation():
     say("pressure via fdm continuation, err vs x*", rel(xs[3], xp))
     assert rel(xs[3], xp) <= 1e-10
     assert infos[3]["iters"] < 60   # launch iterations + the FDM continuation
+
+
+# DG_BATCH_CONCURRENT: the systems as ordinary single-system solves at once
+# on separate streams -- the Poisson system with the FP64 fast-diagonalisation
+# preconditioner, the velocity systems with opts.precond
+
+
+@pytest.mark.parametrize("precond,precision", [(0, 0), (1, 0), (1, 1)],
+                         ids=["jacobi_fp64", "fdm_fp64", "fdm_fp32_transforms"])
+def test_concurrent_batched_equals_single_solves_bitwise(precond, precision):
+    # each system gets exactly the single-system solve's result (same
+    # arithmetic, only the streams differ); x starts from zero either way
+    import paper_2112_04167_amd as dg
+    torch, dev = torch_dev()
+    spec = make_spec((3, 3, 3), 5, (0, 0, 1), True)
+    lams, nus, pois, fs, nu, lam = stage_problem(spec)
+    rc, infos, xc = run_batched(spec, lams, nus, pois, fs, precision=precision, concurrent=True,
+                                precond=precond)
+    say("concurrent batched", rc, infos)
+    assert rc == 0
+    mesh = dg.mesh_from_spec(spec)
+    ov = dg.default_opts(precision=precision, precond=precond)
+    op = dg.default_opts(precond=dg.DG_PC_FDM)
+    for k in range(4):
+        fd = to_dev(fs[k])
+        xd = torch.zeros_like(fd)
+        if pois[k]:
+            info = dg.poisson_solve(mesh, fd, xd, op)
+        else:
+            info = dg.helmholtz_solve(mesh, lams[k], to_dev(nus[k]), 0.0, fd, xd, ov)
+        assert info["status"] == 0 and infos[k]["status"] == 0
+        assert infos[k]["iters"] == info["iters"], k
+        same = bool(np.array_equal(xc[k], xd.cpu().numpy()))
+        say("concurrent vs single", k, info["iters"], same)
+        assert same, k
+    mesh.destroy()
+
+
+def test_concurrent_batched_against_exact():
+    spec = make_spec((2, 3, 2), 5, (0, 0, 1), False)
+    lams, nus, pois, fs, nu, lam = stage_problem(spec)
+    rc, infos, xs = run_batched(spec, lams, nus, pois, fs, precision=0, concurrent=True)
+    assert rc == 0
+    M = dense.mass_diag(spec)
+    A = dense.assemble(spec, lam, nu)
+    for k in range(3):
+        xs_ = dense.solve(spec, A, M * fs[k], lam)
+        say("concurrent velocity err", k, rel(xs[k], xs_))
+        assert infos[k]["status"] == 0 and rel(xs[k], xs_) <= 1e-10
+    pspec = dict(spec)
+    pspec["bc"] = (0, 0, 2)
+    Mp = dense.mass_diag(pspec)
+    xp = kron.FDM(pspec, 0.0).solve(Mp * fs[3])
+    say("concurrent pressure err", rel(xs[3], xp), infos[3])
+    assert infos[3]["status"] == 0 and infos[3]["iters"] <= 2
+    assert rel(xs[3], xp) <= 1e-10
+    assert abs(np.dot(Mp, xs[3])) <= 1e-12 * np.linalg.norm(xs[3])
+
+
+def test_concurrent_batched_argument_errors():
+    import paper_2112_04167_amd as dg
+    spec = make_spec((2, 2, 2), 4, (0, 0, 1), False)
+    lams, nus, pois, fs, nu, lam = stage_problem(spec)
+    # Jacobi systems run in FP64 only
+    rc, _, _ = run_batched(spec, lams, nus, pois, fs, precision=1, concurrent=True, precond=0)
+    assert rc == dg.DG_ERR_ARG
+    # at most four systems
+    rc, _, _ = run_batched(spec, lams + [lam], nus + [nu], pois + [0], fs + [fs[0]], precision=0,
+                           concurrent=True)
+    assert rc == dg.DG_ERR_ARG
