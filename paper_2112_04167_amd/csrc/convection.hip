@@ -46,18 +46,35 @@ __host__ __device__ constexpr int conv_q(int P) { return 3 * P / 2 + 1; }
 // the Q Gauss-Legendre points, the Gauss weights and the GLL weights (the
 // mass).  The Gauss points are the roots of L_Q, by Newton's method on the
 // Legendre recurrence from the starting points -cos(pi (j + 3/4) / (Q + 1/2)),
-// then symmetrised; the weights are 2 / ((1 - x^2) L_Q'(x)^2).  Kept in
-// __constant__ memory: with compile-time indices the kernel reads them with
-// wide scalar loads.
+// then symmetrised; the weights are 2 / ((1 - x^2) L_Q'(x)^2).
+//
+// Both point sets are symmetric about 0, so B[Q-1-q][n-1-a] = B[q][a] and
+// dB[Q-1-q][n-1-a] = -dB[q][a], and every contraction splits into an even
+// and an odd half (Solomonoff's even-odd decomposition): with e, o the sums
+// and differences of mirrored inputs, half the multiply-adds and half the
+// distinct coefficients.  The half tables (h = floor, the middle row or
+// column of an odd size taken alone, so that the vanishing half of it is
+// never formed):
+//   nodes -> Gauss points, y = B x:       FE, FO [q < ceil(Q/2)][a < n/2], FM[q] = B[q][mid];
+//   Gauss points -> nodes, y = B^T x:     TE [a < ceil(n/2)][q < Q/2], TO [a < n/2][q < Q/2], TM[a] = B[Q/2][a];
+//   Gauss points -> nodes, y = dB^T x:    DE [a < ceil(n/2)][q < Q/2] (on o), DO [a < n/2][q < Q/2] (on e),
+//                                         DM[a] = dB[Q/2][a].
+// Every index is a compile-time constant where the kernel uses them, so the
+// compiler emits the coefficients as immediates.
 template <int P>
 struct ConvTab {
     static constexpr int n = P + 1, Q = conv_q(P);
+    static constexpr int hn = n / 2, hq = Q / 2, NN = (n + 1) / 2, NQ = (Q + 1) / 2;
     double B[Q][n];   // B[q][a] = l_a(x_q)
     double dB[Q][n];  // its derivative on [-1, 1]
     double wg[Q];     // Gauss weights
     double w[n];      // GLL weights
+    double FE[NQ][hn > 0 ? hn : 1], FO[NQ][hn > 0 ? hn : 1], FM[NQ];
+    double TE[NN][hq > 0 ? hq : 1], TO[NN][hq > 0 ? hq : 1], TM[NN];
+    double DE[NN][hq > 0 ? hq : 1], DO[NN][hq > 0 ? hq : 1], DM[NN];
 
-    constexpr ConvTab() : B(), dB(), wg(), w()
+    constexpr ConvTab()
+        : B(), dB(), wg(), w(), FE(), FO(), FM(), TE(), TO(), TM(), DE(), DO(), DM()
     {
         const double pi = 3.14159265358979323846;
         double x0[Q] = {};
@@ -91,6 +108,23 @@ struct ConvTab {
                 B[q][a] = l;
                 dB[q][a] = dl;
             }
+        for (int q = 0; q < NQ; ++q) {
+            for (int a = 0; a < hn; ++a) {
+                FE[q][a] = 0.5 * (B[q][a] + B[q][n - 1 - a]);
+                FO[q][a] = 0.5 * (B[q][a] - B[q][n - 1 - a]);
+            }
+            FM[q] = (n % 2) ? B[q][hn] : 0.0;
+        }
+        for (int a = 0; a < NN; ++a) {
+            for (int q = 0; q < hq; ++q) {
+                TE[a][q] = 0.5 * (B[q][a] + B[Q - 1 - q][a]);
+                TO[a][q] = 0.5 * (B[q][a] - B[Q - 1 - q][a]);
+                DE[a][q] = 0.5 * (dB[q][a] - dB[Q - 1 - q][a]);
+                DO[a][q] = 0.5 * (dB[q][a] + dB[Q - 1 - q][a]);
+            }
+            TM[a] = (Q % 2) ? B[hq][a] : 0.0;
+            DM[a] = (Q % 2) ? dB[hq][a] : 0.0;
+        }
     }
 };
 
@@ -149,16 +183,78 @@ __device__ __forceinline__ int layer_node(int d, int layer, int s, int t)
 // chosen per group of whole waves, so that both halves keep compile-time
 // indices without divergence.
 
+// even and odd halves of a line of Q values at the Gauss points
+template <int P>
+struct EoQ {
+    static constexpr int Q = conv_q(P), hq = Q / 2;
+    double e[hq > 0 ? hq : 1], o[hq > 0 ? hq : 1], m;
+};
+
+template <int P>
+__device__ __forceinline__ void split_q(const double (&x)[conv_q(P)], EoQ<P> &s)
+{
+    constexpr int Q = conv_q(P), hq = Q / 2;
+#pragma unroll
+    for (int q = 0; q < hq; ++q) {
+        s.e[q] = x[q] + x[Q - 1 - q];
+        s.o[q] = x[q] - x[Q - 1 - q];
+    }
+    s.m = (Q % 2) ? x[hq] : 0.0;
+}
+
+// the even (E) and odd (O) parts of node pair (a, n-1-a) of B^T x, added to E, O
+template <int P>
+__device__ __forceinline__ void pair_bt(const ConvTab<P> &T, int a, const EoQ<P> &s, double &E, double &O)
+{
+    constexpr int n = P + 1, Q = conv_q(P), hq = Q / 2, hn = n / 2;
+#pragma unroll
+    for (int q = 0; q < hq; ++q) E = fma(T.TE[a][q], s.e[q], E);
+    if (Q % 2) E = fma(T.TM[a], s.m, E);
+    if (a < hn)
+#pragma unroll
+        for (int q = 0; q < hq; ++q) O = fma(T.TO[a][q], s.o[q], O);
+}
+
+// the same for dB^T x
+template <int P>
+__device__ __forceinline__ void pair_dbt(const ConvTab<P> &T, int a, const EoQ<P> &s, double &E, double &O)
+{
+    constexpr int n = P + 1, Q = conv_q(P), hq = Q / 2, hn = n / 2;
+#pragma unroll
+    for (int q = 0; q < hq; ++q) E = fma(T.DE[a][q], s.o[q], E);
+    if (a < hn) {
+#pragma unroll
+        for (int q = 0; q < hq; ++q) O = fma(T.DO[a][q], s.e[q], O);
+        if (Q % 2) O = fma(T.DM[a], s.m, O);
+    }
+}
+
 // y[q] = sum_a B[q][a] x[a]: nodes to Gauss points
 template <int P, int n = P + 1, int Q = conv_q(P)>
 __device__ __forceinline__ void to_gauss(const ConvTab<P> &T, const double (&x)[n], double (&y)[Q])
 {
+    constexpr int hn = n / 2, hq = Q / 2, NQ = (Q + 1) / 2;
+    double e[hn > 0 ? hn : 1], o[hn > 0 ? hn : 1];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        double s = 0.0;
+    for (int a = 0; a < hn; ++a) {
+        e[a] = x[a] + x[n - 1 - a];
+        o[a] = x[a] - x[n - 1 - a];
+    }
 #pragma unroll
-        for (int a = 0; a < n; ++a) s = fma(T.B[q][a], x[a], s);
-        y[q] = s;
+    for (int q = 0; q < NQ; ++q) {
+        double E = 0.0;
+#pragma unroll
+        for (int a = 0; a < hn; ++a) E = fma(T.FE[q][a], e[a], E);
+        if (n % 2) E = fma(T.FM[q], x[hn], E);
+        if (q < hq) {
+            double O = 0.0;
+#pragma unroll
+            for (int a = 0; a < hn; ++a) O = fma(T.FO[q][a], o[a], O);
+            y[q] = E + O;
+            y[Q - 1 - q] = E - O;
+        } else {
+            y[q] = E;  // the middle point of an odd Q
+        }
     }
 }
 
@@ -166,17 +262,38 @@ __device__ __forceinline__ void to_gauss(const ConvTab<P> &T, const double (&x)[
 template <int P, int n = P + 1, int Q = conv_q(P)>
 __device__ __forceinline__ void to_nodes(const ConvTab<P> &T, const double (&x)[Q], double (&y)[n])
 {
+    constexpr int hn = n / 2, NN = (n + 1) / 2;
+    EoQ<P> s;
+    split_q<P>(x, s);
 #pragma unroll
-    for (int a = 0; a < n; ++a) {
-        double s = 0.0;
-#pragma unroll
-        for (int q = 0; q < Q; ++q) s = fma(T.B[q][a], x[q], s);
-        y[a] = s;
+    for (int a = 0; a < NN; ++a) {
+        double E = 0.0, O = 0.0;
+        pair_bt<P>(T, a, s, E, O);
+        if (a < hn) {
+            y[a] = E + O;
+            y[n - 1 - a] = E - O;
+        } else {
+            y[a] = E;  // the middle node of an odd n
+        }
+    }
+}
+
+// store node pair a of a line: y[a] = E + O, y[n-1-a] = E - O (the middle
+// node of an odd line: E), each times f, at stride st from y0
+template <int P>
+__device__ __forceinline__ void store_pair(double *y0, int st, int a, double E, double O, double f)
+{
+    constexpr int n = P + 1, hn = n / 2;
+    if (a < hn) {
+        y0[a * st] = (E + O) * f;
+        y0[(n - 1 - a) * st] = (E - O) * f;
+    } else {
+        y0[a * st] = E * f;
     }
 }
 
 // z pass of the volume term for output component i, Gauss column qxy, node
-// layers c in [C0, C0 + CN): Z_k[c][qxy] = f_k sum_qz T_k[qz][c] wg_qz U_i U_k
+// pairs c in [C0, C0 + CN): Z_k[c][qxy] = f_k sum_qz T_k[qz][c] wg_qz U_i U_k
 // with T_0 = T_1 = B, T_2 = dB
 template <int P, int C0, int CN>
 __device__ __forceinline__ void vol_z(const ConvTab<P> &T, const double *U, int i, int qxy, double f0,
@@ -185,33 +302,34 @@ __device__ __forceinline__ void vol_z(const ConvTab<P> &T, const double *U, int 
     constexpr int n = P + 1, Q = conv_q(P);
     constexpr int Q2 = Q * Q, Q3 = Q2 * Q, nQ2 = n * Q2;
     if constexpr (CN > 0) {
-        double s0[CN], s1[CN], s2[CN];
-#pragma unroll
-        for (int cc = 0; cc < CN; ++cc) s0[cc] = s1[cc] = s2[cc] = 0.0;
+        double p0[Q], p1[Q], p2[Q];
 #pragma unroll
         for (int qz = 0; qz < Q; ++qz) {
             const int q = qz * Q2 + qxy;
             const double u0 = U[q], u1 = U[Q3 + q], u2 = U[2 * Q3 + q];
             const double ui = (i == 0 ? u0 : i == 1 ? u1 : u2) * T.wg[qz];
-            const double p0 = ui * u0, p1 = ui * u1, p2 = ui * u2;
-#pragma unroll
-            for (int cc = 0; cc < CN; ++cc) {
-                s0[cc] = fma(T.B[qz][C0 + cc], p0, s0[cc]);
-                s1[cc] = fma(T.B[qz][C0 + cc], p1, s1[cc]);
-                s2[cc] = fma(T.dB[qz][C0 + cc], p2, s2[cc]);
-            }
+            p0[qz] = ui * u0;
+            p1[qz] = ui * u1;
+            p2[qz] = ui * u2;
         }
+        EoQ<P> s0, s1, s2;
+        split_q<P>(p0, s0);
+        split_q<P>(p1, s1);
+        split_q<P>(p2, s2);
 #pragma unroll
-        for (int cc = 0; cc < CN; ++cc) {
-            const int c = C0 + cc;
-            Z[c * Q2 + qxy] = s0[cc] * f0;
-            Z[nQ2 + c * Q2 + qxy] = s1[cc] * f1;
-            Z[2 * nQ2 + c * Q2 + qxy] = s2[cc] * f2;
+        for (int c = C0; c < C0 + CN; ++c) {
+            double E0 = 0.0, O0 = 0.0, E1 = 0.0, O1 = 0.0, E2 = 0.0, O2 = 0.0;
+            pair_bt<P>(T, c, s0, E0, O0);
+            pair_bt<P>(T, c, s1, E1, O1);
+            pair_dbt<P>(T, c, s2, E2, O2);
+            store_pair<P>(Z + qxy, Q2, c, E0, O0, f0);
+            store_pair<P>(Z + nQ2 + qxy, Q2, c, E1, O1, f1);
+            store_pair<P>(Z + 2 * nQ2 + qxy, Q2, c, E2, O2, f2);
         }
     }
 }
 
-// y pass, line (c, qx), node rows b in [B0, B0 + BN):
+// y pass, line (c, qx), node pairs b in [B0, B0 + BN):
 // Yx = B_y^T Z_0, Ys = dB_y^T Z_1 + B_y^T Z_2
 template <int P, int B0, int BN>
 __device__ __forceinline__ void vol_y(const ConvTab<P> &T, const double *Z, int c, int qx, double *Yb)
@@ -219,46 +337,53 @@ __device__ __forceinline__ void vol_y(const ConvTab<P> &T, const double *Z, int 
     constexpr int n = P + 1, Q = conv_q(P);
     constexpr int nQ2 = n * Q * Q, n2Q = n * n * Q;
     if constexpr (BN > 0) {
-        double sx[BN], ss[BN];
-#pragma unroll
-        for (int bb = 0; bb < BN; ++bb) sx[bb] = ss[bb] = 0.0;
+        double z0[Q], z1[Q], z2[Q];
 #pragma unroll
         for (int qy = 0; qy < Q; ++qy) {
             const int zi = (c * Q + qy) * Q + qx;
-            const double z0 = Z[zi], z1 = Z[nQ2 + zi], z2 = Z[2 * nQ2 + zi];
-#pragma unroll
-            for (int bb = 0; bb < BN; ++bb) {
-                sx[bb] = fma(T.B[qy][B0 + bb], z0, sx[bb]);
-                ss[bb] = fma(T.dB[qy][B0 + bb], z1, fma(T.B[qy][B0 + bb], z2, ss[bb]));
-            }
+            z0[qy] = Z[zi];
+            z1[qy] = Z[nQ2 + zi];
+            z2[qy] = Z[2 * nQ2 + zi];
         }
+        EoQ<P> s0, s1, s2;
+        split_q<P>(z0, s0);
+        split_q<P>(z1, s1);
+        split_q<P>(z2, s2);
 #pragma unroll
-        for (int bb = 0; bb < BN; ++bb) {
-            const int o = (c * n + B0 + bb) * Q + qx;
-            Yb[o] = sx[bb];
-            Yb[n2Q + o] = ss[bb];
+        for (int b = B0; b < B0 + BN; ++b) {
+            double Ex = 0.0, Ox = 0.0, Es = 0.0, Os = 0.0;
+            pair_bt<P>(T, b, s0, Ex, Ox);
+            pair_dbt<P>(T, b, s1, Es, Os);
+            pair_bt<P>(T, b, s2, Es, Os);
+            store_pair<P>(Yb + c * n * Q + qx, Q, b, Ex, Ox, 1.0);
+            store_pair<P>(Yb + n2Q + c * n * Q + qx, Q, b, Es, Os, 1.0);
         }
     }
 }
 
-// x pass, line (c, b) = cb, nodes a in [A0, A0 + AN): acc = dB_x^T Yx + B_x^T Ys
+// x pass, line (c, b) = cb, node pairs a in [A0, A0 + AN): acc = dB_x^T Yx + B_x^T Ys
 template <int P, int A0, int AN>
 __device__ __forceinline__ void vol_x(const ConvTab<P> &T, const double *Yb, int cb, double *acc)
 {
     constexpr int n = P + 1, Q = conv_q(P);
     constexpr int n2Q = n * n * Q;
     if constexpr (AN > 0) {
-        double s[AN];
-#pragma unroll
-        for (int aa = 0; aa < AN; ++aa) s[aa] = 0.0;
+        double yx[Q], ys[Q];
 #pragma unroll
         for (int qx = 0; qx < Q; ++qx) {
-            const double yx = Yb[cb * Q + qx], ys = Yb[n2Q + cb * Q + qx];
-#pragma unroll
-            for (int aa = 0; aa < AN; ++aa) s[aa] = fma(T.dB[qx][A0 + aa], yx, fma(T.B[qx][A0 + aa], ys, s[aa]));
+            yx[qx] = Yb[cb * Q + qx];
+            ys[qx] = Yb[n2Q + cb * Q + qx];
         }
+        EoQ<P> sx, ss;
+        split_q<P>(yx, sx);
+        split_q<P>(ys, ss);
 #pragma unroll
-        for (int aa = 0; aa < AN; ++aa) acc[cb * n + A0 + aa] = s[aa];
+        for (int a = A0; a < A0 + AN; ++a) {
+            double E = 0.0, O = 0.0;
+            pair_dbt<P>(T, a, sx, E, O);
+            pair_bt<P>(T, a, ss, E, O);
+            store_pair<P>(acc + cb * n, 1, a, E, O, 1.0);
+        }
     }
 }
 
@@ -269,7 +394,8 @@ __global__ void __launch_bounds__(256) k_convection(ConvArgs A)
     constexpr int n = L::n, Q = L::Q, n2 = n * n, n3 = n2 * n, Q2 = Q * Q;
     constexpr int nQ2 = n * Q2, n2Q = n2 * Q;
     constexpr int NT = 256;                    // threads per work-group (the launch's block size)
-    constexpr int H = (n + 1) / 2;             // the two halves of a node range: [0, H), [H, n)
+    constexpr int H = (n + 1) / 2;             // the lines c and c + H of the y interpolation pass
+    constexpr int NN = (n + 1) / 2, PH = (NN + 1) / 2;  // node pairs, split [0, PH), [PH, NN)
     constexpr int WZ = (Q2 + 63) / 64 * 64;    // thread slots per half of a pass, whole waves
     constexpr int WY = (n * Q + 63) / 64 * 64;
     constexpr int WX = (n2 + 63) / 64 * 64;
@@ -353,9 +479,9 @@ __global__ void __launch_bounds__(256) k_convection(ConvArgs A)
             if (qxy < Q2) {
                 const double f = twg[qxy % Q] * twg[qxy / Q] * J;
                 if (hf == 0)
-                    vol_z<P, 0, H>(T, U, i, qxy, f * g0, f * g1, f * g2, Z);
+                    vol_z<P, 0, PH>(T, U, i, qxy, f * g0, f * g1, f * g2, Z);
                 else
-                    vol_z<P, H, n - H>(T, U, i, qxy, f * g0, f * g1, f * g2, Z);
+                    vol_z<P, PH, NN - PH>(T, U, i, qxy, f * g0, f * g1, f * g2, Z);
             }
         }
         __syncthreads();
@@ -363,9 +489,9 @@ __global__ void __launch_bounds__(256) k_convection(ConvArgs A)
             const int hf = r / WY, cq = r - hf * WY;
             if (cq < n * Q) {
                 if (hf == 0)
-                    vol_y<P, 0, H>(T, Z, cq / Q, cq % Q, Yb);
+                    vol_y<P, 0, PH>(T, Z, cq / Q, cq % Q, Yb);
                 else
-                    vol_y<P, H, n - H>(T, Z, cq / Q, cq % Q, Yb);
+                    vol_y<P, PH, NN - PH>(T, Z, cq / Q, cq % Q, Yb);
             }
         }
         __syncthreads();
@@ -373,9 +499,9 @@ __global__ void __launch_bounds__(256) k_convection(ConvArgs A)
             const int hf = r / WX, cb = r - hf * WX;
             if (cb < n2) {
                 if (hf == 0)
-                    vol_x<P, 0, H>(T, Yb, cb, acc[i]);
+                    vol_x<P, 0, PH>(T, Yb, cb, acc[i]);
                 else
-                    vol_x<P, H, n - H>(T, Yb, cb, acc[i]);
+                    vol_x<P, PH, NN - PH>(T, Yb, cb, acc[i]);
             }
         }
     }
