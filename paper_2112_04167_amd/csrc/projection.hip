@@ -415,8 +415,14 @@ template <int P>
 __global__ void __launch_bounds__(256) k_gradient_eq(ProjArgs A)
 {
     constexpr int n = P + 1, n2 = n * n, n3 = n2 * n;
-    __shared__ double tdV[n * n], tw[n];  // the 1D tables in LDS (see k_divergence)
-    for (int i = threadIdx.x; i < n * n; i += blockDim.x) tdV[i] = A.t.dVq[i / n][i % n];
+    // the 1D tables in LDS (see k_divergence); tdVt = tdV transposed, for the
+    // x derivative, whose lanes run along the table's row index (strided
+    // rows would put consecutive lanes on the same LDS banks)
+    __shared__ double tdV[n * n], tdVt[n * n], tw[n];
+    for (int i = threadIdx.x; i < n * n; i += blockDim.x) {
+        tdV[i] = A.t.dVq[i / n][i % n];
+        tdVt[i] = A.t.dVq[i % n][i / n];
+    }
     for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = A.t.w[i];
     __syncthreads();
     // psi of the element, the neighbours' traces on the six faces (axis d,
@@ -454,7 +460,7 @@ __global__ void __launch_bounds__(256) k_gradient_eq(ProjArgs A)
             double g = 0.0;
             if (d == 0) {
 #pragma unroll
-                for (int k = 0; k < n; ++k) g += gd * tdV[(a) * n + (k)] * q[(c * n + b) * n + k];
+                for (int k = 0; k < n; ++k) g += gd * tdVt[(k) * n + (a)] * q[(c * n + b) * n + k];
             } else if (d == 1) {
 #pragma unroll
                 for (int k = 0; k < n; ++k) g += gd * tdV[(b) * n + (k)] * q[(c * n + k) * n + a];
