@@ -450,6 +450,7 @@ struct FdmRun {
     bool singular = false, done = false;
     bool f32 = false;         // FP32 transforms (fdm_apply32)
     bool true_resid = true;   // recompute b - A x at the end (info.true_rel_res)
+    bool ended = false;       // the closing work ran with the last chunk (see fdm_chunk)
     FdmDev f{};
     CgVecArgs<double> a{};
     int cap = 0, launched = 0;
@@ -526,6 +527,7 @@ int jacobi_start(dg_mesh *m, FdmRun &R, const dg_solve_opts &o)
     R.plan = ChunkPlan(4, 64, true);
     R.launched = 0;
     R.done = false;
+    R.ended = false;
     return DG_OK;
 }
 
@@ -563,6 +565,7 @@ int fdm_start(dg_mesh *m, FdmRun &R, const dg_solve_opts &o)
     R.plan = ChunkPlan(2, 16, true);
     R.launched = 0;
     R.done = false;
+    R.ended = false;
     return DG_OK;
 }
 
@@ -582,6 +585,7 @@ int fdm_chunk(dg_mesh *m, FdmRun &R)
             if ((rc = cg_pupdate<double>(md, R.a, s))) return rc;
         }
         R.launched += R.plan.chunk;
+        if (!R.true_resid && (rc = cg_finish<double>(md, R.a, s))) return rc;
         DG_HIP_CHECK(hipMemcpyAsync(w.host_sc, w.sc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
         return DG_OK;
     }
@@ -594,6 +598,12 @@ int fdm_chunk(dg_mesh *m, FdmRun &R)
         if ((rc = cg_pupdate_fdm(md, R.a, false, s))) return rc;
     }
     R.launched += R.plan.chunk;
+    // Without a final b - A x, the closing work (the singular mean shift of
+    // x) is enqueued with every chunk, so that the chunk that converges also
+    // ends the solve and its poll is the last host wait.  On a chunk that
+    // does not converge the shift only moves x along the null space (r is
+    // carried by its recurrence), and the last chunk's shift sets the mean.
+    if (!R.true_resid && (rc = cg_finish<double>(md, R.a, s))) return rc;
     DG_HIP_CHECK(hipMemcpyAsync(w.host_sc, w.sc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
     return DG_OK;
 }
@@ -604,6 +614,7 @@ int fdm_poll(FdmRun &R)
     DG_HIP_CHECK(hipStreamSynchronize(R.s));
     if (R.w->host_sc->done) {
         R.done = true;
+        R.ended = !R.true_resid;
         return DG_OK;
     }
     if (R.launched > R.cap + 64) {
@@ -621,6 +632,15 @@ int fdm_end(dg_mesh *m, FdmRun &R, dg_solve_info &info)
     Workspace &w = *R.w;
     hipStream_t s = R.s;
     int rc;
+    if (R.ended) {  // finished with the last chunk, whose scalars are on the host
+        const CgScalars &h = *w.host_sc;
+        info.iters = h.iter;
+        info.outer_iters = 0;
+        info.status = h.status;
+        info.rel_res = h.bnorm2 > 0 ? std::sqrt(h.res2 / h.bnorm2) : 0.0;
+        info.true_rel_res = info.rel_res;
+        return h.status;
+    }
     if ((rc = cg_finish<double>(md, R.a, s))) return rc;
     if (R.true_resid &&
         (rc = launch_resid<double>(md, R.bc, R.lambda, R.nu, R.nu_c, R.x, w.b64, w.q64, w.partial, w.sc, s)))
