@@ -83,7 +83,7 @@ def test_fd2_matches_oracle(case):
     m.destroy()
 
 
-def _gpu_step(spec, v, t, dt, method, nu0, nu1, forcing, final_projection, tol=1e-13, precision=0):
+def _gpu_step(spec, v, t, dt, method, nu0, nu1, forcing, final_projection, tol=1e-13, precision=0, precond=1):
     import paper_2112_04167_amd as dg
     torch, dev = torch_dev()
     ps = dict(spec)
@@ -96,7 +96,7 @@ def _gpu_step(spec, v, t, dt, method, nu0, nu1, forcing, final_projection, tol=1
         f = [[to_dev(c) for c in forcing(t + tab.c[j] * dt)] for j in range(tab.s)]
     info = dg.dg_imex_step(mv, mp, tab, dt, nu0, nu1, synth.VVP_VMAX, vd, forcing=f,
                            final_projection=final_projection,
-                           opts=dg.default_opts(tol=tol, precond=dg.DG_PC_FDM, precision=precision))
+                           opts=dg.default_opts(tol=tol, precond=precond, precision=precision))
     out = [c.cpu().numpy() for c in vd]
     mv.destroy()
     mp.destroy()
@@ -142,6 +142,28 @@ def test_step_vvp_fp32_preconditioner_matches_oracle(method):
     for d in range(3):
         e = rel(got[d], want[d])
         say("step fp32 preconditioner", method, d, e)
+        assert e <= 1e-10
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_step_vvp_jacobi_matches_oracle(precision):
+    # the step with Jacobi-PCG for every solve (velocity solves one after
+    # another, FP64 or FP32 CG with FP64 residual replacement; the stage's
+    # term groups still on three streams)
+    spec = make_spec((2, 2, 2), 4, (0, 0, 0), False, lo=-0.5, hi=0.5)
+    X, Y, Z = node_coords(spec)
+    t, dt, nu0, nu1 = 0.1, 1.0 / 32, 0.01, 0.01
+    v = synth.vvp_velocity(X, Y, Z, t)
+    f = lambda tt: synth.vvp_forcing(X, Y, Z, tt, nu0, nu1)
+    got, info = _gpu_step(spec, v, t, dt, "RK-ARS3", nu0, nu1, f, True, tol=1e-12, precision=precision,
+                          precond=0)
+    want, _ = imex.step(spec, v, t, dt, imex.TABLEAUX["RK-ARS3"], nu0, nu1, synth.VVP_VMAX, f,
+                        final_projection=True, solver="dense")
+    say("step jacobi", precision, info)
+    assert info["status"] == 0
+    for d in range(3):
+        e = rel(got[d], want[d])
+        say("step jacobi", precision, d, e)
         assert e <= 1e-10
 
 
