@@ -672,22 +672,23 @@ def bench_imex_step(dg, torch, reps=3):
     fl = [[c.contiguous() for c in synth.vvp_forcing(XL, YL, ZL, tab.c[j] * dtl, nu0, nu1, xp=torch)]
           for j in range(tab.s)]
     vl0 = [c.contiguous() for c in synth.vvp_velocity(XL, YL, ZL, 0.0, xp=torch)]
-    times = []
-    for r in range(3):
-        v = [c.clone() for c in vl0]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        info = dg.dg_imex_step(mvl, mpl, tab, dtl, nu0, nu1, synth.VVP_VMAX, v, forcing=fl,
-                               final_projection=True, opts=opts)
-        torch.cuda.synchronize()
-        if r > 0:
-            times.append(time.perf_counter() - t0)
-    ve = synth.vvp_velocity(XL, YL, ZL, dtl, xp=torch)
-    err = max(float(torch.linalg.vector_norm(v[d] - ve[d]) / torch.linalg.vector_norm(ve[d])) for d in range(3))
-    t = float(np.median(times))
-    out["RK-ARS3_32cubed"] = dict(ndof_velocity=mvl.ndof, dt=dtl, step_ms=t * 1e3, steps_per_s=1.0 / t,
-                                  solves=info["solves"], pressure_iters=info["pressure_iters"],
-                                  velocity_iters=info["velocity_iters"], rel_error_vs_exact_after_one_step=err)
+    for name, ol in (("RK-ARS3_32cubed", opts), ("RK-ARS3_32cubed_fdm32", opts32)):
+        times = []
+        for r in range(3):
+            v = [c.clone() for c in vl0]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = dg.dg_imex_step(mvl, mpl, tab, dtl, nu0, nu1, synth.VVP_VMAX, v, forcing=fl,
+                                   final_projection=True, opts=ol)
+            torch.cuda.synchronize()
+            if r > 0:
+                times.append(time.perf_counter() - t0)
+        ve = synth.vvp_velocity(XL, YL, ZL, dtl, xp=torch)
+        err = max(float(torch.linalg.vector_norm(v[d] - ve[d]) / torch.linalg.vector_norm(ve[d])) for d in range(3))
+        t = float(np.median(times))
+        out[name] = dict(ndof_velocity=mvl.ndof, dt=dtl, step_ms=t * 1e3, steps_per_s=1.0 / t,
+                         solves=info["solves"], pressure_iters=info["pressure_iters"],
+                         velocity_iters=info["velocity_iters"], rel_error_vs_exact_after_one_step=err)
     del fl, vl0, v, ve, XL, YL, ZL
     mvl.destroy()
     mpl.destroy()
