@@ -296,11 +296,13 @@ __global__ void __launch_bounds__(256) k_fdm_axis(FdmArgs A)
 // LDS row stride of a bundle of NTC column tiles: 16 doubles of padding put
 // consecutive rows half the 64 banks apart, so the 4 rows of a B fragment
 // read take the minimum two passes
-int lds_stride(int ntc) { return 16 * ntc + 16; }
+// (one column tile takes 32 doubles of padding: 16 would put every row on
+// the same banks)
+int lds_stride(int ntc) { return ntc == 1 ? 48 : 16 * ntc + 16; }
 int row_tiles(int Lp) { return (Lp / 16 + 3) / 4; }  // per wave
 bool ntc_valid(int ntc, int Lp)
 {
-    if (ntc != 2 && ntc != 4) return false;
+    if (ntc != 1 && ntc != 2 && ntc != 4) return false;
     const int lds = Lp * lds_stride(ntc) * (int)sizeof(double);
     return row_tiles(Lp) <= 16 / ntc && lds <= 160 * 1024;
 }
@@ -341,6 +343,17 @@ int launch_axis(const MeshDev &m, const FdmDev &f, FdmArgs a, int ntc, hipStream
             case 3: go(integral_constant<int, 4>{}, integral_constant<int, 3>{}); break;
             default: go(integral_constant<int, 4>{}, integral_constant<int, 4>{}); break;
         }
+    } else if (ntc == 1) {
+        switch (mt) {
+            case 1: go(integral_constant<int, 1>{}, integral_constant<int, 1>{}); break;
+            case 2: go(integral_constant<int, 1>{}, integral_constant<int, 2>{}); break;
+            case 3: go(integral_constant<int, 1>{}, integral_constant<int, 3>{}); break;
+            case 4: go(integral_constant<int, 1>{}, integral_constant<int, 4>{}); break;
+            case 5: go(integral_constant<int, 1>{}, integral_constant<int, 5>{}); break;
+            case 6: go(integral_constant<int, 1>{}, integral_constant<int, 6>{}); break;
+            case 7: go(integral_constant<int, 1>{}, integral_constant<int, 7>{}); break;
+            default: go(integral_constant<int, 1>{}, integral_constant<int, 8>{}); break;
+        }
     } else {
         switch (mt) {
             case 1: go(integral_constant<int, 2>{}, integral_constant<int, 1>{}); break;
@@ -359,7 +372,7 @@ int launch_axis(const MeshDev &m, const FdmDev &f, FdmArgs a, int ntc, hipStream
 
 // ---- tile-shape autotuner ------------------------------------------------
 //
-// The column tiles per work-group (NTC = 2 or 4: 32 or 64 mesh lines)
+// The column tiles per work-group (NTC = 1, 2 or 4: 16, 32 or 64 mesh lines)
 // trade the reuse of each transform matrix fragment read from L2 (more
 // columns) against LDS per work-group and the padding of the last chunk of
 // a bundle ((P+1)^2 columns per bundle).  Which is fastest depends on the
@@ -484,7 +497,7 @@ int tile_choice(const MeshDev &m, const FdmDev &f, const FdmArgs &base, const do
     for (int d = 0; d < 3 && rc == DG_OK; ++d) {
         float best = 1e30f;
         ntc[d] = 0;
-        for (int c : {4, 2}) {
+        for (int c : {4, 2, 1}) {
             if (!ntc_valid(c, f.ax[d].Lp)) continue;
             float ms = 0.f;
             a.G = f.ax[d].Gf;

@@ -259,3 +259,23 @@ def test_fdm32_pcg_channel_velocity_full_size():
     assert i32["status"] == 0 and i32["iters"] <= i64["iters"] + 1
     assert pcg.true_rel_res(op.apply, x32, M * f, M) <= 1.2e-10
     assert rel(x32, x64) <= 2e-10
+
+
+@pytest.mark.parametrize("ntc", [1, 2, 4])
+def test_fdm_inverse_every_tile_shape(ntc, tmp_path):
+    # every transform tile shape the autotuner may choose (1, 2 or 4 column
+    # tiles per work-group), forced through the tuning cache in a fresh
+    # process (the cache is read once per process), against the oracle
+    import json
+    import os
+    import subprocess
+    import sys
+    here = os.path.dirname(os.path.abspath(__file__))
+    r = subprocess.run([sys.executable, os.path.join(here, "fdm_forced_tiles.py"), str(tmp_path / "tune.txt"),
+                        str(ntc)], capture_output=True, text=True, timeout=240)
+    say("forced tiles", ntc, r.returncode, r.stdout[-2000:], r.stderr[-2000:])
+    assert r.returncode == 0
+    lines = [json.loads(s) for s in r.stdout.splitlines() if s.startswith("{")]
+    assert len(lines) == 4
+    for c in lines:
+        assert c["rel"] <= 1e-11, c
