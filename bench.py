@@ -789,7 +789,7 @@ def main():
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: multi-GPU runs are not part of this build "
+        print("bench.py measures one GPU only: the library runs on one GPU "
               "(the apply would shard by z-slabs of elements with a one-layer halo)", file=sys.stderr)
         sys.exit(2)
 
