@@ -51,7 +51,7 @@ def build(verbose=True, jobs=None):
     if failed:
         raise RuntimeError("HIP build failed")
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread", "-lrocprofiler-sdk-roctx"]
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     if verbose:

@@ -24,6 +24,7 @@
 #include "dg_internal.h"
 #include "dg_sipdg.h"
 #include "projection.h"
+#include "trace.h"
 
 namespace dg {
 namespace {
@@ -303,6 +304,7 @@ int dg_imex_step(dg_mesh *mv, dg_mesh *mp, const dg_tableau *tab, double dt, dou
                  const double *const *wall, int final_projection, const dg_solve_opts *opts, dg_step_info *info)
 {
     const double t0 = now_s();
+    TraceRange tr("dg_imex_step");
     dg_step_info st{};
     const MeshDev *mdp = mesh_device(mv);
     if (!mdp || !mesh_device(mp) || !vx || !vy || !vz) {
@@ -383,6 +385,7 @@ int dg_imex_step(dg_mesh *mv, dg_mesh *mp, const dg_tableau *tab, double dt, dou
     StepEvents ev;
     if ((rc = ev.create())) return rc;
     auto stage_terms = [&](int j, const double *const v[3]) -> int {
+        TraceRange tj("imex: stage terms");
         int r;
         const double *wb[3];
         const double *const *vb = walls(j, wb);
@@ -498,6 +501,7 @@ int dg_imex_step(dg_mesh *mv, dg_mesh *mp, const dg_tableau *tab, double dt, dou
             }
         }
         if (aii > 0.0) {
+            TraceRange ts("imex: velocity solves");
             dg_solve_info hi[3] = {};
             if (o.precond == DG_PC_FDM) {
                 // (the step reports no true residuals: no final b - A x)
@@ -543,7 +547,10 @@ int dg_imex_step(dg_mesh *mv, dg_mesh *mp, const dg_tableau *tab, double dt, dou
         if ((rc = launch_lincomb(N, Vi[d], (int)coef.size(), coef.data(), xs.data(), V0[d], sv))) return rc;
     }
     if (final_projection && (rc = project(V0, nullptr, true))) return rc;
-    DG_HIP_CHECK(hipStreamSynchronize(sv));
+    {
+        TraceRange tw("imex: wait for the device");
+        DG_HIP_CHECK(hipStreamSynchronize(sv));
+    }
     st.seconds = now_s() - t0;
     if (info) *info = st;
     return st.status;

@@ -20,6 +20,7 @@
 #include "fdm.h"
 #include "kernels.h"
 #include "projection.h"
+#include "trace.h"
 
 namespace dg {
 
@@ -735,6 +736,7 @@ int conc_solve(dg_mesh *m, int nsys, const ConcSys *sys, const dg_solve_opts &o,
         set_error("concurrent solves: need 1 <= nsys <= 4");
         return DG_ERR_ARG;
     }
+    TraceRange tr("solve: concurrent");
     FdmRun R[kMaxConcurrent];
     int rc;
     hipStream_t alt[kMaxConcurrent - 1] = {};
@@ -1038,6 +1040,9 @@ int solve_common(dg_mesh *m, const int bc[3], double lambda, const double *nu, d
         set_error("the no-allocation solve is FP64 only");
         return DG_ERR_ARG;
     }
+    TraceRange tr(o.precond == DG_PC_FDM
+                      ? (o.precision == DG_MIXED ? "solve: FDM-PCG, FP32 transforms" : "solve: FDM-PCG FP64")
+                      : (o.precision == DG_MIXED ? "solve: Jacobi-PCG mixed" : "solve: Jacobi-PCG FP64"));
     if (o.precond == DG_PC_FDM) {
         rc = solve_fdm(m, wk, bc, lambda, nu, nu_c, rhs, x, o, inf, o.precision == DG_MIXED, true_resid);
     } else if (lent) {
@@ -1126,6 +1131,7 @@ int solve_batched(dg_mesh *m, int nsys, const double *lambdas, const double *con
                   const int *is_poisson, const double *const *rhs, double *const *x,
                   const dg_solve_opts &o, dg_solve_info *infos, int flags)
 {
+    TraceRange tr("solve: batched");
     const MeshDev &md = m->dev;
     hipStream_t s = m->stream;
     const bool f32 = o.precision == DG_MIXED;
@@ -1319,6 +1325,7 @@ int solve_fdm_concurrent(dg_mesh *m, int nsys, double lambda, const double *nu, 
 int project_impl(dg_mesh *mv, dg_mesh *mp, double *const vv[3], const double *const vbv[3], double *psi,
                  const dg_solve_opts *opts, dg_solve_info *info, bool step_mode)
 {
+    TraceRange tr("projection");
     double *vx = vv[0], *vy = vv[1], *vz = vv[2];
     const double t0 = now();
     if (int rc = check_mesh(mv)) return rc;

@@ -11,6 +11,7 @@ kernel's per-dispatch counters are scaled by those factors.
 """
 import argparse
 import hashlib
+import json
 import os
 import sqlite3
 
@@ -67,6 +68,43 @@ def trace_since(db, since, until=None, exclude=None):
     return out, span
 
 
+def range_stats(db, outer, skip=0, count=None):
+    """Host-side marker ranges (rocprofv3 --marker-trace) inside the ranges
+    named `outer`, taking those from the skip-th on (count of them, or all):
+    [(name, calls, total_ns)] of the ranges on the same thread that lie
+    within them, the outer ranges' total duration in ns, how many there were,
+    and the kernel time of the dispatches that started within them."""
+    c = sqlite3.connect(db)
+    rows = []
+    # a ROCTx range is recorded under its API call's name; its message is in
+    # the record's extdata
+    for name, ext, tid, st, en in c.execute("select name, extdata, tid, start, end from regions "
+                                           "where category like '%MARKER%' order by start"):
+        try:
+            name = json.loads(ext).get("message", name) if ext else name
+        except ValueError:
+            pass
+        rows.append((name, tid, st, en))
+    outs = [r for r in rows if r[0] == outer][skip:]
+    if count is not None:
+        outs = outs[:count]
+    agg = {}
+    for name, tid, st, en in rows:
+        if name == outer:
+            continue
+        if any(t == tid and st >= s0 and en <= e0 for _, t, s0, e0 in outs):
+            a = agg.setdefault(name, [0, 0])
+            a[0] += 1
+            a[1] += en - st
+    total = sum(e0 - s0 for _, _, s0, e0 in outs)
+    kt = 0
+    for st, en in c.execute("select start, end from kernels").fetchall():
+        if any(s0 <= st <= e0 for _, _, s0, e0 in outs):
+            kt += en - st
+    out = sorted(((k, a[0], a[1]) for k, a in agg.items()), key=lambda r: -r[2])
+    return out, total, len(outs), kt
+
+
 def counter(db, name, pattern, grid=None):
     c = sqlite3.connect(db)
     rows = c.execute("select kernel_name, grid_size, value from counters_collection "
@@ -80,7 +118,7 @@ def main():
     ap.add_argument("--trace", required=True)
     ap.add_argument("--fetch", help="FETCH_SIZE pass (omit for a trace-only summary)")
     ap.add_argument("--write", help="WRITE_SIZE pass (omit for a trace-only summary)")
-    ap.add_argument("--kernel", required=True)
+    ap.add_argument("--kernel", help="the kernel the counter and trace summaries are about")
     ap.add_argument("--calib", default="__amd_rocclr_copyBuffer")
     ap.add_argument("--calib-grid", type=int, default=131072)
     ap.add_argument("--calib-bytes", type=float, default=float(1 << 30))
@@ -91,7 +129,32 @@ def main():
     ap.add_argument("--until", help="trace-only with --since: stop before the first later kernel containing this")
     ap.add_argument("--exclude", help="trace-only with --since: leave out kernels whose names contain this")
     ap.add_argument("--per", type=float, default=0.0, help="trace-only with --since: also per-unit totals")
+    ap.add_argument("--ranges", help="marker ranges nested in the ranges of this name (--marker-trace)")
+    ap.add_argument("--range-skip", type=int, default=0, help="with --ranges: outer ranges to skip")
+    ap.add_argument("--range-count", type=int, help="with --ranges: outer ranges to take")
     a = ap.parse_args()
+
+    if a.ranges:
+        rows, total, n, kt = range_stats(a.trace, a.ranges, a.range_skip, a.range_count)
+        print("# %s" % a.title)
+        print()
+        print("Commands (from the repository root):")
+        print()
+        for c in a.cmd:
+            print("    " + c)
+        print()
+        print("## Host ranges within `%s` (rocprofv3 --marker-trace), %d of them from the %d-th on"
+              % (a.ranges, n, a.range_skip))
+        print()
+        print("`%s`: %.3f ms per call on the host; kernel time of the dispatches started within: "
+              "%.3f ms per call" % (a.ranges, total / 1e6 / max(n, 1), kt / 1e6 / max(n, 1)))
+        print()
+        print("| range | calls per `%s` | ms per `%s` | %% of `%s` |" % ((a.ranges,) * 3))
+        print("|---|---|---|---|")
+        for name, calls, t in rows:
+            print("| `%s` | %.2f | %.3f | %.1f |" % (name, calls / max(n, 1), t / 1e6 / max(n, 1),
+                                                   100.0 * t / max(total, 1)))
+        return
 
     if a.since:
         rows, span = trace_since(a.trace, a.since, a.until, a.exclude)
@@ -116,6 +179,8 @@ def main():
             short = name if len(name) < 90 else name[:87] + "..."
             print("| `%s` | %d | %.1f | %.2f | %.1f |" % (short, calls, t / 1e3, avg / 1e3, pct))
         return
+    if not a.kernel:
+        ap.error("--kernel is needed without --ranges or --since")
     allk, sel = trace_stats(a.trace, a.kernel)
     if not (a.fetch and a.write):
         print("# %s" % a.title)
