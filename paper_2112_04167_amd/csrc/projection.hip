@@ -20,8 +20,9 @@
 //
 // One work-group per element: the element's data is staged in LDS and the
 // 1D factors (interpolation Vq and derivative dVq of the pressure basis at
-// the velocity nodes) are applied one direction at a time.  The face terms
-// read the neighbour's face layer from global memory.
+// the velocity nodes) are applied one direction at a time, to the three
+// components at once.  The face terms read the neighbour's face layer from
+// global memory.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -61,7 +62,7 @@ struct ProjArgs {
 };
 
 // neighbour of element index k along an axis: -1 on a non-periodic boundary
-__device__ __forceinline__ int neighbour(int k, int nk, int bc, bool high)
+__host__ __device__ __forceinline__ int neighbour(int k, int nk, int bc, bool high)
 {
     int kn = high ? k + 1 : k - 1;
     if (kn < 0 || kn >= nk) {
@@ -72,7 +73,7 @@ __device__ __forceinline__ int neighbour(int k, int nk, int bc, bool high)
 }
 
 // element-major offset of element (ex, ey, ez)
-__device__ __forceinline__ size_t elem_base(const ProjArgs &A, int ex, int ey, int ez, int nodes)
+__host__ __device__ __forceinline__ size_t elem_base(const ProjArgs &A, int ex, int ey, int ez, int nodes)
 {
     return ((size_t)(ez * A.n[1] + ey) * A.n[0] + ex) * nodes;
 }
@@ -80,166 +81,258 @@ __device__ __forceinline__ size_t elem_base(const ProjArgs &A, int ex, int ey, i
 // index of node (a, b, c) [x fastest] and of the node at position (s, t) of
 // the face layer `layer` normal to axis d (s: the lower tangential axis)
 template <int n>
-__device__ __forceinline__ int node3(int a, int b, int c) { return (c * n + b) * n + a; }
+__host__ __device__ __forceinline__ int node3(int a, int b, int c) { return (c * n + b) * n + a; }
 template <int n>
-__device__ __forceinline__ int face_node(int d, int layer, int s, int t)
+__host__ __device__ __forceinline__ int face_node(int d, int layer, int s, int t)
 {
     return d == 0 ? node3<n>(layer, s, t) : d == 1 ? node3<n>(s, layer, t) : node3<n>(s, t, layer);
 }
 
-// ---------------------------------------------------------- divergence --
-template <int P, int Q>
-__global__ void __launch_bounds__(256) k_divergence(ProjArgs A)
+// ------------------------------------------- divergence and gradient --
+// All three components of an element are contracted at once, one line per
+// thread and pass, so that an element takes four (gradient) or five
+// (divergence) barriers whatever its faces.  Component d's derivative axis is contracted last (divergence) or
+// first (gradient), and its two face terms ride along as two extra layers
+// on that axis: the tangential contractions act on them exactly as on the
+// volume layers, and the last (first) pass adds them to the face layer of
+// the output.  Buffers are in LDS; the phases are plain functions of the
+// thread index, so that they can be run for every thread in turn on the
+// host.
+
+// the tangential axes of axis d, ascending
+__host__ __device__ __forceinline__ int tan1(int d) { return d == 0 ? 1 : 0; }
+__host__ __device__ __forceinline__ int tan2(int d) { return d == 2 ? 1 : 2; }
+// entry d of a three-vector, d not known at compile time
+__host__ __device__ __forceinline__ double sel3(int d, const double (&v)[3])
 {
-    constexpr int n = P + 1, m = Q + 1, n3 = n * n * n, m3 = m * m * m;
-    // the 1D tables in LDS: their lane-dependent rows would otherwise be
-    // vector loads from the kernel arguments, one per multiply-add
-    __shared__ double tV[n * m], tdV[n * m], tw[n];
-    for (int i = threadIdx.x; i < n * m; i += blockDim.x) {
-        tV[i] = A.t.Vq[i / m][i % m];
-        tdV[i] = A.t.dVq[i / m][i % m];
-    }
-    for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = A.t.w[i];
-    __syncthreads();
-    __shared__ double tv[n3];       // scaled velocity component
-    __shared__ double s1[n * n * m];
-    __shared__ double s2[n * m * m];
-    __shared__ double acc[m3];
-    __shared__ double fs[n * n], fq[n * m];
-    // the face values f = {v_d} or v_b,d of the six faces (axis d, side),
-    // [t][s], staged at the start so that their global loads are in flight
-    // with the first component's
-    __shared__ double fv[6][n * n];
-    const int el = blockIdx.x;
+    return d == 0 ? v[0] : d == 1 ? v[1] : v[2];
+}
+// stride of an axis in a layout with axis 0 fastest and extents e0, e1
+__host__ __device__ __forceinline__ int stride_of(int axis, int e0, int e1)
+{
+    return axis == 0 ? 1 : axis == 1 ? e0 : e0 * e1;
+}
+// extents of a per-component buffer: E along axis d, et1 and et2 along its
+// tangential axes; the stride of `axis` in it
+__host__ __device__ __forceinline__ int comp_stride(int axis, int d, int E, int et1, int et2)
+{
+    const int u1 = tan1(d);
+    const int e0 = d == 0 ? E : (u1 == 0 ? et1 : et2);
+    const int e1 = d == 1 ? E : (u1 == 1 ? et1 : et2);
+    return stride_of(axis, e0, e1);
+}
+
+template <int P, int Q>
+struct DivShape {
+    static constexpr int n = P + 1, m = Q + 1, E = n + 2, n3 = n * n * n, m3 = m * m * m;
+    static constexpr int X = E * n * n;  // scaled velocity plus face layers, per component
+    static constexpr int Y = E * n * m;  // after the first tangential contraction
+    static constexpr int Z = E * m * m;  // after the second
+    static constexpr int BUF_A = 3 * X;  // X, later Z
+    static constexpr int BUF_B = 3 * Y;  // Y, later the three components' results (m^3 each)
+    // threads per work-group: one per line of the largest pass (3 (P+1)
+    // (P+3) lines, 297 at P = 8), so that every pass is a single step
+    static constexpr int NT = 3 * n * E <= 256 ? 256 : 320;
+    static_assert(Z <= X && m3 <= Y, "buffer reuse");
+};
+
+// the velocity GLL weights in LDS (read with lane-dependent indices); the
+// passes read the 1D factors from the kernel arguments, at indices known at
+// compile time and the same on every lane
+template <int P>
+__host__ __device__ __forceinline__ void proj_weights(const ProjArgs &A, int tid, int nt, double *tw)
+{
+    for (int i = tid; i < P + 1; i += nt) tw[i] = A.t.w[i];
+}
+
+// X_d: the velocity component d times the GLL mass (layers 0..n-1 along d),
+// then the face terms +- omega0 w_s w_t f of the low and high faces normal
+// to d (layers n, n+1), f = {v_d}, v_b,d or 0 (no term)
+template <int P, int Q>
+__host__ __device__ __forceinline__ void div_load(const ProjArgs &A, int el, int tid, int nt, const double *tw,
+                                                  double *bufA)
+{
+    using S = DivShape<P, Q>;
+    constexpr int n = S::n, E = S::E, n3 = S::n3;
     const int ex = el % A.n[0], ey = (el / A.n[0]) % A.n[1], ez = el / (A.n[0] * A.n[1]);
     const int e3[3] = {ex, ey, ez};
-    const double hx = A.h[0][ex], hy = A.h[1][ey], hz = A.h[2][ez];
-    const double hh[3] = {hx, hy, hz};
-    const double J = hx * hy * hz * 0.125;
+    const double hh[3] = {A.h[0][ex], A.h[1][ey], A.h[2][ez]};
+    const double J = hh[0] * hh[1] * hh[2] * 0.125;
     const size_t vb0 = elem_base(A, ex, ey, ez, n3);
-    for (int i = threadIdx.x; i < m3; i += blockDim.x) acc[i] = 0.0;
-    for (int r = threadIdx.x; r < 6 * n * n; r += blockDim.x) {
-        const int face = r / (n * n), i = r - face * n * n, sn = i % n, tn = i / n;
+    for (int r = tid; r < 3 * n3; r += nt) {
+        const int d = r / n3, i = r - d * n3;
+        const int a = i % n, b = (i / n) % n, c = i / (n * n);
+        const int k = comp_stride(0, d, E, n, n) * a + comp_stride(1, d, E, n, n) * b +
+                      comp_stride(2, d, E, n, n) * c;
+        bufA[d * S::X + k] = tw[a] * tw[b] * tw[c] * J * A.v[d][vb0 + i];
+    }
+    for (int r = tid; r < 6 * n * n; r += nt) {
+        const int face = r / (n * n), st = r - face * n * n, s = st % n, t = st / n;
         const int d = face >> 1;
         const bool high = (face & 1) != 0;
         const int kn = neighbour(e3[d], A.n[d], A.bc[d], high);
-        const int own = face_node<n>(d, high ? n - 1 : 0, sn, tn);
+        const int own = face_node<n>(d, high ? n - 1 : 0, s, t);
         double f = 0.0;
         if (kn >= 0) {
             int en[3] = {ex, ey, ez};
             en[d] = kn;
             const size_t nb0 = elem_base(A, en[0], en[1], en[2], n3);
-            f = 0.5 * (A.v[d][vb0 + own] + A.v[d][nb0 + face_node<n>(d, high ? 0 : n - 1, sn, tn)]);
+            f = 0.5 * (A.v[d][vb0 + own] + A.v[d][nb0 + face_node<n>(d, high ? 0 : n - 1, s, t)]);
         } else if (A.vb[d]) {
             f = A.vb[d][vb0 + own];
         }
-        fv[face][i] = f;
+        const int u1 = tan1(d), u2 = tan2(d);
+        const double omega0 = (u1 == 0 ? hh[0] : hh[1]) * (u2 == 1 ? hh[1] : hh[2]) * 0.25;
+        const int k = comp_stride(d, d, E, n, n) * (n + (high ? 1 : 0)) + comp_stride(u1, d, E, n, n) * s +
+                      comp_stride(u2, d, E, n, n) * t;
+        bufA[d * S::X + k] = (high ? omega0 : -omega0) * tw[s] * tw[t] * f;
     }
-    // volume: acc -= (A2 (x) A1 (x) A0)^T (W J v_d), A_d = (2/h_d) dVq, others Vq
-    for (int d = 0; d < 3; ++d) {
-        __syncthreads();
-        for (int i = threadIdx.x; i < n3; i += blockDim.x) {
-            const int a = i % n, b = (i / n) % n, c = i / (n * n);
-            tv[i] = tw[a] * tw[b] * tw[c] * J * A.v[d][vb0 + i];
-        }
-        __syncthreads();
-        const double gd = 2.0 / hh[d];
-        // over a (x): s1[c][b][ix]
-        for (int i = threadIdx.x; i < n * n * m; i += blockDim.x) {
-            const int ix = i % m, cb = i / m;
-            double s = 0.0;
-            for (int a = 0; a < n; ++a) s += (d == 0 ? gd * tdV[(a) * m + (ix)] : tV[(a) * m + (ix)]) * tv[cb * n + a];
-            s1[i] = s;
-        }
-        __syncthreads();
-        // over b (y): s2[c][iy][ix]
-        for (int i = threadIdx.x; i < n * m * m; i += blockDim.x) {
-            const int ix = i % m, iy = (i / m) % m, c = i / (m * m);
-            double s = 0.0;
-            for (int b = 0; b < n; ++b)
-                s += (d == 1 ? gd * tdV[(b) * m + (iy)] : tV[(b) * m + (iy)]) * s1[(c * n + b) * m + ix];
-            s2[i] = s;
-        }
-        __syncthreads();
-        // over c (z)
-        for (int i = threadIdx.x; i < m3; i += blockDim.x) {
-            const int ix = i % m, iy = (i / m) % m, iz = i / (m * m);
-            double s = 0.0;
-            for (int c = 0; c < n; ++c)
-                s += (d == 2 ? gd * tdV[(c) * m + (iz)] : tV[(c) * m + (iz)]) * s2[(c * m + iy) * m + ix];
-            acc[i] -= s;
-        }
-    }
-    // faces: +- sum over the face nodes of omega f q, f = {v_d} or v_b,d
-    for (int d = 0; d < 3; ++d) {
-        const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-        for (int hi = 0; hi < 2; ++hi) {
-            const bool high = hi == 1;
-            const int kn = neighbour(e3[d], A.n[d], A.bc[d], high);
-            if (kn < 0 && !A.vb[d]) continue;  // boundary with v_b = 0: no term
-            const double omega0 = hh[t1] * hh[t2] * 0.25, sgn = high ? 1.0 : -1.0;
-            __syncthreads();
-            for (int i = threadIdx.x; i < n * n; i += blockDim.x) {
-                const int s = i % n, t = i / n;
-                fs[i] = sgn * omega0 * tw[s] * tw[t] * fv[2 * d + hi][i];  // [t][s]
-            }
-            __syncthreads();
-            for (int i = threadIdx.x; i < n * m; i += blockDim.x) {  // over s: fq[t][is]
-                const int is = i % m, t = i / m;
-                double sum = 0.0;
-                for (int s = 0; s < n; ++s) sum += tV[(s) * m + (is)] * fs[t * n + s];
-                fq[i] = sum;
-            }
-            __syncthreads();
-            const int ip = high ? m - 1 : 0;
-            for (int i = threadIdx.x; i < m * m; i += blockDim.x) {  // over t
-                const int is = i % m, it = i / m;
-                double sum = 0.0;
-                for (int t = 0; t < n; ++t) sum += tV[(t) * m + (it)] * fq[t * m + is];
-                const int q = d == 0 ? (it * m + is) * m + ip : d == 1 ? (it * m + ip) * m + is
-                                                                        : (ip * m + it) * m + is;
-                acc[q] += sum;
-            }
-        }
-    }
-    __syncthreads();
-    const size_t pb = (size_t)el * m3;
-    for (int i = threadIdx.x; i < m3; i += blockDim.x) A.out[pb + i] = A.scale * acc[i];
 }
 
-// ------------------------------------------------------------ gradient --
+// pass 1: Vq along the first tangential axis (n -> m), X_d -> Y_d
 template <int P, int Q>
-__global__ void __launch_bounds__(256) k_gradient(ProjArgs A)
+__host__ __device__ __forceinline__ void div_pass1(const ProjTables &tab, int tid, const double *bufA,
+                                                   double *bufB)
 {
-    constexpr int n = P + 1, m = Q + 1, n3 = n * n * n, m3 = m * m * m;
-    // the 1D tables in LDS: their lane-dependent rows would otherwise be
-    // vector loads from the kernel arguments, one per multiply-add
-    __shared__ double tV[n * m], tdV[n * m], tw[n];
-    for (int i = threadIdx.x; i < n * m; i += blockDim.x) {
-        tV[i] = A.t.Vq[i / m][i % m];
-        tdV[i] = A.t.dVq[i / m][i % m];
+    using S = DivShape<P, Q>;
+    constexpr int n = S::n, m = S::m, E = S::E, T = n * E;
+    for (int r = tid; r < 3 * T; r += S::NT) {
+        const int d = r / T, q = r - d * T, k2 = q % n, kd = q / n;
+        const int u1 = tan1(d), u2 = tan2(d);
+        const double *x = bufA + d * S::X + comp_stride(u2, d, E, n, n) * k2 + comp_stride(d, d, E, n, n) * kd;
+        const int sx = comp_stride(u1, d, E, n, n);
+        double *y = bufB + d * S::Y + comp_stride(u2, d, E, m, n) * k2 + comp_stride(d, d, E, m, n) * kd;
+        const int sy = comp_stride(u1, d, E, m, n);
+        double xv[n];
+#pragma unroll
+        for (int k = 0; k < n; ++k) xv[k] = x[k * sx];
+#pragma unroll
+        for (int i = 0; i < m; ++i) {
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < n; ++k) s += tab.Vq[k][i] * xv[k];
+            y[i * sy] = s;
+        }
     }
-    for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = A.t.w[i];
+}
+
+// pass 2: Vq along the second tangential axis (n -> m), Y_d -> Z_d
+template <int P, int Q>
+__host__ __device__ __forceinline__ void div_pass2(const ProjTables &tab, int tid, const double *bufB,
+                                                   double *bufA)
+{
+    using S = DivShape<P, Q>;
+    constexpr int n = S::n, m = S::m, E = S::E, T = m * E;
+    for (int r = tid; r < 3 * T; r += S::NT) {
+        const int d = r / T, q = r - d * T, i1 = q % m, kd = q / m;
+        const int u1 = tan1(d), u2 = tan2(d);
+        const double *y = bufB + d * S::Y + comp_stride(u1, d, E, m, n) * i1 + comp_stride(d, d, E, m, n) * kd;
+        const int sy = comp_stride(u2, d, E, m, n);
+        double *z = bufA + d * S::Z + comp_stride(u1, d, E, m, m) * i1 + comp_stride(d, d, E, m, m) * kd;
+        const int sz = comp_stride(u2, d, E, m, m);
+        double yv[n];
+#pragma unroll
+        for (int k = 0; k < n; ++k) yv[k] = y[k * sy];
+#pragma unroll
+        for (int i = 0; i < m; ++i) {
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < n; ++k) s += tab.Vq[k][i] * yv[k];
+            z[i * sz] = s;
+        }
+    }
+}
+
+// pass 3: minus (2/h_d) dVq along d on the volume layers, plus the face
+// layers on the first and last pressure layers; Z_d -> R_d (pressure layout)
+template <int P, int Q>
+__host__ __device__ __forceinline__ void div_pass3(const ProjArgs &A, const ProjTables &tab, int el, int tid,
+                                                   const double *bufA,
+                                                   double *bufB)
+{
+    using S = DivShape<P, Q>;
+    constexpr int n = S::n, m = S::m, E = S::E, T = m * m;
+    const int ex = el % A.n[0], ey = (el / A.n[0]) % A.n[1], ez = el / (A.n[0] * A.n[1]);
+    const double hh[3] = {A.h[0][ex], A.h[1][ey], A.h[2][ez]};
+    for (int r = tid; r < 3 * T; r += S::NT) {
+        const int d = r / T, q = r - d * T, i1 = q % m, i2 = q / m;
+        const int u1 = tan1(d), u2 = tan2(d);
+        const double *z = bufA + d * S::Z + comp_stride(u1, d, E, m, m) * i1 + comp_stride(u2, d, E, m, m) * i2;
+        const int sz = comp_stride(d, d, E, m, m);
+        double *out = bufB + d * S::m3 + stride_of(u1, m, m) * i1 + stride_of(u2, m, m) * i2;
+        const int so = stride_of(d, m, m);
+        const double gd = 2.0 / sel3(d, hh);
+        double zv[E];
+#pragma unroll
+        for (int k = 0; k < E; ++k) zv[k] = z[k * sz];
+#pragma unroll
+        for (int i = 0; i < m; ++i) {
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < n; ++k) s += tab.dVq[k][i] * zv[k];
+            double o = -gd * s;
+            if (i == 0) o += zv[n];
+            if (i == m - 1) o += zv[n + 1];
+            out[i * so] = o;
+        }
+    }
+}
+
+template <int P, int Q>
+__host__ __device__ __forceinline__ void div_store(const ProjArgs &A, int el, int tid, int nt, const double *bufB)
+{
+    using S = DivShape<P, Q>;
+    constexpr int m3 = S::m3;
+    const size_t pb = (size_t)el * m3;
+    for (int i = tid; i < m3; i += nt) A.out[pb + i] = A.scale * (bufB[i] + bufB[m3 + i] + bufB[2 * m3 + i]);
+}
+
+template <int P, int Q>
+__global__ void __launch_bounds__((DivShape<P, Q>::NT)) k_divergence(ProjArgs A)
+{
+    using S = DivShape<P, Q>;
+    __shared__ double tw[S::n];
+    __shared__ double bufA[S::BUF_A], bufB[S::BUF_B];
+    const int el = blockIdx.x, tid = threadIdx.x, nt = S::NT;
+    proj_weights<P>(A, tid, nt, tw);
     __syncthreads();
-    __shared__ double q[m3];
-    __shared__ double s1[m * m * n];
-    __shared__ double s2[m * n * n];
-    __shared__ double g[n3];
-    __shared__ double jf[m * m], jt[n * m], jump[n * n];
-    // the neighbours' pressure traces on the six faces (axis d, side),
-    // [it][is], staged with psi so that every global load is in flight
-    // before the first barrier
-    __shared__ double qn[6][m * m];
-    const int el = blockIdx.x;
+    div_load<P, Q>(A, el, tid, nt, tw, bufA);
+    __syncthreads();
+    div_pass1<P, Q>(A.t, tid, bufA, bufB);
+    __syncthreads();
+    div_pass2<P, Q>(A.t, tid, bufB, bufA);
+    __syncthreads();
+    div_pass3<P, Q>(A, A.t, el, tid, bufA, bufB);
+    __syncthreads();
+    div_store<P, Q>(A, el, tid, nt, bufB);
+}
+
+template <int P, int Q>
+struct GradShape {
+    static constexpr int n = P + 1, m = Q + 1, E = n + 2, n3 = n * n * n, m3 = m * m * m;
+    static constexpr int W1 = E * m * m;  // (2/h_d) dVq along d, plus the two face jumps
+    static constexpr int W2 = E * n * m;  // after the first tangential interpolation
+    static constexpr int W3 = E * n * n;  // after the second
+    static constexpr int BUF_A = 3 * W3;  // W1, later W3
+    static constexpr int BUF_B = 3 * W2;
+    // threads per work-group: 256; at P = 8 the largest pass has 297 lines
+    // and takes two steps (measured faster than 320 threads)
+    static constexpr int NT = 256;
+    static_assert(W1 <= W3, "buffer reuse");
+};
+
+// the element's pressure and its neighbours' traces on the six faces,
+// [face][it][is] (is along the lower tangential axis)
+template <int P, int Q>
+__host__ __device__ __forceinline__ void grad_load(const ProjArgs &A, int el, int tid, int nt, double *q,
+                                                   double *qn)
+{
+    constexpr int m = Q + 1, m3 = m * m * m;
     const int ex = el % A.n[0], ey = (el / A.n[0]) % A.n[1], ez = el / (A.n[0] * A.n[1]);
     const int e3[3] = {ex, ey, ez};
-    const double hh[3] = {A.h[0][ex], A.h[1][ey], A.h[2][ez]};
-    const size_t vbase = elem_base(A, ex, ey, ez, n3), pbase = elem_base(A, ex, ey, ez, m3);
-    auto at = [&](int d, int layer, int s, int t) {
-        return d == 0 ? (t * m + s) * m + layer : d == 1 ? (t * m + layer) * m + s : (layer * m + t) * m + s;
-    };
-    for (int i = threadIdx.x; i < m3; i += blockDim.x) q[i] = A.psi[pbase + i];
-    for (int r = threadIdx.x; r < 6 * m * m; r += blockDim.x) {
+    const size_t pbase = elem_base(A, ex, ey, ez, m3);
+    for (int i = tid; i < m3; i += nt) q[i] = A.psi[pbase + i];
+    for (int r = tid; r < 6 * m * m; r += nt) {
         const int face = r / (m * m), i = r - face * m * m, is = i % m, it = i / m;
         const int d = face >> 1;
         const bool high = (face & 1) != 0;
@@ -248,77 +341,150 @@ __global__ void __launch_bounds__(256) k_gradient(ProjArgs A)
         if (kn >= 0) {
             int en[3] = {ex, ey, ez};
             en[d] = kn;
-            oth = A.psi[elem_base(A, en[0], en[1], en[2], m3) + at(d, high ? 0 : m - 1, is, it)];
+            oth = A.psi[elem_base(A, en[0], en[1], en[2], m3) + face_node<m>(d, high ? 0 : m - 1, is, it)];
         }
-        qn[face][i] = oth;
+        qn[r] = oth;
     }
-    for (int d = 0; d < 3; ++d) {
-        const double gd = 2.0 / hh[d];
-        __syncthreads();
-        for (int i = threadIdx.x; i < m * m * n; i += blockDim.x) {  // over ix: s1[iz][iy][a]
-            const int a = i % n, r = i / n;
+}
+
+// pass 1: (2/h_d) dVq along d (m -> n) on the pressure lines along d, and on
+// layers n, n+1 the jumps psi_L - psi_R across the low and high faces (0
+// without a neighbour); pressure -> W1_d
+template <int P, int Q>
+__host__ __device__ __forceinline__ void grad_pass1(const ProjArgs &A, const ProjTables &tab, int el, int tid,
+                                                    const double *q,
+                                                    const double *qn, double *bufA)
+{
+    using S = GradShape<P, Q>;
+    constexpr int n = S::n, m = S::m, E = S::E, T = m * m;
+    const int ex = el % A.n[0], ey = (el / A.n[0]) % A.n[1], ez = el / (A.n[0] * A.n[1]);
+    const int e3[3] = {ex, ey, ez};
+    const double hh[3] = {A.h[0][ex], A.h[1][ey], A.h[2][ez]};
+    for (int r = tid; r < 3 * T; r += S::NT) {
+        const int d = r / T, t = r - d * T, i1 = t % m, i2 = t / m;
+        const int u1 = tan1(d), u2 = tan2(d);
+        const double *ql = q + stride_of(u1, m, m) * i1 + stride_of(u2, m, m) * i2;
+        const int sq = stride_of(d, m, m);
+        double *w = bufA + d * S::W1 + comp_stride(u1, d, E, m, m) * i1 + comp_stride(u2, d, E, m, m) * i2;
+        const int sw = comp_stride(d, d, E, m, m);
+        const double gd = 2.0 / sel3(d, hh);
+        double qv[m];
+#pragma unroll
+        for (int i = 0; i < m; ++i) qv[i] = ql[i * sq];
+#pragma unroll
+        for (int k = 0; k < n; ++k) {
             double s = 0.0;
-            for (int ix = 0; ix < m; ++ix) s += (d == 0 ? gd * tdV[(a) * m + (ix)] : tV[(a) * m + (ix)]) * q[r * m + ix];
-            s1[i] = s;
+#pragma unroll
+            for (int i = 0; i < m; ++i) s += tab.dVq[k][i] * qv[i];
+            w[k * sw] = gd * s;
         }
-        __syncthreads();
-        for (int i = threadIdx.x; i < m * n * n; i += blockDim.x) {  // over iy: s2[iz][b][a]
-            const int a = i % n, b = (i / n) % n, iz = i / (n * n);
+        const bool lo = neighbour(e3[d], A.n[d], A.bc[d], false) >= 0;
+        const bool hi = neighbour(e3[d], A.n[d], A.bc[d], true) >= 0;
+        w[n * sw] = lo ? qn[(2 * d) * T + t] - qv[0] : 0.0;
+        w[(n + 1) * sw] = hi ? qv[m - 1] - qn[(2 * d + 1) * T + t] : 0.0;
+    }
+}
+
+// pass 2: Vq along the first tangential axis (m -> n), W1_d -> W2_d
+template <int P, int Q>
+__host__ __device__ __forceinline__ void grad_pass2(const ProjTables &tab, int tid, const double *bufA,
+                                                    double *bufB)
+{
+    using S = GradShape<P, Q>;
+    constexpr int n = S::n, m = S::m, E = S::E, T = m * E;
+    for (int r = tid; r < 3 * T; r += S::NT) {
+        const int d = r / T, t = r - d * T, i2 = t % m, kd = t / m;
+        const int u1 = tan1(d), u2 = tan2(d);
+        const double *w = bufA + d * S::W1 + comp_stride(u2, d, E, m, m) * i2 + comp_stride(d, d, E, m, m) * kd;
+        const int sw = comp_stride(u1, d, E, m, m);
+        double *o = bufB + d * S::W2 + comp_stride(u2, d, E, n, m) * i2 + comp_stride(d, d, E, n, m) * kd;
+        const int so = comp_stride(u1, d, E, n, m);
+        double wv[m];
+#pragma unroll
+        for (int i = 0; i < m; ++i) wv[i] = w[i * sw];
+#pragma unroll
+        for (int a = 0; a < n; ++a) {
             double s = 0.0;
-            for (int iy = 0; iy < m; ++iy)
-                s += (d == 1 ? gd * tdV[(b) * m + (iy)] : tV[(b) * m + (iy)]) * s1[(iz * m + iy) * n + a];
-            s2[i] = s;
-        }
-        __syncthreads();
-        for (int i = threadIdx.x; i < n3; i += blockDim.x) {  // over iz: g[c][b][a]
-            const int a = i % n, b = (i / n) % n, c = i / (n * n);
-            double s = 0.0;
-            for (int iz = 0; iz < m; ++iz)
-                s += (d == 2 ? gd * tdV[(c) * m + (iz)] : tV[(c) * m + (iz)]) * s2[(iz * n + b) * n + a];
-            g[i] = s;
-        }
-        // interior faces: g_d -= [psi] / (w_face h_d) on the face's nodes
-        for (int hi = 0; hi < 2; ++hi) {
-            const bool high = hi == 1;
-            const int kn = neighbour(e3[d], A.n[d], A.bc[d], high);
-            if (kn < 0) continue;
-            // L = the element on the low side of the face, R the high side
-            const int pl = m - 1, pr = 0;
-            __syncthreads();
-            for (int i = threadIdx.x; i < m * m; i += blockDim.x) {
-                const int is = i % m, it = i / m;
-                const double own = q[at(d, high ? pl : pr, is, it)];
-                const double oth = qn[2 * d + hi][i];
-                jf[i] = high ? own - oth : oth - own;  // psi_L - psi_R on pressure face nodes
-            }
-            __syncthreads();
-            for (int i = threadIdx.x; i < n * m; i += blockDim.x) {  // over is: jt[it][s]
-                const int s = i % n, it = i / n;
-                double sum = 0.0;
-                for (int is = 0; is < m; ++is) sum += tV[(s) * m + (is)] * jf[it * m + is];
-                jt[i] = sum;
-            }
-            __syncthreads();
-            for (int i = threadIdx.x; i < n * n; i += blockDim.x) {  // over it: jump[t][s]
-                const int s = i % n, t = i / n;
-                double sum = 0.0;
-                for (int it = 0; it < m; ++it) sum += tV[(t) * m + (it)] * jt[it * n + s];
-                jump[i] = sum;
-            }
-            __syncthreads();
-            const int layer = high ? n - 1 : 0;
-            const double f = 1.0 / (tw[layer] * hh[d]);
-            for (int i = threadIdx.x; i < n * n; i += blockDim.x) {
-                const int s = i % n, t = i / n;
-                g[face_node<n>(d, layer, s, t)] -= f * jump[i];
-            }
-        }
-        __syncthreads();
-        for (int i = threadIdx.x; i < n3; i += blockDim.x) {
-            const double gv = A.fac ? A.scale * g[i] * A.fac[vbase + i] : A.scale * g[i];
-            A.g[d][vbase + i] = A.update ? A.v[d][vbase + i] + gv : gv;
+#pragma unroll
+            for (int i = 0; i < m; ++i) s += tab.Vq[a][i] * wv[i];
+            o[a * so] = s;
         }
     }
+}
+
+// pass 3: Vq along the second tangential axis (m -> n), W2_d -> W3_d
+template <int P, int Q>
+__host__ __device__ __forceinline__ void grad_pass3(const ProjTables &tab, int tid, const double *bufB,
+                                                    double *bufA)
+{
+    using S = GradShape<P, Q>;
+    constexpr int n = S::n, m = S::m, E = S::E, T = n * E;
+    for (int r = tid; r < 3 * T; r += S::NT) {
+        const int d = r / T, t = r - d * T, a1 = t % n, kd = t / n;
+        const int u1 = tan1(d), u2 = tan2(d);
+        const double *w = bufB + d * S::W2 + comp_stride(u1, d, E, n, m) * a1 + comp_stride(d, d, E, n, m) * kd;
+        const int sw = comp_stride(u2, d, E, n, m);
+        double *o = bufA + d * S::W3 + comp_stride(u1, d, E, n, n) * a1 + comp_stride(d, d, E, n, n) * kd;
+        const int so = comp_stride(u2, d, E, n, n);
+        double wv[m];
+#pragma unroll
+        for (int i = 0; i < m; ++i) wv[i] = w[i * sw];
+#pragma unroll
+        for (int a = 0; a < n; ++a) {
+            double s = 0.0;
+#pragma unroll
+            for (int i = 0; i < m; ++i) s += tab.Vq[a][i] * wv[i];
+            o[a * so] = s;
+        }
+    }
+}
+
+// g_d = W3_d on the volume layers, minus the interpolated jump over
+// (w_face h_d) on the first and last layers along d; then the factor, the
+// scale and the update
+template <int P, int Q>
+__host__ __device__ __forceinline__ void grad_store(const ProjArgs &A, int el, int tid, int nt, const double *tw,
+                                                    const double *bufA)
+{
+    using S = GradShape<P, Q>;
+    constexpr int n = S::n, E = S::E, n3 = S::n3;
+    const int ex = el % A.n[0], ey = (el / A.n[0]) % A.n[1], ez = el / (A.n[0] * A.n[1]);
+    const double hh[3] = {A.h[0][ex], A.h[1][ey], A.h[2][ez]};
+    const size_t vbase = elem_base(A, ex, ey, ez, n3);
+    for (int r = tid; r < 3 * n3; r += nt) {
+        const int d = r / n3, i = r - d * n3;
+        const int co[3] = {i % n, (i / n) % n, i / (n * n)};
+        const int u1 = tan1(d), u2 = tan2(d);
+        const int cd = d == 0 ? co[0] : d == 1 ? co[1] : co[2];
+        const int c1 = u1 == 0 ? co[0] : co[1], c2 = u2 == 1 ? co[1] : co[2];
+        const double *w = bufA + d * S::W3 + comp_stride(u1, d, E, n, n) * c1 + comp_stride(u2, d, E, n, n) * c2;
+        const int sw = comp_stride(d, d, E, n, n);
+        double g = w[cd * sw];
+        if (cd == 0) g -= (1.0 / (tw[0] * sel3(d, hh))) * w[n * sw];
+        if (cd == n - 1) g -= (1.0 / (tw[n - 1] * sel3(d, hh))) * w[(n + 1) * sw];
+        const double gv = A.fac ? A.scale * g * A.fac[vbase + i] : A.scale * g;
+        A.g[d][vbase + i] = A.update ? A.v[d][vbase + i] + gv : gv;
+    }
+}
+
+template <int P, int Q>
+__global__ void __launch_bounds__((GradShape<P, Q>::NT)) k_gradient(ProjArgs A)
+{
+    using S = GradShape<P, Q>;
+    __shared__ double tw[S::n];
+    __shared__ double q[S::m3], qn[6 * S::m * S::m];
+    __shared__ double bufA[S::BUF_A], bufB[S::BUF_B];
+    const int el = blockIdx.x, tid = threadIdx.x, nt = S::NT;
+    proj_weights<P>(A, tid, nt, tw);
+    grad_load<P, Q>(A, el, tid, nt, q, qn);
+    __syncthreads();
+    grad_pass1<P, Q>(A, A.t, el, tid, q, qn, bufA);
+    __syncthreads();
+    grad_pass2<P, Q>(A.t, tid, bufA, bufB);
+    __syncthreads();
+    grad_pass3<P, Q>(A.t, tid, bufB, bufA);
+    __syncthreads();
+    grad_store<P, Q>(A, el, tid, nt, tw, bufA);
 }
 
 // ------------------------------------------------ equal-order variants --
@@ -326,8 +492,7 @@ __global__ void __launch_bounds__(256) k_gradient(ProjArgs A)
 // interpolation factor Vq is the identity (exact zeros and ones from the
 // product formula), so only the derivative pass along each axis remains:
 // one 1D contraction per direction and node instead of three passes, and the
-// face terms act on the face nodes directly.  Same sums in the same order as
-// the general kernels above, so the results are bitwise theirs.
+// face terms act on the face nodes directly.
 template <int P>
 __global__ void __launch_bounds__(256) k_divergence_eq(ProjArgs A)
 {
@@ -587,7 +752,7 @@ int launch_divergence(const MeshDev &mv, const MeshDev &mp, const double *const 
         if constexpr (Pv == Qv)
             hipLaunchKernelGGL((k_divergence_eq<Pv>), dim3((unsigned)mv.nel), dim3(256), 0, s, a);
         else
-            hipLaunchKernelGGL((k_divergence<Pv, Qv>), dim3((unsigned)mv.nel), dim3(256), 0, s, a);
+            hipLaunchKernelGGL((k_divergence<Pv, Qv>), dim3((unsigned)mv.nel), dim3(DivShape<Pv, Qv>::NT), 0, s, a);
     });
 }
 
@@ -609,7 +774,7 @@ int launch_gradient(const MeshDev &mv, const MeshDev &mp, const double *psi, con
         if constexpr (Pv == Qv)
             hipLaunchKernelGGL((k_gradient_eq<Pv>), dim3((unsigned)mv.nel), dim3(256), 0, s, a);
         else
-            hipLaunchKernelGGL((k_gradient<Pv, Qv>), dim3((unsigned)mv.nel), dim3(256), 0, s, a);
+            hipLaunchKernelGGL((k_gradient<Pv, Qv>), dim3((unsigned)mv.nel), dim3(GradShape<Pv, Qv>::NT), 0, s, a);
     });
 }
 
