@@ -1,0 +1,75 @@
+"""The P / P-1 divergence and gradient kernels' phases run on the CPU, for
+every thread index of a work-group in turn (tests/host_phases), built with an
+address sanitizer on the host side: their LDS and global indexing stays in
+bounds, and their results equal the oracle's definitions (<= 1e-12 relative,
+the same exactly integrated sums in FP64) on every velocity degree 4..8,
+periodic, Dirichlet and Neumann axes, single-element periodic axes, a graded
+axis, with and without wall data."""
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import projection
+from tests.helpers import make_spec, ndof
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+CASES = [((2, 2, 2), 4, (0, 0, 0), False),
+         ((3, 2, 2), 5, (0, 0, 1), True),
+         ((1, 3, 2), 6, (0, 1, 2), False),
+         ((2, 1, 3), 7, (2, 0, 1), True),
+         ((2, 2, 1), 8, (1, 2, 0), False),
+         ((1, 1, 1), 7, (0, 0, 0), False),
+         ((3, 2, 2), 7, (1, 1, 1), True)]
+IDS = ["P4_periodic", "P5_channel", "P6_n1x", "P7_mixed", "P8_n1z", "P7_one_element", "P7_walls"]
+
+
+@pytest.fixture(scope="module")
+def harness(tmp_path_factory):
+    if not os.path.exists(HIPCC):
+        pytest.skip("hipcc not available")
+    exe = str(tmp_path_factory.mktemp("phases") / "projection_phases")
+    cmd = [HIPCC, "-O1", "-std=c++17", "-x", "hip", "--offload-arch=gfx950",
+           "-Xarch_host", "-fsanitize=address",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-I", os.path.join(ROOT, "include"), "-I", os.path.join(ROOT, "paper_2112_04167_amd", "csrc"),
+           os.path.join(HERE, "host_phases", "projection_phases.hip"), "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-4000:]
+    return exe
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+@pytest.mark.parametrize("with_vb", [False, True])
+def test_projection_phases_match_oracle(harness, tmp_path, case, with_vb):
+    n, P, bc, st = case
+    spec = make_spec(n, P, bc, st)
+    N = ndof(spec)
+    Np = n[0] * n[1] * n[2] * P ** 3
+    rng = np.random.default_rng(11 + P)
+    v = [rng.uniform(-1, 1, N) for _ in range(3)]
+    vb = [rng.uniform(-1, 1, N) for _ in range(3)] if with_vb else []
+    psi = np.random.default_rng(23 + P).uniform(-1, 1, Np)
+    h = [np.diff(np.asarray(spec[k], dtype=np.float64)) for k in ("xv", "yv", "zv")]
+    fin, fout = tmp_path / "in.bin", tmp_path / "out.bin"
+    np.concatenate(h + v + vb + [psi]).astype(np.float64).tofile(fin)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0")
+    r = subprocess.run([harness, str(P), *map(str, n), *map(str, bc), str(int(with_vb)), str(fin), str(fout)],
+                       capture_output=True, text=True, env=env)
+    assert r.returncode == 0, r.stderr[-4000:]
+    out = np.fromfile(fout)
+    assert out.size == Np + 3 * N
+    div = out[:Np]
+    g = [out[Np + d * N:Np + (d + 1) * N] for d in range(3)]
+    assert rel(div, projection.divergence(spec, v, vb or None)) <= 1e-12
+    want = projection.gradient(spec, psi)
+    for d in range(3):
+        assert rel(g[d], want[d]) <= 1e-12
