@@ -491,33 +491,37 @@ __global__ void __launch_bounds__((GradShape<P, Q>::NT)) k_gradient(ProjArgs A)
 // With the scalar space equal to the velocity space (Q = P) the
 // interpolation factor Vq is the identity (exact zeros and ones from the
 // product formula), so only the derivative pass along each axis remains:
-// one 1D contraction per direction and node instead of three passes, and the
-// face terms act on the face nodes directly.
+// one 1D contraction per component, along the component's own axis, and
+// the face terms act on the face nodes directly.  One thread takes one line
+// of one component (3 (P+1)^2 lines, at most 243), with the derivative
+// matrix from the kernel arguments at compile-time indices (the GLL weights
+// of the divergence from LDS); a last pass sums
+// (divergence) or scales and stores (gradient) node by node.
 template <int P>
-__global__ void __launch_bounds__(256) k_divergence_eq(ProjArgs A)
+struct EqShape {
+    static constexpr int n = P + 1, n2 = n * n, n3 = n2 * n;
+    static constexpr int NT = 256;
+    static_assert(3 * n2 <= NT, "one line per thread");
+};
+
+// the element's three velocity components (raw) and the face values f of
+// the six faces (axis d, side; [t][s]): the mean of the two traces, the
+// wall data, or 0 (no term)
+template <int P>
+__host__ __device__ __forceinline__ void eqdiv_load(const ProjArgs &A, int el, int tid, double *tv, double *fv,
+                                                    double *tw)
 {
-    constexpr int n = P + 1, n2 = n * n, n3 = n2 * n;
-    __shared__ double tdV[n * n], tw[n];  // the 1D tables in LDS (see k_divergence)
-    for (int i = threadIdx.x; i < n * n; i += blockDim.x) tdV[i] = A.t.dVq[i / n][i % n];
-    for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = A.t.w[i];
-    __syncthreads();
-    __shared__ double tv[3][n3];
-    // the face values f of the six faces (axis d, side), [t][s]: the mean of
-    // the two traces, the wall data, or 0 (no term), staged with the volume
-    // data so that all global loads are in flight before the first barrier
-    __shared__ double fv[6][n2];
-    const int el = blockIdx.x;
+    using S = EqShape<P>;
+    constexpr int n = S::n, n2 = S::n2, n3 = S::n3;
     const int ex = el % A.n[0], ey = (el / A.n[0]) % A.n[1], ez = el / (A.n[0] * A.n[1]);
     const int e3[3] = {ex, ey, ez};
-    const double hh[3] = {A.h[0][ex], A.h[1][ey], A.h[2][ez]};
-    const double J = hh[0] * hh[1] * hh[2] * 0.125;
     const size_t vb0 = elem_base(A, ex, ey, ez, n3);
-    for (int r = threadIdx.x; r < 3 * n3; r += blockDim.x) {
+    for (int i = tid; i < n; i += S::NT) tw[i] = A.t.w[i];
+    for (int r = tid; r < 3 * n3; r += S::NT) {
         const int d = r / n3, i = r - d * n3;
-        const int a = i % n, b = (i / n) % n, c = i / (n * n);
-        tv[d][i] = tw[a] * tw[b] * tw[c] * J * A.v[d][vb0 + i];
+        tv[r] = A.v[d][vb0 + i];
     }
-    for (int r = threadIdx.x; r < 6 * n2; r += blockDim.x) {
+    for (int r = tid; r < 6 * n2; r += S::NT) {
         const int face = r / n2, st = r - face * n2, s = st % n, t = st / n;
         const int d = face >> 1;
         const bool high = (face & 1) != 0;
@@ -532,78 +536,89 @@ __global__ void __launch_bounds__(256) k_divergence_eq(ProjArgs A)
         } else if (A.vb[d]) {
             f = A.vb[d][vb0 + face_node<n>(d, layer, s, t)];
         }
-        fv[face][st] = f;
+        fv[r] = f;
     }
-    __syncthreads();
-    for (int r = threadIdx.x; r < n3; r += blockDim.x) {
-        const int a = r % n, b = (r / n) % n, c = r / (n * n);
-        const int co[3] = {a, b, c};
-        double acc = 0.0;
-        {
-            const double gd = 2.0 / hh[0];
-            double sum = 0.0;
+}
+
+// the line of component d at tangential position (s, t): minus (2/h_d) dV^T
+// of the GLL-weighted values, plus the face terms on its end nodes; written
+// back in place (every line is read whole before any is written, within
+// its own thread, and lines are disjoint)
+template <int P>
+__host__ __device__ __forceinline__ void eqdiv_lines(const ProjArgs &A, const ProjTables &tab, int el, int tid,
+                                                     double *tv, const double *fv, const double *tw)
+{
+    using S = EqShape<P>;
+    constexpr int n = S::n, n2 = S::n2, n3 = S::n3;
+    const int ex = el % A.n[0], ey = (el / A.n[0]) % A.n[1], ez = el / (A.n[0] * A.n[1]);
+    const double hh[3] = {A.h[0][ex], A.h[1][ey], A.h[2][ez]};
+    const double J = hh[0] * hh[1] * hh[2] * 0.125;
+    const int r = tid;
+    if (r < 3 * n2) {
+        const int d = r / n2, st = r - d * n2, s = st % n, t = st / n;
+        const int u1 = tan1(d), u2 = tan2(d);
+        double *x = tv + d * n3 + stride_of(u1, n, n) * s + stride_of(u2, n, n) * t;
+        const int sd = stride_of(d, n, n);
+        const double wst = tw[s] * tw[t];
+        double xv[n];
 #pragma unroll
-            for (int k = 0; k < n; ++k) sum += gd * tdV[(k) * n + (a)] * tv[0][(c * n + b) * n + k];
-            acc -= sum;
+        for (int k = 0; k < n; ++k) xv[k] = tw[k] * x[k * sd];
+        const double c = wst * J, gd = 2.0 / sel3(d, hh);
+        const double omega0 = (u1 == 0 ? hh[0] : hh[1]) * (u2 == 1 ? hh[1] : hh[2]) * 0.25;
+        const double flo = fv[(2 * d) * n2 + st], fhi = fv[(2 * d + 1) * n2 + st];
+        // rows of dV^T in the outer loop: each row is contiguous in the
+        // kernel arguments, so its scalar loads stay few and short-lived
+        double sum[n];
+#pragma unroll
+        for (int i = 0; i < n; ++i) sum[i] = 0.0;
+#pragma unroll
+        for (int k = 0; k < n; ++k)
+#pragma unroll
+            for (int i = 0; i < n; ++i) sum[i] += tab.dVq[k][i] * xv[k];
+#pragma unroll
+        for (int i = 0; i < n; ++i) {
+            double o = -(gd * c) * sum[i];
+            if (i == 0) o -= omega0 * wst * flo;
+            if (i == n - 1) o += omega0 * wst * fhi;
+            x[i * sd] = o;
         }
-        {
-            const double gd = 2.0 / hh[1];
-            double sum = 0.0;
-#pragma unroll
-            for (int k = 0; k < n; ++k) sum += gd * tdV[(k) * n + (b)] * tv[1][(c * n + k) * n + a];
-            acc -= sum;
-        }
-        {
-            const double gd = 2.0 / hh[2];
-            double sum = 0.0;
-#pragma unroll
-            for (int k = 0; k < n; ++k) sum += gd * tdV[(k) * n + (c)] * tv[2][(k * n + b) * n + a];
-            acc -= sum;
-        }
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-            const int s = co[t1], t = co[t2];
-#pragma unroll
-            for (int hi = 0; hi < 2; ++hi) {
-                const bool high = hi == 1;
-                if (co[d] != (high ? n - 1 : 0)) continue;
-                const double omega0 = hh[t1] * hh[t2] * 0.25, sgn = high ? 1.0 : -1.0;
-                acc += sgn * omega0 * tw[s] * tw[t] * fv[2 * d + hi][t * n + s];
-            }
-        }
-        A.out[vb0 + r] = A.scale * acc;
     }
 }
 
 template <int P>
-__global__ void __launch_bounds__(256) k_gradient_eq(ProjArgs A)
+__host__ __device__ __forceinline__ void eqdiv_store(const ProjArgs &A, int el, int tid, const double *tv)
 {
-    constexpr int n = P + 1, n2 = n * n, n3 = n2 * n;
-    // the 1D tables in LDS (see k_divergence); tdVt = tdV transposed, for the
-    // x derivative, whose lanes run along the table's row index (strided
-    // rows would put consecutive lanes on the same LDS banks)
-    __shared__ double tdV[n * n], tdVt[n * n], tw[n];
-    for (int i = threadIdx.x; i < n * n; i += blockDim.x) {
-        tdV[i] = A.t.dVq[i / n][i % n];
-        tdVt[i] = A.t.dVq[i % n][i / n];
-    }
-    for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = A.t.w[i];
+    using S = EqShape<P>;
+    constexpr int n3 = S::n3;
+    const size_t vb0 = (size_t)el * n3;
+    for (int i = tid; i < n3; i += S::NT) A.out[vb0 + i] = A.scale * (tv[i] + tv[n3 + i] + tv[2 * n3 + i]);
+}
+
+template <int P>
+__global__ void __launch_bounds__(EqShape<P>::NT) k_divergence_eq(ProjArgs A)
+{
+    using S = EqShape<P>;
+    __shared__ double tv[3 * S::n3], fv[6 * S::n2], tw[S::n];
+    const int el = blockIdx.x, tid = threadIdx.x;
+    eqdiv_load<P>(A, el, tid, tv, fv, tw);
     __syncthreads();
-    // psi of the element, the neighbours' traces on the six faces (axis d,
-    // side; [t][s]) and the nodal factor, all staged before the first
-    // barrier so that their global loads are in flight together
-    __shared__ double q[n3], qn[6][n2], fq[n3];
-    const int el = blockIdx.x;
+    eqdiv_lines<P>(A, A.t, el, tid, tv, fv, tw);
+    __syncthreads();
+    eqdiv_store<P>(A, el, tid, tv);
+}
+
+// the element's scalar and the neighbours' traces on the six faces (axis d,
+// side; [t][s])
+template <int P>
+__host__ __device__ __forceinline__ void eqgrad_load(const ProjArgs &A, int el, int tid, double *q, double *qn)
+{
+    using S = EqShape<P>;
+    constexpr int n = S::n, n2 = S::n2, n3 = S::n3;
     const int ex = el % A.n[0], ey = (el / A.n[0]) % A.n[1], ez = el / (A.n[0] * A.n[1]);
     const int e3[3] = {ex, ey, ez};
-    const double hh[3] = {A.h[0][ex], A.h[1][ey], A.h[2][ez]};
     const size_t base = elem_base(A, ex, ey, ez, n3);
-    for (int r = threadIdx.x; r < n3; r += blockDim.x) {
-        q[r] = A.psi[base + r];
-        if (A.fac) fq[r] = A.fac[base + r];
-    }
-    for (int r = threadIdx.x; r < 6 * n2; r += blockDim.x) {
+    for (int r = tid; r < n3; r += S::NT) q[r] = A.psi[base + r];
+    for (int r = tid; r < 6 * n2; r += S::NT) {
         const int face = r / n2, st = r - face * n2, s = st % n, t = st / n;
         const int d = face >> 1;
         const bool high = (face & 1) != 0;
@@ -614,41 +629,71 @@ __global__ void __launch_bounds__(256) k_gradient_eq(ProjArgs A)
             en[d] = kn;
             oth = A.psi[elem_base(A, en[0], en[1], en[2], n3) + face_node<n>(d, high ? 0 : n - 1, s, t)];
         }
-        qn[face][st] = oth;
+        qn[r] = oth;
     }
-    __syncthreads();
-    for (int r = threadIdx.x; r < n3; r += blockDim.x) {
-        const int a = r % n, b = (r / n) % n, c = r / (n * n);
-        const int co[3] = {a, b, c};
-        for (int d = 0; d < 3; ++d) {
-            const double gd = 2.0 / hh[d];
-            double g = 0.0;
-            if (d == 0) {
+}
+
+// the line along d at tangential position (s, t): (2/h_d) dV of the scalar,
+// minus the jump over (w_face h_d) on the end nodes whose face has a
+// neighbour; into the component's slot of R
+template <int P>
+__host__ __device__ __forceinline__ void eqgrad_lines(const ProjArgs &A, const ProjTables &tab, int el, int tid,
+                                                      const double *q, const double *qn, double *R)
+{
+    using S = EqShape<P>;
+    constexpr int n = S::n, n2 = S::n2, n3 = S::n3;
+    const int ex = el % A.n[0], ey = (el / A.n[0]) % A.n[1], ez = el / (A.n[0] * A.n[1]);
+    const int e3[3] = {ex, ey, ez};
+    const double hh[3] = {A.h[0][ex], A.h[1][ey], A.h[2][ez]};
+    const int r = tid;
+    if (r < 3 * n2) {
+        const int d = r / n2, st = r - d * n2, s = st % n, t = st / n;
+        const int u1 = tan1(d), u2 = tan2(d);
+        const int off = stride_of(u1, n, n) * s + stride_of(u2, n, n) * t, sd = stride_of(d, n, n);
+        double xv[n];
 #pragma unroll
-                for (int k = 0; k < n; ++k) g += gd * tdVt[(k) * n + (a)] * q[(c * n + b) * n + k];
-            } else if (d == 1) {
+        for (int k = 0; k < n; ++k) xv[k] = q[off + k * sd];
+        const double hd = sel3(d, hh), gd = 2.0 / hd;
+        const bool lo = neighbour(e3[d], A.n[d], A.bc[d], false) >= 0;
+        const bool hi = neighbour(e3[d], A.n[d], A.bc[d], true) >= 0;
+        double *o = R + d * n3 + off;
 #pragma unroll
-                for (int k = 0; k < n; ++k) g += gd * tdV[(b) * n + (k)] * q[(c * n + k) * n + a];
-            } else {
+        for (int i = 0; i < n; ++i) {
+            double sum = 0.0;
 #pragma unroll
-                for (int k = 0; k < n; ++k) g += gd * tdV[(c) * n + (k)] * q[(k * n + b) * n + a];
-            }
-            const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-            for (int hi = 0; hi < 2; ++hi) {
-                const bool high = hi == 1;
-                const int layer = high ? n - 1 : 0;
-                if (co[d] != layer) continue;
-                if (neighbour(e3[d], A.n[d], A.bc[d], high) < 0) continue;
-                const double oth = qn[2 * d + hi][co[t2] * n + co[t1]];
-                const double own = q[r];
-                const double jump = high ? own - oth : oth - own;
-                const double f = 1.0 / (tw[layer] * hh[d]);
-                g -= f * jump;
-            }
-            const double gv = A.fac ? A.scale * g * fq[r] : A.scale * g;
-            A.g[d][base + r] = A.update ? A.v[d][base + r] + gv : gv;
+            for (int k = 0; k < n; ++k) sum += tab.dVq[i][k] * xv[k];
+            double g = gd * sum;
+            if (i == 0 && lo) g -= (1.0 / (tab.w[0] * hd)) * (qn[(2 * d) * n2 + st] - xv[0]);
+            if (i == n - 1 && hi) g -= (1.0 / (tab.w[n - 1] * hd)) * (xv[n - 1] - qn[(2 * d + 1) * n2 + st]);
+            o[i * sd] = g;
         }
     }
+}
+
+template <int P>
+__host__ __device__ __forceinline__ void eqgrad_store(const ProjArgs &A, int el, int tid, const double *R)
+{
+    using S = EqShape<P>;
+    constexpr int n3 = S::n3;
+    const size_t base = (size_t)el * n3;
+    for (int r = tid; r < 3 * n3; r += S::NT) {
+        const int d = r / n3, i = r - d * n3;
+        const double gv = A.fac ? A.scale * R[r] * A.fac[base + i] : A.scale * R[r];
+        A.g[d][base + i] = A.update ? A.v[d][base + i] + gv : gv;
+    }
+}
+
+template <int P>
+__global__ void __launch_bounds__(EqShape<P>::NT) k_gradient_eq(ProjArgs A)
+{
+    using S = EqShape<P>;
+    __shared__ double q[S::n3], qn[6 * S::n2], R[3 * S::n3];
+    const int el = blockIdx.x, tid = threadIdx.x;
+    eqgrad_load<P>(A, el, tid, q, qn);
+    __syncthreads();
+    eqgrad_lines<P>(A, A.t, el, tid, q, qn, R);
+    __syncthreads();
+    eqgrad_store<P>(A, el, tid, R);
 }
 
 ProjTables make_tables(int P, int Q)
@@ -750,7 +795,7 @@ int launch_divergence(const MeshDev &mv, const MeshDev &mp, const double *const 
     return with_pair(mv.P, mp.P, [&](auto PC, auto QC) {
         constexpr int Pv = decltype(PC)::value, Qv = decltype(QC)::value;
         if constexpr (Pv == Qv)
-            hipLaunchKernelGGL((k_divergence_eq<Pv>), dim3((unsigned)mv.nel), dim3(256), 0, s, a);
+            hipLaunchKernelGGL((k_divergence_eq<Pv>), dim3((unsigned)mv.nel), dim3(EqShape<Pv>::NT), 0, s, a);
         else
             hipLaunchKernelGGL((k_divergence<Pv, Qv>), dim3((unsigned)mv.nel), dim3(DivShape<Pv, Qv>::NT), 0, s, a);
     });
@@ -772,7 +817,7 @@ int launch_gradient(const MeshDev &mv, const MeshDev &mp, const double *psi, con
     return with_pair(mv.P, mp.P, [&](auto PC, auto QC) {
         constexpr int Pv = decltype(PC)::value, Qv = decltype(QC)::value;
         if constexpr (Pv == Qv)
-            hipLaunchKernelGGL((k_gradient_eq<Pv>), dim3((unsigned)mv.nel), dim3(256), 0, s, a);
+            hipLaunchKernelGGL((k_gradient_eq<Pv>), dim3((unsigned)mv.nel), dim3(EqShape<Pv>::NT), 0, s, a);
         else
             hipLaunchKernelGGL((k_gradient<Pv, Qv>), dim3((unsigned)mv.nel), dim3(GradShape<Pv, Qv>::NT), 0, s, a);
     });

@@ -1,13 +1,15 @@
-// The projection kernels' phases (divergence and gradient, velocity degree P,
-// pressure degree P-1) run on the CPU: each phase for every thread index of
-// the work-group in turn, element by element, with the LDS buffers on the
-// heap, so that an address sanitizer build checks every shared and global
-// access of the kernels' index arithmetic.  Reads the mesh and the fields
-// from a binary file and writes the divergence and the gradient.
+// The divergence and gradient kernels' phases run on the CPU: each phase for
+// every thread index of the work-group in turn, element by element, with the
+// LDS buffers on the heap, so that an address sanitizer build checks every
+// shared and global access of the kernels' index arithmetic.  Either the
+// projection's pair (velocity degree P, pressure degree P-1) or the equal-order
+// pair (scalar degree P, with a nodal factor on the gradient).  Reads the mesh
+// and the fields from a binary file and writes the divergence and the
+// gradient.
 //
-//   projection_phases P nx ny nz bcx bcy bcz with_vb in.bin out.bin
-//   in.bin:  h_x[nx] h_y[ny] h_z[nz] v0 v1 v2 [vb0 vb1 vb2] psi   (float64)
-//   out.bin: div[Np] g0[N] g1[N] g2[N]
+//   projection_phases P nx ny nz bcx bcy bcz with_vb equal in.bin out.bin
+//   in.bin:  h_x[nx] h_y[ny] h_z[nz] v0 v1 v2 [vb0 vb1 vb2] psi [fac]  (float64)
+//   out.bin: div[Nq] g0[N] g1[N] g2[N]   (Nq = N when equal, else Np)
 #include "projection.hip"
 #include "gll_host.cpp"
 
@@ -48,22 +50,39 @@ void run_elements(const ProjArgs &A, int nel)
         for (int t = 0; t < G::NT; ++t) grad_store<P, Q>(A, el, t, G::NT, tw.data(), ga.data());
     }
 }
+
+template <int P>
+void run_elements_equal(const ProjArgs &A, int nel)
+{
+    using S = EqShape<P>;
+    for (int el = 0; el < nel; ++el) {
+        std::vector<double> tv(3 * S::n3), fv(6 * S::n2), tw(S::n);
+        for (int t = 0; t < S::NT; ++t) eqdiv_load<P>(A, el, t, tv.data(), fv.data(), tw.data());
+        for (int t = 0; t < S::NT; ++t) eqdiv_lines<P>(A, A.t, el, t, tv.data(), fv.data(), tw.data());
+        for (int t = 0; t < S::NT; ++t) eqdiv_store<P>(A, el, t, tv.data());
+        std::vector<double> q(S::n3), qn(6 * S::n2), R(3 * S::n3);
+        for (int t = 0; t < S::NT; ++t) eqgrad_load<P>(A, el, t, q.data(), qn.data());
+        for (int t = 0; t < S::NT; ++t) eqgrad_lines<P>(A, A.t, el, t, q.data(), qn.data(), R.data());
+        for (int t = 0; t < S::NT; ++t) eqgrad_store<P>(A, el, t, R.data());
+    }
+}
 }  // namespace
 }  // namespace dg
 
 int main(int argc, char **argv)
 {
-    if (argc != 11) {
-        fprintf(stderr, "usage: %s P nx ny nz bcx bcy bcz with_vb in.bin out.bin\n", argv[0]);
+    if (argc != 12) {
+        fprintf(stderr, "usage: %s P nx ny nz bcx bcy bcz with_vb equal in.bin out.bin\n", argv[0]);
         return 2;
     }
     const int P = atoi(argv[1]);
     const int n[3] = {atoi(argv[2]), atoi(argv[3]), atoi(argv[4])};
     const int bc[3] = {atoi(argv[5]), atoi(argv[6]), atoi(argv[7])};
-    const int with_vb = atoi(argv[8]);
+    const int with_vb = atoi(argv[8]), equal = atoi(argv[9]);
     const int nel = n[0] * n[1] * n[2];
-    const size_t N = (size_t)nel * (P + 1) * (P + 1) * (P + 1), Np = (size_t)nel * P * P * P;
-    FILE *f = fopen(argv[9], "rb");
+    const size_t N = (size_t)nel * (P + 1) * (P + 1) * (P + 1);
+    const size_t Np = equal ? N : (size_t)nel * P * P * P;
+    FILE *f = fopen(argv[10], "rb");
     if (!f) return 3;
     auto read = [&](size_t k) {
         std::vector<double> v(k);
@@ -76,10 +95,11 @@ int main(int argc, char **argv)
     if (with_vb)
         for (int d = 0; d < 3; ++d) vb[d] = read(N);
     const std::vector<double> psi = read(Np);
+    const std::vector<double> fac = equal ? read(N) : std::vector<double>();
     fclose(f);
     std::vector<double> div(Np, -999.0), g[3];
     dg::ProjArgs A{};
-    A.t = dg::make_tables(P, P - 1);
+    A.t = dg::make_tables(P, equal ? P : P - 1);
     for (int d = 0; d < 3; ++d) {
         g[d].assign(N, -999.0);
         A.n[d] = n[d];
@@ -92,15 +112,28 @@ int main(int argc, char **argv)
     A.psi = psi.data();
     A.out = div.data();
     A.scale = 1.0;
-    switch (P) {
-        case 4: dg::run_elements<4>(A, nel); break;
-        case 5: dg::run_elements<5>(A, nel); break;
-        case 6: dg::run_elements<6>(A, nel); break;
-        case 7: dg::run_elements<7>(A, nel); break;
-        case 8: dg::run_elements<8>(A, nel); break;
-        default: return 4;
+    A.fac = equal ? fac.data() : nullptr;
+    if (equal) {
+        switch (P) {
+            case 3: dg::run_elements_equal<3>(A, nel); break;
+            case 4: dg::run_elements_equal<4>(A, nel); break;
+            case 5: dg::run_elements_equal<5>(A, nel); break;
+            case 6: dg::run_elements_equal<6>(A, nel); break;
+            case 7: dg::run_elements_equal<7>(A, nel); break;
+            case 8: dg::run_elements_equal<8>(A, nel); break;
+            default: return 4;
+        }
+    } else {
+        switch (P) {
+            case 4: dg::run_elements<4>(A, nel); break;
+            case 5: dg::run_elements<5>(A, nel); break;
+            case 6: dg::run_elements<6>(A, nel); break;
+            case 7: dg::run_elements<7>(A, nel); break;
+            case 8: dg::run_elements<8>(A, nel); break;
+            default: return 4;
+        }
     }
-    FILE *o = fopen(argv[10], "wb");
+    FILE *o = fopen(argv[11], "wb");
     if (!o) return 5;
     fwrite(div.data(), sizeof(double), Np, o);
     for (int d = 0; d < 3; ++d) fwrite(g[d].data(), sizeof(double), N, o);

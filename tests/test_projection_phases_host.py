@@ -1,8 +1,9 @@
-"""The P / P-1 divergence and gradient kernels' phases run on the CPU, for
-every thread index of a work-group in turn (tests/host_phases), built with an
+"""The divergence and gradient kernels' phases (the projection's P / P-1 pair
+and the equal-order pair of the viscous terms) run on the CPU, for every
+thread index of a work-group in turn (tests/host_phases), built with an
 address sanitizer on the host side: their LDS and global indexing stays in
 bounds, and their results equal the oracle's definitions (<= 1e-12 relative,
-the same exactly integrated sums in FP64) on every velocity degree 4..8,
+the same exactly integrated sums in FP64) on every degree the kernels take,
 periodic, Dirichlet and Neumann axes, single-element periodic axes, a graded
 axis, with and without wall data."""
 import os
@@ -47,29 +48,47 @@ def rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
-@pytest.mark.parametrize("case", CASES, ids=IDS)
-@pytest.mark.parametrize("with_vb", [False, True])
-def test_projection_phases_match_oracle(harness, tmp_path, case, with_vb):
+def run_case(harness, tmp_path, case, with_vb, equal):
     n, P, bc, st = case
     spec = make_spec(n, P, bc, st)
     N = ndof(spec)
-    Np = n[0] * n[1] * n[2] * P ** 3
+    Nq = N if equal else n[0] * n[1] * n[2] * P ** 3
     rng = np.random.default_rng(11 + P)
     v = [rng.uniform(-1, 1, N) for _ in range(3)]
     vb = [rng.uniform(-1, 1, N) for _ in range(3)] if with_vb else []
-    psi = np.random.default_rng(23 + P).uniform(-1, 1, Np)
+    psi = np.random.default_rng(23 + P).uniform(-1, 1, Nq)
+    fac = [np.random.default_rng(31 + P).uniform(0.5, 2.0, N)] if equal else []
     h = [np.diff(np.asarray(spec[k], dtype=np.float64)) for k in ("xv", "yv", "zv")]
     fin, fout = tmp_path / "in.bin", tmp_path / "out.bin"
-    np.concatenate(h + v + vb + [psi]).astype(np.float64).tofile(fin)
+    np.concatenate(h + v + vb + [psi] + fac).astype(np.float64).tofile(fin)
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0")
-    r = subprocess.run([harness, str(P), *map(str, n), *map(str, bc), str(int(with_vb)), str(fin), str(fout)],
-                       capture_output=True, text=True, env=env)
+    r = subprocess.run([harness, str(P), *map(str, n), *map(str, bc), str(int(with_vb)), str(int(equal)),
+                        str(fin), str(fout)], capture_output=True, text=True, env=env)
     assert r.returncode == 0, r.stderr[-4000:]
     out = np.fromfile(fout)
-    assert out.size == Np + 3 * N
-    div = out[:Np]
-    g = [out[Np + d * N:Np + (d + 1) * N] for d in range(3)]
-    assert rel(div, projection.divergence(spec, v, vb or None)) <= 1e-12
-    want = projection.gradient(spec, psi)
+    assert out.size == Nq + 3 * N
+    q_degree = P if equal else None
+    div = out[:Nq]
+    assert rel(div, projection.divergence(spec, v, vb or None, q_degree=q_degree)) <= 1e-12
+    want = projection.gradient(spec, psi, q_degree=q_degree)
     for d in range(3):
-        assert rel(g[d], want[d]) <= 1e-12
+        g = out[Nq + d * N:Nq + (d + 1) * N]
+        assert rel(g, want[d] * fac[0] if equal else want[d]) <= 1e-12
+
+
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+@pytest.mark.parametrize("with_vb", [False, True])
+def test_projection_phases_match_oracle(harness, tmp_path, case, with_vb):
+    run_case(harness, tmp_path, case, with_vb, False)
+
+
+EQ_CASES = [((2, 2, 2), 3, (0, 0, 0), False)] + CASES
+EQ_IDS = ["P3_periodic"] + IDS
+
+
+@pytest.mark.parametrize("case", EQ_CASES, ids=EQ_IDS)
+@pytest.mark.parametrize("with_vb", [False, True])
+def test_equal_order_phases_match_oracle(harness, tmp_path, case, with_vb):
+    """The equal-order pair (F_d2, F_d3): scalar degree P, the gradient with a
+    nodal factor."""
+    run_case(harness, tmp_path, case, with_vb, True)
