@@ -91,13 +91,13 @@ __host__ __device__ __forceinline__ int face_node(int d, int layer, int s, int t
 // ------------------------------------------- divergence and gradient --
 // All three components of an element are contracted at once, one line per
 // thread and pass, so that an element takes four (gradient) or five
-// (divergence) barriers whatever its faces.  Component d's derivative axis is contracted last (divergence) or
-// first (gradient), and its two face terms ride along as two extra layers
-// on that axis: the tangential contractions act on them exactly as on the
-// volume layers, and the last (first) pass adds them to the face layer of
-// the output.  Buffers are in LDS; the phases are plain functions of the
-// thread index, so that they can be run for every thread in turn on the
-// host.
+// (divergence) barriers whatever its faces.  Component d's derivative axis
+// is contracted last (divergence) or first (gradient), and its two face
+// terms ride along as two extra layers on that axis: the tangential
+// contractions act on them exactly as on the volume layers, and the last
+// (first) pass adds them to the face layer of the output.  Buffers are in
+// LDS; the phases are plain functions of the thread index, so that they can
+// be run for every thread in turn on the host.
 
 // the tangential axes of axis d, ascending
 __host__ __device__ __forceinline__ int tan1(int d) { return d == 0 ? 1 : 0; }
@@ -495,8 +495,8 @@ __global__ void __launch_bounds__((GradShape<P, Q>::NT)) k_gradient(ProjArgs A)
 // the face terms act on the face nodes directly.  One thread takes one line
 // of one component (3 (P+1)^2 lines, at most 243), with the derivative
 // matrix from the kernel arguments at compile-time indices (the GLL weights
-// of the divergence from LDS); a last pass sums
-// (divergence) or scales and stores (gradient) node by node.
+// of the divergence from LDS); a last pass sums (divergence) or scales and
+// stores (gradient) node by node.
 template <int P>
 struct EqShape {
     static constexpr int n = P + 1, n2 = n * n, n3 = n2 * n;
@@ -532,7 +532,8 @@ __host__ __device__ __forceinline__ void eqdiv_load(const ProjArgs &A, int el, i
             int en[3] = {ex, ey, ez};
             en[d] = kn;
             const size_t nb0 = elem_base(A, en[0], en[1], en[2], n3);
-            f = 0.5 * (A.v[d][vb0 + face_node<n>(d, layer, s, t)] + A.v[d][nb0 + face_node<n>(d, high ? 0 : n - 1, s, t)]);
+            f = 0.5 * (A.v[d][vb0 + face_node<n>(d, layer, s, t)] +
+                       A.v[d][nb0 + face_node<n>(d, high ? 0 : n - 1, s, t)]);
         } else if (A.vb[d]) {
             f = A.vb[d][vb0 + face_node<n>(d, layer, s, t)];
         }
