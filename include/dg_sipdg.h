@@ -359,7 +359,7 @@ int dg_dirichlet_load(dg_mesh *m, const double *nu_field, double nu_const, const
 int dg_convection(dg_mesh *m, const double *vx, const double *vy, const double *vz, const double *vbx,
                   const double *vby, const double *vbz, double scale, int accumulate, double *ox, double *oy,
                   double *oz, void *stream);
-/* (ox, oy, oz) = F_d2(v) with the nodal viscosity nu.  Allocates ten scratch
+/* (ox, oy, oz) = F_d2(v) with the nodal viscosity nu.  Allocates nine scratch
    vectors on m at first use (the mesh's step workspace, freed with m).
    Asynchronous on `stream` (NULL = the mesh's stream); outputs must not
    alias v or nu. */
@@ -386,7 +386,7 @@ int dg_viscous_fd2(dg_mesh *m, const double *nu, const double *vx, const double 
    priority; one pair per device, shared by all meshes, created at first use
    and kept until the process ends), each with its own FP64 solve workspace
    (created at first use and kept with the mesh).  Allocates
-   the mesh's step workspace (about (9 s' + 15) N doubles, s' the stages
+   the mesh's step workspace (about (9 s' + 14) N doubles, s' the stages
    whose terms the tableau uses) at first use; synchronous.  Returns the
    first error of a kernel or solve, else info->status. */
 int dg_imex_step(dg_mesh *mv, dg_mesh *mp, const dg_tableau *tab, double dt, double nu0, double nu1,

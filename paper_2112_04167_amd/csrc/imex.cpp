@@ -162,8 +162,8 @@ int check_tableau(const dg_tableau *t)
 // F_d2 = M^-1 D(nu (d_i v_0, d_i v_1, d_i v_2)) per component i: T[3k + i]
 // = nu d_i v_k by the equal-order gradient with a nodal factor, then the
 // equal-order divergence with the field's own trace as boundary data
-int fd2_terms(const MeshDev &md, const double *nu, const double *const v[3], double *T, double *weak,
-              double *const out[3], hipStream_t s)
+int fd2_terms(const MeshDev &md, const double *nu, const double *const v[3], double *T, double *const out[3],
+              hipStream_t s)
 {
     const size_t N = (size_t)md.ndof;
     int rc;
@@ -173,8 +173,7 @@ int fd2_terms(const MeshDev &md, const double *nu, const double *const v[3], dou
     }
     for (int i = 0; i < 3; ++i) {
         const double *w[3] = {T + (size_t)i * N, T + (size_t)(3 + i) * N, T + (size_t)(6 + i) * N};
-        if ((rc = launch_divergence(md, md, w, w, 1.0, weak, s))) return rc;
-        if ((rc = launch_weak_to_nodal(md, weak, nullptr, 1.0, out[i], s))) return rc;
+        if ((rc = launch_divergence_nodal(md, w, w, 1.0, nullptr, out[i], s))) return rc;
     }
     return DG_OK;
 }
@@ -193,14 +192,14 @@ int fd1_terms(const MeshDev &md, const double *nu, const double *const v[3], con
     return DG_OK;
 }
 
-// F_d3 = -G(nu M^-1 D(v; v_b)), equal order
+// F_d3 = -G(nu M^-1 D(v; v_b)), equal order; w: scratch for the nodal
+// field nu M^-1 D(v; v_b)
 int fd3_terms(const MeshDev &md, const double *nu, const double *const v[3], const double *const vb[3],
-              double *weak, double *const out[3], hipStream_t s)
+              double *w, double *const out[3], hipStream_t s)
 {
     int rc;
-    if ((rc = launch_divergence(md, md, v, vb, 1.0, weak, s))) return rc;
-    if ((rc = launch_weak_to_nodal(md, weak, nu, 1.0, weak, s))) return rc;
-    return launch_gradient(md, md, weak, nullptr, -1.0, out, s);
+    if ((rc = launch_divergence_nodal(md, v, vb, 1.0, nu, w, s))) return rc;
+    return launch_gradient(md, md, w, nullptr, -1.0, out, s);
 }
 
 // the events a step orders its streams with (destroyed with the object)
@@ -292,11 +291,11 @@ int dg_viscous_fd2(dg_mesh *m, const double *nu, const double *vx, const double 
     const size_t N = (size_t)md->ndof;
     hipStream_t s = stream ? (hipStream_t)stream : mesh_stream(m);
     if (stream && s != mesh_stream(m)) DG_HIP_CHECK(hipStreamSynchronize(s));  // a buffer swap frees
-    double *buf = mesh_step_buffer(m, 10 * N);
+    double *buf = mesh_step_buffer(m, 9 * N);
     if (!buf) return DG_ERR_OOM;
     const double *v[3] = {vx, vy, vz};
     double *o[3] = {ox, oy, oz};
-    return fd2_terms(*md, nu, v, buf, buf + 9 * N, o, s);
+    return fd2_terms(*md, nu, v, buf, o, s);
 }
 
 int dg_imex_step(dg_mesh *mv, dg_mesh *mp, const dg_tableau *tab, double dt, double nu0, double nu1,
@@ -335,18 +334,18 @@ int dg_imex_step(dg_mesh *mv, dg_mesh *mp, const dg_tableau *tab, double dt, dou
         if (tab->bI[j] - aI(s - 1, j) != 0.0) needD1[j] = 1;
     }
     // workspace: stage velocity (3N), nu (N), F_d2 scratch and the three
-    // Helmholtz loads (9N), weak scratch of F_d2 and of F_d3 (2N), per used
+    // Helmholtz loads (9N), the nodal scratch of F_d3 (N), per used
     // stage C, D1, D3 (9N), the pressure (Np)
     const size_t N = (size_t)md.ndof, Np = (size_t)mesh_device(mp)->ndof;
     std::vector<int> slot(s, -1);
     int nslots = 0;
     for (int j = 0; j < s; ++j)
         if (needC[j] || needD1[j]) slot[j] = nslots++;
-    double *buf = mesh_step_buffer(mv, (15 + 9 * (size_t)nslots) * N + Np);
+    double *buf = mesh_step_buffer(mv, (14 + 9 * (size_t)nslots) * N + Np);
     if (!buf) return DG_ERR_OOM;
     double *Vi[3] = {buf, buf + N, buf + 2 * N};
-    double *nu = buf + 3 * N, *T = buf + 4 * N, *weak = buf + 13 * N, *weak3 = buf + 14 * N;
-    double *terms = buf + 15 * N, *psi = terms + 9 * (size_t)nslots * N;
+    double *nu = buf + 3 * N, *T = buf + 4 * N, *w3 = buf + 13 * N;
+    double *terms = buf + 14 * N, *psi = terms + 9 * (size_t)nslots * N;
     auto C = [&](int j, int d) { return terms + ((size_t)slot[j] * 9 + d) * N; };
     auto D1 = [&](int j, int d) { return terms + ((size_t)slot[j] * 9 + 3 + d) * N; };
     auto D3 = [&](int j, int d) { return terms + ((size_t)slot[j] * 9 + 6 + d) * N; };
@@ -402,8 +401,8 @@ int dg_imex_step(dg_mesh *mv, dg_mesh *mp, const dg_tableau *tab, double dt, dou
                 c3[d] = C(j, d);
                 d3[d] = D3(j, d);
             }
-            if ((r = fd3_terms(md, nu, v, vb, weak3, d3, alt[1]))) return r;
-            if ((r = fd2_terms(md, nu, v, T, weak, c3, sv))) return r;
+            if ((r = fd3_terms(md, nu, v, vb, w3, d3, alt[1]))) return r;
+            if ((r = fd2_terms(md, nu, v, T, c3, sv))) return r;
             if ((r = launch_convection(md, v, vb, 1.0, true, c3, sv))) return r;
         }
         DG_HIP_CHECK(hipEventRecord(ev.e[1], alt[0]));

@@ -12,6 +12,10 @@ namespace dg {
 // (v_b = 0) and each vb[d] may be null (that component's boundary flux zero)
 int launch_divergence(const MeshDev &mv, const MeshDev &mp, const double *const v[3],
                       const double *const vb[3], double scale, double *out, hipStream_t s);
+// out = scale fac M^-1 D(v; v_b) at every node of m (equal order: the
+// scalar space is the velocity space; fac a nodal factor, null: 1)
+int launch_divergence_nodal(const MeshDev &m, const double *const v[3], const double *const vb[3], double scale,
+                            const double *fac, double *out, hipStream_t s);
 // g = scale fac G psi (fac a nodal factor of the velocity mesh, null: 1), or
 // g = v + scale fac G psi when v is given (g may alias v).  mp: the pressure
 // mesh (degree P-1) or, for the equal-order operators of the

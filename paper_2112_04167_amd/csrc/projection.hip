@@ -52,13 +52,14 @@ struct ProjArgs {
     const double *v[3];   // velocity (div) / update input (grad)
     const double *vb[3];  // boundary data (div; null: v_b = 0)
     const double *psi;    // pressure (grad)
-    double *out;          // weak divergence (div)
+    double *out;          // weak divergence (div), or its nodal form (nodal)
     double *g[3];         // gradient or updated velocity (grad)
     const double *h[3];   // element extents per axis
     int n[3], bc[3];
     double scale;         // div: factor on the weak vector; grad: factor on G psi
     int update;           // grad: g = v + scale G psi instead of scale G psi
-    const double *fac;    // grad: nodal factor on scale G psi (null: 1)
+    const double *fac;    // grad: nodal factor on scale G psi; nodal div: on the nodal result (null: 1)
+    int nodal;            // div, equal order: out = fac scale M^-1 D(v; v_b), M the GLL mass
 };
 
 // neighbour of element index k along an axis: -1 on a non-periodic boundary
@@ -586,13 +587,27 @@ __host__ __device__ __forceinline__ void eqdiv_lines(const ProjArgs &A, const Pr
     }
 }
 
+// out = scale x (weak), or with A.nodal scale x (fac or 1) / M, x the sum of
+// the three components' parts
 template <int P>
-__host__ __device__ __forceinline__ void eqdiv_store(const ProjArgs &A, int el, int tid, const double *tv)
+__host__ __device__ __forceinline__ void eqdiv_store(const ProjArgs &A, int el, int tid, const double *tv,
+                                                     const double *tw)
 {
     using S = EqShape<P>;
-    constexpr int n3 = S::n3;
+    constexpr int n = S::n, n3 = S::n3;
+    const int ex = el % A.n[0], ey = (el / A.n[0]) % A.n[1], ez = el / (A.n[0] * A.n[1]);
+    const double J = A.h[0][ex] * A.h[1][ey] * A.h[2][ez] * 0.125;
     const size_t vb0 = (size_t)el * n3;
-    for (int i = tid; i < n3; i += S::NT) A.out[vb0 + i] = A.scale * (tv[i] + tv[n3 + i] + tv[2 * n3 + i]);
+    for (int i = tid; i < n3; i += S::NT) {
+        const double x = tv[i] + tv[n3 + i] + tv[2 * n3 + i];
+        if (A.nodal) {
+            const int a = i % n, b = (i / n) % n, c = i / (n * n);
+            const double v = A.scale * x / (J * tw[a] * tw[b] * tw[c]);
+            A.out[vb0 + i] = A.fac ? v * A.fac[vb0 + i] : v;
+        } else {
+            A.out[vb0 + i] = A.scale * x;
+        }
+    }
 }
 
 template <int P>
@@ -605,7 +620,7 @@ __global__ void __launch_bounds__(EqShape<P>::NT) k_divergence_eq(ProjArgs A)
     __syncthreads();
     eqdiv_lines<P>(A, A.t, el, tid, tv, fv, tw);
     __syncthreads();
-    eqdiv_store<P>(A, el, tid, tv);
+    eqdiv_store<P>(A, el, tid, tv, tw);
 }
 
 // the element's scalar and the neighbours' traces on the six faces (axis d,
@@ -799,6 +814,24 @@ int launch_divergence(const MeshDev &mv, const MeshDev &mp, const double *const 
             hipLaunchKernelGGL((k_divergence_eq<Pv>), dim3((unsigned)mv.nel), dim3(EqShape<Pv>::NT), 0, s, a);
         else
             hipLaunchKernelGGL((k_divergence<Pv, Qv>), dim3((unsigned)mv.nel), dim3(DivShape<Pv, Qv>::NT), 0, s, a);
+    });
+}
+
+int launch_divergence_nodal(const MeshDev &m, const double *const v[3], const double *const vb[3], double scale,
+                            const double *fac, double *out, hipStream_t s)
+{
+    ProjArgs a = base_args(m, m);
+    for (int d = 0; d < 3; ++d) {
+        a.v[d] = v[d];
+        a.vb[d] = vb ? vb[d] : nullptr;
+    }
+    a.out = out;
+    a.scale = scale;
+    a.fac = fac;
+    a.nodal = 1;
+    return with_pair(m.P, m.P, [&](auto PC, auto) {
+        constexpr int Pv = decltype(PC)::value;
+        hipLaunchKernelGGL((k_divergence_eq<Pv>), dim3((unsigned)m.nel), dim3(EqShape<Pv>::NT), 0, s, a);
     });
 }
 

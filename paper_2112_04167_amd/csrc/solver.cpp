@@ -1864,8 +1864,7 @@ int dg_viscous_terms(dg_mesh *m, const double *nu, const double *vx, const doubl
                 return DG_ERR_OOM;
             }
         }
-        if ((rc = launch_divergence(md, md, v, vb, 1.0, m->aux, s))) return rc;
-        if ((rc = launch_weak_to_nodal(md, m->aux, nu, 1.0, m->aux, s))) return rc;
+        if ((rc = launch_divergence_nodal(md, v, vb, 1.0, nu, m->aux, s))) return rc;
         if ((rc = launch_gradient(md, md, m->aux, nullptr, -1.0, f3, s))) return rc;
     }
     return DG_OK;

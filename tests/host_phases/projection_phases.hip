@@ -3,13 +3,13 @@
 // LDS buffers on the heap, so that an address sanitizer build checks every
 // shared and global access of the kernels' index arithmetic.  Either the
 // projection's pair (velocity degree P, pressure degree P-1) or the equal-order
-// pair (scalar degree P, with a nodal factor on the gradient).  Reads the mesh
-// and the fields from a binary file and writes the divergence and the
-// gradient.
+// pair (scalar degree P, the divergence also in its nodal form, M^-1 times a
+// nodal factor, and the gradient with that factor).  Reads the mesh and the
+// fields from a binary file and writes the divergence and the gradient.
 //
 //   projection_phases P nx ny nz bcx bcy bcz with_vb equal in.bin out.bin
 //   in.bin:  h_x[nx] h_y[ny] h_z[nz] v0 v1 v2 [vb0 vb1 vb2] psi [fac]  (float64)
-//   out.bin: div[Nq] g0[N] g1[N] g2[N]   (Nq = N when equal, else Np)
+//   out.bin: div[Nq] [div_nodal[N]] g0[N] g1[N] g2[N]   (Nq = N when equal, else Np)
 #include "projection.hip"
 #include "gll_host.cpp"
 
@@ -52,14 +52,21 @@ void run_elements(const ProjArgs &A, int nel)
 }
 
 template <int P>
-void run_elements_equal(const ProjArgs &A, int nel)
+void run_elements_equal(const ProjArgs &A, int nel, double *out2)
 {
     using S = EqShape<P>;
     for (int el = 0; el < nel; ++el) {
-        std::vector<double> tv(3 * S::n3), fv(6 * S::n2), tw(S::n);
-        for (int t = 0; t < S::NT; ++t) eqdiv_load<P>(A, el, t, tv.data(), fv.data(), tw.data());
-        for (int t = 0; t < S::NT; ++t) eqdiv_lines<P>(A, A.t, el, t, tv.data(), fv.data(), tw.data());
-        for (int t = 0; t < S::NT; ++t) eqdiv_store<P>(A, el, t, tv.data());
+        // the weak divergence into out, its nodal form (M^-1, times fac) into
+        // out2
+        for (int nodal = 0; nodal < 2; ++nodal) {
+            ProjArgs B = A;
+            B.nodal = nodal;
+            if (nodal) B.out = out2;
+            std::vector<double> tv(3 * S::n3), fv(6 * S::n2), tw(S::n);
+            for (int t = 0; t < S::NT; ++t) eqdiv_load<P>(B, el, t, tv.data(), fv.data(), tw.data());
+            for (int t = 0; t < S::NT; ++t) eqdiv_lines<P>(B, B.t, el, t, tv.data(), fv.data(), tw.data());
+            for (int t = 0; t < S::NT; ++t) eqdiv_store<P>(B, el, t, tv.data(), tw.data());
+        }
         std::vector<double> q(S::n3), qn(6 * S::n2), R(3 * S::n3);
         for (int t = 0; t < S::NT; ++t) eqgrad_load<P>(A, el, t, q.data(), qn.data());
         for (int t = 0; t < S::NT; ++t) eqgrad_lines<P>(A, A.t, el, t, q.data(), qn.data(), R.data());
@@ -97,7 +104,7 @@ int main(int argc, char **argv)
     const std::vector<double> psi = read(Np);
     const std::vector<double> fac = equal ? read(N) : std::vector<double>();
     fclose(f);
-    std::vector<double> div(Np, -999.0), g[3];
+    std::vector<double> div(Np, -999.0), div2(equal ? N : 0, -999.0), g[3];
     dg::ProjArgs A{};
     A.t = dg::make_tables(P, equal ? P : P - 1);
     for (int d = 0; d < 3; ++d) {
@@ -115,12 +122,12 @@ int main(int argc, char **argv)
     A.fac = equal ? fac.data() : nullptr;
     if (equal) {
         switch (P) {
-            case 3: dg::run_elements_equal<3>(A, nel); break;
-            case 4: dg::run_elements_equal<4>(A, nel); break;
-            case 5: dg::run_elements_equal<5>(A, nel); break;
-            case 6: dg::run_elements_equal<6>(A, nel); break;
-            case 7: dg::run_elements_equal<7>(A, nel); break;
-            case 8: dg::run_elements_equal<8>(A, nel); break;
+            case 3: dg::run_elements_equal<3>(A, nel, div2.data()); break;
+            case 4: dg::run_elements_equal<4>(A, nel, div2.data()); break;
+            case 5: dg::run_elements_equal<5>(A, nel, div2.data()); break;
+            case 6: dg::run_elements_equal<6>(A, nel, div2.data()); break;
+            case 7: dg::run_elements_equal<7>(A, nel, div2.data()); break;
+            case 8: dg::run_elements_equal<8>(A, nel, div2.data()); break;
             default: return 4;
         }
     } else {
@@ -136,6 +143,7 @@ int main(int argc, char **argv)
     FILE *o = fopen(argv[11], "wb");
     if (!o) return 5;
     fwrite(div.data(), sizeof(double), Np, o);
+    if (equal) fwrite(div2.data(), sizeof(double), N, o);
     for (int d = 0; d < 3; ++d) fwrite(g[d].data(), sizeof(double), N, o);
     fclose(o);
     return 0;

@@ -12,7 +12,7 @@ import subprocess
 import numpy as np
 import pytest
 
-from oracle import projection
+from oracle import gll, projection
 from tests.helpers import make_spec, ndof
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -44,6 +44,16 @@ def harness(tmp_path_factory):
     return exe
 
 
+def gll_mass(spec):
+    """Diagonal of the GLL mass in the ABI layout: J w_a w_b w_c."""
+    P = spec["P"]
+    w = gll.weights(P)
+    hx, hy, hz = (np.diff(np.asarray(spec[k], dtype=np.float64)) for k in ("xv", "yv", "zv"))
+    J = (hz[:, None, None] * hy[None, :, None] * hx[None, None, :]) / 8.0
+    wn = w[:, None, None] * w[None, :, None] * w[None, None, :]  # [c][b][a]
+    return (J[:, :, :, None, None, None] * wn[None, None, None]).ravel()
+
+
 def rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
@@ -66,13 +76,19 @@ def run_case(harness, tmp_path, case, with_vb, equal):
                         str(fin), str(fout)], capture_output=True, text=True, env=env)
     assert r.returncode == 0, r.stderr[-4000:]
     out = np.fromfile(fout)
-    assert out.size == Nq + 3 * N
+    extra = N if equal else 0
+    assert out.size == Nq + extra + 3 * N
     q_degree = P if equal else None
     div = out[:Nq]
-    assert rel(div, projection.divergence(spec, v, vb or None, q_degree=q_degree)) <= 1e-12
+    want_div = projection.divergence(spec, v, vb or None, q_degree=q_degree)
+    assert rel(div, want_div) <= 1e-12
+    if equal:
+        # the nodal form: the weak vector over the diagonal GLL mass
+        # J w_a w_b w_c, times the nodal factor
+        assert rel(out[Nq:Nq + N], want_div / gll_mass(spec) * fac[0]) <= 1e-12
     want = projection.gradient(spec, psi, q_degree=q_degree)
     for d in range(3):
-        g = out[Nq + d * N:Nq + (d + 1) * N]
+        g = out[Nq + extra + d * N:Nq + extra + (d + 1) * N]
         assert rel(g, want[d] * fac[0] if equal else want[d]) <= 1e-12
 
 
