@@ -558,11 +558,40 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_restart64(CgVecArgs<double> A
     publish_partials<4>(red, A.partial, gridDim.x, sh);
 }
 
+// Sums of NC partial-sum arrays partial[c * nblk + 0..nblk) taken by the
+// calling work-group, this thread's share in t[c].  The loads of all
+// components are issued together (summing one component after another would
+// wait for one L2 round trip per component); two accumulators per component,
+// combined in a fixed order, so the result does not depend on timing.
+template <int NC>
+__device__ __forceinline__ void sum_partials(const double *partial, int nblk, double (&t)[NC])
+{
+    double a[NC], b[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) a[c] = b[c] = 0.0;
+    const int B = blockDim.x;
+    int k = threadIdx.x;
+    for (; k + B < nblk; k += 2 * B) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            a[c] += partial[(size_t)c * nblk + k];
+            b[c] += partial[(size_t)c * nblk + k + B];
+        }
+    }
+    if (k < nblk) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) a[c] += partial[(size_t)c * nblk + k];
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) t[c] = a[c] + b[c];
+}
+
 // ---- CG preconditioned by the fast-diagonalisation inverse (FP64) --------
 //
 // z = F r is formed by the transform kernels (fdm.hip) between the update
 // and the r.z reduction, so one step is: apply (q = A p, alpha), update
-// (x, r, residual norm, stopping test), F, r.z (beta), p-update.
+// (x, r, residual norm, stopping test), F, r.z partials, p-update (beta from
+// the partials, no finishing kernel).
 
 // x += alpha p, r -= alpha q; sums of (r/M)^2 (singular: also r and r/M^2,
 // for the norm of the projected residual)
@@ -620,12 +649,27 @@ __global__ void __launch_bounds__(Shape<P>::NTP) k_rz(CgVecArgs<double> A)
     publish_partials<1>(red, A.partial, gridDim.x, sh);
 }
 
+// p = z + beta p with beta = rho'/rho: every work-group sums k_rz's partials
+// (same grid, so gridDim.x of them) in the same fixed order, so all hold the
+// same rho'; work-group 0 leaves it in rho_next, and rho itself changes only
+// in the next apply's finish
 template <int P, bool START>
 __global__ void __launch_bounds__(Shape<P>::NTP) k_pupdate_fdm(CgVecArgs<double> A)
 {
     using S = Shape<P>;
+    __shared__ double sh[16];
     if (A.sc->done) return;
-    const double beta = A.sc->beta;
+    double rz[1];
+    sum_partials<1>(A.partial, (int)gridDim.x, rz);
+    block_sum<1>(rz, sh);
+    if (threadIdx.x == 0) sh[0] = rz[0];
+    __syncthreads();
+    const double rho_new = sh[0];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        A.sc->rho_next = rho_new;
+        A.sc->rho_pending = 1;
+    }
+    const double beta = START ? 0.0 : rho_new / A.sc->rho;
     const LineCtx<P, double> c = line_ctx<P, double>(A);
     if (!c.active) return;
 #pragma unroll
@@ -662,34 +706,6 @@ __global__ void k_fdm_start_scalars(CgScalars *sc)
     } else if (sc->bnorm2 == 0.0 || res2 == 0.0 || (sc->fixed_iters <= 0 && res2 <= sc->tol2)) {
         sc->done = 1;
     }
-}
-
-// Sums of NC partial-sum arrays partial[c * nblk + 0..nblk) taken by the
-// calling work-group, this thread's share in t[c].  The loads of all
-// components are issued together (summing one component after another would
-// wait for one L2 round trip per component); two accumulators per component,
-// combined in a fixed order, so the result does not depend on timing.
-template <int NC>
-__device__ __forceinline__ void sum_partials(const double *partial, int nblk, double (&t)[NC])
-{
-    double a[NC], b[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) a[c] = b[c] = 0.0;
-    const int B = blockDim.x;
-    int k = threadIdx.x;
-    for (; k + B < nblk; k += 2 * B) {
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            a[c] += partial[(size_t)c * nblk + k];
-            b[c] += partial[(size_t)c * nblk + k + B];
-        }
-    }
-    if (k < nblk) {
-#pragma unroll
-        for (int c = 0; c < NC; ++c) a[c] += partial[(size_t)c * nblk + k];
-    }
-#pragma unroll
-    for (int c = 0; c < NC; ++c) t[c] = a[c] + b[c];
 }
 
 __global__ void __launch_bounds__(1024) k_finish_restart64(const double *partial, int nblk, CgScalars *sc)
@@ -780,9 +796,7 @@ template <int NC, int OP>
 __global__ void __launch_bounds__(1024) k_finish(const double *partial, int nblk, CgScalars *sc)
 {
     __shared__ double sh[16 * NC];
-    if ((OP == FIN_APPLY || OP == FIN_UPDATE || OP == FIN_UPDATE_FDM || OP == FIN_RZ ||
-         OP == FIN_RZ_START) && sc->done)
-        return;
+    if ((OP == FIN_APPLY || OP == FIN_UPDATE || OP == FIN_UPDATE_FDM) && sc->done) return;
     double tot[NC];
     sum_partials<NC>(partial, nblk, tot);
     block_sum<NC>(tot, sh);
@@ -864,15 +878,6 @@ __global__ void __launch_bounds__(1024) k_finish(const double *partial, int nblk
             sc->done = 1;
         } else if (sc->iter >= sc->maxit) {
             sc->status = DG_NOT_CONVERGED;
-            sc->done = 1;
-        }
-    } else if constexpr (OP == FIN_RZ || OP == FIN_RZ_START) {
-        const double rz = tot[0];
-        sc->beta = OP == FIN_RZ_START ? 0.0 : rz / sc->rho;
-        sc->rho_prev = sc->rho;
-        sc->rho = rz;
-        if (!isfinite(rz)) {
-            sc->status = DG_ERR_NONFINITE;
             sc->done = 1;
         }
     } else if constexpr (OP == FIN_MEANX) {
@@ -1112,17 +1117,12 @@ int cg_update_fdm(const MeshDev &m, CgVecArgs<double> a, hipStream_t s)
     });
 }
 
-int cg_rz(const MeshDev &m, CgVecArgs<double> a, bool start, hipStream_t s)
+int cg_rz(const MeshDev &m, CgVecArgs<double> a, hipStream_t s)
 {
     prep(m, a);
     return with_P(m.P, [&](auto PC) {
         constexpr int P = decltype(PC)::value;
-        const int nb = apply_groups(P, m.nel);
         hipLaunchKernelGGL((k_rz<P>), DG_GRID(PC), 0, s, a);
-        if (start)
-            hipLaunchKernelGGL((k_finish<1, FIN_RZ_START>), dim3(1), dim3(1024), 0, s, a.partial, nb, a.sc);
-        else
-            hipLaunchKernelGGL((k_finish<1, FIN_RZ>), dim3(1), dim3(1024), 0, s, a.partial, nb, a.sc);
     });
 }
 

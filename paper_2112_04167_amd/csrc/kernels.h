@@ -27,12 +27,24 @@ struct CgScalars {
     double scale_new;  // mixed: scaling chosen for the next residual replacement
     int iter, maxit, fixed_iters, done, status, singular;
     long long ndof;
-    int pad[2];
+    int rho_pending;   // fast-diagonalisation CG: a new r.z waits in rho_next
+    int pad;
+    double rho_next;   // r.z left by the p-update, made rho by the next apply's finish
 };
 
 // Device helpers called by the kernels that finish a reduction.
 __device__ inline void cg_after_apply(CgScalars *sc, double pq, double sumq)
 {
+    if (sc->rho_pending) {  // the r.z of the p-update that precedes this apply
+        sc->rho_pending = 0;
+        sc->rho_prev = sc->rho;
+        sc->rho = sc->rho_next;
+        if (!isfinite(sc->rho)) {
+            sc->status = DG_ERR_NONFINITE;
+            sc->done = 1;
+            return;
+        }
+    }
     sc->pq = pq;
     sc->sumq = sumq;
     if (!isfinite(pq)) {
@@ -62,7 +74,7 @@ __device__ inline void resid_finish(CgScalars *sc, const double (&t)[4])
 
 // reductions finished by a one-work-group kernel after the producer
 enum { FIN_APPLY = 0, FIN_RESID, FIN_SETUP1, FIN_SETUP2, FIN_UPDATE, FIN_MEANX, FIN_IRSCALE,
-       FIN_UPDATE_FDM, FIN_RZ, FIN_RZ_START };
+       FIN_UPDATE_FDM };
 int launch_finish_apply(double *partial, int nblk, CgScalars *sc, hipStream_t s);
 int launch_finish_resid(double *partial, int nblk, CgScalars *sc, hipStream_t s);
 
@@ -134,9 +146,12 @@ int cg_restart64(const MeshDev &m, CgVecArgs<double> a, hipStream_t s);
 int cg_fdm_start(const MeshDev &m, CgVecArgs<double> a, hipStream_t s);
 // x += alpha p, r -= alpha q, ||M^-1 r|| and the stopping test
 int cg_update_fdm(const MeshDev &m, CgVecArgs<double> a, hipStream_t s);
-// rho' = (r - mean_r).z; beta = rho'/rho (start: beta = 0)
-int cg_rz(const MeshDev &m, CgVecArgs<double> a, bool start, hipStream_t s);
-// p = z + beta p (start: p = z)
+// per-work-group partial sums of rho' = (r - mean_r).z
+int cg_rz(const MeshDev &m, CgVecArgs<double> a, hipStream_t s);
+// p = z + beta p, beta = rho'/rho (start: p = z), every work-group summing
+// the partials of cg_rz itself; rho' is left in rho_next for the next
+// apply's finish (cg_after_apply), so no work-group reads a rho another one
+// has changed
 int cg_pupdate_fdm(const MeshDev &m, CgVecArgs<double> a, bool start, hipStream_t s);
 
 }  // namespace dg

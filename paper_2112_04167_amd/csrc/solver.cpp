@@ -560,7 +560,7 @@ int fdm_start(dg_mesh *m, FdmRun &R, const dg_solve_opts &o)
         return rc;
     if ((rc = cg_fdm_start(md, a, s))) return rc;
     if ((rc = fdm_precond(md, R))) return rc;
-    if ((rc = cg_rz(md, a, true, s))) return rc;
+    if ((rc = cg_rz(md, a, s))) return rc;
     if ((rc = cg_pupdate_fdm(md, a, true, s))) return rc;
     R.cap = o.fixed_iters > 0 ? o.fixed_iters : o.maxit;
     R.plan = ChunkPlan(2, 16, true);
@@ -595,7 +595,7 @@ int fdm_chunk(dg_mesh *m, FdmRun &R)
             return rc;
         if ((rc = cg_update_fdm(md, R.a, s))) return rc;
         if ((rc = fdm_precond(md, R))) return rc;
-        if ((rc = cg_rz(md, R.a, false, s))) return rc;
+        if ((rc = cg_rz(md, R.a, s))) return rc;
         if ((rc = cg_pupdate_fdm(md, R.a, false, s))) return rc;
     }
     R.launched += R.plan.chunk;
